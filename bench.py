@@ -1,0 +1,149 @@
+#!/usr/bin/env python3
+"""Throughput of batched voice rendering on one MI355X.
+
+Workload: 16384 voices of the default Voice, render lengths 1, 2 and 4 s
+(by voice index mod 3) at 44.1 kHz packed back to back (1.686e9 samples,
+6.74 GB of float32 audio), note durations uniform in [0.1, 4] s.  A step is
+one pass of the hot path over the batch: the parameter draw (Philox) and the
+fused render, with every input resident in HBM before the timed region.
+
+Prints one JSON line: rendered samples/s (and MHz, x real time), the render
+kernel's HBM roofline fraction measured with HIP events on its stream, and the
+float64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=16384)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-voices", type=int, default=96)
+    ap.add_argument("--graph", type=int, default=1, help="capture the step in a HIP graph")
+    ap.add_argument("--rps", type=int, default=0, help="runs per segment (0 = library default)")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, n_voices):
+    """Float64 oracle on the first n_voices voices of the workload (mixed lengths)."""
+    import torch
+    from oracle import philox, voice
+    threads = len(os.sched_getaffinity(0))
+    torch.set_num_threads(threads)
+    ids = np.arange(n_voices)
+    u = philox.sample_params(wl.seed, ids)
+    t0 = time.perf_counter()
+    y = voice.render(torch.from_numpy(u), ids, wl.lengths[:n_voices], wl.nebula.table(),
+                     wl.sample_rate, wl.control_rate, wl.key_noise())
+    dt = time.perf_counter() - t0
+    n = int(wl.lengths[:n_voices].sum())
+    assert y.numel() == n
+    return {"value": n / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"float64 oracle render of voices 0..{n_voices - 1} of the workload "
+                      f"({n} samples, 1/2/4 s mix), {dt:.2f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import workloads as W
+    import paper_2104_12922_amd as S
+
+    wl = W.ragged_batch(args.batch)
+    table = wl.nebula.table()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    B = wl.batch
+    total = wl.total_samples
+    offsets = torch.from_numpy(wl.offsets).to(dev)
+    params = torch.empty(B, 78, dtype=torch.float32, device=dev)
+    audio = torch.empty(total, dtype=torch.float32, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+
+    def render():
+        if args.rps:
+            S.synth_render_plan(params, table, args.rps, 1, offsets=offsets,
+                                noise_seed=wl.key_noise(), out=audio)
+        else:
+            S.synth_render(params, table, offsets=offsets, noise_seed=wl.key_noise(), out=audio)
+
+    def step():
+        S.synth_sample_params(wl.seed, wl.first_g, B, out=params)
+        render()
+
+    with torch.cuda.stream(stream):
+        step()
+        torch.cuda.synchronize()
+        # render-kernel time with HIP events on the stream the kernel runs on
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(max(3, min(args.steps, 10)))]
+        for a, b in ev:
+            a.record(stream)
+            render()
+            b.record(stream)
+        torch.cuda.synchronize()
+        kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+        graph = None
+        if args.graph:
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=stream):
+                step()
+            torch.cuda.synchronize()
+        run = graph.replay if graph is not None else step
+
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+
+    ms = dt / args.steps * 1e3
+    value = total / (dt / args.steps)
+    alg_bytes = 4.0 * total + 4.0 * 78 * B + 8.0 * (B + 1)
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    out = {
+        "metric": "rendered audio samples/sec", "value": value, "unit": "samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (Philox-drawn parameters, rendered on the fly)",
+        "config": {"workload": wl.name, "voices": B, "samples": total,
+                   "lengths_s": [1, 2, 4], "sample_rate": wl.sample_rate,
+                   "control_rate": wl.control_rate, "note_duration_s": [0.1, 4.0],
+                   "hip_graph": bool(args.graph), "phase_dtype": "f64"},
+        "mhz": value / 1e6, "x_realtime": value / wl.sample_rate,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "render_kernel", "kernel_ms": kern_ms,
+                     "alg_bytes_per_launch": alg_bytes},
+        "context": {"paper_single_gpu_mhz": 714.0, "paper_gpu": "V100"},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_voices)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,119 @@
+/*
+ * synth.h - C ABI of the MI355X modular-synthesizer voice renderer.
+ *
+ * Implements the hot path of "One Billion Audio Sounds from GPU-enabled Modular
+ * Synthesis" (Turian et al., DAFx 2021, arXiv 2104.12922): batched rendering of
+ * the default Voice (Section 3.2) from normalised parameters (Section 3.3),
+ * with deterministic counter-based random numbers for both the parameters and
+ * the noise oscillator (Section 2.1).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an int status (synth_status); none throws.
+ *   - "dev" pointers are HIP device pointers owned by the caller; "host" pointers
+ *     are read during the call only.  The library keeps no reference to either.
+ *   - Calls are stream-ordered and asynchronous on the given HIP stream
+ *     (hipStream_t passed as void*; NULL = the default stream).  The library
+ *     never synchronises; a device fault surfaces at the caller's next sync.
+ *   - Argument errors are detected on the host before any launch and return
+ *     SYNTH_EINVAL / SYNTH_EUNSUPPORTED with nothing written.
+ *   - The library allocates no device memory on these paths.
+ *   - Results are bitwise deterministic for fixed inputs and independent of the
+ *     batch composition (a voice's output depends only on its parameters, its
+ *     voice id and the config).
+ */
+#ifndef SYNTH_H_
+#define SYNTH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SYNTH_OK = 0,
+    SYNTH_EINVAL = -1,        /* bad pointer, size or value */
+    SYNTH_ENOMEM = -2,        /* caller-provided buffer too small */
+    SYNTH_EDEVICE = -3,       /* HIP launch/runtime error */
+    SYNTH_EUNSUPPORTED = -4   /* valid but not implemented configuration */
+} synth_status;
+
+#define SYNTH_NUM_PARAMS 78
+
+/* Render configuration.
+ *   sample_rate  audio rate in Hz (44100 by default, Section 2.2); must be an
+ *                integer multiple q of control_rate with q % 4 == 0, q <= 1024.
+ *   control_rate rate of the control modules (ADSR, LFO) in Hz (441 by
+ *                default, Section 3.1).
+ *   noise_seed   64-bit key of the noise oscillator's counter-based generator.
+ *   mix_mode     0: audio mixer output is the plain sum of the three levelled
+ *                VCA outputs; 1: additionally each voice is divided by
+ *                max(1, peak |y|) (peak-normalise only when clipping).
+ *   nebula       host pointer to [78][4] doubles, row p = (min, max, curve,
+ *                symmetric) of parameter p (Section 3.3; symmetric is 0 or 1,
+ *                curve > 0).  Required. */
+typedef struct synth_config {
+    double sample_rate;
+    double control_rate;
+    uint64_t noise_seed;
+    int32_t mix_mode;
+    int32_t reserved;        /* must be 0 */
+    const double* nebula;
+} synth_config;
+
+/* Number of normalised parameters of the Voice: 78 (Section 1.1). */
+int synth_num_params(void);
+
+/* Static, NUL-terminated description of a status code. */
+const char* synth_status_string(int status);
+
+/* Train/test split of the corpus (Section 2.2): 9*1024 train voices, then 1024
+ * test voices, repeating.  Returns 1 if global voice index g is a test voice. */
+int synth_is_test(uint64_t g);
+
+/* Deterministic parameter draw (Sections 2.1 and 3.3).
+ *   params[i][p] = (w >> 8) * 2^-24, w = word (p & 3) of Philox4x32-10 with
+ *   key (seed lo, seed hi) and counter (g lo, g hi, p >> 2, 0), where
+ *   g = voice_ids[i] if voice_ids != NULL else first_g + i.
+ *   voice_ids  dev uint64 [batch] or NULL.
+ *   params     dev float32 [batch][78], written; values in [0, 1 - 2^-24].
+ *   batch >= 0 (0 is a no-op). */
+int synth_sample_params(uint64_t seed, uint64_t first_g, int64_t batch,
+                        const uint64_t* voice_ids, float* params, void* stream);
+
+/* Render a batch of voices (Sections 3.1-3.3).
+ *   params     dev float32 [batch][78], normalised parameters in [0, 1].
+ *   voice_ids  dev uint64 [batch] or NULL (=> first_g + i); addresses the
+ *              noise oscillator's counter.
+ *   offsets    dev int64 [batch + 1] or NULL.  If given, voice i is written to
+ *              audio[offsets[i] .. offsets[i+1]) (ragged lengths, packed); the
+ *              offsets must be non-decreasing.  If NULL every voice has
+ *              n_samples samples and voice i starts at audio[i * n_samples].
+ *   n_samples  uniform length when offsets == NULL (> 0); ignored otherwise.
+ *   audio      dev float32, written: batch * n_samples floats, or offsets[batch].
+ *   Output: y(n) = L1 * sine(n) * a1(n) + L2 * squaresaw(n) * a2(n)
+ *                  + L3 * noise(n) * a3(n) (mix_mode 0).
+ * Float32 audio; the phase of both oscillators is accumulated in float64. */
+int synth_render(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
+                 uint64_t first_g, int64_t batch, const int64_t* offsets, int64_t n_samples,
+                 float* audio, void* stream);
+
+/* Same as synth_render with an explicit launch plan (used by the autotuner and
+ * by tests): runs_per_segment in {1, 2, 4} splits each control period into
+ * that many per-lane runs; slices_per_voice >= 1 splits each voice (uniform
+ * lengths only) over that many workgroups; persistent != 0 launches
+ * grid_blocks workgroups (0 => chosen by the library) of which workgroup w
+ * renders voices w, w + grid_blocks, w + 2 * grid_blocks, ... (no device
+ * state).  Fails with SYNTH_EUNSUPPORTED for a plan the configuration cannot
+ * use, SYNTH_EINVAL for out-of-range plan values. */
+int synth_render_plan(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
+                      uint64_t first_g, int64_t batch, const int64_t* offsets, int64_t n_samples,
+                      float* audio, int runs_per_segment, int slices_per_voice,
+                      int persistent, int grid_blocks, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SYNTH_H_ */

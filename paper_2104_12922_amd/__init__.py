@@ -1,0 +1,121 @@
+"""MI355X-native batched modular-synth voice renderer (arXiv 2104.12922).
+
+Python face of libsynth.so: the functions below take torch tensors that live on
+the GPU, pass their device pointers and the current HIP stream to the C ABI
+(include/synth.h), and return tensors.  PyTorch provides device memory and
+streams only; the parameter draw and every stage of the render run in the
+library's HIP kernels.  There is no CPU fallback: without the built library or
+a GPU these functions raise.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _native
+
+NUM_PARAMS = _native.NUM_PARAMS
+
+__all__ = ["synth_sample_params", "synth_render", "synth_render_plan", "synth_is_test",
+           "NUM_PARAMS", "SynthError"]
+
+SynthError = _native.SynthError
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dev_ptr(t, name, dtype, numel=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if dtype == torch.uint64 and t.dtype == torch.int64:
+        dtype = torch.int64          # voice ids: same 64-bit pattern
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+    return t.data_ptr()
+
+
+def synth_is_test(g: int) -> bool:
+    return bool(_native.lib().synth_is_test(int(g)))
+
+
+def synth_sample_params(seed: int, first_g: int = 0, batch: int | None = None,
+                        voice_ids: torch.Tensor | None = None, out: torch.Tensor | None = None,
+                        device="cuda") -> torch.Tensor:
+    """Normalised parameters [B, 78] float32 drawn from Philox4x32-10 (see synth.h)."""
+    if voice_ids is not None:
+        batch = voice_ids.numel()
+        device = voice_ids.device
+    if batch is None:
+        raise ValueError("batch or voice_ids is required")
+    if out is None:
+        out = torch.empty(batch, NUM_PARAMS, dtype=torch.float32, device=device)
+    ids = _dev_ptr(voice_ids, "voice_ids", torch.uint64, batch) if voice_ids is not None else None
+    _native.check("synth_sample_params", _native.lib().synth_sample_params(
+        int(seed) & (2**64 - 1), int(first_g), int(batch), ids,
+        _dev_ptr(out, "out", torch.float32, batch * NUM_PARAMS), _stream(out.device)))
+    return out
+
+
+def _render_common(params, nebula, n_samples, offsets, voice_ids, first_g, noise_seed, mix_mode,
+                   sample_rate, control_rate, out):
+    B = params.shape[0]
+    cfg, keep = _native.make_config(nebula, sample_rate, control_rate, noise_seed, mix_mode)
+    if offsets is not None:
+        total = int(offsets[-1].item()) if out is None else out.numel()
+    else:
+        total = B * int(n_samples)
+    if out is None:
+        out = torch.empty(total, dtype=torch.float32, device=params.device)
+    args = (cfg, _dev_ptr(params, "params", torch.float32, B * NUM_PARAMS),
+            _dev_ptr(voice_ids, "voice_ids", torch.uint64, B) if voice_ids is not None else None,
+            int(first_g), int(B),
+            _dev_ptr(offsets, "offsets", torch.int64, B + 1) if offsets is not None else None,
+            int(n_samples) if offsets is None else 0,
+            _dev_ptr(out, "audio", torch.float32, total))
+    return args, out, keep
+
+
+def synth_render(params: torch.Tensor, nebula, n_samples: int | None = None,
+                 offsets: torch.Tensor | None = None, voice_ids: torch.Tensor | None = None,
+                 first_g: int = 0, noise_seed: int = 0, mix_mode: int = 0,
+                 sample_rate: float = 44100.0, control_rate: float = 441.0,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    """Render B voices.  Uniform: returns [B, n_samples]; ragged (offsets given):
+    returns the packed 1-D buffer of offsets[-1] samples."""
+    args, out, keep = _render_common(params, nebula, n_samples, offsets, voice_ids, first_g,
+                                     noise_seed, mix_mode, sample_rate, control_rate, out)
+    st = _native.lib().synth_render(ctypes_ref(args[0]), *args[1:], _stream(params.device))
+    _native.check("synth_render", st)
+    del keep
+    if offsets is None:
+        return out.view(params.shape[0], int(n_samples))
+    return out
+
+
+def synth_render_plan(params: torch.Tensor, nebula, runs_per_segment: int, slices_per_voice: int,
+                      persistent: bool = False, grid_blocks: int = 0, n_samples: int | None = None,
+                      offsets: torch.Tensor | None = None, voice_ids: torch.Tensor | None = None,
+                      first_g: int = 0, noise_seed: int = 0, mix_mode: int = 0,
+                      sample_rate: float = 44100.0, control_rate: float = 441.0,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+    args, out, keep = _render_common(params, nebula, n_samples, offsets, voice_ids, first_g,
+                                     noise_seed, mix_mode, sample_rate, control_rate, out)
+    st = _native.lib().synth_render_plan(ctypes_ref(args[0]), *args[1:], int(runs_per_segment),
+                                         int(slices_per_voice), int(bool(persistent)),
+                                         int(grid_blocks), _stream(params.device))
+    _native.check("synth_render_plan", st)
+    del keep
+    if offsets is None:
+        return out.view(params.shape[0], int(n_samples))
+    return out
+
+
+def ctypes_ref(cfg):
+    import ctypes
+    return ctypes.byref(cfg)
