@@ -18,9 +18,13 @@ LIB = os.path.join(PKG, "libsynth.so")
 SOURCES = ["api.cpp", "params.hip", "render.hip"]
 
 # Packed-FP32 instructions are disabled for all device code (plain float code
-# is scheduled onto the non-packed VALU).
+# is scheduled onto the non-packed VALU).  Machine LICM is disabled: it hoists
+# the float64 constants of the once-per-voice exp2/log2/pow code out of every
+# loop and keeps them live across the audio-rate loops, which doubles the
+# render kernel's VGPR count (200 -> 112) and halves its occupancy.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-mllvm", "-disable-machine-licm",
              "-Wno-unused-command-line-argument"]
 
 

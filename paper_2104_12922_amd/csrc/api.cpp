@@ -51,6 +51,7 @@ int prepare(const synth_config* cfg, RenderArgs* a, bool* clamp) {
   a->sr = sr;
   a->rc = rc;
   a->q = q;
+  a->q_magic = (uint32_t)((((uint64_t)1 << 32) + (uint64_t)q - 1) / (uint64_t)q);
   a->mix_mode = cfg->mix_mode;
   a->nk0 = (uint32_t)cfg->noise_seed;
   a->nk1 = (uint32_t)(cfg->noise_seed >> 32);

@@ -17,10 +17,10 @@
 //                   samples of one segment: float64 phase recurrence, half-cycle
 //                   range reduction, float32 sine, tanh-waveshaped square-saw,
 //                   VCAs, mixer; the result goes to an LDS tile.
-//   store pass      each lane takes 8 consecutive tile samples, adds the noise
+//   store pass      each lane takes 4 consecutive tile samples, adds the noise
 //                   oscillator (one Philox call gives 8 16-bit noise samples)
-//                   through its VCA, and writes them with two 16-byte stores,
-//                   so each store instruction covers 2 KB of contiguous audio.
+//                   through its VCA, and writes them with one 16-byte store, so
+//                   each store instruction covers 1 KB of contiguous audio.
 // Segments at or after the end of the longest release are exactly silent
 // (every envelope is 0 there): they are zero-filled without computation.
 #include <math.h>
@@ -40,23 +40,14 @@ constexpr double kLn2 = 0.693147180559945309417232121458;
 // ---------------------------------------------------------------------------
 // float64 control-rate helpers
 // ---------------------------------------------------------------------------
+// x^e for x in [0, 1] (0^e = 0, 1^e = 1 without evaluating exp2/log2).
 __device__ __forceinline__ double pow01(double x, double e) {
-  return x <= 0.0 ? 0.0 : (x >= 1.0 ? 1.0 : pow(x, e));
+  return x <= 0.0 ? 0.0 : (x >= 1.0 ? 1.0 : exp2(e * log2(x)));
 }
 
-__device__ __forceinline__ double ramp(double j, double start, double len) {
-  return len > 0.0 ? fmin(fmax((j - start) / len, 0.0), 1.0) : (j >= start ? 1.0 : 0.0);
-}
-
-// ADSR (attack, decay, release and note-off in control samples): product of
-// the attack rise, the decay fall towards sustain and the release fall, each
-// ramp raised to the curve exponent alpha.
-__device__ __forceinline__ double adsr(double j, double A, double D, double S, double R,
-                                       double alpha, double O) {
-  const double att = ramp(j, 0.0, A);
-  const double dec = ramp(j, A, D);
-  const double rel = ramp(j, O, R);
-  return pow01(att, alpha) * (S + (1.0 - S) * pow01(1.0 - dec, alpha)) * pow01(1.0 - rel, alpha);
+// clamp((j - start) / len, 0, 1); len == 0 is the step [j >= start].
+__device__ __forceinline__ double ramp(double j, double start, double len, double inv_len) {
+  return len > 0.0 ? fmin(fmax((j - start) * inv_len, 0.0), 1.0) : (j >= start ? 1.0 : 0.0);
 }
 
 __device__ __forceinline__ bool bit(const uint32_t* w, int p) { return (w[p >> 5] >> (p & 31)) & 1u; }
@@ -66,10 +57,10 @@ __device__ __forceinline__ bool bit(const uint32_t* w, int p) { return (w[p >> 5
 __device__ double map_param(double u, int p, const NebulaArgs& nb) {
   const double lo = nb.lo[p], span = nb.hi[p] - nb.lo[p];
   const bool lin = bit(nb.linear, p);
-  if (!bit(nb.sym, p)) return lo + span * (lin ? u : pow01(u, nb.inv_curve[p]));
+  if (!bit(nb.sym, p)) return lo + span * (lin ? u : pow(u, nb.inv_curve[p]));
   const double d = 2.0 * u - 1.0;
   const double ad = fabs(d);
-  const double w = lin ? ad : pow01(ad, nb.inv_curve[p]);
+  const double w = lin ? ad : pow(ad, nb.inv_curve[p]);
   const double sg = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
   return lo + span * (1.0 + sg * w) / 2.0;
 }
@@ -111,7 +102,7 @@ __device__ __forceinline__ void sincos_cycles(double th, float& s, float& c) {
   pc = fmaf(x2, pc, -0.5f);
   const float sn = fmaf(x * x2, ps, x);
   const float cs = fmaf(x2, pc, 1.0f);
-  const bool odd = ((long long)n) & 1;
+  const bool odd = ((int)n) & 1;     // |n| < 2^31: th stays below 2^29 cycles within a chunk
   s = odd ? -sn : sn;
   c = odd ? -cs : cs;
 }
@@ -126,7 +117,7 @@ __device__ __forceinline__ float sin_cycles(double th) {
   ps = fmaf(x2, ps, 8.33333333333333333333e-3f);
   ps = fmaf(x2, ps, -1.66666666666666666667e-1f);
   const float sn = fmaf(x * x2, ps, x);
-  return (((long long)n) & 1) ? -sn : sn;
+  return (((int)n) & 1) ? -sn : sn;
 }
 
 // tanh(z) = sign(z) (1 - e) / (1 + e), e = exp(-2|z|) = 2^(-2 log2(e) |z|).
@@ -143,19 +134,7 @@ __device__ __forceinline__ float squaresaw(double th, float K, float shape, floa
   return gain * tanh_f(K * s) * fmaf(shape, c, 1.0f);
 }
 
-__device__ __forceinline__ void store8(float* dst, const float* o, int64_t valid, bool aligned) {
-  if (valid >= 8 && aligned) {
-    float4* d4 = reinterpret_cast<float4*>(dst);
-    d4[0] = make_float4(o[0], o[1], o[2], o[3]);
-    d4[1] = make_float4(o[4], o[5], o[6], o[7]);
-  } else {
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      if (e < valid) dst[e] = o[e];
-  }
-}
-
-// Zero out[z0, z1) with all 64 lanes (z0 a multiple of 8).
+// Zero out[z0, z1) with all 64 lanes (z0 a multiple of 4).
 __device__ void zero_fill(float* out, int64_t z0, int64_t z1, int lane, bool aligned) {
   if (z1 <= z0) return;
   if (aligned) {
@@ -169,9 +148,23 @@ __device__ void zero_fill(float* out, int64_t z0, int64_t z1, int lane, bool ali
   }
 }
 
+// Per-voice constants derived once from the parameters (LDS, read by every lane).
+enum {
+  kEnvA = 0, kEnvInvA = 6, kEnvD = 12, kEnvInvD = 18, kEnvR = 24, kEnvInvR = 30, kEnvS = 36,
+  kEnvAlpha = 42, kLfoInvW = 48, kMixInvNorm = 50, kDerived = 56
+};
+
+// Per-segment oscillator data of a chunk, one row per VCO.
+enum { kSegTheta = 0, kSegInc = 1, kSegRatio = 2, kSegRunSum = 3, kSegRunRatio = 4, kSegFields = 5 };
+
 struct VoiceShared {
   double v[kNumParams];        // human-readable parameter values
-  float2 namp[kWave];          // per segment of the chunk: noise VCA (start, slope) * level
+  double d[kDerived];          // derived per-voice constants (enum above)
+  double seg[2][kSegFields][kWave];   // per VCO and segment: start phase (cycles, in [0,1)),
+                                      // start increment, per-sample ratio, first-run sum,
+                                      // per-run ratio
+  double carry[4];             // phase carries (cycles): LFO 1, LFO 2, VCO 1, VCO 2
+  float2 namp[kWave];          // per segment of the chunk: noise VCA (start, slope) * level * 2^-15
 };
 
 template <int RPS, bool CLAMP>
@@ -195,19 +188,40 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
   const uint64_t g = a.voice_ids ? a.voice_ids[b] : a.first_g + (uint64_t)b;
   float* out = a.audio + off0;
   const bool aligned = (reinterpret_cast<uintptr_t>(out) & 15u) == 0;
+  const double rc = a.rc, sr = a.sr;
 
   __syncthreads();
   for (int p = lane; p < kNumParams; p += kWave)
     sh.v[p] = map_param((double)a.params[b * kNumParams + p], p, a.neb);
   __syncthreads();
   const double* v = sh.v;
+  if (lane < 6) {                    // envelope k: durations in control samples
+    const int pb = 2 + 5 * lane;
+    const double A = v[pb] * rc, D = v[pb + 1] * rc, R = v[pb + 3] * rc;
+    sh.d[kEnvA + lane] = A;
+    sh.d[kEnvInvA + lane] = 1.0 / A;
+    sh.d[kEnvD + lane] = D;
+    sh.d[kEnvInvD + lane] = 1.0 / D;
+    sh.d[kEnvR + lane] = R;
+    sh.d[kEnvInvR + lane] = 1.0 / R;
+    sh.d[kEnvS + lane] = v[pb + 2];
+    sh.d[kEnvAlpha + lane] = v[pb + 4];
+  } else if (lane < 8) {             // LFO: 1 / sum of shape weights (0 if none)
+    const int pb = 32 + 8 * (lane - 6);
+    const double ws = v[pb + 3] + v[pb + 4] + v[pb + 5] + v[pb + 6] + v[pb + 7];
+    sh.d[kLfoInvW + lane - 6] = ws > 0.0 ? 1.0 / ws : 0.0;
+  } else if (lane < 13) {            // modulation mixer row: 1 / max(1, sum of gains)
+    const int pb = 48 + 4 * (lane - 8);
+    sh.d[kMixInvNorm + lane - 8] = 1.0 / fmax(1.0, v[pb] + v[pb + 1] + v[pb + 2] + v[pb + 3]);
+  }
+  __syncthreads();
+  const double* dv = sh.d;
 
   const int64_t J = (N + q - 1) / q;     // control samples == segments
   const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
   const int64_t c_lo = nchunks * slice / a.slices;
   const int64_t c_hi = nchunks * (slice + 1) / a.slices;
 
-  const double rc = a.rc, sr = a.sr;
   const double note_off = v[1] * rc;
   // Every envelope is exactly 0 from control sample js on: the release ramp
   // has reached 1 (at least one control sample past note-off + release).
@@ -228,13 +242,12 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
   const double L1 = v[75], L2 = v[76], L3 = v[77];
 
   // phase carries in cycles, reduced mod 1 at every chunk boundary
-  double lfo_carry[2] = {v[34] / kTwoPi, v[42] / kTwoPi};
-  double vco_carry[2] = {v[70] / kTwoPi, v[73] / kTwoPi};
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    lfo_carry[i] -= floor(lfo_carry[i]);
-    vco_carry[i] -= floor(vco_carry[i]);
+  if (lane < 4) {
+    const double ph0 = v[lane == 0 ? 34 : lane == 1 ? 42 : lane == 2 ? 70 : 73] / kTwoPi;
+    sh.carry[lane] = ph0 - floor(ph0);
   }
+  __syncthreads();
+  const uint32_t glo = (uint32_t)g, ghi = (uint32_t)(g >> 32);
 
   for (int64_t c = 0; c < c_hi; ++c) {
     if (c >= c_sil) {
@@ -246,60 +259,70 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
     // ---------------- control stage: lane = control sample j ----------------
     const int64_t j = c * kSegsPerChunk + lane;
     const double jd = (double)j;
-    double env[6];
-#pragma unroll
+    // Envelopes go through LDS (the tile is idle during the control stage), one
+    // at a time, which keeps the float64 exp2/log2 chains from being interleaved.
+    double* envs = reinterpret_cast<double*>(tile);
+#pragma unroll 1
     for (int k = 0; k < 6; ++k) {
-      const int pb = 2 + 5 * k;
-      env[k] = adsr(jd, v[pb] * rc, v[pb + 1] * rc, v[pb + 2], v[pb + 3] * rc, v[pb + 4], note_off);
+      // ADSR: attack rise, decay fall towards sustain, release fall from note-off,
+      // each ramp raised to the curve exponent alpha.
+      const double A = dv[kEnvA + k], D = dv[kEnvD + k], R = dv[kEnvR + k];
+      const double S = dv[kEnvS + k], al = dv[kEnvAlpha + k];
+      const double att = ramp(jd, 0.0, A, dv[kEnvInvA + k]);
+      const double dec = ramp(jd, A, D, dv[kEnvInvD + k]);
+      const double rel = ramp(jd, note_off, R, dv[kEnvInvR + k]);
+      envs[k * kWave + lane] =
+          pow01(att, al) * (S + (1.0 - S) * pow01(1.0 - dec, al)) * pow01(1.0 - rel, al);
     }
-    double x[4] = {env[0], env[1], 0.0, 0.0};
-#pragma unroll
+    // LFOs (rate ADSR modulates the rate; amp ADSR is a control-rate VCA),
+    // written next to the envelopes: lfo'_i at envs[(6 + i) * 64 + lane].
+#pragma unroll 1
     for (int i = 0; i < 2; ++i) {
       const int pb = 32 + 8 * i;
-      const double f = fmax(0.0, v[pb] + v[pb + 1] * env[2 + 2 * i]);
+      const double f = fmax(0.0, v[pb] + v[pb + 1] * envs[(2 + 2 * i) * kWave + lane]);
       const double inc = lane < kPointsPerChunk - 1 ? f / rc : 0.0;
-      const double th = lfo_carry[i] + wave_excl_scan(inc, lane);
+      const double th = sh.carry[i] + wave_excl_scan(inc, lane);
       const double ph = th - floor(th);
-      const double w0 = v[pb + 3], w1 = v[pb + 4], w2 = v[pb + 5], w3 = v[pb + 6], w4 = v[pb + 7];
-      const double wsum = w0 + w1 + w2 + w3 + w4;
-      const double num = w0 * ((1.0 + sin(kTwoPi * ph)) / 2.0) + w1 * (1.0 - fabs(2.0 * ph - 1.0)) +
-                         w2 * ph + w3 * (1.0 - ph) + w4 * (ph < 0.5 ? 1.0 : 0.0);
-      const double l = wsum > 0.0 ? num / wsum : 0.0;
-      x[2 + i] = l * env[3 + 2 * i];                 // control-rate VCA (amp ADSR)
-      const double nc = __shfl(th, kSegsPerChunk);   // phase at the next chunk's first point
-      lfo_carry[i] = nc - floor(nc);
+      const double num = v[pb + 3] * ((1.0 + sinpi(2.0 * ph)) / 2.0) +
+                         v[pb + 4] * (1.0 - fabs(2.0 * ph - 1.0)) + v[pb + 5] * ph +
+                         v[pb + 6] * (1.0 - ph) + v[pb + 7] * (ph < 0.5 ? 1.0 : 0.0);
+      envs[(6 + i) * kWave + lane] = (num * dv[kLfoInvW + i]) * envs[(3 + 2 * i) * kWave + lane];
+      const double nc = __shfl(th, kSegsPerChunk);            // phase at the next chunk's first point
+      __syncthreads();
+      if (lane == 0) sh.carry[i] = nc - floor(nc);
     }
+    // modulation mixer: inputs adsr_1, adsr_2, lfo'_1, lfo'_2
+    const double x0 = envs[lane], x1 = envs[kWave + lane];
+    const double x2 = envs[6 * kWave + lane], x3 = envs[7 * kWave + lane];
     double y[5], yn[5];
     const bool last = (j + 1 >= J);                  // right end held at the last control sample
 #pragma unroll
     for (int o = 0; o < 5; ++o) {
       const int pb = 48 + 4 * o;
-      const double gs = v[pb] + v[pb + 1] + v[pb + 2] + v[pb + 3];
-      const double acc = v[pb] * x[0] + v[pb + 1] * x[1] + v[pb + 2] * x[2] + v[pb + 3] * x[3];
-      y[o] = acc / fmax(1.0, gs);
+      const double acc = v[pb] * x0 + v[pb + 1] * x1 + v[pb + 2] * x2 + v[pb + 3] * x3;
+      y[o] = acc * dv[kMixInvNorm + o];
     }
 #pragma unroll
     for (int o = 0; o < 5; ++o) {
       const double t = __shfl_down(y[o], 1);
       yn[o] = last ? y[o] : t;
     }
-    // per segment (lane < 62): pitch glide, phase advance, VCA ramps
-    double thS[2], inc0[2], rr[2], Sh[2], Rh[2];
-#pragma unroll
+    // per segment (lane < 62): pitch glide, phase advance; one VCO at a time
+#pragma unroll 1
     for (int vc = 0; vc < 2; ++vc) {
       const int tb = vc ? 71 : 68;
-      const int yo = vc ? 2 : 0;
+      const double ya = vc ? y[2] : y[0];
+      const double yb = vc ? yn[2] : yn[0];
       const double base = midi + v[tb];
-      const double m0 = base + v[tb + 1] * y[yo];
-      const double m1 = base + v[tb + 1] * yn[yo];
+      const double m0 = base + v[tb + 1] * ya;
+      const double m1 = base + v[tb + 1] * yb;
       const double i0 = 440.0 * exp2((m0 - 69.0) / 12.0) / sr;
       const double Lr = (m1 - m0) * (kLn2 / (12.0 * qd));   // log of the per-sample ratio
       const double e1 = expm1(Lr);
       const double eh = expm1(Lr * hd);
-      inc0[vc] = i0;
-      rr[vc] = 1.0 + e1;
-      Rh[vc] = 1.0 + eh;
-      Sh[vc] = (e1 == 0.0) ? i0 * hd : i0 * (eh / e1);
+      const double rr = 1.0 + e1;
+      const double Rh = 1.0 + eh;
+      const double Sh = (e1 == 0.0) ? i0 * hd : i0 * (eh / e1);
       double S;
       if constexpr (CLAMP) {
         // some increments may exceed 1/2 cycle (f > sr/2): sum them one by one
@@ -307,29 +330,35 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
         double inc = i0;
         for (int k = 0; k < q; ++k) {
           S += fmin(inc, 0.5);
-          inc *= rr[vc];
+          inc *= rr;
         }
       } else {
-        S = Sh[vc];
-        double t = Sh[vc];
+        S = Sh;
+        double t = Sh;
 #pragma unroll
         for (int m = 1; m < RPS; ++m) {
-          t *= Rh[vc];
+          t *= Rh;
           S += t;
         }
       }
-      const double th = vco_carry[vc] + wave_excl_scan(lane < kSegsPerChunk ? S : 0.0, lane);
-      thS[vc] = th - floor(th);
+      const double th = sh.carry[2 + vc] + wave_excl_scan(lane < kSegsPerChunk ? S : 0.0, lane);
+      sh.seg[vc][kSegTheta][lane] = th - floor(th);
+      sh.seg[vc][kSegInc][lane] = i0;
+      sh.seg[vc][kSegRatio][lane] = rr;
+      sh.seg[vc][kSegRunSum][lane] = Sh;
+      sh.seg[vc][kSegRunRatio][lane] = Rh;
       const double nc = __shfl(th, kSegsPerChunk);
-      vco_carry[vc] = nc - floor(nc);
+      __syncthreads();
+      if (lane == 0) sh.carry[2 + vc] = nc - floor(nc);
     }
     if (c < c_lo) continue;                      // slice starts later: only carries needed
 
     const float a10 = (float)(L1 * y[1]), a1d = (float)(L1 * (yn[1] - y[1]) / qd);
     const float a20 = (float)(L2 * y[3]), a2d = (float)(L2 * (yn[3] - y[3]) / qd);
     __syncthreads();                             // previous chunk's readers of namp are done
-    if (lane < kSegsPerChunk)
-      sh.namp[lane] = make_float2((float)(L3 * y[4]), (float)(L3 * (yn[4] - y[4]) / qd));
+    if (lane < kSegsPerChunk)                    // noise VCA ramp, pre-scaled by the 2^-15 of the noise map
+      sh.namp[lane] = make_float2((float)(L3 * y[4]) * (1.0f / 32768.0f),
+                                  (float)(L3 * (yn[4] - y[4]) / qd) * (1.0f / 32768.0f));
     __syncthreads();
 
     // ---------------- oscillator and store passes ----------------
@@ -341,8 +370,9 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
       const int ls = p * segs_pp + lane / RPS;   // chunk-local segment of this lane's run
       const int m = lane % RPS;                  // run within the segment
       const int src = ls < kWave ? ls : kWave - 1;
-      double t1 = __shfl(thS[0], src), i1 = __shfl(inc0[0], src), r1 = __shfl(rr[0], src);
-      double t2 = __shfl(thS[1], src), i2 = __shfl(inc0[1], src), r2 = __shfl(rr[1], src);
+      double t1 = sh.seg[0][kSegTheta][src], i1 = sh.seg[0][kSegInc][src];
+      double t2 = sh.seg[1][kSegTheta][src], i2 = sh.seg[1][kSegInc][src];
+      const double r1 = sh.seg[0][kSegRatio][src], r2 = sh.seg[1][kSegRatio][src];
       const float A10 = __shfl(a10, src), A1d = __shfl(a1d, src);
       const float A20 = __shfl(a20, src), A2d = __shfl(a2d, src);
       if constexpr (CLAMP) {
@@ -351,8 +381,8 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
           t2 += fmin(i2, 0.5); i2 *= r2;
         }
       } else {
-        double s1 = __shfl(Sh[0], src), R1 = __shfl(Rh[0], src);
-        double s2 = __shfl(Sh[1], src), R2 = __shfl(Rh[1], src);
+        double s1 = sh.seg[0][kSegRunSum][src], R1 = sh.seg[0][kSegRunRatio][src];
+        double s2 = sh.seg[1][kSegRunSum][src], R2 = sh.seg[1][kSegRunRatio][src];
         for (int t = 0; t < m; ++t) {
           t1 += s1; s1 *= R1; i1 *= R1;
           t2 += s2; s2 *= R2; i2 *= R2;
@@ -376,33 +406,48 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
         kf += 1.0f;
       }
       __syncthreads();
+      // Store pass: noise + VCA, 4 consecutive samples per lane per 16-byte store.
+      // Every lane computes one Philox call (8 noise samples) per 512 samples;
+      // lane l's 4 samples of each 256-sample half take two of its group's
+      // words from the lane that drew them.  4 samples never straddle a
+      // segment because q is a multiple of 4.
       const int64_t pbase = (c * kSegsPerChunk + (int64_t)p * segs_pp) * q;
-      int64_t cnt = (int64_t)((nseg - p * segs_pp) < segs_pp ? (nseg - p * segs_pp) : segs_pp) * q;
-      if (cnt > N - pbase) cnt = N - pbase;
-      const int ngroups = (int)((cnt + 7) / 8);
-      for (int gi = lane; gi < ngroups; gi += kWave) {
-        const int64_t n = pbase + 8 * (int64_t)gi;
-        uint32_t w[4] = {(uint32_t)g, (uint32_t)(g >> 32), (uint32_t)(n >> 3), 1u};
+      int64_t cnt64 = (int64_t)((nseg - p * segs_pp) < segs_pp ? (nseg - p * segs_pp) : segs_pp) * q;
+      if (cnt64 > N - pbase) cnt64 = N - pbase;
+      const int cnt = (int)cnt64;
+      const uint32_t grp0 = (uint32_t)(pbase >> 3);
+      const int seg0 = p * segs_pp;
+      for (int base = 0; base < cnt; base += 512) {
+        uint32_t w[4] = {glo, ghi, grp0 + (uint32_t)(base >> 3) + (uint32_t)lane, 1u};
         philox4x32_10(w, a.nk0, a.nk1);
-        const int cl = p * segs_pp * q + 8 * gi;     // chunk-local sample
-        int sg = cl / q;
-        int kk = cl - sg * q;
-        float2 na = sh.namp[sg];
-        float o[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          if (kk == q) {
-            kk = 0;
-            ++sg;
-            na = sh.namp[sg < kWave ? sg : kWave - 1];
+        for (int sub = 0; sub < 2; ++sub) {
+          const int src_l = sub * 32 + (lane >> 1);
+          const uint32_t w0 = __shfl(w[0], src_l), w1 = __shfl(w[1], src_l);
+          const uint32_t w2 = __shfl(w[2], src_l), w3 = __shfl(w[3], src_l);
+          const uint32_t wa = (lane & 1) ? w2 : w0;
+          const uint32_t wb = (lane & 1) ? w3 : w1;
+          const int li = base + sub * 256 + 4 * lane;   // pass-local sample
+          if (li < cnt) {
+            const int lsg = (int)__umulhi((uint32_t)li, a.q_magic);   // li / q
+            const float kf0 = (float)(li - lsg * q);
+            const float2 na = sh.namp[seg0 + lsg];
+            const float4 t4 = *reinterpret_cast<const float4*>(tile + li);
+            float o[4];
+            o[0] = fmaf((float)(wa & 0xFFFFu) - 32767.5f, fmaf(kf0, na.y, na.x), t4.x);
+            o[1] = fmaf((float)(wa >> 16) - 32767.5f, fmaf(kf0 + 1.0f, na.y, na.x), t4.y);
+            o[2] = fmaf((float)(wb & 0xFFFFu) - 32767.5f, fmaf(kf0 + 2.0f, na.y, na.x), t4.z);
+            o[3] = fmaf((float)(wb >> 16) - 32767.5f, fmaf(kf0 + 3.0f, na.y, na.x), t4.w);
+            float* dst = out + pbase + li;
+            if (aligned && li + 4 <= cnt) {
+              *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
+            } else {
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                if (li + e < cnt) dst[e] = o[e];
+            }
           }
-          const uint32_t hw = (w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-          const float x3 = ((float)hw - 32767.5f) * (1.0f / 32768.0f);
-          const float an = fmaf((float)kk, na.y, na.x);
-          o[e] = fmaf(an, x3, tile[8 * gi + e]);
-          ++kk;
         }
-        store8(out + n, o, cnt - 8 * (int64_t)gi, aligned);
       }
       __syncthreads();
     }
@@ -412,7 +457,7 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
 template <int RPS, bool CLAMP>
 __global__ void __launch_bounds__(kWave) render_kernel(const RenderArgs a) {
   __shared__ VoiceShared sh;
-  extern __shared__ float tile[];
+  extern __shared__ __align__(16) float tile[];
   const int64_t nitems = a.batch * a.slices;
   for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x)
     render_item<RPS, CLAMP>(a, item / a.slices, (int)(item % a.slices), sh, tile);
@@ -447,7 +492,10 @@ __global__ void __launch_bounds__(256) peak_normalise_kernel(const RenderArgs a)
 
 template <int RPS>
 hipError_t launch_rps(const RenderArgs& a, bool clamp, int grid, hipStream_t s) {
-  const size_t shmem = (size_t)kWave * (a.q / RPS) * sizeof(float);
+  // LDS tile: one run of q / RPS floats per lane; it also holds the six
+  // float64 envelopes and two LFO outputs of the control stage.
+  size_t shmem = (size_t)kWave * (a.q / RPS) * sizeof(float);
+  if (shmem < 8 * kWave * sizeof(double)) shmem = 8 * kWave * sizeof(double);
   if (clamp)
     hipLaunchKernelGGL((render_kernel<RPS, true>), dim3(grid), dim3(kWave), shmem, s, a);
   else

@@ -30,6 +30,7 @@ struct RenderArgs {
   double rc;                 // control rate
   double nyq_midi;           // pitch (MIDI) above which f > sr / 2
   int q;                     // audio samples per control sample
+  uint32_t q_magic;          // ceil(2^32 / q): x / q == umulhi(x, q_magic) for x < 2^16
   int slices;                // workgroups per voice (uniform lengths only)
   int persistent_grid;       // >0: workgroup w renders voices w, w+grid, ...
   int mix_mode;
