@@ -112,6 +112,20 @@ int synth_render_plan(const synth_config* cfg, const float* params, const uint64
                       float* audio, int runs_per_segment, int slices_per_voice,
                       int persistent, int grid_blocks, void* stream);
 
+/* Multi-resolution log-magnitude STFT L1 loss (Section 4.3: multi-scale
+ * spectrogram distance, L1), per voice, and optionally its gradient.
+ *   For voice b: loss[b] = sum over n in (512, 1024, 2048), hop n/4, of the mean
+ *   over frames t < F_n = floor((N - n) / hop) + 1 and bins k <= n/2 of
+ *   |log(|X_tk| + 1e-5) - log(|T_tk| + 1e-5)|, X and T the periodic-Hann STFTs
+ *   (frames start at t * hop, no padding) of x and target.
+ *   x, target  dev float32 [batch][n_samples].
+ *   loss       dev float64 [batch], written.
+ *   grad_x     dev float32 [batch][n_samples] or NULL; if given it receives
+ *              d loss[b] / d x[b][.] (float32 FFT arithmetic).
+ *   n_samples  > 0, <= 2^31.  Bitwise deterministic. */
+int synth_mrstft_loss(const float* x, const float* target, int64_t batch, int64_t n_samples,
+                      double* loss, float* grad_x, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

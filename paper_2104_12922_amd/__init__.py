@@ -17,6 +17,7 @@ from . import _native
 NUM_PARAMS = _native.NUM_PARAMS
 
 __all__ = ["synth_sample_params", "synth_render", "synth_render_plan", "synth_is_test",
+           "synth_mrstft_loss",
            "NUM_PARAMS", "SynthError"]
 
 SynthError = _native.SynthError
@@ -114,6 +115,21 @@ def synth_render_plan(params: torch.Tensor, nebula, runs_per_segment: int, slice
     if offsets is None:
         return out.view(params.shape[0], int(n_samples))
     return out
+
+
+def synth_mrstft_loss(x: torch.Tensor, target: torch.Tensor, grad: bool = False):
+    """Per-voice multi-resolution log-magnitude STFT L1 (float64 [B]) and, if
+    grad, d loss[b] / d x[b] (float32 [B, N]) - see synth.h."""
+    if x.shape != target.shape or x.dim() != 2:
+        raise ValueError("x and target must both be [B, N]")
+    B, N = x.shape
+    loss = torch.empty(B, dtype=torch.float64, device=x.device)
+    g = torch.empty_like(x) if grad else None
+    _native.check("synth_mrstft_loss", _native.lib().synth_mrstft_loss(
+        _dev_ptr(x, "x", torch.float32, B * N), _dev_ptr(target, "target", torch.float32, B * N),
+        B, N, _dev_ptr(loss, "loss", torch.float64, B),
+        _dev_ptr(g, "grad", torch.float32, B * N) if grad else None, _stream(x.device)))
+    return (loss, g) if grad else loss
 
 
 def ctypes_ref(cfg):

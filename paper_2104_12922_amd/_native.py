@@ -55,6 +55,10 @@ def lib() -> ctypes.CDLL:
         L.synth_render.argtypes = render_args + [ctypes.c_void_p]
         L.synth_render_plan.restype = ctypes.c_int
         L.synth_render_plan.argtypes = render_args + [ctypes.c_int] * 4 + [ctypes.c_void_p]
+        L.synth_mrstft_loss.restype = ctypes.c_int
+        L.synth_mrstft_loss.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]
         _lib = L
     return _lib
 

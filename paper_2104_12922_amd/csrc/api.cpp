@@ -170,4 +170,14 @@ int synth_render(const synth_config* cfg, const float* params, const uint64_t* v
                            slices, 0, 0, stream);
 }
 
+int synth_mrstft_loss(const float* x, const float* target, int64_t batch, int64_t n_samples,
+                      double* loss, float* grad_x, void* stream) {
+  if (batch < 0 || n_samples <= 0 || n_samples > ((int64_t)1 << 31)) return SYNTH_EINVAL;
+  if (batch == 0) return SYNTH_OK;
+  if (!x || !target || !loss) return SYNTH_EINVAL;
+  if (batch > 0x7FFFFFFF) return SYNTH_EINVAL;
+  return to_status(synth::launch_mrstft(x, target, batch, n_samples, loss, grad_x,
+                                        (hipStream_t)stream));
+}
+
 }  // extern "C"

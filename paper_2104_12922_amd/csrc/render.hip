@@ -80,58 +80,64 @@ __device__ __forceinline__ double wave_excl_scan(double x, int lane) {
 // ---------------------------------------------------------------------------
 // float32 audio-rate helpers
 // ---------------------------------------------------------------------------
-// sin and cos of 2*pi*th.  th (cycles, float64) is reduced to the nearest half
-// cycle in float64, r = th - n/2 in [-1/4, 1/4] (exact), so sin(2 pi th) =
-// (-1)^n sin(2 pi r) is evaluated with a relative (not only absolute) error of
-// ~1e-7 near every zero crossing - the square-saw's tanh edge amplifies the
-// sine by up to ~1600 there.  Taylor polynomials of sin x (to x^11) and cos x
-// (to x^12) on |x| <= pi/2: truncation below 6e-8.
+// sin(2 pi th) for the sine VCO: th (cycles, float64) is reduced to the
+// nearest integer in float64, r = th - rint(th) in [-1/2, 1/2], and the
+// hardware sine (input in revolutions, absolute error ~1.3e-7 on [-1/2, 1/2])
+// is evaluated on float(r).
+__device__ __forceinline__ float sin_cycles(double th) {
+  const float r = (float)(th - rint(th));
+  return __builtin_amdgcn_sinf(r);
+}
+
+// sin and cos of 2 pi th for the square-saw.  Its tanh edge multiplies the
+// sine by K (up to ~1600) at every zero crossing, so the sine must be
+// relatively accurate there, at th = 0 and th = 1/2 alike: th is reduced to
+// the nearest half cycle in float64, r = th - n/2 in [-1/4, 1/4] (exact),
+// sin(2 pi th) = (-1)^n sin(2 pi r), cos(2 pi th) = (-1)^n cos(2 pi r).  The
+// hardware sine has ~9e-7 relative error near 0, which moves tanh(K sin) by
+// at most ~4e-7.
 __device__ __forceinline__ void sincos_cycles(double th, float& s, float& c) {
   const double n = rint(2.0 * th);
   const float r = (float)fma(-0.5, n, th);
-  const float x = r * 6.28318530717958647692f;
-  const float x2 = x * x;
-  float ps = fmaf(x2, -2.50521083854417187751e-8f, 2.75573192239858906526e-6f);
-  ps = fmaf(x2, ps, -1.98412698412698412698e-4f);
-  ps = fmaf(x2, ps, 8.33333333333333333333e-3f);
-  ps = fmaf(x2, ps, -1.66666666666666666667e-1f);
-  float pc = fmaf(x2, 2.08767569878680989792e-9f, -2.75573192239858906526e-7f);
-  pc = fmaf(x2, pc, 2.48015873015873015873e-5f);
-  pc = fmaf(x2, pc, -1.38888888888888888889e-3f);
-  pc = fmaf(x2, pc, 4.16666666666666666667e-2f);
-  pc = fmaf(x2, pc, -0.5f);
-  const float sn = fmaf(x * x2, ps, x);
-  const float cs = fmaf(x2, pc, 1.0f);
-  const bool odd = ((int)n) & 1;     // |n| < 2^31: th stays below 2^29 cycles within a chunk
-  s = odd ? -sn : sn;
-  c = odd ? -cs : cs;
+  const uint32_t flip = ((uint32_t)(int)n) << 31;     // sign bit of (-1)^n
+  s = __uint_as_float(__float_as_uint(__builtin_amdgcn_sinf(r)) ^ flip);
+  c = __uint_as_float(__float_as_uint(__builtin_amdgcn_cosf(r)) ^ flip);
 }
 
-__device__ __forceinline__ float sin_cycles(double th) {
-  const double n = rint(2.0 * th);
-  const float r = (float)fma(-0.5, n, th);
-  const float x = r * 6.28318530717958647692f;
-  const float x2 = x * x;
-  float ps = fmaf(x2, -2.50521083854417187751e-8f, 2.75573192239858906526e-6f);
-  ps = fmaf(x2, ps, -1.98412698412698412698e-4f);
-  ps = fmaf(x2, ps, 8.33333333333333333333e-3f);
-  ps = fmaf(x2, ps, -1.66666666666666666667e-1f);
-  const float sn = fmaf(x * x2, ps, x);
-  return (((int)n) & 1) ? -sn : sn;
+// tanh(z) = 1 - 2 / (exp(2z) + 1) from z2 = 2 log2(e) z; saturates to +-1
+// through exp2 overflow or underflow, absolute error ~1e-7.
+__device__ __forceinline__ float tanh_from_log2(float z2) {
+  const float e = __builtin_amdgcn_exp2f(z2);
+  return fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
 }
 
-// tanh(z) = sign(z) (1 - e) / (1 + e), e = exp(-2|z|) = 2^(-2 log2(e) |z|).
-__device__ __forceinline__ float tanh_f(float z) {
-  const float e = __builtin_amdgcn_exp2f(-2.88539008177792681472f * fabsf(z));
-  const float t = (1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e);
-  return copysignf(t, z);
-}
-
-// Square-saw: (1 - s/2) tanh(K sin 2 pi th) (1 + s cos 2 pi th).
-__device__ __forceinline__ float squaresaw(double th, float K, float shape, float gain) {
+// Square-saw: (1 - s/2) tanh(K sin 2 pi th) (1 + s cos 2 pi th); K2 = 2 log2(e) K.
+__device__ __forceinline__ float squaresaw(double th, float K2, float shape, float gain) {
   float s, c;
   sincos_cycles(th, s, c);
-  return gain * tanh_f(K * s) * fmaf(shape, c, 1.0f);
+  return gain * tanh_from_log2(K2 * s) * fmaf(shape, c, 1.0f);
+}
+
+// expm1(x) in float64: Taylor series for |x| <= 1/4 (terms to x^15, relative
+// truncation < 1e-19), the library routine otherwise.
+__device__ __forceinline__ double expm1_f64(double x) {
+  if (fabs(x) > 0.25) return expm1(x);
+  double p = 1.0 / 1307674368000.0;          // 1/15!
+  p = fma(p, x, 1.0 / 87178291200.0);
+  p = fma(p, x, 1.0 / 6227020800.0);
+  p = fma(p, x, 1.0 / 479001600.0);
+  p = fma(p, x, 1.0 / 39916800.0);
+  p = fma(p, x, 1.0 / 3628800.0);
+  p = fma(p, x, 1.0 / 362880.0);
+  p = fma(p, x, 1.0 / 40320.0);
+  p = fma(p, x, 1.0 / 5040.0);
+  p = fma(p, x, 1.0 / 720.0);
+  p = fma(p, x, 1.0 / 120.0);
+  p = fma(p, x, 1.0 / 24.0);
+  p = fma(p, x, 1.0 / 6.0);
+  p = fma(p, x, 0.5);
+  p = fma(p, x, 1.0);
+  return p * x;
 }
 
 // Zero out[z0, z1) with all 64 lanes (z0 a multiple of 4).
@@ -236,7 +242,7 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
   const double midi = v[0];
   const double m_hi = fmax(0.0, midi + v[71] + fmax(0.0, v[72]));
   const double f_hi = fmin(440.0 * exp2((m_hi - 69.0) / 12.0), sr / 2.0);
-  const float K = (float)(12000.0 / (f_hi * log10(f_hi)));
+  const float K2 = (float)(2.0 * 1.4426950408889634 * 12000.0 / (f_hi * log10(f_hi)));
   const float shape = (float)v[74];
   const float sq_gain = (float)(1.0 - v[74] / 2.0);
   const double L1 = v[75], L2 = v[76], L3 = v[77];
@@ -318,8 +324,8 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
       const double m1 = base + v[tb + 1] * yb;
       const double i0 = 440.0 * exp2((m0 - 69.0) / 12.0) / sr;
       const double Lr = (m1 - m0) * (kLn2 / (12.0 * qd));   // log of the per-sample ratio
-      const double e1 = expm1(Lr);
-      const double eh = expm1(Lr * hd);
+      const double e1 = expm1_f64(Lr);
+      const double eh = expm1_f64(Lr * hd);
       const double rr = 1.0 + e1;
       const double Rh = 1.0 + eh;
       const double Sh = (e1 == 0.0) ? i0 * hd : i0 * (eh / e1);
@@ -392,7 +398,7 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
       float* trow = tile + lane * h;
       for (int k = 0; k < h; ++k) {
         const float x1 = sin_cycles(t1);
-        const float x2 = squaresaw(t2, K, shape, sq_gain);
+        const float x2 = squaresaw(t2, K2, shape, sq_gain);
         const float A1 = fmaf(kf, A1d, A10);
         const float A2 = fmaf(kf, A2d, A20);
         trow[k] = fmaf(A2, x2, A1 * x1);
@@ -430,14 +436,14 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
           const int li = base + sub * 256 + 4 * lane;   // pass-local sample
           if (li < cnt) {
             const int lsg = (int)__umulhi((uint32_t)li, a.q_magic);   // li / q
-            const float kf0 = (float)(li - lsg * q);
             const float2 na = sh.namp[seg0 + lsg];
+            const float a0 = fmaf((float)(li - lsg * q), na.y, na.x);   // noise VCA at li
             const float4 t4 = *reinterpret_cast<const float4*>(tile + li);
             float o[4];
-            o[0] = fmaf((float)(wa & 0xFFFFu) - 32767.5f, fmaf(kf0, na.y, na.x), t4.x);
-            o[1] = fmaf((float)(wa >> 16) - 32767.5f, fmaf(kf0 + 1.0f, na.y, na.x), t4.y);
-            o[2] = fmaf((float)(wb & 0xFFFFu) - 32767.5f, fmaf(kf0 + 2.0f, na.y, na.x), t4.z);
-            o[3] = fmaf((float)(wb >> 16) - 32767.5f, fmaf(kf0 + 3.0f, na.y, na.x), t4.w);
+            o[0] = fmaf((float)(wa & 0xFFFFu) - 32767.5f, a0, t4.x);
+            o[1] = fmaf((float)(wa >> 16) - 32767.5f, fmaf(1.0f, na.y, a0), t4.y);
+            o[2] = fmaf((float)(wb & 0xFFFFu) - 32767.5f, fmaf(2.0f, na.y, a0), t4.z);
+            o[3] = fmaf((float)(wb >> 16) - 32767.5f, fmaf(3.0f, na.y, a0), t4.w);
             float* dst = out + pbase + li;
             if (aligned && li + 4 <= cnt) {
               *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);

@@ -47,4 +47,7 @@ hipError_t launch_render(const RenderArgs& a, int runs_per_segment, bool clamp, 
 
 hipError_t launch_peak_normalise(const RenderArgs& a, hipStream_t s);
 
+hipError_t launch_mrstft(const float* x, const float* target, int64_t batch, int64_t n_samples,
+                         double* loss, float* grad, hipStream_t s);
+
 }  // namespace synth
