@@ -27,118 +27,12 @@
 
 #include "philox.h"
 #include "synth_internal.h"
+#include "voice_device.h"
 
 namespace synth {
 namespace {
 
-constexpr int kWave = 64;
-constexpr int kSegsPerChunk = 62;
-constexpr int kPointsPerChunk = kSegsPerChunk + 1;
-constexpr double kTwoPi = 6.283185307179586476925286766559;
-constexpr double kLn2 = 0.693147180559945309417232121458;
-
-// ---------------------------------------------------------------------------
-// float64 control-rate helpers
-// ---------------------------------------------------------------------------
-// x^e for x in [0, 1] (0^e = 0, 1^e = 1 without evaluating exp2/log2).
-__device__ __forceinline__ double pow01(double x, double e) {
-  return x <= 0.0 ? 0.0 : (x >= 1.0 ? 1.0 : exp2(e * log2(x)));
-}
-
-// clamp((j - start) / len, 0, 1); len == 0 is the step [j >= start].
-__device__ __forceinline__ double ramp(double j, double start, double len, double inv_len) {
-  return len > 0.0 ? fmin(fmax((j - start) * inv_len, 0.0), 1.0) : (j >= start ? 1.0 : 0.0);
-}
-
-__device__ __forceinline__ bool bit(const uint32_t* w, int p) { return (w[p >> 5] >> (p & 31)) & 1u; }
-
-// Normalised u -> human-readable value (Section 3.3): u^(1/curve) on [min, max],
-// or for symmetric parameters sign(d)|d|^(1/curve), d = 2u - 1, centred.
-__device__ double map_param(double u, int p, const NebulaArgs& nb) {
-  const double lo = nb.lo[p], span = nb.hi[p] - nb.lo[p];
-  const bool lin = bit(nb.linear, p);
-  if (!bit(nb.sym, p)) return lo + span * (lin ? u : pow(u, nb.inv_curve[p]));
-  const double d = 2.0 * u - 1.0;
-  const double ad = fabs(d);
-  const double w = lin ? ad : pow(ad, nb.inv_curve[p]);
-  const double sg = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
-  return lo + span * (1.0 + sg * w) / 2.0;
-}
-
-// Exclusive prefix sum across the 64 lanes (lane 0 gets 0).
-__device__ __forceinline__ double wave_excl_scan(double x, int lane) {
-  double incl = x;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const double t = __shfl_up(incl, d);
-    if (lane >= d) incl += t;
-  }
-  const double ex = __shfl_up(incl, 1);
-  return lane == 0 ? 0.0 : ex;
-}
-
-// ---------------------------------------------------------------------------
-// float32 audio-rate helpers
-// ---------------------------------------------------------------------------
-// sin(2 pi th) for the sine VCO: th (cycles, float64) is reduced to the
-// nearest integer in float64, r = th - rint(th) in [-1/2, 1/2], and the
-// hardware sine (input in revolutions, absolute error ~1.3e-7 on [-1/2, 1/2])
-// is evaluated on float(r).
-__device__ __forceinline__ float sin_cycles(double th) {
-  const float r = (float)(th - rint(th));
-  return __builtin_amdgcn_sinf(r);
-}
-
-// sin and cos of 2 pi th for the square-saw.  Its tanh edge multiplies the
-// sine by K (up to ~1600) at every zero crossing, so the sine must be
-// relatively accurate there, at th = 0 and th = 1/2 alike: th is reduced to
-// the nearest half cycle in float64, r = th - n/2 in [-1/4, 1/4] (exact),
-// sin(2 pi th) = (-1)^n sin(2 pi r), cos(2 pi th) = (-1)^n cos(2 pi r).  The
-// hardware sine has ~9e-7 relative error near 0, which moves tanh(K sin) by
-// at most ~4e-7.
-__device__ __forceinline__ void sincos_cycles(double th, float& s, float& c) {
-  const double n = rint(2.0 * th);
-  const float r = (float)fma(-0.5, n, th);
-  const uint32_t flip = ((uint32_t)(int)n) << 31;     // sign bit of (-1)^n
-  s = __uint_as_float(__float_as_uint(__builtin_amdgcn_sinf(r)) ^ flip);
-  c = __uint_as_float(__float_as_uint(__builtin_amdgcn_cosf(r)) ^ flip);
-}
-
-// tanh(z) = 1 - 2 / (exp(2z) + 1) from z2 = 2 log2(e) z; saturates to +-1
-// through exp2 overflow or underflow, absolute error ~1e-7.
-__device__ __forceinline__ float tanh_from_log2(float z2) {
-  const float e = __builtin_amdgcn_exp2f(z2);
-  return fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
-}
-
-// Square-saw: (1 - s/2) tanh(K sin 2 pi th) (1 + s cos 2 pi th); K2 = 2 log2(e) K.
-__device__ __forceinline__ float squaresaw(double th, float K2, float shape, float gain) {
-  float s, c;
-  sincos_cycles(th, s, c);
-  return gain * tanh_from_log2(K2 * s) * fmaf(shape, c, 1.0f);
-}
-
-// expm1(x) in float64: Taylor series for |x| <= 1/4 (terms to x^15, relative
-// truncation < 1e-19), the library routine otherwise.
-__device__ __forceinline__ double expm1_f64(double x) {
-  if (fabs(x) > 0.25) return expm1(x);
-  double p = 1.0 / 1307674368000.0;          // 1/15!
-  p = fma(p, x, 1.0 / 87178291200.0);
-  p = fma(p, x, 1.0 / 6227020800.0);
-  p = fma(p, x, 1.0 / 479001600.0);
-  p = fma(p, x, 1.0 / 39916800.0);
-  p = fma(p, x, 1.0 / 3628800.0);
-  p = fma(p, x, 1.0 / 362880.0);
-  p = fma(p, x, 1.0 / 40320.0);
-  p = fma(p, x, 1.0 / 5040.0);
-  p = fma(p, x, 1.0 / 720.0);
-  p = fma(p, x, 1.0 / 120.0);
-  p = fma(p, x, 1.0 / 24.0);
-  p = fma(p, x, 1.0 / 6.0);
-  p = fma(p, x, 0.5);
-  p = fma(p, x, 1.0);
-  return p * x;
-}
+using namespace voice;
 
 // Zero out[z0, z1) with all 64 lanes (z0 a multiple of 4).
 __device__ void zero_fill(float* out, int64_t z0, int64_t z1, int lane, bool aligned) {
@@ -153,25 +47,6 @@ __device__ void zero_fill(float* out, int64_t z0, int64_t z1, int lane, bool ali
     for (int64_t i = z0 + lane; i < z1; i += kWave) out[i] = 0.0f;
   }
 }
-
-// Per-voice constants derived once from the parameters (LDS, read by every lane).
-enum {
-  kEnvA = 0, kEnvInvA = 6, kEnvD = 12, kEnvInvD = 18, kEnvR = 24, kEnvInvR = 30, kEnvS = 36,
-  kEnvAlpha = 42, kLfoInvW = 48, kMixInvNorm = 50, kDerived = 56
-};
-
-// Per-segment oscillator data of a chunk, one row per VCO.
-enum { kSegTheta = 0, kSegInc = 1, kSegRatio = 2, kSegRunSum = 3, kSegRunRatio = 4, kSegFields = 5 };
-
-struct VoiceShared {
-  double v[kNumParams];        // human-readable parameter values
-  double d[kDerived];          // derived per-voice constants (enum above)
-  double seg[2][kSegFields][kWave];   // per VCO and segment: start phase (cycles, in [0,1)),
-                                      // start increment, per-sample ratio, first-run sum,
-                                      // per-run ratio
-  double carry[4];             // phase carries (cycles): LFO 1, LFO 2, VCO 1, VCO 2
-  float2 namp[kWave];          // per segment of the chunk: noise VCA (start, slope) * level * 2^-15
-};
 
 template <int RPS, bool CLAMP>
 __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShared& sh,
@@ -196,31 +71,8 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
   const bool aligned = (reinterpret_cast<uintptr_t>(out) & 15u) == 0;
   const double rc = a.rc, sr = a.sr;
 
-  __syncthreads();
-  for (int p = lane; p < kNumParams; p += kWave)
-    sh.v[p] = map_param((double)a.params[b * kNumParams + p], p, a.neb);
-  __syncthreads();
+  voice_setup(a, b, sh, lane);
   const double* v = sh.v;
-  if (lane < 6) {                    // envelope k: durations in control samples
-    const int pb = 2 + 5 * lane;
-    const double A = v[pb] * rc, D = v[pb + 1] * rc, R = v[pb + 3] * rc;
-    sh.d[kEnvA + lane] = A;
-    sh.d[kEnvInvA + lane] = 1.0 / A;
-    sh.d[kEnvD + lane] = D;
-    sh.d[kEnvInvD + lane] = 1.0 / D;
-    sh.d[kEnvR + lane] = R;
-    sh.d[kEnvInvR + lane] = 1.0 / R;
-    sh.d[kEnvS + lane] = v[pb + 2];
-    sh.d[kEnvAlpha + lane] = v[pb + 4];
-  } else if (lane < 8) {             // LFO: 1 / sum of shape weights (0 if none)
-    const int pb = 32 + 8 * (lane - 6);
-    const double ws = v[pb + 3] + v[pb + 4] + v[pb + 5] + v[pb + 6] + v[pb + 7];
-    sh.d[kLfoInvW + lane - 6] = ws > 0.0 ? 1.0 / ws : 0.0;
-  } else if (lane < 13) {            // modulation mixer row: 1 / max(1, sum of gains)
-    const int pb = 48 + 4 * (lane - 8);
-    sh.d[kMixInvNorm + lane - 8] = 1.0 / fmax(1.0, v[pb] + v[pb + 1] + v[pb + 2] + v[pb + 3]);
-  }
-  __syncthreads();
   const double* dv = sh.d;
 
   const int64_t J = (N + q - 1) / q;     // control samples == segments
@@ -247,12 +99,6 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
   const float sq_gain = (float)(1.0 - v[74] / 2.0);
   const double L1 = v[75], L2 = v[76], L3 = v[77];
 
-  // phase carries in cycles, reduced mod 1 at every chunk boundary
-  if (lane < 4) {
-    const double ph0 = v[lane == 0 ? 34 : lane == 1 ? 42 : lane == 2 ? 70 : 73] / kTwoPi;
-    sh.carry[lane] = ph0 - floor(ph0);
-  }
-  __syncthreads();
   const uint32_t glo = (uint32_t)g, ghi = (uint32_t)(g >> 32);
 
   for (int64_t c = 0; c < c_hi; ++c) {
@@ -263,100 +109,8 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
       break;
     }
     // ---------------- control stage: lane = control sample j ----------------
-    const int64_t j = c * kSegsPerChunk + lane;
-    const double jd = (double)j;
-    // Envelopes go through LDS (the tile is idle during the control stage), one
-    // at a time, which keeps the float64 exp2/log2 chains from being interleaved.
-    double* envs = reinterpret_cast<double*>(tile);
-#pragma unroll 1
-    for (int k = 0; k < 6; ++k) {
-      // ADSR: attack rise, decay fall towards sustain, release fall from note-off,
-      // each ramp raised to the curve exponent alpha.
-      const double A = dv[kEnvA + k], D = dv[kEnvD + k], R = dv[kEnvR + k];
-      const double S = dv[kEnvS + k], al = dv[kEnvAlpha + k];
-      const double att = ramp(jd, 0.0, A, dv[kEnvInvA + k]);
-      const double dec = ramp(jd, A, D, dv[kEnvInvD + k]);
-      const double rel = ramp(jd, note_off, R, dv[kEnvInvR + k]);
-      envs[k * kWave + lane] =
-          pow01(att, al) * (S + (1.0 - S) * pow01(1.0 - dec, al)) * pow01(1.0 - rel, al);
-    }
-    // LFOs (rate ADSR modulates the rate; amp ADSR is a control-rate VCA),
-    // written next to the envelopes: lfo'_i at envs[(6 + i) * 64 + lane].
-#pragma unroll 1
-    for (int i = 0; i < 2; ++i) {
-      const int pb = 32 + 8 * i;
-      const double f = fmax(0.0, v[pb] + v[pb + 1] * envs[(2 + 2 * i) * kWave + lane]);
-      const double inc = lane < kPointsPerChunk - 1 ? f / rc : 0.0;
-      const double th = sh.carry[i] + wave_excl_scan(inc, lane);
-      const double ph = th - floor(th);
-      const double num = v[pb + 3] * ((1.0 + sinpi(2.0 * ph)) / 2.0) +
-                         v[pb + 4] * (1.0 - fabs(2.0 * ph - 1.0)) + v[pb + 5] * ph +
-                         v[pb + 6] * (1.0 - ph) + v[pb + 7] * (ph < 0.5 ? 1.0 : 0.0);
-      envs[(6 + i) * kWave + lane] = (num * dv[kLfoInvW + i]) * envs[(3 + 2 * i) * kWave + lane];
-      const double nc = __shfl(th, kSegsPerChunk);            // phase at the next chunk's first point
-      __syncthreads();
-      if (lane == 0) sh.carry[i] = nc - floor(nc);
-    }
-    // modulation mixer: inputs adsr_1, adsr_2, lfo'_1, lfo'_2
-    const double x0 = envs[lane], x1 = envs[kWave + lane];
-    const double x2 = envs[6 * kWave + lane], x3 = envs[7 * kWave + lane];
     double y[5], yn[5];
-    const bool last = (j + 1 >= J);                  // right end held at the last control sample
-#pragma unroll
-    for (int o = 0; o < 5; ++o) {
-      const int pb = 48 + 4 * o;
-      const double acc = v[pb] * x0 + v[pb + 1] * x1 + v[pb + 2] * x2 + v[pb + 3] * x3;
-      y[o] = acc * dv[kMixInvNorm + o];
-    }
-#pragma unroll
-    for (int o = 0; o < 5; ++o) {
-      const double t = __shfl_down(y[o], 1);
-      yn[o] = last ? y[o] : t;
-    }
-    // per segment (lane < 62): pitch glide, phase advance; one VCO at a time
-#pragma unroll 1
-    for (int vc = 0; vc < 2; ++vc) {
-      const int tb = vc ? 71 : 68;
-      const double ya = vc ? y[2] : y[0];
-      const double yb = vc ? yn[2] : yn[0];
-      const double base = midi + v[tb];
-      const double m0 = base + v[tb + 1] * ya;
-      const double m1 = base + v[tb + 1] * yb;
-      const double i0 = 440.0 * exp2((m0 - 69.0) / 12.0) / sr;
-      const double Lr = (m1 - m0) * (kLn2 / (12.0 * qd));   // log of the per-sample ratio
-      const double e1 = expm1_f64(Lr);
-      const double eh = expm1_f64(Lr * hd);
-      const double rr = 1.0 + e1;
-      const double Rh = 1.0 + eh;
-      const double Sh = (e1 == 0.0) ? i0 * hd : i0 * (eh / e1);
-      double S;
-      if constexpr (CLAMP) {
-        // some increments may exceed 1/2 cycle (f > sr/2): sum them one by one
-        S = 0.0;
-        double inc = i0;
-        for (int k = 0; k < q; ++k) {
-          S += fmin(inc, 0.5);
-          inc *= rr;
-        }
-      } else {
-        S = Sh;
-        double t = Sh;
-#pragma unroll
-        for (int m = 1; m < RPS; ++m) {
-          t *= Rh;
-          S += t;
-        }
-      }
-      const double th = sh.carry[2 + vc] + wave_excl_scan(lane < kSegsPerChunk ? S : 0.0, lane);
-      sh.seg[vc][kSegTheta][lane] = th - floor(th);
-      sh.seg[vc][kSegInc][lane] = i0;
-      sh.seg[vc][kSegRatio][lane] = rr;
-      sh.seg[vc][kSegRunSum][lane] = Sh;
-      sh.seg[vc][kSegRunRatio][lane] = Rh;
-      const double nc = __shfl(th, kSegsPerChunk);
-      __syncthreads();
-      if (lane == 0) sh.carry[2 + vc] = nc - floor(nc);
-    }
+    control_stage<RPS, CLAMP>(a, sh, reinterpret_cast<double*>(tile), c, J, h, lane, y, yn);
     if (c < c_lo) continue;                      // slice starts later: only carries needed
 
     const float a10 = (float)(L1 * y[1]), a1d = (float)(L1 * (yn[1] - y[1]) / qd);
