@@ -112,6 +112,29 @@ int synth_render_plan(const synth_config* cfg, const float* params, const uint64
                       float* audio, int runs_per_segment, int slices_per_voice,
                       int persistent, int grid_blocks, void* stream);
 
+/* Workspace (bytes of device memory) that synth_render_backward needs for a
+ * batch of uniform-length voices: batch * ceil(n_samples / q) * 21 doubles.
+ * Returns 0 for an invalid cfg. */
+size_t synth_render_backward_workspace(const synth_config* cfg, int64_t batch, int64_t n_samples);
+
+/* Adjoint of synth_render (uniform lengths): grad_params[i][p] =
+ * sum_n grad_audio[i][n] * d audio[i][n] / d params[i][p], the exact
+ * derivative of the render's definition almost everywhere (hard LFO square
+ * and saw wraps, ramp kinks and the noise contribute their one-sided /
+ * zero derivatives).  Envelopes and oscillators are recomputed, not stored.
+ *   params, voice_ids, first_g, batch, n_samples  as for synth_render.
+ *   grad_audio   dev float32 [batch][n_samples].
+ *   grad_params  dev float32 [batch][78], written.
+ *   workspace    dev buffer of >= synth_render_backward_workspace() bytes,
+ *                caller-owned, contents clobbered.
+ * Returns SYNTH_EUNSUPPORTED for mix_mode 1, for nebulas whose pitch can exceed
+ * sample_rate / 2, and for voices longer than 512 * 62 control samples;
+ * SYNTH_ENOMEM if workspace_bytes is too small. */
+int synth_render_backward(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
+                          uint64_t first_g, int64_t batch, int64_t n_samples,
+                          const float* grad_audio, float* grad_params, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
 /* Multi-resolution log-magnitude STFT L1 loss (Section 4.3: multi-scale
  * spectrogram distance, L1), per voice, and optionally its gradient.
  *   For voice b: loss[b] = sum over n in (512, 1024, 2048), hop n/4, of the mean

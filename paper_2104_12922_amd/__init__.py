@@ -17,7 +17,7 @@ from . import _native
 NUM_PARAMS = _native.NUM_PARAMS
 
 __all__ = ["synth_sample_params", "synth_render", "synth_render_plan", "synth_is_test",
-           "synth_mrstft_loss",
+           "synth_mrstft_loss", "synth_render_backward", "SynthRender", "MRSTFTLoss",
            "NUM_PARAMS", "SynthError"]
 
 SynthError = _native.SynthError
@@ -130,6 +130,70 @@ def synth_mrstft_loss(x: torch.Tensor, target: torch.Tensor, grad: bool = False)
         B, N, _dev_ptr(loss, "loss", torch.float64, B),
         _dev_ptr(g, "grad", torch.float32, B * N) if grad else None, _stream(x.device)))
     return (loss, g) if grad else loss
+
+
+def synth_render_backward(params: torch.Tensor, grad_audio: torch.Tensor, nebula,
+                          voice_ids: torch.Tensor | None = None, first_g: int = 0,
+                          noise_seed: int = 0, sample_rate: float = 44100.0,
+                          control_rate: float = 441.0, workspace: torch.Tensor | None = None
+                          ) -> torch.Tensor:
+    """d(sum grad_audio * render(params)) / d params, float32 [B, 78] (see synth.h)."""
+    import ctypes
+    B, N = grad_audio.shape
+    cfg, keep = _native.make_config(nebula, sample_rate, control_rate, noise_seed, 0)
+    L = _native.lib()
+    need = L.synth_render_backward_workspace(ctypes.byref(cfg), B, N)
+    if workspace is None or workspace.numel() * workspace.element_size() < need:
+        workspace = torch.empty(max(need, 8), dtype=torch.uint8, device=params.device)
+    gp = torch.empty(B, NUM_PARAMS, dtype=torch.float32, device=params.device)
+    _native.check("synth_render_backward", L.synth_render_backward(
+        ctypes.byref(cfg), _dev_ptr(params, "params", torch.float32, B * NUM_PARAMS),
+        _dev_ptr(voice_ids, "voice_ids", torch.uint64, B) if voice_ids is not None else None,
+        int(first_g), B, N, _dev_ptr(grad_audio, "grad_audio", torch.float32, B * N),
+        _dev_ptr(gp, "grad_params", torch.float32, B * NUM_PARAMS), workspace.data_ptr(),
+        workspace.numel() * workspace.element_size(), _stream(params.device)))
+    del keep
+    return gp
+
+
+class SynthRender(torch.autograd.Function):
+    """Differentiable render of uniform-length voices: forward = synth_render,
+    backward = synth_render_backward (envelopes and oscillators are recomputed;
+    only the parameters are saved)."""
+
+    @staticmethod
+    def forward(ctx, params, nebula, n_samples, first_g=0, noise_seed=0, sample_rate=44100.0,
+                control_rate=441.0):
+        p = params.detach().contiguous()
+        y = synth_render(p, nebula, n_samples=n_samples, first_g=first_g, noise_seed=noise_seed,
+                         sample_rate=sample_rate, control_rate=control_rate)
+        ctx.save_for_backward(p)
+        ctx.cfg = (nebula, first_g, noise_seed, sample_rate, control_rate)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        (p,) = ctx.saved_tensors
+        nebula, first_g, noise_seed, sr, rc = ctx.cfg
+        gp = synth_render_backward(p, gy.contiguous().float(), nebula, first_g=first_g,
+                                   noise_seed=noise_seed, sample_rate=sr, control_rate=rc)
+        return gp, None, None, None, None, None, None
+
+
+class MRSTFTLoss(torch.autograd.Function):
+    """Per-voice multi-resolution log-magnitude STFT L1 (float64 [B]) with its
+    gradient w.r.t. the render computed by the same kernel."""
+
+    @staticmethod
+    def forward(ctx, x, target):
+        loss, g = synth_mrstft_loss(x.detach().contiguous(), target.contiguous(), grad=True)
+        ctx.save_for_backward(g)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gl):
+        (g,) = ctx.saved_tensors
+        return g * gl.to(g.dtype)[:, None], None
 
 
 def ctypes_ref(cfg):

@@ -59,6 +59,14 @@ def lib() -> ctypes.CDLL:
         L.synth_mrstft_loss.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                         ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]
+        L.synth_render_backward_workspace.restype = ctypes.c_size_t
+        L.synth_render_backward_workspace.argtypes = [ctypes.POINTER(SynthConfig), ctypes.c_int64,
+                                                      ctypes.c_int64]
+        L.synth_render_backward.restype = ctypes.c_int
+        L.synth_render_backward.argtypes = [ctypes.POINTER(SynthConfig), ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64,
+                                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         _lib = L
     return _lib
 

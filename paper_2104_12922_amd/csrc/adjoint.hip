@@ -1,0 +1,629 @@
+// Adjoint of the Voice render: d(sum_n g(n) y(n)) / d(params), g = dL/dy given.
+//
+// Forward recap (per voice; q audio samples per control sample):
+//   a_o(n) = (1 - t) y_o(j) + t y_o(j+1), j = n div q, t = (n mod q) / q
+//   theta_v(n) = phi_v / 2pi + sum_{k<n} inc_v(k), inc_v = hz(m_v) / sr,
+//   m_v = midi + tune_v + depth_v a_pitch_v
+//   y = L1 sin(2 pi theta_1) a_1 + L2 x2(theta_2) a_3 + L3 noise a_4
+//
+// Kernel A (one wavefront per voice) recomputes the forward with the render's
+// own control stage and phase recurrences and reduces, per control segment s,
+//   D_v = sum dtheta_v,  C{0,1}_v = sum w{0,1} inc_v,  E{0,1}_v = sum w{0,1} inc_v P_v
+// (w0 = 1 - t, w1 = t, P_v the inclusive in-segment prefix of dtheta_v), the
+// VCA row sums A{0,1}_o = sum w{0,1} g L x, and the sums for the levels, the
+// square-saw shape and its gain K.  With Gend_v(s) = sum of D_v over later
+// segments, the upsampled pitch adjoint of segment s is
+//   B{0,1}_v(s) = (Gend_v(s) + D_v(s)) C{0,1}_v(s) - E{0,1}_v(s),
+// i.e. sum_k w inc Gtheta(k) with Gtheta(k) = sum_{n>k} dtheta(n): the reverse
+// (suffix) scan of the phase adjoint is split into an in-segment part (here)
+// and a cross-segment float64 scan (kernel B).
+//
+// Kernel B (one wavefront per voice) walks the control samples backward by
+// chunks: segment adjoints -> dy_o(j) (transposed upsampling), modulation
+// mixer, LFOs (shape weights, phase with its own suffix scan, rate clamp),
+// control-rate VCAs and the six ADSRs, accumulating d(human value) per lane in
+// LDS; then a fixed-order lane reduction and the curve-mapping Jacobian give
+// d/d(normalised parameter).  Deterministic; no atomics.
+#include <math.h>
+
+#include "philox.h"
+#include "synth_internal.h"
+#include "voice_device.h"
+
+namespace synth {
+namespace {
+
+using namespace voice;
+
+enum {
+  kRD1 = 0, kRC01, kRC11, kRE01, kRE11,           // sine VCO phase adjoint
+  kRD2, kRC02, kRC12, kRE02, kRE12,               // square-saw VCO phase adjoint
+  kRA01, kRA11, kRA03, kRA13, kRA04, kRA14,       // VCA rows 1, 3, 4
+  kRL1, kRL2, kRL3, kRShape, kRK,                 // levels, shape, square-saw gain
+  kNumRed
+};
+
+template <int RPS>
+__global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a,
+                                                              const float* __restrict__ g_audio,
+                                                              double* __restrict__ red) {
+  __shared__ VoiceShared sh;
+  extern __shared__ __align__(16) float tile[];
+  const int lane = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  const int q = a.q;
+  const int h = q / RPS;
+  const double qd = (double)q;
+  const int64_t N = a.n_uniform;
+  const int64_t J = (N + q - 1) / q;
+  const uint64_t g = a.voice_ids ? a.voice_ids[b] : a.first_g + (uint64_t)b;
+  const float* gv = g_audio + b * N;
+  double* rv = red + b * J * kNumRed;
+  float* tg = tile;                 // g(n) of the pass
+  float* tgn = tile + kWave * h;    // g(n) * noise(n) of the pass
+
+  voice_setup(a, b, sh, lane);
+  const double* v = sh.v;
+  const double rc = a.rc, sr = a.sr;
+  const double note_off = v[1] * rc;
+  double jsil = 0.0;
+  for (int k = 0; k < 6; ++k) jsil = fmax(jsil, note_off + v[2 + 5 * k + 3] * rc);
+  jsil = fmin(jsil, 9.0e15);
+  const int64_t js = (int64_t)floor(jsil) + 2;
+  const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
+  const int64_t c_sil = (js + kSegsPerChunk - 1) / kSegsPerChunk;
+
+  const double midi = v[0];
+  const double m_hi = fmax(0.0, midi + v[71] + fmax(0.0, v[72]));
+  const double f_hi = fmin(440.0 * exp2((m_hi - 69.0) / 12.0), sr / 2.0);
+  const float K = (float)(12000.0 / (f_hi * log10(f_hi)));
+  const float K2 = (float)(2.0 * 1.4426950408889634 * 12000.0 / (f_hi * log10(f_hi)));
+  const float shape = (float)v[74];
+  const float cg = (float)(1.0 - v[74] / 2.0);
+  const float L1 = (float)v[75], L2 = (float)v[76], L3 = (float)v[77];
+  const float two_pi = 6.28318530717958647692f;
+  const uint32_t glo = (uint32_t)g, ghi = (uint32_t)(g >> 32);
+
+  for (int64_t c = 0; c < nchunks; ++c) {
+    if (c >= c_sil) {
+      // exactly silent from here on: every reduction is zero (the envelopes are
+      // 0 with zero derivative, so no parameter sees these samples)
+      const int64_t s0 = c * kSegsPerChunk;
+      for (int64_t i = lane; i < (J - s0) * kNumRed; i += kWave) rv[s0 * kNumRed + i] = 0.0;
+      break;
+    }
+    double y[5], yn[5];
+    control_stage<RPS, false>(a, sh, reinterpret_cast<double*>(tile), c, J, h, lane, y, yn);
+    // unscaled VCA ramps of this lane's segment
+    const float a10 = (float)y[1], a1d = (float)((yn[1] - y[1]) / qd);
+    const float a30 = (float)y[3], a3d = (float)((yn[3] - y[3]) / qd);
+    const float a40 = (float)y[4], a4d = (float)((yn[4] - y[4]) / qd);
+    __syncthreads();
+
+    constexpr int segs_pp = kWave / RPS;
+    const int nseg = (int)((J - c * kSegsPerChunk) < kSegsPerChunk ? (J - c * kSegsPerChunk)
+                                                                    : kSegsPerChunk);
+    const int npass = (nseg + segs_pp - 1) / segs_pp;
+    for (int p = 0; p < npass; ++p) {
+      // ---- load pass: g and g * noise into LDS, 4 samples per lane ----
+      const int64_t pbase = (c * kSegsPerChunk + (int64_t)p * segs_pp) * q;
+      int64_t cnt64 = (int64_t)((nseg - p * segs_pp) < segs_pp ? (nseg - p * segs_pp) : segs_pp) * q;
+      if (cnt64 > N - pbase) cnt64 = N - pbase;
+      const int cnt = (int)cnt64;
+      const int tcap = kWave * h;
+      const uint32_t grp0 = (uint32_t)(pbase >> 3);
+      for (int base = 0; base < tcap; base += 512) {
+        uint32_t w[4] = {glo, ghi, grp0 + (uint32_t)(base >> 3) + (uint32_t)lane, 1u};
+        philox4x32_10(w, a.nk0, a.nk1);
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+          const int src_l = sub * 32 + (lane >> 1);
+          const uint32_t w0 = __shfl(w[0], src_l), w1 = __shfl(w[1], src_l);
+          const uint32_t w2 = __shfl(w[2], src_l), w3 = __shfl(w[3], src_l);
+          const uint32_t wa = (lane & 1) ? w2 : w0;
+          const uint32_t wb = (lane & 1) ? w3 : w1;
+          const int li = base + sub * 256 + 4 * lane;
+          if (li < tcap) {
+            float gg[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) gg[e] = li + e < cnt ? gv[pbase + li + e] : 0.0f;
+            const float n0 = ((float)(wa & 0xFFFFu) - 32767.5f) * (1.0f / 32768.0f);
+            const float n1 = ((float)(wa >> 16) - 32767.5f) * (1.0f / 32768.0f);
+            const float n2 = ((float)(wb & 0xFFFFu) - 32767.5f) * (1.0f / 32768.0f);
+            const float n3 = ((float)(wb >> 16) - 32767.5f) * (1.0f / 32768.0f);
+            *reinterpret_cast<float4*>(tg + li) = make_float4(gg[0], gg[1], gg[2], gg[3]);
+            *reinterpret_cast<float4*>(tgn + li) =
+                make_float4(gg[0] * n0, gg[1] * n1, gg[2] * n2, gg[3] * n3);
+          }
+        }
+      }
+      __syncthreads();
+      // ---- run pass: forward recompute and per-run reductions ----
+      const int ls = p * segs_pp + lane / RPS;
+      const int m = lane % RPS;
+      const int src = ls < kWave ? ls : kWave - 1;
+      double t1 = sh.seg[0][kSegTheta][src], i1 = sh.seg[0][kSegInc][src];
+      double t2 = sh.seg[1][kSegTheta][src], i2 = sh.seg[1][kSegInc][src];
+      const double r1 = sh.seg[0][kSegRatio][src], r2 = sh.seg[1][kSegRatio][src];
+      {
+        double s1 = sh.seg[0][kSegRunSum][src], R1 = sh.seg[0][kSegRunRatio][src];
+        double s2 = sh.seg[1][kSegRunSum][src], R2 = sh.seg[1][kSegRunRatio][src];
+        for (int t = 0; t < m; ++t) {
+          t1 += s1; s1 *= R1; i1 *= R1;
+          t2 += s2; s2 *= R2; i2 *= R2;
+        }
+      }
+      const float A10 = __shfl(a10, src), A1d = __shfl(a1d, src);
+      const float A30 = __shfl(a30, src), A3d = __shfl(a3d, src);
+      const float A40 = __shfl(a40, src), A4d = __shfl(a4d, src);
+      double acc[kNumRed];
+#pragma unroll
+      for (int r = 0; r < kNumRed; ++r) acc[r] = 0.0;
+      double P1 = 0.0, P2 = 0.0;
+      const int seg_valid = ls < nseg ? 1 : 0;
+      for (int k = 0; k < h; ++k) {
+        const int ks = m * h + k;                  // sample index within the segment
+        const float kf = (float)ks;
+        const double wt1 = (double)ks / qd, wt0 = 1.0 - wt1;
+        const float gk = seg_valid ? tg[lane * h + k] : 0.0f;
+        const float gnk = seg_valid ? tgn[lane * h + k] : 0.0f;
+        const float a1 = fmaf(kf, A1d, A10), a3 = fmaf(kf, A3d, A30), a4 = fmaf(kf, A4d, A40);
+        // sine VCO
+        const float r1f = (float)(t1 - rint(t1));
+        const float x1 = __builtin_amdgcn_sinf(r1f), c1 = __builtin_amdgcn_cosf(r1f);
+        const float dth1 = gk * L1 * a1 * two_pi * c1;
+        // square-saw VCO: T = tanh(K s), sech^2 = 4e/(1+e)^2 with e = exp(-2|K s|)
+        float s2f, c2f;
+        sincos_cycles(t2, s2f, c2f);
+        const float z2 = K2 * s2f;
+        const float e = __builtin_amdgcn_exp2f(-fabsf(z2));
+        const float ri = __builtin_amdgcn_rcpf(1.0f + e);
+        const float T = copysignf((1.0f - e) * ri, z2);
+        const float sech2 = 4.0f * e * ri * ri;
+        const float Q = fmaf(shape, c2f, 1.0f);
+        const float x2 = cg * T * Q;
+        const float dx2 = cg * two_pi * (sech2 * K * c2f * Q - T * shape * s2f);
+        const float gl2a3 = gk * L2 * a3;
+        const float dth2 = gl2a3 * dx2;
+        // phase-adjoint reductions (float64)
+        P1 += (double)dth1;
+        P2 += (double)dth2;
+        acc[kRC01] += wt0 * i1;
+        acc[kRC11] += wt1 * i1;
+        acc[kRE01] += wt0 * i1 * P1;
+        acc[kRE11] += wt1 * i1 * P1;
+        acc[kRC02] += wt0 * i2;
+        acc[kRC12] += wt1 * i2;
+        acc[kRE02] += wt0 * i2 * P2;
+        acc[kRE12] += wt1 * i2 * P2;
+        // VCA rows (transposed upsampling weights), levels, shape, K
+        const double d1 = (double)(gk * L1 * x1), d3 = (double)(gk * L2 * x2), d4 = (double)(L3 * gnk);
+        acc[kRA01] += wt0 * d1;
+        acc[kRA11] += wt1 * d1;
+        acc[kRA03] += wt0 * d3;
+        acc[kRA13] += wt1 * d3;
+        acc[kRA04] += wt0 * d4;
+        acc[kRA14] += wt1 * d4;
+        acc[kRL1] += (double)(gk * x1 * a1);
+        acc[kRL2] += (double)(gk * x2 * a3);
+        acc[kRL3] += (double)(gnk * a4);
+        acc[kRShape] += (double)(gl2a3 * (cg * T * c2f - 0.5f * T * Q));
+        acc[kRK] += (double)(gl2a3 * cg * sech2 * s2f * Q);
+        t1 += i1; i1 *= r1;
+        t2 += i2; i2 *= r2;
+      }
+      acc[kRD1] = P1;
+      acc[kRD2] = P2;
+      // combine the RPS runs of each segment: E += P_before * C, then sums
+      if (RPS > 1) {
+        const int gb = lane & ~(RPS - 1);          // first lane of this segment's group
+        double pb1 = 0.0, pb2 = 0.0;
+        for (int mm = 0; mm < RPS; ++mm) {
+          const double d1v = __shfl(P1, gb + mm), d2v = __shfl(P2, gb + mm);
+          if (mm < m) { pb1 += d1v; pb2 += d2v; }
+        }
+        acc[kRE01] += pb1 * acc[kRC01];
+        acc[kRE11] += pb1 * acc[kRC11];
+        acc[kRE02] += pb2 * acc[kRC02];
+        acc[kRE12] += pb2 * acc[kRC12];
+#pragma unroll
+        for (int r = 0; r < kNumRed; ++r) {
+          double tot = 0.0;
+          for (int mm = 0; mm < RPS; ++mm) tot += __shfl(acc[r], gb + mm);
+          acc[r] = tot;
+        }
+      }
+      const int64_t sglob = c * kSegsPerChunk + ls;
+      if (m == 0 && ls < nseg) {
+#pragma unroll
+        for (int r = 0; r < kNumRed; ++r) rv[sglob * kNumRed + r] = acc[r];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// d(human value) accumulators: one column per lane, summed in lane order at the end.
+struct AdjShared {
+  VoiceShared vs;
+  double gacc[kNumParams][kWave];
+  double lfo_carry[512][2];          // LFO phase (cycles) at each chunk's first owned point
+};
+
+__device__ __forceinline__ void gadd(AdjShared& S, int p, int lane, double x) {
+  S.gacc[p][lane] += x;
+}
+
+// Reverse exclusive scan over lanes: sum of x over lanes l' > l.
+__device__ __forceinline__ double wave_rev_excl_scan(double x, int lane) {
+  double incl = x;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const double t = __shfl_down(incl, d);
+    if (lane + d < kWave) incl += t;
+  }
+  const double ex = __shfl_down(incl, 1);
+  return lane == kWave - 1 ? 0.0 : ex;
+}
+
+// float64 ADSR with the pieces its adjoint needs.
+struct EnvEval {
+  double att, dec, rel, Pa, Pd, Pr, M, env;
+};
+
+__device__ __forceinline__ EnvEval env_eval(const double* dv, int k, double jd, double note_off) {
+  EnvEval E;
+  const double A = dv[kEnvA + k], D = dv[kEnvD + k], R = dv[kEnvR + k];
+  const double S = dv[kEnvS + k], al = dv[kEnvAlpha + k];
+  E.att = ramp(jd, 0.0, A, dv[kEnvInvA + k]);
+  E.dec = ramp(jd, A, D, dv[kEnvInvD + k]);
+  E.rel = ramp(jd, note_off, R, dv[kEnvInvR + k]);
+  E.Pa = pow01(E.att, al);
+  E.Pd = pow01(1.0 - E.dec, al);
+  E.Pr = pow01(1.0 - E.rel, al);
+  E.M = S + (1.0 - S) * E.Pd;
+  E.env = E.Pa * E.M * E.Pr;
+  return E;
+}
+
+// d/dx x^alpha and d/dalpha x^alpha for x in (0, 1] (0 for x <= 0, as the
+// oracle's masked power).
+__device__ __forceinline__ void pow01_grad(double x, double al, double P, double& dx, double& dal) {
+  if (x > 0.0) {
+    dx = al * P / x;
+    dal = P * log(x);
+  } else {
+    dx = 0.0;
+    dal = 0.0;
+  }
+}
+
+// ramp = clamp((j - s) / L, 0, 1): gradient passes inside [0, 1] (inclusive)
+// for L > 0; d/ds = -1/L, d/dL = -(j - s) / L^2.
+__device__ __forceinline__ bool ramp_live(double jd, double s, double L, double invL) {
+  if (!(L > 0.0)) return false;
+  const double r = (jd - s) * invL;
+  return r >= 0.0 && r <= 1.0;
+}
+
+__global__ void __launch_bounds__(kWave) adjoint_control_kernel(const RenderArgs a,
+                                                                const double* __restrict__ red,
+                                                                float* __restrict__ grad_params) {
+  __shared__ AdjShared S;
+  const int lane = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  const int q = a.q;
+  const int64_t N = a.n_uniform;
+  const int64_t J = (N + q - 1) / q;
+  const double* rv = red + b * J * kNumRed;
+  const double rc = a.rc;
+  const double kPitch = kLn2 / 12.0;
+
+  voice_setup(a, b, S.vs, lane);
+  const double* v = S.vs.v;
+  const double* dv = S.vs.d;
+  for (int p = 0; p < kNumParams; ++p) S.gacc[p][lane] = 0.0;
+  const double note_off = v[1] * rc;
+  // chunk c owns control samples j = 62c .. 62c+61 on lanes 1..62 (lane l <->
+  // j = 62c - 1 + l); lane 0 carries segment 62c - 1, whose right-end
+  // adjoint lands on lane 1.
+  const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
+  const bool owned_lane = lane >= 1 && lane <= kSegsPerChunk;
+
+  // ---- forward: LFO phase at every chunk's first owned control sample ----
+  double lc[2] = {S.vs.carry[0], S.vs.carry[1]};
+  for (int64_t c = 0; c < nchunks; ++c) {
+    const int64_t j = c * kSegsPerChunk - 1 + lane;
+    const double jd = (double)j;
+    if (lane == 0) {
+      S.lfo_carry[c][0] = lc[0];
+      S.lfo_carry[c][1] = lc[1];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int pb = 32 + 8 * i;
+      const EnvEval Er = env_eval(dv, 2 + 2 * i, jd, note_off);
+      const double f = fmax(0.0, v[pb] + v[pb + 1] * Er.env);
+      const double inc = owned_lane && j < J ? f / rc : 0.0;
+      double s = inc;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+      lc[i] += s;
+      lc[i] -= floor(lc[i]);
+    }
+  }
+  __syncthreads();
+
+  // ---- backward over chunks ----
+  double Gend1 = 0.0, Gend2 = 0.0;     // sum of D over all later segments
+  double Lsuf[2] = {0.0, 0.0};         // sum of dtheta_lfo over all later control samples
+  for (int64_t c = nchunks - 1; c >= 0; --c) {
+    const int64_t j = c * kSegsPerChunk - 1 + lane;
+    const double jd = (double)j;
+    const bool inr = j >= 0 && j < J;
+    const bool own = owned_lane && inr;
+    double R[kNumRed];
+#pragma unroll
+    for (int r = 0; r < kNumRed; ++r) R[r] = inr ? rv[j * kNumRed + r] : 0.0;
+    // segment phase adjoints: Gend over later segments of this chunk + carry
+    const double D1 = own ? R[kRD1] : 0.0, D2 = own ? R[kRD2] : 0.0;
+    const double Ge1 = Gend1 + wave_rev_excl_scan(D1, lane);
+    const double Ge2 = Gend2 + wave_rev_excl_scan(D2, lane);
+    // lane 0 (segment 62c - 1) needs the sum over all of this chunk's segments
+    const double G1 = lane == 0 ? __shfl(Ge1, 1) + __shfl(D1, 1) : Ge1;
+    const double G2 = lane == 0 ? __shfl(Ge2, 1) + __shfl(D2, 1) : Ge2;
+    const double B01 = (G1 + R[kRD1]) * R[kRC01] - R[kRE01];
+    const double B11 = (G1 + R[kRD1]) * R[kRC11] - R[kRE11];
+    const double B02 = (G2 + R[kRD2]) * R[kRC02] - R[kRE02];
+    const double B12 = (G2 + R[kRD2]) * R[kRC12] - R[kRE12];
+    {
+      double s1 = D1, s2 = D2;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        s1 += __shfl_xor(s1, o);
+        s2 += __shfl_xor(s2, o);
+      }
+      Gend1 += s1;
+      Gend2 += s2;
+    }
+    // right-end contributions come from the previous segment (lane - 1)
+    const double pB11 = __shfl_up(B11, 1), pB12 = __shfl_up(B12, 1);
+    const double pA11 = __shfl_up(R[kRA11], 1), pA13 = __shfl_up(R[kRA13], 1);
+    const double pA14 = __shfl_up(R[kRA14], 1);
+    const bool lastj = (j == J - 1);
+
+    // forward recompute at control sample j
+    EnvEval E[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) E[k] = env_eval(dv, k, jd, note_off);
+    double ph[2], shp[2][5], lfo[2], fpre[2];
+    {
+      // LFO phase: carry at the chunk's first owned sample + exclusive scan
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int pb = 32 + 8 * i;
+        fpre[i] = v[pb] + v[pb + 1] * E[2 + 2 * i].env;
+        const double inc = owned_lane ? fmax(0.0, fpre[i]) / rc : 0.0;
+        double incl = inc;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+          const double t = __shfl_up(incl, d);
+          if (lane >= d) incl += t;
+        }
+        const double th = S.lfo_carry[c][i] + (incl - inc);
+        const double p = th - floor(th);
+        ph[i] = p;
+        shp[i][0] = (1.0 + sinpi(2.0 * p)) / 2.0;
+        shp[i][1] = 1.0 - fabs(2.0 * p - 1.0);
+        shp[i][2] = p;
+        shp[i][3] = 1.0 - p;
+        shp[i][4] = p < 0.5 ? 1.0 : 0.0;
+        const double num = v[pb + 3] * shp[i][0] + v[pb + 4] * shp[i][1] + v[pb + 5] * shp[i][2] +
+                           v[pb + 6] * shp[i][3] + v[pb + 7] * shp[i][4];
+        lfo[i] = num * dv[kLfoInvW + i];
+      }
+    }
+    const double x[4] = {E[0].env, E[1].env, lfo[0] * E[3].env, lfo[1] * E[5].env};
+    double y[5];
+#pragma unroll
+    for (int o = 0; o < 5; ++o) {
+      const int pb = 48 + 4 * o;
+      y[o] = (v[pb] * x[0] + v[pb + 1] * x[1] + v[pb + 2] * x[2] + v[pb + 3] * x[3]) *
+             dv[kMixInvNorm + o];
+    }
+    double yn_p[2];
+    {
+      const double t0 = __shfl_down(y[0], 1), t2 = __shfl_down(y[2], 1);
+      yn_p[0] = lastj ? y[0] : t0;
+      yn_p[1] = lastj ? y[2] : t2;
+    }
+
+    // dy_o(j): transposed upsampling of the segment adjoints
+    double dy[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (own) {
+      const double b1 = B01 + (lane >= 1 ? pB11 : 0.0) + (lastj ? B11 : 0.0);
+      const double b2 = B02 + (lane >= 1 ? pB12 : 0.0) + (lastj ? B12 : 0.0);
+      dy[0] = v[69] * kPitch * b1;
+      dy[2] = v[72] * kPitch * b2;
+      dy[1] = R[kRA01] + pA11 + (lastj ? R[kRA11] : 0.0);
+      dy[3] = R[kRA03] + pA13 + (lastj ? R[kRA13] : 0.0);
+      dy[4] = R[kRA04] + pA14 + (lastj ? R[kRA14] : 0.0);
+      // pitch, phase, level, shape and K contributions of segment j
+      const double m1 = kPitch * (B01 + B11), m2 = kPitch * (B02 + B12);
+      gadd(S, 0, lane, m1 + m2);
+      gadd(S, 68, lane, m1);
+      gadd(S, 71, lane, m2);
+      gadd(S, 69, lane, kPitch * (y[0] * B01 + yn_p[0] * B11));
+      gadd(S, 72, lane, kPitch * (y[2] * B02 + yn_p[1] * B12));
+      gadd(S, 70, lane, R[kRD1] / kTwoPi);
+      gadd(S, 73, lane, R[kRD2] / kTwoPi);
+      gadd(S, 75, lane, R[kRL1]);
+      gadd(S, 76, lane, R[kRL2]);
+      gadd(S, 77, lane, R[kRL3]);
+      gadd(S, 74, lane, R[kRShape]);
+    }
+    // the square-saw gain K = 12000 / (f_hi log10 f_hi), f_hi from the highest pitch
+    const double dK = own ? R[kRK] : 0.0;
+    if (dK != 0.0) {
+      const double midi = v[0];
+      const double mh = midi + v[71] + fmax(0.0, v[72]);
+      const double m_hi = fmax(0.0, mh);
+      const double fh = 440.0 * exp2((m_hi - 69.0) / 12.0);
+      if (fh <= a.sr / 2.0) {
+        const double Kd = 12000.0 / (fh * log10(fh));
+        const double dKdf = -(Kd / fh) * (1.0 + 1.0 / log(fh));
+        const double dm = dK * dKdf * fh * kPitch;
+        if (mh >= 0.0) {
+          gadd(S, 0, lane, dm);
+          gadd(S, 71, lane, dm);
+          if (v[72] >= 0.0) gadd(S, 72, lane, dm);
+        }
+      }
+    }
+
+    // modulation mixer: y_o = sum_i G_oi x_i / n_o, n_o = max(1, sum_i G_oi)
+    double dx[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int o = 0; o < 5; ++o) {
+      const int pb = 48 + 4 * o;
+      const double inv = dv[kMixInvNorm + o];
+      const bool big = (v[pb] + v[pb + 1] + v[pb + 2] + v[pb + 3]) >= 1.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        dx[i] += v[pb + i] * dy[o] * inv;
+        if (own) gadd(S, pb + i, lane, dy[o] * (x[i] - (big ? y[o] : 0.0)) * inv);
+      }
+    }
+    double denv[6] = {dx[0], dx[1], 0.0, 0.0, 0.0, 0.0};
+    // LFOs
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int pb = 32 + 8 * i;
+      const double dl = dx[2 + i] * E[3 + 2 * i].env;
+      denv[3 + 2 * i] += dx[2 + i] * lfo[i];
+      const double invW = dv[kLfoInvW + i];
+      double dph = 0.0;
+      if (invW > 0.0) {
+        const double p = ph[i];
+        const double sd = (p * 2.0 - 1.0) > 0.0 ? 1.0 : ((p * 2.0 - 1.0) < 0.0 ? -1.0 : 0.0);
+        const double der = v[pb + 3] * (0.5 * kTwoPi * cospi(2.0 * p)) + v[pb + 4] * (-2.0 * sd) +
+                           v[pb + 5] - v[pb + 6];
+        dph = own ? dl * der * invW : 0.0;
+        if (own)
+#pragma unroll
+          for (int k = 0; k < 5; ++k) gadd(S, pb + 3 + k, lane, dl * (shp[i][k] - lfo[i]) * invW);
+      }
+      // phase: d phi += dph / 2 pi; d inc(k) = sum_{j > k} dph(j)
+      if (own) gadd(S, pb + 2, lane, dph / kTwoPi);
+      const double later = Lsuf[i] + wave_rev_excl_scan(dph, lane);
+      {
+        double s = dph;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        Lsuf[i] += s;
+      }
+      if (own && fpre[i] >= 0.0) {
+        const double df = later / rc;
+        gadd(S, pb, lane, df);
+        gadd(S, pb + 1, lane, df * E[2 + 2 * i].env);
+        denv[2 + 2 * i] += df * v[pb + 1];
+      }
+    }
+    // ADSRs
+    if (own) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const int pb = 2 + 5 * k;
+        const EnvEval& e = E[k];
+        const double de = denv[k];
+        if (de == 0.0) continue;
+        const double A = dv[kEnvA + k], D = dv[kEnvD + k], Rr = dv[kEnvR + k];
+        const double Sus = dv[kEnvS + k], al = dv[kEnvAlpha + k];
+        const double dPa = de * e.M * e.Pr;
+        const double dM = de * e.Pa * e.Pr;
+        const double dPr = de * e.Pa * e.M;
+        gadd(S, pb + 2, lane, dM * (1.0 - e.Pd));
+        const double dPd = dM * (1.0 - Sus);
+        double gx, ga, dA = 0.0, dD = 0.0, dR = 0.0, dO = 0.0, dal = 0.0;
+        pow01_grad(e.att, al, e.Pa, gx, ga);
+        dal += dPa * ga;
+        if (ramp_live(jd, 0.0, A, dv[kEnvInvA + k])) dA += dPa * gx * (-jd * dv[kEnvInvA + k] * dv[kEnvInvA + k]);
+        pow01_grad(1.0 - e.dec, al, e.Pd, gx, ga);
+        dal += dPd * ga;
+        if (ramp_live(jd, A, D, dv[kEnvInvD + k])) {
+          const double dd = -dPd * gx;       // d/d dec
+          dA += dd * (-dv[kEnvInvD + k]);
+          dD += dd * (-(jd - A) * dv[kEnvInvD + k] * dv[kEnvInvD + k]);
+        }
+        pow01_grad(1.0 - e.rel, al, e.Pr, gx, ga);
+        dal += dPr * ga;
+        if (ramp_live(jd, note_off, Rr, dv[kEnvInvR + k])) {
+          const double dr = -dPr * gx;       // d/d rel
+          dO += dr * (-dv[kEnvInvR + k]);
+          dR += dr * (-(jd - note_off) * dv[kEnvInvR + k] * dv[kEnvInvR + k]);
+        }
+        gadd(S, pb + 0, lane, dA * rc);
+        gadd(S, pb + 1, lane, dD * rc);
+        gadd(S, pb + 3, lane, dR * rc);
+        gadd(S, pb + 4, lane, dal);
+        gadd(S, 1, lane, dO * rc);
+      }
+    }
+  }
+  __syncthreads();
+  // ---- lane-order reduction and the curve-mapping Jacobian ----
+  for (int p = lane; p < kNumParams; p += kWave) {
+    double s = 0.0;
+    for (int l = 0; l < kWave; ++l) s += S.gacc[p][l];
+    const double u = (double)a.params[b * kNumParams + p];
+    const NebulaArgs& nb = a.neb;
+    const double span = nb.hi[p] - nb.lo[p];
+    const bool lin = bit(nb.linear, p);
+    const double e = nb.inv_curve[p];
+    double jac;
+    if (!bit(nb.sym, p)) {
+      jac = lin ? span : (u > 0.0 ? span * e * pow(u, e - 1.0) : 0.0);
+    } else {
+      const double d = 2.0 * u - 1.0;
+      const double ad = fabs(d);
+      jac = ad > 0.0 ? (lin ? span : span * e * pow(ad, e - 1.0)) : 0.0;
+    }
+    grad_params[b * kNumParams + p] = (float)(s * jac);
+  }
+}
+
+template <int RPS>
+hipError_t launch_adjoint_rps(const RenderArgs& a, const float* g, double* red, float* gp,
+                              hipStream_t s) {
+  size_t shmem = (size_t)2 * kWave * (a.q / RPS) * sizeof(float);
+  if (shmem < 8 * kWave * sizeof(double)) shmem = 8 * kWave * sizeof(double);
+  hipLaunchKernelGGL((adjoint_audio_kernel<RPS>), dim3((unsigned)a.batch), dim3(kWave), shmem, s,
+                     a, g, red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(adjoint_control_kernel, dim3((unsigned)a.batch), dim3(kWave), 0, s, a, red,
+                     gp);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t adjoint_workspace_bytes(int64_t batch, int64_t n_samples, int q) {
+  const int64_t J = (n_samples + q - 1) / q;
+  return (size_t)batch * (size_t)J * kNumRed * sizeof(double);
+}
+
+int64_t adjoint_max_chunks() { return 512; }
+
+hipError_t launch_render_backward(const RenderArgs& a, const float* grad_audio, double* ws,
+                                  float* grad_params, int runs_per_segment, hipStream_t s) {
+  if (a.batch == 0) return hipSuccess;
+  switch (runs_per_segment) {
+    case 1: return launch_adjoint_rps<1>(a, grad_audio, ws, grad_params, s);
+    case 2: return launch_adjoint_rps<2>(a, grad_audio, ws, grad_params, s);
+    case 4: return launch_adjoint_rps<4>(a, grad_audio, ws, grad_params, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace synth

@@ -170,6 +170,40 @@ int synth_render(const synth_config* cfg, const float* params, const uint64_t* v
                            slices, 0, 0, stream);
 }
 
+size_t synth_render_backward_workspace(const synth_config* cfg, int64_t batch, int64_t n_samples) {
+  RenderArgs a;
+  bool clamp = false;
+  if (prepare(cfg, &a, &clamp) != SYNTH_OK || batch < 0 || n_samples <= 0) return 0;
+  return synth::adjoint_workspace_bytes(batch, n_samples, a.q);
+}
+
+int synth_render_backward(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
+                          uint64_t first_g, int64_t batch, int64_t n_samples,
+                          const float* grad_audio, float* grad_params, void* workspace,
+                          size_t workspace_bytes, void* stream) {
+  if (batch < 0) return SYNTH_EINVAL;
+  RenderArgs a;
+  bool clamp = false;
+  const int st = prepare(cfg, &a, &clamp);
+  if (st != SYNTH_OK) return st;
+  if (batch == 0) return SYNTH_OK;
+  if (!params || !grad_audio || !grad_params || !workspace) return SYNTH_EINVAL;
+  if (n_samples <= 0 || n_samples > ((int64_t)1 << 40) || batch > 0x7FFFFFFF) return SYNTH_EINVAL;
+  if (a.mix_mode != 0 || clamp) return SYNTH_EUNSUPPORTED;
+  const int64_t J = (n_samples + a.q - 1) / a.q;
+  if ((J + kSegsPerChunk - 1) / kSegsPerChunk > synth::adjoint_max_chunks()) return SYNTH_EUNSUPPORTED;
+  if (workspace_bytes < synth::adjoint_workspace_bytes(batch, n_samples, a.q)) return SYNTH_ENOMEM;
+  const int rps = (a.q % 4 == 0 && a.q / 4 <= 192) ? 4 : 1;
+  a.params = params;
+  a.voice_ids = voice_ids;
+  a.first_g = first_g;
+  a.batch = batch;
+  a.n_uniform = n_samples;
+  a.slices = 1;
+  return to_status(synth::launch_render_backward(a, grad_audio, (double*)workspace, grad_params,
+                                                 rps, (hipStream_t)stream));
+}
+
 int synth_mrstft_loss(const float* x, const float* target, int64_t batch, int64_t n_samples,
                       double* loss, float* grad_x, void* stream) {
   if (batch < 0 || n_samples <= 0 || n_samples > ((int64_t)1 << 31)) return SYNTH_EINVAL;

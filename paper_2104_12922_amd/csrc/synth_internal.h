@@ -47,6 +47,11 @@ hipError_t launch_render(const RenderArgs& a, int runs_per_segment, bool clamp, 
 
 hipError_t launch_peak_normalise(const RenderArgs& a, hipStream_t s);
 
+size_t adjoint_workspace_bytes(int64_t batch, int64_t n_samples, int q);
+int64_t adjoint_max_chunks();
+hipError_t launch_render_backward(const RenderArgs& a, const float* grad_audio, double* ws,
+                                  float* grad_params, int runs_per_segment, hipStream_t s);
+
 hipError_t launch_mrstft(const float* x, const float* target, int64_t batch, int64_t n_samples,
                          double* loss, float* grad, hipStream_t s);
 
