@@ -140,7 +140,8 @@ int synth_render_backward(const synth_config* cfg, const float* params, const ui
  *   For voice b: loss[b] = sum over n in (512, 1024, 2048), hop n/4, of the mean
  *   over frames t < F_n = floor((N - n) / hop) + 1 and bins k <= n/2 of
  *   |log(|X_tk| + 1e-5) - log(|T_tk| + 1e-5)|, X and T the periodic-Hann STFTs
- *   (frames start at t * hop, no padding) of x and target.
+ *   (frames start at t * hop, no padding) of x and target; a resolution with
+ *   no complete frame (n_samples < n) contributes 0.
  *   x, target  dev float32 [batch][n_samples].
  *   loss       dev float64 [batch], written.
  *   grad_x     dev float32 [batch][n_samples] or NULL; if given it receives

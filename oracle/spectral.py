@@ -13,7 +13,8 @@ HTK mel scale) are listed in the design doc.
   stft(x, n, hop)     X[t, k] = sum_m w(m) x(t*hop + m) exp(-2 pi i k m / n),
                       k = 0..n/2, w(m) = (1 - cos(2 pi m / n)) / 2
   mrstft_loss(x, T)   sum over n in (512, 1024, 2048), hop n/4, of the mean over
-                      (voice, frame, bin) of |log(|X| + 1e-5) - log(|T| + 1e-5)|
+                      (voice, frame, bin) of |log(|X| + 1e-5) - log(|T| + 1e-5)|;
+                      a resolution without a complete frame contributes 0
   logmel(x)           log(M |X|^2 + 1e-6), 64 frames of n = 2048 at hop 2756,
                       128 HTK triangles from 0 to sr/2, no area normalisation
 """
@@ -65,9 +66,12 @@ def dft_bruteforce(frame: np.ndarray) -> np.ndarray:
 
 
 def mrstft_loss(x: torch.Tensor, target: torch.Tensor, sizes=MR_SIZES) -> torch.Tensor:
-    """Multi-resolution log-magnitude STFT L1 between [B, N] batches (scalar)."""
+    """Multi-resolution log-magnitude STFT L1 between [B, N] batches (scalar).
+    A resolution with no complete frame (N < n) contributes 0."""
     total = torch.zeros((), dtype=F64)
     for n in sizes:
+        if num_frames(x.shape[-1], n, n // 4) == 0:
+            continue
         X = stft(x, n, n // 4).abs()
         T = stft(target, n, n // 4).abs()
         total = total + (torch.log(X + MAG_EPS) - torch.log(T + MAG_EPS)).abs().mean()
@@ -78,6 +82,8 @@ def mrstft_loss_per_voice(x: torch.Tensor, target: torch.Tensor, sizes=MR_SIZES)
     """Same loss, one value per voice [B] (mean over frames and bins of each voice)."""
     total = torch.zeros(x.shape[0], dtype=F64)
     for n in sizes:
+        if num_frames(x.shape[-1], n, n // 4) == 0:
+            continue
         X = stft(x, n, n // 4).abs()
         T = stft(target, n, n // 4).abs()
         total = total + (torch.log(X + MAG_EPS) - torch.log(T + MAG_EPS)).abs().mean(dim=(-2, -1))

@@ -161,8 +161,12 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
       for (int r = 0; r < kNumRed; ++r) acc[r] = 0.0;
       double P1 = 0.0, P2 = 0.0;
       const int seg_valid = ls < nseg ? 1 : 0;
+      // samples of this run that exist in the voice (the last segment may be partial)
+      const int64_t run0 = (c * kSegsPerChunk + ls) * (int64_t)q + m * h;
+      const int nlive = seg_valid ? (int)(N - run0 < h ? (N - run0 > 0 ? N - run0 : 0) : h) : 0;
       for (int k = 0; k < h; ++k) {
         const int ks = m * h + k;                  // sample index within the segment
+        const double live = k < nlive ? 1.0 : 0.0;
         const float kf = (float)ks;
         const double wt1 = (double)ks / qd, wt0 = 1.0 - wt1;
         const float gk = seg_valid ? tg[lane * h + k] : 0.0f;
@@ -188,14 +192,15 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
         // phase-adjoint reductions (float64)
         P1 += (double)dth1;
         P2 += (double)dth2;
-        acc[kRC01] += wt0 * i1;
-        acc[kRC11] += wt1 * i1;
-        acc[kRE01] += wt0 * i1 * P1;
-        acc[kRE11] += wt1 * i1 * P1;
-        acc[kRC02] += wt0 * i2;
-        acc[kRC12] += wt1 * i2;
-        acc[kRE02] += wt0 * i2 * P2;
-        acc[kRE12] += wt1 * i2 * P2;
+        const double l1 = live * i1, l2 = live * i2;
+        acc[kRC01] += wt0 * l1;
+        acc[kRC11] += wt1 * l1;
+        acc[kRE01] += wt0 * l1 * P1;
+        acc[kRE11] += wt1 * l1 * P1;
+        acc[kRC02] += wt0 * l2;
+        acc[kRC12] += wt1 * l2;
+        acc[kRE02] += wt0 * l2 * P2;
+        acc[kRE12] += wt1 * l2 * P2;
         // VCA rows (transposed upsampling weights), levels, shape, K
         const double d1 = (double)(gk * L1 * x1), d3 = (double)(gk * L2 * x2), d4 = (double)(L3 * gnk);
         acc[kRA01] += wt0 * d1;
@@ -369,9 +374,13 @@ __global__ void __launch_bounds__(kWave) adjoint_control_kernel(const RenderArgs
     const double D1 = own ? R[kRD1] : 0.0, D2 = own ? R[kRD2] : 0.0;
     const double Ge1 = Gend1 + wave_rev_excl_scan(D1, lane);
     const double Ge2 = Gend2 + wave_rev_excl_scan(D2, lane);
-    // lane 0 (segment 62c - 1) needs the sum over all of this chunk's segments
-    const double G1 = lane == 0 ? __shfl(Ge1, 1) + __shfl(D1, 1) : Ge1;
-    const double G2 = lane == 0 ? __shfl(Ge2, 1) + __shfl(D2, 1) : Ge2;
+    // lane 0 (segment 62c - 1) needs the sum over all of this chunk's segments.
+    // The shuffles run on every lane: a cross-lane read from a lane that is
+    // masked off by a branch returns no data.
+    const double ge1_1 = __shfl(Ge1, 1), d1_1 = __shfl(D1, 1);
+    const double ge2_1 = __shfl(Ge2, 1), d2_1 = __shfl(D2, 1);
+    const double G1 = lane == 0 ? ge1_1 + d1_1 : Ge1;
+    const double G2 = lane == 0 ? ge2_1 + d2_1 : Ge2;
     const double B01 = (G1 + R[kRD1]) * R[kRC01] - R[kRE01];
     const double B11 = (G1 + R[kRD1]) * R[kRC11] - R[kRE11];
     const double B02 = (G2 + R[kRD2]) * R[kRC02] - R[kRE02];

@@ -3,9 +3,10 @@ float64 oracle (autograd of the oracle loss), through the C ABI.
 
 Tolerances come from the arithmetic: evaluating the same definition with
 float32 FFTs on the CPU moves the per-voice loss by < 2e-7 relative and the
-gradient by < 2e-3 relative L2 (bins near the float32 noise floor, where
-d log|X| / d|X| = 1 / (|X| + 1e-5) is large).  The GPU kernel is held to 1e-5
-and 1e-2 respectively.
+gradient by up to ~2e-3 relative L2 (more for very quiet voices: bins near the
+float32 noise floor, where d log|X| / d|X| = 1 / (|X| + 1e-5) is large).  The
+GPU kernel is held to 1e-5 on the loss and, per voice, to max(1e-2, 10x the
+CPU float32 evaluation's error) on the gradient.
 """
 import sys
 
@@ -33,11 +34,26 @@ def renders(seed, B, N):
                                 noise_seed=seed).float()
 
 
+def loss32(x, t):
+    """The same definition evaluated with float32 FFTs on the CPU."""
+    tot = torch.zeros(x.shape[0])
+    for n in sp.MR_SIZES:
+        if sp.num_frames(x.shape[-1], n, n // 4) == 0:
+            continue
+        w = sp.hann(n).float()
+        X = torch.fft.rfft(sp.frames(x, n, n // 4) * w, dim=-1).abs()
+        T = torch.fft.rfft(sp.frames(t, n, n // 4) * w, dim=-1).abs()
+        tot = tot + (torch.log(X + 1e-5) - torch.log(T + 1e-5)).abs().mean(dim=(-2, -1))
+    return tot
+
+
 def check(synth, x32, t32, loss_rtol=1e-5, grad_rtol=1e-2):
     x64, t64 = x32.double(), t32.double()
     xr = x64.clone().requires_grad_(True)
     ref = sp.mrstft_loss_per_voice(xr, t64)
     ref.sum().backward()
+    xf = x32.clone().requires_grad_(True)
+    loss32(xf, t32).sum().backward()
     loss, g = synth.synth_mrstft_loss(x32.cuda(), t32.cuda(), grad=True)
     torch.cuda.synchronize()
     loss, g = loss.cpu(), g.cpu().double()
@@ -49,7 +65,9 @@ def check(synth, x32, t32, loss_rtol=1e-5, grad_rtol=1e-2):
             assert g[b].abs().max() == 0
             continue
         err = float((g[b] - gr).norm() / gr.norm())
-        assert err <= grad_rtol, (b, err)
+        err32 = float((xf.grad[b].double() - gr).norm() / gr.norm())
+        print("voice", b, "grad rel L2", err, "cpu float32", err32, file=sys.stderr, flush=True)
+        assert err <= max(grad_rtol, 10 * err32), (b, err, err32)
 
 
 def test_mrstft_loss_and_grad_4s(synth):
