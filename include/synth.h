@@ -150,6 +150,74 @@ int synth_render_backward(const synth_config* cfg, const float* params, const ui
 int synth_mrstft_loss(const float* x, const float* target, int64_t batch, int64_t n_samples,
                       double* loss, float* grad_x, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Learned proposal: log-mel features and an MLP mapping them to parameters
+ * (inverse synthesis, audio -> parameters, Section 2).  bf16 operands with
+ * float32 accumulation on the MFMA units.  "bf16" pointers hold raw bfloat16
+ * (uint16) values.  All pointers are dev unless stated; all calls are
+ * stream-ordered, deterministic, and write only the outputs named.
+ * ------------------------------------------------------------------------- */
+
+/* C[M][N] (row stride ldc) = epi(alpha * A B + bias) (+ beta * C).
+ *   a_layout 0: A[m * lda + k] (K contiguous); 1: A[k * lda + m].
+ *   b_layout 0: B[n * ldb + k] (K contiguous); 1: B[k * ldb + n].
+ *   c_bf16 1: C is bf16, 0: float32.  bias float32 [N] or NULL.
+ *   epilogue 0 none, 1 GELU (erf form), 2 sigmoid, 3 multiply by GELU'(aux)
+ *   with aux float32 laid out like C.  pre: optional float32 copy of the
+ *   pre-epilogue value (layout of C).  Operands need not be aligned; 16-byte
+ *   aligned rows take the vector path. */
+int synth_gemm_bf16(int a_layout, int b_layout, int64_t M, int64_t N, int64_t K, const void* A,
+                    int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc, int c_bf16,
+                    const float* bias, int epilogue, const float* aux, float* pre, float alpha,
+                    float beta, void* stream);
+
+/* Log-mel features: 64 frames of 2048 samples at hop 2756 (no padding),
+ * periodic Hann window, power spectrum via a bf16 DFT GEMM, 128 HTK mel
+ * triangles from 0 to sample_rate / 2 (no area normalisation), log(x + 1e-6).
+ * synth_logmel_init fills the tables once: dft_basis bf16 [2050][2048]
+ * (rows cos, -sin per bin), mel_basis bf16 [128][1032]; it synchronises the
+ * stream.  synth_logmel: audio float32 [batch][n_samples] with
+ * n_samples >= 175676; workspace >= synth_logmel_workspace(batch) bytes;
+ * features float32 [batch][128][64] (mel bin major, frame minor). */
+size_t synth_logmel_workspace(int64_t batch);
+int synth_logmel_init(double sample_rate, void* dft_basis, void* mel_basis, void* stream);
+int synth_logmel(const float* audio, int64_t batch, int64_t n_samples, const void* dft_basis,
+                 const void* mel_basis, void* workspace, size_t workspace_bytes, float* features,
+                 void* stream);
+
+/* Column sums (and sums of squares if sumsq != NULL) of a rows x cols matrix
+ * (row stride ld; bf16 if x_bf16 else float32), float32 outputs [cols]. */
+int synth_colstats(const void* x, int x_bf16, int64_t rows, int64_t cols, int64_t ld, float* sum,
+                   float* sumsq, void* stream);
+/* y (bf16) = (x - mean[col]) * inv_std[col] for a rows x cols float32 matrix. */
+int synth_standardize(const float* x, const float* mean, const float* inv_std, int64_t rows,
+                      int64_t cols, void* y_bf16, void* stream);
+/* y (bf16) = round-to-nearest-even(x), n elements. */
+int synth_to_bf16(const float* x, void* y, int64_t n, void* stream);
+
+/* MLP forward, d_in -> d_h -> d_h -> d_out: h1 = gelu(x W1 + b1),
+ * h2 = gelu(h1 W2 + b2), out = sigmoid(h2 W3 + b3).  Weights are stored
+ * transposed and K-major: w1t [d_h][d_in], w2t [d_h][d_h], w3t [d_out][d_h]
+ * (bf16); biases float32.  x, h1, h2 bf16 [batch][.]; h1pre, h2pre float32
+ * pre-activations (may be NULL when no backward follows); out float32. */
+int synth_mlp_forward(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out, const void* x,
+                      const void* w1t, const float* b1, const void* w2t, const float* b2,
+                      const void* w3t, const float* b3, float* h1pre, void* h1, float* h2pre,
+                      void* h2, float* out, void* stream);
+/* MLP backward of the loss mean((out - target)^2) over batch x d_out:
+ * loss_rows (float64 [batch]) receives each row's sum of squared errors;
+ * gw*t (float32, layouts of w*t) and gb* (float32) receive the gradients;
+ * dz3 bf16 [batch][d_out], dh2 / dh1 bf16 [batch][d_h] are scratch. */
+int synth_mlp_backward(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out, const void* x,
+                       const void* w2t, const void* w3t, const float* h1pre, const void* h1,
+                       const float* h2pre, const void* h2, const float* out, const float* target,
+                       float* gw1t, float* gb1, float* gw2t, float* gb2, float* gw3t, float* gb3,
+                       void* dz3, void* dh2, void* dh1, double* loss_rows, void* stream);
+/* Bias-corrected Adam step `step` (>= 1) on float32 w with moments m, v; if
+ * w_bf16 != NULL it receives the updated weights rounded to bf16. */
+int synth_adam(int64_t n, float* w, void* w_bf16, const float* grad, float* m, float* v, float lr,
+               float beta1, float beta2, float eps, int step, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -120,3 +120,26 @@ def logmel(x: torch.Tensor, sr: float = 44100.0) -> torch.Tensor:
     M = torch.from_numpy(mel_filterbank(sr))                    # [128, 1025]
     mel = torch.einsum("bk,ntk->nbt", M, P)                     # [B, 128, 64]
     return torch.log(mel + MEL_EPS)
+
+
+def logmel_bf16(x: torch.Tensor, sr: float = 44100.0) -> torch.Tensor:
+    """Log-mel with the GPU path's quantisation points: windowed frames, DFT
+    basis, power spectrum and mel basis rounded to bfloat16 (the window and the
+    basis through float32); products accumulated in float64 here.
+    Returns [B, 128, 64]."""
+    n = MEL_NFFT
+    k = torch.arange(n, dtype=torch.float32)
+    w = 0.5 - 0.5 * torch.cos(2.0 * math.pi * k / n)                  # float32 window
+    fr = frames(x.float(), n, MEL_HOP, count=MEL_FRAMES) * w          # float32 product
+    fr = fr.to(torch.bfloat16).to(F64)
+    f = torch.arange(n // 2 + 1, dtype=torch.int64)[:, None]
+    ph = (f * torch.arange(n)[None, :]) % n                           # exact angle reduction
+    ang = 2.0 * math.pi * ph.to(F64) / n
+    cosb = torch.cos(ang).float().to(torch.bfloat16).to(F64)
+    sinb = (-torch.sin(ang)).float().to(torch.bfloat16).to(F64)
+    re = fr @ cosb.T
+    im = fr @ sinb.T
+    P = (re * re + im * im).float().to(torch.bfloat16).to(F64)        # [B, 64, 1025]
+    M = torch.from_numpy(mel_filterbank(sr)).float().to(torch.bfloat16).to(F64)
+    mel = torch.einsum("bk,ntk->nbt", M, P)
+    return torch.log(mel + MEL_EPS)

@@ -214,4 +214,189 @@ int synth_mrstft_loss(const float* x, const float* target, int64_t batch, int64_
                                         (hipStream_t)stream));
 }
 
+// ---------------------------------------------------------------------------
+// bf16 MFMA GEMM, log-mel features, learned proposal (MLP) and Adam
+// ---------------------------------------------------------------------------
+int synth_gemm_bf16(int a_layout, int b_layout, int64_t M, int64_t N, int64_t K, const void* A,
+                    int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc, int c_bf16,
+                    const float* bias, int epilogue, const float* aux, float* pre, float alpha,
+                    float beta, void* stream) {
+  if (M < 0 || N < 0 || K < 0) return SYNTH_EINVAL;
+  if (M == 0 || N == 0) return SYNTH_OK;
+  if (!A || !B || !C) return SYNTH_EINVAL;
+  if ((a_layout != synth::kOpKMajor && a_layout != synth::kOpRowMajorMN) ||
+      (b_layout != synth::kOpKMajor && b_layout != synth::kOpRowMajorMN))
+    return SYNTH_EINVAL;
+  if (epilogue < synth::kEpiNone || epilogue > synth::kEpiGeluGrad) return SYNTH_EINVAL;
+  if (epilogue == synth::kEpiGeluGrad && !aux) return SYNTH_EINVAL;
+  if (lda < (a_layout == synth::kOpKMajor ? K : M) || ldb < (b_layout == synth::kOpKMajor ? K : N) ||
+      ldc < N)
+    return SYNTH_EINVAL;
+  synth::GemmArgs g = {};
+  g.M = M; g.N = N; g.K = K; g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.c_bf16 = c_bf16 ? 1 : 0; g.bias = bias; g.epilogue = epilogue; g.aux = aux; g.pre = pre;
+  g.alpha = alpha; g.beta = beta;
+  return to_status(synth::launch_gemm_bf16(g, a_layout, b_layout, (hipStream_t)stream));
+}
+
+namespace {
+constexpr int kMelNfft = 2048, kMelHop = 2756, kMelFrames = 64, kMelBins = 128, kMelLd = 1032;
+
+uint16_t host_f2bf(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+}  // namespace
+
+size_t synth_logmel_workspace(int64_t batch) {
+  return batch < 0 ? 0 : (size_t)batch * kMelFrames * kMelLd * sizeof(uint16_t);
+}
+
+int synth_logmel_init(double sample_rate, void* dft_basis, void* mel_basis, void* stream) {
+  if (!dft_basis || !mel_basis || !(sample_rate > 0.0)) return SYNTH_EINVAL;
+  hipError_t e = synth::launch_dft_basis(dft_basis, kMelNfft, (hipStream_t)stream);
+  if (e != hipSuccess) return SYNTH_EDEVICE;
+  // HTK mel triangles (mel = 2595 log10(1 + f / 700)), 130 edges from 0 to sr/2,
+  // peak 1, no area normalisation; stored K-major [128][1032] in bf16.
+  static thread_local uint16_t table[kMelBins * kMelLd];
+  auto hz2mel = [](double f) { return 2595.0 * log10(1.0 + f / 700.0); };
+  auto mel2hz = [](double m) { return 700.0 * (pow(10.0, m / 2595.0) - 1.0); };
+  const double mtop = hz2mel(sample_rate / 2.0);
+  double edges[kMelBins + 2];
+  for (int i = 0; i < kMelBins + 2; ++i) edges[i] = mel2hz(mtop * i / (kMelBins + 1));
+  for (int b = 0; b < kMelBins; ++b)
+    for (int k = 0; k < kMelLd; ++k) {
+      double w = 0.0;
+      if (k <= kMelNfft / 2) {
+        const double f = k * sample_rate / kMelNfft;
+        const double up = (f - edges[b]) / (edges[b + 1] - edges[b]);
+        const double down = (edges[b + 2] - f) / (edges[b + 2] - edges[b + 1]);
+        w = fmax(0.0, fmin(up, down));
+      }
+      table[b * kMelLd + k] = host_f2bf((float)w);
+    }
+  e = hipMemcpyAsync(mel_basis, table, sizeof(table), hipMemcpyHostToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return SYNTH_EDEVICE;
+  return to_status(hipStreamSynchronize((hipStream_t)stream));
+}
+
+int synth_logmel(const float* audio, int64_t batch, int64_t n_samples, const void* dft_basis,
+                 const void* mel_basis, void* workspace, size_t workspace_bytes, float* features,
+                 void* stream) {
+  if (batch < 0) return SYNTH_EINVAL;
+  if (batch == 0) return SYNTH_OK;
+  if (!audio || !dft_basis || !mel_basis || !workspace || !features) return SYNTH_EINVAL;
+  if (n_samples < (int64_t)(kMelFrames - 1) * kMelHop + kMelNfft) return SYNTH_EINVAL;
+  if (workspace_bytes < synth_logmel_workspace(batch)) return SYNTH_ENOMEM;
+  synth::GemmArgs g = {};
+  g.M = batch * kMelFrames; g.N = kMelNfft + 2; g.K = kMelNfft;
+  g.A = audio; g.lda = n_samples; g.frame_hop = kMelHop; g.frame_count = kMelFrames;
+  g.B = dft_basis; g.ldb = kMelNfft;
+  g.C = workspace; g.ldc = kMelLd; g.c_bf16 = 1; g.epilogue = synth::kEpiPowerPairs;
+  g.alpha = 1.0f;
+  hipError_t e = synth::launch_gemm_bf16(g, synth::kOpFrames, synth::kOpKMajor, (hipStream_t)stream);
+  if (e != hipSuccess) return SYNTH_EDEVICE;
+  synth::GemmArgs h = {};
+  h.M = batch * kMelFrames; h.N = kMelBins; h.K = kMelNfft / 2 + 1;
+  h.A = workspace; h.lda = kMelLd; h.B = mel_basis; h.ldb = kMelLd;
+  h.C = features; h.ldc = kMelBins; h.c_bf16 = 0; h.epilogue = synth::kEpiLogMelT; h.alpha = 1.0f;
+  return to_status(synth::launch_gemm_bf16(h, synth::kOpKMajor, synth::kOpKMajor, (hipStream_t)stream));
+}
+
+int synth_colstats(const void* x, int x_bf16, int64_t rows, int64_t cols, int64_t ld, float* sum,
+                   float* sumsq, void* stream) {
+  if (rows < 0 || cols < 0 || ld < cols || (cols > 0 && (!x || !sum))) return SYNTH_EINVAL;
+  return to_status(synth::launch_colsum(x, x_bf16, rows, cols, ld, sum, sumsq, (hipStream_t)stream));
+}
+
+int synth_standardize(const float* x, const float* mean, const float* inv_std, int64_t rows,
+                      int64_t cols, void* y_bf16, void* stream) {
+  if (rows < 0 || cols < 0) return SYNTH_EINVAL;
+  if (rows * cols > 0 && (!x || !mean || !inv_std || !y_bf16)) return SYNTH_EINVAL;
+  return to_status(synth::launch_standardize(x, mean, inv_std, rows, cols, y_bf16, (hipStream_t)stream));
+}
+
+int synth_to_bf16(const float* x, void* y, int64_t n, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !y))) return SYNTH_EINVAL;
+  return to_status(synth::launch_f32_to_bf16(x, y, n, (hipStream_t)stream));
+}
+
+int synth_mlp_forward(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out, const void* x,
+                      const void* w1t, const float* b1, const void* w2t, const float* b2,
+                      const void* w3t, const float* b3, float* h1pre, void* h1, float* h2pre,
+                      void* h2, float* out, void* stream) {
+  if (batch < 0 || d_in <= 0 || d_h <= 0 || d_out <= 0) return SYNTH_EINVAL;
+  if (batch == 0) return SYNTH_OK;
+  if (!x || !w1t || !b1 || !w2t || !b2 || !w3t || !b3 || !h1 || !h2 || !out) return SYNTH_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  synth::GemmArgs g = {};
+  g.alpha = 1.0f;
+  // h1 = gelu(x W1 + b1): A = x [batch][d_in], B = W1^T [d_h][d_in] (K-major)
+  g.M = batch; g.N = d_h; g.K = d_in; g.A = x; g.lda = d_in; g.B = w1t; g.ldb = d_in;
+  g.C = h1; g.ldc = d_h; g.c_bf16 = 1; g.bias = b1; g.epilogue = synth::kEpiGelu; g.pre = h1pre;
+  hipError_t e = synth::launch_gemm_bf16(g, synth::kOpKMajor, synth::kOpKMajor, s);
+  if (e != hipSuccess) return SYNTH_EDEVICE;
+  g.K = d_h; g.A = h1; g.lda = d_h; g.B = w2t; g.ldb = d_h; g.C = h2; g.bias = b2; g.pre = h2pre;
+  e = synth::launch_gemm_bf16(g, synth::kOpKMajor, synth::kOpKMajor, s);
+  if (e != hipSuccess) return SYNTH_EDEVICE;
+  g.N = d_out; g.A = h2; g.B = w3t; g.C = out; g.ldc = d_out; g.c_bf16 = 0; g.bias = b3;
+  g.epilogue = synth::kEpiSigmoid; g.pre = nullptr;
+  return to_status(synth::launch_gemm_bf16(g, synth::kOpKMajor, synth::kOpKMajor, s));
+}
+
+int synth_mlp_backward(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out, const void* x,
+                       const void* w2t, const void* w3t, const float* h1pre, const void* h1,
+                       const float* h2pre, const void* h2, const float* out, const float* target,
+                       float* gw1t, float* gb1, float* gw2t, float* gb2, float* gw3t, float* gb3,
+                       void* dz3, void* dh2, void* dh1, double* loss_rows, void* stream) {
+  if (batch <= 0 || d_in <= 0 || d_h <= 0 || d_out <= 0) return SYNTH_EINVAL;
+  if (!x || !w2t || !w3t || !h1pre || !h1 || !h2pre || !h2 || !out || !target || !gw1t || !gb1 ||
+      !gw2t || !gb2 || !gw3t || !gb3 || !dz3 || !dh2 || !dh1 || !loss_rows)
+    return SYNTH_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  using synth::kOpKMajor;
+  using synth::kOpRowMajorMN;
+  hipError_t e = synth::launch_mse_sigmoid_grad(out, target, batch, d_out, dz3, loss_rows, s);
+  if (e != hipSuccess) return SYNTH_EDEVICE;
+  synth::GemmArgs g = {};
+  g.alpha = 1.0f;
+  // dW3^T [d_out][d_h] = dz3^T h2
+  g.M = d_out; g.N = d_h; g.K = batch; g.A = dz3; g.lda = d_out; g.B = h2; g.ldb = d_h;
+  g.C = gw3t; g.ldc = d_h; g.c_bf16 = 0;
+  if ((e = synth::launch_gemm_bf16(g, kOpRowMajorMN, kOpRowMajorMN, s)) != hipSuccess) return SYNTH_EDEVICE;
+  if ((e = synth::launch_colsum(dz3, 1, batch, d_out, d_out, gb3, nullptr, s)) != hipSuccess) return SYNTH_EDEVICE;
+  // dh2 = (dz3 W3^T^T) * gelu'(h2pre): A = dz3 [batch][d_out], B[k][n] = W3^T[k][n]
+  g = {}; g.alpha = 1.0f;
+  g.M = batch; g.N = d_h; g.K = d_out; g.A = dz3; g.lda = d_out; g.B = w3t; g.ldb = d_h;
+  g.C = dh2; g.ldc = d_h; g.c_bf16 = 1; g.epilogue = synth::kEpiGeluGrad; g.aux = h2pre;
+  if ((e = synth::launch_gemm_bf16(g, kOpKMajor, kOpRowMajorMN, s)) != hipSuccess) return SYNTH_EDEVICE;
+  // dW2^T = dh2^T h1, db2
+  g = {}; g.alpha = 1.0f;
+  g.M = d_h; g.N = d_h; g.K = batch; g.A = dh2; g.lda = d_h; g.B = h1; g.ldb = d_h;
+  g.C = gw2t; g.ldc = d_h;
+  if ((e = synth::launch_gemm_bf16(g, kOpRowMajorMN, kOpRowMajorMN, s)) != hipSuccess) return SYNTH_EDEVICE;
+  if ((e = synth::launch_colsum(dh2, 1, batch, d_h, d_h, gb2, nullptr, s)) != hipSuccess) return SYNTH_EDEVICE;
+  // dh1 = (dh2 W2^T^T) * gelu'(h1pre)
+  g = {}; g.alpha = 1.0f;
+  g.M = batch; g.N = d_h; g.K = d_h; g.A = dh2; g.lda = d_h; g.B = w2t; g.ldb = d_h;
+  g.C = dh1; g.ldc = d_h; g.c_bf16 = 1; g.epilogue = synth::kEpiGeluGrad; g.aux = h1pre;
+  if ((e = synth::launch_gemm_bf16(g, kOpKMajor, kOpRowMajorMN, s)) != hipSuccess) return SYNTH_EDEVICE;
+  // dW1^T = dh1^T x, db1
+  g = {}; g.alpha = 1.0f;
+  g.M = d_h; g.N = d_in; g.K = batch; g.A = dh1; g.lda = d_h; g.B = x; g.ldb = d_in;
+  g.C = gw1t; g.ldc = d_in;
+  if ((e = synth::launch_gemm_bf16(g, kOpRowMajorMN, kOpRowMajorMN, s)) != hipSuccess) return SYNTH_EDEVICE;
+  return to_status(synth::launch_colsum(dh1, 1, batch, d_h, d_h, gb1, nullptr, s));
+}
+
+int synth_adam(int64_t n, float* w, void* w_bf16, const float* grad, float* m, float* v, float lr,
+               float beta1, float beta2, float eps, int step, void* stream) {
+  if (n < 0 || step < 1) return SYNTH_EINVAL;
+  if (n > 0 && (!w || !grad || !m || !v)) return SYNTH_EINVAL;
+  return to_status(synth::launch_adam(n, w, w_bf16, grad, m, v, lr, beta1, beta2, eps, step,
+                                      (hipStream_t)stream));
+}
+
 }  // extern "C"

@@ -1,0 +1,162 @@
+// Elementwise and reduction kernels of the learned proposal: bf16 casts,
+// per-column sums (bias gradients, feature statistics), feature
+// standardisation, the sigmoid-output MSE gradient, Adam, and the DFT basis
+// of the log-mel features.  All deterministic (fixed-order reductions).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "synth_internal.h"
+
+namespace synth {
+namespace {
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__global__ void f32_to_bf16_kernel(const float* __restrict__ x, uint16_t* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = f2bf(x[i]);
+}
+
+// sum (and sum of squares) of each column over rows, one thread per column,
+// rows in order: deterministic.
+__global__ void colsum_kernel(const void* __restrict__ x, int x_bf16, int64_t rows, int64_t cols,
+                              int64_t ld, float* __restrict__ sum, float* __restrict__ sumsq) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double s = 0.0, s2 = 0.0;
+  for (int64_t r = 0; r < rows; ++r) {
+    const float v = x_bf16 ? bf2f(reinterpret_cast<const uint16_t*>(x)[r * ld + c])
+                           : reinterpret_cast<const float*>(x)[r * ld + c];
+    s += v;
+    s2 += (double)v * v;
+  }
+  sum[c] = (float)s;
+  if (sumsq) sumsq[c] = (float)s2;
+}
+
+// y = bf16((x - mean[col]) * inv_std[col])
+__global__ void standardize_kernel(const float* __restrict__ x, const float* __restrict__ mean,
+                                   const float* __restrict__ inv_std, int64_t rows, int64_t cols,
+                                   uint16_t* __restrict__ y) {
+  const int64_t n = rows * cols;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = i % cols;
+    y[i] = f2bf((x[i] - mean[c]) * inv_std[c]);
+  }
+}
+
+// MSE on sigmoid outputs: loss_rows[r] = sum_c (o - u)^2; dz = 2 (o - u) o (1 - o) / (rows cols)
+__global__ void mse_sigmoid_grad_kernel(const float* __restrict__ out, const float* __restrict__ target,
+                                        int64_t rows, int64_t cols, uint16_t* __restrict__ dz,
+                                        double* __restrict__ loss_rows) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const float scale = 2.0f / ((float)rows * (float)cols);
+  double l = 0.0;
+  for (int64_t c = 0; c < cols; ++c) {
+    const float o = out[r * cols + c];
+    const float d = o - target[r * cols + c];
+    l += (double)d * d;
+    dz[r * cols + c] = f2bf(scale * d * o * (1.0f - o));
+  }
+  loss_rows[r] = l;
+}
+
+// Adam (bias-corrected) on float32 master weights, refreshing the bf16 copy.
+__global__ void adam_kernel(int64_t n, float* __restrict__ w, uint16_t* __restrict__ wb,
+                            const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, float lr, float b1, float b2, float eps,
+                            float c1, float c2) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (wb) wb[i] = f2bf(wi);
+  }
+}
+
+// DFT basis, K-major: row 2f = cos(2 pi f k / n), row 2f+1 = -sin(2 pi f k / n),
+// f = 0..n/2, k = 0..n-1 (float64 angle reduction, rounded to bf16).
+__global__ void dft_basis_kernel(uint16_t* __restrict__ basis, int n) {
+  const int64_t total = (int64_t)(n + 2) * n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = i / n, k = i % n;
+    const int64_t f = row >> 1;
+    const int64_t ph = (f * k) % n;            // exact angle reduction
+    const double a = 2.0 * (double)ph / (double)n;
+    const double val = (row & 1) ? -sinpi(a) : cospi(a);
+    basis[i] = f2bf((float)val);
+  }
+}
+
+dim3 grid_for(int64_t n, int threads) {
+  int64_t b = (n + threads - 1) / threads;
+  if (b > 65535 * 4) b = 65535 * 4;
+  if (b < 1) b = 1;
+  return dim3((unsigned)b);
+}
+
+}  // namespace
+
+hipError_t launch_f32_to_bf16(const float* x, void* y, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(f32_to_bf16_kernel, grid_for(n, 256), dim3(256), 0, s, x, (uint16_t*)y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const void* x, int x_bf16, int64_t rows, int64_t cols, int64_t ld,
+                         float* sum, float* sumsq, hipStream_t s) {
+  if (cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, s, x,
+                     x_bf16, rows, cols, ld, sum, sumsq);
+  return hipGetLastError();
+}
+
+hipError_t launch_standardize(const float* x, const float* mean, const float* inv_std,
+                              int64_t rows, int64_t cols, void* y_bf16, hipStream_t s) {
+  if (rows * cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(standardize_kernel, grid_for(rows * cols, 256), dim3(256), 0, s, x, mean,
+                     inv_std, rows, cols, (uint16_t*)y_bf16);
+  return hipGetLastError();
+}
+
+hipError_t launch_mse_sigmoid_grad(const float* out, const float* target, int64_t rows,
+                                   int64_t cols, void* dz_bf16, double* loss_rows,
+                                   hipStream_t s) {
+  if (rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(mse_sigmoid_grad_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0,
+                     s, out, target, rows, cols, (uint16_t*)dz_bf16, loss_rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(int64_t n, float* w, void* w_bf16, const float* g, float* m, float* v,
+                       float lr, float b1, float b2, float eps, int step, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  hipLaunchKernelGGL(adam_kernel, grid_for(n, 256), dim3(256), 0, s, n, w, (uint16_t*)w_bf16, g,
+                     m, v, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_dft_basis(void* basis_bf16, int n_fft, hipStream_t s) {
+  const int64_t total = (int64_t)(n_fft + 2) * n_fft;
+  hipLaunchKernelGGL(dft_basis_kernel, grid_for(total, 256), dim3(256), 0, s,
+                     (uint16_t*)basis_bf16, n_fft);
+  return hipGetLastError();
+}
+
+}  // namespace synth

@@ -38,6 +38,52 @@ struct RenderArgs {
   NebulaArgs neb;
 };
 
+// ---------------------------------------------------------------------------
+// bf16 MFMA GEMM (gemm.hip): C[M x N] = alpha * A[M x K] B[K x N] (+ bias, epilogue)
+// ---------------------------------------------------------------------------
+enum {
+  kEpiNone = 0,        // store x
+  kEpiGelu = 1,        // store gelu(x) (erf form); pre-activation to pre if given
+  kEpiSigmoid = 2,     // store 1 / (1 + exp(-x))
+  kEpiGeluGrad = 3,    // store x * gelu'(aux[row][col])
+  kEpiPowerPairs = 4,  // columns (2f, 2f+1) = (Re, Im): store Re^2 + Im^2 at column f
+  kEpiLogMelT = 5      // store log(x + 1e-6) at feature[(row / 64) * 8192 + col * 64 + row % 64]
+};
+enum { kOpKMajor = 0, kOpRowMajorMN = 1, kOpFrames = 2 };
+
+struct GemmArgs {
+  int64_t M, N, K;
+  const void* A;       // bf16 (or float32 audio for kOpFrames)
+  int64_t lda;         // kOpFrames: samples per voice
+  const void* B;       // bf16
+  int64_t ldb;
+  void* C;
+  int64_t ldc;
+  int c_bf16;          // output dtype: 1 bf16, 0 float32
+  const float* bias;   // [N] or null
+  int epilogue;
+  const float* aux;    // kEpiGeluGrad operand, same layout as C
+  float* pre;          // optional float32 pre-activation output (layout of C)
+  float alpha, beta;   // beta != 0: C = epi(...) + beta * C
+  int frame_hop;       // kOpFrames: hop between frames; frames per voice in frame_count
+  int frame_count;
+};
+
+hipError_t launch_gemm_bf16(const GemmArgs& g, int a_op, int b_op, hipStream_t s);
+
+// elementwise / reduction helpers of the learned proposal (mlp.hip)
+hipError_t launch_f32_to_bf16(const float* x, void* y, int64_t n, hipStream_t s);
+hipError_t launch_colsum(const void* x, int x_bf16, int64_t rows, int64_t cols, int64_t ld,
+                         float* sum, float* sumsq, hipStream_t s);
+hipError_t launch_standardize(const float* x, const float* mean, const float* inv_std,
+                              int64_t rows, int64_t cols, void* y_bf16, hipStream_t s);
+hipError_t launch_mse_sigmoid_grad(const float* out, const float* target, int64_t rows,
+                                   int64_t cols, void* dz_bf16, double* loss_rows,
+                                   hipStream_t s);
+hipError_t launch_adam(int64_t n, float* w, void* w_bf16, const float* g, float* m, float* v,
+                       float lr, float b1, float b2, float eps, int step, hipStream_t s);
+hipError_t launch_dft_basis(void* basis_bf16, int n_fft, hipStream_t s);
+
 hipError_t launch_sample_params(uint64_t seed, uint64_t first_g, int64_t batch,
                                 const uint64_t* voice_ids, float* params, hipStream_t s);
 

@@ -1,0 +1,212 @@
+"""Learned proposal (inverse synthesis, audio -> parameters): log-mel features
+and an MLP 8192 -> 1024 -> 1024 -> 78 (GELU, sigmoid output), trained with Adam.
+
+Argument marshalling only: the DFT and mel GEMMs, the MLP forward and
+backward GEMMs with their fused epilogues, the loss gradient, the bias and
+statistics reductions and Adam all run in libsynth.so's HIP kernels.  bf16
+tensors are torch.bfloat16 (raw bfloat16 storage, as the C ABI expects).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _native
+from . import _dev_ptr, _stream
+
+BF16 = torch.bfloat16
+F32 = torch.float32
+MEL_FEATURES = 128 * 64
+
+
+def _sig(L):
+    vp, i64, i32, f32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_float, ctypes.c_size_t
+    L.synth_gemm_bf16.argtypes = [i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, vp, i32,
+                                  vp, vp, f32, f32, vp]
+    L.synth_logmel_workspace.restype = sz
+    L.synth_logmel_workspace.argtypes = [i64]
+    L.synth_logmel_init.argtypes = [ctypes.c_double, vp, vp, vp]
+    L.synth_logmel.argtypes = [vp, i64, i64, vp, vp, vp, sz, vp, vp]
+    L.synth_colstats.argtypes = [vp, i32, i64, i64, i64, vp, vp, vp]
+    L.synth_standardize.argtypes = [vp, vp, vp, i64, i64, vp, vp]
+    L.synth_to_bf16.argtypes = [vp, vp, i64, vp]
+    L.synth_mlp_forward.argtypes = [i64, i64, i64, i64] + [vp] * 12
+    L.synth_mlp_backward.argtypes = [i64, i64, i64, i64] + [vp] * 19
+    L.synth_adam.argtypes = [i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]
+    for n in ("synth_gemm_bf16", "synth_logmel_init", "synth_logmel", "synth_colstats",
+              "synth_standardize", "synth_to_bf16", "synth_mlp_forward", "synth_mlp_backward",
+              "synth_adam"):
+        getattr(L, n).restype = ctypes.c_int
+    return L
+
+
+_L = None
+
+
+def lib():
+    global _L
+    if _L is None:
+        _L = _sig(_native.lib())
+    return _L
+
+
+def _p(t, name, dtype, numel=None):
+    return _dev_ptr(t, name, dtype, numel)
+
+
+def gemm_bf16(A, B, M, N, K, a_layout=0, b_layout=0, lda=None, ldb=None, out=None, out_bf16=False,
+              bias=None, epilogue=0, aux=None, pre=None, alpha=1.0, beta=0.0):
+    """C = epi(alpha A B + bias) (+ beta C) on the bf16 MFMA GEMM (see synth.h)."""
+    lda = lda or (K if a_layout == 0 else M)
+    ldb = ldb or (K if b_layout == 0 else N)
+    if out is None:
+        out = torch.empty(M, N, dtype=BF16 if out_bf16 else F32, device=A.device)
+    ldc = out.shape[-1]
+    _native.check("synth_gemm_bf16", lib().synth_gemm_bf16(
+        a_layout, b_layout, M, N, K, _p(A, "A", BF16), lda, _p(B, "B", BF16), ldb,
+        _p(out, "C", BF16 if out_bf16 else F32), ldc, int(out_bf16),
+        _p(bias, "bias", F32) if bias is not None else None, epilogue,
+        _p(aux, "aux", F32) if aux is not None else None,
+        _p(pre, "pre", F32) if pre is not None else None, float(alpha), float(beta),
+        _stream(A.device)))
+    return out
+
+
+class LogMel:
+    """Log-mel features [B, 128 * 64] (mel-bin major) of 4 s renders."""
+
+    def __init__(self, sample_rate: float = 44100.0, device="cuda"):
+        self.device = torch.device(device)
+        self.dft = torch.empty(2050, 2048, dtype=BF16, device=self.device)
+        self.mel = torch.empty(128, 1032, dtype=BF16, device=self.device)
+        _native.check("synth_logmel_init", lib().synth_logmel_init(
+            float(sample_rate), self.dft.data_ptr(), self.mel.data_ptr(), _stream(self.device)))
+        self._ws = None
+
+    def __call__(self, audio: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        B, N = audio.shape
+        need = lib().synth_logmel_workspace(B)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        if out is None:
+            out = torch.empty(B, MEL_FEATURES, dtype=F32, device=self.device)
+        _native.check("synth_logmel", lib().synth_logmel(
+            _p(audio, "audio", F32, B * N), B, N, self.dft.data_ptr(), self.mel.data_ptr(),
+            self._ws.data_ptr(), self._ws.numel(), _p(out, "features", F32, B * MEL_FEATURES),
+            _stream(self.device)))
+        return out
+
+
+def colstats(x: torch.Tensor):
+    rows, cols = x.shape
+    s = torch.empty(cols, dtype=F32, device=x.device)
+    s2 = torch.empty(cols, dtype=F32, device=x.device)
+    _native.check("synth_colstats", lib().synth_colstats(
+        x.data_ptr(), int(x.dtype == BF16), rows, cols, cols, s.data_ptr(), s2.data_ptr(),
+        _stream(x.device)))
+    return s, s2
+
+
+def standardize(x: torch.Tensor, mean: torch.Tensor, inv_std: torch.Tensor, out=None):
+    rows, cols = x.shape
+    if out is None:
+        out = torch.empty(rows, cols, dtype=BF16, device=x.device)
+    _native.check("synth_standardize", lib().synth_standardize(
+        _p(x, "x", F32), _p(mean, "mean", F32), _p(inv_std, "inv_std", F32), rows, cols,
+        _p(out, "y", BF16), _stream(x.device)))
+    return out
+
+
+def to_bf16(x: torch.Tensor, out=None):
+    if out is None:
+        out = torch.empty(x.shape, dtype=BF16, device=x.device)
+    _native.check("synth_to_bf16", lib().synth_to_bf16(_p(x, "x", F32), _p(out, "y", BF16),
+                                                       x.numel(), _stream(x.device)))
+    return out
+
+
+class MLP:
+    """8192 -> 1024 -> 1024 -> 78 proposal network: float32 master weights
+    (transposed, K-major) with bf16 copies, Adam moments, activation buffers."""
+
+    def __init__(self, init: dict, device="cuda", lr=3e-4, betas=(0.9, 0.999), eps=1e-8):
+        self.device = torch.device(device)
+        self.d_in, self.d_h, self.d_out = init["w1t"].shape[1], init["w1t"].shape[0], init["w3t"].shape[0]
+        self.names = ("w1t", "b1", "w2t", "b2", "w3t", "b3")
+        self.w = {k: torch.as_tensor(np.asarray(init[k], np.float32)).to(self.device).contiguous()
+                  for k in self.names}
+        self.wb = {k: to_bf16(self.w[k]) for k in ("w1t", "w2t", "w3t")}
+        self.m = {k: torch.zeros_like(v) for k, v in self.w.items()}
+        self.v = {k: torch.zeros_like(v) for k, v in self.w.items()}
+        self.g = {k: torch.zeros_like(v) for k, v in self.w.items()}
+        self.lr, self.betas, self.eps = lr, betas, eps
+        self.step_count = 0
+        self._act_batch = 0
+
+    def _acts(self, B):
+        if B != self._act_batch:
+            d, h, o = self.d_in, self.d_h, self.d_out
+            mk = lambda shape, dt: torch.empty(shape, dtype=dt, device=self.device)
+            self.a = {"h1pre": mk((B, h), F32), "h1": mk((B, h), BF16), "h2pre": mk((B, h), F32),
+                      "h2": mk((B, h), BF16), "out": mk((B, o), F32), "dz3": mk((B, o), BF16),
+                      "dh2": mk((B, h), BF16), "dh1": mk((B, h), BF16),
+                      "loss_rows": mk((B,), torch.float64)}
+            self._act_batch = B
+        return self.a
+
+    def forward(self, x_bf16: torch.Tensor, keep=True) -> torch.Tensor:
+        B = x_bf16.shape[0]
+        a = self._acts(B)
+        w, wb = self.w, self.wb
+        _native.check("synth_mlp_forward", lib().synth_mlp_forward(
+            B, self.d_in, self.d_h, self.d_out, _p(x_bf16, "x", BF16, B * self.d_in),
+            wb["w1t"].data_ptr(), w["b1"].data_ptr(), wb["w2t"].data_ptr(), w["b2"].data_ptr(),
+            wb["w3t"].data_ptr(), w["b3"].data_ptr(), a["h1pre"].data_ptr(), a["h1"].data_ptr(),
+            a["h2pre"].data_ptr(), a["h2"].data_ptr(), a["out"].data_ptr(), _stream(self.device)))
+        return a["out"]
+
+    def backward(self, x_bf16: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
+        """Gradients of mean((out - target)^2) into self.g; returns the loss (0-d, float64)."""
+        B = x_bf16.shape[0]
+        a, wb, g = self.a, self.wb, self.g
+        _native.check("synth_mlp_backward", lib().synth_mlp_backward(
+            B, self.d_in, self.d_h, self.d_out, x_bf16.data_ptr(), wb["w2t"].data_ptr(),
+            wb["w3t"].data_ptr(), a["h1pre"].data_ptr(), a["h1"].data_ptr(), a["h2pre"].data_ptr(),
+            a["h2"].data_ptr(), a["out"].data_ptr(), _p(target, "target", F32, B * self.d_out),
+            g["w1t"].data_ptr(), g["b1"].data_ptr(), g["w2t"].data_ptr(), g["b2"].data_ptr(),
+            g["w3t"].data_ptr(), g["b3"].data_ptr(), a["dz3"].data_ptr(), a["dh2"].data_ptr(),
+            a["dh1"].data_ptr(), a["loss_rows"].data_ptr(), _stream(self.device)))
+        return a["loss_rows"].sum() / (B * self.d_out)
+
+    def adam_step(self):
+        self.step_count += 1
+        b1, b2 = self.betas
+        for k in self.names:
+            _native.check("synth_adam", lib().synth_adam(
+                self.w[k].numel(), self.w[k].data_ptr(),
+                self.wb[k].data_ptr() if k in self.wb else None, self.g[k].data_ptr(),
+                self.m[k].data_ptr(), self.v[k].data_ptr(), float(self.lr), float(b1), float(b2),
+                float(self.eps), self.step_count, _stream(self.device)))
+
+    def train_step(self, x_bf16, target):
+        self.forward(x_bf16)
+        loss = self.backward(x_bf16, target)
+        self.adam_step()
+        return loss
+
+    def state_dict(self):
+        return {"w": {k: v.detach().cpu().clone() for k, v in self.w.items()},
+                "m": {k: v.detach().cpu().clone() for k, v in self.m.items()},
+                "v": {k: v.detach().cpu().clone() for k, v in self.v.items()},
+                "step": self.step_count}
+
+    def load_state_dict(self, sd):
+        for k in self.names:
+            self.w[k].copy_(sd["w"][k])
+            self.m[k].copy_(sd["m"][k])
+            self.v[k].copy_(sd["v"][k])
+        for k in self.wb:
+            to_bf16(self.w[k], out=self.wb[k])
+        self.step_count = int(sd["step"])

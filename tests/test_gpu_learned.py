@@ -1,0 +1,153 @@
+"""GPU parity of the learned proposal's kernels (bf16 MFMA GEMM with fused
+epilogues, log-mel features, MLP forward/backward, Adam) against float64
+references that take the same bf16 quantisation decisions.
+
+Tolerances: the GPU accumulates in float32 (relative ~1e-6 for K <= 8192);
+bf16 stores of intermediates can round a value one bf16 ulp (2^-8) the other
+way when the float32 and float64 accumulations straddle a rounding tie, which
+moves downstream results by O(1e-5) relative.  GEMM/MLP results are held to
+2e-3 relative L2; log-mel to 5e-3 absolute (one bf16 ulp of a band's dominant
+power term) with a median below 1e-4.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import mlp as omlp, philox, spectral as sp, voice
+
+pytestmark = pytest.mark.gpu
+BF = torch.bfloat16
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2104_12922_amd import learned
+    return learned
+
+
+def rel(a, b):
+    a, b = torch.as_tensor(a, dtype=torch.float64), torch.as_tensor(b, dtype=torch.float64)
+    return float((a - b).norm() / max(b.norm(), 1e-300))
+
+
+@pytest.mark.parametrize("M,N,K", [(256, 256, 128), (200, 78, 100), (130, 300, 1000), (64, 1030, 2048)])
+@pytest.mark.parametrize("a_layout,b_layout", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_gemm_layouts(L, M, N, K, a_layout, b_layout):
+    g = torch.Generator().manual_seed(M * 7 + N + K)
+    A = torch.randn(M, K, generator=g).to(BF)
+    B = torch.randn(K, N, generator=g).to(BF)
+    Ad = (A if a_layout == 0 else A.T).contiguous().cuda()
+    Bd = (B.T if b_layout == 0 else B).contiguous().cuda()
+    C = L.gemm_bf16(Ad, Bd, M, N, K, a_layout, b_layout)
+    ref = A.double() @ B.double()
+    assert rel(C.cpu(), ref) < 1e-5
+
+
+@pytest.mark.parametrize("epi", [1, 2, 3])
+def test_gemm_epilogues(L, epi):
+    M, N, K = 300, 200, 256
+    g = torch.Generator().manual_seed(epi)
+    A = torch.randn(M, K, generator=g).to(BF)
+    Bt = (torch.randn(N, K, generator=g) / 16).to(BF)
+    bias = torch.randn(N, generator=g)
+    aux = torch.randn(M, N, generator=g)
+    pre = torch.empty(M, N, device="cuda")
+    C = L.gemm_bf16(A.cuda(), Bt.cuda(), M, N, K, bias=bias.cuda(), epilogue=epi,
+                    aux=aux.cuda() if epi == 3 else None, pre=pre)
+    x = A.double() @ Bt.double().T + bias.double()
+    ref = {1: omlp.gelu(x), 2: torch.sigmoid(x), 3: x * omlp.gelu_grad(aux.double())}[epi]
+    assert rel(C.cpu(), ref) < 1e-5
+    assert rel(pre.cpu(), x) < 1e-5
+    Cb = L.gemm_bf16(A.cuda(), Bt.cuda(), M, N, K, bias=bias.cuda(), epilogue=epi, out_bf16=True,
+                     aux=aux.cuda() if epi == 3 else None)
+    assert rel(Cb.cpu().double(), ref) < 5e-3
+
+
+def test_logmel_matches_bf16_reference(L):
+    u = philox.sample_params(0, np.arange(6))
+    x = voice.render_uniform(torch.tensor(u), np.arange(6), 176400, W.default_nebula().table()).float()
+    feat = L.LogMel()(x.cuda())
+    torch.cuda.synchronize()
+    ref = sp.logmel_bf16(x.double()).reshape(6, -1)
+    d = (feat.cpu().double() - ref).abs()
+    print("logmel max abs", float(d.max()), "median", float(d.median()), file=sys.stderr)
+    assert float(d.median()) < 1e-4
+    assert float(d.max()) < 5e-3
+
+
+def test_mlp_forward_backward_full_size(L):
+    """8192 -> 1024 -> 1024 -> 78 at batch 512 against the float64 reference."""
+    w = W.mlp_init(0)
+    rng = np.random.default_rng(1)
+    for k, n in (("b1", 1024), ("b2", 1024), ("b3", 78)):
+        w[k] = (rng.standard_normal(n) * 0.05).astype(np.float32)
+    B = 512
+    x = torch.tensor(rng.standard_normal((B, 8192)), dtype=torch.float32)
+    t = torch.tensor(rng.random((B, 78)), dtype=torch.float32)
+    net = L.MLP(w)
+    xb = x.to(BF).cuda()
+    out = net.forward(xb)
+    loss = net.backward(xb, t.cuda())
+    torch.cuda.synchronize()
+    f = omlp.forward(x.double(), w, round_bf16=True)
+    ref_loss, g = omlp.backward(f, t.double(), round_bf16=True)
+    assert rel(out.cpu(), f["out"]) < 2e-3
+    assert abs(float(loss) - float(ref_loss)) < 1e-6 * max(1.0, float(ref_loss)) + 1e-7
+    for k in ("w1t", "b1", "w2t", "b2", "w3t", "b3"):
+        e = rel(net.g[k].cpu(), g[k])
+        print(k, "rel L2", e, file=sys.stderr)
+        assert e < 2e-3, (k, e)
+
+
+def test_adam_step(L):
+    w = W.mlp_init(2, 64, 32, 78)
+    net = L.MLP(w, lr=1e-2)
+    grads = {k: torch.randn_like(v) for k, v in net.w.items()}
+    for k in grads:
+        net.g[k].copy_(grads[k])
+    before = {k: v.cpu().clone() for k, v in net.w.items()}
+    net.adam_step()
+    net.adam_step()
+    for k in grads:
+        gk = grads[k].cpu().double()
+        w, m, v = before[k].double(), torch.zeros_like(gk), torch.zeros_like(gk)
+        for t in (1, 2):     # bias-corrected Adam, written out in float64
+            m = 0.9 * m + 0.1 * gk
+            v = 0.999 * v + 0.001 * gk * gk
+            w = w - 1e-2 * (m / (1 - 0.9 ** t)) / (torch.sqrt(v / (1 - 0.999 ** t)) + 1e-8)
+        assert torch.allclose(net.w[k].cpu().double(), w, atol=1e-6), k
+    assert torch.equal(net.wb["w1t"].cpu(), net.w["w1t"].cpu().to(BF))
+
+
+def test_short_training_reduces_loss(L):
+    """A few hundred Adam steps on renders drawn from the synth itself reduce
+    the held-out parameter MSE well below the MSE of predicting 0.5."""
+    import paper_2104_12922_amd as S
+    tab = W.default_nebula().table()
+    lm = L.LogMel()
+    net = L.MLP(W.mlp_init(0), lr=3e-4)
+    B = 256
+
+    def batch(seed, first):
+        u = S.synth_sample_params(seed, first, B)
+        y = S.synth_render(u, tab, n_samples=176400, first_g=first, noise_seed=seed)
+        return lm(y), u
+
+    f0, _ = batch(W.SEED_TRAIN, 0)
+    s, s2 = L.colstats(f0)
+    mean = s / B
+    inv_std = 1.0 / torch.sqrt(torch.clamp(s2 / B - mean * mean, min=1e-6))
+    fh, uh = batch(W.SEED_HELDOUT, 0)
+    xh = L.standardize(fh, mean, inv_std)
+    base = float(((uh - 0.5) ** 2).mean())
+    for step in range(300):
+        f, u = batch(W.SEED_TRAIN, (step + 1) * B)
+        net.train_step(L.standardize(f, mean, inv_std), u)
+    held = float(((net.forward(xh) - uh) ** 2).mean())
+    print("held-out MSE", held, "predict-0.5 MSE", base, file=sys.stderr)
+    assert held < 0.9 * base

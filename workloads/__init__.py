@@ -165,3 +165,18 @@ def gradient_batch(batch: int = 256) -> Workload:
     return Workload("grad_b%d_4s" % batch, batch, SEED_PARAM, 0,
                     np.full(batch, int(4 * SAMPLE_RATE), dtype=np.int64), default_nebula())
 
+
+
+def mlp_init(seed: int = 0, d_in: int = 8192, d_h: int = 1024, d_out: int = 78) -> dict:
+    """Initial weights of the proposal MLP (inputs, drawn from a seeded numpy
+    generator): He-normal hidden layers, a 1/sqrt(fan_in) output layer, zero
+    biases.  Weights are stored transposed (K-major): w1t [d_h][d_in], etc."""
+    rng = np.random.default_rng(seed)
+    return {
+        "w1t": (rng.standard_normal((d_h, d_in)) * math.sqrt(2.0 / d_in)).astype(np.float32),
+        "b1": np.zeros(d_h, np.float32),
+        "w2t": (rng.standard_normal((d_h, d_h)) * math.sqrt(2.0 / d_h)).astype(np.float32),
+        "b2": np.zeros(d_h, np.float32),
+        "w3t": (rng.standard_normal((d_out, d_h)) * math.sqrt(1.0 / d_h)).astype(np.float32),
+        "b3": np.zeros(d_out, np.float32),
+    }
