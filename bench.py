@@ -37,7 +37,22 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graph", type=int, default=1, help="capture the step in a HIP graph")
     ap.add_argument("--rps", type=int, default=0, help="runs per segment (0 = library default)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many bytes (the "
+                         "reference point that scales HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_only(nbytes):
+    """A plain copy kernel of known size: reads and writes nbytes once each."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
 
 
 def cpu_baseline(wl, min_seconds):
@@ -71,6 +86,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_bytes:
+        copy_only(args.copy_bytes)
+        return
     import torch
     import workloads as W
     import paper_2104_12922_amd as S

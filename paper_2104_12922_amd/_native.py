@@ -42,6 +42,7 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(LIB_PATH)
         L.synth_num_params.restype = ctypes.c_int
         L.synth_status_string.restype = ctypes.c_char_p
+        L.synth_num_params.argtypes = []
         L.synth_status_string.argtypes = [ctypes.c_int]
         L.synth_is_test.restype = ctypes.c_int
         L.synth_is_test.argtypes = [ctypes.c_uint64]

@@ -32,8 +32,8 @@ def _sig(L):
     L.synth_colstats.argtypes = [vp, i32, i64, i64, i64, vp, vp, vp]
     L.synth_standardize.argtypes = [vp, vp, vp, i64, i64, vp, vp]
     L.synth_to_bf16.argtypes = [vp, vp, i64, vp]
-    L.synth_mlp_forward.argtypes = [i64, i64, i64, i64] + [vp] * 12
-    L.synth_mlp_backward.argtypes = [i64, i64, i64, i64] + [vp] * 19
+    L.synth_mlp_forward.argtypes = [i64, i64, i64, i64] + [vp] * 13
+    L.synth_mlp_backward.argtypes = [i64, i64, i64, i64] + [vp] * 20
     L.synth_adam.argtypes = [i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]
     for n in ("synth_gemm_bf16", "synth_logmel_init", "synth_logmel", "synth_colstats",
               "synth_standardize", "synth_to_bf16", "synth_mlp_forward", "synth_mlp_backward",

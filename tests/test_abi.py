@@ -104,3 +104,31 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_native, "_lib", None)
     with pytest.raises(ImportError):
         _native.lib()
+
+
+def header_arities():
+    """{name: number of parameters} of every function the headers declare."""
+    out = {}
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        txt = re.sub(r"//[^\n]*", "", txt)
+        for name, params in re.findall(r"\b(synth_[a-z0-9_]+)\s*\(([^()]*)\)\s*;", txt):
+            params = params.strip()
+            out[name] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_ctypes_signatures_match_header_arity():
+    """Every binding declares exactly the header's parameters: an argument past
+    the declared list would be passed as a C int (a truncated stream pointer)."""
+    from paper_2104_12922_amd import learned
+    L = learned.lib()
+    ar = header_arities()
+    assert len(ar) == len(header_functions())
+    for name, n in ar.items():
+        at = getattr(L, name).argtypes
+        assert at is not None, f"{name} has no argtypes"
+        assert len(at) == n, f"{name}: header has {n} parameters, binding {len(at)}"
