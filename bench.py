@@ -84,7 +84,7 @@ def cpu_baseline(wl, min_seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the renderer is benchmarked on one GPU only (voices shard with no communication); --gpus must be 1"}))
         sys.exit(2)
     if args.copy_bytes:
         copy_only(args.copy_bytes)

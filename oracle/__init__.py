@@ -23,7 +23,7 @@ Parity status
 -------------
 Every definition the paper leaves to torchsynth's code and documentation (the
 exact ADSR, LFO, square-saw and mixer formulas, the RNG streams) is a reading
-of this build; sample parity with the published synth1B1 corpus is therefore
+of the paper's prose; sample parity with the published synth1B1 corpus is therefore
 "parity unpinned" and not claimed.  Each stage is pinned by closed forms and
 invariants in ``tests/test_oracle_*.py``.
 """

@@ -6,8 +6,8 @@ The paper scores sounds with a multi-scale spectrogram distance, linear plus
 log magnitudes over several FFT sizes, and prefers L1 distances (Section 4.3,
 Table "distance-eval").  The loss used here for gradient-based sound matching
 is its log-magnitude L1 form at three resolutions; the learned proposal reads
-log-mel features.  Readings (no centring or padding, periodic Hann window,
-HTK mel scale) are listed in the design doc.
+log-mel features.  Where the paper leaves details open, the readings taken
+here are: no centring or padding, a periodic Hann window, the HTK mel scale.
 
   frames(x, n, hop)   F = floor((N - n) / hop) + 1 frames, frame t starts at t*hop
   stft(x, n, hop)     X[t, k] = sum_m w(m) x(t*hop + m) exp(-2 pi i k m / n),

@@ -12,8 +12,7 @@ the audio modules use them (Section 3.2).  Parameters are stored normalised in
 symmetry hyperparameters (Section 3.3).
 
 The paper gives the module list and routing in prose only; the formulas below
-are this build's readings (listed in DESIGN.md, "Readings"), each cited at
-its function.  Parameter order p = 0..77:
+are readings of that prose, each stated and cited at its function.  Parameter order p = 0..77:
 
   0 midi_f0, 1 note duration (s)
   2 + 5k   ADSR k in (adsr_1, adsr_2, lfo_1 rate, lfo_1 amp, lfo_2 rate, lfo_2 amp):
