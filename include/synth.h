@@ -176,14 +176,18 @@ int synth_gemm_bf16(int a_layout, int b_layout, int64_t M, int64_t N, int64_t K,
  * triangles from 0 to sample_rate / 2 (no area normalisation), log(x + 1e-6).
  * synth_logmel_init fills the tables once: dft_basis bf16 [2050][2048]
  * (rows cos, -sin per bin), mel_basis bf16 [128][1032]; it synchronises the
- * stream.  synth_logmel: audio float32 [batch][n_samples] with
- * n_samples >= 175676; workspace >= synth_logmel_workspace(batch) bytes;
- * features float32 [batch][128][64] (mel bin major, frame minor). */
+ * stream.  synth_logmel: audio float32, voice b = audio[b * n_samples ..] of
+ * n_samples samples (offsets == NULL, n_samples > 0) or the ragged range
+ * audio[offsets[b] .. offsets[b+1]) (offsets dev int64 [batch + 1]); samples
+ * past a voice's end count as 0 (a render shorter than the 175676 samples
+ * the frames span is featurised as if zero-padded); workspace >=
+ * synth_logmel_workspace(batch) bytes; features float32 [batch][128][64]
+ * (mel bin major, frame minor). */
 size_t synth_logmel_workspace(int64_t batch);
 int synth_logmel_init(double sample_rate, void* dft_basis, void* mel_basis, void* stream);
-int synth_logmel(const float* audio, int64_t batch, int64_t n_samples, const void* dft_basis,
-                 const void* mel_basis, void* workspace, size_t workspace_bytes, float* features,
-                 void* stream);
+int synth_logmel(const float* audio, const int64_t* offsets, int64_t batch, int64_t n_samples,
+                 const void* dft_basis, const void* mel_basis, void* workspace,
+                 size_t workspace_bytes, float* features, void* stream);
 
 /* Column sums (and sums of squares if sumsq != NULL) of a rows x cols matrix
  * (row stride ld; bf16 if x_bf16 else float32), float32 outputs [cols]. */
@@ -217,6 +221,33 @@ int synth_mlp_backward(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out, 
  * w_bf16 != NULL it receives the updated weights rounded to bf16. */
 int synth_adam(int64_t n, float* w, void* w_bf16, const float* grad, float* m, float* v, float lr,
                float beta1, float beta2, float eps, int step, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Sound matching (inverse synthesis by gradient descent through the render,
+ * Sections 2 and 2.3: estimating the parameters of a given sound).  The
+ * parameters are optimised as logits z with u = sigmoid(z), so every step
+ * stays inside [0, 1].
+ * ------------------------------------------------------------------------- */
+
+/* z = log(u' / (1 - u')) with u' = clamp(u, eps, 1 - eps), and
+ * u_out = sigmoid(z) (u_out may alias u).  0 < eps < 1/2; n floats. */
+int synth_logit_init(const float* u, float* z, float* u_out, int64_t n, float eps, void* stream);
+
+/* One Adam step (bias-corrected, step >= 1) on logits z given dL/du at the
+ * current u = sigmoid(z): dL/dz = dL/du * u (1 - u); then u <- sigmoid(z).
+ * z, u, m, v updated in place; grad_u read; n floats each. */
+int synth_logit_adam(int64_t n, float* z, float* u, const float* grad_u, float* m, float* v,
+                     float lr, float beta1, float beta2, float eps, int step, void* stream);
+
+/* Best-so-far tracking.  For each row r < rows, over columns c < cols, the
+ * loss of element e = r * row_stride + c * col_stride is loss[e]; the
+ * smallest (first on ties) replaces best[r] if strictly smaller, and then
+ * best_idx[r] = col_base + c (if best_idx != NULL) and best_params[r][.] =
+ * params[e][.] (param_dim floats; both NULL or both given).  loss float64,
+ * best float64 [rows] (initialise to +inf), best_idx int64 [rows]. */
+int synth_best_update(const double* loss, int64_t rows, int64_t cols, int64_t row_stride,
+                      int64_t col_stride, int64_t col_base, const float* params, int64_t param_dim,
+                      double* best, int64_t* best_idx, float* best_params, void* stream);
 
 #ifdef __cplusplus
 }

@@ -282,17 +282,18 @@ int synth_logmel_init(double sample_rate, void* dft_basis, void* mel_basis, void
   return to_status(hipStreamSynchronize((hipStream_t)stream));
 }
 
-int synth_logmel(const float* audio, int64_t batch, int64_t n_samples, const void* dft_basis,
-                 const void* mel_basis, void* workspace, size_t workspace_bytes, float* features,
-                 void* stream) {
+int synth_logmel(const float* audio, const int64_t* offsets, int64_t batch, int64_t n_samples,
+                 const void* dft_basis, const void* mel_basis, void* workspace,
+                 size_t workspace_bytes, float* features, void* stream) {
   if (batch < 0) return SYNTH_EINVAL;
   if (batch == 0) return SYNTH_OK;
   if (!audio || !dft_basis || !mel_basis || !workspace || !features) return SYNTH_EINVAL;
-  if (n_samples < (int64_t)(kMelFrames - 1) * kMelHop + kMelNfft) return SYNTH_EINVAL;
+  if (!offsets && n_samples <= 0) return SYNTH_EINVAL;
   if (workspace_bytes < synth_logmel_workspace(batch)) return SYNTH_ENOMEM;
   synth::GemmArgs g = {};
   g.M = batch * kMelFrames; g.N = kMelNfft + 2; g.K = kMelNfft;
-  g.A = audio; g.lda = n_samples; g.frame_hop = kMelHop; g.frame_count = kMelFrames;
+  g.A = audio; g.lda = offsets ? 0 : n_samples; g.frame_hop = kMelHop; g.frame_count = kMelFrames;
+  g.frame_offsets = offsets;
   g.B = dft_basis; g.ldb = kMelNfft;
   g.C = workspace; g.ldc = kMelLd; g.c_bf16 = 1; g.epilogue = synth::kEpiPowerPairs;
   g.alpha = 1.0f;
@@ -389,6 +390,33 @@ int synth_mlp_backward(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out, 
   g.C = gw1t; g.ldc = d_in;
   if ((e = synth::launch_gemm_bf16(g, kOpRowMajorMN, kOpRowMajorMN, s)) != hipSuccess) return SYNTH_EDEVICE;
   return to_status(synth::launch_colsum(dh1, 1, batch, d_h, d_h, gb1, nullptr, s));
+}
+
+int synth_logit_init(const float* u, float* z, float* u_out, int64_t n, float eps, void* stream) {
+  if (n < 0 || !(eps > 0.0f && eps < 0.5f)) return SYNTH_EINVAL;
+  if (n > 0 && (!u || !z || !u_out)) return SYNTH_EINVAL;
+  return to_status(synth::launch_logit_init(u, z, u_out, n, eps, (hipStream_t)stream));
+}
+
+int synth_logit_adam(int64_t n, float* z, float* u, const float* grad_u, float* m, float* v,
+                     float lr, float beta1, float beta2, float eps, int step, void* stream) {
+  if (n < 0 || step < 1) return SYNTH_EINVAL;
+  if (n > 0 && (!z || !u || !grad_u || !m || !v)) return SYNTH_EINVAL;
+  return to_status(synth::launch_logit_adam(n, z, u, grad_u, m, v, lr, beta1, beta2, eps, step,
+                                            (hipStream_t)stream));
+}
+
+int synth_best_update(const double* loss, int64_t rows, int64_t cols, int64_t row_stride,
+                      int64_t col_stride, int64_t col_base, const float* params, int64_t param_dim,
+                      double* best, int64_t* best_idx, float* best_params, void* stream) {
+  if (rows < 0 || cols < 0 || row_stride < 0 || col_stride < 0 || param_dim < 0) return SYNTH_EINVAL;
+  if (rows == 0) return SYNTH_OK;
+  if (!loss || !best || (cols > 0 && rows > 1 && row_stride == 0)) return SYNTH_EINVAL;
+  if ((params != nullptr) != (best_params != nullptr)) return SYNTH_EINVAL;
+  if (params && param_dim == 0) return SYNTH_EINVAL;
+  return to_status(synth::launch_best_update(loss, rows, cols, row_stride, col_stride, col_base,
+                                             params, param_dim, best, best_idx, best_params,
+                                             (hipStream_t)stream));
 }
 
 int synth_adam(int64_t n, float* w, void* w_bf16, const float* grad, float* m, float* v, float lr,

@@ -103,6 +103,62 @@ __global__ void dft_basis_kernel(uint16_t* __restrict__ basis, int n) {
   }
 }
 
+// Sound matching in logit space (u = sigmoid(z)).
+__global__ void logit_init_kernel(const float* __restrict__ u, float* __restrict__ z,
+                                  float* __restrict__ u_out, int64_t n, float eps) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float uc = fminf(fmaxf(u[i], eps), 1.0f - eps);
+    const float zi = logf(uc) - log1pf(-uc);
+    z[i] = zi;
+    u_out[i] = 1.0f / (1.0f + expf(-zi));
+  }
+}
+
+// dL/dz = dL/du * u (1 - u) at the current u; Adam on z; u <- sigmoid(z).
+__global__ void logit_adam_kernel(int64_t n, float* __restrict__ z, float* __restrict__ u,
+                                  const float* __restrict__ gu, float* __restrict__ m,
+                                  float* __restrict__ v, float lr, float b1, float b2, float eps,
+                                  float c1, float c2) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float ui = u[i];
+    const float gi = gu[i] * ui * (1.0f - ui);
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float zi = z[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    z[i] = zi;
+    u[i] = 1.0f / (1.0f + expf(-zi));
+  }
+}
+
+// Per row r: the smallest loss over columns c (element r * rs + c * cs; the
+// first one on ties); if it beats best[r], record it, its column index
+// (col_base + c) and, if params is given, that element's param_dim floats.
+__global__ void best_update_kernel(const double* __restrict__ loss, int64_t rows, int64_t cols,
+                                   int64_t rs, int64_t cs, int64_t col_base,
+                                   const float* __restrict__ params, int64_t param_dim,
+                                   double* __restrict__ best, int64_t* __restrict__ best_idx,
+                                   float* __restrict__ best_params) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  double lm = 0.0;
+  int64_t cm = -1;
+  for (int64_t c = 0; c < cols; ++c) {
+    const double l = loss[r * rs + c * cs];
+    if (cm < 0 || l < lm) { lm = l; cm = c; }
+  }
+  if (cm < 0 || !(lm < best[r])) return;
+  best[r] = lm;
+  if (best_idx) best_idx[r] = col_base + cm;
+  if (params && best_params) {
+    const float* src = params + (r * rs + cm * cs) * param_dim;
+    for (int64_t p = 0; p < param_dim; ++p) best_params[r * param_dim + p] = src[p];
+  }
+}
+
 dim3 grid_for(int64_t n, int threads) {
   int64_t b = (n + threads - 1) / threads;
   if (b > 65535 * 4) b = 65535 * 4;
@@ -156,6 +212,34 @@ hipError_t launch_dft_basis(void* basis_bf16, int n_fft, hipStream_t s) {
   const int64_t total = (int64_t)(n_fft + 2) * n_fft;
   hipLaunchKernelGGL(dft_basis_kernel, grid_for(total, 256), dim3(256), 0, s,
                      (uint16_t*)basis_bf16, n_fft);
+  return hipGetLastError();
+}
+
+hipError_t launch_logit_init(const float* u, float* z, float* u_out, int64_t n, float eps,
+                             hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(logit_init_kernel, grid_for(n, 256), dim3(256), 0, s, u, z, u_out, n, eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_logit_adam(int64_t n, float* z, float* u, const float* grad_u, float* m,
+                             float* v, float lr, float b1, float b2, float eps, int step,
+                             hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  hipLaunchKernelGGL(logit_adam_kernel, grid_for(n, 256), dim3(256), 0, s, n, z, u, grad_u, m, v,
+                     lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_best_update(const double* loss, int64_t rows, int64_t cols, int64_t row_stride,
+                              int64_t col_stride, int64_t col_base, const float* params,
+                              int64_t param_dim, double* best, int64_t* best_idx,
+                              float* best_params, hipStream_t s) {
+  if (rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(best_update_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s,
+                     loss, rows, cols, row_stride, col_stride, col_base, params, param_dim, best,
+                     best_idx, best_params);
   return hipGetLastError();
 }
 

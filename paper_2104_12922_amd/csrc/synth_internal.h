@@ -67,6 +67,7 @@ struct GemmArgs {
   float alpha, beta;   // beta != 0: C = epi(...) + beta * C
   int frame_hop;       // kOpFrames: hop between frames; frames per voice in frame_count
   int frame_count;
+  const int64_t* frame_offsets;  // kOpFrames: voice v = audio[off[v], off[v+1]) (null: v * lda, lda long)
 };
 
 hipError_t launch_gemm_bf16(const GemmArgs& g, int a_op, int b_op, hipStream_t s);
@@ -83,6 +84,15 @@ hipError_t launch_mse_sigmoid_grad(const float* out, const float* target, int64_
 hipError_t launch_adam(int64_t n, float* w, void* w_bf16, const float* g, float* m, float* v,
                        float lr, float b1, float b2, float eps, int step, hipStream_t s);
 hipError_t launch_dft_basis(void* basis_bf16, int n_fft, hipStream_t s);
+hipError_t launch_logit_init(const float* u, float* z, float* u_out, int64_t n, float eps,
+                             hipStream_t s);
+hipError_t launch_logit_adam(int64_t n, float* z, float* u, const float* grad_u, float* m,
+                             float* v, float lr, float b1, float b2, float eps, int step,
+                             hipStream_t s);
+hipError_t launch_best_update(const double* loss, int64_t rows, int64_t cols, int64_t row_stride,
+                              int64_t col_stride, int64_t col_base, const float* params,
+                              int64_t param_dim, double* best, int64_t* best_idx,
+                              float* best_params, hipStream_t s);
 
 hipError_t launch_sample_params(uint64_t seed, uint64_t first_g, int64_t batch,
                                 const uint64_t* voice_ids, float* params, hipStream_t s);

@@ -28,16 +28,19 @@ def _sig(L):
     L.synth_logmel_workspace.restype = sz
     L.synth_logmel_workspace.argtypes = [i64]
     L.synth_logmel_init.argtypes = [ctypes.c_double, vp, vp, vp]
-    L.synth_logmel.argtypes = [vp, i64, i64, vp, vp, vp, sz, vp, vp]
+    L.synth_logmel.argtypes = [vp, vp, i64, i64, vp, vp, vp, sz, vp, vp]
     L.synth_colstats.argtypes = [vp, i32, i64, i64, i64, vp, vp, vp]
     L.synth_standardize.argtypes = [vp, vp, vp, i64, i64, vp, vp]
     L.synth_to_bf16.argtypes = [vp, vp, i64, vp]
     L.synth_mlp_forward.argtypes = [i64, i64, i64, i64] + [vp] * 13
     L.synth_mlp_backward.argtypes = [i64, i64, i64, i64] + [vp] * 20
     L.synth_adam.argtypes = [i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]
+    L.synth_logit_init.argtypes = [vp, vp, vp, i64, f32, vp]
+    L.synth_logit_adam.argtypes = [i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]
+    L.synth_best_update.argtypes = [vp, i64, i64, i64, i64, i64, vp, i64, vp, vp, vp, vp]
     for n in ("synth_gemm_bf16", "synth_logmel_init", "synth_logmel", "synth_colstats",
               "synth_standardize", "synth_to_bf16", "synth_mlp_forward", "synth_mlp_backward",
-              "synth_adam"):
+              "synth_adam", "synth_logit_init", "synth_logit_adam", "synth_best_update"):
         getattr(L, n).restype = ctypes.c_int
     return L
 
@@ -85,17 +88,25 @@ class LogMel:
             float(sample_rate), self.dft.data_ptr(), self.mel.data_ptr(), _stream(self.device)))
         self._ws = None
 
-    def __call__(self, audio: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        B, N = audio.shape
+    def __call__(self, audio: torch.Tensor, out: torch.Tensor | None = None,
+                 offsets: torch.Tensor | None = None) -> torch.Tensor:
+        """audio [B, N] (uniform) or, with offsets int64 [B + 1], a packed 1-D
+        buffer of ragged voices; samples past a voice's end count as 0."""
+        if offsets is None:
+            B, N = audio.shape
+            offp = None
+        else:
+            B, N = offsets.numel() - 1, 0
+            offp = _p(offsets, "offsets", torch.int64, B + 1)
         need = lib().synth_logmel_workspace(B)
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         if out is None:
             out = torch.empty(B, MEL_FEATURES, dtype=F32, device=self.device)
         _native.check("synth_logmel", lib().synth_logmel(
-            _p(audio, "audio", F32, B * N), B, N, self.dft.data_ptr(), self.mel.data_ptr(),
-            self._ws.data_ptr(), self._ws.numel(), _p(out, "features", F32, B * MEL_FEATURES),
-            _stream(self.device)))
+            _p(audio, "audio", F32, audio.numel()), offp, B, N, self.dft.data_ptr(),
+            self.mel.data_ptr(), self._ws.data_ptr(), self._ws.numel(),
+            _p(out, "features", F32, B * MEL_FEATURES), _stream(self.device)))
         return out
 
 
@@ -210,3 +221,35 @@ class MLP:
         for k in self.wb:
             to_bf16(self.w[k], out=self.wb[k])
         self.step_count = int(sd["step"])
+
+
+def logit_init(u: torch.Tensor, eps: float = 1e-4):
+    """(z, u') with z = logit(clamp(u, eps, 1 - eps)) and u' = sigmoid(z)."""
+    z = torch.empty_like(u)
+    u2 = torch.empty_like(u)
+    _native.check("synth_logit_init", lib().synth_logit_init(
+        _p(u, "u", F32), _p(z, "z", F32), _p(u2, "u_out", F32), u.numel(), float(eps),
+        _stream(u.device)))
+    return z, u2
+
+
+def logit_adam(z, u, grad_u, m, v, step, lr=0.05, betas=(0.9, 0.999), eps=1e-8):
+    """In place: Adam on z with dL/dz = grad_u u (1 - u); u <- sigmoid(z)."""
+    n = z.numel()
+    _native.check("synth_logit_adam", lib().synth_logit_adam(
+        n, _p(z, "z", F32, n), _p(u, "u", F32, n), _p(grad_u, "grad_u", F32, n),
+        _p(m, "m", F32, n), _p(v, "v", F32, n), float(lr), float(betas[0]), float(betas[1]),
+        float(eps), int(step), _stream(z.device)))
+
+
+def best_update(loss, rows, cols, row_stride, col_stride, best, best_idx=None, col_base=0,
+                params=None, best_params=None):
+    """Per-row running minimum of loss (see synth_best_update in synth.h)."""
+    pd = 0 if params is None else best_params.shape[-1]
+    _native.check("synth_best_update", lib().synth_best_update(
+        _p(loss, "loss", torch.float64), rows, cols, row_stride, col_stride, col_base,
+        _p(params, "params", F32) if params is not None else None, pd,
+        _p(best, "best", torch.float64, rows),
+        _p(best_idx, "best_idx", torch.int64, rows) if best_idx is not None else None,
+        _p(best_params, "best_params", F32, rows * pd) if best_params is not None else None,
+        _stream(loss.device)))

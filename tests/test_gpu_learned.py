@@ -151,3 +151,77 @@ def test_short_training_reduces_loss(L):
     held = float(((net.forward(xh) - uh) ** 2).mean())
     print("held-out MSE", held, "predict-0.5 MSE", base, file=sys.stderr)
     assert held < 0.9 * base
+
+
+def test_logmel_ragged_and_short_voices_read_as_zero_padded(L):
+    """Ragged voices (1..4 s, packed) give the features of the same renders
+    zero-padded to 4 s, bit for bit, and match the bf16 reference."""
+    n4 = 176400
+    u = philox.sample_params(3, np.arange(4))
+    full = voice.render_uniform(torch.tensor(u), np.arange(4), n4, W.default_nebula().table()).float()
+    lens = [44100, 88200, 132300, 176400]
+    padded = full.clone()
+    for b, n in enumerate(lens):
+        padded[b, n:] = 0
+    packed = torch.cat([full[b, :n] for b, n in enumerate(lens)])
+    offs = torch.tensor(np.concatenate([[0], np.cumsum(lens)]), dtype=torch.int64)
+    lm = L.LogMel()
+    fr = lm(packed.cuda(), offsets=offs.cuda())
+    fp = lm(padded.cuda())
+    fs = lm(full[:, :50000].contiguous().cuda())          # uniform but shorter than the frames span
+    torch.cuda.synchronize()
+    assert torch.equal(fr.cpu(), fp.cpu())
+    ref = sp.logmel_bf16(padded.double()).reshape(4, -1)
+    d = (fr.cpu().double() - ref).abs()
+    assert float(d.median()) < 1e-4 and float(d.max()) < 5e-3
+    short = torch.zeros(4, n4)
+    short[:, :50000] = full[:, :50000]
+    assert torch.equal(fs.cpu(), lm(short.cuda()).cpu())
+
+
+def test_logit_init_and_adam(L):
+    g = torch.Generator().manual_seed(5)
+    u = torch.rand(1000, generator=g)
+    u[:3] = torch.tensor([0.0, 1.0, 0.5])
+    z, u2 = L.logit_init(u.cuda(), eps=1e-4)
+    uc = u.double().clamp(1e-4, 1 - 1e-4)
+    zr = torch.log(uc / (1 - uc))
+    assert torch.allclose(z.cpu().double(), zr, rtol=1e-5, atol=1e-5)
+    assert torch.allclose(u2.cpu().double(), torch.sigmoid(zr), atol=1e-6)
+    gu = torch.randn(1000, generator=g)
+    m, v = torch.zeros(1000, device="cuda"), torch.zeros(1000, device="cuda")
+    zz, uu = z.clone(), u2.clone()
+    zd, ud = z.cpu().double(), u2.cpu().double()
+    md, vd = torch.zeros(1000, dtype=torch.float64), torch.zeros(1000, dtype=torch.float64)
+    for step in (1, 2, 3):
+        L.logit_adam(zz, uu, gu.cuda(), m, v, step, lr=0.05)
+        gz = gu.double() * ud * (1 - ud)
+        md = 0.9 * md + 0.1 * gz
+        vd = 0.999 * vd + 0.001 * gz * gz
+        zd = zd - 0.05 * (md / (1 - 0.9 ** step)) / (torch.sqrt(vd / (1 - 0.999 ** step)) + 1e-8)
+        ud = torch.sigmoid(zd)
+    assert torch.allclose(zz.cpu().double(), zd, atol=1e-4)
+    assert torch.allclose(uu.cpu().double(), ud, atol=1e-5)
+
+
+def test_best_update(L):
+    g = torch.Generator().manual_seed(6)
+    T, C, P = 37, 5, 78
+    loss = torch.rand(C, T, generator=g, dtype=torch.float64)      # element (t, c) at c * T + t
+    loss[2, 4] = loss[3, 4] = -1.0                                  # tie: first column wins
+    params = torch.rand(C, T, P, generator=g)
+    best = torch.full((T,), float("inf"), dtype=torch.float64)
+    best[0] = -5.0                                                   # already better: untouched
+    idx = torch.full((T,), -1, dtype=torch.int64)
+    bp = torch.zeros(T, P)
+    bd, idd, bpd = best.cuda(), idx.cuda(), bp.cuda()
+    L.best_update(loss.cuda(), T, C, 1, T, bd, idd, col_base=100, params=params.cuda(), best_params=bpd)
+    torch.cuda.synchronize()
+    mn, am = loss.min(dim=0)
+    for t in range(T):
+        if t == 0:
+            assert float(bd[0]) == -5.0 and int(idd[0]) == -1
+            continue
+        assert float(bd[t]) == float(mn[t]) and int(idd[t]) == 100 + int(am[t])
+        assert torch.equal(bpd[t].cpu(), params[int(am[t]), t])
+    assert int(idd[4]) == 102
