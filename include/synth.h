@@ -193,6 +193,11 @@ int synth_logmel(const float* audio, const int64_t* offsets, int64_t batch, int6
  * (row stride ld; bf16 if x_bf16 else float32), float32 outputs [cols]. */
 int synth_colstats(const void* x, int x_bf16, int64_t rows, int64_t cols, int64_t ld, float* sum,
                    float* sumsq, void* stream);
+/* Feature standardisation statistics of a rows x cols float32 matrix (rows
+ * > 0): mean[c] and inv_std[c] = 1 / sqrt(max(var_c, min_var)) with the
+ * population variance, both float32 [cols], accumulated in float64. */
+int synth_feature_stats(const float* x, int64_t rows, int64_t cols, float min_var, float* mean,
+                        float* inv_std, void* stream);
 /* y (bf16) = (x - mean[col]) * inv_std[col] for a rows x cols float32 matrix. */
 int synth_standardize(const float* x, const float* mean, const float* inv_std, int64_t rows,
                       int64_t cols, void* y_bf16, void* stream);

@@ -135,8 +135,8 @@ def synth_mrstft_loss(x: torch.Tensor, target: torch.Tensor, grad: bool = False)
 def synth_render_backward(params: torch.Tensor, grad_audio: torch.Tensor, nebula,
                           voice_ids: torch.Tensor | None = None, first_g: int = 0,
                           noise_seed: int = 0, sample_rate: float = 44100.0,
-                          control_rate: float = 441.0, workspace: torch.Tensor | None = None
-                          ) -> torch.Tensor:
+                          control_rate: float = 441.0, workspace: torch.Tensor | None = None,
+                          out: torch.Tensor | None = None) -> torch.Tensor:
     """d(sum grad_audio * render(params)) / d params, float32 [B, 78] (see synth.h)."""
     import ctypes
     B, N = grad_audio.shape
@@ -145,7 +145,8 @@ def synth_render_backward(params: torch.Tensor, grad_audio: torch.Tensor, nebula
     need = L.synth_render_backward_workspace(ctypes.byref(cfg), B, N)
     if workspace is None or workspace.numel() * workspace.element_size() < need:
         workspace = torch.empty(max(need, 8), dtype=torch.uint8, device=params.device)
-    gp = torch.empty(B, NUM_PARAMS, dtype=torch.float32, device=params.device)
+    gp = out if out is not None else torch.empty(B, NUM_PARAMS, dtype=torch.float32,
+                                                 device=params.device)
     _native.check("synth_render_backward", L.synth_render_backward(
         ctypes.byref(cfg), _dev_ptr(params, "params", torch.float32, B * NUM_PARAMS),
         _dev_ptr(voice_ids, "voice_ids", torch.uint64, B) if voice_ids is not None else None,
@@ -154,6 +155,19 @@ def synth_render_backward(params: torch.Tensor, grad_audio: torch.Tensor, nebula
         workspace.numel() * workspace.element_size(), _stream(params.device)))
     del keep
     return gp
+
+
+def synth_render_backward_workspace(nebula, batch: int, n_samples: int,
+                                    sample_rate: float = 44100.0,
+                                    control_rate: float = 441.0) -> torch.Tensor:
+    """A device workspace large enough for synth_render_backward."""
+    import ctypes
+    cfg, keep = _native.make_config(nebula, sample_rate, control_rate, 0, 0)
+    need = _native.lib().synth_render_backward_workspace(ctypes.byref(cfg), batch, n_samples)
+    del keep
+    if need == 0:
+        raise ValueError("invalid configuration for synth_render_backward")
+    return torch.empty(need, dtype=torch.uint8, device="cuda")
 
 
 class SynthRender(torch.autograd.Function):

@@ -312,6 +312,14 @@ int synth_colstats(const void* x, int x_bf16, int64_t rows, int64_t cols, int64_
   return to_status(synth::launch_colsum(x, x_bf16, rows, cols, ld, sum, sumsq, (hipStream_t)stream));
 }
 
+int synth_feature_stats(const float* x, int64_t rows, int64_t cols, float min_var, float* mean,
+                        float* inv_std, void* stream) {
+  if (rows <= 0 || cols < 0 || !(min_var > 0.0f)) return SYNTH_EINVAL;
+  if (cols > 0 && (!x || !mean || !inv_std)) return SYNTH_EINVAL;
+  return to_status(synth::launch_feature_stats(x, rows, cols, min_var, mean, inv_std,
+                                               (hipStream_t)stream));
+}
+
 int synth_standardize(const float* x, const float* mean, const float* inv_std, int64_t rows,
                       int64_t cols, void* y_bf16, void* stream) {
   if (rows < 0 || cols < 0) return SYNTH_EINVAL;

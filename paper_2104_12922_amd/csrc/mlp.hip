@@ -41,6 +41,26 @@ __global__ void colsum_kernel(const void* __restrict__ x, int x_bf16, int64_t ro
   if (sumsq) sumsq[c] = (float)s2;
 }
 
+// Per-column mean and 1 / sqrt(max(var, min_var)) (population variance), two
+// float64 passes over the rows, one thread per column.
+__global__ void feature_stats_kernel(const float* __restrict__ x, int64_t rows, int64_t cols,
+                                     float min_var, float* __restrict__ mean,
+                                     float* __restrict__ inv_std) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double s = 0.0;
+  for (int64_t r = 0; r < rows; ++r) s += x[r * cols + c];
+  const double mu = s / (double)rows;
+  double s2 = 0.0;
+  for (int64_t r = 0; r < rows; ++r) {
+    const double d = x[r * cols + c] - mu;
+    s2 += d * d;
+  }
+  const double var = fmax(s2 / (double)rows, (double)min_var);
+  mean[c] = (float)mu;
+  inv_std[c] = (float)(1.0 / sqrt(var));
+}
+
 // y = bf16((x - mean[col]) * inv_std[col])
 __global__ void standardize_kernel(const float* __restrict__ x, const float* __restrict__ mean,
                                    const float* __restrict__ inv_std, int64_t rows, int64_t cols,
@@ -179,6 +199,14 @@ hipError_t launch_colsum(const void* x, int x_bf16, int64_t rows, int64_t cols, 
   if (cols == 0) return hipSuccess;
   hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, s, x,
                      x_bf16, rows, cols, ld, sum, sumsq);
+  return hipGetLastError();
+}
+
+hipError_t launch_feature_stats(const float* x, int64_t rows, int64_t cols, float min_var,
+                                float* mean, float* inv_std, hipStream_t s) {
+  if (cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(feature_stats_kernel, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, s,
+                     x, rows, cols, min_var, mean, inv_std);
   return hipGetLastError();
 }
 

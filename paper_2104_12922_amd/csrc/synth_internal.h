@@ -76,6 +76,8 @@ hipError_t launch_gemm_bf16(const GemmArgs& g, int a_op, int b_op, hipStream_t s
 hipError_t launch_f32_to_bf16(const float* x, void* y, int64_t n, hipStream_t s);
 hipError_t launch_colsum(const void* x, int x_bf16, int64_t rows, int64_t cols, int64_t ld,
                          float* sum, float* sumsq, hipStream_t s);
+hipError_t launch_feature_stats(const float* x, int64_t rows, int64_t cols, float min_var,
+                                float* mean, float* inv_std, hipStream_t s);
 hipError_t launch_standardize(const float* x, const float* mean, const float* inv_std,
                               int64_t rows, int64_t cols, void* y_bf16, hipStream_t s);
 hipError_t launch_mse_sigmoid_grad(const float* out, const float* target, int64_t rows,

@@ -31,6 +31,7 @@ def _sig(L):
     L.synth_logmel.argtypes = [vp, vp, i64, i64, vp, vp, vp, sz, vp, vp]
     L.synth_colstats.argtypes = [vp, i32, i64, i64, i64, vp, vp, vp]
     L.synth_standardize.argtypes = [vp, vp, vp, i64, i64, vp, vp]
+    L.synth_feature_stats.argtypes = [vp, i64, i64, f32, vp, vp, vp]
     L.synth_to_bf16.argtypes = [vp, vp, i64, vp]
     L.synth_mlp_forward.argtypes = [i64, i64, i64, i64] + [vp] * 13
     L.synth_mlp_backward.argtypes = [i64, i64, i64, i64] + [vp] * 20
@@ -40,7 +41,7 @@ def _sig(L):
     L.synth_best_update.argtypes = [vp, i64, i64, i64, i64, i64, vp, i64, vp, vp, vp, vp]
     for n in ("synth_gemm_bf16", "synth_logmel_init", "synth_logmel", "synth_colstats",
               "synth_standardize", "synth_to_bf16", "synth_mlp_forward", "synth_mlp_backward",
-              "synth_adam", "synth_logit_init", "synth_logit_adam", "synth_best_update"):
+              "synth_adam", "synth_feature_stats", "synth_logit_init", "synth_logit_adam", "synth_best_update"):
         getattr(L, n).restype = ctypes.c_int
     return L
 
@@ -118,6 +119,17 @@ def colstats(x: torch.Tensor):
         x.data_ptr(), int(x.dtype == BF16), rows, cols, cols, s.data_ptr(), s2.data_ptr(),
         _stream(x.device)))
     return s, s2
+
+
+def feature_stats(x: torch.Tensor, min_var: float = 1e-6):
+    """(mean, inv_std) float32 [cols] of a float32 [rows, cols] feature matrix."""
+    rows, cols = x.shape
+    mean = torch.empty(cols, dtype=F32, device=x.device)
+    inv_std = torch.empty(cols, dtype=F32, device=x.device)
+    _native.check("synth_feature_stats", lib().synth_feature_stats(
+        _p(x, "x", F32, rows * cols), rows, cols, float(min_var), mean.data_ptr(),
+        inv_std.data_ptr(), _stream(x.device)))
+    return mean, inv_std
 
 
 def standardize(x: torch.Tensor, mean: torch.Tensor, inv_std: torch.Tensor, out=None):
@@ -253,3 +265,90 @@ def best_update(loss, rows, cols, row_stride, col_stride, best, best_idx=None, c
         _p(best_idx, "best_idx", torch.int64, rows) if best_idx is not None else None,
         _p(best_params, "best_params", F32, rows * pd) if best_params is not None else None,
         _stream(loss.device)))
+
+
+# ---------------------------------------------------------------------------
+# Training the proposal on rendered voices
+# ---------------------------------------------------------------------------
+TRAIN_BLOCK, TEST_BLOCK = 9 * 1024, 1024
+
+
+def train_ids(first: int, count: int, device="cuda") -> torch.Tensor:
+    """Global voice indices of training voices first .. first + count - 1,
+    counted in the corpus order with every test block of 1024 skipped (the
+    split of Section 2.1: 9 x 1024 train voices, then 1024 test voices)."""
+    i = torch.arange(first, first + count, device=device, dtype=torch.int64)
+    return (i // TRAIN_BLOCK) * (TRAIN_BLOCK + TEST_BLOCK) + i % TRAIN_BLOCK
+
+
+def ragged_offsets(ids: torch.Tensor, lengths_s=(1, 2, 3, 4), sample_rate=44100.0) -> torch.Tensor:
+    """offsets [B + 1] of voices rendered lengths_s[g mod len] seconds long."""
+    per = torch.tensor([int(round(x * sample_rate)) for x in lengths_s], dtype=torch.int64,
+                       device=ids.device)
+    n = per[ids % len(lengths_s)]
+    return torch.cat([torch.zeros(1, dtype=torch.int64, device=ids.device), torch.cumsum(n, 0)])
+
+
+class Proposal:
+    """Audio -> parameter estimate: log-mel features, standardised with fixed
+    statistics, through the MLP; returns u in (0, 1), float32 [B, 78]."""
+
+    def __init__(self, mlp: MLP, logmel: LogMel, mean: torch.Tensor, inv_std: torch.Tensor):
+        self.mlp, self.logmel, self.mean, self.inv_std = mlp, logmel, mean, inv_std
+
+    def features(self, audio, offsets=None):
+        return standardize(self.logmel(audio, offsets=offsets), self.mean, self.inv_std)
+
+    def __call__(self, audio, offsets=None):
+        return self.mlp.forward(self.features(audio, offsets)).clone()
+
+
+def render_batch(seed, ids, nebula_table, lengths_s=(1, 2, 3, 4)):
+    """(u, packed audio, offsets) of voices ids drawn and rendered on the GPU."""
+    from . import synth_render, synth_sample_params
+    offs = ragged_offsets(ids, lengths_s)
+    u = synth_sample_params(seed, voice_ids=ids)
+    audio = synth_render(u, nebula_table, offsets=offs, voice_ids=ids, noise_seed=seed)
+    return u, audio, offs
+
+
+def train_proposal(nebula_table, steps: int, batch: int = 4096, seed: int = 10,
+                   lengths_s=(1, 2, 3, 4), lr: float = 3e-4, warmup: int = 500, init=None,
+                   log_every: int = 0, log=print):
+    """Train the proposal on freshly rendered training voices: each step draws
+    `batch` new voices, renders them (ragged lengths), computes log-mel
+    features and takes one Adam step on the MSE between the MLP's sigmoid
+    output and the drawn u.  Feature statistics come from the first batch.
+    Returns (Proposal, history of (step, loss))."""
+    from workloads import mlp_init
+    lm = LogMel()
+    net = MLP(init if init is not None else mlp_init(0), lr=lr)
+    _, audio, offs = render_batch(seed, train_ids(0, batch), nebula_table, lengths_s)
+    mean, inv_std = feature_stats(lm(audio, offsets=offs))
+    del audio
+    hist, pending = [], []
+    for s in range(steps):
+        u, audio, offs = render_batch(seed, train_ids((s + 1) * batch, batch), nebula_table,
+                                      lengths_s)
+        x = standardize(lm(audio, offsets=offs), mean, inv_std)
+        net.lr = lr * min(1.0, (s + 1) / max(1, warmup))
+        pending.append((s, net.train_step(x, u).clone()))
+        if log_every and ((s + 1) % log_every == 0 or s + 1 == steps):
+            hist += [(i, float(l)) for i, l in pending]
+            pending = []
+            log(f"train step {s + 1}/{steps} loss {hist[-1][1]:.5f}")
+    hist += [(i, float(l)) for i, l in pending]
+    return Proposal(net, lm, mean, inv_std), hist
+
+
+def heldout_mse(proposal: Proposal, nebula_table, seed: int = 11, count: int = 4096,
+                lengths_s=(1, 2, 3, 4), batch: int = 1024):
+    """Mean squared error of the proposal's u on held-out voices (another seed)."""
+    tot, n = 0.0, 0
+    for first in range(0, count, batch):
+        ids = torch.arange(first, min(first + batch, count), device="cuda", dtype=torch.int64)
+        u, audio, offs = render_batch(seed, ids, nebula_table, lengths_s)
+        est = proposal(audio, offs)
+        tot += float(((est - u) ** 2).sum())
+        n += u.numel()
+    return tot / n
