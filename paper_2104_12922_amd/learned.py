@@ -342,13 +342,16 @@ def train_proposal(nebula_table, steps: int, batch: int = 4096, seed: int = 10,
 
 
 def heldout_mse(proposal: Proposal, nebula_table, seed: int = 11, count: int = 4096,
-                lengths_s=(1, 2, 3, 4), batch: int = 1024):
-    """Mean squared error of the proposal's u on held-out voices (another seed)."""
-    tot, n = 0.0, 0
+                lengths_s=(1, 2, 3, 4), batch: int = 1024, per_param: bool = False):
+    """Mean squared error of the proposal's u on held-out voices (another
+    seed); per_param=True returns the float64 [78] per-parameter errors."""
+    tot = torch.zeros(78, dtype=torch.float64, device="cuda")
+    n = 0
     for first in range(0, count, batch):
         ids = torch.arange(first, min(first + batch, count), device="cuda", dtype=torch.int64)
         u, audio, offs = render_batch(seed, ids, nebula_table, lengths_s)
         est = proposal(audio, offs)
-        tot += float(((est - u) ** 2).sum())
-        n += u.numel()
-    return tot / n
+        tot += ((est - u).double() ** 2).sum(0)
+        n += u.shape[0]
+    per = (tot / n).cpu()
+    return per if per_param else float(per.mean())
