@@ -26,6 +26,25 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes moved by one render launch on the ragged 16384-voice workload,
+# from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB; the
+# factors make each counter read 1 GiB for a plain 1 GiB device copy).  Valid
+# only for the kernel sources with this digest; reported as null otherwise.
+RENDER_TRAFFIC = {"sources_sha256_16": "ee3d2af3afaab1c8",
+                  "fetch_bytes": 8922470, "write_bytes": 6758339686}
+RENDER_SOURCES = ("render.hip", "voice_device.h", "philox.h")
+
+
+def render_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for f in RENDER_SOURCES:
+        with open(os.path.join(ROOT, "paper_2104_12922_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != RENDER_TRAFFIC["sources_sha256_16"]:
+        return None
+    return float(RENDER_TRAFFIC["fetch_bytes"] + RENDER_TRAFFIC["write_bytes"])
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -160,7 +179,9 @@ def main():
                    "hip_graph": bool(args.graph), "phase_dtype": "f64"},
         "mhz": value / 1e6, "x_realtime": value / wl.sample_rate,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": render_traffic() if wl.batch == 16384 else None,
+                     "traffic_unit": "B/launch",
                      "kernel": "render_kernel", "kernel_ms": kern_ms,
                      "alg_bytes_per_launch": alg_bytes},
         "context": {"paper_single_gpu_mhz": 714.0, "paper_gpu": "V100"},
