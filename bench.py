@@ -31,7 +31,8 @@ HBM_PEAK_GBS = 8000.0
 # factors make each counter read 1 GiB for a plain 1 GiB device copy).  Valid
 # only for the kernel sources with this digest; reported as null otherwise.
 RENDER_TRAFFIC = {"sources_sha256_16": "ee3d2af3afaab1c8",
-                  "fetch_bytes": 8922470, "write_bytes": 6758339686}
+                  "fetch_bytes": 8922470, "write_bytes": 6758339686,
+                  "valu_busy": 0.77}
 RENDER_SOURCES = ("render.hip", "voice_device.h", "philox.h")
 
 
@@ -43,7 +44,7 @@ def render_traffic():
             h.update(fh.read())
     if h.hexdigest()[:16] != RENDER_TRAFFIC["sources_sha256_16"]:
         return None
-    return float(RENDER_TRAFFIC["fetch_bytes"] + RENDER_TRAFFIC["write_bytes"])
+    return RENDER_TRAFFIC
 
 
 def parse():
@@ -164,6 +165,7 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
 
+    prof = render_traffic() if wl.batch == 16384 and not args.rps else None
     ms = dt / args.steps * 1e3
     value = total / (dt / args.steps)
     alg_bytes = 4.0 * total + 4.0 * 78 * B + 8.0 * (B + 1)
@@ -180,8 +182,10 @@ def main():
         "mhz": value / 1e6, "x_realtime": value / wl.sample_rate,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": render_traffic() if wl.batch == 16384 else None,
+                     "traffic": (float(prof["fetch_bytes"] + prof["write_bytes"])
+                                 if prof else None),
                      "traffic_unit": "B/launch",
+                     "valu_busy_profiled": prof["valu_busy"] if prof else None,
                      "kernel": "render_kernel", "kernel_ms": kern_ms,
                      "alg_bytes_per_launch": alg_bytes},
         "context": {"paper_single_gpu_mhz": 714.0, "paper_gpu": "V100"},

@@ -150,6 +150,10 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
       }
       float kf = (float)(m * h);
       float* trow = tile + lane * h;
+      // Consume the LDS and cross-lane loads here, so that the loop below
+      // carries no wait on them (its own LDS stores are never waited for).
+      asm volatile("" ::"v"(t1), "v"(i1), "v"(t2), "v"(i2), "v"(r1), "v"(r2));
+      asm volatile("" ::"v"(A10), "v"(A1d), "v"(A20), "v"(A2d));
       for (int k = 0; k < h; ++k) {
         const float x1 = sin_cycles(t1);
         const float x2 = squaresaw(t2, K2, shape, sq_gain);
