@@ -57,6 +57,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graph", type=int, default=1, help="capture the step in a HIP graph")
     ap.add_argument("--rps", type=int, default=0, help="runs per segment (0 = library default)")
+    ap.add_argument("--workload", default="render", choices=("render", "learned", "grad"),
+                    help="render: the headline ragged render; learned: one proposal "
+                         "training step (render + log-mel + MLP); grad: render, MR-STFT "
+                         "loss and gradient, render adjoint")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (the "
                          "reference point that scales HBM byte counters) and exit")
@@ -101,6 +105,125 @@ def cpu_baseline(wl, min_seconds):
                       f"({n} samples, 1/2/4 s mix) in batches of 128, {dt:.1f} s wall"}
 
 
+def _events(n):
+    import torch
+    return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in range(n)]
+
+
+def bench_learned(args):
+    """One training step of the proposal at batch 4096: draw and render 4096
+    training voices (1-4 s by voice index mod 4), log-mel features of the
+    64 frames, standardisation, MLP forward + backward + Adam."""
+    import torch
+    import workloads as W
+    from paper_2104_12922_amd import learned as Lr
+    B = 4096
+    tab = W.default_nebula().table()
+    lm = Lr.LogMel()
+    net = Lr.MLP(W.mlp_init(0))
+    stream = torch.cuda.Stream()
+    mel_flop = 2.0 * 64 * 2048 * 2050 + 2.0 * 64 * 1025 * 128       # per voice
+    mlp_flop = 2.0 * (8192 * 1024 + 1024 * 1024 + 1024 * 78) * 3 - 2.0 * 8192 * 1024
+    with torch.cuda.stream(stream):
+        ids = Lr.train_ids(0, B)
+        u, audio, offs = Lr.render_batch(W.SEED_TRAIN, ids, tab)
+        feat = lm(audio, offsets=offs)
+        mean, inv_std = Lr.feature_stats(feat)
+        x = Lr.standardize(feat, mean, inv_std)
+        torch.cuda.synchronize()
+        n_ev = max(3, min(args.steps, 10))
+        e_r, e_l, e_m = _events(n_ev), _events(n_ev), _events(n_ev)
+        t_step = []
+        for i in range(args.warmup + args.steps):
+            first = (i + 1) * B
+            t0 = time.perf_counter()
+            j = i - args.warmup
+            if 0 <= j < n_ev:
+                e_r[j][0].record(stream)
+            ids = Lr.train_ids(first, B)
+            u, audio, offs = Lr.render_batch(W.SEED_TRAIN, ids, tab)
+            if 0 <= j < n_ev:
+                e_r[j][1].record(stream)
+                e_l[j][0].record(stream)
+            lm(audio, out=feat, offsets=offs)
+            if 0 <= j < n_ev:
+                e_l[j][1].record(stream)
+                e_m[j][0].record(stream)
+            Lr.standardize(feat, mean, inv_std, out=x)
+            net.train_step(x, u)
+            if 0 <= j < n_ev:
+                e_m[j][1].record(stream)
+            torch.cuda.synchronize()
+            if j >= 0:
+                t_step.append(time.perf_counter() - t0)
+        ms = lambda ev: float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        r_ms, l_ms, m_ms = ms(e_r), ms(e_l), ms(e_m)
+    step_s = float(np.mean(t_step))
+    tf = mel_flop * B / (l_ms * 1e-3) / 1e12
+    out = {"metric": "proposal training voices/sec", "value": B / step_s, "unit": "voices/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_s * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+           "data": "synthetic (Philox-drawn training voices rendered on the fly)",
+           "config": {"workload": "proposal_train_b4096_1-4s", "batch": B,
+                      "features": "log-mel 128 x 64", "mlp": "8192-1024-1024-78"},
+           "phase_ms": {"render": r_ms, "logmel": l_ms, "mlp_train": m_ms},
+           "roofline": {"bound": "mfma", "achieved": tf, "peak": 2500.0, "unit": "TFLOP/s",
+                        "frac": tf / 2500.0, "traffic": None, "kernel": "log-mel GEMMs",
+                        "alg_flop_per_launch": mel_flop * B},
+           "mlp_tflops": mlp_flop * B / (m_ms * 1e-3) / 1e12}
+    print(json.dumps(out), flush=True)
+
+
+def bench_grad(args):
+    """Gradient workload: 256 voices x 4 s rendered, MR-STFT loss and gradient
+    against targets of another seed, render adjoint to the 78 parameters."""
+    import torch
+    import workloads as W
+    import paper_2104_12922_amd as S
+    wl = W.gradient_batch()
+    tab = wl.nebula.table()
+    B, N = wl.batch, 176400
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        u = S.synth_sample_params(wl.seed, 0, B)
+        ut = S.synth_sample_params(W.SEED_TARGET, 0, B)
+        t = S.synth_render(ut, tab, n_samples=N, noise_seed=W.SEED_TARGET)
+        x = torch.empty(B, N, device="cuda")
+        gp = torch.empty(B, 78, device="cuda")
+        ws = S.synth_render_backward_workspace(tab, B, N)
+        n_ev = max(3, min(args.steps, 10))
+        e = [_events(n_ev) for _ in range(3)]
+        tt = []
+        for i in range(args.warmup + args.steps):
+            j = i - args.warmup
+            t0 = time.perf_counter()
+            if 0 <= j < n_ev:
+                e[0][j][0].record(stream)
+            S.synth_render(u, tab, n_samples=N, noise_seed=wl.seed, out=x)
+            if 0 <= j < n_ev:
+                e[0][j][1].record(stream)
+                e[1][j][0].record(stream)
+            loss, gx = S.synth_mrstft_loss(x, t, grad=True)
+            if 0 <= j < n_ev:
+                e[1][j][1].record(stream)
+                e[2][j][0].record(stream)
+            S.synth_render_backward(u, gx, tab, noise_seed=wl.seed, workspace=ws, out=gp)
+            if 0 <= j < n_ev:
+                e[2][j][1].record(stream)
+            torch.cuda.synchronize()
+            if j >= 0:
+                tt.append(time.perf_counter() - t0)
+        ms = [float(np.mean([a.elapsed_time(b) for a, b in ev])) for ev in e]
+    step = float(np.mean(tt))
+    out = {"metric": "gradient steps voices/sec", "value": B / step, "unit": "voices/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": step * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic", "config": {"workload": wl.name, "voices": B, "samples": B * N},
+           "phase_ms": {"render": ms[0], "mrstft_loss_grad": ms[1], "render_adjoint": ms[2]}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -109,6 +232,10 @@ def main():
     if args.copy_bytes:
         copy_only(args.copy_bytes)
         return
+    if args.workload == "learned":
+        return bench_learned(args)
+    if args.workload == "grad":
+        return bench_grad(args)
     import torch
     import workloads as W
     import paper_2104_12922_amd as S
