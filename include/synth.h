@@ -174,9 +174,11 @@ int synth_gemm_bf16(int a_layout, int b_layout, int64_t M, int64_t N, int64_t K,
 /* Log-mel features: 64 frames of 2048 samples at hop 2756 (no padding),
  * periodic Hann window, power spectrum via a bf16 DFT GEMM, 128 HTK mel
  * triangles from 0 to sample_rate / 2 (no area normalisation), log(x + 1e-6).
- * synth_logmel_init fills the tables once: dft_basis bf16 [2050][2048]
- * (rows cos, -sin per bin), mel_basis bf16 [128][1032]; it synchronises the
- * stream.  synth_logmel: audio float32, voice b = audio[b * n_samples ..] of
+ * The frames are rounded to bf16, the window is folded into the basis.
+ * synth_logmel_init fills the tables once: dft_basis bf16 [2048][2048]
+ * (row 0: w(k), row 1: w(k)(-1)^k - the real bins 0 and 1024 - then rows
+ * 2f, 2f+1: w(k) cos(2 pi f k / 2048), -w(k) sin(...) for f = 1..1023),
+ * mel_basis bf16 [128][1032]; it synchronises the stream.  synth_logmel: audio float32, voice b = audio[b * n_samples ..] of
  * n_samples samples (offsets == NULL, n_samples > 0) or the ragged range
  * audio[offsets[b] .. offsets[b+1]) (offsets dev int64 [batch + 1]); samples
  * past a voice's end count as 0 (a render shorter than the 175676 samples

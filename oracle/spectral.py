@@ -123,20 +123,23 @@ def logmel(x: torch.Tensor, sr: float = 44100.0) -> torch.Tensor:
 
 
 def logmel_bf16(x: torch.Tensor, sr: float = 44100.0) -> torch.Tensor:
-    """Log-mel with the GPU path's quantisation points: windowed frames, DFT
-    basis, power spectrum and mel basis rounded to bfloat16 (the window and the
-    basis through float32); products accumulated in float64 here.
-    Returns [B, 128, 64]."""
+    """Log-mel with bfloat16 operands at fixed points: the frames (float32
+    samples) rounded to bfloat16; the DFT basis with the periodic Hann window
+    folded in, w(k) cos(2 pi f k / n) and -w(k) sin(2 pi f k / n), computed in
+    float64, rounded to float32 and then to bfloat16; the power spectrum and the
+    mel basis rounded to bfloat16; products accumulated in float64 here.
+    Windowing the basis instead of the frame is the same linear map, so this
+    differs from ``logmel`` only by the roundings.  Returns [B, 128, 64]."""
     n = MEL_NFFT
-    k = torch.arange(n, dtype=torch.float32)
-    w = 0.5 - 0.5 * torch.cos(2.0 * math.pi * k / n)                  # float32 window
-    fr = frames(x.float(), n, MEL_HOP, count=MEL_FRAMES) * w          # float32 product
+    k = torch.arange(n, dtype=F64)
+    w = 0.5 - 0.5 * torch.cos(2.0 * math.pi * k / n)                  # float64 window
+    fr = frames(x.float(), n, MEL_HOP, count=MEL_FRAMES)
     fr = fr.to(torch.bfloat16).to(F64)
     f = torch.arange(n // 2 + 1, dtype=torch.int64)[:, None]
     ph = (f * torch.arange(n)[None, :]) % n                           # exact angle reduction
     ang = 2.0 * math.pi * ph.to(F64) / n
-    cosb = torch.cos(ang).float().to(torch.bfloat16).to(F64)
-    sinb = (-torch.sin(ang)).float().to(torch.bfloat16).to(F64)
+    cosb = (w * torch.cos(ang)).float().to(torch.bfloat16).to(F64)
+    sinb = (-w * torch.sin(ang)).float().to(torch.bfloat16).to(F64)
     re = fr @ cosb.T
     im = fr @ sinb.T
     P = (re * re + im * im).float().to(torch.bfloat16).to(F64)        # [B, 64, 1025]

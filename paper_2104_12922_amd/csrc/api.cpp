@@ -256,7 +256,7 @@ size_t synth_logmel_workspace(int64_t batch) {
 
 int synth_logmel_init(double sample_rate, void* dft_basis, void* mel_basis, void* stream) {
   if (!dft_basis || !mel_basis || !(sample_rate > 0.0)) return SYNTH_EINVAL;
-  hipError_t e = synth::launch_dft_basis(dft_basis, kMelNfft, (hipStream_t)stream);
+  hipError_t e = synth::launch_dft_basis(dft_basis, (hipStream_t)stream);
   if (e != hipSuccess) return SYNTH_EDEVICE;
   // HTK mel triangles (mel = 2595 log10(1 + f / 700)), 130 edges from 0 to sr/2,
   // peak 1, no area normalisation; stored K-major [128][1032] in bf16.
@@ -290,14 +290,8 @@ int synth_logmel(const float* audio, const int64_t* offsets, int64_t batch, int6
   if (!audio || !dft_basis || !mel_basis || !workspace || !features) return SYNTH_EINVAL;
   if (!offsets && n_samples <= 0) return SYNTH_EINVAL;
   if (workspace_bytes < synth_logmel_workspace(batch)) return SYNTH_ENOMEM;
-  synth::GemmArgs g = {};
-  g.M = batch * kMelFrames; g.N = kMelNfft + 2; g.K = kMelNfft;
-  g.A = audio; g.lda = offsets ? 0 : n_samples; g.frame_hop = kMelHop; g.frame_count = kMelFrames;
-  g.frame_offsets = offsets;
-  g.B = dft_basis; g.ldb = kMelNfft;
-  g.C = workspace; g.ldc = kMelLd; g.c_bf16 = 1; g.epilogue = synth::kEpiPowerPairs;
-  g.alpha = 1.0f;
-  hipError_t e = synth::launch_gemm_bf16(g, synth::kOpFrames, synth::kOpKMajor, (hipStream_t)stream);
+  hipError_t e = synth::launch_dft_power(audio, offsets, offsets ? 0 : n_samples, batch,
+                                         dft_basis, workspace, kMelLd, (hipStream_t)stream);
   if (e != hipSuccess) return SYNTH_EDEVICE;
   synth::GemmArgs h = {};
   h.M = batch * kMelFrames; h.N = kMelBins; h.K = kMelNfft / 2 + 1;

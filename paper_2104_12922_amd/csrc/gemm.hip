@@ -2,12 +2,7 @@
 // float32 accumulation (v_mfma_f32_32x32x16_bf16).
 //
 // Operand layouts: kOpKMajor (row r of the operand has K contiguous:
-// X[r * ld + k]), kOpRowMajorMN (X[k * ld + r]), and for A only kOpFrames:
-// A[m][k] = bf16(hann(k) * x_v[t * hop + k]) with v = m / frames,
-// t = m % frames, x_v voice v's audio (v * lda, lda samples long, or the
-// ragged range [off[v], off[v+1])) read as 0 past its end - the framed,
-// windowed audio of a DFT, formed while staging so no frame matrix is ever
-// written.
+// X[r * ld + k]) and kOpRowMajorMN (X[k * ld + r]).
 //
 // Tiles of 128 x 128 x 32 per 256-thread workgroup (four wavefronts in 2 x 2,
 // each 64 x 64 as 2 x 2 MFMA 32 x 32 blocks).  Tiles are staged in LDS as
@@ -100,35 +95,6 @@ __device__ __forceinline__ void stage(uint16_t (*dst)[PADK], const GemmArgs& g, 
     }
 #pragma unroll
     for (int e = 0; e < 16; ++e) dst[r0 + e][kk] = v[e];
-  } else {  // kOpFrames
-    const float* audio = reinterpret_cast<const float*>(srcv);
-    const int r = t >> 1;
-    const int kk = (t & 1) * 16;
-    const int64_t gr = row0 + r;
-    int64_t start = 0, len = 0;                // samples at or past len read as 0
-    if (gr < nrows) {
-      const int64_t vox = gr / g.frame_count;
-      if (g.frame_offsets) {
-        start = g.frame_offsets[vox];
-        len = g.frame_offsets[vox + 1] - start;
-      } else {
-        start = vox * ld;
-        len = ld;
-      }
-    }
-    const int64_t pos0 = (gr - (gr / g.frame_count) * g.frame_count) * g.frame_hop + k0 + kk;
-    const float* x = audio + start;
-    const float inv_n = 1.0f / (float)K;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int64_t gk = k0 + kk + e;
-      uint16_t h = 0;
-      if (gk < K && pos0 + e < len) {
-        const float w = 0.5f - 0.5f * cospif(2.0f * (float)gk * inv_n);
-        h = f2bf(w * x[pos0 + e]);
-      }
-      dst[r][kk + e] = h;
-    }
   }
 }
 
@@ -237,7 +203,6 @@ hipError_t launch_gemm_bf16(const GemmArgs& g, int a_op, int b_op, hipStream_t s
   switch (a_op) {
     case kOpKMajor: return launch_b<kOpKMajor>(g, b_op, grid, s);
     case kOpRowMajorMN: return launch_b<kOpRowMajorMN>(g, b_op, grid, s);
-    case kOpFrames: return launch_b<kOpFrames>(g, b_op, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -1,7 +1,7 @@
 // Elementwise and reduction kernels of the learned proposal: bf16 casts,
 // per-column sums (bias gradients, feature statistics), feature
-// standardisation, the sigmoid-output MSE gradient, Adam, and the DFT basis
-// of the log-mel features.  All deterministic (fixed-order reductions).
+// standardisation, the sigmoid-output MSE gradient, Adam, and the
+// logit-space updates and best-so-far tracking of sound matching.  All deterministic (fixed-order reductions).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -105,21 +105,6 @@ __global__ void adam_kernel(int64_t n, float* __restrict__ w, uint16_t* __restri
     const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
     w[i] = wi;
     if (wb) wb[i] = f2bf(wi);
-  }
-}
-
-// DFT basis, K-major: row 2f = cos(2 pi f k / n), row 2f+1 = -sin(2 pi f k / n),
-// f = 0..n/2, k = 0..n-1 (float64 angle reduction, rounded to bf16).
-__global__ void dft_basis_kernel(uint16_t* __restrict__ basis, int n) {
-  const int64_t total = (int64_t)(n + 2) * n;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = i / n, k = i % n;
-    const int64_t f = row >> 1;
-    const int64_t ph = (f * k) % n;            // exact angle reduction
-    const double a = 2.0 * (double)ph / (double)n;
-    const double val = (row & 1) ? -sinpi(a) : cospi(a);
-    basis[i] = f2bf((float)val);
   }
 }
 
@@ -233,13 +218,6 @@ hipError_t launch_adam(int64_t n, float* w, void* w_bf16, const float* g, float*
   const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
   hipLaunchKernelGGL(adam_kernel, grid_for(n, 256), dim3(256), 0, s, n, w, (uint16_t*)w_bf16, g,
                      m, v, lr, b1, b2, eps, c1, c2);
-  return hipGetLastError();
-}
-
-hipError_t launch_dft_basis(void* basis_bf16, int n_fft, hipStream_t s) {
-  const int64_t total = (int64_t)(n_fft + 2) * n_fft;
-  hipLaunchKernelGGL(dft_basis_kernel, grid_for(total, 256), dim3(256), 0, s,
-                     (uint16_t*)basis_bf16, n_fft);
   return hipGetLastError();
 }
 

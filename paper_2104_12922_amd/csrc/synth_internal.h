@@ -49,12 +49,12 @@ enum {
   kEpiPowerPairs = 4,  // columns (2f, 2f+1) = (Re, Im): store Re^2 + Im^2 at column f
   kEpiLogMelT = 5      // store log(x + 1e-6) at feature[(row / 64) * 8192 + col * 64 + row % 64]
 };
-enum { kOpKMajor = 0, kOpRowMajorMN = 1, kOpFrames = 2 };
+enum { kOpKMajor = 0, kOpRowMajorMN = 1 };
 
 struct GemmArgs {
   int64_t M, N, K;
-  const void* A;       // bf16 (or float32 audio for kOpFrames)
-  int64_t lda;         // kOpFrames: samples per voice
+  const void* A;       // bf16
+  int64_t lda;
   const void* B;       // bf16
   int64_t ldb;
   void* C;
@@ -65,9 +65,6 @@ struct GemmArgs {
   const float* aux;    // kEpiGeluGrad operand, same layout as C
   float* pre;          // optional float32 pre-activation output (layout of C)
   float alpha, beta;   // beta != 0: C = epi(...) + beta * C
-  int frame_hop;       // kOpFrames: hop between frames; frames per voice in frame_count
-  int frame_count;
-  const int64_t* frame_offsets;  // kOpFrames: voice v = audio[off[v], off[v+1]) (null: v * lda, lda long)
 };
 
 hipError_t launch_gemm_bf16(const GemmArgs& g, int a_op, int b_op, hipStream_t s);
@@ -85,7 +82,11 @@ hipError_t launch_mse_sigmoid_grad(const float* out, const float* target, int64_
                                    hipStream_t s);
 hipError_t launch_adam(int64_t n, float* w, void* w_bf16, const float* g, float* m, float* v,
                        float lr, float b1, float b2, float eps, int step, hipStream_t s);
-hipError_t launch_dft_basis(void* basis_bf16, int n_fft, hipStream_t s);
+// log-mel power spectrum (dft.hip): basis bf16 [2048][2048]; power bf16 [batch * 64][ldp]
+hipError_t launch_dft_basis(void* basis_bf16, hipStream_t s);
+hipError_t launch_dft_power(const float* audio, const int64_t* offsets, int64_t n_uniform,
+                            int64_t batch, const void* basis, void* power, int64_t ldp,
+                            hipStream_t s);
 hipError_t launch_logit_init(const float* u, float* z, float* u_out, int64_t n, float eps,
                              hipStream_t s);
 hipError_t launch_logit_adam(int64_t n, float* z, float* u, const float* grad_u, float* m,

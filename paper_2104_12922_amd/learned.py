@@ -83,7 +83,7 @@ class LogMel:
 
     def __init__(self, sample_rate: float = 44100.0, device="cuda"):
         self.device = torch.device(device)
-        self.dft = torch.empty(2050, 2048, dtype=BF16, device=self.device)
+        self.dft = torch.empty(2048, 2048, dtype=BF16, device=self.device)
         self.mel = torch.empty(128, 1032, dtype=BF16, device=self.device)
         _native.check("synth_logmel_init", lib().synth_logmel_init(
             float(sample_rate), self.dft.data_ptr(), self.mel.data_ptr(), _stream(self.device)))
