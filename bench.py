@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graph", type=int, default=1, help="capture the step in a HIP graph")
     ap.add_argument("--rps", type=int, default=0, help="runs per segment (0 = library default)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="time the candidate launch plans on this batch first (untimed) and "
+                         "render with the fastest")
     ap.add_argument("--workload", default="render", choices=("render", "learned", "grad"),
                     help="render: the headline ragged render; learned: one proposal "
                          "training step (render + log-mel + MLP); grad: render, MR-STFT "
@@ -192,6 +195,8 @@ def bench_grad(args):
         x = torch.empty(B, N, device="cuda")
         gp = torch.empty(B, 78, device="cuda")
         ws = S.synth_render_backward_workspace(tab, B, N)
+        ws_loss = S.synth_mrstft_workspace(B, N, grad=True)
+        gx = torch.empty(B, N, device="cuda")
         n_ev = max(3, min(args.steps, 10))
         e = [_events(n_ev) for _ in range(3)]
         tt = []
@@ -204,7 +209,7 @@ def bench_grad(args):
             if 0 <= j < n_ev:
                 e[0][j][1].record(stream)
                 e[1][j][0].record(stream)
-            loss, gx = S.synth_mrstft_loss(x, t, grad=True)
+            loss, gx = S.synth_mrstft_loss(x, t, grad=True, workspace=ws_loss, out_grad=gx)
             if 0 <= j < n_ev:
                 e[1][j][1].record(stream)
                 e[2][j][0].record(stream)
@@ -251,9 +256,21 @@ def main():
     audio = torch.empty(total, dtype=torch.float32, device=dev)
     stream = torch.cuda.Stream(device=dev)
 
+    plan = None
+    if args.rps:
+        plan = (args.rps, 1, 0, 0)
+    elif args.autotune:
+        from paper_2104_12922_amd.autotune import RenderTuner
+        with torch.cuda.stream(stream):
+            S.synth_sample_params(wl.seed, wl.first_g, B, out=params)
+            plan, _ = RenderTuner().tune(params, table, offsets=offsets,
+                                         noise_seed=wl.key_noise(), out=audio)
+        torch.cuda.synchronize()
+
     def render():
-        if args.rps:
-            S.synth_render_plan(params, table, args.rps, 1, offsets=offsets,
+        if plan is not None:
+            S.synth_render_plan(params, table, plan[0], plan[1], persistent=bool(plan[2]),
+                                grid_blocks=plan[3], offsets=offsets,
                                 noise_seed=wl.key_noise(), out=audio)
         else:
             S.synth_render(params, table, offsets=offsets, noise_seed=wl.key_noise(), out=audio)
@@ -292,7 +309,7 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
 
-    prof = render_traffic() if wl.batch == 16384 and not args.rps else None
+    prof = render_traffic() if wl.batch == 16384 and plan in (None, (4, 1, 0, 0)) else None
     ms = dt / args.steps * 1e3
     value = total / (dt / args.steps)
     alg_bytes = 4.0 * total + 4.0 * 78 * B + 8.0 * (B + 1)
@@ -305,7 +322,8 @@ def main():
         "config": {"workload": wl.name, "voices": B, "samples": total,
                    "lengths_s": [1, 2, 4], "sample_rate": wl.sample_rate,
                    "control_rate": wl.control_rate, "note_duration_s": [0.1, 4.0],
-                   "hip_graph": bool(args.graph), "phase_dtype": "f64"},
+                   "hip_graph": bool(args.graph), "phase_dtype": "f64",
+                   "launch_plan": list(plan) if plan is not None else "default"},
         "mhz": value / 1e6, "x_realtime": value / wl.sample_rate,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

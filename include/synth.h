@@ -135,7 +135,7 @@ int synth_render_backward(const synth_config* cfg, const float* params, const ui
                           const float* grad_audio, float* grad_params, void* workspace,
                           size_t workspace_bytes, void* stream);
 
-/* Multi-resolution log-magnitude STFT L1 loss (Section 4.3: multi-scale
+/* Multi-resolution log-magnitude STFT L1 loss (Section 4: the multi-scale
  * spectrogram distance, L1), per voice, and optionally its gradient.
  *   For voice b: loss[b] = sum over n in (512, 1024, 2048), hop n/4, of the mean
  *   over frames t < F_n = floor((N - n) / hop) + 1 and bins k <= n/2 of
@@ -146,9 +146,16 @@ int synth_render_backward(const synth_config* cfg, const float* params, const ui
  *   loss       dev float64 [batch], written.
  *   grad_x     dev float32 [batch][n_samples] or NULL; if given it receives
  *              d loss[b] / d x[b][.] (float32 FFT arithmetic).
- *   n_samples  > 0, <= 2^31.  Bitwise deterministic. */
+ *   workspace  dev buffer of >= synth_mrstft_workspace(batch, n_samples,
+ *              grad_x != NULL) bytes, caller-owned, contents clobbered (with
+ *              a gradient: 4 bytes per frame sample of every resolution,
+ *              about 48 bytes per input sample).
+ *   0 < n_samples <= 2^31, batch <= 65535 (SYNTH_EUNSUPPORTED above).
+ *   Bitwise deterministic. */
+size_t synth_mrstft_workspace(int64_t batch, int64_t n_samples, int with_grad);
 int synth_mrstft_loss(const float* x, const float* target, int64_t batch, int64_t n_samples,
-                      double* loss, float* grad_x, void* stream);
+                      double* loss, float* grad_x, void* workspace, size_t workspace_bytes,
+                      void* stream);
 
 /* ---------------------------------------------------------------------------
  * Learned proposal: log-mel features and an MLP mapping them to parameters

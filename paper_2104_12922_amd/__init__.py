@@ -117,18 +117,31 @@ def synth_render_plan(params: torch.Tensor, nebula, runs_per_segment: int, slice
     return out
 
 
-def synth_mrstft_loss(x: torch.Tensor, target: torch.Tensor, grad: bool = False):
+def synth_mrstft_workspace(batch: int, n_samples: int, grad: bool = False) -> torch.Tensor:
+    """A device workspace large enough for synth_mrstft_loss."""
+    need = _native.lib().synth_mrstft_workspace(int(batch), int(n_samples), int(bool(grad)))
+    if need == 0:
+        raise ValueError("invalid MR-STFT sizes")
+    return torch.empty(need, dtype=torch.uint8, device="cuda")
+
+
+def synth_mrstft_loss(x: torch.Tensor, target: torch.Tensor, grad: bool = False,
+                      workspace: torch.Tensor | None = None, out_grad: torch.Tensor | None = None):
     """Per-voice multi-resolution log-magnitude STFT L1 (float64 [B]) and, if
     grad, d loss[b] / d x[b] (float32 [B, N]) - see synth.h."""
     if x.shape != target.shape or x.dim() != 2:
         raise ValueError("x and target must both be [B, N]")
     B, N = x.shape
     loss = torch.empty(B, dtype=torch.float64, device=x.device)
-    g = torch.empty_like(x) if grad else None
+    g = (out_grad if out_grad is not None else torch.empty_like(x)) if grad else None
+    need = _native.lib().synth_mrstft_workspace(int(B), int(N), int(bool(grad)))
+    if workspace is None or workspace.numel() * workspace.element_size() < need:
+        workspace = torch.empty(max(need, 8), dtype=torch.uint8, device=x.device)
     _native.check("synth_mrstft_loss", _native.lib().synth_mrstft_loss(
         _dev_ptr(x, "x", torch.float32, B * N), _dev_ptr(target, "target", torch.float32, B * N),
         B, N, _dev_ptr(loss, "loss", torch.float64, B),
-        _dev_ptr(g, "grad", torch.float32, B * N) if grad else None, _stream(x.device)))
+        _dev_ptr(g, "grad", torch.float32, B * N) if grad else None, workspace.data_ptr(),
+        workspace.numel() * workspace.element_size(), _stream(x.device)))
     return (loss, g) if grad else loss
 
 

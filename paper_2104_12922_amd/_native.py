@@ -59,7 +59,9 @@ def lib() -> ctypes.CDLL:
         L.synth_mrstft_loss.restype = ctypes.c_int
         L.synth_mrstft_loss.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                         ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
-                                        ctypes.c_void_p]
+                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.synth_mrstft_workspace.restype = ctypes.c_size_t
+        L.synth_mrstft_workspace.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
         L.synth_render_backward_workspace.restype = ctypes.c_size_t
         L.synth_render_backward_workspace.argtypes = [ctypes.POINTER(SynthConfig), ctypes.c_int64,
                                                       ctypes.c_int64]

@@ -1,0 +1,104 @@
+"""Launch-plan autotuner for the batched render.
+
+A plan is (runs_per_segment, slices_per_voice, persistent, grid_blocks) of
+`synth_render_plan`.  Plans with the same runs per segment render identical
+bits; changing the runs per segment regroups the float64 phase sums, which
+moves samples by float32 rounding only (every plan is held to the same parity
+tolerance against the oracle), so the choice is one of speed.  The tuner times each candidate plan on the caller's
+own batch (HIP events on the current stream, median of `reps` launches after
+one warm-up), keeps the fastest per batch shape, and can save and reload its
+table as JSON.  Tuning happens outside any timed region; a tuned render is
+one `synth_render_plan` call.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+import torch
+
+from . import synth_render_plan
+
+
+def default_candidates(batch: int, uniform: bool):
+    """Plans worth timing: 2 or 4 runs per control period; one workgroup per
+    voice, or a persistent grid of 1-4 workgroups per CU (256 CUs); uniform
+    batches smaller than the CU count also try splitting voices into slices."""
+    c = []
+    for rps in (2, 4):
+        c.append((rps, 1, 0, 0))
+        for g in (1024, 2048, 4096):
+            if g < batch:
+                c.append((rps, 1, 1, g))
+        if uniform and batch < 256:
+            for sl in (2, 4, 8):
+                c.append((rps, sl, 0, 0))
+    return c
+
+
+class RenderTuner:
+    def __init__(self, reps: int = 3, candidates=None):
+        self.reps = reps
+        self.candidates = candidates
+        self.table: dict[str, tuple] = {}
+        self.timings: dict[str, dict] = {}
+
+    @staticmethod
+    def key(batch: int, n_samples: int | None, offsets: torch.Tensor | None) -> str:
+        if offsets is None:
+            return f"u:{batch}:{int(n_samples)}"
+        lens = torch.diff(offsets).cpu().numpy()
+        h = int(np.bitwise_xor.reduce(lens.astype(np.int64) * 1000003 + np.arange(lens.size)))
+        return f"r:{batch}:{int(lens.sum())}:{h & 0xFFFFFFFF:08x}"
+
+    def tune(self, params, nebula, n_samples=None, offsets=None, out=None, **kw):
+        B = params.shape[0]
+        k = self.key(B, n_samples, offsets)
+        cands = self.candidates or default_candidates(B, offsets is None)
+        stream = torch.cuda.current_stream()
+        times = {}
+        for plan in cands:
+            rps, sl, pers, grid = plan
+
+            def run():
+                return synth_render_plan(params, nebula, rps, sl, persistent=bool(pers),
+                                         grid_blocks=grid, n_samples=n_samples, offsets=offsets,
+                                         out=out, **kw)
+            out = run()                          # warm-up (and the output buffer)
+            ts = []
+            for _ in range(self.reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                run()
+                b.record(stream)
+                b.synchronize()
+                ts.append(a.elapsed_time(b))
+            times[plan] = float(np.median(ts))
+        best = min(times, key=times.get)
+        self.table[k] = best
+        self.timings[k] = {",".join(map(str, p)): t for p, t in times.items()}
+        return best, times
+
+    def plan_for(self, params, nebula, n_samples=None, offsets=None, **kw):
+        k = self.key(params.shape[0], n_samples, offsets)
+        if k not in self.table:
+            self.tune(params, nebula, n_samples=n_samples, offsets=offsets, **kw)
+        return self.table[k]
+
+    def render(self, params, nebula, n_samples=None, offsets=None, out=None, **kw):
+        rps, sl, pers, grid = self.plan_for(params, nebula, n_samples=n_samples, offsets=offsets,
+                                            **kw)
+        return synth_render_plan(params, nebula, rps, sl, persistent=bool(pers), grid_blocks=grid,
+                                 n_samples=n_samples, offsets=offsets, out=out, **kw)
+
+    def save(self, path: str):
+        with open(path, "w") as f:
+            json.dump({"table": {k: list(v) for k, v in self.table.items()},
+                       "timings_ms": self.timings}, f, indent=1)
+
+    def load(self, path: str):
+        if os.path.exists(path):
+            with open(path) as f:
+                d = json.load(f)
+            self.table.update({k: tuple(v) for k, v in d.get("table", {}).items()})

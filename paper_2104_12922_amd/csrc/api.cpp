@@ -204,13 +204,21 @@ int synth_render_backward(const synth_config* cfg, const float* params, const ui
                                                  rps, (hipStream_t)stream));
 }
 
+size_t synth_mrstft_workspace(int64_t batch, int64_t n_samples, int with_grad) {
+  if (batch < 0 || n_samples <= 0 || n_samples > ((int64_t)1 << 31)) return 0;
+  return synth::mrstft_workspace_bytes(batch, n_samples, with_grad != 0);
+}
+
 int synth_mrstft_loss(const float* x, const float* target, int64_t batch, int64_t n_samples,
-                      double* loss, float* grad_x, void* stream) {
+                      double* loss, float* grad_x, void* workspace, size_t workspace_bytes,
+                      void* stream) {
   if (batch < 0 || n_samples <= 0 || n_samples > ((int64_t)1 << 31)) return SYNTH_EINVAL;
   if (batch == 0) return SYNTH_OK;
-  if (!x || !target || !loss) return SYNTH_EINVAL;
-  if (batch > 0x7FFFFFFF) return SYNTH_EINVAL;
-  return to_status(synth::launch_mrstft(x, target, batch, n_samples, loss, grad_x,
+  if (!x || !target || !loss || !workspace) return SYNTH_EINVAL;
+  if (batch > 65535) return SYNTH_EUNSUPPORTED;
+  if (workspace_bytes < synth::mrstft_workspace_bytes(batch, n_samples, grad_x != nullptr))
+    return SYNTH_ENOMEM;
+  return to_status(synth::launch_mrstft(x, target, batch, n_samples, loss, grad_x, workspace,
                                         (hipStream_t)stream));
 }
 

@@ -24,41 +24,74 @@ __global__ void f32_to_bf16_kernel(const float* __restrict__ x, uint16_t* __rest
     y[i] = f2bf(x[i]);
 }
 
-// sum (and sum of squares) of each column over rows, one thread per column,
-// rows in order: deterministic.
-__global__ void colsum_kernel(const void* __restrict__ x, int x_bf16, int64_t rows, int64_t cols,
-                              int64_t ld, float* __restrict__ sum, float* __restrict__ sumsq) {
-  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= cols) return;
-  double s = 0.0, s2 = 0.0;
-  for (int64_t r = 0; r < rows; ++r) {
-    const float v = x_bf16 ? bf2f(reinterpret_cast<const uint16_t*>(x)[r * ld + c])
-                           : reinterpret_cast<const float*>(x)[r * ld + c];
-    s += v;
-    s2 += (double)v * v;
+// Column reductions use 1024-thread workgroups of 16 columns x 64 row groups:
+// thread (g, c) accumulates rows g, g + 64, ... of column c in float64, then
+// the 64 partial sums are added in a fixed tree order - deterministic.
+constexpr int kRedCols = 16, kRedGroups = 64;
+
+__device__ __forceinline__ double tree_sum(double* red, int c, int g, double v) {
+  red[g * kRedCols + c] = v;
+  __syncthreads();
+  for (int s = kRedGroups / 2; s > 0; s >>= 1) {
+    if (g < s) red[g * kRedCols + c] += red[(g + s) * kRedCols + c];
+    __syncthreads();
   }
-  sum[c] = (float)s;
-  if (sumsq) sumsq[c] = (float)s2;
+  const double r = red[c];
+  __syncthreads();
+  return r;
+}
+
+// sum (and sum of squares) of each column over rows.
+__global__ void __launch_bounds__(1024) colsum_kernel(const void* __restrict__ x, int x_bf16,
+                                                      int64_t rows, int64_t cols, int64_t ld,
+                                                      float* __restrict__ sum,
+                                                      float* __restrict__ sumsq) {
+  __shared__ double red[kRedGroups * kRedCols];
+  const int c = threadIdx.x % kRedCols, g = threadIdx.x / kRedCols;
+  const int64_t col = blockIdx.x * (int64_t)kRedCols + c;
+  double s = 0.0, s2 = 0.0;
+  if (col < cols) {
+    for (int64_t r = g; r < rows; r += kRedGroups) {
+      const float v = x_bf16 ? bf2f(reinterpret_cast<const uint16_t*>(x)[r * ld + col])
+                             : reinterpret_cast<const float*>(x)[r * ld + col];
+      s += v;
+      s2 += (double)v * v;
+    }
+  }
+  s = tree_sum(red, c, g, s);
+  if (sumsq) s2 = tree_sum(red, c, g, s2);
+  if (g == 0 && col < cols) {
+    sum[col] = (float)s;
+    if (sumsq) sumsq[col] = (float)s2;
+  }
 }
 
 // Per-column mean and 1 / sqrt(max(var, min_var)) (population variance), two
-// float64 passes over the rows, one thread per column.
-__global__ void feature_stats_kernel(const float* __restrict__ x, int64_t rows, int64_t cols,
-                                     float min_var, float* __restrict__ mean,
-                                     float* __restrict__ inv_std) {
-  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+// float64 passes over the rows.
+__global__ void __launch_bounds__(1024) feature_stats_kernel(const float* __restrict__ x,
+                                                             int64_t rows, int64_t cols,
+                                                             float min_var,
+                                                             float* __restrict__ mean,
+                                                             float* __restrict__ inv_std) {
+  __shared__ double red[kRedGroups * kRedCols];
+  const int c = threadIdx.x % kRedCols, g = threadIdx.x / kRedCols;
+  const int64_t col = blockIdx.x * (int64_t)kRedCols + c;
   double s = 0.0;
-  for (int64_t r = 0; r < rows; ++r) s += x[r * cols + c];
-  const double mu = s / (double)rows;
+  if (col < cols)
+    for (int64_t r = g; r < rows; r += kRedGroups) s += x[r * cols + col];
+  const double mu = tree_sum(red, c, g, s) / (double)rows;
   double s2 = 0.0;
-  for (int64_t r = 0; r < rows; ++r) {
-    const double d = x[r * cols + c] - mu;
-    s2 += d * d;
+  if (col < cols)
+    for (int64_t r = g; r < rows; r += kRedGroups) {
+      const double d = x[r * cols + col] - mu;
+      s2 += d * d;
+    }
+  s2 = tree_sum(red, c, g, s2);
+  if (g == 0 && col < cols) {
+    const double var = fmax(s2 / (double)rows, (double)min_var);
+    mean[col] = (float)mu;
+    inv_std[col] = (float)(1.0 / sqrt(var));
   }
-  const double var = fmax(s2 / (double)rows, (double)min_var);
-  mean[c] = (float)mu;
-  inv_std[c] = (float)(1.0 / sqrt(var));
 }
 
 // y = bf16((x - mean[col]) * inv_std[col])
@@ -182,16 +215,16 @@ hipError_t launch_f32_to_bf16(const float* x, void* y, int64_t n, hipStream_t s)
 hipError_t launch_colsum(const void* x, int x_bf16, int64_t rows, int64_t cols, int64_t ld,
                          float* sum, float* sumsq, hipStream_t s) {
   if (cols == 0) return hipSuccess;
-  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, s, x,
-                     x_bf16, rows, cols, ld, sum, sumsq);
+  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((cols + kRedCols - 1) / kRedCols)), dim3(1024),
+                     0, s, x, x_bf16, rows, cols, ld, sum, sumsq);
   return hipGetLastError();
 }
 
 hipError_t launch_feature_stats(const float* x, int64_t rows, int64_t cols, float min_var,
                                 float* mean, float* inv_std, hipStream_t s) {
   if (cols == 0) return hipSuccess;
-  hipLaunchKernelGGL(feature_stats_kernel, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, s,
-                     x, rows, cols, min_var, mean, inv_std);
+  hipLaunchKernelGGL(feature_stats_kernel, dim3((unsigned)((cols + kRedCols - 1) / kRedCols)),
+                     dim3(1024), 0, s, x, rows, cols, min_var, mean, inv_std);
   return hipGetLastError();
 }
 

@@ -1,21 +1,27 @@
 // Multi-resolution log-magnitude STFT L1 loss and its gradient (float32 FFT).
 //
 // The paper scores sounds with a multi-scale spectrogram distance over several
-// FFT sizes and prefers L1 (Section 4.3).  Per voice:
+// FFT sizes and prefers L1 (Section 4, distance evaluation).  Per voice:
 //   loss = sum over n in (512, 1024, 2048), hop n/4, of
 //          mean_{frame t, bin k <= n/2} |log(|X_tk| + 1e-5) - log(|T_tk| + 1e-5)|
 // with X, T the periodic-Hann STFTs (no padding) of the render x and target.
 //
-// One 1024-thread workgroup per voice walks the voice in blocks of 512
-// samples.  For every resolution a block is one group of S = 2048/n frames
-// (S * hop = 512), so each thread owns exactly one radix-2 butterfly per FFT
-// stage.  Render and target frames get separate FFTs.  The gradient
-// w.r.t. x of a frame is w(m) Re(sum_k G_k e^{2 pi i k m / n}) with
-// G_k = sign(d_k) X_k / (|X_k| (|X_k| + eps)) / (F (n/2 + 1)); it is formed by
-// an inverse FFT of the Hermitian extension of G and overlap-added into an LDS
-// ring covering [block, block + 2560).  After a block no later frame reaches
-// its first 512 samples, which are then written once: no atomics, no
-// read-modify-write of global memory, bitwise deterministic.
+// Frames are independent jobs.  Kernel 1 (512 threads per workgroup, grid =
+// voices x (frame chunks of every resolution)) takes 16 frames of one
+// resolution per workgroup.  A real frame of n samples is transformed as a
+// complex sequence of n/2 points (even samples real, odd imaginary) by a
+// Stockham autosort FFT - radix-4 passes and one radix-2 pass when log2(n/2)
+// is odd - with one radix-4 butterfly per thread and pass, twiddles from an
+// LDS table, then split into the n/2 + 1 bins of the real spectrum.  Render
+// and target frames get separate FFTs (a shared complex FFT would leak the
+// louder signal's rounding noise into the quieter one's spectrum).  For the
+// gradient, G_k = sign(d_k) X_k / (|X_k| (|X_k| + eps)) / (F (n/2 + 1)) is
+// extended to a Hermitian spectrum H (H_0 = 2 Re G_0, H_{n/2} = 2 Re G_{n/2}),
+// inverted by the same half-size complex FFT, and the frame's gradient
+// 0.5 w(m) h(m) is written to a workspace row of its own.  Kernel 2 adds,
+// for every sample, the rows of the frames that cover it in a fixed order
+// (resolution, then frame), and sums the per-workgroup loss partials in a
+// fixed order: bitwise deterministic, no atomics.
 #include <math.h>
 
 #include "synth_internal.h"
@@ -23,189 +29,323 @@
 namespace synth {
 namespace {
 
-constexpr int kThreads = 1024;
+constexpr int kThreads = 512;
 constexpr int kMaxN = 2048;
-constexpr int kBlock = 512;                 // output samples finalised per step
-constexpr int kRing = kBlock + kMaxN;       // 2560
+constexpr int kFramesPerBlock = 16;
 constexpr float kEps = 1e-5f;
 
 struct SpecShared {
-  float2 buf[2][kMaxN];                     // FFT ping-pong
-  float ring[kRing];                        // gradient overlap-add window
-  double red[kThreads / 64];                // per-wave loss partial sums
+  float2 tw[kMaxN];            // tw[k] = exp(-2 pi i k / n)
+  float win[kMaxN];            // periodic Hann window
+  float2 buf[2][kMaxN];        // FFT ping-pong: (512 / (n/8)) transforms of n/2 points
+  double red[kThreads / 64];
 };
 
-// Stockham radix-2 autosort FFT of S independent length-n sequences stored
-// back to back in buf[src] (S * n == 2048).  dir = -1 forward, +1 inverse
-// (unnormalised).  Thread t owns butterfly t of the stage.  Returns the index
-// of the buffer holding the result.
-__device__ int fft_group(SpecShared& sh, int src, int n, int logn, float dir) {
-  const int t = threadIdx.x;
-  const int half = n >> 1;
-  const int slot = t / half;
-  const int b = t - slot * half;
-  int len = n;       // current sub-transform length
-  int stride = 1;    // number of interleaved sub-transforms
-  for (int st = 0; st < logn; ++st) {
-    const int m = len >> 1;
-    const int p = b / stride;
-    const int qq = b - p * stride;
-    const float2* x = sh.buf[src] + slot * n;
-    float2* y = sh.buf[src ^ 1] + slot * n;
-    const float2 a = x[qq + stride * p];
-    const float2 c = x[qq + stride * (p + m)];
-    float sn, cs;
-    sincospif(dir * 2.0f * (float)p / (float)len, &sn, &cs);
-    const float2 d = make_float2(a.x - c.x, a.y - c.y);
-    y[qq + stride * (2 * p)] = make_float2(a.x + c.x, a.y + c.y);
-    y[qq + stride * (2 * p + 1)] = make_float2(d.x * cs - d.y * sn, d.x * sn + d.y * cs);
-    src ^= 1;
-    len = m;
-    stride <<= 1;
-    __syncthreads();
+struct MrArgs {
+  const float* x;
+  const float* t;
+  int64_t n;                   // samples per voice
+  int64_t batch;
+  int F[3];                    // frames per resolution
+  int chunk_base[4];           // first block index of each resolution's chunks
+  int64_t wbase[3];            // workspace float offset of each resolution's rows
+  double scale[3];             // 1 / (F (n/2 + 1))
+  float* wgrad;                // frame gradient rows (null: loss only)
+  double* partial;             // [batch][chunk_base[3]] loss partial sums
+  float* grad;                 // output gradient (null: loss only)
+  double* loss;
+};
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// One Stockham pass of radix R on the transform of Nc points whose butterfly
+// j (0 <= j < Nc / R) this thread owns: inputs v[r] = src[j + r Nc / R], the
+// twiddles exp(dir 2 pi i (j mod Ns) r / (Ns R)), the R-point DFT, outputs to
+// dst[(j / Ns) Ns R + (j mod Ns) + r Ns].  tw holds exp(-2 pi i k / (2 Nc)).
+template <int R>
+__device__ __forceinline__ void butterfly(float2 (&v)[4], int j, int Ns, int Nc, float dir,
+                                          const float2* tw) {
+  const int k = j % Ns;
+  const int step = Nc / (Ns * R);
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    const int idx = (k * r * step) % Nc;          // exp(-2 pi i idx / Nc) = tw[2 idx]
+    float2 w = tw[2 * idx];
+    if (dir > 0.0f) w.y = -w.y;
+    v[r] = cmul(v[r], w);
   }
-  return src;
+  if constexpr (R == 4) {
+    const float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    const float2 t2 = cadd(v[1], v[3]);
+    float2 t3 = csub(v[1], v[3]);
+    t3 = dir < 0.0f ? make_float2(t3.y, -t3.x) : make_float2(-t3.y, t3.x);   // -i or +i
+    v[0] = cadd(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[2] = csub(t0, t2);
+    v[3] = csub(t1, t3);
+  } else {
+    const float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
 }
 
-__device__ __forceinline__ float hann_f(int m, int n) {
-  return 0.5f - 0.5f * cospif(2.0f * (float)m / (float)n);
-}
-
-__global__ void __launch_bounds__(kThreads) mrstft_kernel(const float* __restrict__ x,
-                                                          const float* __restrict__ target,
-                                                          int64_t N, double* __restrict__ loss,
-                                                          float* __restrict__ grad) {
-  __shared__ SpecShared sh;
-  const int t = threadIdx.x;
-  const int64_t b = blockIdx.x;
-  const float* xv = x + b * N;
-  const float* tv = target + b * N;
-  float* gv = grad ? grad + b * N : nullptr;
-  double acc = 0.0;                          // this thread's share of the loss
-
-  int F[3], logn[3];
-  double scale[3];
-  for (int r = 0; r < 3; ++r) {
-    const int n = 512 << r;
-    logn[r] = 9 + r;
-    F[r] = N < n ? 0 : (int)((N - n) / (n / 4)) + 1;
-    scale[r] = F[r] > 0 ? 1.0 / ((double)F[r] * (double)(n / 2 + 1)) : 0.0;
-  }
-  if (gv)
-    for (int i = t; i < kRing; i += kThreads) sh.ring[i] = 0.0f;
-  __syncthreads();
-
-  const int64_t nblocks = (N + kBlock - 1) / kBlock;
-  for (int64_t blk = 0; blk < nblocks; ++blk) {
-    const int64_t base = blk * kBlock;
-    for (int r = 0; r < 3; ++r) {
-      const int n = 512 << r;
-      const int hop = n / 4;
-      const int S = kMaxN / n;
-      const int64_t f0 = blk * S;            // first frame of this group
-      if (f0 >= F[r]) continue;              // uniform across the workgroup
-      // bins owned by this thread: k = t mod (n/2) of its frame slot, plus
-      // k = n/2 for the thread with k == 0
-      const int half = n >> 1;
-      const int slot = t / half;
-      const int k = t - slot * half;
-      const int64_t fr = f0 + slot;
-      const bool live = fr < F[r];
-      // Two real-input FFTs, render then target, each with its own float32
-      // noise floor (sharing one complex FFT would leak the louder signal's
-      // rounding noise into the quieter one's spectrum).
-      float2 Xa, Xb, Ta, Tb;
-      int res = 0;
-      for (int which = 0; which < 2; ++which) {
-        const float* sig = which == 0 ? xv : tv;
-        for (int e = t; e < kMaxN; e += kThreads) {
-          const int sl = e / n;
-          const int m = e - sl * n;
-          const int64_t frm = f0 + sl;
-          float v = 0.0f;
-          if (frm < F[r]) v = hann_f(m, n) * sig[frm * hop + m];
-          sh.buf[0][e] = make_float2(v, 0.0f);
-        }
-        __syncthreads();
-        res = fft_group(sh, 0, n, logn[r], -1.0f);
-        const float2* Z = sh.buf[res] + slot * n;
-        const float2 za = Z[k];
-        const float2 zb = k == 0 ? Z[half] : make_float2(0.f, 0.f);
-        if (which == 0) { Xa = za; Xb = zb; } else { Ta = za; Tb = zb; }
-        __syncthreads();                     // buffers are reused
-      }
-      float2 G0 = make_float2(0.f, 0.f), G1 = make_float2(0.f, 0.f);
-      for (int pass = 0; pass < (k == 0 ? 2 : 1); ++pass) {
-        const float2 X = pass == 0 ? Xa : Xb;
-        const float2 T = pass == 0 ? Ta : Tb;
-        const float ax = sqrtf(X.x * X.x + X.y * X.y);
-        const float at = sqrtf(T.x * T.x + T.y * T.y);
-        const float d = logf(ax + kEps) - logf(at + kEps);
-        if (live) acc += scale[r] * (double)fabsf(d);
-        float2 G = make_float2(0.f, 0.f);
-        if (live && ax > 0.0f && d != 0.0f) {
-          const float gm = copysignf((float)scale[r], d) / ((ax + kEps) * ax);
-          G = make_float2(gm * X.x, gm * X.y);
-        }
-        if (pass == 0) G0 = G; else G1 = G;
-      }
-      if (gv) {
-        // Hermitian extension H of G (H_0 = 2 Re G_0, H_{n/2} = 2 Re G_{n/2},
-        // H_{n-k} = conj G_k)
-        float2* H = sh.buf[0] + slot * n;
-        if (k == 0) {
-          H[0] = make_float2(2.0f * G0.x, 0.0f);
-          H[half] = make_float2(2.0f * G1.x, 0.0f);
-        } else {
-          H[k] = G0;
-          H[n - k] = make_float2(G0.x, -G0.y);
-        }
-        __syncthreads();
-        const int ri = fft_group(sh, 0, n, logn[r], 1.0f);
-        // frame gradient 0.5 w(m) Re(h(m)), overlap-added in frame order
-        for (int s = 0; s < S; ++s) {
-          if (f0 + s < F[r]) {
-            const int off = s * hop;          // ring position of frame s's first sample
-            for (int m = t; m < n; m += kThreads)
-              sh.ring[off + m] += 0.5f * hann_f(m, n) * sh.buf[ri][s * n + m].x;
-          }
-          __syncthreads();
+// Complex FFT of Nc points held by Nc / 4 threads (thread j of the transform),
+// starting from v (the first pass's inputs v[r] = z[j + r Nc / 4]), working in
+// base[2] (each Nc points long).  All threads of the workgroup call it (it
+// contains barriers); `active` marks the threads that own a butterfly.
+// Returns the buffer index holding the natural-order result.
+__device__ int fft_pass_all(float2 (&v)[4], int j, int Nc, float dir, const float2* tw,
+                            float2* base0, float2* base1, bool active) {
+  int Ns = 1;
+  int cur = 0;                                     // buffer the next pass writes
+  bool first = true;
+  int rem = Nc;
+  while (rem > 1) {
+    const int R = (rem % 4 == 0) ? 4 : 2;
+    float2* dst = cur == 0 ? base0 : base1;
+    const float2* src = cur == 0 ? base1 : base0;
+    if (active) {
+      if (R == 4) {
+        if (!first)
+          for (int r = 0; r < 4; ++r) v[r] = src[j + r * (Nc / 4)];
+        butterfly<4>(v, j, Ns, Nc, dir, tw);
+        const int d = (j / Ns) * Ns * 4 + (j % Ns);
+        for (int r = 0; r < 4; ++r) dst[d + r * Ns] = v[r];
+      } else {
+        // radix 2: Nc / 2 butterflies, two per thread (j and j + Nc / 4)
+        for (int h = 0; h < 2; ++h) {
+          const int jj = j + h * (Nc / 4);
+          float2 u[4];
+          u[0] = first ? v[h * 2] : src[jj];
+          u[1] = first ? v[h * 2 + 1] : src[jj + Nc / 2];
+          butterfly<2>(u, jj, Ns, Nc, dir, tw);
+          const int d = (jj / Ns) * Ns * 2 + (jj % Ns);
+          dst[d] = u[0];
+          dst[d + Ns] = u[1];
         }
       }
     }
-    if (gv) {
-      // samples [base, base + 512) are final: write, then slide the ring
-      for (int i = t; i < kBlock; i += kThreads)
-        if (base + i < N) gv[base + i] = sh.ring[i];
-      __syncthreads();
-      float carry[3];
-      int nc = 0;
-      for (int i = t; i < kRing - kBlock; i += kThreads) carry[nc++] = sh.ring[i + kBlock];
-      __syncthreads();
-      nc = 0;
-      for (int i = t; i < kRing - kBlock; i += kThreads) sh.ring[i] = carry[nc++];
-      for (int i = kRing - kBlock + t; i < kRing; i += kThreads) sh.ring[i] = 0.0f;
+    __syncthreads();
+    first = false;
+    Ns *= R;
+    rem /= R;
+    cur ^= 1;
+  }
+  return cur ^ 1;
+}
+
+__global__ void __launch_bounds__(kThreads) mrstft_frames_kernel(const MrArgs a) {
+  __shared__ SpecShared sh;
+  const int tid = threadIdx.x;
+  const int64_t b = blockIdx.y;
+  const int blk = blockIdx.x;
+  const int r = blk < a.chunk_base[1] ? 0 : (blk < a.chunk_base[2] ? 1 : 2);
+  const int chunk = blk - a.chunk_base[r];
+  const int n = 512 << r;
+  const int Nc = n / 2;                 // complex points per transform
+  const int tpt = Nc / 4;               // threads per transform
+  const int ntr = kThreads / tpt;       // transforms in flight: 8, 4, 2
+  const int fpi = ntr / 2;              // frames per iteration: 4, 2, 1
+  const int hop = n / 4;
+  const int F = a.F[r];
+  const bool want_grad = a.wgrad != nullptr;
+
+  for (int k = tid; k < n; k += kThreads) {
+    float s, c;
+    sincospif(2.0f * (float)k / (float)n, &s, &c);
+    sh.tw[k] = make_float2(c, -s);
+    sh.win[k] = 0.5f - 0.5f * cospif(2.0f * (float)k / (float)n);
+  }
+  __syncthreads();
+
+  const int tr = tid / tpt;             // transform of this thread
+  const int j = tid - tr * tpt;         // butterfly index within the transform
+  const int slot = tr >> 1;             // frame slot of the iteration
+  const int sig = tr & 1;               // 0: render, 1: target
+  const float* src = (sig ? a.t : a.x) + b * a.n;
+  const double scale = a.scale[r];
+  double acc = 0.0;
+
+  const int f_begin = chunk * kFramesPerBlock;
+  const int f_end = min(F, f_begin + kFramesPerBlock);
+  for (int f0 = f_begin; f0 < f_end; f0 += fpi) {
+    const int f = f0 + slot;
+    const bool live = f < f_end;
+    // ---- forward transforms: z[m] = w x[2m] + i w x[2m+1] ----
+    float2 v[4];
+    const float* fr = src + (int64_t)f * hop;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = j + q * tpt;
+      v[q] = live ? make_float2(sh.win[2 * m] * fr[2 * m], sh.win[2 * m + 1] * fr[2 * m + 1])
+                  : make_float2(0.f, 0.f);
+    }
+    float2* b0 = sh.buf[0] + tr * Nc;
+    float2* b1 = sh.buf[1] + tr * Nc;
+    const int zb = fft_pass_all(v, j, Nc, -1.0f, sh.tw, b0, b1, true);
+    // ---- bins: frame slot's 2 * tpt threads take bins k = u, u + 2 tpt, ... ----
+    const float2* Zx = sh.buf[zb] + (2 * slot) * Nc;
+    const float2* Zt = sh.buf[zb] + (2 * slot + 1) * Nc;
+    float2* Hs = sh.buf[zb ^ 1] + slot * (Nc + 4);   // Hermitian half H_0 .. H_Nc
+    const int u = tid - slot * 2 * tpt;
+    for (int k = u; k <= Nc; k += 2 * tpt) {
+      const float2 tw = k < Nc ? sh.tw[k] : make_float2(-1.0f, 0.0f);
+      const int kc = k == Nc ? 0 : k, km = k == 0 ? 0 : Nc - k;   // Z_Nc = Z_0
+      float2 X, T;
+      {
+        const float2 zk = Zx[kc], zc = cconj(Zx[km]);
+        const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+        const float2 D = csub(zk, zc);
+        const float2 O = make_float2(0.5f * D.y, -0.5f * D.x);     // -i D / 2
+        X = cadd(E, cmul(tw, O));
+      }
+      {
+        const float2 zk = Zt[kc], zc = cconj(Zt[km]);
+        const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+        const float2 D = csub(zk, zc);
+        const float2 O = make_float2(0.5f * D.y, -0.5f * D.x);
+        T = cadd(E, cmul(tw, O));
+      }
+      const float ax = sqrtf(X.x * X.x + X.y * X.y);
+      const float at = sqrtf(T.x * T.x + T.y * T.y);
+      const float d = logf(ax + kEps) - logf(at + kEps);
+      if (live) acc += scale * (double)fabsf(d);
+      if (want_grad) {
+        float2 G = make_float2(0.f, 0.f);
+        if (live && ax > 0.0f && d != 0.0f) {
+          const float gm = copysignf((float)scale, d) / ((ax + kEps) * ax);
+          G = make_float2(gm * X.x, gm * X.y);
+        }
+        if (k == 0 || k == Nc) G = make_float2(2.0f * G.x, 0.0f);
+        Hs[k] = G;
+      }
+    }
+    __syncthreads();
+    if (want_grad) {
+      // ---- inverse: Y_k = (H_k + conj H_{Nc-k}) + i conj(tw_k) (H_k - conj H_{Nc-k}) ----
+      const bool inv_active = sig == 0;             // one inverse per frame
+      float2 y[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = j + q * tpt;
+        const float2 hk = Hs[k], hc = cconj(Hs[Nc - k]);
+        const float2 A = cadd(hk, hc), D = csub(hk, hc);
+        const float2 c = cconj(sh.tw[k]);
+        const float2 cd = cmul(c, D);
+        y[q] = make_float2(A.x - cd.y, A.y + cd.x);   // A + i (c D)
+      }
+      __syncthreads();                              // H read before buffers are reused
+      float2* c0 = sh.buf[0] + slot * 2 * Nc;       // the frame slot's two transform areas
+      float2* c1 = sh.buf[1] + slot * 2 * Nc;
+      const int yb = fft_pass_all(y, j, Nc, 1.0f, sh.tw, c0, c1, inv_active);
+      if (live && inv_active) {
+        const float2* Y = sh.buf[yb] + slot * 2 * Nc;
+        float* out = a.wgrad + a.wbase[r] + ((int64_t)b * F + f) * n;
+        for (int m = j; m < Nc; m += tpt) {
+          const float2 yy = Y[m];
+          out[2 * m] = 0.5f * sh.win[2 * m] * yy.x;
+          out[2 * m + 1] = 0.5f * sh.win[2 * m + 1] * yy.y;
+        }
+      }
       __syncthreads();
     }
   }
   // fixed-order reduction of the per-thread loss shares
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o);
-  if ((t & 63) == 0) sh.red[t >> 6] = acc;
+  if ((tid & 63) == 0) sh.red[tid >> 6] = acc;
   __syncthreads();
-  if (t == 0) {
+  if (tid == 0) {
     double s = 0.0;
     for (int w = 0; w < kThreads / 64; ++w) s += sh.red[w];
-    loss[b] = s;
+    a.partial[b * a.chunk_base[3] + blk] = s;
   }
+}
+
+// grad[b][i] = sum over resolutions, then frames f covering i, of the frame
+// row at i - f hop; block x == 0 also sums voice b's loss partials.
+__global__ void __launch_bounds__(256) mrstft_combine_kernel(const MrArgs a) {
+  const int64_t b = blockIdx.y;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int c = 0; c < a.chunk_base[3]; ++c) s += a.partial[b * a.chunk_base[3] + c];
+    a.loss[b] = s;
+  }
+  if (!a.grad) return;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  float g = 0.0f;
+  for (int r = 0; r < 3; ++r) {
+    const int n = 512 << r, hop = n / 4, F = a.F[r];
+    if (F == 0) continue;
+    int64_t fhi = i / hop;
+    if (fhi > F - 1) fhi = F - 1;
+    int64_t flo = i - n + 1 <= 0 ? 0 : (i - n + 1 + hop - 1) / hop;
+    const float* rows = a.wgrad + a.wbase[r] + b * (int64_t)F * n;
+    for (int64_t f = flo; f <= fhi; ++f) g += rows[f * n + (i - f * hop)];
+  }
+  a.grad[b * a.n + i] = g;
+}
+
+void plan(int64_t batch, int64_t n_samples, MrArgs& a, size_t& partial_bytes, size_t& wgrad_floats) {
+  int cb = 0;
+  int64_t wb = 0;
+  for (int r = 0; r < 3; ++r) {
+    const int n = 512 << r;
+    const int64_t F = n_samples < n ? 0 : (n_samples - n) / (n / 4) + 1;
+    a.F[r] = (int)F;
+    a.chunk_base[r] = cb;
+    cb += (int)((F + kFramesPerBlock - 1) / kFramesPerBlock);
+    a.wbase[r] = wb;
+    wb += batch * F * n;
+    a.scale[r] = F > 0 ? 1.0 / ((double)F * (double)(n / 2 + 1)) : 0.0;
+  }
+  a.chunk_base[3] = cb;
+  partial_bytes = (size_t)batch * (size_t)(cb > 0 ? cb : 1) * sizeof(double);
+  wgrad_floats = (size_t)wb;
 }
 
 }  // namespace
 
+size_t mrstft_workspace_bytes(int64_t batch, int64_t n_samples, bool with_grad) {
+  MrArgs a = {};
+  size_t pb, wf;
+  plan(batch, n_samples, a, pb, wf);
+  pb = (pb + 255) & ~(size_t)255;
+  return pb + (with_grad ? wf * sizeof(float) : 0);
+}
+
 hipError_t launch_mrstft(const float* x, const float* target, int64_t batch, int64_t n_samples,
-                         double* loss, float* grad, hipStream_t s) {
+                         double* loss, float* grad, void* workspace, hipStream_t s) {
   if (batch == 0) return hipSuccess;
-  hipLaunchKernelGGL(mrstft_kernel, dim3((unsigned)batch), dim3(kThreads), 0, s, x, target,
-                     n_samples, loss, grad);
+  MrArgs a = {};
+  size_t pb, wf;
+  plan(batch, n_samples, a, pb, wf);
+  pb = (pb + 255) & ~(size_t)255;
+  a.x = x;
+  a.t = target;
+  a.n = n_samples;
+  a.batch = batch;
+  a.partial = reinterpret_cast<double*>(workspace);
+  a.wgrad = grad ? reinterpret_cast<float*>(reinterpret_cast<char*>(workspace) + pb) : nullptr;
+  a.grad = grad;
+  a.loss = loss;
+  if (batch > 65535) return hipErrorInvalidValue;
+  if (a.chunk_base[3] > 0) {
+    hipLaunchKernelGGL(mrstft_frames_kernel, dim3((unsigned)a.chunk_base[3], (unsigned)batch),
+                       dim3(kThreads), 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  // (with no complete frame at any resolution the combine kernel writes
+  // loss 0 and a zero gradient)
+  const int64_t gx = grad ? (n_samples + 255) / 256 : 1;
+  hipLaunchKernelGGL(mrstft_combine_kernel, dim3((unsigned)gx, (unsigned)batch), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -111,7 +111,8 @@ int64_t adjoint_max_chunks();
 hipError_t launch_render_backward(const RenderArgs& a, const float* grad_audio, double* ws,
                                   float* grad_params, int runs_per_segment, hipStream_t s);
 
+size_t mrstft_workspace_bytes(int64_t batch, int64_t n_samples, bool with_grad);
 hipError_t launch_mrstft(const float* x, const float* target, int64_t batch, int64_t n_samples,
-                         double* loss, float* grad, hipStream_t s);
+                         double* loss, float* grad, void* workspace, hipStream_t s);
 
 }  // namespace synth

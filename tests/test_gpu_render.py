@@ -157,6 +157,23 @@ def test_launch_plans_bit_identical(synth, nebula_table):
         assert np.abs(y.cpu().numpy() - ref).max() <= TOL, rps
 
 
+def test_autotuner_picks_a_plan_and_renders_with_it(synth):
+    from paper_2104_12922_amd.autotune import RenderTuner
+    wl = W.ragged_batch(600)
+    tab = wl.nebula.table()
+    offs = torch.from_numpy(wl.offsets).cuda()
+    u = synth.synth_sample_params(wl.seed, 0, wl.batch)
+    tuner = RenderTuner(reps=1)
+    plan, times = tuner.tune(u, tab, offsets=offs, noise_seed=wl.key_noise())
+    assert plan in times and len(times) >= 2
+    y = tuner.render(u, tab, offsets=offs, noise_seed=wl.key_noise())
+    z = synth.synth_render_plan(u, tab, plan[0], plan[1], bool(plan[2]), plan[3], offsets=offs,
+                                noise_seed=wl.key_noise())
+    d = synth.synth_render(u, tab, offsets=offs, noise_seed=wl.key_noise())
+    assert torch.equal(y, z)
+    assert float((y - d).abs().max()) <= 1e-5
+
+
 def test_batch_independence_and_determinism(synth, nebula_table):
     u = synth.synth_sample_params(0, 0, 64)
     a = synth.synth_render(u, nebula_table, n_samples=50000)
