@@ -135,7 +135,7 @@ def bench_learned(args):
         mean, inv_std = Lr.feature_stats(feat)
         x = Lr.standardize(feat, mean, inv_std)
         torch.cuda.synchronize()
-        n_ev = max(3, min(args.steps, 10))
+        n_ev = max(1, min(args.steps, 10))
         e_r, e_l, e_m = _events(n_ev), _events(n_ev), _events(n_ev)
         t_step = []
         for i in range(args.warmup + args.steps):
@@ -197,7 +197,7 @@ def bench_grad(args):
         ws = S.synth_render_backward_workspace(tab, B, N)
         ws_loss = S.synth_mrstft_workspace(B, N, grad=True)
         gx = torch.empty(B, N, device="cuda")
-        n_ev = max(3, min(args.steps, 10))
+        n_ev = max(1, min(args.steps, 10))
         e = [_events(n_ev) for _ in range(3)]
         tt = []
         for i in range(args.warmup + args.steps):

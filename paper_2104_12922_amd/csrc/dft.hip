@@ -51,92 +51,65 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
-__global__ void __launch_bounds__(kThreads) dft_power_kernel(const float* __restrict__ audio,
-                                                        const int64_t* __restrict__ offsets,
-                                                        int64_t n_uniform, int64_t rows,
-                                                        const uint16_t* __restrict__ basis,
-                                                        uint16_t* __restrict__ power,
-                                                        int64_t ldp) {
-  __shared__ __align__(16) uint16_t As[2][kBM][kLDK];
-  __shared__ __align__(16) uint16_t Bs[2][kBN][kLDK];
+// The k-loop and epilogue of one tile.  The four frame rows this thread
+// stages start at abase[q] with lim[q] samples left in their voice; past that
+// the frame reads as 0.  Loads are unconditional (addresses of rows past the
+// voice's end are redirected to `audio`) and the mask is applied when the
+// registers are written to LDS, so nothing waits on a load before the MFMAs.
+// VEC: every voice is 16-byte aligned with a length divisible by 4, so one
+// float4 is wholly inside or wholly outside; otherwise four scalar loads.
+template <bool VEC>
+__device__ __forceinline__ void dft_tile(const float* __restrict__ audio, const float* const (&abase)[4],
+                                         const int64_t (&lim)[4], const uint16_t* bsrc0,
+                                         const uint16_t* bsrc1, uint16_t (*As)[kBM][kLDK],
+                                         uint16_t (*Bs)[kBN][kLDK], int64_t m0, int64_t n0,
+                                         int64_t rows, uint16_t* __restrict__ power, int64_t ldp) {
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wave = t >> 6;
   const int wm = wave >> 2, wn = wave & 3;
-
-  // XCD-aware tile order: workgroup b runs on XCD b % 8; give each XCD a
-  // contiguous range of tiles (N-tiles of one M row are consecutive).
-  constexpr int64_t tiles_n = kN / kBN;   // 8
-  const int64_t nblk = gridDim.x;
-  const int64_t b = blockIdx.x;
-  const int64_t per = nblk / kXcds, extra = nblk % kXcds;
-  const int64_t x = b % kXcds, i = b / kXcds;
-  const int64_t tile = x * per + (x < extra ? x : extra) + i;
-  const int64_t m0 = (tile / tiles_n) * kBM, n0 = (tile % tiles_n) * kBN;
-
-  // A staging: 8 threads per row (one float4 each), 64 rows per pass, 4
-  // passes.  The 256 rows of the tile are 4 whole voices (64 frames each):
-  // pass p reads frame a_r of voice m0 / 64 + p.
   const int a_c = (t & 7) * 4;
   const int a_r = t >> 3;
-  const int64_t batch = rows >> 6;
-  int64_t vstart[4], vlen[4];
-  bool vvec[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t v = (m0 >> 6) + q;
-    vstart[q] = 0;
-    vlen[q] = 0;
-    if (v < batch) {
-      if (offsets) {
-        vstart[q] = offsets[v];
-        vlen[q] = offsets[v + 1] - vstart[q];
-      } else {
-        vstart[q] = v * n_uniform;
-        vlen[q] = n_uniform;
-      }
-    }
-    vvec[q] = ((reinterpret_cast<uintptr_t>(audio + vstart[q]) & 15u) == 0);
-  }
-  const int pos = a_r * 2756;          // frame start (hop 2756)
-  // B staging: 4 threads per row (16 bytes each), 128 rows per pass, 2 passes.
   const int b_c = (t & 3) * 8;
   const int b_r = t >> 2;
 
-  float4 ra[4];
-  uint4 rb[2];
+  // prefetch registers: named scalars so that they stay in VGPRs
+  float4 ra0, ra1, ra2, ra3;
+  uint4 rb0, rb1;
 
-  auto load = [&](int ks) {
-    const int k0 = ks * kBK + a_c;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t av = vlen[q] - pos - k0;          // samples left in the voice
-      const float* src = audio + vstart[q] + pos + k0;
-      if (vvec[q] && av >= 4) {
-        ra[q] = *reinterpret_cast<const float4*>(src);
-      } else {
-        ra[q].x = av > 0 ? src[0] : 0.0f;
-        ra[q].y = av > 1 ? src[1] : 0.0f;
-        ra[q].z = av > 2 ? src[2] : 0.0f;
-        ra[q].w = av > 3 ? src[3] : 0.0f;
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < 2; ++p)
-      rb[p] = *reinterpret_cast<const uint4*>(basis + (n0 + p * 128 + b_r) * (int64_t)kN +
-                                              ks * kBK + b_c);
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      uint2 w;
-      w.x = pack_bf16(ra[q].x, ra[q].y);
-      w.y = pack_bf16(ra[q].z, ra[q].w);
-      *reinterpret_cast<uint2*>(&As[buf][q * 64 + a_r][a_c]) = w;
-    }
-#pragma unroll
-    for (int p = 0; p < 2; ++p) *reinterpret_cast<uint4*>(&Bs[buf][p * 128 + b_r][b_c]) = rb[p];
-  };
+#define DFT_LD1(RA, Q, K0)                                                      \
+  if constexpr (VEC) {                                                          \
+    const float* p_ = (K0) < lim[Q] ? abase[Q] + (K0) : audio;                  \
+    RA = *reinterpret_cast<const float4*>(p_);                                  \
+  } else {                                                                      \
+    RA.x = *((K0) + 0 < lim[Q] ? abase[Q] + (K0) + 0 : audio);                  \
+    RA.y = *((K0) + 1 < lim[Q] ? abase[Q] + (K0) + 1 : audio);                  \
+    RA.z = *((K0) + 2 < lim[Q] ? abase[Q] + (K0) + 2 : audio);                  \
+    RA.w = *((K0) + 3 < lim[Q] ? abase[Q] + (K0) + 3 : audio);                  \
+  }
+#define DFT_LOAD(KS)                                                            \
+  {                                                                             \
+    const int k0 = (KS) * kBK + a_c;                                            \
+    DFT_LD1(ra0, 0, k0) DFT_LD1(ra1, 1, k0) DFT_LD1(ra2, 2, k0)                 \
+    DFT_LD1(ra3, 3, k0)                                                         \
+    rb0 = *reinterpret_cast<const uint4*>(bsrc0 + (KS) * kBK);                  \
+    rb1 = *reinterpret_cast<const uint4*>(bsrc1 + (KS) * kBK);                  \
+  }
+#define DFT_ST1(RA, Q, K0, BUF)                                                 \
+  {                                                                             \
+    uint2 w_;                                                                   \
+    w_.x = pack_bf16((K0) + 0 < lim[Q] ? RA.x : 0.0f, (K0) + 1 < lim[Q] ? RA.y : 0.0f); \
+    w_.y = pack_bf16((K0) + 2 < lim[Q] ? RA.z : 0.0f, (K0) + 3 < lim[Q] ? RA.w : 0.0f); \
+    *reinterpret_cast<uint2*>(&As[BUF][(Q) * 64 + a_r][a_c]) = w_;              \
+  }
+#define DFT_STORE(KS, BUF)                                                      \
+  {                                                                             \
+    const int k0 = (KS) * kBK + a_c;                                            \
+    DFT_ST1(ra0, 0, k0, BUF) DFT_ST1(ra1, 1, k0, BUF) DFT_ST1(ra2, 2, k0, BUF)  \
+    DFT_ST1(ra3, 3, k0, BUF)                                                    \
+    *reinterpret_cast<uint4*>(&Bs[BUF][b_r][b_c]) = rb0;                        \
+    *reinterpret_cast<uint4*>(&Bs[BUF][128 + b_r][b_c]) = rb1;                  \
+  }
 
   f32x16 acc[4][2];
 #pragma unroll
@@ -146,12 +119,14 @@ __global__ void __launch_bounds__(kThreads) dft_power_kernel(const float* __rest
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[ii][j][v] = 0.0f;
 
-  load(0);
-  store(0);
+  DFT_LOAD(0)
+  DFT_STORE(0, 0)
   __syncthreads();
   for (int ks = 0; ks < kKSteps; ++ks) {
     const int buf = ks & 1;
-    if (ks + 1 < kKSteps) load(ks + 1);
+    const bool more = ks + 1 < kKSteps;
+    if (more) DFT_LOAD(ks + 1)
+    __builtin_amdgcn_sched_barrier(0);           // issue the prefetch before the MFMAs
 #pragma unroll
     for (int kk = 0; kk < kBK; kk += 16) {
       const int kq = kk + 8 * (lane >> 5);
@@ -168,9 +143,14 @@ __global__ void __launch_bounds__(kThreads) dft_power_kernel(const float* __rest
         for (int j = 0; j < 2; ++j)
           acc[ii][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[ii], bf[j], acc[ii][j], 0, 0, 0);
     }
-    if (ks + 1 < kKSteps) store(buf ^ 1);
+    __builtin_amdgcn_sched_barrier(0);           // wait for the prefetch only after them
+    if (more) DFT_STORE(ks + 1, buf ^ 1)
     __syncthreads();
   }
+#undef DFT_LD1
+#undef DFT_LOAD
+#undef DFT_ST1
+#undef DFT_STORE
 
   // Epilogue: (Re, Im) of a bin sit in adjacent columns = adjacent lanes.
   // Column pair (0, 1) holds the real bins 0 and 1024.
@@ -195,6 +175,63 @@ __global__ void __launch_bounds__(kThreads) dft_power_kernel(const float* __rest
         }
       }
     }
+}
+
+__global__ void __launch_bounds__(kThreads) dft_power_kernel(const float* __restrict__ audio,
+                                                        const int64_t* __restrict__ offsets,
+                                                        int64_t n_uniform, int64_t rows,
+                                                        const uint16_t* __restrict__ basis,
+                                                        uint16_t* __restrict__ power,
+                                                        int64_t ldp) {
+  __shared__ __align__(16) uint16_t As[2][kBM][kLDK];
+  __shared__ __align__(16) uint16_t Bs[2][kBN][kLDK];
+  const int t = threadIdx.x;
+
+  // XCD-aware tile order: workgroup b runs on XCD b % 8; give each XCD a
+  // contiguous range of tiles (N-tiles of one M row are consecutive).
+  constexpr int64_t tiles_n = kN / kBN;   // 8
+  const int64_t nblk = gridDim.x;
+  const int64_t b = blockIdx.x;
+  const int64_t per = nblk / kXcds, extra = nblk % kXcds;
+  const int64_t x = b % kXcds, i = b / kXcds;
+  const int64_t tile = x * per + (x < extra ? x : extra) + i;
+  const int64_t m0 = (tile / tiles_n) * kBM, n0 = (tile % tiles_n) * kBN;
+
+  // A staging: 8 threads per row (one float4 each), 64 rows per pass, 4
+  // passes.  The 256 rows of the tile are 4 whole voices (64 frames each):
+  // pass q reads frame a_r of voice m0 / 64 + q, which starts at a_r * 2756.
+  const int a_r = t >> 3;
+  const int64_t batch = rows >> 6;
+  const int64_t pos = a_r * 2756;
+  const float* abase[4];
+  int64_t lim[4];
+  bool vec = true;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t v = (m0 >> 6) + q;
+    int64_t start = 0, len = 0;
+    if (v < batch) {
+      if (offsets) {
+        start = offsets[v];
+        len = offsets[v + 1] - start;
+      } else {
+        start = v * n_uniform;
+        len = n_uniform;
+      }
+    }
+    vec = vec && (len & 3) == 0 && (reinterpret_cast<uintptr_t>(audio + start) & 15u) == 0;
+    abase[q] = audio + start + pos;
+    lim[q] = len - pos;
+  }
+  // B staging: 4 threads per row (16 bytes each), 128 rows per pass, 2 passes.
+  const int b_c = (t & 3) * 8;
+  const int b_r = t >> 2;
+  const uint16_t* bsrc0 = basis + (n0 + b_r) * (int64_t)kN + b_c;
+  const uint16_t* bsrc1 = basis + (n0 + 128 + b_r) * (int64_t)kN + b_c;
+  if (vec)                                       // uniform across the workgroup
+    dft_tile<true>(audio, abase, lim, bsrc0, bsrc1, As, Bs, m0, n0, rows, power, ldp);
+  else
+    dft_tile<false>(audio, abase, lim, bsrc0, bsrc1, As, Bs, m0, n0, rows, power, ldp);
 }
 
 // Basis rows as described above, float64 angle and window, rounded to bf16.
