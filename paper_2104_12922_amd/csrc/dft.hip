@@ -177,6 +177,7 @@ __device__ __forceinline__ void dft_tile(const float* __restrict__ audio, const 
     }
 }
 
+template <bool VEC>
 __global__ void __launch_bounds__(kThreads) dft_power_kernel(const float* __restrict__ audio,
                                                         const int64_t* __restrict__ offsets,
                                                         int64_t n_uniform, int64_t rows,
@@ -228,10 +229,11 @@ __global__ void __launch_bounds__(kThreads) dft_power_kernel(const float* __rest
   const int b_r = t >> 2;
   const uint16_t* bsrc0 = basis + (n0 + b_r) * (int64_t)kN + b_c;
   const uint16_t* bsrc1 = basis + (n0 + 128 + b_r) * (int64_t)kN + b_c;
-  if (vec)                                       // uniform across the workgroup
-    dft_tile<true>(audio, abase, lim, bsrc0, bsrc1, As, Bs, m0, n0, rows, power, ldp);
-  else
-    dft_tile<false>(audio, abase, lim, bsrc0, bsrc1, As, Bs, m0, n0, rows, power, ldp);
+  // Both instantiations run over the same grid; each takes the tiles whose
+  // voices suit it (the flag is uniform across the workgroup), so every tile
+  // is computed once and each instantiation gets its own register budget.
+  if (vec != VEC) return;
+  dft_tile<VEC>(audio, abase, lim, bsrc0, bsrc1, As, Bs, m0, n0, rows, power, ldp);
 }
 
 // Basis rows as described above, float64 angle and window, rounded to bf16.
@@ -265,8 +267,17 @@ hipError_t launch_dft_power(const float* audio, const int64_t* offsets, int64_t 
   if (rows == 0) return hipSuccess;
   const int64_t tiles = ((rows + kBM - 1) / kBM) * (kN / kBN);
   if (tiles > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(dft_power_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, audio, offsets,
-                     n_uniform, rows, (const uint16_t*)basis, (uint16_t*)power, ldp);
+  hipLaunchKernelGGL(dft_power_kernel<true>, dim3((unsigned)tiles), dim3(kThreads), 0, s, audio,
+                     offsets, n_uniform, rows, (const uint16_t*)basis, (uint16_t*)power, ldp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // Tiles with a voice that is not 16-byte aligned or whose length is not a
+  // multiple of 4 (none for uniform batches of aligned audio).
+  const bool all_vec = !offsets && (n_uniform & 3) == 0 &&
+                       (reinterpret_cast<uintptr_t>(audio) & 15u) == 0;
+  if (!all_vec)
+    hipLaunchKernelGGL(dft_power_kernel<false>, dim3((unsigned)tiles), dim3(kThreads), 0, s, audio,
+                       offsets, n_uniform, rows, (const uint16_t*)basis, (uint16_t*)power, ldp);
   return hipGetLastError();
 }
 
