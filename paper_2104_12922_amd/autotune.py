@@ -22,11 +22,12 @@ from . import synth_render_plan
 
 
 def default_candidates(batch: int, uniform: bool):
-    """Plans worth timing: 2 or 4 runs per control period; one workgroup per
-    voice, or a persistent grid of 1-4 workgroups per CU (256 CUs); uniform
-    batches smaller than the CU count also try splitting voices into slices."""
+    """Plans worth timing (the library's default plan first): 4 or 2 runs per
+    control period; one workgroup per voice, or a persistent grid of 4-16
+    workgroups per CU (256 CUs); uniform batches smaller than the CU count
+    also try splitting voices into slices."""
     c = []
-    for rps in (2, 4):
+    for rps in (4, 2):
         c.append((rps, 1, 0, 0))
         for g in (1024, 2048, 4096):
             if g < batch:
@@ -38,8 +39,9 @@ def default_candidates(batch: int, uniform: bool):
 
 
 class RenderTuner:
-    def __init__(self, reps: int = 3, candidates=None):
+    def __init__(self, reps: int = 5, candidates=None, margin: float = 0.02):
         self.reps = reps
+        self.margin = margin
         self.candidates = candidates
         self.table: dict[str, tuple] = {}
         self.timings: dict[str, dict] = {}
@@ -76,6 +78,9 @@ class RenderTuner:
                 ts.append(a.elapsed_time(b))
             times[plan] = float(np.median(ts))
         best = min(times, key=times.get)
+        default = cands[0]
+        if default in times and times[best] > (1.0 - self.margin) * times[default]:
+            best = default                     # keep the default plan unless clearly faster
         self.table[k] = best
         self.timings[k] = {",".join(map(str, p)): t for p, t in times.items()}
         return best, times
