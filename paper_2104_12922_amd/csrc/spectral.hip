@@ -63,18 +63,18 @@ __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
-// One Stockham pass of radix R on the transform of Nc points whose butterfly
-// j (0 <= j < Nc / R) this thread owns: inputs v[r] = src[j + r Nc / R], the
-// twiddles exp(dir 2 pi i (j mod Ns) r / (Ns R)), the R-point DFT, outputs to
-// dst[(j / Ns) Ns R + (j mod Ns) + r Ns].  tw holds exp(-2 pi i k / (2 Nc)).
-template <int R>
-__device__ __forceinline__ void butterfly(float2 (&v)[4], int j, int Ns, int Nc, float dir,
-                                          const float2* tw) {
-  const int k = j % Ns;
-  const int step = Nc / (Ns * R);
+// One Stockham pass of radix R on the transform of NC points whose butterfly
+// j (0 <= j < NC / R) this thread owns: inputs v[r] = src[j + r NC / R], the
+// twiddles exp(dir 2 pi i (j mod NS) r / (NS R)), the R-point DFT, outputs to
+// dst[(j / NS) NS R + (j mod NS) + r NS].  tw holds exp(-2 pi i k / (2 NC)).
+// NS and NC are powers of two known at compile time.
+template <int R, int NS, int NC>
+__device__ __forceinline__ void butterfly(float2 (&v)[4], int j, float dir, const float2* tw) {
+  const int k = j & (NS - 1);
+  constexpr int step = NC / (NS * R);
 #pragma unroll
   for (int r = 1; r < R; ++r) {
-    const int idx = (k * r * step) % Nc;          // exp(-2 pi i idx / Nc) = tw[2 idx]
+    const int idx = (k * r * step) & (NC - 1);     // exp(-2 pi i idx / NC) = tw[2 idx]
     float2 w = tw[2 * idx];
     if (dir > 0.0f) w.y = -w.y;
     v[r] = cmul(v[r], w);
@@ -95,64 +95,64 @@ __device__ __forceinline__ void butterfly(float2 (&v)[4], int j, int Ns, int Nc,
   }
 }
 
-// Complex FFT of Nc points held by Nc / 4 threads (thread j of the transform),
-// starting from v (the first pass's inputs v[r] = z[j + r Nc / 4]), working in
-// base[2] (each Nc points long).  All threads of the workgroup call it (it
-// contains barriers); `active` marks the threads that own a butterfly.
-// Returns the buffer index holding the natural-order result.
-__device__ int fft_pass_all(float2 (&v)[4], int j, int Nc, float dir, const float2* tw,
-                            float2* base0, float2* base1, bool active) {
-  int Ns = 1;
-  int cur = 0;                                     // buffer the next pass writes
-  bool first = true;
-  int rem = Nc;
-  while (rem > 1) {
-    const int R = (rem % 4 == 0) ? 4 : 2;
-    float2* dst = cur == 0 ? base0 : base1;
-    const float2* src = cur == 0 ? base1 : base0;
+// The passes of a complex FFT of NC points held by NC / 4 threads (thread j
+// of the transform), starting from v (the first pass's inputs v[r] =
+// z[j + r NC / 4]), ping-ponging between base0 and base1 (each NC points).
+// Every thread of the workgroup calls it (it contains barriers); `active`
+// marks the threads that own a butterfly.  CUR is the buffer the pass writes;
+// the natural-order result ends in the buffer whose index is returned.
+template <int NC, int NS, int CUR>
+__device__ __forceinline__ int fft_passes(float2 (&v)[4], int j, float dir, const float2* tw,
+                                          float2* base0, float2* base1, bool active) {
+  constexpr int REM = NC / NS;
+  if constexpr (REM <= 1) {
+    return CUR ^ 1;
+  } else {
+    constexpr int R = (REM % 4 == 0) ? 4 : 2;
+    float2* dst = CUR == 0 ? base0 : base1;
+    const float2* src = CUR == 0 ? base1 : base0;
+    constexpr bool first = NS == 1;
     if (active) {
-      if (R == 4) {
-        if (!first)
-          for (int r = 0; r < 4; ++r) v[r] = src[j + r * (Nc / 4)];
-        butterfly<4>(v, j, Ns, Nc, dir, tw);
-        const int d = (j / Ns) * Ns * 4 + (j % Ns);
-        for (int r = 0; r < 4; ++r) dst[d + r * Ns] = v[r];
+      if constexpr (R == 4) {
+        if constexpr (!first) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[r] = src[j + r * (NC / 4)];
+        }
+        butterfly<4, NS, NC>(v, j, dir, tw);
+        const int d = ((j & ~(NS - 1)) << 2) + (j & (NS - 1));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[d + r * NS] = v[r];
       } else {
-        // radix 2: Nc / 2 butterflies, two per thread (j and j + Nc / 4)
+        // radix 2 (last pass): NC / 2 butterflies, two per thread (j, j + NC / 4)
+#pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const int jj = j + h * (Nc / 4);
+          const int jj = j + h * (NC / 4);
           float2 u[4];
-          u[0] = first ? v[h * 2] : src[jj];
-          u[1] = first ? v[h * 2 + 1] : src[jj + Nc / 2];
-          butterfly<2>(u, jj, Ns, Nc, dir, tw);
-          const int d = (jj / Ns) * Ns * 2 + (jj % Ns);
+          u[0] = src[jj];
+          u[1] = src[jj + NC / 2];
+          butterfly<2, NS, NC>(u, jj, dir, tw);
+          const int d = ((jj & ~(NS - 1)) << 1) + (jj & (NS - 1));
           dst[d] = u[0];
-          dst[d + Ns] = u[1];
+          dst[d + NS] = u[1];
         }
       }
     }
     __syncthreads();
-    first = false;
-    Ns *= R;
-    rem /= R;
-    cur ^= 1;
+    return fft_passes<NC, NS * R, CUR ^ 1>(v, j, dir, tw, base0, base1, active);
   }
-  return cur ^ 1;
 }
 
-__global__ void __launch_bounds__(kThreads) mrstft_frames_kernel(const MrArgs a) {
-  __shared__ SpecShared sh;
+template <int RES>
+__device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, int64_t b, int blk) {
+  constexpr int r = RES;
   const int tid = threadIdx.x;
-  const int64_t b = blockIdx.y;
-  const int blk = blockIdx.x;
-  const int r = blk < a.chunk_base[1] ? 0 : (blk < a.chunk_base[2] ? 1 : 2);
   const int chunk = blk - a.chunk_base[r];
-  const int n = 512 << r;
-  const int Nc = n / 2;                 // complex points per transform
-  const int tpt = Nc / 4;               // threads per transform
-  const int ntr = kThreads / tpt;       // transforms in flight: 8, 4, 2
-  const int fpi = ntr / 2;              // frames per iteration: 4, 2, 1
-  const int hop = n / 4;
+  constexpr int n = 512 << r;
+  constexpr int Nc = n / 2;             // complex points per transform
+  constexpr int tpt = Nc / 4;           // threads per transform
+  constexpr int ntr = kThreads / tpt;   // transforms in flight: 8, 4, 2
+  constexpr int fpi = ntr / 2;          // frames per iteration: 4, 2, 1
+  constexpr int hop = n / 4;
   const int F = a.F[r];
   const bool want_grad = a.wgrad != nullptr;
 
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(kThreads) mrstft_frames_kernel(const MrArgs a)
     }
     float2* b0 = sh.buf[0] + tr * Nc;
     float2* b1 = sh.buf[1] + tr * Nc;
-    const int zb = fft_pass_all(v, j, Nc, -1.0f, sh.tw, b0, b1, true);
+    const int zb = fft_passes<Nc, 1, 0>(v, j, -1.0f, sh.tw, b0, b1, true);
     // ---- bins: frame slot's 2 * tpt threads take bins k = u, u + 2 tpt, ... ----
     const float2* Zx = sh.buf[zb] + (2 * slot) * Nc;
     const float2* Zt = sh.buf[zb] + (2 * slot + 1) * Nc;
@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(kThreads) mrstft_frames_kernel(const MrArgs a)
       __syncthreads();                              // H read before buffers are reused
       float2* c0 = sh.buf[0] + slot * 2 * Nc;       // the frame slot's two transform areas
       float2* c1 = sh.buf[1] + slot * 2 * Nc;
-      const int yb = fft_pass_all(y, j, Nc, 1.0f, sh.tw, c0, c1, inv_active);
+      const int yb = fft_passes<Nc, 1, 0>(y, j, 1.0f, sh.tw, c0, c1, inv_active);
       if (live && inv_active) {
         const float2* Y = sh.buf[yb] + slot * 2 * Nc;
         float* out = a.wgrad + a.wbase[r] + ((int64_t)b * F + f) * n;
@@ -265,6 +265,18 @@ __global__ void __launch_bounds__(kThreads) mrstft_frames_kernel(const MrArgs a)
     for (int w = 0; w < kThreads / 64; ++w) s += sh.red[w];
     a.partial[b * a.chunk_base[3] + blk] = s;
   }
+}
+
+__global__ void __launch_bounds__(kThreads) mrstft_frames_kernel(const MrArgs a) {
+  __shared__ SpecShared sh;
+  const int64_t b = blockIdx.y;
+  const int blk = blockIdx.x;
+  if (blk < a.chunk_base[1])
+    mrstft_frames<0>(a, sh, b, blk);
+  else if (blk < a.chunk_base[2])
+    mrstft_frames<1>(a, sh, b, blk);
+  else
+    mrstft_frames<2>(a, sh, b, blk);
 }
 
 // grad[b][i] = sum over resolutions, then frames f covering i, of the frame
