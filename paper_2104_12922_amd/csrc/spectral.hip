@@ -33,11 +33,15 @@ constexpr int kThreads = 512;
 constexpr int kMaxN = 2048;
 constexpr int kFramesPerBlock = 16;
 constexpr float kEps = 1e-5f;
+// LDS index with one float2 of padding after every 16, so the power-of-two
+// strides of the Stockham passes spread over the banks.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+constexpr int kPadded = kMaxN + kMaxN / 16;
 
 struct SpecShared {
   float2 tw[kMaxN];            // tw[k] = exp(-2 pi i k / n)
   float win[kMaxN];            // periodic Hann window
-  float2 buf[2][kMaxN];        // FFT ping-pong: (512 / (n/8)) transforms of n/2 points
+  float2 buf[2][kPadded];      // FFT ping-pong: (512 / (n/8)) transforms of n/2 points (padded)
   double red[kThreads / 64];
 };
 
@@ -73,7 +77,7 @@ __device__ __forceinline__ void butterfly(float2 (&v)[4], int j, float dir, cons
   const int k = j & (NS - 1);
   constexpr int step = NC / (NS * R);
 #pragma unroll
-  for (int r = 1; r < R; ++r) {
+  for (int r = 1; r < (NS == 1 ? 1 : R); ++r) {       // the first pass has no twiddles
     const int idx = (k * r * step) & (NC - 1);     // exp(-2 pi i idx / NC) = tw[2 idx]
     float2 w = tw[2 * idx];
     if (dir > 0.0f) w.y = -w.y;
@@ -116,24 +120,24 @@ __device__ __forceinline__ int fft_passes(float2 (&v)[4], int j, float dir, cons
       if constexpr (R == 4) {
         if constexpr (!first) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) v[r] = src[j + r * (NC / 4)];
+          for (int r = 0; r < 4; ++r) v[r] = src[pad(j + r * (NC / 4))];
         }
         butterfly<4, NS, NC>(v, j, dir, tw);
         const int d = ((j & ~(NS - 1)) << 2) + (j & (NS - 1));
 #pragma unroll
-        for (int r = 0; r < 4; ++r) dst[d + r * NS] = v[r];
+        for (int r = 0; r < 4; ++r) dst[pad(d + r * NS)] = v[r];
       } else {
         // radix 2 (last pass): NC / 2 butterflies, two per thread (j, j + NC / 4)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int jj = j + h * (NC / 4);
           float2 u[4];
-          u[0] = src[jj];
-          u[1] = src[jj + NC / 2];
+          u[0] = src[pad(jj)];
+          u[1] = src[pad(jj + NC / 2)];
           butterfly<2, NS, NC>(u, jj, dir, tw);
           const int d = ((jj & ~(NS - 1)) << 1) + (jj & (NS - 1));
-          dst[d] = u[0];
-          dst[d + NS] = u[1];
+          dst[pad(d)] = u[0];
+          dst[pad(d + NS)] = u[1];
         }
       }
     }
@@ -186,27 +190,27 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, i
       v[q] = live ? make_float2(sh.win[2 * m] * fr[2 * m], sh.win[2 * m + 1] * fr[2 * m + 1])
                   : make_float2(0.f, 0.f);
     }
-    float2* b0 = sh.buf[0] + tr * Nc;
-    float2* b1 = sh.buf[1] + tr * Nc;
+    float2* b0 = sh.buf[0] + pad(tr * Nc);
+    float2* b1 = sh.buf[1] + pad(tr * Nc);
     const int zb = fft_passes<Nc, 1, 0>(v, j, -1.0f, sh.tw, b0, b1, true);
     // ---- bins: frame slot's 2 * tpt threads take bins k = u, u + 2 tpt, ... ----
-    const float2* Zx = sh.buf[zb] + (2 * slot) * Nc;
-    const float2* Zt = sh.buf[zb] + (2 * slot + 1) * Nc;
-    float2* Hs = sh.buf[zb ^ 1] + slot * (Nc + 4);   // Hermitian half H_0 .. H_Nc
+    const float2* Zx = sh.buf[zb] + pad((2 * slot) * Nc);
+    const float2* Zt = sh.buf[zb] + pad((2 * slot + 1) * Nc);
+    float2* Hs = sh.buf[zb ^ 1] + slot * (Nc + 4);   // Hermitian half H_0 .. H_Nc (unpadded)
     const int u = tid - slot * 2 * tpt;
     for (int k = u; k <= Nc; k += 2 * tpt) {
       const float2 tw = k < Nc ? sh.tw[k] : make_float2(-1.0f, 0.0f);
       const int kc = k == Nc ? 0 : k, km = k == 0 ? 0 : Nc - k;   // Z_Nc = Z_0
       float2 X, T;
       {
-        const float2 zk = Zx[kc], zc = cconj(Zx[km]);
+        const float2 zk = Zx[pad(kc)], zc = cconj(Zx[pad(km)]);
         const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
         const float2 D = csub(zk, zc);
         const float2 O = make_float2(0.5f * D.y, -0.5f * D.x);     // -i D / 2
         X = cadd(E, cmul(tw, O));
       }
       {
-        const float2 zk = Zt[kc], zc = cconj(Zt[km]);
+        const float2 zk = Zt[pad(kc)], zc = cconj(Zt[pad(km)]);
         const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
         const float2 D = csub(zk, zc);
         const float2 O = make_float2(0.5f * D.y, -0.5f * D.x);
@@ -241,14 +245,14 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, i
         y[q] = make_float2(A.x - cd.y, A.y + cd.x);   // A + i (c D)
       }
       __syncthreads();                              // H read before buffers are reused
-      float2* c0 = sh.buf[0] + slot * 2 * Nc;       // the frame slot's two transform areas
-      float2* c1 = sh.buf[1] + slot * 2 * Nc;
+      float2* c0 = sh.buf[0] + pad(slot * 2 * Nc);  // the frame slot's two transform areas
+      float2* c1 = sh.buf[1] + pad(slot * 2 * Nc);
       const int yb = fft_passes<Nc, 1, 0>(y, j, 1.0f, sh.tw, c0, c1, inv_active);
       if (live && inv_active) {
-        const float2* Y = sh.buf[yb] + slot * 2 * Nc;
+        const float2* Y = sh.buf[yb] + pad(slot * 2 * Nc);
         float* out = a.wgrad + a.wbase[r] + ((int64_t)b * F + f) * n;
         for (int m = j; m < Nc; m += tpt) {
-          const float2 yy = Y[m];
+          const float2 yy = Y[pad(m)];
           out[2 * m] = 0.5f * sh.win[2 * m] * yy.x;
           out[2 * m + 1] = 0.5f * sh.win[2 * m + 1] * yy.y;
         }
