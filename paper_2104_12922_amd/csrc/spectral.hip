@@ -33,15 +33,17 @@ constexpr int kThreads = 512;
 constexpr int kMaxN = 2048;
 constexpr int kFramesPerBlock = 16;
 constexpr float kEps = 1e-5f;
-// LDS index with one float2 of padding after every 16, so the power-of-two
-// strides of the Stockham passes spread over the banks.
-__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
-constexpr int kPadded = kMaxN + kMaxN / 16;
+// LDS slot swizzle (a bijection within each block of 128 float2): XORs index
+// bits 4-6 into bits 0-4 so that the strided writes of the first Stockham
+// passes (strides of 4 and 16 slots) and the contiguous reads all fall on
+// distinct banks, for 32 or 64 four-byte banks.
+__device__ __forceinline__ int swz(int i) { return i ^ (5 * ((i >> 4) & 3)) ^ ((i >> 2) & 16); }
+constexpr int kPadded = kMaxN;
 
 struct SpecShared {
   float2 tw[kMaxN];            // tw[k] = exp(-2 pi i k / n)
   float win[kMaxN];            // periodic Hann window
-  float2 buf[2][kPadded];      // FFT ping-pong: (512 / (n/8)) transforms of n/2 points (padded)
+  float2 buf[2][kPadded];      // FFT ping-pong: (512 / (n/8)) transforms of n/2 points (swizzled)
   double red[kThreads / 64];
 };
 
@@ -120,24 +122,24 @@ __device__ __forceinline__ int fft_passes(float2 (&v)[4], int j, float dir, cons
       if constexpr (R == 4) {
         if constexpr (!first) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) v[r] = src[pad(j + r * (NC / 4))];
+          for (int r = 0; r < 4; ++r) v[r] = src[swz(j + r * (NC / 4))];
         }
         butterfly<4, NS, NC>(v, j, dir, tw);
         const int d = ((j & ~(NS - 1)) << 2) + (j & (NS - 1));
 #pragma unroll
-        for (int r = 0; r < 4; ++r) dst[pad(d + r * NS)] = v[r];
+        for (int r = 0; r < 4; ++r) dst[swz(d + r * NS)] = v[r];
       } else {
         // radix 2 (last pass): NC / 2 butterflies, two per thread (j, j + NC / 4)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int jj = j + h * (NC / 4);
           float2 u[4];
-          u[0] = src[pad(jj)];
-          u[1] = src[pad(jj + NC / 2)];
+          u[0] = src[swz(jj)];
+          u[1] = src[swz(jj + NC / 2)];
           butterfly<2, NS, NC>(u, jj, dir, tw);
           const int d = ((jj & ~(NS - 1)) << 1) + (jj & (NS - 1));
-          dst[pad(d)] = u[0];
-          dst[pad(d + NS)] = u[1];
+          dst[swz(d)] = u[0];
+          dst[swz(d + NS)] = u[1];
         }
       }
     }
@@ -190,27 +192,27 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, i
       v[q] = live ? make_float2(sh.win[2 * m] * fr[2 * m], sh.win[2 * m + 1] * fr[2 * m + 1])
                   : make_float2(0.f, 0.f);
     }
-    float2* b0 = sh.buf[0] + pad(tr * Nc);
-    float2* b1 = sh.buf[1] + pad(tr * Nc);
+    float2* b0 = sh.buf[0] + tr * Nc;
+    float2* b1 = sh.buf[1] + tr * Nc;
     const int zb = fft_passes<Nc, 1, 0>(v, j, -1.0f, sh.tw, b0, b1, true);
     // ---- bins: frame slot's 2 * tpt threads take bins k = u, u + 2 tpt, ... ----
-    const float2* Zx = sh.buf[zb] + pad((2 * slot) * Nc);
-    const float2* Zt = sh.buf[zb] + pad((2 * slot + 1) * Nc);
-    float2* Hs = sh.buf[zb ^ 1] + slot * (Nc + 4);   // Hermitian half H_0 .. H_Nc (unpadded)
+    const float2* Zx = sh.buf[zb] + (2 * slot) * Nc;
+    const float2* Zt = sh.buf[zb] + (2 * slot + 1) * Nc;
+    float2* Hs = sh.buf[zb ^ 1] + slot * (Nc + 4);   // Hermitian half H_0 .. H_Nc (plain)
     const int u = tid - slot * 2 * tpt;
     for (int k = u; k <= Nc; k += 2 * tpt) {
       const float2 tw = k < Nc ? sh.tw[k] : make_float2(-1.0f, 0.0f);
       const int kc = k == Nc ? 0 : k, km = k == 0 ? 0 : Nc - k;   // Z_Nc = Z_0
       float2 X, T;
       {
-        const float2 zk = Zx[pad(kc)], zc = cconj(Zx[pad(km)]);
+        const float2 zk = Zx[swz(kc)], zc = cconj(Zx[swz(km)]);
         const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
         const float2 D = csub(zk, zc);
         const float2 O = make_float2(0.5f * D.y, -0.5f * D.x);     // -i D / 2
         X = cadd(E, cmul(tw, O));
       }
       {
-        const float2 zk = Zt[pad(kc)], zc = cconj(Zt[pad(km)]);
+        const float2 zk = Zt[swz(kc)], zc = cconj(Zt[swz(km)]);
         const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
         const float2 D = csub(zk, zc);
         const float2 O = make_float2(0.5f * D.y, -0.5f * D.x);
@@ -245,14 +247,14 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, i
         y[q] = make_float2(A.x - cd.y, A.y + cd.x);   // A + i (c D)
       }
       __syncthreads();                              // H read before buffers are reused
-      float2* c0 = sh.buf[0] + pad(slot * 2 * Nc);  // the frame slot's two transform areas
-      float2* c1 = sh.buf[1] + pad(slot * 2 * Nc);
+      float2* c0 = sh.buf[0] + slot * 2 * Nc;  // the frame slot's two transform areas
+      float2* c1 = sh.buf[1] + slot * 2 * Nc;
       const int yb = fft_passes<Nc, 1, 0>(y, j, 1.0f, sh.tw, c0, c1, inv_active);
       if (live && inv_active) {
-        const float2* Y = sh.buf[yb] + pad(slot * 2 * Nc);
+        const float2* Y = sh.buf[yb] + slot * 2 * Nc;
         float* out = a.wgrad + a.wbase[r] + ((int64_t)b * F + f) * n;
         for (int m = j; m < Nc; m += tpt) {
-          const float2 yy = Y[pad(m)];
+          const float2 yy = Y[swz(m)];
           out[2 * m] = 0.5f * sh.win[2 * m] * yy.x;
           out[2 * m + 1] = 0.5f * sh.win[2 * m + 1] * yy.y;
         }
