@@ -40,8 +40,11 @@ constexpr float kEps = 1e-5f;
 __device__ __forceinline__ int swz(int i) { return i ^ (5 * ((i >> 4) & 3)) ^ ((i >> 2) & 16); }
 constexpr int kPadded = kMaxN;
 
+constexpr int kPassTw = 1280;  // per-pass twiddles (Nc = 512 needs 1276)
+
 struct SpecShared {
   float2 tw[kMaxN];            // tw[k] = exp(-2 pi i k / n)
+  float2 ptw[kPassTw];         // per-pass twiddles, contiguous in the butterfly index
   float win[kMaxN];            // periodic Hann window
   float2 buf[2][kPadded];      // FFT ping-pong: (512 / (n/8)) transforms of n/2 points (swizzled)
   double red[kThreads / 64];
@@ -74,16 +77,22 @@ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(
 // twiddles exp(dir 2 pi i (j mod NS) r / (NS R)), the R-point DFT, outputs to
 // dst[(j / NS) NS R + (j mod NS) + r NS].  tw holds exp(-2 pi i k / (2 NC)).
 // NS and NC are powers of two known at compile time.
+// Per-pass twiddle tables: the radix-4 pass with stride NS (NS >= 4) keeps
+// exp(-2 pi i k r / (4 NS)) for k < NS, r = 1..3 at ptw[off4(NS) + 3 k + r - 1];
+// the radix-2 pass (stride NS) keeps exp(-2 pi i k / (2 NS)) at ptw[off4(NS) + k].
+// Lanes read consecutive entries.
+constexpr int off4(int ns) { return ns <= 4 ? 0 : off4(ns / 4) + 3 * (ns / 4); }
+
 template <int R, int NS, int NC>
-__device__ __forceinline__ void butterfly(float2 (&v)[4], int j, float dir, const float2* tw) {
+__device__ __forceinline__ void butterfly(float2 (&v)[4], int j, float dir, const float2* ptw) {
   const int k = j & (NS - 1);
-  constexpr int step = NC / (NS * R);
+  if constexpr (NS > 1) {
 #pragma unroll
-  for (int r = 1; r < (NS == 1 ? 1 : R); ++r) {       // the first pass has no twiddles
-    const int idx = (k * r * step) & (NC - 1);     // exp(-2 pi i idx / NC) = tw[2 idx]
-    float2 w = tw[2 * idx];
-    if (dir > 0.0f) w.y = -w.y;
-    v[r] = cmul(v[r], w);
+    for (int r = 1; r < R; ++r) {
+      float2 w = ptw[off4(NS) + (R - 1) * k + (r - 1)];
+      if (dir > 0.0f) w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
   }
   if constexpr (R == 4) {
     const float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
@@ -108,7 +117,7 @@ __device__ __forceinline__ void butterfly(float2 (&v)[4], int j, float dir, cons
 // marks the threads that own a butterfly.  CUR is the buffer the pass writes;
 // the natural-order result ends in the buffer whose index is returned.
 template <int NC, int NS, int CUR>
-__device__ __forceinline__ int fft_passes(float2 (&v)[4], int j, float dir, const float2* tw,
+__device__ __forceinline__ int fft_passes(float2 (&v)[4], int j, float dir, const float2* ptw,
                                           float2* base0, float2* base1, bool active) {
   constexpr int REM = NC / NS;
   if constexpr (REM <= 1) {
@@ -124,7 +133,7 @@ __device__ __forceinline__ int fft_passes(float2 (&v)[4], int j, float dir, cons
 #pragma unroll
           for (int r = 0; r < 4; ++r) v[r] = src[swz(j + r * (NC / 4))];
         }
-        butterfly<4, NS, NC>(v, j, dir, tw);
+        butterfly<4, NS, NC>(v, j, dir, ptw);
         const int d = ((j & ~(NS - 1)) << 2) + (j & (NS - 1));
 #pragma unroll
         for (int r = 0; r < 4; ++r) dst[swz(d + r * NS)] = v[r];
@@ -136,7 +145,7 @@ __device__ __forceinline__ int fft_passes(float2 (&v)[4], int j, float dir, cons
           float2 u[4];
           u[0] = src[swz(jj)];
           u[1] = src[swz(jj + NC / 2)];
-          butterfly<2, NS, NC>(u, jj, dir, tw);
+          butterfly<2, NS, NC>(u, jj, dir, ptw);
           const int d = ((jj & ~(NS - 1)) << 1) + (jj & (NS - 1));
           dst[swz(d)] = u[0];
           dst[swz(d + NS)] = u[1];
@@ -144,7 +153,7 @@ __device__ __forceinline__ int fft_passes(float2 (&v)[4], int j, float dir, cons
       }
     }
     __syncthreads();
-    return fft_passes<NC, NS * R, CUR ^ 1>(v, j, dir, tw, base0, base1, active);
+    return fft_passes<NC, NS * R, CUR ^ 1>(v, j, dir, ptw, base0, base1, active);
   }
 }
 
@@ -167,6 +176,16 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, i
     sincospif(2.0f * (float)k / (float)n, &s, &c);
     sh.tw[k] = make_float2(c, -s);
     sh.win[k] = 0.5f - 0.5f * cospif(2.0f * (float)k / (float)n);
+  }
+  for (int ns = 4, rem = Nc / 4; rem > 1; ns *= 4, rem /= 4) {
+    const int R = rem % 4 == 0 ? 4 : 2;       // radix of the pass with stride ns
+    for (int e = tid; e < (R - 1) * ns; e += kThreads) {
+      const int k = e / (R - 1), r = e % (R - 1) + 1;
+      float sn, cs;
+      sincospif(-2.0f * (float)(k * r) / (float)(R * ns), &sn, &cs);
+      sh.ptw[off4(ns) + e] = make_float2(cs, sn);
+    }
+    if (R == 2) break;
   }
   __syncthreads();
 
@@ -194,7 +213,7 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, i
     }
     float2* b0 = sh.buf[0] + tr * Nc;
     float2* b1 = sh.buf[1] + tr * Nc;
-    const int zb = fft_passes<Nc, 1, 0>(v, j, -1.0f, sh.tw, b0, b1, true);
+    const int zb = fft_passes<Nc, 1, 0>(v, j, -1.0f, sh.ptw, b0, b1, true);
     // ---- bins: frame slot's 2 * tpt threads take bins k = u, u + 2 tpt, ... ----
     const float2* Zx = sh.buf[zb] + (2 * slot) * Nc;
     const float2* Zt = sh.buf[zb] + (2 * slot + 1) * Nc;
@@ -249,7 +268,7 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, i
       __syncthreads();                              // H read before buffers are reused
       float2* c0 = sh.buf[0] + slot * 2 * Nc;  // the frame slot's two transform areas
       float2* c1 = sh.buf[1] + slot * 2 * Nc;
-      const int yb = fft_passes<Nc, 1, 0>(y, j, 1.0f, sh.tw, c0, c1, inv_active);
+      const int yb = fft_passes<Nc, 1, 0>(y, j, 1.0f, sh.ptw, c0, c1, inv_active);
       if (live && inv_active) {
         const float2* Y = sh.buf[yb] + slot * 2 * Nc;
         float* out = a.wgrad + a.wbase[r] + ((int64_t)b * F + f) * n;
