@@ -159,6 +159,13 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
       double acc[kNumRed];
 #pragma unroll
       for (int r = 0; r < kNumRed; ++r) acc[r] = 0.0;
+      // The amplitude-side sums (VCA rows, levels, shape, K) are accumulated in
+      // float32 over the run (at most q / RPS samples) and promoted once; the
+      // phase-adjoint sums stay float64.
+      float fa[kNumRed - kRA01];
+#pragma unroll
+      for (int r = 0; r < kNumRed - kRA01; ++r) fa[r] = 0.0f;
+      const double inv_q = 1.0 / qd;
       double P1 = 0.0, P2 = 0.0;
       const int seg_valid = ls < nseg ? 1 : 0;
       // samples of this run that exist in the voice (the last segment may be partial)
@@ -168,7 +175,8 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
         const int ks = m * h + k;                  // sample index within the segment
         const double live = k < nlive ? 1.0 : 0.0;
         const float kf = (float)ks;
-        const double wt1 = (double)ks / qd, wt0 = 1.0 - wt1;
+        const double wt1 = (double)ks * inv_q, wt0 = 1.0 - wt1;
+        const float wt1f = (float)ks * (float)inv_q, wt0f = 1.0f - wt1f;
         const float gk = seg_valid ? tg[lane * h + k] : 0.0f;
         const float gnk = seg_valid ? tgn[lane * h + k] : 0.0f;
         const float a1 = fmaf(kf, A1d, A10), a3 = fmaf(kf, A3d, A30), a4 = fmaf(kf, A4d, A40);
@@ -202,23 +210,25 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
         acc[kRE02] += wt0 * l2 * P2;
         acc[kRE12] += wt1 * l2 * P2;
         // VCA rows (transposed upsampling weights), levels, shape, K
-        const double d1 = (double)(gk * L1 * x1), d3 = (double)(gk * L2 * x2), d4 = (double)(L3 * gnk);
-        acc[kRA01] += wt0 * d1;
-        acc[kRA11] += wt1 * d1;
-        acc[kRA03] += wt0 * d3;
-        acc[kRA13] += wt1 * d3;
-        acc[kRA04] += wt0 * d4;
-        acc[kRA14] += wt1 * d4;
-        acc[kRL1] += (double)(gk * x1 * a1);
-        acc[kRL2] += (double)(gk * x2 * a3);
-        acc[kRL3] += (double)(gnk * a4);
-        acc[kRShape] += (double)(gl2a3 * (cg * T * c2f - 0.5f * T * Q));
-        acc[kRK] += (double)(gl2a3 * cg * sech2 * s2f * Q);
+        const float d1 = gk * L1 * x1, d3 = gk * L2 * x2, d4 = L3 * gnk;
+        fa[kRA01 - kRA01] = fmaf(wt0f, d1, fa[kRA01 - kRA01]);
+        fa[kRA11 - kRA01] = fmaf(wt1f, d1, fa[kRA11 - kRA01]);
+        fa[kRA03 - kRA01] = fmaf(wt0f, d3, fa[kRA03 - kRA01]);
+        fa[kRA13 - kRA01] = fmaf(wt1f, d3, fa[kRA13 - kRA01]);
+        fa[kRA04 - kRA01] = fmaf(wt0f, d4, fa[kRA04 - kRA01]);
+        fa[kRA14 - kRA01] = fmaf(wt1f, d4, fa[kRA14 - kRA01]);
+        fa[kRL1 - kRA01] += gk * x1 * a1;
+        fa[kRL2 - kRA01] += gk * x2 * a3;
+        fa[kRL3 - kRA01] += gnk * a4;
+        fa[kRShape - kRA01] += gl2a3 * (cg * T * c2f - 0.5f * T * Q);
+        fa[kRK - kRA01] += gl2a3 * cg * sech2 * s2f * Q;
         t1 += i1; i1 *= r1;
         t2 += i2; i2 *= r2;
       }
       acc[kRD1] = P1;
       acc[kRD2] = P2;
+#pragma unroll
+      for (int r = kRA01; r < kNumRed; ++r) acc[r] = (double)fa[r - kRA01];
       // combine the RPS runs of each segment: E += P_before * C, then sums
       if (RPS > 1) {
         const int gb = lane & ~(RPS - 1);          // first lane of this segment's group
