@@ -50,7 +50,8 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
   __shared__ VoiceShared sh;
   extern __shared__ __align__(16) float tile[];
   const int lane = threadIdx.x;
-  const int64_t b = blockIdx.x;
+  const int64_t b = blockIdx.x / a.slices;
+  const int slice = (int)(blockIdx.x % a.slices);
   const int q = a.q;
   const int h = q / RPS;
   const double qd = (double)q;
@@ -72,6 +73,11 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
   const int64_t js = (int64_t)floor(jsil) + 2;
   const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
   const int64_t c_sil = (js + kSegsPerChunk - 1) / kSegsPerChunk;
+  // this workgroup's chunks (a voice may be split over several workgroups;
+  // the earlier chunks are walked through the control stage only, for its
+  // carries)
+  const int64_t c_lo = nchunks * slice / a.slices;
+  const int64_t c_hi = nchunks * (slice + 1) / a.slices;
 
   const double midi = v[0];
   const double m_hi = fmax(0.0, midi + v[71] + fmax(0.0, v[72]));
@@ -84,16 +90,18 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
   const float two_pi = 6.28318530717958647692f;
   const uint32_t glo = (uint32_t)g, ghi = (uint32_t)(g >> 32);
 
-  for (int64_t c = 0; c < nchunks; ++c) {
+  for (int64_t c = 0; c < c_hi; ++c) {
     if (c >= c_sil) {
       // exactly silent from here on: every reduction is zero (the envelopes are
       // 0 with zero derivative, so no parameter sees these samples)
-      const int64_t s0 = c * kSegsPerChunk;
-      for (int64_t i = lane; i < (J - s0) * kNumRed; i += kWave) rv[s0 * kNumRed + i] = 0.0;
+      const int64_t s0 = (c > c_lo ? c : c_lo) * kSegsPerChunk;
+      const int64_t s1 = c_hi * kSegsPerChunk < J ? c_hi * kSegsPerChunk : J;
+      for (int64_t i = lane; i < (s1 - s0) * kNumRed; i += kWave) rv[s0 * kNumRed + i] = 0.0;
       break;
     }
     double y[5], yn[5];
     control_stage<RPS, false>(a, sh, reinterpret_cast<double*>(tile), c, J, h, lane, y, yn);
+    if (c < c_lo) continue;                      // slice starts later: only carries needed
     // unscaled VCA ramps of this lane's segment
     const float a10 = (float)y[1], a1d = (float)((yn[1] - y[1]) / qd);
     const float a30 = (float)y[3], a3d = (float)((yn[3] - y[3]) / qd);
@@ -616,8 +624,8 @@ hipError_t launch_adjoint_rps(const RenderArgs& a, const float* g, double* red, 
                               hipStream_t s) {
   size_t shmem = (size_t)2 * kWave * (a.q / RPS) * sizeof(float);
   if (shmem < 8 * kWave * sizeof(double)) shmem = 8 * kWave * sizeof(double);
-  hipLaunchKernelGGL((adjoint_audio_kernel<RPS>), dim3((unsigned)a.batch), dim3(kWave), shmem, s,
-                     a, g, red);
+  hipLaunchKernelGGL((adjoint_audio_kernel<RPS>), dim3((unsigned)(a.batch * a.slices)), dim3(kWave),
+                     shmem, s, a, g, red);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(adjoint_control_kernel, dim3((unsigned)a.batch), dim3(kWave), 0, s, a, red,

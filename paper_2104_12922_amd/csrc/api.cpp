@@ -199,7 +199,15 @@ int synth_render_backward(const synth_config* cfg, const float* params, const ui
   a.first_g = first_g;
   a.batch = batch;
   a.n_uniform = n_samples;
-  a.slices = 1;
+  {
+    // Small batches: split each voice's audio-rate pass over several
+    // workgroups so that the grid covers the chip (as the render does).
+    const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
+    int64_t want = (2048 + batch - 1) / batch;
+    if (want > nchunks / 4) want = nchunks / 4;
+    a.slices = want > 1 ? (int)want : 1;
+    if (batch * (int64_t)a.slices > 0x7FFFFFFF) a.slices = 1;
+  }
   return to_status(synth::launch_render_backward(a, grad_audio, (double*)workspace, grad_params,
                                                  rps, (hipStream_t)stream));
 }
