@@ -60,8 +60,9 @@ def parse():
     ap.add_argument("--autotune", type=int, default=1,
                     help="time the candidate launch plans on this batch first (untimed) and "
                          "render with the fastest")
-    ap.add_argument("--workload", default="render", choices=("render", "learned", "grad"),
-                    help="render: the headline ragged render; learned: one proposal "
+    ap.add_argument("--workload", default="render", choices=("render", "plain", "learned", "grad"),
+                    help="render: the headline ragged render; plain: 128 voices x 4 s "
+                         "(200 renders per timed step, in a HIP graph); learned: one proposal "
                          "training step (render + log-mel + MLP); grad: render, MR-STFT "
                          "loss and gradient, render adjoint")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -178,6 +179,55 @@ def bench_learned(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_plain(args):
+    """The plain render: 128 voices x 4 s (22.6 M samples).  One render takes
+    tens of microseconds, so a timed step is 200 back-to-back renders captured
+    in one HIP graph; value = rendered samples per second."""
+    import torch
+    import workloads as W
+    import paper_2104_12922_amd as S
+    wl = W.plain_render()
+    tab = wl.nebula.table()
+    B, N = wl.batch, 176400
+    stream = torch.cuda.Stream()
+    reps = 200
+    with torch.cuda.stream(stream):
+        u = S.synth_sample_params(wl.seed, 0, B)
+        out = torch.empty(B, N, device="cuda")
+        S.synth_render(u, tab, n_samples=N, noise_seed=wl.key_noise(), out=out)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            for _ in range(reps):
+                S.synth_render(u, tab, n_samples=N, noise_seed=wl.key_noise(), out=out)
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            g.replay()
+            b.record(stream)
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+    ms = float(np.mean(ts))
+    per = ms / reps
+    alg = 4.0 * B * N + 312.0 * B
+    out = {"metric": "rendered audio samples/sec", "value": B * N / (per * 1e-3),
+           "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": wl.name, "voices": B, "samples": B * N,
+                      "renders_per_step": reps},
+           "roofline": {"bound": "hbm", "achieved": alg / (per * 1e-3) / 1e9,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": alg / (per * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "render_kernel", "kernel_ms": per}}
+    print(json.dumps(out), flush=True)
+
+
 def bench_grad(args):
     """Gradient workload: 256 voices x 4 s rendered, MR-STFT loss and gradient
     against targets of another seed, render adjoint to the 78 parameters."""
@@ -241,6 +291,8 @@ def main():
         return bench_learned(args)
     if args.workload == "grad":
         return bench_grad(args)
+    if args.workload == "plain":
+        return bench_plain(args)
     import torch
     import workloads as W
     import paper_2104_12922_amd as S

@@ -65,6 +65,13 @@ typedef struct synth_config {
 /* Number of normalised parameters of the Voice: 78 (Section 1.1). */
 int synth_num_params(void);
 
+/* Parameter p (0 <= p < 78) of the default Voice in canonical order: its
+ * name ("module.parameter", static string), and the default nebula's min,
+ * max, curve and symmetric flag (Section 3.3).  Any output pointer may be
+ * NULL.  SYNTH_EINVAL for p out of range. */
+int synth_param_info(int p, const char** name, double* min, double* max, double* curve,
+                     int* symmetric);
+
 /* Static, NUL-terminated description of a status code. */
 const char* synth_status_string(int status);
 

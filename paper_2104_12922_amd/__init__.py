@@ -41,6 +41,19 @@ def _dev_ptr(t, name, dtype, numel=None):
     return t.data_ptr()
 
 
+def synth_param_info(p: int) -> dict:
+    """Name and default nebula range of parameter p (see synth.h)."""
+    import ctypes
+    nm = ctypes.c_char_p()
+    lo, hi, cv = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    sym = ctypes.c_int()
+    _native.check("synth_param_info", _native.lib().synth_param_info(
+        int(p), ctypes.byref(nm), ctypes.byref(lo), ctypes.byref(hi), ctypes.byref(cv),
+        ctypes.byref(sym)))
+    return {"name": nm.value.decode(), "min": lo.value, "max": hi.value, "curve": cv.value,
+            "symmetric": bool(sym.value)}
+
+
 def synth_is_test(g: int) -> bool:
     return bool(_native.lib().synth_is_test(int(g)))
 

@@ -43,6 +43,9 @@ def lib() -> ctypes.CDLL:
         L.synth_num_params.restype = ctypes.c_int
         L.synth_status_string.restype = ctypes.c_char_p
         L.synth_num_params.argtypes = []
+        L.synth_param_info.restype = ctypes.c_int
+        L.synth_param_info.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p)] + \
+            [ctypes.POINTER(ctypes.c_double)] * 3 + [ctypes.POINTER(ctypes.c_int)]
         L.synth_status_string.argtypes = [ctypes.c_int]
         L.synth_is_test.restype = ctypes.c_int
         L.synth_is_test.argtypes = [ctypes.c_uint64]

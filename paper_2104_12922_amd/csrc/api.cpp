@@ -74,6 +74,110 @@ extern "C" {
 
 int synth_num_params(void) { return SYNTH_NUM_PARAMS; }
 
+namespace {
+// Default Voice parameters in canonical order (Section 3.3 and the Voice's
+// module list, Section 3.2): name, min, max, curve, symmetric.  Ranges are
+// those of the default nebula (note duration from 0 s).
+constexpr double kPi = 3.14159265358979323846;
+struct ParamInfo {
+  const char* name;
+  double lo, hi, curve;
+  int sym;
+};
+const ParamInfo kParamInfo[SYNTH_NUM_PARAMS] = {
+    {"keyboard.midi_f0", 24.0, 84.0, 1.0, 0},
+    {"keyboard.duration", 0.0, 4.0, 1.0, 0},
+    {"adsr_1.attack", 0.0, 2.0, 1.0, 0},
+    {"adsr_1.decay", 0.0, 2.0, 1.0, 0},
+    {"adsr_1.sustain", 0.0, 1.0, 1.0, 0},
+    {"adsr_1.release", 0.0, 2.0, 1.0, 0},
+    {"adsr_1.alpha", 0.1, 6.0, 1.0, 0},
+    {"adsr_2.attack", 0.0, 2.0, 1.0, 0},
+    {"adsr_2.decay", 0.0, 2.0, 1.0, 0},
+    {"adsr_2.sustain", 0.0, 1.0, 1.0, 0},
+    {"adsr_2.release", 0.0, 2.0, 1.0, 0},
+    {"adsr_2.alpha", 0.1, 6.0, 1.0, 0},
+    {"lfo_1_rate_adsr.attack", 0.0, 2.0, 1.0, 0},
+    {"lfo_1_rate_adsr.decay", 0.0, 2.0, 1.0, 0},
+    {"lfo_1_rate_adsr.sustain", 0.0, 1.0, 1.0, 0},
+    {"lfo_1_rate_adsr.release", 0.0, 2.0, 1.0, 0},
+    {"lfo_1_rate_adsr.alpha", 0.1, 6.0, 1.0, 0},
+    {"lfo_1_amp_adsr.attack", 0.0, 2.0, 1.0, 0},
+    {"lfo_1_amp_adsr.decay", 0.0, 2.0, 1.0, 0},
+    {"lfo_1_amp_adsr.sustain", 0.0, 1.0, 1.0, 0},
+    {"lfo_1_amp_adsr.release", 0.0, 2.0, 1.0, 0},
+    {"lfo_1_amp_adsr.alpha", 0.1, 6.0, 1.0, 0},
+    {"lfo_2_rate_adsr.attack", 0.0, 2.0, 1.0, 0},
+    {"lfo_2_rate_adsr.decay", 0.0, 2.0, 1.0, 0},
+    {"lfo_2_rate_adsr.sustain", 0.0, 1.0, 1.0, 0},
+    {"lfo_2_rate_adsr.release", 0.0, 2.0, 1.0, 0},
+    {"lfo_2_rate_adsr.alpha", 0.1, 6.0, 1.0, 0},
+    {"lfo_2_amp_adsr.attack", 0.0, 2.0, 1.0, 0},
+    {"lfo_2_amp_adsr.decay", 0.0, 2.0, 1.0, 0},
+    {"lfo_2_amp_adsr.sustain", 0.0, 1.0, 1.0, 0},
+    {"lfo_2_amp_adsr.release", 0.0, 2.0, 1.0, 0},
+    {"lfo_2_amp_adsr.alpha", 0.1, 6.0, 1.0, 0},
+    {"lfo_1.rate", 0.0, 20.0, 1.0, 0},
+    {"lfo_1.mod_depth", -10.0, 20.0, 1.0, 0},
+    {"lfo_1.initial_phase", -kPi, kPi, 1.0, 0},
+    {"lfo_1.w_sin", 0.0, 1.0, 1.0, 0},
+    {"lfo_1.w_tri", 0.0, 1.0, 1.0, 0},
+    {"lfo_1.w_saw", 0.0, 1.0, 1.0, 0},
+    {"lfo_1.w_rsaw", 0.0, 1.0, 1.0, 0},
+    {"lfo_1.w_sqr", 0.0, 1.0, 1.0, 0},
+    {"lfo_2.rate", 0.0, 20.0, 1.0, 0},
+    {"lfo_2.mod_depth", -10.0, 20.0, 1.0, 0},
+    {"lfo_2.initial_phase", -kPi, kPi, 1.0, 0},
+    {"lfo_2.w_sin", 0.0, 1.0, 1.0, 0},
+    {"lfo_2.w_tri", 0.0, 1.0, 1.0, 0},
+    {"lfo_2.w_saw", 0.0, 1.0, 1.0, 0},
+    {"lfo_2.w_rsaw", 0.0, 1.0, 1.0, 0},
+    {"lfo_2.w_sqr", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.vco_1_pitch<-adsr_1", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.vco_1_pitch<-adsr_2", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.vco_1_pitch<-lfo_1", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.vco_1_pitch<-lfo_2", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.vco_1_amp<-adsr_1", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.vco_1_amp<-adsr_2", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.vco_1_amp<-lfo_1", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.vco_1_amp<-lfo_2", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.vco_2_pitch<-adsr_1", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.vco_2_pitch<-adsr_2", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.vco_2_pitch<-lfo_1", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.vco_2_pitch<-lfo_2", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.vco_2_amp<-adsr_1", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.vco_2_amp<-adsr_2", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.vco_2_amp<-lfo_1", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.vco_2_amp<-lfo_2", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.noise_amp<-adsr_1", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.noise_amp<-adsr_2", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.noise_amp<-lfo_1", 0.0, 1.0, 1.0, 0},
+    {"mod_matrix.noise_amp<-lfo_2", 0.0, 1.0, 1.0, 0},
+    {"vco_1.tuning", -24.0, 24.0, 1.0, 1},
+    {"vco_1.mod_depth", -12.0, 12.0, 1.0, 1},
+    {"vco_1.initial_phase", -kPi, kPi, 1.0, 0},
+    {"vco_2.tuning", -24.0, 24.0, 1.0, 1},
+    {"vco_2.mod_depth", -12.0, 12.0, 1.0, 1},
+    {"vco_2.initial_phase", -kPi, kPi, 1.0, 0},
+    {"vco_2.shape", 0.0, 1.0, 1.0, 0},
+    {"mixer.level_sine", 0.0, 1.0, 1.0, 0},
+    {"mixer.level_squaresaw", 0.0, 1.0, 1.0, 0},
+    {"mixer.level_noise", 0.0, 1.0, 1.0, 0},
+};
+}  // namespace
+
+int synth_param_info(int p, const char** name, double* min, double* max, double* curve,
+                     int* symmetric) {
+  if (p < 0 || p >= SYNTH_NUM_PARAMS) return SYNTH_EINVAL;
+  const ParamInfo& q = kParamInfo[p];
+  if (name) *name = q.name;
+  if (min) *min = q.lo;
+  if (max) *max = q.hi;
+  if (curve) *curve = q.curve;
+  if (symmetric) *symmetric = q.sym;
+  return SYNTH_OK;
+}
+
 const char* synth_status_string(int status) {
   switch (status) {
     case SYNTH_OK: return "ok";

@@ -41,6 +41,19 @@ def test_scalar_entry_points():
         assert bool(L.synth_is_test(g)) == ((g // 1024) % 10 == 9)
 
 
+def test_param_info_matches_default_nebula():
+    import paper_2104_12922_amd as S
+    names = W.param_names()
+    tab = W.default_nebula().table()
+    for p in range(78):
+        info = S.synth_param_info(p)
+        assert info["name"] == names[p]
+        assert (info["min"], info["max"], info["curve"], float(info["symmetric"])) == tuple(tab[p])
+    L = _native.lib()
+    assert L.synth_param_info(78, None, None, None, None, None) == EINVAL
+    assert L.synth_param_info(-1, None, None, None, None, None) == EINVAL
+
+
 def _render(cfg, params=1, ids=None, B=1, offsets=None, n=1000, audio=1, rps=4, slices=1,
             persistent=0, grid=0):
     L = _native.lib()
