@@ -13,8 +13,9 @@
 // Workgroup tile 256 (M) x 256 (N) x 32 (K), 512 threads = 8 wavefronts in
 // 2 (M) x 4 (N), each owning 128 x 64 = 4 x 2 blocks of
 // v_mfma_f32_32x32x16_bf16 (two wavefronts per SIMD).
-// Global loads for k-step s + 1 are issued before the MFMAs of step s and
-// land in the other LDS buffer afterwards (one barrier per k-step).  Tiles
+// Global loads for k-step s + 2 are issued before the MFMAs of step s (two
+// register sets) and written to LDS two steps later; the LDS tile is double
+// buffered (one barrier per k-step).  Tiles
 // are assigned so that consecutive tiles of one M row share an XCD (and its
 // L2), which reads every frame from HBM about once.
 //
@@ -73,9 +74,11 @@ __device__ __forceinline__ void dft_tile(const float* __restrict__ audio, const 
   const int b_c = (t & 3) * 8;
   const int b_r = t >> 2;
 
-  // prefetch registers: named scalars so that they stay in VGPRs
-  float4 ra0, ra1, ra2, ra3;
-  uint4 rb0, rb1;
+  // Two sets of prefetch registers (named scalars, so that they stay in
+  // VGPRs): the loads for k-step s + 2 are issued at the start of step s, so
+  // each has two steps of MFMA work to arrive before it is written to LDS.
+  float4 ra0, ra1, ra2, ra3, sa0, sa1, sa2, sa3;
+  uint4 rb0, rb1, sb0, sb1;
 
 #define DFT_LD1(RA, Q, K0)                                                      \
   if constexpr (VEC) {                                                          \
@@ -87,13 +90,12 @@ __device__ __forceinline__ void dft_tile(const float* __restrict__ audio, const 
     RA.z = *((K0) + 2 < lim[Q] ? abase[Q] + (K0) + 2 : audio);                  \
     RA.w = *((K0) + 3 < lim[Q] ? abase[Q] + (K0) + 3 : audio);                  \
   }
-#define DFT_LOAD(KS)                                                            \
+#define DFT_LOAD(A0, A1, A2, A3, B0, B1, KS)                                    \
   {                                                                             \
     const int k0 = (KS) * kBK + a_c;                                            \
-    DFT_LD1(ra0, 0, k0) DFT_LD1(ra1, 1, k0) DFT_LD1(ra2, 2, k0)                 \
-    DFT_LD1(ra3, 3, k0)                                                         \
-    rb0 = *reinterpret_cast<const uint4*>(bsrc0 + (KS) * kBK);                  \
-    rb1 = *reinterpret_cast<const uint4*>(bsrc1 + (KS) * kBK);                  \
+    DFT_LD1(A0, 0, k0) DFT_LD1(A1, 1, k0) DFT_LD1(A2, 2, k0) DFT_LD1(A3, 3, k0) \
+    B0 = *reinterpret_cast<const uint4*>(bsrc0 + (KS) * kBK);                   \
+    B1 = *reinterpret_cast<const uint4*>(bsrc1 + (KS) * kBK);                   \
   }
 #define DFT_ST1(RA, Q, K0, BUF)                                                 \
   {                                                                             \
@@ -102,13 +104,25 @@ __device__ __forceinline__ void dft_tile(const float* __restrict__ audio, const 
     w_.y = pack_bf16((K0) + 2 < lim[Q] ? RA.z : 0.0f, (K0) + 3 < lim[Q] ? RA.w : 0.0f); \
     *reinterpret_cast<uint2*>(&As[BUF][(Q) * 64 + a_r][a_c]) = w_;              \
   }
-#define DFT_STORE(KS, BUF)                                                      \
+#define DFT_STORE(A0, A1, A2, A3, B0, B1, KS, BUF)                              \
   {                                                                             \
     const int k0 = (KS) * kBK + a_c;                                            \
-    DFT_ST1(ra0, 0, k0, BUF) DFT_ST1(ra1, 1, k0, BUF) DFT_ST1(ra2, 2, k0, BUF)  \
-    DFT_ST1(ra3, 3, k0, BUF)                                                    \
-    *reinterpret_cast<uint4*>(&Bs[BUF][b_r][b_c]) = rb0;                        \
-    *reinterpret_cast<uint4*>(&Bs[BUF][128 + b_r][b_c]) = rb1;                  \
+    DFT_ST1(A0, 0, k0, BUF) DFT_ST1(A1, 1, k0, BUF) DFT_ST1(A2, 2, k0, BUF)     \
+    DFT_ST1(A3, 3, k0, BUF)                                                     \
+    *reinterpret_cast<uint4*>(&Bs[BUF][b_r][b_c]) = B0;                         \
+    *reinterpret_cast<uint4*>(&Bs[BUF][128 + b_r][b_c]) = B1;                   \
+  }
+#define DFT_MFMA(BUF)                                                           \
+  _Pragma("unroll") for (int kk = 0; kk < kBK; kk += 16) {                      \
+    const int kq = kk + 8 * (lane >> 5);                                        \
+    bf16x8 af[4], bf[2];                                                        \
+    _Pragma("unroll") for (int ii = 0; ii < 4; ++ii) af[ii] =                   \
+        *reinterpret_cast<const bf16x8*>(&As[BUF][wm * 128 + ii * 32 + (lane & 31)][kq]); \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j) bf[j] =                       \
+        *reinterpret_cast<const bf16x8*>(&Bs[BUF][wn * 64 + j * 32 + (lane & 31)][kq]); \
+    _Pragma("unroll") for (int ii = 0; ii < 4; ++ii)                            \
+      _Pragma("unroll") for (int j = 0; j < 2; ++j)                             \
+        acc[ii][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[ii], bf[j], acc[ii][j], 0, 0, 0); \
   }
 
   f32x16 acc[4][2];
@@ -119,38 +133,32 @@ __device__ __forceinline__ void dft_tile(const float* __restrict__ audio, const 
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[ii][j][v] = 0.0f;
 
-  DFT_LOAD(0)
-  DFT_STORE(0, 0)
+  static_assert(kKSteps % 2 == 0, "the k-loop is unrolled by two");
+  DFT_LOAD(ra0, ra1, ra2, ra3, rb0, rb1, 0)
+  DFT_LOAD(sa0, sa1, sa2, sa3, sb0, sb1, 1)
+  DFT_STORE(ra0, ra1, ra2, ra3, rb0, rb1, 0, 0)
   __syncthreads();
-  for (int ks = 0; ks < kKSteps; ++ks) {
-    const int buf = ks & 1;
-    const bool more = ks + 1 < kKSteps;
-    if (more) DFT_LOAD(ks + 1)
-    __builtin_amdgcn_sched_barrier(0);           // issue the prefetch before the MFMAs
-#pragma unroll
-    for (int kk = 0; kk < kBK; kk += 16) {
-      const int kq = kk + 8 * (lane >> 5);
-      bf16x8 af[4], bf[2];
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii)
-        af[ii] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 128 + ii * 32 + (lane & 31)][kq]);
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        bf[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn * 64 + j * 32 + (lane & 31)][kq]);
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[ii][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[ii], bf[j], acc[ii][j], 0, 0, 0);
-    }
-    __builtin_amdgcn_sched_barrier(0);           // wait for the prefetch only after them
-    if (more) DFT_STORE(ks + 1, buf ^ 1)
+  for (int ks = 0; ks < kKSteps; ks += 2) {
+    // step ks: LDS buffer 0 holds ks, set s (ks + 1) is in flight, set r is free
+    if (ks + 2 < kKSteps) DFT_LOAD(ra0, ra1, ra2, ra3, rb0, rb1, ks + 2)
+    __builtin_amdgcn_sched_barrier(0);
+    DFT_MFMA(0)
+    __builtin_amdgcn_sched_barrier(0);
+    DFT_STORE(sa0, sa1, sa2, sa3, sb0, sb1, ks + 1, 1)
+    __syncthreads();
+    // step ks + 1: LDS buffer 1 holds ks + 1, set r (ks + 2) is in flight
+    if (ks + 3 < kKSteps) DFT_LOAD(sa0, sa1, sa2, sa3, sb0, sb1, ks + 3)
+    __builtin_amdgcn_sched_barrier(0);
+    DFT_MFMA(1)
+    __builtin_amdgcn_sched_barrier(0);
+    if (ks + 2 < kKSteps) DFT_STORE(ra0, ra1, ra2, ra3, rb0, rb1, ks + 2, 0)
     __syncthreads();
   }
 #undef DFT_LD1
 #undef DFT_LOAD
 #undef DFT_ST1
 #undef DFT_STORE
+#undef DFT_MFMA
 
   // Epilogue: (Re, Im) of a bin sit in adjacent columns = adjacent lanes.
   // Column pair (0, 1) holds the real bins 0 and 1024.
