@@ -41,6 +41,9 @@ constexpr int kBM = 256, kBN = 256, kBK = 32, kLDK = kBK + 8, kThreads = 512;
 constexpr int kKSteps = kN / kBK;   // 64
 constexpr int kXcds = 8;
 
+// Source of the zeros read for frame samples past a voice's end.
+__device__ __align__(16) const float kZeros[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+
 __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
   const f32x2 v = {a, b};
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
@@ -54,14 +57,13 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 
 // The k-loop and epilogue of one tile.  The four frame rows this thread
 // stages start at abase[q] with lim[q] samples left in their voice; past that
-// the frame reads as 0.  Loads are unconditional (addresses of rows past the
-// voice's end are redirected to `audio`) and the mask is applied when the
-// registers are written to LDS, so nothing waits on a load before the MFMAs.
+// the frame reads as 0: those loads are redirected to a zero constant, so the
+// loads are unconditional and nothing waits on a load before the MFMAs.
 // VEC: every voice is 16-byte aligned with a length divisible by 4, so one
 // float4 is wholly inside or wholly outside; otherwise four scalar loads.
 template <bool VEC>
 __device__ __forceinline__ void dft_tile(const float* __restrict__ audio, const float* const (&abase)[4],
-                                         const int64_t (&lim)[4], const uint16_t* bsrc0,
+                                         const int (&lim)[4], const uint16_t* bsrc0,
                                          const uint16_t* bsrc1, uint16_t (*As)[kBM][kLDK],
                                          uint16_t (*Bs)[kBN][kLDK], int64_t m0, int64_t n0,
                                          int64_t rows, uint16_t* __restrict__ power, int64_t ldp) {
@@ -82,13 +84,13 @@ __device__ __forceinline__ void dft_tile(const float* __restrict__ audio, const 
 
 #define DFT_LD1(RA, Q, K0)                                                      \
   if constexpr (VEC) {                                                          \
-    const float* p_ = (K0) < lim[Q] ? abase[Q] + (K0) : audio;                  \
+    const float* p_ = (K0) < lim[Q] ? abase[Q] + (K0) : kZeros;                 \
     RA = *reinterpret_cast<const float4*>(p_);                                  \
   } else {                                                                      \
-    RA.x = *((K0) + 0 < lim[Q] ? abase[Q] + (K0) + 0 : audio);                  \
-    RA.y = *((K0) + 1 < lim[Q] ? abase[Q] + (K0) + 1 : audio);                  \
-    RA.z = *((K0) + 2 < lim[Q] ? abase[Q] + (K0) + 2 : audio);                  \
-    RA.w = *((K0) + 3 < lim[Q] ? abase[Q] + (K0) + 3 : audio);                  \
+    RA.x = *((K0) + 0 < lim[Q] ? abase[Q] + (K0) + 0 : kZeros);                 \
+    RA.y = *((K0) + 1 < lim[Q] ? abase[Q] + (K0) + 1 : kZeros);                 \
+    RA.z = *((K0) + 2 < lim[Q] ? abase[Q] + (K0) + 2 : kZeros);                 \
+    RA.w = *((K0) + 3 < lim[Q] ? abase[Q] + (K0) + 3 : kZeros);                 \
   }
 #define DFT_LOAD(A0, A1, A2, A3, B0, B1, KS)                                    \
   {                                                                             \
@@ -100,8 +102,8 @@ __device__ __forceinline__ void dft_tile(const float* __restrict__ audio, const 
 #define DFT_ST1(RA, Q, K0, BUF)                                                 \
   {                                                                             \
     uint2 w_;                                                                   \
-    w_.x = pack_bf16((K0) + 0 < lim[Q] ? RA.x : 0.0f, (K0) + 1 < lim[Q] ? RA.y : 0.0f); \
-    w_.y = pack_bf16((K0) + 2 < lim[Q] ? RA.z : 0.0f, (K0) + 3 < lim[Q] ? RA.w : 0.0f); \
+    w_.x = pack_bf16(RA.x, RA.y);                                               \
+    w_.y = pack_bf16(RA.z, RA.w);                                               \
     *reinterpret_cast<uint2*>(&As[BUF][(Q) * 64 + a_r][a_c]) = w_;              \
   }
 #define DFT_STORE(A0, A1, A2, A3, B0, B1, KS, BUF)                              \
@@ -213,7 +215,7 @@ __global__ void __launch_bounds__(kThreads) dft_power_kernel(const float* __rest
   const int64_t batch = rows >> 6;
   const int64_t pos = a_r * 2756;
   const float* abase[4];
-  int64_t lim[4];
+  int lim[4];
   bool vec = true;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -230,7 +232,8 @@ __global__ void __launch_bounds__(kThreads) dft_power_kernel(const float* __rest
     }
     vec = vec && (len & 3) == 0 && (reinterpret_cast<uintptr_t>(audio + start) & 15u) == 0;
     abase[q] = audio + start + pos;
-    lim[q] = len - pos;
+    const int64_t l = len - pos;                 // samples of the frame in the voice
+    lim[q] = (int)(l < 4096 ? (l > -1 ? l : -1) : 4096);
   }
   // B staging: 4 threads per row (16 bytes each), 128 rows per pass, 2 passes.
   const int b_c = (t & 3) * 8;
