@@ -146,3 +146,20 @@ def logmel_bf16(x: torch.Tensor, sr: float = 44100.0) -> torch.Tensor:
     M = torch.from_numpy(mel_filterbank(sr)).float().to(torch.bfloat16).to(F64)
     mel = torch.einsum("bk,ntk->nbt", M, P)
     return torch.log(mel + MEL_EPS)
+
+
+def logmel_p16(x: torch.Tensor, sr: float = 44100.0) -> torch.Tensor:
+    """Log-mel with the power spectrum and the mel basis rounded to bfloat16:
+    the windowed frames are formed in float32 (window and samples float32),
+    transformed exactly (float64 FFT), |X|^2 rounded through float32 to
+    bfloat16, projected with the bfloat16 mel basis in float64, log(+1e-6).
+    Returns [B, 128, 64]."""
+    n = MEL_NFFT
+    k = torch.arange(n, dtype=torch.float32)
+    w = 0.5 - 0.5 * torch.cos(2.0 * math.pi * k / n)                  # float32 window
+    fr = (frames(x.float(), n, MEL_HOP, count=MEL_FRAMES) * w).to(F64)
+    X = torch.fft.rfft(fr, dim=-1)                                    # [B, 64, 1025]
+    P = (X.real ** 2 + X.imag ** 2).float().to(torch.bfloat16).to(F64)
+    M = torch.from_numpy(mel_filterbank(sr)).float().to(torch.bfloat16).to(F64)
+    mel = torch.einsum("bk,ntk->nbt", M, P)
+    return torch.log(mel + MEL_EPS)

@@ -375,9 +375,12 @@ size_t synth_logmel_workspace(int64_t batch) {
 }
 
 int synth_logmel_init(double sample_rate, void* dft_basis, void* mel_basis, void* stream) {
-  if (!dft_basis || !mel_basis || !(sample_rate > 0.0)) return SYNTH_EINVAL;
-  hipError_t e = synth::launch_dft_basis(dft_basis, (hipStream_t)stream);
-  if (e != hipSuccess) return SYNTH_EDEVICE;
+  if (!mel_basis || !(sample_rate > 0.0)) return SYNTH_EINVAL;
+  hipError_t e = hipSuccess;
+  if (dft_basis) {
+    e = synth::launch_dft_basis(dft_basis, (hipStream_t)stream);
+    if (e != hipSuccess) return SYNTH_EDEVICE;
+  }
   // HTK mel triangles (mel = 2595 log10(1 + f / 700)), 130 edges from 0 to sr/2,
   // peak 1, no area normalisation; stored K-major [128][1032] in bf16.
   static thread_local uint16_t table[kMelBins * kMelLd];
@@ -402,22 +405,41 @@ int synth_logmel_init(double sample_rate, void* dft_basis, void* mel_basis, void
   return to_status(hipStreamSynchronize((hipStream_t)stream));
 }
 
-int synth_logmel(const float* audio, const int64_t* offsets, int64_t batch, int64_t n_samples,
-                 const void* dft_basis, const void* mel_basis, void* workspace,
-                 size_t workspace_bytes, float* features, void* stream) {
+namespace {
+int logmel_common(bool fft, const float* audio, const int64_t* offsets, int64_t batch,
+                  int64_t n_samples, const void* dft_basis, const void* mel_basis,
+                  void* workspace, size_t workspace_bytes, float* features, void* stream) {
   if (batch < 0) return SYNTH_EINVAL;
   if (batch == 0) return SYNTH_OK;
-  if (!audio || !dft_basis || !mel_basis || !workspace || !features) return SYNTH_EINVAL;
+  if (!audio || (!fft && !dft_basis) || !mel_basis || !workspace || !features) return SYNTH_EINVAL;
   if (!offsets && n_samples <= 0) return SYNTH_EINVAL;
   if (workspace_bytes < synth_logmel_workspace(batch)) return SYNTH_ENOMEM;
-  hipError_t e = synth::launch_dft_power(audio, offsets, offsets ? 0 : n_samples, batch,
-                                         dft_basis, workspace, kMelLd, (hipStream_t)stream);
+  const hipStream_t s = (hipStream_t)stream;
+  const int64_t n = offsets ? 0 : n_samples;
+  hipError_t e = fft ? synth::launch_melpower(audio, offsets, n, batch, workspace, kMelLd, s)
+                     : synth::launch_dft_power(audio, offsets, n, batch, dft_basis, workspace,
+                                               kMelLd, s);
   if (e != hipSuccess) return SYNTH_EDEVICE;
   synth::GemmArgs h = {};
   h.M = batch * kMelFrames; h.N = kMelBins; h.K = kMelNfft / 2 + 1;
   h.A = workspace; h.lda = kMelLd; h.B = mel_basis; h.ldb = kMelLd;
   h.C = features; h.ldc = kMelBins; h.c_bf16 = 0; h.epilogue = synth::kEpiLogMelT; h.alpha = 1.0f;
-  return to_status(synth::launch_gemm_bf16(h, synth::kOpKMajor, synth::kOpKMajor, (hipStream_t)stream));
+  return to_status(synth::launch_gemm_bf16(h, synth::kOpKMajor, synth::kOpKMajor, s));
+}
+}  // namespace
+
+int synth_logmel(const float* audio, const int64_t* offsets, int64_t batch, int64_t n_samples,
+                 const void* mel_basis, void* workspace, size_t workspace_bytes, float* features,
+                 void* stream) {
+  return logmel_common(true, audio, offsets, batch, n_samples, nullptr, mel_basis, workspace,
+                       workspace_bytes, features, stream);
+}
+
+int synth_logmel_mfma(const float* audio, const int64_t* offsets, int64_t batch,
+                      int64_t n_samples, const void* dft_basis, const void* mel_basis,
+                      void* workspace, size_t workspace_bytes, float* features, void* stream) {
+  return logmel_common(false, audio, offsets, batch, n_samples, dft_basis, mel_basis, workspace,
+                       workspace_bytes, features, stream);
 }
 
 int synth_colstats(const void* x, int x_bf16, int64_t rows, int64_t cols, int64_t ld, float* sum,

@@ -157,20 +157,13 @@ __device__ __forceinline__ int fft_passes(float2 (&v)[4], int j, float dir, cons
   }
 }
 
+// Twiddle, window and per-pass tables for frames of n = 512 << RES samples
+// (every thread of the workgroup takes part; ends with a barrier).
 template <int RES>
-__device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, int64_t b, int blk) {
-  constexpr int r = RES;
+__device__ __forceinline__ void fft_tables(SpecShared& sh) {
+  constexpr int n = 512 << RES;
+  constexpr int Nc = n / 2;
   const int tid = threadIdx.x;
-  const int chunk = blk - a.chunk_base[r];
-  constexpr int n = 512 << r;
-  constexpr int Nc = n / 2;             // complex points per transform
-  constexpr int tpt = Nc / 4;           // threads per transform
-  constexpr int ntr = kThreads / tpt;   // transforms in flight: 8, 4, 2
-  constexpr int fpi = ntr / 2;          // frames per iteration: 4, 2, 1
-  constexpr int hop = n / 4;
-  const int F = a.F[r];
-  const bool want_grad = a.wgrad != nullptr;
-
   for (int k = tid; k < n; k += kThreads) {
     float s, c;
     sincospif(2.0f * (float)k / (float)n, &s, &c);
@@ -188,6 +181,36 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, i
     if (R == 2) break;
   }
   __syncthreads();
+}
+
+// Bin k (0 <= k <= Nc) of the real spectrum of a frame of 2 Nc samples from
+// the half-size complex FFT Z (even samples real, odd imaginary; swizzled).
+template <int Nc>
+__device__ __forceinline__ float2 real_bin(const float2* Z, const float2* tw, int k) {
+  const float2 w = k < Nc ? tw[k] : make_float2(-1.0f, 0.0f);
+  const int kc = k == Nc ? 0 : k, km = k == 0 ? 0 : Nc - k;   // Z_Nc = Z_0
+  const float2 zk = Z[swz(kc)], zc = cconj(Z[swz(km)]);
+  const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+  const float2 D = csub(zk, zc);
+  const float2 O = make_float2(0.5f * D.y, -0.5f * D.x);       // -i D / 2
+  return cadd(E, cmul(w, O));
+}
+
+template <int RES>
+__device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, int64_t b, int blk) {
+  constexpr int r = RES;
+  const int tid = threadIdx.x;
+  const int chunk = blk - a.chunk_base[r];
+  constexpr int n = 512 << r;
+  constexpr int Nc = n / 2;             // complex points per transform
+  constexpr int tpt = Nc / 4;           // threads per transform
+  constexpr int ntr = kThreads / tpt;   // transforms in flight: 8, 4, 2
+  constexpr int fpi = ntr / 2;          // frames per iteration: 4, 2, 1
+  constexpr int hop = n / 4;
+  const int F = a.F[r];
+  const bool want_grad = a.wgrad != nullptr;
+
+  fft_tables<RES>(sh);
 
   const int tr = tid / tpt;             // transform of this thread
   const int j = tid - tr * tpt;         // butterfly index within the transform
@@ -220,23 +243,8 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, i
     float2* Hs = sh.buf[zb ^ 1] + slot * (Nc + 4);   // Hermitian half H_0 .. H_Nc (plain)
     const int u = tid - slot * 2 * tpt;
     for (int k = u; k <= Nc; k += 2 * tpt) {
-      const float2 tw = k < Nc ? sh.tw[k] : make_float2(-1.0f, 0.0f);
-      const int kc = k == Nc ? 0 : k, km = k == 0 ? 0 : Nc - k;   // Z_Nc = Z_0
-      float2 X, T;
-      {
-        const float2 zk = Zx[swz(kc)], zc = cconj(Zx[swz(km)]);
-        const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
-        const float2 D = csub(zk, zc);
-        const float2 O = make_float2(0.5f * D.y, -0.5f * D.x);     // -i D / 2
-        X = cadd(E, cmul(tw, O));
-      }
-      {
-        const float2 zk = Zt[swz(kc)], zc = cconj(Zt[swz(km)]);
-        const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
-        const float2 D = csub(zk, zc);
-        const float2 O = make_float2(0.5f * D.y, -0.5f * D.x);
-        T = cadd(E, cmul(tw, O));
-      }
+      const float2 X = real_bin<Nc>(Zx, sh.tw, k);
+      const float2 T = real_bin<Nc>(Zt, sh.tw, k);
       const float ax = sqrtf(X.x * X.x + X.y * X.y);
       const float at = sqrtf(T.x * T.x + T.y * T.y);
       const float d = logf(ax + kEps) - logf(at + kEps);
@@ -304,6 +312,62 @@ __global__ void __launch_bounds__(kThreads) mrstft_frames_kernel(const MrArgs a)
     mrstft_frames<2>(a, sh, b, blk);
 }
 
+// Power spectrum of the log-mel frames by FFT: voice b's frames f < 64 of
+// 2048 samples at hop 2756 (samples past the voice's end read as 0), periodic
+// Hann window, P[b * 64 + f][k] = |X_fk|^2 for k <= 1024, rounded to bf16.
+// One workgroup per voice, two frames (two 1024-point complex FFTs) at a time.
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__global__ void __launch_bounds__(kThreads) melpower_kernel(const float* __restrict__ audio,
+                                                           const int64_t* __restrict__ offsets,
+                                                           int64_t n_uniform,
+                                                           uint16_t* __restrict__ power,
+                                                           int64_t ldp) {
+  __shared__ SpecShared sh;
+  constexpr int n = 2048, Nc = 1024, tpt = 256, hop = 2756, frames = 64;
+  const int tid = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  int64_t start, len;
+  if (offsets) {
+    start = offsets[b];
+    len = offsets[b + 1] - start;
+  } else {
+    start = b * n_uniform;
+    len = n_uniform;
+  }
+  const float* x = audio + start;
+  fft_tables<2>(sh);
+  const int tr = tid / tpt;             // 0, 1: the iteration's two frames
+  const int j = tid - tr * tpt;
+  for (int f0 = 0; f0 < frames; f0 += 2) {
+    const int f = f0 + tr;
+    const int64_t pos = (int64_t)f * hop;
+    float2 v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = j + q * tpt;
+      const int64_t i0 = pos + 2 * m;
+      const float s0 = i0 < len ? x[i0] : 0.0f;
+      const float s1 = i0 + 1 < len ? x[i0 + 1] : 0.0f;
+      v[q] = make_float2(sh.win[2 * m] * s0, sh.win[2 * m + 1] * s1);
+    }
+    float2* b0 = sh.buf[0] + tr * Nc;
+    float2* b1 = sh.buf[1] + tr * Nc;
+    const int zb = fft_passes<Nc, 1, 0>(v, j, -1.0f, sh.ptw, b0, b1, true);
+    const float2* Z = sh.buf[zb] + tr * Nc;
+    uint16_t* prow = power + (b * frames + f) * ldp;
+    for (int k = j; k <= Nc; k += tpt) {
+      const float2 X = real_bin<Nc>(Z, sh.tw, k);
+      prow[k] = f2bf(X.x * X.x + X.y * X.y);
+    }
+    __syncthreads();                    // the buffers are reused by the next frames
+  }
+}
+
 // grad[b][i] = sum over resolutions, then frames f covering i, of the frame
 // row at i - f hop; block x == 0 also sums voice b's loss partials.
 __global__ void __launch_bounds__(256) mrstft_combine_kernel(const MrArgs a) {
@@ -348,6 +412,15 @@ void plan(int64_t batch, int64_t n_samples, MrArgs& a, size_t& partial_bytes, si
 }
 
 }  // namespace
+
+hipError_t launch_melpower(const float* audio, const int64_t* offsets, int64_t n_uniform,
+                           int64_t batch, void* power, int64_t ldp, hipStream_t s) {
+  if (batch == 0) return hipSuccess;
+  if (batch > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(melpower_kernel, dim3((unsigned)batch), dim3(kThreads), 0, s, audio, offsets,
+                     n_uniform, (uint16_t*)power, ldp);
+  return hipGetLastError();
+}
 
 size_t mrstft_workspace_bytes(int64_t batch, int64_t n_samples, bool with_grad) {
   MrArgs a = {};

@@ -111,6 +111,9 @@ int64_t adjoint_max_chunks();
 hipError_t launch_render_backward(const RenderArgs& a, const float* grad_audio, double* ws,
                                   float* grad_params, int runs_per_segment, hipStream_t s);
 
+// log-mel power spectrum by FFT (spectral.hip): power bf16 [batch * 64][ldp]
+hipError_t launch_melpower(const float* audio, const int64_t* offsets, int64_t n_uniform,
+                           int64_t batch, void* power, int64_t ldp, hipStream_t s);
 size_t mrstft_workspace_bytes(int64_t batch, int64_t n_samples, bool with_grad);
 hipError_t launch_mrstft(const float* x, const float* target, int64_t batch, int64_t n_samples,
                          double* loss, float* grad, void* workspace, hipStream_t s);

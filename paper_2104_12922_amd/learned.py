@@ -28,7 +28,8 @@ def _sig(L):
     L.synth_logmel_workspace.restype = sz
     L.synth_logmel_workspace.argtypes = [i64]
     L.synth_logmel_init.argtypes = [ctypes.c_double, vp, vp, vp]
-    L.synth_logmel.argtypes = [vp, vp, i64, i64, vp, vp, vp, sz, vp, vp]
+    L.synth_logmel.argtypes = [vp, vp, i64, i64, vp, vp, sz, vp, vp]
+    L.synth_logmel_mfma.argtypes = [vp, vp, i64, i64, vp, vp, vp, sz, vp, vp]
     L.synth_colstats.argtypes = [vp, i32, i64, i64, i64, vp, vp, vp]
     L.synth_standardize.argtypes = [vp, vp, vp, i64, i64, vp, vp]
     L.synth_feature_stats.argtypes = [vp, i64, i64, f32, vp, vp, vp]
@@ -39,7 +40,8 @@ def _sig(L):
     L.synth_logit_init.argtypes = [vp, vp, vp, i64, f32, vp]
     L.synth_logit_adam.argtypes = [i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]
     L.synth_best_update.argtypes = [vp, i64, i64, i64, i64, i64, vp, i64, vp, vp, vp, vp]
-    for n in ("synth_gemm_bf16", "synth_logmel_init", "synth_logmel", "synth_colstats",
+    for n in ("synth_gemm_bf16", "synth_logmel_init", "synth_logmel", "synth_logmel_mfma",
+              "synth_colstats",
               "synth_standardize", "synth_to_bf16", "synth_mlp_forward", "synth_mlp_backward",
               "synth_adam", "synth_feature_stats", "synth_logit_init", "synth_logit_adam", "synth_best_update"):
         getattr(L, n).restype = ctypes.c_int
@@ -79,14 +81,22 @@ def gemm_bf16(A, B, M, N, K, a_layout=0, b_layout=0, lda=None, ldb=None, out=Non
 
 
 class LogMel:
-    """Log-mel features [B, 128 * 64] (mel-bin major) of 4 s renders."""
+    """Log-mel features [B, 128 * 64] (mel-bin major) of renders.
 
-    def __init__(self, sample_rate: float = 44100.0, device="cuda"):
+    method "fft" (default): float32 FFT power spectrum; "mfma": the power
+    spectrum as a bf16 DFT GEMM on the matrix cores."""
+
+    def __init__(self, sample_rate: float = 44100.0, device="cuda", method: str = "fft"):
+        if method not in ("fft", "mfma"):
+            raise ValueError("method must be 'fft' or 'mfma'")
         self.device = torch.device(device)
-        self.dft = torch.empty(2048, 2048, dtype=BF16, device=self.device)
+        self.method = method
+        self.dft = (torch.empty(2048, 2048, dtype=BF16, device=self.device)
+                    if method == "mfma" else None)
         self.mel = torch.empty(128, 1032, dtype=BF16, device=self.device)
         _native.check("synth_logmel_init", lib().synth_logmel_init(
-            float(sample_rate), self.dft.data_ptr(), self.mel.data_ptr(), _stream(self.device)))
+            float(sample_rate), self.dft.data_ptr() if self.dft is not None else None,
+            self.mel.data_ptr(), _stream(self.device)))
         self._ws = None
 
     def __call__(self, audio: torch.Tensor, out: torch.Tensor | None = None,
@@ -104,10 +114,14 @@ class LogMel:
             self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         if out is None:
             out = torch.empty(B, MEL_FEATURES, dtype=F32, device=self.device)
-        _native.check("synth_logmel", lib().synth_logmel(
-            _p(audio, "audio", F32, audio.numel()), offp, B, N, self.dft.data_ptr(),
-            self.mel.data_ptr(), self._ws.data_ptr(), self._ws.numel(),
-            _p(out, "features", F32, B * MEL_FEATURES), _stream(self.device)))
+        common = (_p(audio, "audio", F32, audio.numel()), offp, B, N)
+        tail = (self.mel.data_ptr(), self._ws.data_ptr(), self._ws.numel(),
+                _p(out, "features", F32, B * MEL_FEATURES), _stream(self.device))
+        if self.method == "fft":
+            _native.check("synth_logmel", lib().synth_logmel(*common, *tail))
+        else:
+            _native.check("synth_logmel_mfma",
+                          lib().synth_logmel_mfma(*common, self.dft.data_ptr(), *tail))
         return out
 
 

@@ -68,14 +68,17 @@ def test_gemm_epilogues(L, epi):
     assert rel(Cb.cpu().double(), ref) < 5e-3
 
 
-def test_logmel_matches_bf16_reference(L):
+@pytest.mark.parametrize("method", ["fft", "mfma"])
+def test_logmel_matches_bf16_reference(L, method):
+    """FFT path against the reference rounding P and the mel basis to bf16;
+    MFMA path against the reference rounding frames, basis, P and mel to bf16."""
     u = philox.sample_params(0, np.arange(6))
     x = voice.render_uniform(torch.tensor(u), np.arange(6), 176400, W.default_nebula().table()).float()
-    feat = L.LogMel()(x.cuda())
+    feat = L.LogMel(method=method)(x.cuda())
     torch.cuda.synchronize()
-    ref = sp.logmel_bf16(x.double()).reshape(6, -1)
+    ref = (sp.logmel_p16 if method == "fft" else sp.logmel_bf16)(x.double()).reshape(6, -1)
     d = (feat.cpu().double() - ref).abs()
-    print("logmel max abs", float(d.max()), "median", float(d.median()), file=sys.stderr)
+    print(method, "logmel max abs", float(d.max()), "median", float(d.median()), file=sys.stderr)
     assert float(d.median()) < 1e-4
     assert float(d.max()) < 5e-3
 
@@ -152,7 +155,8 @@ def test_short_training_reduces_loss(L):
     assert float(per[0]) < 0.5 / 12
 
 
-def test_logmel_ragged_and_short_voices_read_as_zero_padded(L):
+@pytest.mark.parametrize("method", ["fft", "mfma"])
+def test_logmel_ragged_and_short_voices_read_as_zero_padded(L, method):
     """Ragged voices (1..4 s, packed) give the features of the same renders
     zero-padded to 4 s, bit for bit, and match the bf16 reference."""
     n4 = 176400
@@ -164,13 +168,13 @@ def test_logmel_ragged_and_short_voices_read_as_zero_padded(L):
         padded[b, n:] = 0
     packed = torch.cat([full[b, :n] for b, n in enumerate(lens)])
     offs = torch.tensor(np.concatenate([[0], np.cumsum(lens)]), dtype=torch.int64)
-    lm = L.LogMel()
+    lm = L.LogMel(method=method)
     fr = lm(packed.cuda(), offsets=offs.cuda())
     fp = lm(padded.cuda())
     fs = lm(full[:, :50000].contiguous().cuda())          # uniform but shorter than the frames span
     torch.cuda.synchronize()
     assert torch.equal(fr.cpu(), fp.cpu())
-    ref = sp.logmel_bf16(padded.double()).reshape(4, -1)
+    ref = (sp.logmel_p16 if method == "fft" else sp.logmel_bf16)(padded.double()).reshape(4, -1)
     d = (fr.cpu().double() - ref).abs()
     assert float(d.median()) < 1e-4 and float(d.max()) < 5e-3
     short = torch.zeros(4, n4)

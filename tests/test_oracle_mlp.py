@@ -65,3 +65,16 @@ def test_logmel_bf16_within_bf16_error_of_float64():
     loud = a > math.log(1e-3)
     assert float(d[loud].median()) < 2e-2
     assert (b.argmax(1) == a.argmax(1)).float().mean() > 0.9
+
+
+def test_logmel_p16_within_bf16_rounding_of_float64():
+    """Rounding only the power spectrum and the mel basis to bf16 moves a loud
+    band by at most the two roundings (2 x 2^-9 relative, ~4e-3 in log)."""
+    u = philox.sample_params(1, np.arange(2))
+    x = voice.render_uniform(torch.tensor(u), np.arange(2), 176400, W.default_nebula().table())
+    a = sp.logmel(x)
+    b = sp.logmel_p16(x)
+    loud = a > math.log(1e-2)
+    assert bool(loud.any())
+    assert float((a - b).abs()[loud].max()) < 1e-2
+    assert float((a - b).abs()[loud].median()) < 3e-3
