@@ -108,8 +108,9 @@ int synth_render(const synth_config* cfg, const float* params, const uint64_t* v
 
 /* Same as synth_render with an explicit launch plan (used by the autotuner and
  * by tests): runs_per_segment in {1, 2, 4} splits each control period into
- * that many per-lane runs; slices_per_voice >= 1 splits each voice (uniform
- * lengths only) over that many workgroups; persistent != 0 launches
+ * that many per-lane runs; slices_per_voice >= 1 splits each voice over that
+ * many workgroups (each takes a contiguous share of the voice's 62-period
+ * chunks; uniform lengths must have at least that many chunks); persistent != 0 launches
  * grid_blocks workgroups (0 => chosen by the library) of which workgroup w
  * renders voices w, w + grid_blocks, w + 2 * grid_blocks, ... (no device
  * state).  Fails with SYNTH_EUNSUPPORTED for a plan the configuration cannot

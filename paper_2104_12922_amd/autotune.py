@@ -24,16 +24,20 @@ from . import synth_render_plan
 def default_candidates(batch: int, uniform: bool):
     """Plans worth timing (the library's default plan first): 4 or 2 runs per
     control period; one workgroup per voice, or a persistent grid of 4-16
-    workgroups per CU (256 CUs); uniform batches smaller than the CU count
-    also try splitting voices into slices."""
+    workgroups per CU (256 CUs); batches of up to 8192 voices also try
+    splitting each voice over 2-8 workgroups (slices), which evens out the
+    load when lengths differ."""
     c = []
     for rps in (4, 2):
         c.append((rps, 1, 0, 0))
         for g in (1024, 2048, 4096):
             if g < batch:
                 c.append((rps, 1, 1, g))
-        if uniform and batch < 256:
+        if batch < 256 and uniform:
             for sl in (2, 4, 8):
+                c.append((rps, sl, 0, 0))
+        elif batch <= 8192:
+            for sl in (2, 4):
                 c.append((rps, sl, 0, 0))
     return c
 

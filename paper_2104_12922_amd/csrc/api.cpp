@@ -218,7 +218,6 @@ int synth_render_plan(const synth_config* cfg, const float* params, const uint64
   if (a.q % runs_per_segment != 0) return SYNTH_EUNSUPPORTED;
   if (a.q / runs_per_segment > 192) return SYNTH_EUNSUPPORTED;   // LDS tile <= 48 KB
   if (slices_per_voice < 1 || grid_blocks < 0) return SYNTH_EINVAL;
-  if (offsets && slices_per_voice != 1) return SYNTH_EUNSUPPORTED;
   if (!offsets) {
     const int64_t J = (n_samples + a.q - 1) / a.q;
     const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;

@@ -81,7 +81,6 @@ def test_render_argument_checks_before_launch():
     assert _render(cfg, n=0) == EINVAL
     assert _render(cfg, rps=3) == EINVAL
     assert _render(cfg, slices=0) == EINVAL
-    assert _render(cfg, offsets=1, slices=2) == EUNSUP
     assert _render(cfg, n=100, slices=5) == EUNSUP     # more slices than chunks
     c2, k2 = cfg_with(mix_mode=2)
     assert _render(c2) == EINVAL

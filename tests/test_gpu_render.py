@@ -157,6 +157,21 @@ def test_launch_plans_bit_identical(synth, nebula_table):
         assert np.abs(y.cpu().numpy() - ref).max() <= TOL, rps
 
 
+def test_ragged_slices_bit_identical(synth):
+    """Splitting ragged voices over workgroups (including voices shorter than
+    the number of slices' worth of chunks, and empty voices) changes nothing."""
+    lengths = np.array([44100, 0, 1, 6200, 176400, 99, 88200, 132300, 12401, 176400])
+    off = torch.from_numpy(np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)).cuda()
+    tab = W.default_nebula(duration_min=0.1).table()
+    u = synth.synth_sample_params(4, 0, lengths.size)
+    base = synth.synth_render_plan(u, tab, 4, 1, offsets=off, noise_seed=4)
+    for sl in (2, 3, 8):
+        y = synth.synth_render_plan(u, tab, 4, sl, offsets=off, noise_seed=4)
+        assert torch.equal(y, base), sl
+    y = synth.synth_render_plan(u, tab, 4, 4, True, 7, offsets=off, noise_seed=4)
+    assert torch.equal(y, base)
+
+
 def test_autotuner_picks_a_plan_and_renders_with_it(synth):
     from paper_2104_12922_amd.autotune import RenderTuner
     wl = W.ragged_batch(600)
