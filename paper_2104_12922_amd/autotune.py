@@ -24,7 +24,7 @@ from . import synth_render_plan
 def default_candidates(batch: int, uniform: bool):
     """Plans worth timing (the library's default plan first): 4 or 2 runs per
     control period; one workgroup per voice, or a persistent grid of 4-16
-    workgroups per CU (256 CUs); batches of up to 8192 voices also try
+    workgroups per CU (256 CUs); batches of up to 16384 voices also try
     splitting each voice over 2-8 workgroups (slices), which evens out the
     load when lengths differ."""
     c = []
@@ -36,8 +36,8 @@ def default_candidates(batch: int, uniform: bool):
         if batch < 256 and uniform:
             for sl in (2, 4, 8):
                 c.append((rps, sl, 0, 0))
-        elif batch <= 8192:
-            for sl in (2, 4):
+        elif batch <= 16384:
+            for sl in (2, 3, 4):
                 c.append((rps, sl, 0, 0))
     return c
 
@@ -52,11 +52,14 @@ class RenderTuner:
 
     @staticmethod
     def key(batch: int, n_samples: int | None, offsets: torch.Tensor | None) -> str:
+        """Batch shape: uniform length, or the histogram of ragged lengths (the
+        plan's speed depends on the mix of lengths, not on their order)."""
         if offsets is None:
             return f"u:{batch}:{int(n_samples)}"
-        lens = torch.diff(offsets).cpu().numpy()
-        h = int(np.bitwise_xor.reduce(lens.astype(np.int64) * 1000003 + np.arange(lens.size)))
-        return f"r:{batch}:{int(lens.sum())}:{h & 0xFFFFFFFF:08x}"
+        lens = torch.diff(offsets).cpu().numpy().astype(np.int64)
+        vals, counts = np.unique(lens, return_counts=True)
+        h = hash((tuple(vals.tolist()), tuple(counts.tolist()))) & 0xFFFFFFFF
+        return f"r:{batch}:{int(lens.sum())}:{h:08x}"
 
     def tune(self, params, nebula, n_samples=None, offsets=None, out=None, **kw):
         B = params.shape[0]

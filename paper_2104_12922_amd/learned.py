@@ -317,12 +317,23 @@ class Proposal:
         return self.mlp.forward(self.features(audio, offsets)).clone()
 
 
-def render_batch(seed, ids, nebula_table, lengths_s=(1, 2, 3, 4)):
-    """(u, packed audio, offsets) of voices ids drawn and rendered on the GPU."""
+_TUNER = None
+
+
+def render_batch(seed, ids, nebula_table, lengths_s=(1, 2, 3, 4), tune: bool = True):
+    """(u, packed audio, offsets) of voices ids drawn and rendered on the GPU
+    (with the launch plan the autotuner picked for this batch shape)."""
+    global _TUNER
     from . import synth_render, synth_sample_params
     offs = ragged_offsets(ids, lengths_s)
     u = synth_sample_params(seed, voice_ids=ids)
-    audio = synth_render(u, nebula_table, offsets=offs, voice_ids=ids, noise_seed=seed)
+    if tune:
+        if _TUNER is None:
+            from .autotune import RenderTuner
+            _TUNER = RenderTuner(reps=3)
+        audio = _TUNER.render(u, nebula_table, offsets=offs, voice_ids=ids, noise_seed=seed)
+    else:
+        audio = synth_render(u, nebula_table, offsets=offs, voice_ids=ids, noise_seed=seed)
     return u, audio, offs
 
 
