@@ -73,43 +73,28 @@ __device__ __forceinline__ void stage(uint16_t (*dst)[PADK], const GemmArgs& g, 
       }
     }
   } else if constexpr (OP == kOpRowMajorMN) {
-    // X[k * ld + r]: threads 0..63 each transpose one 8 (k) x 8 (r) block in
-    // registers - eight 16-byte loads along r, 32 half-word packs, eight
-    // 16-byte LDS writes of 8 consecutive k for one r.
-    if (t < 64) {
-      const uint16_t* src = reinterpret_cast<const uint16_t*>(srcv);
-      const int rb = (t & 15) * 8;          // 16 blocks of 8 rows
-      const int kb = (t >> 4) * 8;          // 4 blocks of 8 k
-      const int64_t gr = row0 + rb;
-      const bool vec = gr + 8 <= nrows && ((ld & 7) == 0) && aligned16(src);
-      uint32_t w[8][4];
+    const uint16_t* src = reinterpret_cast<const uint16_t*>(srcv);
+    const int kk = t >> 3;                // 32 k rows, 8 threads per k
+    const int r0 = (t & 7) * 16;
+    const int64_t gk = k0 + kk;
+    uint16_t v[16];
+    const bool full = gk < K && row0 + r0 + 16 <= nrows && ((ld & 7) == 0) && aligned16(src);
+    if (full) {
+      const uint4* p = reinterpret_cast<const uint4*>(src + gk * ld + row0 + r0);
+      const uint4 a = p[0], b = p[1];
+      const uint16_t* pa = reinterpret_cast<const uint16_t*>(&a);
+      const uint16_t* pb = reinterpret_cast<const uint16_t*>(&b);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t gk = k0 + kb + e;
-        if (vec && gk < K) {
-          const uint4 v = *reinterpret_cast<const uint4*>(src + gk * ld + gr);
-          w[e][0] = v.x; w[e][1] = v.y; w[e][2] = v.z; w[e][3] = v.w;
-        } else {
-          uint16_t h[8];
+      for (int e = 0; e < 8; ++e) { v[e] = pa[e]; v[8 + e] = pb[e]; }
+    } else {
 #pragma unroll
-          for (int i = 0; i < 8; ++i)
-            h[i] = (gk < K && gr + i < nrows) ? src[gk * ld + gr + i] : (uint16_t)0;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) w[e][q] = (uint32_t)h[2 * q] | ((uint32_t)h[2 * q + 1] << 16);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        uint4 o;
-        uint32_t* ow = reinterpret_cast<uint32_t*>(&o);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const uint32_t lo = w[2 * q][r >> 1], hi = w[2 * q + 1][r >> 1];
-          ow[q] = (r & 1) ? ((lo >> 16) | (hi & 0xFFFF0000u)) : ((lo & 0xFFFFu) | (hi << 16));
-        }
-        *reinterpret_cast<uint4*>(&dst[rb + r][kb]) = o;
+      for (int e = 0; e < 16; ++e) {
+        const int64_t gr = row0 + r0 + e;
+        v[e] = (gk < K && gr < nrows) ? src[gk * ld + gr] : (uint16_t)0;
       }
     }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) dst[r0 + e][kk] = v[e];
   }
 }
 
