@@ -245,14 +245,16 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, i
     for (int k = u; k <= Nc; k += 2 * tpt) {
       const float2 X = real_bin<Nc>(Zx, sh.tw, k);
       const float2 T = real_bin<Nc>(Zt, sh.tw, k);
-      const float ax = sqrtf(X.x * X.x + X.y * X.y);
-      const float at = sqrtf(T.x * T.x + T.y * T.y);
-      const float d = logf(ax + kEps) - logf(at + kEps);
+      // hardware sqrt, log2 and reciprocal (about 1 ulp each)
+      const float ax = __builtin_amdgcn_sqrtf(X.x * X.x + X.y * X.y);
+      const float at = __builtin_amdgcn_sqrtf(T.x * T.x + T.y * T.y);
+      const float d = 0.69314718055994531f *
+                      (__builtin_amdgcn_logf(ax + kEps) - __builtin_amdgcn_logf(at + kEps));
       if (live) acc += scale * (double)fabsf(d);
       if (want_grad) {
         float2 G = make_float2(0.f, 0.f);
         if (live && ax > 0.0f && d != 0.0f) {
-          const float gm = copysignf((float)scale, d) / ((ax + kEps) * ax);
+          const float gm = copysignf((float)scale, d) * __builtin_amdgcn_rcpf((ax + kEps) * ax);
           G = make_float2(gm * X.x, gm * X.y);
         }
         if (k == 0 || k == Nc) G = make_float2(2.0f * G.x, 0.0f);
