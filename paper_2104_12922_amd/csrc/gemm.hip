@@ -7,7 +7,8 @@
 // Tiles of 128 x 128 x 32 per 256-thread workgroup (four wavefronts in 2 x 2,
 // each 64 x 64 as 2 x 2 MFMA 32 x 32 blocks).  Tiles are staged in LDS as
 // [row][k] with K contiguous (rows padded by 16 bytes), so every lane's
-// 8-element MFMA fragment is one 16-byte LDS read.
+// 8-element MFMA fragment is one 16-byte LDS read; the LDS tiles are double
+// buffered and the next k-step is prefetched into registers.
 //
 // MFMA 32x32x16 lane layout (verified on gfx950): A fragment = row (lane % 32),
 // k = 8 (lane / 32) .. +7; B fragment = column (lane % 32), same k; the 16
@@ -49,59 +50,77 @@ __device__ __forceinline__ bool aligned16(const void* p) {
   return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
 }
 
-// Stage a 128 x 32 tile (rows row0.., k k0..) of an operand into dst[row][k].
+// Staging of a 128 x 32 tile (rows row0.., k k0..) of an operand into
+// dst[row][k], in two phases so that the loads of the next k-step can be in
+// flight during the MFMAs: load() fills two 16-byte registers per thread,
+// store() writes them to LDS.
+//   K-major: thread t takes row t / 2, k (t & 1) * 16 .. +15 (32 bytes).
+//   row-major (X[k * ld + r]): thread t takes k t / 8, rows (t & 7) * 16 ..
+//   +15, written to LDS transposed (16 two-byte writes).
+// Tiles at the matrix edge (or unaligned operands) are read element by
+// element with bounds checks and zero fill.
 template <int OP>
-__device__ __forceinline__ void stage(uint16_t (*dst)[PADK], const GemmArgs& g, const void* srcv,
-                                      int64_t ld, int64_t row0, int64_t nrows, int64_t k0) {
+__device__ __forceinline__ void load_tile(uint4& r0, uint4& r1, const GemmArgs& g,
+                                          const void* srcv, int64_t ld, int64_t row0,
+                                          int64_t nrows, int64_t k0) {
   const int t = threadIdx.x;
   const int64_t K = g.K;
+  const uint16_t* src = reinterpret_cast<const uint16_t*>(srcv);
+  uint16_t v[16];
   if constexpr (OP == kOpKMajor) {
-    const uint16_t* src = reinterpret_cast<const uint16_t*>(srcv);
-    const int r = t >> 1;                 // 128 rows, 2 threads per row
-    const int kk = (t & 1) * 16;
-    const int64_t gr = row0 + r;
-    const bool full = gr < nrows && k0 + kk + 16 <= K && ((ld & 7) == 0) && aligned16(src);
-    if (full) {
-      const uint4* p = reinterpret_cast<const uint4*>(src + gr * ld + k0 + kk);
-      *reinterpret_cast<uint4*>(&dst[r][kk]) = p[0];
-      *reinterpret_cast<uint4*>(&dst[r][kk + 8]) = p[1];
-    } else {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int64_t gk = k0 + kk + e;
-        dst[r][kk + e] = (gr < nrows && gk < K) ? src[gr * ld + gk] : (uint16_t)0;
-      }
-    }
-  } else if constexpr (OP == kOpRowMajorMN) {
-    const uint16_t* src = reinterpret_cast<const uint16_t*>(srcv);
-    const int kk = t >> 3;                // 32 k rows, 8 threads per k
-    const int r0 = (t & 7) * 16;
-    const int64_t gk = k0 + kk;
-    uint16_t v[16];
-    const bool full = gk < K && row0 + r0 + 16 <= nrows && ((ld & 7) == 0) && aligned16(src);
-    if (full) {
-      const uint4* p = reinterpret_cast<const uint4*>(src + gk * ld + row0 + r0);
-      const uint4 a = p[0], b = p[1];
-      const uint16_t* pa = reinterpret_cast<const uint16_t*>(&a);
-      const uint16_t* pb = reinterpret_cast<const uint16_t*>(&b);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) { v[e] = pa[e]; v[8 + e] = pb[e]; }
-    } else {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int64_t gr = row0 + r0 + e;
-        v[e] = (gk < K && gr < nrows) ? src[gk * ld + gr] : (uint16_t)0;
-      }
+    const int64_t gr = row0 + (t >> 1);
+    const int64_t kb = k0 + (t & 1) * 16;
+    if (gr < nrows && kb + 16 <= K && ((ld & 7) == 0) && aligned16(src)) {
+      const uint4* p = reinterpret_cast<const uint4*>(src + gr * ld + kb);
+      r0 = p[0];
+      r1 = p[1];
+      return;
     }
 #pragma unroll
-    for (int e = 0; e < 16; ++e) dst[r0 + e][kk] = v[e];
+    for (int e = 0; e < 16; ++e)
+      v[e] = (gr < nrows && kb + e < K) ? src[gr * ld + kb + e] : (uint16_t)0;
+  } else {
+    const int64_t gk = k0 + (t >> 3);
+    const int64_t gr = row0 + (t & 7) * 16;
+    if (gk < K && gr + 16 <= nrows && ((ld & 7) == 0) && aligned16(src)) {
+      const uint4* p = reinterpret_cast<const uint4*>(src + gk * ld + gr);
+      r0 = p[0];
+      r1 = p[1];
+      return;
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      v[e] = (gk < K && gr + e < nrows) ? src[gk * ld + gr + e] : (uint16_t)0;
+  }
+  r0 = make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16),
+                  v[4] | ((uint32_t)v[5] << 16), v[6] | ((uint32_t)v[7] << 16));
+  r1 = make_uint4(v[8] | ((uint32_t)v[9] << 16), v[10] | ((uint32_t)v[11] << 16),
+                  v[12] | ((uint32_t)v[13] << 16), v[14] | ((uint32_t)v[15] << 16));
+}
+
+template <int OP>
+__device__ __forceinline__ void store_tile(const uint4& r0, const uint4& r1,
+                                           uint16_t (*dst)[PADK]) {
+  const int t = threadIdx.x;
+  if constexpr (OP == kOpKMajor) {
+    const int r = t >> 1, kk = (t & 1) * 16;
+    *reinterpret_cast<uint4*>(&dst[r][kk]) = r0;
+    *reinterpret_cast<uint4*>(&dst[r][kk + 8]) = r1;
+  } else {
+    const int kk = t >> 3, rr = (t & 7) * 16;
+    const uint32_t w[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      dst[rr + 2 * e][kk] = (uint16_t)(w[e] & 0xFFFFu);
+      dst[rr + 2 * e + 1][kk] = (uint16_t)(w[e] >> 16);
+    }
   }
 }
 
 template <int AOP, int BOP>
 __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
-  __shared__ __align__(16) uint16_t As[BM][PADK];
-  __shared__ __align__(16) uint16_t Bs[BN][PADK];
+  __shared__ __align__(16) uint16_t As[2][BM][PADK];
+  __shared__ __align__(16) uint16_t Bs[2][BN][PADK];
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wave = t >> 6;
@@ -118,25 +137,43 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-  for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
-    stage<AOP>(As, g, g.A, g.lda, m0, g.M, k0);
-    stage<BOP>(Bs, g, g.B, g.ldb, n0, g.N, k0);
-    __syncthreads();
+  // LDS double buffer; the next k-step's tiles are loaded into registers
+  // before this step's MFMAs and written to the other buffer after them.
+  uint4 a0, a1, b0, b1;
+  load_tile<AOP>(a0, a1, g, g.A, g.lda, m0, g.M, 0);
+  load_tile<BOP>(b0, b1, g, g.B, g.ldb, n0, g.N, 0);
+  store_tile<AOP>(a0, a1, As[0]);
+  store_tile<BOP>(b0, b1, Bs[0]);
+  __syncthreads();
+  const int64_t nk = (g.K + BK - 1) / BK;
+  for (int64_t ks = 0; ks < nk; ++ks) {
+    const int buf = (int)(ks & 1);
+    const bool more = ks + 1 < nk;
+    if (more) {
+      load_tile<AOP>(a0, a1, g, g.A, g.lda, m0, g.M, (ks + 1) * BK);
+      load_tile<BOP>(b0, b1, g, g.B, g.ldb, n0, g.N, (ks + 1) * BK);
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int ks = 0; ks < BK; ks += 16) {
-      const int kq = ks + 8 * (lane >> 5);
+    for (int kk = 0; kk < BK; kk += 16) {
+      const int kq = kk + 8 * (lane >> 5);
       bf16x8 af[2], bfr[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
-        af[i] = *reinterpret_cast<const bf16x8*>(&As[wm * 64 + i * 32 + (lane & 31)][kq]);
+        af[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 64 + i * 32 + (lane & 31)][kq]);
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-        bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn * 64 + j * 32 + (lane & 31)][kq]);
+        bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn * 64 + j * 32 + (lane & 31)][kq]);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (more) {
+      store_tile<AOP>(a0, a1, As[buf ^ 1]);
+      store_tile<BOP>(b0, b1, Bs[buf ^ 1]);
     }
     __syncthreads();
   }
