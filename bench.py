@@ -177,6 +177,8 @@ def bench_learned(args):
                       "features": "log-mel 128 x 64 (FFT power spectrum)",
                       "mlp": "8192-1024-1024-78"},
            "phase_ms": {"render": r_ms, "logmel": l_ms, "mlp_train": m_ms},
+           "render_plans": (dict(Lr._TUNER.table) if Lr._TUNER is not None else None),
+           "render_plan_ms": (dict(Lr._TUNER.timings) if Lr._TUNER is not None else None),
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": gbs / HBM_PEAK_GBS, "traffic": None,
                         "kernel": "log-mel (FFT power + mel GEMM)",
