@@ -61,9 +61,9 @@ class RenderTuner:
         h = hash((tuple(vals.tolist()), tuple(counts.tolist()))) & 0xFFFFFFFF
         return f"r:{batch}:{int(lens.sum())}:{h:08x}"
 
-    def tune(self, params, nebula, n_samples=None, offsets=None, out=None, **kw):
+    def tune(self, params, nebula, n_samples=None, offsets=None, out=None, key=None, **kw):
         B = params.shape[0]
-        k = self.key(B, n_samples, offsets)
+        k = key if key is not None else self.key(B, n_samples, offsets)
         cands = self.candidates or default_candidates(B, offsets is None)
         stream = torch.cuda.current_stream()
         times = {}
@@ -92,15 +92,17 @@ class RenderTuner:
         self.timings[k] = {",".join(map(str, p)): t for p, t in times.items()}
         return best, times
 
-    def plan_for(self, params, nebula, n_samples=None, offsets=None, **kw):
-        k = self.key(params.shape[0], n_samples, offsets)
+    def plan_for(self, params, nebula, n_samples=None, offsets=None, key=None, **kw):
+        """The plan for this batch shape, tuning it on first sight.  `key` lets a
+        caller that knows its shape name it (avoids reading the offsets back)."""
+        k = key if key is not None else self.key(params.shape[0], n_samples, offsets)
         if k not in self.table:
-            self.tune(params, nebula, n_samples=n_samples, offsets=offsets, **kw)
+            self.tune(params, nebula, n_samples=n_samples, offsets=offsets, key=k, **kw)
         return self.table[k]
 
-    def render(self, params, nebula, n_samples=None, offsets=None, out=None, **kw):
+    def render(self, params, nebula, n_samples=None, offsets=None, out=None, key=None, **kw):
         rps, sl, pers, grid = self.plan_for(params, nebula, n_samples=n_samples, offsets=offsets,
-                                            **kw)
+                                            key=key, **kw)
         return synth_render_plan(params, nebula, rps, sl, persistent=bool(pers), grid_blocks=grid,
                                  n_samples=n_samples, offsets=offsets, out=out, **kw)
 

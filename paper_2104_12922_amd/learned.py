@@ -331,7 +331,16 @@ def render_batch(seed, ids, nebula_table, lengths_s=(1, 2, 3, 4), tune: bool = T
         if _TUNER is None:
             from .autotune import RenderTuner
             _TUNER = RenderTuner(reps=3)
-        audio = _TUNER.render(u, nebula_table, offsets=offs, voice_ids=ids, noise_seed=seed)
+        # every batch of B consecutive training voices has the same length mix
+        # when B is a multiple of the cycle, so the shape is named, not read back
+        B, c = ids.numel(), len(lengths_s)
+        key, out = None, None
+        if B % c == 0:
+            key = f"train:{B}:{tuple(lengths_s)}"
+            total = (B // c) * sum(int(round(x * 44100.0)) for x in lengths_s)
+            out = torch.empty(total, dtype=F32, device=ids.device)
+        audio = _TUNER.render(u, nebula_table, offsets=offs, voice_ids=ids, noise_seed=seed,
+                              key=key, out=out)
     else:
         audio = synth_render(u, nebula_table, offsets=offs, voice_ids=ids, noise_seed=seed)
     return u, audio, offs
