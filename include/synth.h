@@ -231,24 +231,35 @@ int synth_standardize(const float* x, const float* mean, const float* inv_std, i
 /* y (bf16) = round-to-nearest-even(x), n elements. */
 int synth_to_bf16(const float* x, void* y, int64_t n, void* stream);
 
+/* Bytes of the optional MLP workspace (0 when no GEMM of this shape splits
+ * its reduction).  With it, a GEMM whose output has too few 128 x 128 tiles to
+ * fill the chip splits K over several workgroups, writes float32 partial sums
+ * there and adds them in a fixed order, so results stay deterministic. */
+size_t synth_mlp_workspace(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out);
+
 /* MLP forward, d_in -> d_h -> d_h -> d_out: h1 = gelu(x W1 + b1),
  * h2 = gelu(h1 W2 + b2), out = sigmoid(h2 W3 + b3).  Weights are stored
  * transposed and K-major: w1t [d_h][d_in], w2t [d_h][d_h], w3t [d_out][d_h]
  * (bf16); biases float32.  x, h1, h2 bf16 [batch][.]; h1pre, h2pre float32
- * pre-activations (may be NULL when no backward follows); out float32. */
+ * pre-activations (may be NULL when no backward follows); out float32.
+ * workspace: NULL (no split reductions) or synth_mlp_workspace() bytes,
+ * else SYNTH_ENOMEM; calls sharing one workspace must be stream-ordered. */
 int synth_mlp_forward(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out, const void* x,
                       const void* w1t, const float* b1, const void* w2t, const float* b2,
                       const void* w3t, const float* b3, float* h1pre, void* h1, float* h2pre,
-                      void* h2, float* out, void* stream);
+                      void* h2, float* out, void* workspace, size_t workspace_bytes,
+                      void* stream);
 /* MLP backward of the loss mean((out - target)^2) over batch x d_out:
  * loss_rows (float64 [batch]) receives each row's sum of squared errors;
  * gw*t (float32, layouts of w*t) and gb* (float32) receive the gradients;
- * dz3 bf16 [batch][d_out], dh2 / dh1 bf16 [batch][d_h] are scratch. */
+ * dz3 bf16 [batch][d_out], dh2 / dh1 bf16 [batch][d_h] are scratch;
+ * workspace as for synth_mlp_forward. */
 int synth_mlp_backward(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out, const void* x,
                        const void* w2t, const void* w3t, const float* h1pre, const void* h1,
                        const float* h2pre, const void* h2, const float* out, const float* target,
                        float* gw1t, float* gb1, float* gw2t, float* gb2, float* gw3t, float* gb3,
-                       void* dz3, void* dh2, void* dh1, double* loss_rows, void* stream);
+                       void* dz3, void* dh2, void* dh1, double* loss_rows, void* workspace,
+                       size_t workspace_bytes, void* stream);
 /* Bias-corrected Adam step `step` (>= 1) on float32 w with moments m, v; if
  * w_bf16 != NULL it receives the updated weights rounded to bf16. */
 int synth_adam(int64_t n, float* w, void* w_bf16, const float* grad, float* m, float* v, float lr,

@@ -467,38 +467,77 @@ int synth_to_bf16(const float* x, void* y, int64_t n, void* stream) {
   return to_status(synth::launch_f32_to_bf16(x, y, n, (hipStream_t)stream));
 }
 
+namespace {
+// The MLP's GEMMs as (M, N, K); forward: 0-2, backward: 3-7.
+void mlp_shapes(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out, int64_t sh[8][3]) {
+  const int64_t v[8][3] = {{batch, d_h, d_in}, {batch, d_h, d_h},  {batch, d_out, d_h},
+                           {d_out, d_h, batch}, {batch, d_h, d_out}, {d_h, d_h, batch},
+                           {batch, d_h, d_h},  {d_h, d_in, batch}};
+  memcpy(sh, v, sizeof(v));
+}
+
+// Runs g with K split over workgroups when its output tiles alone would leave
+// CUs idle and the caller gave a workspace for the partial sums.
+hipError_t gemm_maybe_split(synth::GemmArgs g, int a_op, int b_op, void* workspace,
+                            hipStream_t s) {
+  if (workspace) {
+    g.split = synth::gemm_split_for(g.M, g.N, g.K);
+    g.partial = static_cast<float*>(workspace);
+  }
+  return synth::launch_gemm_bf16(g, a_op, b_op, s);
+}
+}  // namespace
+
+size_t synth_mlp_workspace(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out) {
+  if (batch <= 0 || d_in <= 0 || d_h <= 0 || d_out <= 0) return 0;
+  int64_t sh[8][3];
+  mlp_shapes(batch, d_in, d_h, d_out, sh);
+  size_t b = 0;
+  for (auto& m : sh) {
+    const size_t x = synth::gemm_split_bytes(m[0], m[1], synth::gemm_split_for(m[0], m[1], m[2]));
+    b = x > b ? x : b;
+  }
+  return b;
+}
+
 int synth_mlp_forward(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out, const void* x,
                       const void* w1t, const float* b1, const void* w2t, const float* b2,
                       const void* w3t, const float* b3, float* h1pre, void* h1, float* h2pre,
-                      void* h2, float* out, void* stream) {
+                      void* h2, float* out, void* workspace, size_t workspace_bytes,
+                      void* stream) {
   if (batch < 0 || d_in <= 0 || d_h <= 0 || d_out <= 0) return SYNTH_EINVAL;
   if (batch == 0) return SYNTH_OK;
   if (!x || !w1t || !b1 || !w2t || !b2 || !w3t || !b3 || !h1 || !h2 || !out) return SYNTH_EINVAL;
+  if (workspace && workspace_bytes < synth_mlp_workspace(batch, d_in, d_h, d_out))
+    return SYNTH_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   synth::GemmArgs g = {};
   g.alpha = 1.0f;
   // h1 = gelu(x W1 + b1): A = x [batch][d_in], B = W1^T [d_h][d_in] (K-major)
   g.M = batch; g.N = d_h; g.K = d_in; g.A = x; g.lda = d_in; g.B = w1t; g.ldb = d_in;
   g.C = h1; g.ldc = d_h; g.c_bf16 = 1; g.bias = b1; g.epilogue = synth::kEpiGelu; g.pre = h1pre;
-  hipError_t e = synth::launch_gemm_bf16(g, synth::kOpKMajor, synth::kOpKMajor, s);
+  hipError_t e = gemm_maybe_split(g, synth::kOpKMajor, synth::kOpKMajor, workspace, s);
   if (e != hipSuccess) return SYNTH_EDEVICE;
   g.K = d_h; g.A = h1; g.lda = d_h; g.B = w2t; g.ldb = d_h; g.C = h2; g.bias = b2; g.pre = h2pre;
-  e = synth::launch_gemm_bf16(g, synth::kOpKMajor, synth::kOpKMajor, s);
+  e = gemm_maybe_split(g, synth::kOpKMajor, synth::kOpKMajor, workspace, s);
   if (e != hipSuccess) return SYNTH_EDEVICE;
   g.N = d_out; g.A = h2; g.B = w3t; g.C = out; g.ldc = d_out; g.c_bf16 = 0; g.bias = b3;
   g.epilogue = synth::kEpiSigmoid; g.pre = nullptr;
-  return to_status(synth::launch_gemm_bf16(g, synth::kOpKMajor, synth::kOpKMajor, s));
+  return to_status(gemm_maybe_split(g, synth::kOpKMajor, synth::kOpKMajor, workspace, s));
 }
 
 int synth_mlp_backward(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out, const void* x,
                        const void* w2t, const void* w3t, const float* h1pre, const void* h1,
                        const float* h2pre, const void* h2, const float* out, const float* target,
                        float* gw1t, float* gb1, float* gw2t, float* gb2, float* gw3t, float* gb3,
-                       void* dz3, void* dh2, void* dh1, double* loss_rows, void* stream) {
+                       void* dz3, void* dh2, void* dh1, double* loss_rows, void* workspace,
+                       size_t workspace_bytes, void* stream) {
   if (batch <= 0 || d_in <= 0 || d_h <= 0 || d_out <= 0) return SYNTH_EINVAL;
   if (!x || !w2t || !w3t || !h1pre || !h1 || !h2pre || !h2 || !out || !target || !gw1t || !gb1 ||
       !gw2t || !gb2 || !gw3t || !gb3 || !dz3 || !dh2 || !dh1 || !loss_rows)
     return SYNTH_EINVAL;
+  if (workspace && workspace_bytes < synth_mlp_workspace(batch, d_in, d_h, d_out))
+    return SYNTH_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   using synth::kOpKMajor;
   using synth::kOpRowMajorMN;
@@ -509,29 +548,29 @@ int synth_mlp_backward(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out, 
   // dW3^T [d_out][d_h] = dz3^T h2
   g.M = d_out; g.N = d_h; g.K = batch; g.A = dz3; g.lda = d_out; g.B = h2; g.ldb = d_h;
   g.C = gw3t; g.ldc = d_h; g.c_bf16 = 0;
-  if ((e = synth::launch_gemm_bf16(g, kOpRowMajorMN, kOpRowMajorMN, s)) != hipSuccess) return SYNTH_EDEVICE;
+  if ((e = gemm_maybe_split(g, kOpRowMajorMN, kOpRowMajorMN, workspace, s)) != hipSuccess) return SYNTH_EDEVICE;
   if ((e = synth::launch_colsum(dz3, 1, batch, d_out, d_out, gb3, nullptr, s)) != hipSuccess) return SYNTH_EDEVICE;
   // dh2 = (dz3 W3^T^T) * gelu'(h2pre): A = dz3 [batch][d_out], B[k][n] = W3^T[k][n]
   g = {}; g.alpha = 1.0f;
   g.M = batch; g.N = d_h; g.K = d_out; g.A = dz3; g.lda = d_out; g.B = w3t; g.ldb = d_h;
   g.C = dh2; g.ldc = d_h; g.c_bf16 = 1; g.epilogue = synth::kEpiGeluGrad; g.aux = h2pre;
-  if ((e = synth::launch_gemm_bf16(g, kOpKMajor, kOpRowMajorMN, s)) != hipSuccess) return SYNTH_EDEVICE;
+  if ((e = gemm_maybe_split(g, kOpKMajor, kOpRowMajorMN, workspace, s)) != hipSuccess) return SYNTH_EDEVICE;
   // dW2^T = dh2^T h1, db2
   g = {}; g.alpha = 1.0f;
   g.M = d_h; g.N = d_h; g.K = batch; g.A = dh2; g.lda = d_h; g.B = h1; g.ldb = d_h;
   g.C = gw2t; g.ldc = d_h;
-  if ((e = synth::launch_gemm_bf16(g, kOpRowMajorMN, kOpRowMajorMN, s)) != hipSuccess) return SYNTH_EDEVICE;
+  if ((e = gemm_maybe_split(g, kOpRowMajorMN, kOpRowMajorMN, workspace, s)) != hipSuccess) return SYNTH_EDEVICE;
   if ((e = synth::launch_colsum(dh2, 1, batch, d_h, d_h, gb2, nullptr, s)) != hipSuccess) return SYNTH_EDEVICE;
   // dh1 = (dh2 W2^T^T) * gelu'(h1pre)
   g = {}; g.alpha = 1.0f;
   g.M = batch; g.N = d_h; g.K = d_h; g.A = dh2; g.lda = d_h; g.B = w2t; g.ldb = d_h;
   g.C = dh1; g.ldc = d_h; g.c_bf16 = 1; g.epilogue = synth::kEpiGeluGrad; g.aux = h1pre;
-  if ((e = synth::launch_gemm_bf16(g, kOpKMajor, kOpRowMajorMN, s)) != hipSuccess) return SYNTH_EDEVICE;
+  if ((e = gemm_maybe_split(g, kOpKMajor, kOpRowMajorMN, workspace, s)) != hipSuccess) return SYNTH_EDEVICE;
   // dW1^T = dh1^T x, db1
   g = {}; g.alpha = 1.0f;
   g.M = d_h; g.N = d_in; g.K = batch; g.A = dh1; g.lda = d_h; g.B = x; g.ldb = d_in;
   g.C = gw1t; g.ldc = d_in;
-  if ((e = synth::launch_gemm_bf16(g, kOpRowMajorMN, kOpRowMajorMN, s)) != hipSuccess) return SYNTH_EDEVICE;
+  if ((e = gemm_maybe_split(g, kOpRowMajorMN, kOpRowMajorMN, workspace, s)) != hipSuccess) return SYNTH_EDEVICE;
   return to_status(synth::launch_colsum(dh1, 1, batch, d_h, d_h, gb1, nullptr, s));
 }
 

@@ -57,14 +57,12 @@ __device__ __forceinline__ bool aligned16(const void* p) {
 //   K-major: thread t takes row t / 2, k (t & 1) * 16 .. +15 (32 bytes).
 //   row-major (X[k * ld + r]): thread t takes k t / 8, rows (t & 7) * 16 ..
 //   +15, written to LDS transposed (16 two-byte writes).
-// Tiles at the matrix edge (or unaligned operands) are read element by
-// element with bounds checks and zero fill.
+// Tiles at the matrix edge or at the end K of the k-range (or unaligned
+// operands) are read element by element with bounds checks and zero fill.
 template <int OP>
-__device__ __forceinline__ void load_tile(uint4& r0, uint4& r1, const GemmArgs& g,
-                                          const void* srcv, int64_t ld, int64_t row0,
-                                          int64_t nrows, int64_t k0) {
+__device__ __forceinline__ void load_tile(uint4& r0, uint4& r1, int64_t K, const void* srcv,
+                                          int64_t ld, int64_t row0, int64_t nrows, int64_t k0) {
   const int t = threadIdx.x;
-  const int64_t K = g.K;
   const uint16_t* src = reinterpret_cast<const uint16_t*>(srcv);
   uint16_t v[16];
   if constexpr (OP == kOpKMajor) {
@@ -117,6 +115,21 @@ __device__ __forceinline__ void store_tile(const uint4& r0, const uint4& r1,
   }
 }
 
+// Element (row, col) of the standard epilogues: x is alpha A B (+ bias added here).
+__device__ __forceinline__ void epi_store(const GemmArgs& g, int64_t row, int64_t col, float x) {
+  const int64_t o = row * g.ldc + col;
+  if (g.bias) x += g.bias[col];
+  if (g.pre) g.pre[o] = x;
+  if (g.epilogue == kEpiGelu) x = gelu_erf(x);
+  else if (g.epilogue == kEpiSigmoid) x = 1.0f / (1.0f + expf(-x));
+  else if (g.epilogue == kEpiGeluGrad) x = x * gelu_erf_grad(g.aux[o]);
+  if (g.beta != 0.0f)
+    x += g.beta * (g.c_bf16 ? bf2f(reinterpret_cast<const uint16_t*>(g.C)[o])
+                            : reinterpret_cast<const float*>(g.C)[o]);
+  if (g.c_bf16) reinterpret_cast<uint16_t*>(g.C)[o] = f2bf(x);
+  else reinterpret_cast<float*>(g.C)[o] = x;
+}
+
 template <int AOP, int BOP>
 __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
   __shared__ __align__(16) uint16_t As[2][BM][PADK];
@@ -126,8 +139,16 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
   const int wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int64_t tiles_n = (g.N + BN - 1) / BN;
-  const int64_t tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  const int64_t tiles = ((g.M + BM - 1) / BM) * tiles_n;
+  const int64_t tile = blockIdx.x % tiles;
+  const int64_t tm = tile / tiles_n, tn = tile % tiles_n;
   const int64_t m0 = tm * BM, n0 = tn * BN;
+  // split K: workgroup part p takes [kbeg, kend), a whole number of k-steps
+  const int split = g.split > 1 ? g.split : 1;
+  const int64_t part = blockIdx.x / tiles;
+  const int64_t kper = ((g.K + split - 1) / split + BK - 1) / BK * BK;
+  const int64_t kbeg = part * kper;
+  const int64_t kend = kbeg + kper < g.K ? kbeg + kper : g.K;
 
   f32x16 acc[2][2];
 #pragma unroll
@@ -140,18 +161,18 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
   // LDS double buffer; the next k-step's tiles are loaded into registers
   // before this step's MFMAs and written to the other buffer after them.
   uint4 a0, a1, b0, b1;
-  load_tile<AOP>(a0, a1, g, g.A, g.lda, m0, g.M, 0);
-  load_tile<BOP>(b0, b1, g, g.B, g.ldb, n0, g.N, 0);
+  load_tile<AOP>(a0, a1, kend, g.A, g.lda, m0, g.M, kbeg);
+  load_tile<BOP>(b0, b1, kend, g.B, g.ldb, n0, g.N, kbeg);
   store_tile<AOP>(a0, a1, As[0]);
   store_tile<BOP>(b0, b1, Bs[0]);
   __syncthreads();
-  const int64_t nk = (g.K + BK - 1) / BK;
+  const int64_t nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
   for (int64_t ks = 0; ks < nk; ++ks) {
     const int buf = (int)(ks & 1);
     const bool more = ks + 1 < nk;
     if (more) {
-      load_tile<AOP>(a0, a1, g, g.A, g.lda, m0, g.M, (ks + 1) * BK);
-      load_tile<BOP>(b0, b1, g, g.B, g.ldb, n0, g.N, (ks + 1) * BK);
+      load_tile<AOP>(a0, a1, kend, g.A, g.lda, m0, g.M, kbeg + (ks + 1) * BK);
+      load_tile<BOP>(b0, b1, kend, g.B, g.ldb, n0, g.N, kbeg + (ks + 1) * BK);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -179,18 +200,33 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
   }
 
   // ---- epilogue ----
+  if (split > 1) {
+    // raw partial sums; the reduction applies the epilogue
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int64_t col = n0 + wn * 64 + j * 32 + (lane & 31);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          if (col < g.N && row < g.M) g.partial[(part * g.M + row) * g.N + col] = acc[i][j][v];
+        }
+      }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int64_t col = n0 + wn * 64 + j * 32 + (lane & 31);
       const bool col_ok = col < g.N;
-      const float bias = (g.bias && col_ok) ? g.bias[col] : 0.0f;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int64_t row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        float x = acc[i][j][v] * g.alpha + bias;
+        float x = acc[i][j][v] * g.alpha;
         if (g.epilogue == kEpiPowerPairs) {
+          x += (g.bias && col_ok) ? g.bias[col] : 0.0f;
           // (Re, Im) sit in adjacent columns = adjacent lanes; every lane shuffles
           const float other = __shfl_xor(x, 1);
           if ((col & 1) == 0 && col_ok && row < g.M) {
@@ -203,22 +239,25 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
         }
         if (!col_ok || row >= g.M) continue;
         if (g.epilogue == kEpiLogMelT) {
+          if (g.bias) x += g.bias[col];
           const int64_t o = (row / 64) * 8192 + col * 64 + (row % 64);
           reinterpret_cast<float*>(g.C)[o] = logf(x + 1e-6f);
           continue;
         }
-        const int64_t o = row * g.ldc + col;
-        if (g.pre) g.pre[o] = x;
-        if (g.epilogue == kEpiGelu) x = gelu_erf(x);
-        else if (g.epilogue == kEpiSigmoid) x = 1.0f / (1.0f + expf(-x));
-        else if (g.epilogue == kEpiGeluGrad) x = x * gelu_erf_grad(g.aux[o]);
-        if (g.beta != 0.0f)
-          x += g.beta * (g.c_bf16 ? bf2f(reinterpret_cast<const uint16_t*>(g.C)[o])
-                                  : reinterpret_cast<const float*>(g.C)[o]);
-        if (g.c_bf16) reinterpret_cast<uint16_t*>(g.C)[o] = f2bf(x);
-        else reinterpret_cast<float*>(g.C)[o] = x;
+        epi_store(g, row, col, x);
       }
     }
+}
+
+// Sum of the split-K partials in part order, then the epilogue.
+__global__ void __launch_bounds__(256) gemm_split_reduce_kernel(GemmArgs g) {
+  const int64_t n = g.M * g.N;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float x = 0.0f;
+    for (int p = 0; p < g.split; ++p) x += g.partial[p * n + i];
+    epi_store(g, i / g.N, i % g.N, x * g.alpha);
+  }
 }
 
 template <int AOP>
@@ -232,16 +271,37 @@ hipError_t launch_b(const GemmArgs& g, int b_op, dim3 grid, hipStream_t s) {
 
 }  // namespace
 
+int gemm_split_for(int64_t M, int64_t N, int64_t K) {
+  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  int64_t split = 1;
+  // double the split while the grid is under one workgroup per CU and each
+  // part keeps at least 4 k-steps
+  while (tiles * split < 256 && K >= split * 2 * 4 * BK) split *= 2;
+  return (int)split;
+}
+
+size_t gemm_split_bytes(int64_t M, int64_t N, int split) {
+  return split > 1 ? (size_t)split * (size_t)M * (size_t)N * sizeof(float) : 0;
+}
+
 hipError_t launch_gemm_bf16(const GemmArgs& g, int a_op, int b_op, hipStream_t s) {
   if (g.M == 0 || g.N == 0) return hipSuccess;
   const int64_t tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
-  if (tiles > 0x7FFFFFFF) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)tiles);
+  const int split = g.split > 1 ? g.split : 1;
+  if (split > 1 && (!g.partial || g.epilogue > kEpiGeluGrad)) return hipErrorInvalidValue;
+  if (tiles * split > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(tiles * split));
+  hipError_t e;
   switch (a_op) {
-    case kOpKMajor: return launch_b<kOpKMajor>(g, b_op, grid, s);
-    case kOpRowMajorMN: return launch_b<kOpRowMajorMN>(g, b_op, grid, s);
+    case kOpKMajor: e = launch_b<kOpKMajor>(g, b_op, grid, s); break;
+    case kOpRowMajorMN: e = launch_b<kOpRowMajorMN>(g, b_op, grid, s); break;
     default: return hipErrorInvalidValue;
   }
+  if (e != hipSuccess || split == 1) return e;
+  int64_t blocks = (g.M * g.N + 255) / 256;
+  if (blocks > 65535 * 4) blocks = 65535 * 4;
+  hipLaunchKernelGGL(gemm_split_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g);
+  return hipGetLastError();
 }
 
 }  // namespace synth

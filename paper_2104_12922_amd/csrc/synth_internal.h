@@ -65,9 +65,15 @@ struct GemmArgs {
   const float* aux;    // kEpiGeluGrad operand, same layout as C
   float* pre;          // optional float32 pre-activation output (layout of C)
   float alpha, beta;   // beta != 0: C = epi(...) + beta * C
+  int split;           // > 1: split K over that many workgroups per tile (epilogues 0-3)
+  float* partial;      // split > 1: float32 workspace [split][M][N]
 };
 
 hipError_t launch_gemm_bf16(const GemmArgs& g, int a_op, int b_op, hipStream_t s);
+// Split that fills the chip for a GEMM of this shape (1: none), and its
+// workspace bytes.
+int gemm_split_for(int64_t M, int64_t N, int64_t K);
+size_t gemm_split_bytes(int64_t M, int64_t N, int split);
 
 // elementwise / reduction helpers of the learned proposal (mlp.hip)
 hipError_t launch_f32_to_bf16(const float* x, void* y, int64_t n, hipStream_t s);

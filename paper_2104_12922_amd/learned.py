@@ -34,8 +34,10 @@ def _sig(L):
     L.synth_standardize.argtypes = [vp, vp, vp, i64, i64, vp, vp]
     L.synth_feature_stats.argtypes = [vp, i64, i64, f32, vp, vp, vp]
     L.synth_to_bf16.argtypes = [vp, vp, i64, vp]
-    L.synth_mlp_forward.argtypes = [i64, i64, i64, i64] + [vp] * 13
-    L.synth_mlp_backward.argtypes = [i64, i64, i64, i64] + [vp] * 20
+    L.synth_mlp_workspace.restype = sz
+    L.synth_mlp_workspace.argtypes = [i64, i64, i64, i64]
+    L.synth_mlp_forward.argtypes = [i64, i64, i64, i64] + [vp] * 13 + [sz, vp]
+    L.synth_mlp_backward.argtypes = [i64, i64, i64, i64] + [vp] * 20 + [sz, vp]
     L.synth_adam.argtypes = [i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]
     L.synth_logit_init.argtypes = [vp, vp, vp, i64, f32, vp]
     L.synth_logit_adam.argtypes = [i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]
@@ -166,9 +168,12 @@ def to_bf16(x: torch.Tensor, out=None):
 
 class MLP:
     """8192 -> 1024 -> 1024 -> 78 proposal network: float32 master weights
-    (transposed, K-major) with bf16 copies, Adam moments, activation buffers."""
+    (transposed, K-major) with bf16 copies, Adam moments, activation buffers.
+    `split_k` gives the library a workspace so that GEMMs with few output
+    tiles split their reduction over workgroups."""
 
-    def __init__(self, init: dict, device="cuda", lr=3e-4, betas=(0.9, 0.999), eps=1e-8):
+    def __init__(self, init: dict, device="cuda", lr=3e-4, betas=(0.9, 0.999), eps=1e-8,
+                 split_k=True):
         self.device = torch.device(device)
         self.d_in, self.d_h, self.d_out = init["w1t"].shape[1], init["w1t"].shape[0], init["w3t"].shape[0]
         self.names = ("w1t", "b1", "w2t", "b2", "w3t", "b3")
@@ -181,6 +186,7 @@ class MLP:
         self.lr, self.betas, self.eps = lr, betas, eps
         self.step_count = 0
         self._act_batch = 0
+        self.split_k = split_k
 
     def _acts(self, B):
         if B != self._act_batch:
@@ -190,8 +196,13 @@ class MLP:
                       "h2": mk((B, h), BF16), "out": mk((B, o), F32), "dz3": mk((B, o), BF16),
                       "dh2": mk((B, h), BF16), "dh1": mk((B, h), BF16),
                       "loss_rows": mk((B,), torch.float64)}
+            nws = lib().synth_mlp_workspace(B, d, h, o) if self.split_k else 0
+            self.ws = mk((max(nws, 1),), torch.uint8) if nws else None
             self._act_batch = B
         return self.a
+
+    def _ws_args(self):
+        return (None, 0) if self.ws is None else (self.ws.data_ptr(), self.ws.numel())
 
     def forward(self, x_bf16: torch.Tensor, keep=True) -> torch.Tensor:
         B = x_bf16.shape[0]
@@ -201,7 +212,8 @@ class MLP:
             B, self.d_in, self.d_h, self.d_out, _p(x_bf16, "x", BF16, B * self.d_in),
             wb["w1t"].data_ptr(), w["b1"].data_ptr(), wb["w2t"].data_ptr(), w["b2"].data_ptr(),
             wb["w3t"].data_ptr(), w["b3"].data_ptr(), a["h1pre"].data_ptr(), a["h1"].data_ptr(),
-            a["h2pre"].data_ptr(), a["h2"].data_ptr(), a["out"].data_ptr(), _stream(self.device)))
+            a["h2pre"].data_ptr(), a["h2"].data_ptr(), a["out"].data_ptr(), *self._ws_args(),
+            _stream(self.device)))
         return a["out"]
 
     def backward(self, x_bf16: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
@@ -214,7 +226,7 @@ class MLP:
             a["h2"].data_ptr(), a["out"].data_ptr(), _p(target, "target", F32, B * self.d_out),
             g["w1t"].data_ptr(), g["b1"].data_ptr(), g["w2t"].data_ptr(), g["b2"].data_ptr(),
             g["w3t"].data_ptr(), g["b3"].data_ptr(), a["dz3"].data_ptr(), a["dh2"].data_ptr(),
-            a["dh1"].data_ptr(), a["loss_rows"].data_ptr(), _stream(self.device)))
+            a["dh1"].data_ptr(), a["loss_rows"].data_ptr(), *self._ws_args(), _stream(self.device)))
         return a["loss_rows"].sum() / (B * self.d_out)
 
     def adam_step(self):

@@ -83,8 +83,10 @@ def test_logmel_matches_bf16_reference(L, method):
     assert float(d.max()) < 5e-3
 
 
-def test_mlp_forward_backward_full_size(L):
-    """8192 -> 1024 -> 1024 -> 78 at batch 512 against the float64 reference."""
+@pytest.mark.parametrize("split_k", [True, False])
+def test_mlp_forward_backward_full_size(L, split_k):
+    """8192 -> 1024 -> 1024 -> 78 at batch 512 against the float64 reference;
+    with split_k every GEMM but dh2 and dW1 splits its reduction."""
     w = W.mlp_init(0)
     rng = np.random.default_rng(1)
     for k, n in (("b1", 1024), ("b2", 1024), ("b3", 78)):
@@ -92,11 +94,18 @@ def test_mlp_forward_backward_full_size(L):
     B = 512
     x = torch.tensor(rng.standard_normal((B, 8192)), dtype=torch.float32)
     t = torch.tensor(rng.random((B, 78)), dtype=torch.float32)
-    net = L.MLP(w)
+    net = L.MLP(w, split_k=split_k)
     xb = x.to(BF).cuda()
     out = net.forward(xb)
     loss = net.backward(xb, t.cuda())
     torch.cuda.synchronize()
+    assert (net.ws is not None) == split_k
+    if split_k:                                      # fixed-order partial sums: reruns are bit-equal
+        first = {k: v.clone() for k, v in net.g.items()}
+        out2 = net.forward(xb).clone()
+        net.backward(xb, t.cuda())
+        assert torch.equal(out2, out)
+        assert all(torch.equal(first[k], net.g[k]) for k in first)
     f = omlp.forward(x.double(), w, round_bf16=True)
     ref_loss, g = omlp.backward(f, t.double(), round_bf16=True)
     assert rel(out.cpu(), f["out"]) < 2e-3
