@@ -189,24 +189,27 @@ int synth_gemm_bf16(int a_layout, int b_layout, int64_t M, int64_t N, int64_t K,
 /* Log-mel features: 64 frames of 2048 samples at hop 2756 (no padding),
  * periodic Hann window, power spectrum, 128 HTK mel triangles from 0 to
  * sample_rate / 2 (no area normalisation), log(x + 1e-6).
- *   synth_logmel_init fills the tables once: mel_basis bf16 [128][1032] and,
- *   if dft_basis != NULL, dft_basis bf16 [2048][2048] for synth_logmel_mfma
- *   (row 0: w(k), row 1: w(k)(-1)^k - the real bins 0 and 1024 - then rows
- *   2f, 2f+1: w(k) cos(2 pi f k / 2048), -w(k) sin(...) for f = 1..1023);
- *   it synchronises the stream.
+ *   synth_logmel_init fills the tables once: mel_basis bf16 [128][1032]
+ *   (columns 0-1024 the weights; columns 1025 and 1026 of band b hold, as
+ *   uint16, its first and last nonzero bin) and, if dft_basis != NULL,
+ *   dft_basis bf16 [2048][2048] for synth_logmel_mfma (row 0: w(k), row 1:
+ *   w(k)(-1)^k - the real bins 0 and 1024 - then rows 2f, 2f+1:
+ *   w(k) cos(2 pi f k / 2048), -w(k) sin(...) for f = 1..1023); it
+ *   synchronises the stream.  SYNTH_EUNSUPPORTED if a band's nonzero bins
+ *   are not one run or there are more than 2304 nonzero weights.
  *   synth_logmel: power spectrum by float32 FFT of the windowed frames,
- *   rounded to bf16; the mel projection is a bf16 MFMA GEMM with float32
- *   accumulation.
- *   synth_logmel_mfma: the same features with the power spectrum as one bf16
- *   MFMA GEMM of the frames (rounded to bf16) with dft_basis (window folded
- *   in) - more arithmetic, bf16 inputs.
+ *   rounded to bf16; each band summed over its nonzero bins in float32; one
+ *   kernel, workspace unused (may be NULL).
+ *   synth_logmel_mfma: the power spectrum as one bf16 MFMA GEMM of the frames
+ *   (rounded to bf16) with dft_basis (window folded in) - more arithmetic,
+ *   bf16 inputs - and the mel projection as a bf16 MFMA GEMM with float32
+ *   accumulation; workspace >= synth_logmel_workspace(batch) bytes.
  *   audio: float32, voice b = audio[b * n_samples ..] of n_samples samples
  *   (offsets == NULL, n_samples > 0) or the ragged range
  *   audio[offsets[b] .. offsets[b+1]) (offsets dev int64 [batch + 1]); samples
  *   past a voice's end count as 0 (a render shorter than the 175676 samples
- *   the frames span is featurised as if zero-padded).  workspace >=
- *   synth_logmel_workspace(batch) bytes; features float32 [batch][128][64]
- *   (mel bin major, frame minor). */
+ *   the frames span is featurised as if zero-padded).  features float32
+ *   [batch][128][64] (mel bin major, frame minor). */
 size_t synth_logmel_workspace(int64_t batch);
 int synth_logmel_init(double sample_rate, void* dft_basis, void* mel_basis, void* stream);
 int synth_logmel(const float* audio, const int64_t* offsets, int64_t batch, int64_t n_samples,

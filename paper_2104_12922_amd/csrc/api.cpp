@@ -399,6 +399,24 @@ int synth_logmel_init(double sample_rate, void* dft_basis, void* mel_basis, void
       }
       table[b * kMelLd + k] = host_f2bf((float)w);
     }
+  // padding columns 1025, 1026 of band b: its first and last nonzero bin
+  // (first > last when the band has none), read by the FFT path
+  int total = 0;
+  for (int b = 0; b < kMelBins; ++b) {
+    int lo = kMelNfft / 2 + 1, hi = -1;
+    for (int k = 0; k <= kMelNfft / 2; ++k)
+      if (table[b * kMelLd + k] != 0) {
+        lo = k < lo ? k : lo;
+        hi = k;
+      }
+    if (hi < 0) lo = 1, hi = 0;
+    for (int k = lo; k <= hi; ++k)       // triangles: nonzero on one run of bins
+      if (table[b * kMelLd + k] == 0) return SYNTH_EUNSUPPORTED;
+    total += hi - lo + 1;
+    table[b * kMelLd + kMelNfft / 2 + 1] = (uint16_t)lo;
+    table[b * kMelLd + kMelNfft / 2 + 2] = (uint16_t)hi;
+  }
+  if (total > synth::kMelWeightsMax) return SYNTH_EUNSUPPORTED;
   e = hipMemcpyAsync(mel_basis, table, sizeof(table), hipMemcpyHostToDevice, (hipStream_t)stream);
   if (e != hipSuccess) return SYNTH_EDEVICE;
   return to_status(hipStreamSynchronize((hipStream_t)stream));
@@ -410,14 +428,16 @@ int logmel_common(bool fft, const float* audio, const int64_t* offsets, int64_t 
                   void* workspace, size_t workspace_bytes, float* features, void* stream) {
   if (batch < 0) return SYNTH_EINVAL;
   if (batch == 0) return SYNTH_OK;
-  if (!audio || (!fft && !dft_basis) || !mel_basis || !workspace || !features) return SYNTH_EINVAL;
+  if (!audio || !mel_basis || !features) return SYNTH_EINVAL;
   if (!offsets && n_samples <= 0) return SYNTH_EINVAL;
-  if (workspace_bytes < synth_logmel_workspace(batch)) return SYNTH_ENOMEM;
   const hipStream_t s = (hipStream_t)stream;
   const int64_t n = offsets ? 0 : n_samples;
-  hipError_t e = fft ? synth::launch_melpower(audio, offsets, n, batch, workspace, kMelLd, s)
-                     : synth::launch_dft_power(audio, offsets, n, batch, dft_basis, workspace,
-                                               kMelLd, s);
+  if (fft)
+    return to_status(synth::launch_logmel_fft(audio, offsets, n, batch, mel_basis, kMelLd,
+                                              features, s));
+  if (!dft_basis || !workspace) return SYNTH_EINVAL;
+  if (workspace_bytes < synth_logmel_workspace(batch)) return SYNTH_ENOMEM;
+  hipError_t e = synth::launch_dft_power(audio, offsets, n, batch, dft_basis, workspace, kMelLd, s);
   if (e != hipSuccess) return SYNTH_EDEVICE;
   synth::GemmArgs h = {};
   h.M = batch * kMelFrames; h.N = kMelBins; h.K = kMelNfft / 2 + 1;

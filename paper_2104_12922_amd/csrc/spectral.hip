@@ -43,7 +43,7 @@ constexpr int kPadded = kMaxN;
 constexpr int kPassTw = 1280;  // per-pass twiddles (Nc = 512 needs 1276)
 
 struct SpecShared {
-  float2 tw[kMaxN];            // tw[k] = exp(-2 pi i k / n)
+  float2 tw[kMaxN / 2];        // tw[k] = exp(-2 pi i k / n), k < n / 2
   float2 ptw[kPassTw];         // per-pass twiddles, contiguous in the butterfly index
   float win[kMaxN];            // periodic Hann window
   float2 buf[2][kPadded];      // FFT ping-pong: (512 / (n/8)) transforms of n/2 points (swizzled)
@@ -165,9 +165,11 @@ __device__ __forceinline__ void fft_tables(SpecShared& sh) {
   constexpr int Nc = n / 2;
   const int tid = threadIdx.x;
   for (int k = tid; k < n; k += kThreads) {
-    float s, c;
-    sincospif(2.0f * (float)k / (float)n, &s, &c);
-    sh.tw[k] = make_float2(c, -s);
+    if (k < Nc) {
+      float s, c;
+      sincospif(2.0f * (float)k / (float)n, &s, &c);
+      sh.tw[k] = make_float2(c, -s);
+    }
     sh.win[k] = 0.5f - 0.5f * cospif(2.0f * (float)k / (float)n);
   }
   for (int ns = 4, rem = Nc / 4; rem > 1; ns *= 4, rem /= 4) {
@@ -314,23 +316,44 @@ __global__ void __launch_bounds__(kThreads) mrstft_frames_kernel(const MrArgs a)
     mrstft_frames<2>(a, sh, b, blk);
 }
 
-// Power spectrum of the log-mel frames by FFT: voice b's frames f < 64 of
-// 2048 samples at hop 2756 (samples past the voice's end read as 0), periodic
-// Hann window, P[b * 64 + f][k] = |X_fk|^2 for k <= 1024, rounded to bf16.
-// One workgroup per voice, two frames (two 1024-point complex FFTs) at a time.
+// Log-mel features by FFT, one workgroup per voice: frames f < 64 of 2048
+// samples at hop 2756 (samples past the voice's end read as 0), periodic Hann
+// window, power spectrum |X_fk|^2 (k <= 1024) rounded to bf16, each mel band's
+// sum over its nonzero bins in float32, log(x + 1e-6) into
+// features[b][band][f].  Two frames (two 1024-point complex FFTs) at a time;
+// the power row goes to the transform's free ping-pong buffer and the bands
+// are summed from there, so nothing but the features leaves the CU.
 __device__ __forceinline__ uint16_t f2bf(float f) {
   const uint32_t u = __float_as_uint(f);
   if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
   return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__global__ void __launch_bounds__(kThreads) melpower_kernel(const float* __restrict__ audio,
-                                                           const int64_t* __restrict__ offsets,
-                                                           int64_t n_uniform,
-                                                           uint16_t* __restrict__ power,
-                                                           int64_t ldp) {
+// A band's weights are summed in chunks of at most kMelChunk bins, one chunk
+// per thread, then each band adds its chunks' sums in order: the work per
+// thread stays even although band widths range from 1 to ~60 bins.
+constexpr int kMelChunk = 12;
+constexpr int kMelChunksMax = kMelWeightsMax / kMelChunk + kMelBands;
+
+struct MelShared {
+  float w[kMelWeightsMax];     // band b's weights, bins lo[b] .. lo[b] + width - 1, at w[off[b]]
+  int lo[kMelBands];
+  int off[kMelBands + 1];
+  int cbase[kMelBands + 1];    // band b's chunks: cbase[b] .. cbase[b + 1] - 1
+  int chunk[kMelChunksMax];    // weight start | bin start << 12 | count << 23
+  float st[kMelBands][17];     // features of up to 16 frames, written out together
+};
+
+__global__ void __launch_bounds__(kThreads) logmel_fft_kernel(const float* __restrict__ audio,
+                                                              const int64_t* __restrict__ offsets,
+                                                              int64_t n_uniform,
+                                                              const uint16_t* __restrict__ mel,
+                                                              int64_t ldm,
+                                                              float* __restrict__ features) {
   __shared__ SpecShared sh;
-  constexpr int n = 2048, Nc = 1024, tpt = 256, hop = 2756, frames = 64;
+  __shared__ MelShared ms;
+  constexpr int Nc = 1024, tpt = 256, hop = 2756, frames = 64;
   const int tid = threadIdx.x;
   const int64_t b = blockIdx.x;
   int64_t start, len;
@@ -342,31 +365,162 @@ __global__ void __launch_bounds__(kThreads) melpower_kernel(const float* __restr
     len = n_uniform;
   }
   const float* x = audio + start;
-  fft_tables<2>(sh);
+  float* feat = features + b * (int64_t)(kMelBands * frames);
+
+  // band table: each band's first and last nonzero bin sit in its row's
+  // padding columns 1025, 1026; weight offsets and chunk counts are
+  // prefix-summed by one wave
+  if (tid < 64) {
+    int lo[2], wd[2], nc[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint16_t* row = mel + (int64_t)(2 * tid + h) * ldm;
+      lo[h] = row[Nc + 1] <= Nc ? row[Nc + 1] : Nc;
+      const int hi = row[Nc + 2] <= Nc ? row[Nc + 2] : Nc;
+      wd[h] = hi >= lo[h] ? hi - lo[h] + 1 : 0;
+      nc[h] = (wd[h] + kMelChunk - 1) / kMelChunk;
+    }
+    const int pw = wd[0] + wd[1], pc = nc[0] + nc[1];
+    int iw = pw, ic = pc;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int yw = __shfl_up(iw, d), yc = __shfl_up(ic, d);
+      if (tid >= d) iw += yw, ic += yc;
+    }
+    ms.lo[2 * tid] = lo[0];
+    ms.lo[2 * tid + 1] = lo[1];
+    ms.off[2 * tid] = iw - pw;
+    ms.off[2 * tid + 1] = iw - pw + wd[0];
+    ms.cbase[2 * tid] = min(ic - pc, kMelChunksMax);
+    ms.cbase[2 * tid + 1] = min(ic - pc + nc[0], kMelChunksMax);
+    if (tid == 63) {
+      ms.off[kMelBands] = iw;
+      ms.cbase[kMelBands] = min(ic, kMelChunksMax);
+    }
+  }
+  fft_tables<2>(sh);                    // ends with a barrier
+  for (int e = tid; e < kMelBands * 4; e += kThreads) {
+    const int bd = e >> 2;
+    const int o0 = ms.off[bd], o1 = min(ms.off[bd + 1], kMelWeightsMax);
+    const uint16_t* row = mel + (int64_t)bd * ldm + ms.lo[bd];
+    for (int i = e & 3; o0 + i < o1; i += 4) ms.w[o0 + i] = bf2f(row[i]);
+    for (int c = ms.cbase[bd] + (e & 3), q = e & 3; c < ms.cbase[bd + 1]; c += 4, q += 4) {
+      const int ws = o0 + q * kMelChunk;
+      const int cnt = max(0, min(kMelChunk, o1 - ws));
+      ms.chunk[c] = min(ws, kMelWeightsMax) | ((ms.lo[bd] + q * kMelChunk) << 12) | (cnt << 23);
+    }
+  }
+  __syncthreads();
+  const int nchunks = ms.cbase[kMelBands];
+  // thread j's first chunk (c = j) is the same for every frame: its weights
+  // stay in registers
+  const int e0 = tid % 256 < nchunks ? ms.chunk[tid % 256] : 0;
+  const int ps0 = (e0 >> 12) & 2047, cnt0 = e0 >> 23;
+  float w0[kMelChunk];
+#pragma unroll
+  for (int i = 0; i < kMelChunk; ++i)
+    w0[i] = i < cnt0 ? ms.w[min((e0 & 4095) + i, kMelWeightsMax - 1)] : 0.0f;
+
   const int tr = tid / tpt;             // 0, 1: the iteration's two frames
   const int j = tid - tr * tpt;
-  for (int f0 = 0; f0 < frames; f0 += 2) {
+  // Frames that start at or past the voice's end hold only zero padding:
+  // their features are log(1e-6) and they skip the FFT.
+  const int64_t nlive = len <= 0 ? 0 : (len + hop - 1) / hop;
+  const int live = (int)(nlive < frames ? nlive : frames);
+  const int live2 = (live + 1) & ~1;    // frames are transformed in pairs
+  // the next pair's samples are fetched into registers during this pair's FFT
+  float s[8];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t i0 = (int64_t)tr * hop + 2 * (j + q * tpt);
+    s[2 * q] = i0 < len ? x[i0] : 0.0f;
+    s[2 * q + 1] = i0 + 1 < len ? x[i0 + 1] : 0.0f;
+  }
+  for (int f0 = 0; f0 < live2; f0 += 2) {
     const int f = f0 + tr;
-    const int64_t pos = (int64_t)f * hop;
     float2 v[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int m = j + q * tpt;
-      const int64_t i0 = pos + 2 * m;
-      const float s0 = i0 < len ? x[i0] : 0.0f;
-      const float s1 = i0 + 1 < len ? x[i0 + 1] : 0.0f;
-      v[q] = make_float2(sh.win[2 * m] * s0, sh.win[2 * m + 1] * s1);
+      v[q] = make_float2(sh.win[2 * m] * s[2 * q], sh.win[2 * m + 1] * s[2 * q + 1]);
+    }
+    if (f0 + 2 < live2) {
+      const int64_t pos = (int64_t)(f + 2) * hop;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t i0 = pos + 2 * (j + q * tpt);
+        s[2 * q] = i0 < len ? x[i0] : 0.0f;
+        s[2 * q + 1] = i0 + 1 < len ? x[i0 + 1] : 0.0f;
+      }
     }
     float2* b0 = sh.buf[0] + tr * Nc;
     float2* b1 = sh.buf[1] + tr * Nc;
     const int zb = fft_passes<Nc, 1, 0>(v, j, -1.0f, sh.ptw, b0, b1, true);
     const float2* Z = sh.buf[zb] + tr * Nc;
-    uint16_t* prow = power + (b * frames + f) * ldp;
+    // the power row and the chunk sums go to this transform's other
+    // ping-pong buffer, which only the last pass read
+    float* P = reinterpret_cast<float*>(sh.buf[zb ^ 1] + tr * Nc);
+    float* part = P + 1032;
     for (int k = j; k <= Nc; k += tpt) {
       const float2 X = real_bin<Nc>(Z, sh.tw, k);
-      prow[k] = f2bf(X.x * X.x + X.y * X.y);
+      P[k] = bf2f(f2bf(X.x * X.x + X.y * X.y));
     }
-    __syncthreads();                    // the buffers are reused by the next frames
+    __syncthreads();
+    if (j < nchunks) {
+      // all loads issued at once (indices clamped in bounds; unused weights are 0)
+      float acc = 0.0f;
+#pragma unroll
+      for (int i = 0; i < kMelChunk; ++i) acc += w0[i] * P[min(ps0 + i, Nc)];
+      part[j] = acc;
+    }
+    for (int c = j + tpt; c < nchunks; c += tpt) {
+      const int e = ms.chunk[c];
+      const int ws = e & 4095, ps = (e >> 12) & 2047, cnt = e >> 23;
+      float acc = 0.0f;
+#pragma unroll
+      for (int i = 0; i < kMelChunk; ++i) {
+        const float wv = ms.w[min(ws + i, kMelWeightsMax - 1)];
+        const float pv = P[min(ps + i, Nc)];
+        acc += i < cnt ? wv * pv : 0.0f;
+      }
+      part[c] = acc;
+    }
+    __syncthreads();
+    if (j < kMelBands) {
+      const int c0 = ms.cbase[j], c1 = ms.cbase[j + 1];
+      float acc = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        const float pv = part[min(c0 + i, kMelChunksMax - 1)];
+        acc += c0 + i < c1 ? pv : 0.0f;
+      }
+      for (int c = c0 + 6; c < c1; ++c) acc += part[c];
+      ms.st[j][f & 15] = logf(acc + 1e-6f);
+    }
+    if (((f0 + 2) & 15) == 0 || f0 + 2 == live2) {
+      // write out the staged frames gs .. f0 + 1: 16 consecutive frames of a
+      // band are 64 contiguous bytes
+      __syncthreads();
+      const int gs = f0 & ~15, cnt = f0 + 2 - gs;
+      for (int e = tid; e < kMelBands * 16; e += kThreads) {
+        const int bd = e >> 4, fr = e & 15;
+        if (fr < cnt) feat[bd * frames + gs + fr] = ms.st[bd][fr];
+      }
+    }
+    // The next pair's first pass writes buffer zb (read above only before the
+    // first barrier after the FFT); its second pass, after a barrier, writes
+    // this one and, later, the staging rows are rewritten after two more.
+    if (zb != 0) __syncthreads();
+  }
+  const int nz = frames - live2;
+  if (nz > 0) {
+    float zero = 0.0f;
+    asm volatile("" : "+v"(zero));      // log(0 + 1e-6) evaluated as for a computed frame
+    const float floor_v = logf(zero + 1e-6f);
+    for (int e = tid; e < kMelBands * nz; e += kThreads) {
+      const int bd = e / nz;
+      feat[bd * frames + live2 + (e - bd * nz)] = floor_v;
+    }
   }
 }
 
@@ -415,12 +569,13 @@ void plan(int64_t batch, int64_t n_samples, MrArgs& a, size_t& partial_bytes, si
 
 }  // namespace
 
-hipError_t launch_melpower(const float* audio, const int64_t* offsets, int64_t n_uniform,
-                           int64_t batch, void* power, int64_t ldp, hipStream_t s) {
+hipError_t launch_logmel_fft(const float* audio, const int64_t* offsets, int64_t n_uniform,
+                            int64_t batch, const void* mel_basis, int64_t ldm, float* features,
+                            hipStream_t s) {
   if (batch == 0) return hipSuccess;
   if (batch > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(melpower_kernel, dim3((unsigned)batch), dim3(kThreads), 0, s, audio, offsets,
-                     n_uniform, (uint16_t*)power, ldp);
+  hipLaunchKernelGGL(logmel_fft_kernel, dim3((unsigned)batch), dim3(kThreads), 0, s, audio,
+                     offsets, n_uniform, (const uint16_t*)mel_basis, ldm, features);
   return hipGetLastError();
 }
 

@@ -117,9 +117,14 @@ int64_t adjoint_max_chunks();
 hipError_t launch_render_backward(const RenderArgs& a, const float* grad_audio, double* ws,
                                   float* grad_params, int runs_per_segment, hipStream_t s);
 
-// log-mel power spectrum by FFT (spectral.hip): power bf16 [batch * 64][ldp]
-hipError_t launch_melpower(const float* audio, const int64_t* offsets, int64_t n_uniform,
-                           int64_t batch, void* power, int64_t ldp, hipStream_t s);
+// log-mel features by FFT (spectral.hip): mel_basis bf16 [128][ldm] with each
+// band's first and last nonzero bin in columns 1025 and 1026; features float32
+// [batch][128][64].
+constexpr int kMelBands = 128;
+constexpr int kMelWeightsMax = 2304;   // nonzero mel weights over all bands
+hipError_t launch_logmel_fft(const float* audio, const int64_t* offsets, int64_t n_uniform,
+                             int64_t batch, const void* mel_basis, int64_t ldm, float* features,
+                             hipStream_t s);
 size_t mrstft_workspace_bytes(int64_t batch, int64_t n_samples, bool with_grad);
 hipError_t launch_mrstft(const float* x, const float* target, int64_t batch, int64_t n_samples,
                          double* loss, float* grad, void* workspace, hipStream_t s);

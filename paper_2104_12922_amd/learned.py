@@ -111,14 +111,17 @@ class LogMel:
         else:
             B, N = offsets.numel() - 1, 0
             offp = _p(offsets, "offsets", torch.int64, B + 1)
-        need = lib().synth_logmel_workspace(B)
-        if self._ws is None or self._ws.numel() < need:
-            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         if out is None:
             out = torch.empty(B, MEL_FEATURES, dtype=F32, device=self.device)
         common = (_p(audio, "audio", F32, audio.numel()), offp, B, N)
-        tail = (self.mel.data_ptr(), self._ws.data_ptr(), self._ws.numel(),
-                _p(out, "features", F32, B * MEL_FEATURES), _stream(self.device))
+        ws = (None, 0)
+        if self.method == "mfma":              # the FFT path needs no workspace
+            need = lib().synth_logmel_workspace(B)
+            if self._ws is None or self._ws.numel() < need:
+                self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            ws = (self._ws.data_ptr(), self._ws.numel())
+        tail = (self.mel.data_ptr(), *ws, _p(out, "features", F32, B * MEL_FEATURES),
+                _stream(self.device))
         if self.method == "fft":
             _native.check("synth_logmel", lib().synth_logmel(*common, *tail))
         else:
