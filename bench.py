@@ -163,11 +163,12 @@ def bench_learned(args):
         ms = lambda ev: float(np.mean([a.elapsed_time(b) for a, b in ev]))
         r_ms, l_ms, m_ms = ms(e_r), ms(e_l), ms(e_m)
     step_s = float(np.mean(t_step))
-    # log-mel algorithmic bytes: frame samples inside each voice (float32),
-    # the bf16 power spectrum written and read back, the float32 features
+    # log-mel algorithmic bytes (one fused kernel): frame samples inside each
+    # voice read once (float32; frames do not overlap at hop 2756), the
+    # float32 features written
     lens = np.array([int(round(s * 44100.0)) for s in (1, 2, 3, 4)])[np.arange(B) % 4]
     inside = int(np.clip(lens[:, None] - 2756 * np.arange(64)[None, :], 0, 2048).sum())
-    mel_bytes = 4.0 * inside + 2 * 2.0 * B * 64 * 1025 + 4.0 * B * 8192
+    mel_bytes = 4.0 * inside + 4.0 * B * 8192
     gbs = mel_bytes / (l_ms * 1e-3) / 1e9
     out = {"metric": "proposal training voices/sec", "value": B / step_s, "unit": "voices/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_s * 1e3,
@@ -181,7 +182,7 @@ def bench_learned(args):
            "render_plan_ms": (dict(Lr._TUNER.timings) if Lr._TUNER is not None else None),
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                        "kernel": "log-mel (FFT power + mel GEMM)",
+                        "kernel": "logmel_fft_kernel (FFT, power, mel bands, log)",
                         "alg_bytes_per_launch": mel_bytes},
            "mlp_tflops": mlp_flop * B / (m_ms * 1e-3) / 1e12}
     print(json.dumps(out), flush=True)
