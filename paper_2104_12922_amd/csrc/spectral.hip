@@ -32,6 +32,10 @@ namespace {
 constexpr int kThreads = 512;
 constexpr int kMaxN = 2048;
 constexpr int kFramesPerBlock = 16;
+// A workgroup's frames f0 .. f0 + 15 cover hops f0 .. f0 + 18 of the voice:
+// their gradient rows are overlap-added in LDS into one segment of 19 hops.
+constexpr int kSegHops = kFramesPerBlock + 3;
+constexpr int kOlaSlots = 2048;
 constexpr float kEps = 1e-5f;
 // LDS slot swizzle (a bijection within each block of 128 float2): XORs index
 // bits 4-6 into bits 0-4 so that the strided writes of the first Stockham
@@ -57,9 +61,9 @@ struct MrArgs {
   int64_t batch;
   int F[3];                    // frames per resolution
   int chunk_base[4];           // first block index of each resolution's chunks
-  int64_t wbase[3];            // workspace float offset of each resolution's rows
+  int64_t wbase[3];            // workspace float offset of each resolution's segments
   double scale[3];             // 1 / (F (n/2 + 1))
-  float* wgrad;                // frame gradient rows (null: loss only)
+  float* wgrad;                // per-workgroup gradient segments (null: loss only)
   double* partial;             // [batch][chunk_base[3]] loss partial sums
   float* grad;                 // output gradient (null: loss only)
   double* loss;
@@ -199,7 +203,8 @@ __device__ __forceinline__ float2 real_bin(const float2* Z, const float2* tw, in
 }
 
 template <int RES>
-__device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, int64_t b, int blk) {
+__device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, float* ola,
+                                              int64_t b, int blk) {
   constexpr int r = RES;
   const int tid = threadIdx.x;
   const int chunk = blk - a.chunk_base[r];
@@ -224,6 +229,15 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, i
 
   const int f_begin = chunk * kFramesPerBlock;
   const int f_end = min(F, f_begin + kFramesPerBlock);
+  // Overlap-add accumulator: block-relative position p lives at ola[p % 2048]
+  // (the unfinished positions never span more than (fpi - 1) hop + n <= 2048);
+  // a position is written out to the segment, and its slot cleared, as soon
+  // as no later frame of the block covers it.
+  const int nch = a.chunk_base[r + 1] - a.chunk_base[r];
+  float* seg = want_grad ? a.wgrad + a.wbase[r] + ((int64_t)b * nch + chunk) * (kSegHops * hop)
+                         : nullptr;
+  if (want_grad)
+    for (int i = tid; i < kOlaSlots; i += kThreads) ola[i] = 0.0f;
   for (int f0 = f_begin; f0 < f_end; f0 += fpi) {
     const int f = f0 + slot;
     const bool live = f < f_end;
@@ -281,17 +295,36 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, i
       float2* c0 = sh.buf[0] + slot * 2 * Nc;  // the frame slot's two transform areas
       float2* c1 = sh.buf[1] + slot * 2 * Nc;
       const int yb = fft_passes<Nc, 1, 0>(y, j, 1.0f, sh.ptw, c0, c1, inv_active);
-      if (live && inv_active) {
-        const float2* Y = sh.buf[yb] + slot * 2 * Nc;
-        float* out = a.wgrad + a.wbase[r] + ((int64_t)b * F + f) * n;
-        for (int m = j; m < Nc; m += tpt) {
-          const float2 yy = Y[swz(m)];
-          out[2 * m] = 0.5f * sh.win[2 * m] * yy.x;
-          out[2 * m + 1] = 0.5f * sh.win[2 * m + 1] * yy.y;
+      // ---- overlap-add: frame f0 + s contributes 0.5 w(o) y(o) at o = p - s hop ----
+      const int p0 = (f0 - f_begin) * hop;           // block-relative start of frame f0
+      for (int p = tid; p < (fpi - 1) * hop + n; p += kThreads) {
+        float g = 0.0f;
+#pragma unroll
+        for (int s2 = 0; s2 < fpi; ++s2) {
+          const int o = p - s2 * hop;
+          if (o >= 0 && o < n && f0 + s2 < f_end) {
+            const float2 yy = (sh.buf[yb] + s2 * 2 * Nc)[swz(o >> 1)];
+            g += 0.5f * sh.win[o] * ((o & 1) ? yy.y : yy.x);
+          }
+        }
+        float* slotp = ola + ((p0 + p) & (kOlaSlots - 1));
+        const float v = *slotp + g;
+        if (p < fpi * hop) {                         // no later frame reaches it
+          seg[p0 + p] = v;
+          *slotp = 0.0f;
+        } else {
+          *slotp = v;
         }
       }
       __syncthreads();
     }
+  }
+  if (want_grad) {
+    // the rest of the segment: the last frames' tails (3 hops past the
+    // written part), then zeros
+    const int done = ((f_end - f_begin + fpi - 1) / fpi) * fpi * hop;
+    for (int p = done + tid; p < kSegHops * hop; p += kThreads)
+      seg[p] = p < done + 3 * hop ? ola[p & (kOlaSlots - 1)] : 0.0f;
   }
   // fixed-order reduction of the per-thread loss shares
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o);
@@ -306,14 +339,15 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, i
 
 __global__ void __launch_bounds__(kThreads) mrstft_frames_kernel(const MrArgs a) {
   __shared__ SpecShared sh;
+  __shared__ float ola[kOlaSlots];
   const int64_t b = blockIdx.y;
   const int blk = blockIdx.x;
   if (blk < a.chunk_base[1])
-    mrstft_frames<0>(a, sh, b, blk);
+    mrstft_frames<0>(a, sh, ola, b, blk);
   else if (blk < a.chunk_base[2])
-    mrstft_frames<1>(a, sh, b, blk);
+    mrstft_frames<1>(a, sh, ola, b, blk);
   else
-    mrstft_frames<2>(a, sh, b, blk);
+    mrstft_frames<2>(a, sh, ola, b, blk);
 }
 
 // Log-mel features by FFT, one workgroup per voice: frames f < 64 of 2048
@@ -524,8 +558,9 @@ __global__ void __launch_bounds__(kThreads) logmel_fft_kernel(const float* __res
   }
 }
 
-// grad[b][i] = sum over resolutions, then frames f covering i, of the frame
-// row at i - f hop; block x == 0 also sums voice b's loss partials.
+// grad[b][i] = sum over resolutions, then over the (at most two) workgroup
+// segments covering i, in workgroup order; block x == 0 also sums voice b's
+// loss partials.
 __global__ void __launch_bounds__(256) mrstft_combine_kernel(const MrArgs a) {
   const int64_t b = blockIdx.y;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -538,13 +573,17 @@ __global__ void __launch_bounds__(256) mrstft_combine_kernel(const MrArgs a) {
   if (i >= a.n) return;
   float g = 0.0f;
   for (int r = 0; r < 3; ++r) {
-    const int n = 512 << r, hop = n / 4, F = a.F[r];
-    if (F == 0) continue;
-    int64_t fhi = i / hop;
-    if (fhi > F - 1) fhi = F - 1;
-    int64_t flo = i - n + 1 <= 0 ? 0 : (i - n + 1 + hop - 1) / hop;
-    const float* rows = a.wgrad + a.wbase[r] + b * (int64_t)F * n;
-    for (int64_t f = flo; f <= fhi; ++f) g += rows[f * n + (i - f * hop)];
+    const int n = 512 << r, hop = n / 4;
+    const int nch = a.chunk_base[r + 1] - a.chunk_base[r];
+    if (nch == 0) continue;
+    const int64_t h = i / hop;                       // hop of sample i
+    int64_t khi = h / kFramesPerBlock;
+    if (khi > nch - 1) khi = nch - 1;
+    const int64_t klo = h >= kSegHops ? (h - kSegHops) / kFramesPerBlock + 1 : 0;
+    const int64_t seglen = (int64_t)kSegHops * hop;
+    const float* segs = a.wgrad + a.wbase[r] + b * nch * seglen;
+    for (int64_t k = klo; k <= khi; ++k)
+      g += segs[k * seglen + (i - k * kFramesPerBlock * hop)];
   }
   a.grad[b * a.n + i] = g;
 }
@@ -559,7 +598,7 @@ void plan(int64_t batch, int64_t n_samples, MrArgs& a, size_t& partial_bytes, si
     a.chunk_base[r] = cb;
     cb += (int)((F + kFramesPerBlock - 1) / kFramesPerBlock);
     a.wbase[r] = wb;
-    wb += batch * F * n;
+    wb += batch * ((F + kFramesPerBlock - 1) / kFramesPerBlock) * kSegHops * (n / 4);
     a.scale[r] = F > 0 ? 1.0 / ((double)F * (double)(n / 2 + 1)) : 0.0;
   }
   a.chunk_base[3] = cb;
