@@ -25,6 +25,7 @@
 #include <math.h>
 
 #include "synth_internal.h"
+#include "wave_fft.h"
 
 namespace synth {
 namespace {
@@ -350,45 +351,55 @@ __global__ void __launch_bounds__(kThreads) mrstft_frames_kernel(const MrArgs a)
     mrstft_frames<2>(a, sh, ola, b, blk);
 }
 
-// Log-mel features by FFT, one workgroup per voice: frames f < 64 of 2048
-// samples at hop 2756 (samples past the voice's end read as 0), periodic Hann
-// window, power spectrum |X_fk|^2 (k <= 1024) rounded to bf16, each mel band's
-// sum over its nonzero bins in float32, log(x + 1e-6) into
-// features[b][band][f].  Two frames (two 1024-point complex FFTs) at a time;
-// the power row goes to the transform's free ping-pong buffer and the bands
-// are summed from there, so nothing but the features leaves the CU.
+// Log-mel features by FFT, one workgroup of 4 wavefronts per voice: frames
+// f < 64 of 2048 samples at hop 2756 (samples past the voice's end read as
+// 0), periodic Hann window, power spectrum |X_fk|^2 (k <= 1024) rounded to
+// bf16, each mel band's sum over its nonzero bins in float32, log(x + 1e-6)
+// into features[b][band][f].  Wavefront w takes frames w, w + 4, ...: a
+// 1024-point complex wave FFT of z[m] = w x[2m] + i w x[2m+1], the real
+// spectrum from Z_k and Z_{1024-k}, the power row and the band sums in its
+// own LDS buffer; the only workgroup barriers are around the staged feature
+// stores (every 16 frames).
 __device__ __forceinline__ uint16_t f2bf(float f) {
   const uint32_t u = __float_as_uint(f);
   if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
   return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// |X|^2 rounded to bf16 (hardware round-to-nearest-even conversion)
+__device__ __forceinline__ float pow_bf16(float2 X) {
+  return (float)(__bf16)(X.x * X.x + X.y * X.y);
+}
 
 // A band's weights are summed in chunks of at most kMelChunk bins, one chunk
-// per thread, then each band adds its chunks' sums in order: the work per
-// thread stays even although band widths range from 1 to ~60 bins.
+// per lane, then each band adds its chunks' sums in order: the work per lane
+// stays even although band widths range from 1 to ~60 bins.
 constexpr int kMelChunk = 12;
 constexpr int kMelChunksMax = kMelWeightsMax / kMelChunk + kMelBands;
+constexpr int kMelWaves = 4;
+constexpr int kMelThreads = 64 * kMelWaves;
 
 struct MelShared {
-  float w[kMelWeightsMax];     // band b's weights, bins lo[b] .. lo[b] + width - 1, at w[off[b]]
+  float wt[kMelChunk][kMelChunksMax];   // chunk c's weights, zero-padded to kMelChunk
   int lo[kMelBands];
   int off[kMelBands + 1];
   int cbase[kMelBands + 1];    // band b's chunks: cbase[b] .. cbase[b + 1] - 1
-  int chunk[kMelChunksMax];    // weight start | bin start << 12 | count << 23
-  float st[kMelBands][17];     // features of up to 16 frames, written out together
+  int chunk[kMelChunksMax];    // first bin of chunk c
+  float st[kMelBands][17];     // features of 16 frames, written out together
+  alignas(8) float win[2048];  // periodic Hann window
+  float2 rs[513];              // exp(-2 pi i k / 2048), k <= 512 (real split)
+  float2 pt[wfft::pt_size<1024>()];   // FFT pass twiddles
 };
 
-__global__ void __launch_bounds__(kThreads) logmel_fft_kernel(const float* __restrict__ audio,
-                                                              const int64_t* __restrict__ offsets,
-                                                              int64_t n_uniform,
-                                                              const uint16_t* __restrict__ mel,
-                                                              int64_t ldm,
-                                                              float* __restrict__ features) {
-  __shared__ SpecShared sh;
+__global__ void __launch_bounds__(kMelThreads) __attribute__((amdgpu_waves_per_eu(2)))
+logmel_fft_kernel(const float* __restrict__ audio, const int64_t* __restrict__ offsets,
+                  int64_t n_uniform, const uint16_t* __restrict__ mel, int64_t ldm,
+                  float* __restrict__ features) {
+  constexpr int Nc = 1024, P = 16, hop = 2756, frames = 64;
+  __shared__ float2 wbuf[kMelWaves][Nc];
   __shared__ MelShared ms;
-  constexpr int Nc = 1024, tpt = 256, hop = 2756, frames = 64;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
   const int64_t b = blockIdx.x;
   int64_t start, len;
   if (offsets) {
@@ -401,9 +412,7 @@ __global__ void __launch_bounds__(kThreads) logmel_fft_kernel(const float* __res
   const float* x = audio + start;
   float* feat = features + b * (int64_t)(kMelBands * frames);
 
-  // band table: each band's first and last nonzero bin sit in its row's
-  // padding columns 1025, 1026; weight offsets and chunk counts are
-  // prefix-summed by one wave
+  // ---- set-up: band table (wavefront 0), twiddle table T[k] = exp(-2 pi i k / 2048) ----
   if (tid < 64) {
     int lo[2], wd[2], nc[2];
 #pragma unroll
@@ -432,128 +441,128 @@ __global__ void __launch_bounds__(kThreads) logmel_fft_kernel(const float* __res
       ms.cbase[kMelBands] = min(ic, kMelChunksMax);
     }
   }
-  fft_tables<2>(sh);                    // ends with a barrier
-  for (int e = tid; e < kMelBands * 4; e += kThreads) {
+  for (int k = tid; k <= Nc / 2; k += kMelThreads) {
+    float sn, cs;
+    sincospif((float)k / (float)Nc, &sn, &cs);
+    ms.rs[k] = make_float2(cs, -sn);
+  }
+  for (int k = tid; k < 2 * Nc; k += kMelThreads)
+    ms.win[k] = 0.5f - 0.5f * cospif(2.0f * (float)k / (float)(2 * Nc));
+  wfft::build_pass_twiddles<Nc>(ms.pt, tid, kMelThreads);
+  __syncthreads();                      // band table and LDS tables written
+  for (int e = tid; e < kMelBands * 4; e += kMelThreads) {
     const int bd = e >> 2;
-    const int o0 = ms.off[bd], o1 = min(ms.off[bd + 1], kMelWeightsMax);
+    const int wd = ms.off[bd + 1] - ms.off[bd];
     const uint16_t* row = mel + (int64_t)bd * ldm + ms.lo[bd];
-    for (int i = e & 3; o0 + i < o1; i += 4) ms.w[o0 + i] = bf2f(row[i]);
     for (int c = ms.cbase[bd] + (e & 3), q = e & 3; c < ms.cbase[bd + 1]; c += 4, q += 4) {
-      const int ws = o0 + q * kMelChunk;
-      const int cnt = max(0, min(kMelChunk, o1 - ws));
-      ms.chunk[c] = min(ws, kMelWeightsMax) | ((ms.lo[bd] + q * kMelChunk) << 12) | (cnt << 23);
+      ms.chunk[c] = ms.lo[bd] + q * kMelChunk;
+#pragma unroll
+      for (int i = 0; i < kMelChunk; ++i)
+        ms.wt[i][c] = q * kMelChunk + i < wd ? bf2f(row[q * kMelChunk + i]) : 0.0f;
     }
   }
   __syncthreads();
   const int nchunks = ms.cbase[kMelBands];
-  // thread j's first chunk (c = j) is the same for every frame: its weights
-  // stay in registers
-  const int e0 = tid % 256 < nchunks ? ms.chunk[tid % 256] : 0;
-  const int ps0 = (e0 >> 12) & 2047, cnt0 = e0 >> 23;
-  float w0[kMelChunk];
-#pragma unroll
-  for (int i = 0; i < kMelChunk; ++i)
-    w0[i] = i < cnt0 ? ms.w[min((e0 & 4095) + i, kMelWeightsMax - 1)] : 0.0f;
 
-  const int tr = tid / tpt;             // 0, 1: the iteration's two frames
-  const int j = tid - tr * tpt;
+  float2* buf = wbuf[wv];
+  // power row P[0..1024] (a chunk may read up to 11 slots past it, where its
+  // weights are 0), chunk sums from 1040
+  float* Pw = reinterpret_cast<float*>(buf);
+  float* part = Pw + 1040;
   // Frames that start at or past the voice's end hold only zero padding:
   // their features are log(1e-6) and they skip the FFT.
   const int64_t nlive = len <= 0 ? 0 : (len + hop - 1) / hop;
   const int live = (int)(nlive < frames ? nlive : frames);
-  const int live2 = (live + 1) & ~1;    // frames are transformed in pairs
-  // the next pair's samples are fetched into registers during this pair's FFT
-  float s[8];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t i0 = (int64_t)tr * hop + 2 * (j + q * tpt);
-    s[2 * q] = i0 < len ? x[i0] : 0.0f;
-    s[2 * q + 1] = i0 + 1 < len ? x[i0 + 1] : 0.0f;
+  // this wavefront's next frame's samples, fetched during the current one
+  float s[2 * P];
+#define LM_FETCH(f_)                                                    \
+  {                                                                     \
+    const int64_t pos = (int64_t)(f_) * hop;                            \
+    _Pragma("unroll") for (int r = 0; r < P; ++r) {                     \
+      const int64_t i0 = pos + 2 * (lane + 64 * r);                     \
+      s[2 * r] = i0 < len ? x[i0] : 0.0f;                               \
+      s[2 * r + 1] = i0 + 1 < len ? x[i0 + 1] : 0.0f;                   \
+    }                                                                   \
   }
-  for (int f0 = 0; f0 < live2; f0 += 2) {
-    const int f = f0 + tr;
-    float2 v[4];
+  if (wv < live) LM_FETCH(wv)
+  for (int g = 0; 16 * g < live; ++g) {
+#pragma unroll 1
+    for (int i = 0; i < 4; ++i) {
+      const int f = 16 * g + wv + 4 * i;
+      if (f >= live) break;
+      float2 v[P];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int m = j + q * tpt;
-      v[q] = make_float2(sh.win[2 * m] * s[2 * q], sh.win[2 * m + 1] * s[2 * q + 1]);
-    }
-    if (f0 + 2 < live2) {
-      const int64_t pos = (int64_t)(f + 2) * hop;
+      for (int r = 0; r < P; ++r) {
+        const float2 w2 = *reinterpret_cast<const float2*>(&ms.win[2 * (lane + 64 * r)]);
+        v[r] = make_float2(w2.x * s[2 * r], w2.y * s[2 * r + 1]);
+      }
+      if (f + 4 < live) LM_FETCH(f + 4)
+      wfft::wave_fft<Nc, true>(v, buf, ms.pt, lane);
+      // ---- real spectrum: X_k = E + W^k O, X_{Nc-k} = conj(E - W^k O) ----
+      float pk[9], pm[9];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t i0 = pos + 2 * (j + q * tpt);
-        s[2 * q] = i0 < len ? x[i0] : 0.0f;
-        s[2 * q + 1] = i0 + 1 < len ? x[i0 + 1] : 0.0f;
+      for (int q = 0; q < 9; ++q) {
+        const int k = q < 8 ? lane + 64 * q : 512;
+        const float2 zk = buf[wfft::swz<Nc>(k)];
+        const float2 zc = buf[wfft::swz<Nc>((Nc - k) & (Nc - 1))];
+        const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
+        const float2 O = make_float2(0.5f * (zk.y + zc.y), -0.5f * (zk.x - zc.x));
+        const float2 w = ms.rs[k];
+        const float2 WO = wfft::cmul(w, O);
+        pk[q] = pow_bf16(wfft::add(E, WO));
+        pm[q] = pow_bf16(wfft::sub(E, WO));
+      }
+      wfft::wave_fence();
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = lane + 64 * q;
+        Pw[k] = pk[q];
+        Pw[Nc - k] = pm[q];
+      }
+      if (lane == 0) Pw[512] = pk[8];
+      wfft::wave_fence();
+      // ---- band sums: chunk c = lane + 64 i, then band b = lane, lane + 64 ----
+      for (int c = lane; c < nchunks; c += 64) {
+        const float* pc = Pw + ms.chunk[c];
+        float acc = 0.0f;
+#pragma unroll
+        for (int i2 = 0; i2 < kMelChunk; ++i2) acc = fmaf(ms.wt[i2][c], pc[i2], acc);
+        part[c] = acc;
+      }
+      wfft::wave_fence();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int bd = lane + 64 * h;
+        const int c0 = ms.cbase[bd], c1 = ms.cbase[bd + 1];
+        float acc = 0.0f;
+#pragma unroll
+        for (int i2 = 0; i2 < 6; ++i2) {
+          const float pv = part[min(c0 + i2, kMelChunksMax - 1)];
+          acc += c0 + i2 < c1 ? pv : 0.0f;
+        }
+        for (int c = c0 + 6; c < c1; ++c) acc += part[c];
+        ms.st[bd][f & 15] = logf(acc + 1e-6f);
       }
     }
-    float2* b0 = sh.buf[0] + tr * Nc;
-    float2* b1 = sh.buf[1] + tr * Nc;
-    const int zb = fft_passes<Nc, 1, 0>(v, j, -1.0f, sh.ptw, b0, b1, true);
-    const float2* Z = sh.buf[zb] + tr * Nc;
-    // the power row and the chunk sums go to this transform's other
-    // ping-pong buffer, which only the last pass read
-    float* P = reinterpret_cast<float*>(sh.buf[zb ^ 1] + tr * Nc);
-    float* part = P + 1032;
-    for (int k = j; k <= Nc; k += tpt) {
-      const float2 X = real_bin<Nc>(Z, sh.tw, k);
-      P[k] = bf2f(f2bf(X.x * X.x + X.y * X.y));
+    // write out frames 16 g .. of the group: 16 consecutive frames of a band
+    // are 64 contiguous bytes
+    __syncthreads();
+    const int cnt = min(16, live - 16 * g);
+    for (int e = tid; e < kMelBands * 16; e += kMelThreads) {
+      const int bd = e >> 4, fr = e & 15;
+      if (fr < cnt) feat[bd * frames + 16 * g + fr] = ms.st[bd][fr];
     }
     __syncthreads();
-    if (j < nchunks) {
-      // all loads issued at once (indices clamped in bounds; unused weights are 0)
-      float acc = 0.0f;
-#pragma unroll
-      for (int i = 0; i < kMelChunk; ++i) acc += w0[i] * P[min(ps0 + i, Nc)];
-      part[j] = acc;
-    }
-    for (int c = j + tpt; c < nchunks; c += tpt) {
-      const int e = ms.chunk[c];
-      const int ws = e & 4095, ps = (e >> 12) & 2047, cnt = e >> 23;
-      float acc = 0.0f;
-#pragma unroll
-      for (int i = 0; i < kMelChunk; ++i) {
-        const float wv = ms.w[min(ws + i, kMelWeightsMax - 1)];
-        const float pv = P[min(ps + i, Nc)];
-        acc += i < cnt ? wv * pv : 0.0f;
-      }
-      part[c] = acc;
-    }
-    __syncthreads();
-    if (j < kMelBands) {
-      const int c0 = ms.cbase[j], c1 = ms.cbase[j + 1];
-      float acc = 0.0f;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        const float pv = part[min(c0 + i, kMelChunksMax - 1)];
-        acc += c0 + i < c1 ? pv : 0.0f;
-      }
-      for (int c = c0 + 6; c < c1; ++c) acc += part[c];
-      ms.st[j][f & 15] = logf(acc + 1e-6f);
-    }
-    if (((f0 + 2) & 15) == 0 || f0 + 2 == live2) {
-      // write out the staged frames gs .. f0 + 1: 16 consecutive frames of a
-      // band are 64 contiguous bytes
-      __syncthreads();
-      const int gs = f0 & ~15, cnt = f0 + 2 - gs;
-      for (int e = tid; e < kMelBands * 16; e += kThreads) {
-        const int bd = e >> 4, fr = e & 15;
-        if (fr < cnt) feat[bd * frames + gs + fr] = ms.st[bd][fr];
-      }
-    }
-    // The next pair's first pass writes buffer zb (read above only before the
-    // first barrier after the FFT); its second pass, after a barrier, writes
-    // this one and, later, the staging rows are rewritten after two more.
-    if (zb != 0) __syncthreads();
   }
-  const int nz = frames - live2;
+#undef LM_FETCH
+  const int nz = frames - live;
   if (nz > 0) {
     float zero = 0.0f;
     asm volatile("" : "+v"(zero));      // log(0 + 1e-6) evaluated as for a computed frame
     const float floor_v = logf(zero + 1e-6f);
-    for (int e = tid; e < kMelBands * nz; e += kThreads) {
+    for (int e = tid; e < kMelBands * nz; e += kMelThreads) {
       const int bd = e / nz;
-      feat[bd * frames + live2 + (e - bd * nz)] = floor_v;
+      feat[bd * frames + live + (e - bd * nz)] = floor_v;
     }
   }
 }
@@ -613,7 +622,7 @@ hipError_t launch_logmel_fft(const float* audio, const int64_t* offsets, int64_t
                             hipStream_t s) {
   if (batch == 0) return hipSuccess;
   if (batch > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(logmel_fft_kernel, dim3((unsigned)batch), dim3(kThreads), 0, s, audio,
+  hipLaunchKernelGGL(logmel_fft_kernel, dim3((unsigned)batch), dim3(kMelThreads), 0, s, audio,
                      offsets, n_uniform, (const uint16_t*)mel_basis, ldm, features);
   return hipGetLastError();
 }
