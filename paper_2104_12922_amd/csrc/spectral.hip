@@ -6,22 +6,22 @@
 //          mean_{frame t, bin k <= n/2} |log(|X_tk| + 1e-5) - log(|T_tk| + 1e-5)|
 // with X, T the periodic-Hann STFTs (no padding) of the render x and target.
 //
-// Frames are independent jobs.  Kernel 1 (512 threads per workgroup, grid =
-// voices x (frame chunks of every resolution)) takes 16 frames of one
-// resolution per workgroup.  A real frame of n samples is transformed as a
-// complex sequence of n/2 points (even samples real, odd imaginary) by a
-// Stockham autosort FFT - radix-4 passes and one radix-2 pass when log2(n/2)
-// is odd - with one radix-4 butterfly per thread and pass, twiddles from an
-// LDS table, then split into the n/2 + 1 bins of the real spectrum.  Render
-// and target frames get separate FFTs (a shared complex FFT would leak the
-// louder signal's rounding noise into the quieter one's spectrum).  For the
-// gradient, G_k = sign(d_k) X_k / (|X_k| (|X_k| + eps)) / (F (n/2 + 1)) is
-// extended to a Hermitian spectrum H (H_0 = 2 Re G_0, H_{n/2} = 2 Re G_{n/2}),
-// inverted by the same half-size complex FFT, and the frame's gradient
-// 0.5 w(m) h(m) is written to a workspace row of its own.  Kernel 2 adds,
-// for every sample, the rows of the frames that cover it in a fixed order
-// (resolution, then frame), and sums the per-workgroup loss partials in a
-// fixed order: bitwise deterministic, no atomics.
+// Frames are independent jobs.  Kernel 1 (grid = voices x frame chunks of
+// every resolution) takes 16 frames of one resolution per workgroup of four
+// wavefronts; wavefront w takes frames f0 + 4 i + w.  A real frame of n
+// samples is transformed as a complex sequence of n/2 points (even samples
+// real, odd imaginary) by a wave-level Stockham FFT, then split into the
+// n/2 + 1 bins of the real spectrum.  Render and target frames get separate
+// FFTs (a shared complex FFT would leak the louder signal's rounding noise
+// into the quieter one's spectrum).  For the gradient,
+// G_k = sign(d_k) X_k / (|X_k| (|X_k| + eps)) / (F (n/2 + 1)) is extended to a
+// Hermitian spectrum H (H_0 = 2 Re G_0, H_{n/2} = 2 Re G_{n/2}), inverted by
+// the same half-size complex FFT, and the frame's gradient 0.5 w(m) h(m) is
+// overlap-added, four frames at a time in frame order, into the workgroup's
+// segment of 19 hops.  Kernel 2 adds, for every sample, the (at most two)
+// segments that cover it per resolution in a fixed order, and sums the
+// per-workgroup loss partials in a fixed order: bitwise deterministic, no
+// atomics.
 #include <math.h>
 
 #include "synth_internal.h"
@@ -30,30 +30,14 @@
 namespace synth {
 namespace {
 
-constexpr int kThreads = 512;
-constexpr int kMaxN = 2048;
+constexpr int kMrWaves = 4;
+constexpr int kMrThreads = 64 * kMrWaves;
 constexpr int kFramesPerBlock = 16;
 // A workgroup's frames f0 .. f0 + 15 cover hops f0 .. f0 + 18 of the voice:
 // their gradient rows are overlap-added in LDS into one segment of 19 hops.
 constexpr int kSegHops = kFramesPerBlock + 3;
-constexpr int kOlaSlots = 2048;
+constexpr int kOlaSlots = 4096;   // >= the 7 hops of four frames at n = 2048
 constexpr float kEps = 1e-5f;
-// LDS slot swizzle (a bijection within each block of 128 float2): XORs index
-// bits 4-6 into bits 0-4 so that the strided writes of the first Stockham
-// passes (strides of 4 and 16 slots) and the contiguous reads all fall on
-// distinct banks, for 32 or 64 four-byte banks.
-__device__ __forceinline__ int swz(int i) { return i ^ (5 * ((i >> 4) & 3)) ^ ((i >> 2) & 16); }
-constexpr int kPadded = kMaxN;
-
-constexpr int kPassTw = 1280;  // per-pass twiddles (Nc = 512 needs 1276)
-
-struct SpecShared {
-  float2 tw[kMaxN / 2];        // tw[k] = exp(-2 pi i k / n), k < n / 2
-  float2 ptw[kPassTw];         // per-pass twiddles, contiguous in the butterfly index
-  float win[kMaxN];            // periodic Hann window
-  float2 buf[2][kPadded];      // FFT ping-pong: (512 / (n/8)) transforms of n/2 points (swizzled)
-  double red[kThreads / 64];
-};
 
 struct MrArgs {
   const float* x;
@@ -70,285 +54,224 @@ struct MrArgs {
   double* loss;
 };
 
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+struct MrShared {
+  float2 buf[kMrWaves][1024];  // one FFT buffer per wavefront (n/2 complex points)
+  alignas(8) float win[2048];  // periodic Hann window of the workgroup's resolution
+  float2 rs[513];              // exp(-2 pi i k / n), k <= n / 4 (real split)
+  float2 pt[wfft::pt_size<1024>()];   // FFT pass twiddles
+  float ola[kOlaSlots];        // overlap-add accumulator
+  double red[kMrWaves];
+};
 
-// One Stockham pass of radix R on the transform of NC points whose butterfly
-// j (0 <= j < NC / R) this thread owns: inputs v[r] = src[j + r NC / R], the
-// twiddles exp(dir 2 pi i (j mod NS) r / (NS R)), the R-point DFT, outputs to
-// dst[(j / NS) NS R + (j mod NS) + r NS].  tw holds exp(-2 pi i k / (2 NC)).
-// NS and NC are powers of two known at compile time.
-// Per-pass twiddle tables: the radix-4 pass with stride NS (NS >= 4) keeps
-// exp(-2 pi i k r / (4 NS)) for k < NS, r = 1..3 at ptw[off4(NS) + 3 k + r - 1];
-// the radix-2 pass (stride NS) keeps exp(-2 pi i k / (2 NS)) at ptw[off4(NS) + k].
-// Lanes read consecutive entries.
-constexpr int off4(int ns) { return ns <= 4 ? 0 : off4(ns / 4) + 3 * (ns / 4); }
-
-template <int R, int NS, int NC>
-__device__ __forceinline__ void butterfly(float2 (&v)[4], int j, float dir, const float2* ptw) {
-  const int k = j & (NS - 1);
-  if constexpr (NS > 1) {
-#pragma unroll
-    for (int r = 1; r < R; ++r) {
-      float2 w = ptw[off4(NS) + (R - 1) * k + (r - 1)];
-      if (dir > 0.0f) w.y = -w.y;
-      v[r] = cmul(v[r], w);
-    }
-  }
-  if constexpr (R == 4) {
-    const float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-    const float2 t2 = cadd(v[1], v[3]);
-    float2 t3 = csub(v[1], v[3]);
-    t3 = dir < 0.0f ? make_float2(t3.y, -t3.x) : make_float2(-t3.y, t3.x);   // -i or +i
-    v[0] = cadd(t0, t2);
-    v[1] = cadd(t1, t3);
-    v[2] = csub(t0, t2);
-    v[3] = csub(t1, t3);
-  } else {
-    const float2 a = v[0], b = v[1];
-    v[0] = cadd(a, b);
-    v[1] = csub(a, b);
-  }
-}
-
-// The passes of a complex FFT of NC points held by NC / 4 threads (thread j
-// of the transform), starting from v (the first pass's inputs v[r] =
-// z[j + r NC / 4]), ping-ponging between base0 and base1 (each NC points).
-// Every thread of the workgroup calls it (it contains barriers); `active`
-// marks the threads that own a butterfly.  CUR is the buffer the pass writes;
-// the natural-order result ends in the buffer whose index is returned.
-template <int NC, int NS, int CUR>
-__device__ __forceinline__ int fft_passes(float2 (&v)[4], int j, float dir, const float2* ptw,
-                                          float2* base0, float2* base1, bool active) {
-  constexpr int REM = NC / NS;
-  if constexpr (REM <= 1) {
-    return CUR ^ 1;
-  } else {
-    constexpr int R = (REM % 4 == 0) ? 4 : 2;
-    float2* dst = CUR == 0 ? base0 : base1;
-    const float2* src = CUR == 0 ? base1 : base0;
-    constexpr bool first = NS == 1;
-    if (active) {
-      if constexpr (R == 4) {
-        if constexpr (!first) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) v[r] = src[swz(j + r * (NC / 4))];
-        }
-        butterfly<4, NS, NC>(v, j, dir, ptw);
-        const int d = ((j & ~(NS - 1)) << 2) + (j & (NS - 1));
-#pragma unroll
-        for (int r = 0; r < 4; ++r) dst[swz(d + r * NS)] = v[r];
-      } else {
-        // radix 2 (last pass): NC / 2 butterflies, two per thread (j, j + NC / 4)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int jj = j + h * (NC / 4);
-          float2 u[4];
-          u[0] = src[swz(jj)];
-          u[1] = src[swz(jj + NC / 2)];
-          butterfly<2, NS, NC>(u, jj, dir, ptw);
-          const int d = ((jj & ~(NS - 1)) << 1) + (jj & (NS - 1));
-          dst[swz(d)] = u[0];
-          dst[swz(d + NS)] = u[1];
-        }
-      }
-    }
-    __syncthreads();
-    return fft_passes<NC, NS * R, CUR ^ 1>(v, j, dir, ptw, base0, base1, active);
-  }
-}
-
-// Twiddle, window and per-pass tables for frames of n = 512 << RES samples
-// (every thread of the workgroup takes part; ends with a barrier).
-template <int RES>
-__device__ __forceinline__ void fft_tables(SpecShared& sh) {
-  constexpr int n = 512 << RES;
-  constexpr int Nc = n / 2;
-  const int tid = threadIdx.x;
-  for (int k = tid; k < n; k += kThreads) {
-    if (k < Nc) {
-      float s, c;
-      sincospif(2.0f * (float)k / (float)n, &s, &c);
-      sh.tw[k] = make_float2(c, -s);
-    }
-    sh.win[k] = 0.5f - 0.5f * cospif(2.0f * (float)k / (float)n);
-  }
-  for (int ns = 4, rem = Nc / 4; rem > 1; ns *= 4, rem /= 4) {
-    const int R = rem % 4 == 0 ? 4 : 2;       // radix of the pass with stride ns
-    for (int e = tid; e < (R - 1) * ns; e += kThreads) {
-      const int k = e / (R - 1), r = e % (R - 1) + 1;
-      float sn, cs;
-      sincospif(-2.0f * (float)(k * r) / (float)(R * ns), &sn, &cs);
-      sh.ptw[off4(ns) + e] = make_float2(cs, sn);
-    }
-    if (R == 2) break;
-  }
-  __syncthreads();
-}
-
-// Bin k (0 <= k <= Nc) of the real spectrum of a frame of 2 Nc samples from
-// the half-size complex FFT Z (even samples real, odd imaginary; swizzled).
+// Bins k and Nc - k (k < Nc / 2) of the real spectrum of a frame whose
+// half-size complex FFT Z is in buf: X_k = E + W O, X_{Nc-k} = conj(E - W O)
+// with E = (Z_k + conj Z_{Nc-k}) / 2, O = -i (Z_k - conj Z_{Nc-k}) / 2,
+// W = exp(-2 pi i k / n).  k = Nc / 2 gives X_{Nc/2} in the first output.
 template <int Nc>
-__device__ __forceinline__ float2 real_bin(const float2* Z, const float2* tw, int k) {
-  const float2 w = k < Nc ? tw[k] : make_float2(-1.0f, 0.0f);
-  const int kc = k == Nc ? 0 : k, km = k == 0 ? 0 : Nc - k;   // Z_Nc = Z_0
-  const float2 zk = Z[swz(kc)], zc = cconj(Z[swz(km)]);
-  const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
-  const float2 D = csub(zk, zc);
-  const float2 O = make_float2(0.5f * D.y, -0.5f * D.x);       // -i D / 2
-  return cadd(E, cmul(w, O));
+__device__ __forceinline__ void real_pair(const float2* buf, const float2* rs, int k, float2& Xk,
+                                          float2& Xm) {
+  const float2 zk = buf[wfft::swz<Nc>(k)];
+  const float2 zc = buf[wfft::swz<Nc>((Nc - k) & (Nc - 1))];
+  const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
+  const float2 O = make_float2(0.5f * (zk.y + zc.y), -0.5f * (zk.x - zc.x));
+  const float2 WO = wfft::cmul(rs[k], O);
+  Xk = wfft::add(E, WO);
+  const float2 D = wfft::sub(E, WO);
+  Xm = make_float2(D.x, -D.y);
+}
+
+// One bin's loss share (added to acc) and gradient spectrum value.
+__device__ __forceinline__ float2 bin_grad(float2 X, float2 T, double scale_d, float scale,
+                                           bool edge, bool want_grad, double& acc) {
+  // hardware sqrt, log2 and reciprocal (about 1 ulp each)
+  const float ax = __builtin_amdgcn_sqrtf(X.x * X.x + X.y * X.y);
+  const float at = __builtin_amdgcn_sqrtf(T.x * T.x + T.y * T.y);
+  const float d = 0.69314718055994531f *
+                  (__builtin_amdgcn_logf(ax + kEps) - __builtin_amdgcn_logf(at + kEps));
+  acc += scale_d * (double)fabsf(d);
+  float2 G = make_float2(0.f, 0.f);
+  if (want_grad && ax > 0.0f && d != 0.0f) {
+    const float gm = copysignf(scale, d) * __builtin_amdgcn_rcpf((ax + kEps) * ax);
+    G = make_float2(gm * X.x, gm * X.y);
+  }
+  if (edge) G = make_float2(2.0f * G.x, 0.0f);
+  return G;
 }
 
 template <int RES>
-__device__ __forceinline__ void mrstft_frames(const MrArgs& a, SpecShared& sh, float* ola,
-                                              int64_t b, int blk) {
+__device__ __forceinline__ void mrstft_frames(const MrArgs& a, MrShared& sh, int64_t b, int blk) {
   constexpr int r = RES;
-  const int tid = threadIdx.x;
-  const int chunk = blk - a.chunk_base[r];
   constexpr int n = 512 << r;
   constexpr int Nc = n / 2;             // complex points per transform
-  constexpr int tpt = Nc / 4;           // threads per transform
-  constexpr int ntr = kThreads / tpt;   // transforms in flight: 8, 4, 2
-  constexpr int fpi = ntr / 2;          // frames per iteration: 4, 2, 1
+  constexpr int P = Nc / 64;            // points per lane
+  constexpr int QB = Nc / 128;          // bin pairs per lane (k = lane + 64 q < Nc / 2)
   constexpr int hop = n / 4;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int chunk = blk - a.chunk_base[r];
   const int F = a.F[r];
   const bool want_grad = a.wgrad != nullptr;
+  // The scale is applied in float32 to the gradient and in float64 to the loss.
+  const double scale_d = a.scale[r];
+  const float scale = (float)scale_d;
 
-  fft_tables<RES>(sh);
-
-  const int tr = tid / tpt;             // transform of this thread
-  const int j = tid - tr * tpt;         // butterfly index within the transform
-  const int slot = tr >> 1;             // frame slot of the iteration
-  const int sig = tr & 1;               // 0: render, 1: target
-  const float* src = (sig ? a.t : a.x) + b * a.n;
-  const double scale = a.scale[r];
-  double acc = 0.0;
+  // ---- tables of this resolution ----
+  for (int k = tid; k < n; k += kMrThreads) sh.win[k] = 0.5f - 0.5f * cospif(2.0f * (float)k / (float)n);
+  for (int k = tid; k <= Nc / 2; k += kMrThreads) {
+    float sn, cs;
+    sincospif(2.0f * (float)k / (float)n, &sn, &cs);
+    sh.rs[k] = make_float2(cs, -sn);
+  }
+  wfft::build_pass_twiddles<Nc>(sh.pt, tid, kMrThreads);
+  for (int i = tid; i < kOlaSlots; i += kMrThreads) sh.ola[i] = 0.0f;
+  __syncthreads();
 
   const int f_begin = chunk * kFramesPerBlock;
   const int f_end = min(F, f_begin + kFramesPerBlock);
-  // Overlap-add accumulator: block-relative position p lives at ola[p % 2048]
-  // (the unfinished positions never span more than (fpi - 1) hop + n <= 2048);
-  // a position is written out to the segment, and its slot cleared, as soon
-  // as no later frame of the block covers it.
   const int nch = a.chunk_base[r + 1] - a.chunk_base[r];
   float* seg = want_grad ? a.wgrad + a.wbase[r] + ((int64_t)b * nch + chunk) * (kSegHops * hop)
                          : nullptr;
-  if (want_grad)
-    for (int i = tid; i < kOlaSlots; i += kThreads) ola[i] = 0.0f;
-  for (int f0 = f_begin; f0 < f_end; f0 += fpi) {
-    const int f = f0 + slot;
-    const bool live = f < f_end;
-    // ---- forward transforms: z[m] = w x[2m] + i w x[2m+1] ----
-    float2 v[4];
-    const float* fr = src + (int64_t)f * hop;
+  float2* buf = sh.buf[wv];
+  const float* xs = a.x + b * a.n;
+  const float* ts = a.t + b * a.n;
+  double acc = 0.0;
+
+  for (int f0 = f_begin; f0 < f_end; f0 += kMrWaves) {
+    const int f = f0 + wv;
+    const bool live = f < f_end;        // wave-uniform
+    if (live) {
+      const float* fx = xs + (int64_t)f * hop;
+      const float* ft = ts + (int64_t)f * hop;
+      // ---- render frame: X bins kept in registers ----
+      float2 v[P];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int m = j + q * tpt;
-      v[q] = live ? make_float2(sh.win[2 * m] * fr[2 * m], sh.win[2 * m + 1] * fr[2 * m + 1])
-                  : make_float2(0.f, 0.f);
-    }
-    float2* b0 = sh.buf[0] + tr * Nc;
-    float2* b1 = sh.buf[1] + tr * Nc;
-    const int zb = fft_passes<Nc, 1, 0>(v, j, -1.0f, sh.ptw, b0, b1, true);
-    // ---- bins: frame slot's 2 * tpt threads take bins k = u, u + 2 tpt, ... ----
-    const float2* Zx = sh.buf[zb] + (2 * slot) * Nc;
-    const float2* Zt = sh.buf[zb] + (2 * slot + 1) * Nc;
-    float2* Hs = sh.buf[zb ^ 1] + slot * (Nc + 4);   // Hermitian half H_0 .. H_Nc (plain)
-    const int u = tid - slot * 2 * tpt;
-    for (int k = u; k <= Nc; k += 2 * tpt) {
-      const float2 X = real_bin<Nc>(Zx, sh.tw, k);
-      const float2 T = real_bin<Nc>(Zt, sh.tw, k);
-      // hardware sqrt, log2 and reciprocal (about 1 ulp each)
-      const float ax = __builtin_amdgcn_sqrtf(X.x * X.x + X.y * X.y);
-      const float at = __builtin_amdgcn_sqrtf(T.x * T.x + T.y * T.y);
-      const float d = 0.69314718055994531f *
-                      (__builtin_amdgcn_logf(ax + kEps) - __builtin_amdgcn_logf(at + kEps));
-      if (live) acc += scale * (double)fabsf(d);
-      if (want_grad) {
-        float2 G = make_float2(0.f, 0.f);
-        if (live && ax > 0.0f && d != 0.0f) {
-          const float gm = copysignf((float)scale, d) * __builtin_amdgcn_rcpf((ax + kEps) * ax);
-          G = make_float2(gm * X.x, gm * X.y);
+      for (int q = 0; q < P; ++q) {
+        const int m = lane + 64 * q;
+        const float2 w2 = *reinterpret_cast<const float2*>(&sh.win[2 * m]);
+        v[q] = make_float2(w2.x * fx[2 * m], w2.y * fx[2 * m + 1]);
+      }
+      wfft::wave_fft<Nc, true>(v, buf, sh.pt, lane);
+      float2 Xk[QB + 1], Xm[QB + 1];
+#pragma unroll
+      for (int q = 0; q <= QB; ++q) real_pair<Nc>(buf, sh.rs, q < QB ? lane + 64 * q : Nc / 2, Xk[q], Xm[q]);
+      // ---- target frame ----
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const int m = lane + 64 * q;
+        const float2 w2 = *reinterpret_cast<const float2*>(&sh.win[2 * m]);
+        v[q] = make_float2(w2.x * ft[2 * m], w2.y * ft[2 * m + 1]);
+      }
+      wfft::wave_fft<Nc, true>(v, buf, sh.pt, lane);
+      float2 Hk[QB + 1], Hm[QB + 1];
+#pragma unroll
+      for (int q = 0; q <= QB; ++q) {
+        const int k = q < QB ? lane + 64 * q : Nc / 2;
+        float2 Tk, Tm;
+        real_pair<Nc>(buf, sh.rs, k, Tk, Tm);
+        if (q < QB) {
+          Hk[q] = bin_grad(Xk[q], Tk, scale_d, scale, k == 0, want_grad, acc);
+          Hm[q] = bin_grad(Xm[q], Tm, scale_d, scale, k == 0, want_grad, acc);   // bin Nc - k
+        } else {
+          // bin Nc / 2, once per frame (lane 0)
+          double a2 = 0.0;
+          Hk[q] = bin_grad(Xk[q], Tk, scale_d, scale, false, want_grad, a2);
+          if (lane == 0) acc += a2;
+          Hm[q] = make_float2(0.f, 0.f);
         }
-        if (k == 0 || k == Nc) G = make_float2(2.0f * G.x, 0.0f);
-        Hs[k] = G;
+      }
+      if (want_grad) {
+        // ---- H to LDS (slot k holds H_k; slot 0 holds (H_0, H_Nc), both real) ----
+        wfft::wave_fence();
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+          const int k = lane + 64 * q;
+          if (k == 0) {
+            buf[wfft::swz<Nc>(0)] = make_float2(Hk[q].x, Hm[q].x);
+          } else {
+            buf[wfft::swz<Nc>(k)] = Hk[q];
+            buf[wfft::swz<Nc>(Nc - k)] = Hm[q];
+          }
+        }
+        if (lane == 0) buf[wfft::swz<Nc>(Nc / 2)] = Hk[QB];
+        wfft::wave_fence();
+        // ---- inverse input: Y_m = (H_m + conj H_{Nc-m}) + i conj(W^m) (H_m - conj H_{Nc-m}) ----
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          const int m = lane + 64 * q;
+          float2 hk, hc;
+          if (m == 0) {
+            const float2 h0 = buf[wfft::swz<Nc>(0)];
+            hk = make_float2(h0.x, 0.f);
+            hc = make_float2(h0.y, 0.f);
+          } else {
+            hk = buf[wfft::swz<Nc>(m)];
+            const float2 t2 = buf[wfft::swz<Nc>(Nc - m)];
+            hc = make_float2(t2.x, -t2.y);
+          }
+          const float2 A = wfft::add(hk, hc), D = wfft::sub(hk, hc);
+          // W^m = exp(-2 pi i m / n); for m > Nc / 2 from W^{Nc - m} = -conj(W^m)
+          const float2 wm = m <= Nc / 2 ? sh.rs[m] : make_float2(-sh.rs[Nc - m].x, sh.rs[Nc - m].y);
+          const float2 cd = wfft::cmulc(D, wm);        // conj(W^m) D
+          v[q] = make_float2(A.x - cd.y, A.y + cd.x);   // A + i (conj(W^m) D)
+        }
+        wfft::wave_fft<Nc, false>(v, buf, sh.pt, lane);
       }
     }
-    __syncthreads();
     if (want_grad) {
-      // ---- inverse: Y_k = (H_k + conj H_{Nc-k}) + i conj(tw_k) (H_k - conj H_{Nc-k}) ----
-      const bool inv_active = sig == 0;             // one inverse per frame
-      float2 y[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = j + q * tpt;
-        const float2 hk = Hs[k], hc = cconj(Hs[Nc - k]);
-        const float2 A = cadd(hk, hc), D = csub(hk, hc);
-        const float2 c = cconj(sh.tw[k]);
-        const float2 cd = cmul(c, D);
-        y[q] = make_float2(A.x - cd.y, A.y + cd.x);   // A + i (c D)
-      }
-      __syncthreads();                              // H read before buffers are reused
-      float2* c0 = sh.buf[0] + slot * 2 * Nc;  // the frame slot's two transform areas
-      float2* c1 = sh.buf[1] + slot * 2 * Nc;
-      const int yb = fft_passes<Nc, 1, 0>(y, j, 1.0f, sh.ptw, c0, c1, inv_active);
+      __syncthreads();                  // the four frames' rows are in the buffers
       // ---- overlap-add: frame f0 + s contributes 0.5 w(o) y(o) at o = p - s hop ----
       const int p0 = (f0 - f_begin) * hop;           // block-relative start of frame f0
-      for (int p = tid; p < (fpi - 1) * hop + n; p += kThreads) {
+      for (int p = tid; p < (kMrWaves - 1) * hop + n; p += kMrThreads) {
         float g = 0.0f;
 #pragma unroll
-        for (int s2 = 0; s2 < fpi; ++s2) {
+        for (int s2 = 0; s2 < kMrWaves; ++s2) {
           const int o = p - s2 * hop;
           if (o >= 0 && o < n && f0 + s2 < f_end) {
-            const float2 yy = (sh.buf[yb] + s2 * 2 * Nc)[swz(o >> 1)];
+            const float2 yy = sh.buf[s2][wfft::swz<Nc>(o >> 1)];
             g += 0.5f * sh.win[o] * ((o & 1) ? yy.y : yy.x);
           }
         }
-        float* slotp = ola + ((p0 + p) & (kOlaSlots - 1));
-        const float v = *slotp + g;
-        if (p < fpi * hop) {                         // no later frame reaches it
-          seg[p0 + p] = v;
+        float* slotp = sh.ola + ((p0 + p) & (kOlaSlots - 1));
+        const float v2 = *slotp + g;
+        if (p < kMrWaves * hop) {                    // no later frame reaches it
+          seg[p0 + p] = v2;
           *slotp = 0.0f;
         } else {
-          *slotp = v;
+          *slotp = v2;
         }
       }
-      __syncthreads();
+      __syncthreads();                  // buffers and accumulator reused next
     }
   }
   if (want_grad) {
     // the rest of the segment: the last frames' tails (3 hops past the
     // written part), then zeros
-    const int done = ((f_end - f_begin + fpi - 1) / fpi) * fpi * hop;
-    for (int p = done + tid; p < kSegHops * hop; p += kThreads)
-      seg[p] = p < done + 3 * hop ? ola[p & (kOlaSlots - 1)] : 0.0f;
+    const int done = ((f_end - f_begin + kMrWaves - 1) / kMrWaves) * kMrWaves * hop;
+    for (int p = done + tid; p < kSegHops * hop; p += kMrThreads)
+      seg[p] = p < done + 3 * hop ? sh.ola[p & (kOlaSlots - 1)] : 0.0f;
   }
-  // fixed-order reduction of the per-thread loss shares
+  // fixed-order reduction of the per-lane loss shares
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o);
-  if ((tid & 63) == 0) sh.red[tid >> 6] = acc;
+  if (lane == 0) sh.red[wv] = acc;
   __syncthreads();
   if (tid == 0) {
     double s = 0.0;
-    for (int w = 0; w < kThreads / 64; ++w) s += sh.red[w];
+    for (int w = 0; w < kMrWaves; ++w) s += sh.red[w];
     a.partial[b * a.chunk_base[3] + blk] = s;
   }
 }
 
-__global__ void __launch_bounds__(kThreads) mrstft_frames_kernel(const MrArgs a) {
-  __shared__ SpecShared sh;
-  __shared__ float ola[kOlaSlots];
+__global__ void __launch_bounds__(kMrThreads) __attribute__((amdgpu_waves_per_eu(2)))
+mrstft_frames_kernel(const MrArgs a) {
+  __shared__ MrShared sh;
   const int64_t b = blockIdx.y;
   const int blk = blockIdx.x;
   if (blk < a.chunk_base[1])
-    mrstft_frames<0>(a, sh, ola, b, blk);
+    mrstft_frames<0>(a, sh, b, blk);
   else if (blk < a.chunk_base[2])
-    mrstft_frames<1>(a, sh, ola, b, blk);
+    mrstft_frames<1>(a, sh, b, blk);
   else
-    mrstft_frames<2>(a, sh, ola, b, blk);
+    mrstft_frames<2>(a, sh, b, blk);
 }
 
 // Log-mel features by FFT, one workgroup of 4 wavefronts per voice: frames
@@ -653,7 +576,7 @@ hipError_t launch_mrstft(const float* x, const float* target, int64_t batch, int
   if (batch > 65535) return hipErrorInvalidValue;
   if (a.chunk_base[3] > 0) {
     hipLaunchKernelGGL(mrstft_frames_kernel, dim3((unsigned)a.chunk_base[3], (unsigned)batch),
-                       dim3(kThreads), 0, s, a);
+                       dim3(kMrThreads), 0, s, a);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -78,12 +78,12 @@ constexpr int pt_size() { return pt_offset<NC>(Plan<NC>::passes); }
 template <int NC, int p = 1>
 __device__ __forceinline__ void build_pass_twiddles(float2* PT, int t, int nthreads) {
   if constexpr (p < Plan<NC>::passes) {
-    constexpr int NS = stride_of<NC>(p), R = Plan<NC>::radix(p);
+    constexpr int NS = stride_of<NC>(p), R = Plan<NC>::radix(p), OFF = pt_offset<NC>(p);
     for (int i = t; i < (R - 1) * NS; i += nthreads) {
       const int r = i / NS + 1, k = i % NS;
       float sn, cs;
       sincospif(-2.0f * (float)(k * r) / (float)(NS * R), &sn, &cs);
-      PT[pt_offset<NC>(p) + i] = make_float2(cs, sn);
+      PT[OFF + i] = make_float2(cs, sn);
     }
     build_pass_twiddles<NC, p + 1>(PT, t, nthreads);
   }
@@ -178,6 +178,7 @@ __device__ __forceinline__ void run_passes(float2 (&v)[NC / 64], float2* buf, co
                                            int lane) {
   if constexpr (p < Plan<NC>::passes) {
     constexpr int P = NC / 64, R = Plan<NC>::radix(p), NS = stride_of<NC>(p), NB = P / R;
+    constexpr int OFF = pt_offset<NC>(p);
     wave_fence();                       // earlier reads of buf stay before these writes
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -189,7 +190,7 @@ __device__ __forceinline__ void run_passes(float2 (&v)[NC / 64], float2* buf, co
       if constexpr (NS > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          const float2 w = T[pt_offset<NC>(p) + (r - 1) * NS + k];
+          const float2 w = T[OFF + (r - 1) * NS + k];
           x[r] = FWD ? cmul(x[r], w) : cmulc(x[r], w);
         }
       }
