@@ -154,10 +154,11 @@ int synth_render_backward(const synth_config* cfg, const float* params, const ui
  *   loss       dev float64 [batch], written.
  *   grad_x     dev float32 [batch][n_samples] or NULL; if given it receives
  *              d loss[b] / d x[b][.] (float32 FFT arithmetic).
- *   workspace  dev buffer of >= synth_mrstft_workspace(batch, n_samples,
- *              grad_x != NULL) bytes, caller-owned, contents clobbered (with
- *              a gradient: 4 bytes per frame sample of every resolution,
- *              about 48 bytes per input sample).
+ *   workspace  dev buffer, 16-byte aligned (SYNTH_EINVAL otherwise), of >=
+ *              synth_mrstft_workspace(batch, n_samples, grad_x != NULL)
+ *              bytes, caller-owned, contents clobbered (with a gradient: each
+ *              workgroup's overlap-added segment of 19 hops per 16 frames,
+ *              about 14 bytes per input sample).
  *   0 < n_samples <= 2^31, batch <= 65535 (SYNTH_EUNSUPPORTED above).
  *   Bitwise deterministic. */
 size_t synth_mrstft_workspace(int64_t batch, int64_t n_samples, int with_grad);

@@ -326,6 +326,7 @@ int synth_mrstft_loss(const float* x, const float* target, int64_t batch, int64_
   if (batch < 0 || n_samples <= 0 || n_samples > ((int64_t)1 << 31)) return SYNTH_EINVAL;
   if (batch == 0) return SYNTH_OK;
   if (!x || !target || !loss || !workspace) return SYNTH_EINVAL;
+  if (reinterpret_cast<uintptr_t>(workspace) & 15) return SYNTH_EINVAL;
   if (batch > 65535) return SYNTH_EUNSUPPORTED;
   if (workspace_bytes < synth::mrstft_workspace_bytes(batch, n_samples, grad_x != nullptr))
     return SYNTH_ENOMEM;

@@ -501,23 +501,39 @@ __global__ void __launch_bounds__(256) mrstft_combine_kernel(const MrArgs a) {
     a.loss[b] = s;
   }
   if (!a.grad) return;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  float g = 0.0f;
+  // four consecutive samples per thread: hops are multiples of 4, so they
+  // share their segments, and segment rows are 16-byte aligned
+  const int64_t i0 = 4 * (blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+  if (i0 >= a.n) return;
+  float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
   for (int r = 0; r < 3; ++r) {
     const int n = 512 << r, hop = n / 4;
     const int nch = a.chunk_base[r + 1] - a.chunk_base[r];
     if (nch == 0) continue;
-    const int64_t h = i / hop;                       // hop of sample i
+    const int64_t h = i0 / hop;                      // hop of samples i0 .. i0 + 3
     int64_t khi = h / kFramesPerBlock;
     if (khi > nch - 1) khi = nch - 1;
     const int64_t klo = h >= kSegHops ? (h - kSegHops) / kFramesPerBlock + 1 : 0;
     const int64_t seglen = (int64_t)kSegHops * hop;
     const float* segs = a.wgrad + a.wbase[r] + b * nch * seglen;
-    for (int64_t k = klo; k <= khi; ++k)
-      g += segs[k * seglen + (i - k * kFramesPerBlock * hop)];
+    for (int64_t k = klo; k <= khi; ++k) {
+      const float4 v = *reinterpret_cast<const float4*>(segs + k * seglen +
+                                                        (i0 - k * kFramesPerBlock * hop));
+      g.x += v.x;
+      g.y += v.y;
+      g.z += v.z;
+      g.w += v.w;
+    }
   }
-  a.grad[b * a.n + i] = g;
+  float* out = a.grad + b * a.n + i0;
+  if (i0 + 4 <= a.n && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+    *reinterpret_cast<float4*>(out) = g;
+  } else {
+    const float gv[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (i0 + e < a.n) out[e] = gv[e];
+  }
 }
 
 void plan(int64_t batch, int64_t n_samples, MrArgs& a, size_t& partial_bytes, size_t& wgrad_floats) {
@@ -582,7 +598,7 @@ hipError_t launch_mrstft(const float* x, const float* target, int64_t batch, int
   }
   // (with no complete frame at any resolution the combine kernel writes
   // loss 0 and a zero gradient)
-  const int64_t gx = grad ? (n_samples + 255) / 256 : 1;
+  const int64_t gx = grad ? (n_samples + 1023) / 1024 : 1;
   hipLaunchKernelGGL(mrstft_combine_kernel, dim3((unsigned)gx, (unsigned)batch), dim3(256), 0, s, a);
   return hipGetLastError();
 }

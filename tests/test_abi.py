@@ -111,6 +111,25 @@ def test_sample_params_argument_checks():
     assert L.synth_sample_params(0, 0, 5, None, None, None) == EINVAL
 
 
+def test_mrstft_argument_checks_before_launch():
+    """Rejected before any device work: bad sizes, missing buffers, a
+    workspace that is not 16-byte aligned, more voices than the grid holds."""
+    L = _native.lib()
+    fake = ctypes.c_void_p(0x10000)            # never dereferenced on these paths
+    odd = ctypes.c_void_p(0x10004)
+
+    def call(B=2, n=4096, x=fake, t=fake, loss=fake, ws=fake, nbytes=1 << 40):
+        return L.synth_mrstft_loss(x, t, B, n, loss, None, ws, nbytes, None)
+    assert call(B=-1) == EINVAL
+    assert call(n=0) == EINVAL
+    assert call(x=None) == EINVAL
+    assert call(ws=None) == EINVAL
+    assert call(ws=odd) == EINVAL
+    assert call(B=65536) == EUNSUP
+    assert call(B=0) == 0
+    assert call(nbytes=16) == -2                   # SYNTH_ENOMEM
+
+
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_native, "LIB_PATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(_native, "_lib", None)
