@@ -36,7 +36,6 @@ constexpr int kFramesPerBlock = 16;
 // A workgroup's frames f0 .. f0 + 15 cover hops f0 .. f0 + 18 of the voice:
 // their gradient rows are overlap-added in LDS into one segment of 19 hops.
 constexpr int kSegHops = kFramesPerBlock + 3;
-constexpr int kOlaSlots = 4096;   // >= the 7 hops of four frames at n = 2048
 constexpr float kEps = 1e-5f;
 
 struct MrArgs {
@@ -54,12 +53,15 @@ struct MrArgs {
   double* loss;
 };
 
+// LDS of one resolution (Nc = n / 2 complex points per transform).
+template <int Nc>
 struct MrShared {
-  float2 buf[kMrWaves][1024];  // one FFT buffer per wavefront (n/2 complex points)
-  alignas(8) float win[2048];  // periodic Hann window of the workgroup's resolution
-  float2 rs[513];              // exp(-2 pi i k / n), k <= n / 4 (real split)
-  float2 pt[wfft::pt_size<1024>()];   // FFT pass twiddles
-  float ola[kOlaSlots];        // overlap-add accumulator
+  static constexpr int ola_slots = 4 * Nc;   // >= the 7 hops of four frames
+  float2 buf[kMrWaves][Nc];    // one FFT buffer per wavefront
+  alignas(8) float win[2 * Nc];  // periodic Hann window
+  float2 rs[Nc / 2 + 1];       // exp(-2 pi i k / n), k <= n / 4 (real split)
+  float2 pt[wfft::pt_size<Nc>()];   // FFT pass twiddles
+  float ola[ola_slots];        // overlap-add accumulator
   double red[kMrWaves];
 };
 
@@ -99,10 +101,12 @@ __device__ __forceinline__ float2 bin_grad(float2 X, float2 T, double scale_d, f
 }
 
 template <int RES>
-__device__ __forceinline__ void mrstft_frames(const MrArgs& a, MrShared& sh, int64_t b, int blk) {
+__device__ __forceinline__ void mrstft_frames(const MrArgs& a, MrShared<256 << RES>& sh, int64_t b,
+                                              int blk) {
   constexpr int r = RES;
   constexpr int n = 512 << r;
   constexpr int Nc = n / 2;             // complex points per transform
+  constexpr int kOlaSlots = MrShared<Nc>::ola_slots;
   constexpr int P = Nc / 64;            // points per lane
   constexpr int QB = Nc / 128;          // bin pairs per lane (k = lane + 64 q < Nc / 2)
   constexpr int hop = n / 4;
@@ -261,17 +265,12 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, MrShared& sh, int
   }
 }
 
-__global__ void __launch_bounds__(kMrThreads) __attribute__((amdgpu_waves_per_eu(2)))
-mrstft_frames_kernel(const MrArgs a) {
-  __shared__ MrShared sh;
-  const int64_t b = blockIdx.y;
-  const int blk = blockIdx.x;
-  if (blk < a.chunk_base[1])
-    mrstft_frames<0>(a, sh, b, blk);
-  else if (blk < a.chunk_base[2])
-    mrstft_frames<1>(a, sh, b, blk);
-  else
-    mrstft_frames<2>(a, sh, b, blk);
+// One launch per resolution, so that each gets the LDS and registers of its
+// own transform size (and the occupancy they allow).
+template <int RES>
+__global__ void __launch_bounds__(kMrThreads) mrstft_frames_kernel(const MrArgs a) {
+  __shared__ MrShared<256 << RES> sh;
+  mrstft_frames<RES>(a, sh, blockIdx.y, a.chunk_base[RES] + (int)blockIdx.x);
 }
 
 // Log-mel features by FFT, one workgroup of 4 wavefronts per voice: frames
@@ -590,9 +589,18 @@ hipError_t launch_mrstft(const float* x, const float* target, int64_t batch, int
   a.grad = grad;
   a.loss = loss;
   if (batch > 65535) return hipErrorInvalidValue;
-  if (a.chunk_base[3] > 0) {
-    hipLaunchKernelGGL(mrstft_frames_kernel, dim3((unsigned)a.chunk_base[3], (unsigned)batch),
+  const int nch[3] = {a.chunk_base[1] - a.chunk_base[0], a.chunk_base[2] - a.chunk_base[1],
+                      a.chunk_base[3] - a.chunk_base[2]};
+  if (nch[0] > 0)
+    hipLaunchKernelGGL(mrstft_frames_kernel<0>, dim3((unsigned)nch[0], (unsigned)batch),
                        dim3(kMrThreads), 0, s, a);
+  if (nch[1] > 0)
+    hipLaunchKernelGGL(mrstft_frames_kernel<1>, dim3((unsigned)nch[1], (unsigned)batch),
+                       dim3(kMrThreads), 0, s, a);
+  if (nch[2] > 0)
+    hipLaunchKernelGGL(mrstft_frames_kernel<2>, dim3((unsigned)nch[2], (unsigned)batch),
+                       dim3(kMrThreads), 0, s, a);
+  if (a.chunk_base[3] > 0) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
