@@ -83,6 +83,25 @@ def test_logmel_matches_bf16_reference(L, method):
     assert float(d.max()) < 5e-3
 
 
+@pytest.mark.parametrize("sr", [16000.0, 22050.0, 48000.0])
+def test_logmel_fft_other_sample_rates(L, sr):
+    """Other rates move every band edge, so the bands' bin runs, chunk counts
+    and chunk layout differ from 44.1 kHz (narrow low bands of one bin or
+    none, wide high bands); white noise of 4 s at that rate, FFT path
+    against the reference that rounds P and the mel basis to bf16."""
+    g = torch.Generator().manual_seed(int(sr))
+    n4 = int(4 * sr)
+    x = torch.zeros(3, max(n4, 176400))              # the 64 frames span 175676 samples
+    x[:, :n4] = torch.randn(3, n4, generator=g) * 0.3
+    feat = L.LogMel(sample_rate=sr)(x.cuda())
+    torch.cuda.synchronize()
+    ref = sp.logmel_p16(x.double(), sr=sr).reshape(3, -1)
+    d = (feat.cpu().double() - ref).abs()
+    print(sr, "logmel max abs", float(d.max()), "median", float(d.median()), file=sys.stderr)
+    assert float(d.median()) < 1e-4
+    assert float(d.max()) < 5e-3
+
+
 @pytest.mark.parametrize("split_k", [True, False])
 def test_mlp_forward_backward_full_size(L, split_k):
     """8192 -> 1024 -> 1024 -> 78 at batch 512 against the float64 reference;
