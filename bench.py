@@ -332,6 +332,7 @@ def main():
         if plan is not None:
             S.synth_render_plan(params, table, plan[0], plan[1], persistent=bool(plan[2]),
                                 grid_blocks=plan[3], offsets=offsets,
+                                carries=len(plan) > 4 and bool(plan[4]), max_samples=4 * 44100,
                                 noise_seed=wl.key_noise(), out=audio)
         else:
             S.synth_render(params, table, offsets=offsets, noise_seed=wl.key_noise(), out=audio)

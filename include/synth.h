@@ -106,6 +106,17 @@ int synth_render(const synth_config* cfg, const float* params, const uint64_t* v
                  uint64_t first_g, int64_t batch, const int64_t* offsets, int64_t n_samples,
                  float* audio, void* stream);
 
+/* synth_render with a workspace: small uniform batches then split each voice
+ * over more workgroups, with the chunk-start phase carries computed first
+ * (see synth_render_plan_ws); the audio is bit-identical to synth_render's.
+ * synth_render_workspace returns the bytes it needs (0: the default plan does
+ * not split this batch, and synth_render_ws is synth_render).  workspace ==
+ * NULL or offsets != NULL: exactly synth_render. */
+size_t synth_render_workspace(const synth_config* cfg, int64_t batch, int64_t n_samples);
+int synth_render_ws(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
+                    uint64_t first_g, int64_t batch, const int64_t* offsets, int64_t n_samples,
+                    float* audio, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Same as synth_render with an explicit launch plan (used by the autotuner and
  * by tests): runs_per_segment in {1, 2, 4} splits each control period into
  * that many per-lane runs; slices_per_voice >= 1 splits each voice over that
@@ -119,6 +130,27 @@ int synth_render_plan(const synth_config* cfg, const float* params, const uint64
                       uint64_t first_g, int64_t batch, const int64_t* offsets, int64_t n_samples,
                       float* audio, int runs_per_segment, int slices_per_voice,
                       int persistent, int grid_blocks, void* stream);
+
+/* synth_render_plan with a workspace for split voices.  With
+ * slices_per_voice > 1 a workgroup that starts inside a voice needs the
+ * phase carries (LFOs, VCOs) at its first chunk; synth_render_plan walks the
+ * earlier chunks' control stages for them, this entry computes every chunk's
+ * carries first, in parallel over chunks (the chunks' own sums, then the
+ * per-voice carry updates in chunk order: the same float64 operations, so the
+ * audio is bit-identical to synth_render_plan's).
+ *   max_samples  longest voice with offsets (ignored without): sizes the
+ *                carries; a longer voice still renders correctly (its later
+ *                chunks walk as in synth_render_plan).
+ *   workspace    dev, >= synth_render_plan_workspace(cfg, batch, max_samples)
+ *                bytes (SYNTH_ENOMEM otherwise), contents clobbered; NULL or
+ *                slices_per_voice == 1: exactly synth_render_plan.
+ *   batch <= 65535 with a workspace and slices > 1 (SYNTH_EUNSUPPORTED). */
+size_t synth_render_plan_workspace(const synth_config* cfg, int64_t batch, int64_t max_samples);
+int synth_render_plan_ws(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
+                         uint64_t first_g, int64_t batch, const int64_t* offsets,
+                         int64_t n_samples, int64_t max_samples, float* audio,
+                         int runs_per_segment, int slices_per_voice, int persistent,
+                         int grid_blocks, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Workspace (bytes of device memory) that synth_render_backward needs for a
  * batch of uniform-length voices: batch * ceil(n_samples / q) * 21 doubles.

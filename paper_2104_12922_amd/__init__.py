@@ -101,11 +101,21 @@ def synth_render(params: torch.Tensor, nebula, n_samples: int | None = None,
                  sample_rate: float = 44100.0, control_rate: float = 441.0,
                  out: torch.Tensor | None = None) -> torch.Tensor:
     """Render B voices.  Uniform: returns [B, n_samples]; ragged (offsets given):
-    returns the packed 1-D buffer of offsets[-1] samples."""
+    returns the packed 1-D buffer of offsets[-1] samples.  Small uniform
+    batches get a workspace for the chunk-start carries (`synth_render_ws`)."""
     args, out, keep = _render_common(params, nebula, n_samples, offsets, voice_ids, first_g,
                                      noise_seed, mix_mode, sample_rate, control_rate, out)
-    st = _native.lib().synth_render(ctypes_ref(args[0]), *args[1:], _stream(params.device))
-    _native.check("synth_render", st)
+    L = _native.lib()
+    need = 0 if offsets is not None else L.synth_render_workspace(
+        ctypes_ref(args[0]), params.shape[0], int(n_samples))
+    if need:
+        ws = torch.empty(need, dtype=torch.uint8, device=params.device)
+        st = L.synth_render_ws(ctypes_ref(args[0]), *args[1:], ws.data_ptr(), ws.numel(),
+                               _stream(params.device))
+        _native.check("synth_render_ws", st)
+    else:
+        st = L.synth_render(ctypes_ref(args[0]), *args[1:], _stream(params.device))
+        _native.check("synth_render", st)
     del keep
     if offsets is None:
         return out.view(params.shape[0], int(n_samples))
@@ -117,13 +127,35 @@ def synth_render_plan(params: torch.Tensor, nebula, runs_per_segment: int, slice
                       offsets: torch.Tensor | None = None, voice_ids: torch.Tensor | None = None,
                       first_g: int = 0, noise_seed: int = 0, mix_mode: int = 0,
                       sample_rate: float = 44100.0, control_rate: float = 441.0,
-                      out: torch.Tensor | None = None) -> torch.Tensor:
+                      out: torch.Tensor | None = None, carries: bool = True,
+                      max_samples: int | None = None,
+                      workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Render with an explicit launch plan.  With slices_per_voice > 1 and
+    `carries`, the chunk-start phase carries are computed first in a
+    workspace (`synth_render_plan_ws`); `max_samples` (longest voice, ragged
+    batches) avoids reading the offsets back; `workspace` may be given to
+    reuse a buffer."""
     args, out, keep = _render_common(params, nebula, n_samples, offsets, voice_ids, first_g,
                                      noise_seed, mix_mode, sample_rate, control_rate, out)
-    st = _native.lib().synth_render_plan(ctypes_ref(args[0]), *args[1:], int(runs_per_segment),
-                                         int(slices_per_voice), int(bool(persistent)),
-                                         int(grid_blocks), _stream(params.device))
-    _native.check("synth_render_plan", st)
+    L = _native.lib()
+    plan = (int(runs_per_segment), int(slices_per_voice), int(bool(persistent)), int(grid_blocks))
+    B = params.shape[0]
+    if carries and slices_per_voice > 1 and B > 0:
+        if offsets is None:
+            lmax = int(n_samples)
+        elif max_samples is not None:
+            lmax = int(max_samples)
+        else:
+            lmax = int(torch.diff(offsets).max().item())
+        need = L.synth_render_plan_workspace(ctypes_ref(args[0]), B, max(lmax, 1))
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=params.device)
+        st = L.synth_render_plan_ws(ctypes_ref(args[0]), *args[1:7], lmax, args[7], *plan,
+                                    workspace.data_ptr(), workspace.numel(), _stream(params.device))
+        _native.check("synth_render_plan_ws", st)
+    else:
+        st = L.synth_render_plan(ctypes_ref(args[0]), *args[1:], *plan, _stream(params.device))
+        _native.check("synth_render_plan", st)
     del keep
     if offsets is None:
         return out.view(params.shape[0], int(n_samples))

@@ -57,8 +57,21 @@ def lib() -> ctypes.CDLL:
                        ctypes.c_void_p]
         L.synth_render.restype = ctypes.c_int
         L.synth_render.argtypes = render_args + [ctypes.c_void_p]
+        L.synth_render_workspace.restype = ctypes.c_size_t
+        L.synth_render_workspace.argtypes = [ctypes.POINTER(SynthConfig), ctypes.c_int64,
+                                             ctypes.c_int64]
+        L.synth_render_ws.restype = ctypes.c_int
+        L.synth_render_ws.argtypes = render_args + [ctypes.c_void_p, ctypes.c_size_t,
+                                                    ctypes.c_void_p]
         L.synth_render_plan.restype = ctypes.c_int
         L.synth_render_plan.argtypes = render_args + [ctypes.c_int] * 4 + [ctypes.c_void_p]
+        L.synth_render_plan_workspace.restype = ctypes.c_size_t
+        L.synth_render_plan_workspace.argtypes = [ctypes.POINTER(SynthConfig), ctypes.c_int64,
+                                                  ctypes.c_int64]
+        L.synth_render_plan_ws.restype = ctypes.c_int
+        L.synth_render_plan_ws.argtypes = (render_args[:7] + [ctypes.c_int64] + render_args[7:] +
+                                           [ctypes.c_int] * 4 +
+                                           [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p])
         L.synth_mrstft_loss.restype = ctypes.c_int
         L.synth_mrstft_loss.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                         ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,

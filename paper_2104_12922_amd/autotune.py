@@ -1,7 +1,9 @@
 """Launch-plan autotuner for the batched render.
 
-A plan is (runs_per_segment, slices_per_voice, persistent, grid_blocks) of
-`synth_render_plan`.  Plans with the same runs per segment render identical
+A plan is (runs_per_segment, slices_per_voice, persistent, grid_blocks,
+carries) of `synth_render_plan` (carries: split voices start from
+precomputed chunk carries instead of walking the earlier chunks; a 4-tuple
+means carries off).  Plans with the same runs per segment render identical
 bits; changing the runs per segment regroups the float64 phase sums, which
 moves samples by float32 rounding only (every plan is held to the same parity
 tolerance against the oracle), so the choice is one of speed.  The tuner times each candidate plan on the caller's
@@ -21,12 +23,14 @@ import torch
 from . import synth_render_plan
 
 
-def default_candidates(batch: int, uniform: bool):
+def default_candidates(batch: int, uniform: bool, nchunks: int | None = None):
     """Plans worth timing (the library's default plan first): 4 or 2 runs per
     control period; one workgroup per voice, or a persistent grid of 4-16
     workgroups per CU (256 CUs); batches of up to 16384 voices also try
-    splitting each voice over 2-8 workgroups (slices), which evens out the
-    load when lengths differ."""
+    splitting each voice over several workgroups (slices: 2-32 for small
+    uniform batches, at most the voice's chunk count; 2-4 otherwise), which
+    evens out the load when lengths differ.  Split plans render with the
+    chunk-start carries computed first."""
     c = []
     for rps in (4, 2):
         c.append((rps, 1, 0, 0))
@@ -34,12 +38,18 @@ def default_candidates(batch: int, uniform: bool):
             if g < batch:
                 c.append((rps, 1, 1, g))
         if batch < 256 and uniform:
-            for sl in (2, 4, 8):
-                c.append((rps, sl, 0, 0))
+            for sl in (2, 4, 8, 16, 32):
+                if nchunks is None or sl <= nchunks:
+                    c.append((rps, sl, 0, 0, 1))
         elif batch <= 16384:
             for sl in (2, 3, 4):
-                c.append((rps, sl, 0, 0))
+                c.append((rps, sl, 0, 0, 0))
+                c.append((rps, sl, 0, 0, 1))
     return c
+
+
+def _plan5(plan):
+    return tuple(plan) + (0,) * (5 - len(plan))
 
 
 class RenderTuner:
@@ -64,16 +74,21 @@ class RenderTuner:
     def tune(self, params, nebula, n_samples=None, offsets=None, out=None, key=None, **kw):
         B = params.shape[0]
         k = key if key is not None else self.key(B, n_samples, offsets)
-        cands = self.candidates or default_candidates(B, offsets is None)
+        nch = None
+        if offsets is None and n_samples:
+            q = int(round(kw.get("sample_rate", 44100.0) / kw.get("control_rate", 441.0)))
+            periods = -(-int(n_samples) // q)
+            nch = -(-periods // 62)                      # chunks of 62 control periods
+        cands = self.candidates or default_candidates(B, offsets is None, nch)
         stream = torch.cuda.current_stream()
         times = {}
         for plan in cands:
-            rps, sl, pers, grid = plan
+            rps, sl, pers, grid, car = _plan5(plan)
 
             def run():
                 return synth_render_plan(params, nebula, rps, sl, persistent=bool(pers),
                                          grid_blocks=grid, n_samples=n_samples, offsets=offsets,
-                                         out=out, **kw)
+                                         out=out, carries=bool(car), **kw)
             out = run()                          # warm-up (and the output buffer)
             ts = []
             for _ in range(self.reps):
@@ -101,10 +116,11 @@ class RenderTuner:
         return self.table[k]
 
     def render(self, params, nebula, n_samples=None, offsets=None, out=None, key=None, **kw):
-        rps, sl, pers, grid = self.plan_for(params, nebula, n_samples=n_samples, offsets=offsets,
-                                            key=key, **kw)
+        rps, sl, pers, grid, car = _plan5(self.plan_for(params, nebula, n_samples=n_samples,
+                                                         offsets=offsets, key=key, **kw))
         return synth_render_plan(params, nebula, rps, sl, persistent=bool(pers), grid_blocks=grid,
-                                 n_samples=n_samples, offsets=offsets, out=out, **kw)
+                                 n_samples=n_samples, offsets=offsets, out=out,
+                                 carries=bool(car), **kw)
 
     def save(self, path: str):
         with open(path, "w") as f:

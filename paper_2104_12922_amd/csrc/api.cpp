@@ -201,10 +201,17 @@ int synth_sample_params(uint64_t seed, uint64_t first_g, int64_t batch, const ui
                                                (hipStream_t)stream));
 }
 
-int synth_render_plan(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
-                      uint64_t first_g, int64_t batch, const int64_t* offsets, int64_t n_samples,
-                      float* audio, int runs_per_segment, int slices_per_voice, int persistent,
-                      int grid_blocks, void* stream) {
+namespace {
+int64_t chunks_of(int64_t n_samples, int q) {
+  const int64_t J = (n_samples + q - 1) / q;
+  return (J + kSegsPerChunk - 1) / kSegsPerChunk;
+}
+
+int render_plan_impl(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
+                     uint64_t first_g, int64_t batch, const int64_t* offsets, int64_t n_samples,
+                     int64_t max_samples, float* audio, int runs_per_segment,
+                     int slices_per_voice, int persistent, int grid_blocks, void* workspace,
+                     size_t workspace_bytes, void* stream) {
   if (batch < 0) return SYNTH_EINVAL;
   RenderArgs a;
   bool clamp = false;
@@ -240,7 +247,20 @@ int synth_render_plan(const synth_config* cfg, const float* params, const uint64
     if ((int64_t)grid > items) grid = (int)items;
     a.persistent_grid = grid;
   }
-  hipError_t e = synth::launch_render(a, runs_per_segment, clamp, grid, (hipStream_t)stream);
+  hipError_t e;
+  if (workspace && slices_per_voice > 1) {
+    const int64_t lmax = offsets ? max_samples : n_samples;
+    if (lmax <= 0) return SYNTH_EINVAL;
+    const int64_t stride = chunks_of(lmax, a.q);
+    if (workspace_bytes < (size_t)(batch * stride) * 4 * sizeof(double)) return SYNTH_ENOMEM;
+    if (batch > 65535 || stride > 0x7FFFFFFF) return SYNTH_EUNSUPPORTED;
+    e = synth::launch_voice_carries(a, runs_per_segment, clamp, (double*)workspace, stride,
+                                    (hipStream_t)stream);
+    if (e != hipSuccess) return SYNTH_EDEVICE;
+    a.carries = (const double*)workspace;
+    a.carry_stride = stride;
+  }
+  e = synth::launch_render(a, runs_per_segment, clamp, grid, (hipStream_t)stream);
   if (e != hipSuccess) return SYNTH_EDEVICE;
   if (a.mix_mode == 1) {
     a.slices = 1;
@@ -248,29 +268,83 @@ int synth_render_plan(const synth_config* cfg, const float* params, const uint64
   }
   return to_status(e);
 }
+}  // namespace
+
+int synth_render_plan(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
+                      uint64_t first_g, int64_t batch, const int64_t* offsets, int64_t n_samples,
+                      float* audio, int runs_per_segment, int slices_per_voice, int persistent,
+                      int grid_blocks, void* stream) {
+  return render_plan_impl(cfg, params, voice_ids, first_g, batch, offsets, n_samples, 0, audio,
+                          runs_per_segment, slices_per_voice, persistent, grid_blocks, nullptr, 0,
+                          stream);
+}
+
+size_t synth_render_plan_workspace(const synth_config* cfg, int64_t batch, int64_t max_samples) {
+  RenderArgs a;
+  bool clamp = false;
+  if (batch <= 0 || max_samples <= 0 || prepare(cfg, &a, &clamp) != SYNTH_OK) return 0;
+  return (size_t)(batch * chunks_of(max_samples, a.q)) * 4 * sizeof(double);
+}
+
+int synth_render_plan_ws(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
+                         uint64_t first_g, int64_t batch, const int64_t* offsets,
+                         int64_t n_samples, int64_t max_samples, float* audio,
+                         int runs_per_segment, int slices_per_voice, int persistent,
+                         int grid_blocks, void* workspace, size_t workspace_bytes, void* stream) {
+  return render_plan_impl(cfg, params, voice_ids, first_g, batch, offsets, n_samples, max_samples,
+                          audio, runs_per_segment, slices_per_voice, persistent, grid_blocks,
+                          workspace, workspace_bytes, stream);
+}
+
+namespace {
+// The library's default plan: runs per segment 4 (1 if q is not a multiple
+// of 4); small uniform batches split each voice over workgroups so that the
+// grid covers the chip - at most a quarter of its chunks when the slices
+// walk the earlier chunks for their carries, up to all of them when the
+// carries are computed first.
+void default_plan(const synth_config* cfg, int64_t batch, const int64_t* offsets,
+                  int64_t n_samples, bool carried, int* rps, int* slices) {
+  *slices = 1;
+  *rps = 4;
+  if (!cfg || !(cfg->control_rate > 0.0)) return;
+  const double q = nearbyint(cfg->sample_rate / cfg->control_rate);
+  if (fmod(q, 4.0) != 0.0) *rps = 1;
+  if (!offsets && n_samples > 0 && batch > 0 && q >= 4.0) {
+    const int64_t nchunks = chunks_of(n_samples, (int)q);
+    int64_t want = (2048 + batch - 1) / batch;
+    const int64_t cap = carried ? nchunks : nchunks / 4;
+    if (want > cap) want = cap;
+    if (want > 1) *slices = (int)want;
+  }
+}
+}  // namespace
 
 int synth_render(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
                  uint64_t first_g, int64_t batch, const int64_t* offsets, int64_t n_samples,
                  float* audio, void* stream) {
-  int slices = 1;
-  if (!offsets && cfg && n_samples > 0 && batch > 0 && cfg->control_rate > 0.0) {
-    // Small uniform batches: split voices so that the grid covers the chip.
-    const double q = nearbyint(cfg->sample_rate / cfg->control_rate);
-    if (q >= 4.0) {
-      const int64_t J = (n_samples + (int64_t)q - 1) / (int64_t)q;
-      const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
-      int64_t want = (2048 + batch - 1) / batch;
-      if (want > nchunks / 4) want = nchunks / 4;
-      if (want > 1) slices = (int)want;
-    }
-  }
-  int rps = 4;
-  if (cfg && cfg->control_rate > 0.0) {
-    const double q = nearbyint(cfg->sample_rate / cfg->control_rate);
-    if (fmod(q, 4.0) != 0.0) rps = 1;
-  }
+  int rps, slices;
+  default_plan(cfg, batch, offsets, n_samples, false, &rps, &slices);
   return synth_render_plan(cfg, params, voice_ids, first_g, batch, offsets, n_samples, audio, rps,
                            slices, 0, 0, stream);
+}
+
+size_t synth_render_workspace(const synth_config* cfg, int64_t batch, int64_t n_samples) {
+  int rps, slices;
+  default_plan(cfg, batch, nullptr, n_samples, true, &rps, &slices);
+  if (slices <= 1 || batch > 65535) return 0;
+  return synth_render_plan_workspace(cfg, batch, n_samples);
+}
+
+int synth_render_ws(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
+                    uint64_t first_g, int64_t batch, const int64_t* offsets, int64_t n_samples,
+                    float* audio, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!workspace || offsets) {
+    return synth_render(cfg, params, voice_ids, first_g, batch, offsets, n_samples, audio, stream);
+  }
+  int rps, slices;
+  default_plan(cfg, batch, offsets, n_samples, true, &rps, &slices);
+  return render_plan_impl(cfg, params, voice_ids, first_g, batch, offsets, n_samples, n_samples,
+                          audio, rps, slices, 0, 0, workspace, workspace_bytes, stream);
 }
 
 size_t synth_render_backward_workspace(const synth_config* cfg, int64_t batch, int64_t n_samples) {

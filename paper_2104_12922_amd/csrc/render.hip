@@ -101,7 +101,16 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
 
   const uint32_t glo = (uint32_t)g, ghi = (uint32_t)(g >> 32);
 
-  for (int64_t c = 0; c < c_hi; ++c) {
+  int64_t c_start = 0;
+  if (a.carries && c_lo > 0 && c_lo < a.carry_stride) {
+    // the carries at chunk c_lo were computed beforehand: no walk over the
+    // earlier chunks' control stages (a voice longer than the carries cover
+    // walks as before)
+    if (lane < 4) sh.carry[lane] = a.carries[(b * a.carry_stride + c_lo) * 4 + lane];
+    __syncthreads();
+    c_start = c_lo;
+  }
+  for (int64_t c = c_start; c < c_hi; ++c) {
     if (c >= c_sil) {
       const int64_t z0 = (c > c_lo ? c : c_lo) * (int64_t)kSegsPerChunk * q;
       const int64_t z1 = c_hi * (int64_t)kSegsPerChunk * q < N ? c_hi * (int64_t)kSegsPerChunk * q : N;
@@ -227,6 +236,63 @@ __global__ void __launch_bounds__(kWave) render_kernel(const RenderArgs a) {
     render_item<RPS, CLAMP>(a, item / a.slices, (int)(item % a.slices), sh, tile);
 }
 
+// Chunk-start carries for launches that split voices over workgroups: the
+// LFO and VCO phases the control stage carries from chunk to chunk, at the
+// start of every chunk, without walking the chunks one after another.  Each
+// chunk's raw sums come from its own control stage (one wavefront per chunk
+// and voice); one wavefront per voice then applies the updates
+// carry' = (carry + t) - floor(carry + t) in chunk order, the same float64
+// operations the walk performs, so a split render is bit-identical to an
+// unsplit one.  Pass 0 takes the LFO sums (the LFO rates depend on envelopes
+// only), pass 1 the VCO sums given the LFO carries.
+template <int RPS, bool CLAMP, int PASS>
+__global__ void __launch_bounds__(kWave) carry_sums_kernel(const RenderArgs a, double* carries,
+                                                           int64_t stride) {
+  __shared__ VoiceShared sh;
+  __shared__ double envs[8 * kWave];
+  const int lane = threadIdx.x;
+  const int64_t c = blockIdx.x, b = blockIdx.y;
+  const int64_t N = a.offsets ? a.offsets[b + 1] - a.offsets[b] : a.n_uniform;
+  const int64_t J = (N + a.q - 1) / a.q;
+  const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
+  if (N <= 0 || c >= nchunks) return;
+  voice_setup(a, b, sh, lane);
+  double* cr = carries + (b * stride + c) * 4;
+  if (PASS == 1 && lane < 2) sh.carry[lane] = cr[lane];
+  __syncthreads();
+  double y[5], yn[5], tl[4];
+  control_stage<RPS, CLAMP>(a, sh, envs, c, J, a.q / RPS, lane, y, yn, tl);
+  if (lane == 0) {
+    cr[2 * PASS] = tl[2 * PASS];
+    cr[2 * PASS + 1] = tl[2 * PASS + 1];
+  }
+}
+
+template <int PASS>
+__global__ void __launch_bounds__(kWave) carry_scan_kernel(const RenderArgs a, double* carries,
+                                                           int64_t stride) {
+  __shared__ VoiceShared sh;
+  const int lane = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  const int64_t N = a.offsets ? a.offsets[b + 1] - a.offsets[b] : a.n_uniform;
+  const int64_t J = (N + a.q - 1) / a.q;
+  const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
+  if (N <= 0) return;
+  voice_setup(a, b, sh, lane);
+  if (lane < 2) {
+    const int k = 2 * PASS + lane;
+    double cy = sh.carry[k];
+    const int64_t nc_max = nchunks < stride ? nchunks : stride;
+    for (int64_t c = 0; c < nc_max; ++c) {
+      double* cr = carries + (b * stride + c) * 4;
+      const double t = cr[k];
+      cr[k] = cy;
+      const double nc = cy + t;
+      cy = nc - floor(nc);
+    }
+  }
+}
+
 // Mix mode 1: y <- y / max(1, max |y|) per voice.  One 256-thread workgroup per voice.
 __global__ void __launch_bounds__(256) peak_normalise_kernel(const RenderArgs a) {
   __shared__ float red[256];
@@ -276,6 +342,37 @@ hipError_t launch_render(const RenderArgs& a, int runs_per_segment, bool clamp, 
     case 1: return launch_rps<1>(a, clamp, grid, s);
     case 2: return launch_rps<2>(a, clamp, grid, s);
     case 4: return launch_rps<4>(a, clamp, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int RPS, bool CLAMP>
+hipError_t carries_rps(const RenderArgs& a, double* carries, int64_t stride, hipStream_t s) {
+  const dim3 grid((unsigned)stride, (unsigned)a.batch);
+  hipLaunchKernelGGL((carry_sums_kernel<RPS, CLAMP, 0>), grid, dim3(kWave), 0, s, a, carries, stride);
+  hipLaunchKernelGGL((carry_scan_kernel<0>), dim3((unsigned)a.batch), dim3(kWave), 0, s, a, carries,
+                     stride);
+  hipLaunchKernelGGL((carry_sums_kernel<RPS, CLAMP, 1>), grid, dim3(kWave), 0, s, a, carries, stride);
+  hipLaunchKernelGGL((carry_scan_kernel<1>), dim3((unsigned)a.batch), dim3(kWave), 0, s, a, carries,
+                     stride);
+  return hipGetLastError();
+}
+
+template <int RPS>
+hipError_t carries_clamp(const RenderArgs& a, bool clamp, double* carries, int64_t stride,
+                         hipStream_t s) {
+  return clamp ? carries_rps<RPS, true>(a, carries, stride, s)
+               : carries_rps<RPS, false>(a, carries, stride, s);
+}
+
+hipError_t launch_voice_carries(const RenderArgs& a, int runs_per_segment, bool clamp,
+                                double* carries, int64_t stride, hipStream_t s) {
+  if (a.batch == 0 || stride == 0) return hipSuccess;
+  if (a.batch > 65535 || stride > 0x7FFFFFFF) return hipErrorInvalidValue;
+  switch (runs_per_segment) {
+    case 1: return carries_clamp<1>(a, clamp, carries, stride, s);
+    case 2: return carries_clamp<2>(a, clamp, carries, stride, s);
+    case 4: return carries_clamp<4>(a, clamp, carries, stride, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -36,6 +36,8 @@ struct RenderArgs {
   int mix_mode;
   uint32_t nk0, nk1;         // noise key
   NebulaArgs neb;
+  const double* carries;     // null, or [B][carry_stride][4] chunk-start carries
+  int64_t carry_stride;      // chunks per voice in carries
 };
 
 // ---------------------------------------------------------------------------
@@ -109,6 +111,11 @@ hipError_t launch_sample_params(uint64_t seed, uint64_t first_g, int64_t batch,
 // runs_per_segment in {1, 2, 4}; clamp: some pitch can exceed sr / 2.
 hipError_t launch_render(const RenderArgs& a, int runs_per_segment, bool clamp, int grid,
                          hipStream_t s);
+// Chunk-start phase carries of every voice for a render split over
+// workgroups (render.hip): [B][stride][4] doubles (LFO 1, LFO 2, VCO 1,
+// VCO 2), stride = chunks of the longest voice.
+hipError_t launch_voice_carries(const RenderArgs& a, int runs_per_segment, bool clamp,
+                                double* carries, int64_t stride, hipStream_t s);
 
 hipError_t launch_peak_normalise(const RenderArgs& a, hipStream_t s);
 

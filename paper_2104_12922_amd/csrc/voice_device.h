@@ -183,8 +183,12 @@ __device__ inline void voice_setup(const RenderArgs& a, int64_t b, VoiceShared& 
 // (lane < 62) the oscillator data sh.seg; advances the LFO and VCO phase
 // carries to the next chunk.  All 64 lanes call it.
 template <int RPS, bool CLAMP>
+//   tl (optional): receives the four raw chunk sums the carries advance by
+//   (LFO 1, LFO 2, VCO 1, VCO 2: the exclusive scans at lane 62), so that
+//   carry' = (carry + tl) - floor(carry + tl) reproduces this chunk's update.
 __device__ inline void control_stage(const RenderArgs& a, VoiceShared& sh, double* envs, int64_t c,
-                                     int64_t J, int h, int lane, double y[5], double yn[5]) {
+                                     int64_t J, int h, int lane, double y[5], double yn[5],
+                                     double* tl = nullptr) {
   const double* v = sh.v;
   const double* dv = sh.d;
   const double rc = a.rc, sr = a.sr;
@@ -215,7 +219,12 @@ __device__ inline void control_stage(const RenderArgs& a, VoiceShared& sh, doubl
     const int pb = 32 + 8 * i;
     const double f = fmax(0.0, v[pb] + v[pb + 1] * envs[(2 + 2 * i) * kWave + lane]);
     const double inc = lane < kPointsPerChunk - 1 ? f / rc : 0.0;
-    const double th = sh.carry[i] + wave_excl_scan(inc, lane);
+    const double sc = wave_excl_scan(inc, lane);
+    const double th = sh.carry[i] + sc;
+    if (tl) {
+      const double s62 = __shfl(sc, kSegsPerChunk);
+      if (lane == 0) tl[i] = s62;
+    }
     const double ph = th - floor(th);
     const double num = v[pb + 3] * ((1.0 + sinpi(2.0 * ph)) / 2.0) +
                        v[pb + 4] * (1.0 - fabs(2.0 * ph - 1.0)) + v[pb + 5] * ph +
@@ -274,7 +283,12 @@ __device__ inline void control_stage(const RenderArgs& a, VoiceShared& sh, doubl
         S += t;
       }
     }
-    const double th = sh.carry[2 + vc] + wave_excl_scan(lane < kSegsPerChunk ? S : 0.0, lane);
+    const double sc = wave_excl_scan(lane < kSegsPerChunk ? S : 0.0, lane);
+    const double th = sh.carry[2 + vc] + sc;
+    if (tl) {
+      const double s62 = __shfl(sc, kSegsPerChunk);
+      if (lane == 0) tl[2 + vc] = s62;
+    }
     sh.seg[vc][kSegTheta][lane] = th - floor(th);
     sh.seg[vc][kSegInc][lane] = i0;
     sh.seg[vc][kSegRatio][lane] = rr;

@@ -354,8 +354,9 @@ def render_batch(seed, ids, nebula_table, lengths_s=(1, 2, 3, 4), tune: bool = T
             key = f"train:{B}:{tuple(lengths_s)}"
             total = (B // c) * sum(int(round(x * 44100.0)) for x in lengths_s)
             out = torch.empty(total, dtype=F32, device=ids.device)
+        lmax = max(int(round(x * 44100.0)) for x in lengths_s)
         audio = _TUNER.render(u, nebula_table, offsets=offs, voice_ids=ids, noise_seed=seed,
-                              key=key, out=out)
+                              key=key, out=out, max_samples=lmax)
     else:
         audio = synth_render(u, nebula_table, offsets=offs, voice_ids=ids, noise_seed=seed)
     return u, audio, offs

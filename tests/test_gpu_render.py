@@ -166,9 +166,13 @@ def test_ragged_slices_bit_identical(synth):
     u = synth.synth_sample_params(4, 0, lengths.size)
     base = synth.synth_render_plan(u, tab, 4, 1, offsets=off, noise_seed=4)
     for sl in (2, 3, 8):
-        y = synth.synth_render_plan(u, tab, 4, sl, offsets=off, noise_seed=4)
-        assert torch.equal(y, base), sl
+        for car in (False, True):
+            y = synth.synth_render_plan(u, tab, 4, sl, offsets=off, noise_seed=4, carries=car)
+            assert torch.equal(y, base), (sl, car)
     y = synth.synth_render_plan(u, tab, 4, 4, True, 7, offsets=off, noise_seed=4)
+    assert torch.equal(y, base)
+    # carries sized for 1 s: longer voices' later slices walk their chunks
+    y = synth.synth_render_plan(u, tab, 4, 8, offsets=off, noise_seed=4, max_samples=44100)
     assert torch.equal(y, base)
 
 
@@ -183,6 +187,7 @@ def test_autotuner_picks_a_plan_and_renders_with_it(synth):
     assert plan in times and len(times) >= 2
     y = tuner.render(u, tab, offsets=offs, noise_seed=wl.key_noise())
     z = synth.synth_render_plan(u, tab, plan[0], plan[1], bool(plan[2]), plan[3], offsets=offs,
+                                carries=len(plan) > 4 and bool(plan[4]),
                                 noise_seed=wl.key_noise())
     d = synth.synth_render(u, tab, offsets=offs, noise_seed=wl.key_noise())
     assert torch.equal(y, z)
