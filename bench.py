@@ -30,9 +30,8 @@ HBM_PEAK_GBS = 8000.0
 # from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB; the
 # factors make each counter read 1 GiB for a plain 1 GiB device copy).  Valid
 # only for the kernel sources with this digest; reported as null otherwise.
-RENDER_TRAFFIC = {"sources_sha256_16": "e6233602a7f421ce",
-                  "fetch_bytes": 8911437, "write_bytes": 6757857587,
-                  "valu_busy": 0.78}
+RENDER_TRAFFIC = {"sources_sha256_16": "bf33673a02bf9ee7",
+                  "fetch_bytes": 8935347, "write_bytes": 6758020653, "valu_busy": 0.78}
 RENDER_SOURCES = ("render.hip", "voice_device.h", "philox.h")
 
 

@@ -244,7 +244,8 @@ __global__ void __launch_bounds__(kWave) render_kernel(const RenderArgs a) {
 // carry' = (carry + t) - floor(carry + t) in chunk order, the same float64
 // operations the walk performs, so a split render is bit-identical to an
 // unsplit one.  Pass 0 takes the LFO sums (the LFO rates depend on envelopes
-// only), pass 1 the VCO sums given the LFO carries.
+// only: just those envelopes are evaluated), pass 1 the VCO sums given the
+// LFO carries.
 template <int RPS, bool CLAMP, int PASS>
 __global__ void __launch_bounds__(kWave) carry_sums_kernel(const RenderArgs a, double* carries,
                                                            int64_t stride) {
@@ -261,7 +262,10 @@ __global__ void __launch_bounds__(kWave) carry_sums_kernel(const RenderArgs a, d
   if (PASS == 1 && lane < 2) sh.carry[lane] = cr[lane];
   __syncthreads();
   double y[5], yn[5], tl[4];
-  control_stage<RPS, CLAMP>(a, sh, envs, c, J, a.q / RPS, lane, y, yn, tl);
+  if (PASS == 0)
+    lfo_chunk_sums(a, sh, c, lane, tl);
+  else
+    control_stage<RPS, CLAMP>(a, sh, envs, c, J, a.q / RPS, lane, y, yn, tl);
   if (lane == 0) {
     cr[2 * PASS] = tl[2 * PASS];
     cr[2 * PASS + 1] = tl[2 * PASS + 1];

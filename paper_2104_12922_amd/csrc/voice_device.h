@@ -176,6 +176,37 @@ __device__ inline void voice_setup(const RenderArgs& a, int64_t b, VoiceShared& 
   __syncthreads();
 }
 
+// ADSR k at control sample jd: attack rise, decay fall towards sustain,
+// release fall from note-off, each ramp raised to the curve exponent alpha.
+__device__ __forceinline__ double adsr_value(const double* dv, int k, double jd, double note_off) {
+  const double A = dv[kEnvA + k], D = dv[kEnvD + k], R = dv[kEnvR + k];
+  const double S = dv[kEnvS + k], al = dv[kEnvAlpha + k];
+  const double att = ramp(jd, 0.0, A, dv[kEnvInvA + k]);
+  const double dec = ramp(jd, A, D, dv[kEnvInvD + k]);
+  const double rel = ramp(jd, note_off, R, dv[kEnvInvR + k]);
+  return pow01(att, al) * (S + (1.0 - S) * pow01(1.0 - dec, al)) * pow01(1.0 - rel, al);
+}
+
+// The raw LFO chunk sums of control_stage (tl[0], tl[1]) alone: the rate
+// ADSRs and the rate scan, with the same float64 operations.
+__device__ inline void lfo_chunk_sums(const RenderArgs& a, const VoiceShared& sh, int64_t c,
+                                      int lane, double* tl) {
+  const double* v = sh.v;
+  const double* dv = sh.d;
+  const double rc = a.rc;
+  const double note_off = v[1] * rc;
+  const double jd = (double)(c * kSegsPerChunk + lane);
+#pragma unroll 1
+  for (int i = 0; i < 2; ++i) {
+    const int pb = 32 + 8 * i;
+    const double f = fmax(0.0, v[pb] + v[pb + 1] * adsr_value(dv, 2 + 2 * i, jd, note_off));
+    const double inc = lane < kPointsPerChunk - 1 ? f / rc : 0.0;
+    const double sc = wave_excl_scan(inc, lane);
+    const double s62 = __shfl(sc, kSegsPerChunk);
+    if (lane == 0) tl[i] = s62;
+  }
+}
+
 // Control stage of chunk c (control samples j = 62c + lane): the six ADSRs
 // (to envs[k * 64 + lane], float64 LDS scratch of 8 * 64 doubles), both LFOs
 // after their amplitude ADSR (envs[(6 + i) * 64 + lane]), the modulation mixer
@@ -201,17 +232,7 @@ __device__ inline void control_stage(const RenderArgs& a, VoiceShared& sh, doubl
   // Envelopes go through LDS (the tile is idle during the control stage), one
   // at a time, which keeps the float64 exp2/log2 chains from being interleaved.
 #pragma unroll 1
-  for (int k = 0; k < 6; ++k) {
-    // ADSR: attack rise, decay fall towards sustain, release fall from note-off,
-    // each ramp raised to the curve exponent alpha.
-    const double A = dv[kEnvA + k], D = dv[kEnvD + k], R = dv[kEnvR + k];
-    const double S = dv[kEnvS + k], al = dv[kEnvAlpha + k];
-    const double att = ramp(jd, 0.0, A, dv[kEnvInvA + k]);
-    const double dec = ramp(jd, A, D, dv[kEnvInvD + k]);
-    const double rel = ramp(jd, note_off, R, dv[kEnvInvR + k]);
-    envs[k * kWave + lane] =
-        pow01(att, al) * (S + (1.0 - S) * pow01(1.0 - dec, al)) * pow01(1.0 - rel, al);
-  }
+  for (int k = 0; k < 6; ++k) envs[k * kWave + lane] = adsr_value(dv, k, jd, note_off);
   // LFOs (rate ADSR modulates the rate; amp ADSR is a control-rate VCA),
   // written next to the envelopes: lfo'_i at envs[(6 + i) * 64 + lane].
 #pragma unroll 1

@@ -344,8 +344,12 @@ def render_batch(seed, ids, nebula_table, lengths_s=(1, 2, 3, 4), tune: bool = T
     u = synth_sample_params(seed, voice_ids=ids)
     if tune:
         if _TUNER is None:
-            from .autotune import RenderTuner
-            _TUNER = RenderTuner(reps=3)
+            from .autotune import RenderTuner, default_candidates
+            # Every step renders new voices (new note lengths and silent tails):
+            # persistent round-robin grids, whose speed depends on the order of
+            # the voices' costs, are left out; slices balance the load per voice.
+            cands = [p for p in default_candidates(ids.numel(), False) if not p[2]]
+            _TUNER = RenderTuner(reps=3, candidates=cands)
         # every batch of B consecutive training voices has the same length mix
         # when B is a multiple of the cycle, so the shape is named, not read back
         B, c = ids.numel(), len(lengths_s)
