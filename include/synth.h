@@ -153,7 +153,9 @@ int synth_render_plan_ws(const synth_config* cfg, const float* params, const uin
                          int grid_blocks, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Workspace (bytes of device memory) that synth_render_backward needs for a
- * batch of uniform-length voices: batch * ceil(n_samples / q) * 21 doubles.
+ * batch of uniform-length voices: batch * (ceil(n_samples / q) * 21 +
+ * chunks * 4) doubles (per-segment sums, then the chunk-start phase carries
+ * of voices split over workgroups; chunks = ceil(ceil(n_samples / q) / 62)).
  * Returns 0 for an invalid cfg. */
 size_t synth_render_backward_workspace(const synth_config* cfg, int64_t batch, int64_t n_samples);
 

@@ -74,8 +74,8 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
   const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
   const int64_t c_sil = (js + kSegsPerChunk - 1) / kSegsPerChunk;
   // this workgroup's chunks (a voice may be split over several workgroups;
-  // the earlier chunks are walked through the control stage only, for its
-  // carries)
+  // the carries at its first chunk are precomputed, or the earlier chunks
+  // are walked through the control stage only)
   const int64_t c_lo = nchunks * slice / a.slices;
   const int64_t c_hi = nchunks * (slice + 1) / a.slices;
 
@@ -90,7 +90,14 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
   const float two_pi = 6.28318530717958647692f;
   const uint32_t glo = (uint32_t)g, ghi = (uint32_t)(g >> 32);
 
-  for (int64_t c = 0; c < c_hi; ++c) {
+  int64_t c_start = 0;
+  if (a.carries && c_lo > 0 && c_lo < a.carry_stride) {
+    // chunk-start carries computed beforehand (as for a split render)
+    if (lane < 4) sh.carry[lane] = a.carries[(b * a.carry_stride + c_lo) * 4 + lane];
+    __syncthreads();
+    c_start = c_lo;
+  }
+  for (int64_t c = c_start; c < c_hi; ++c) {
     if (c >= c_sil) {
       // exactly silent from here on: every reduction is zero (the envelopes are
       // 0 with zero derivative, so no parameter sees these samples)
@@ -636,8 +643,15 @@ hipError_t launch_adjoint_rps(const RenderArgs& a, const float* g, double* red, 
 }  // namespace
 
 size_t adjoint_workspace_bytes(int64_t batch, int64_t n_samples, int q) {
+  // per-segment sums, then the chunk-start carries [batch][chunks][4]
   const int64_t J = (n_samples + q - 1) / q;
-  return (size_t)batch * (size_t)J * kNumRed * sizeof(double);
+  const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
+  return (size_t)batch * ((size_t)J * kNumRed + (size_t)nchunks * 4) * sizeof(double);
+}
+
+double* adjoint_carries(double* ws, int64_t batch, int64_t n_samples, int q) {
+  const int64_t J = (n_samples + q - 1) / q;
+  return ws + batch * J * kNumRed;
 }
 
 int64_t adjoint_max_chunks() { return 512; }

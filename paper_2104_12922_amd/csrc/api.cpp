@@ -376,14 +376,25 @@ int synth_render_backward(const synth_config* cfg, const float* params, const ui
   a.first_g = first_g;
   a.batch = batch;
   a.n_uniform = n_samples;
+  const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
+  const bool carried = batch <= 65535;
   {
     // Small batches: split each voice's audio-rate pass over several
-    // workgroups so that the grid covers the chip (as the render does).
-    const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
+    // workgroups so that the grid covers the chip (as the render does),
+    // starting from precomputed chunk carries.
     int64_t want = (2048 + batch - 1) / batch;
-    if (want > nchunks / 4) want = nchunks / 4;
+    const int64_t cap = carried ? nchunks : nchunks / 4;
+    if (want > cap) want = cap;
     a.slices = want > 1 ? (int)want : 1;
     if (batch * (int64_t)a.slices > 0x7FFFFFFF) a.slices = 1;
+  }
+  if (carried && a.slices > 1) {
+    double* carries = synth::adjoint_carries((double*)workspace, batch, n_samples, a.q);
+    if (synth::launch_voice_carries(a, rps, false, carries, nchunks, (hipStream_t)stream) !=
+        hipSuccess)
+      return SYNTH_EDEVICE;
+    a.carries = carries;
+    a.carry_stride = nchunks;
   }
   return to_status(synth::launch_render_backward(a, grad_audio, (double*)workspace, grad_params,
                                                  rps, (hipStream_t)stream));

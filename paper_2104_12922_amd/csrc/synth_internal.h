@@ -120,6 +120,8 @@ hipError_t launch_voice_carries(const RenderArgs& a, int runs_per_segment, bool 
 hipError_t launch_peak_normalise(const RenderArgs& a, hipStream_t s);
 
 size_t adjoint_workspace_bytes(int64_t batch, int64_t n_samples, int q);
+// where the chunk-start carries begin in an adjoint workspace
+double* adjoint_carries(double* ws, int64_t batch, int64_t n_samples, int q);
 int64_t adjoint_max_chunks();
 hipError_t launch_render_backward(const RenderArgs& a, const float* grad_audio, double* ws,
                                   float* grad_params, int runs_per_segment, hipStream_t s);
