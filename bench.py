@@ -316,25 +316,26 @@ def main():
     audio = torch.empty(total, dtype=torch.float32, device=dev)
     stream = torch.cuda.Stream(device=dev)
 
-    plan = None
+    # launch order: longest voices first (the lengths are known with the
+    # offsets), so that short voices fill the end of the launch
+    order = torch.from_numpy(np.argsort(-wl.lengths, kind="stable").astype(np.int32)).to(dev)
+    lmax = int(wl.lengths.max())
+    plan = (4, 1, 0, 0)                       # the library's default plan
     if args.rps:
         plan = (args.rps, 1, 0, 0)
     elif args.autotune:
         from paper_2104_12922_amd.autotune import RenderTuner
         with torch.cuda.stream(stream):
             S.synth_sample_params(wl.seed, wl.first_g, B, out=params)
-            plan, _ = RenderTuner().tune(params, table, offsets=offsets,
-                                         noise_seed=wl.key_noise(), out=audio)
+            plan, _ = RenderTuner().tune(params, table, offsets=offsets, order=order,
+                                         max_samples=lmax, noise_seed=wl.key_noise(), out=audio)
         torch.cuda.synchronize()
 
     def render():
-        if plan is not None:
-            S.synth_render_plan(params, table, plan[0], plan[1], persistent=bool(plan[2]),
-                                grid_blocks=plan[3], offsets=offsets,
-                                carries=len(plan) > 4 and bool(plan[4]), max_samples=4 * 44100,
-                                noise_seed=wl.key_noise(), out=audio)
-        else:
-            S.synth_render(params, table, offsets=offsets, noise_seed=wl.key_noise(), out=audio)
+        S.synth_render_plan(params, table, plan[0], plan[1], persistent=bool(plan[2]),
+                            grid_blocks=plan[3], offsets=offsets,
+                            carries=len(plan) > 4 and bool(plan[4]), max_samples=lmax,
+                            order=order, noise_seed=wl.key_noise(), out=audio)
 
     def step():
         S.synth_sample_params(wl.seed, wl.first_g, B, out=params)
@@ -384,7 +385,8 @@ def main():
                    "lengths_s": [1, 2, 4], "sample_rate": wl.sample_rate,
                    "control_rate": wl.control_rate, "note_duration_s": [0.1, 4.0],
                    "hip_graph": bool(args.graph), "phase_dtype": "f64",
-                   "launch_plan": list(plan) if plan is not None else "default"},
+                   "launch_plan": list(plan) if plan is not None else "default",
+                   "launch_order": "longest voices first"},
         "mhz": value / 1e6, "x_realtime": value / wl.sample_rate,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -131,7 +131,7 @@ int synth_render_plan(const synth_config* cfg, const float* params, const uint64
                       float* audio, int runs_per_segment, int slices_per_voice,
                       int persistent, int grid_blocks, void* stream);
 
-/* synth_render_plan with a workspace for split voices.  With
+/* synth_render_plan with a voice order and a workspace for split voices.  With
  * slices_per_voice > 1 a workgroup that starts inside a voice needs the
  * phase carries (LFOs, VCOs) at its first chunk; synth_render_plan walks the
  * earlier chunks' control stages for them, this entry computes every chunk's
@@ -141,16 +141,22 @@ int synth_render_plan(const synth_config* cfg, const float* params, const uint64
  *   max_samples  longest voice with offsets (ignored without): sizes the
  *                carries; a longer voice still renders correctly (its later
  *                chunks walk as in synth_render_plan).
+ *   order        dev int32 [batch], a permutation of 0 .. batch - 1, or NULL:
+ *                workgroups take the voices in this order (e.g. longest
+ *                first, so that short voices fill the end of the launch);
+ *                the output does not depend on it.  Entries outside
+ *                0 .. batch - 1 are skipped.
  *   workspace    dev, >= synth_render_plan_workspace(cfg, batch, max_samples)
  *                bytes (SYNTH_ENOMEM otherwise), contents clobbered; NULL or
- *                slices_per_voice == 1: exactly synth_render_plan.
+ *                slices_per_voice == 1: no carries are precomputed.
  *   batch <= 65535 with a workspace and slices > 1 (SYNTH_EUNSUPPORTED). */
 size_t synth_render_plan_workspace(const synth_config* cfg, int64_t batch, int64_t max_samples);
 int synth_render_plan_ws(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
                          uint64_t first_g, int64_t batch, const int64_t* offsets,
                          int64_t n_samples, int64_t max_samples, float* audio,
                          int runs_per_segment, int slices_per_voice, int persistent,
-                         int grid_blocks, void* workspace, size_t workspace_bytes, void* stream);
+                         int grid_blocks, const int32_t* order, void* workspace,
+                         size_t workspace_bytes, void* stream);
 
 /* Workspace (bytes of device memory) that synth_render_backward needs for a
  * batch of uniform-length voices: batch * (ceil(n_samples / q) * 21 +

@@ -128,30 +128,36 @@ def synth_render_plan(params: torch.Tensor, nebula, runs_per_segment: int, slice
                       first_g: int = 0, noise_seed: int = 0, mix_mode: int = 0,
                       sample_rate: float = 44100.0, control_rate: float = 441.0,
                       out: torch.Tensor | None = None, carries: bool = True,
-                      max_samples: int | None = None,
-                      workspace: torch.Tensor | None = None) -> torch.Tensor:
+                      max_samples: int | None = None, workspace: torch.Tensor | None = None,
+                      order: torch.Tensor | None = None) -> torch.Tensor:
     """Render with an explicit launch plan.  With slices_per_voice > 1 and
     `carries`, the chunk-start phase carries are computed first in a
     workspace (`synth_render_plan_ws`); `max_samples` (longest voice, ragged
     batches) avoids reading the offsets back; `workspace` may be given to
-    reuse a buffer."""
+    reuse a buffer.  `order` (int32 [B], a permutation) is the order in which
+    workgroups take the voices (the output does not depend on it)."""
     args, out, keep = _render_common(params, nebula, n_samples, offsets, voice_ids, first_g,
                                      noise_seed, mix_mode, sample_rate, control_rate, out)
     L = _native.lib()
     plan = (int(runs_per_segment), int(slices_per_voice), int(bool(persistent)), int(grid_blocks))
     B = params.shape[0]
-    if carries and slices_per_voice > 1 and B > 0:
-        if offsets is None:
-            lmax = int(n_samples)
-        elif max_samples is not None:
-            lmax = int(max_samples)
-        else:
-            lmax = int(torch.diff(offsets).max().item())
-        need = L.synth_render_plan_workspace(ctypes_ref(args[0]), B, max(lmax, 1))
-        if workspace is None or workspace.numel() < need:
-            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=params.device)
-        st = L.synth_render_plan_ws(ctypes_ref(args[0]), *args[1:7], lmax, args[7], *plan,
-                                    workspace.data_ptr(), workspace.numel(), _stream(params.device))
+    use_carries = carries and slices_per_voice > 1 and B > 0
+    if use_carries or order is not None:
+        ordp = _dev_ptr(order, "order", torch.int32, B) if order is not None else None
+        lmax, wsp, wsn = 0, None, 0
+        if use_carries:
+            if offsets is None:
+                lmax = int(n_samples)
+            elif max_samples is not None:
+                lmax = int(max_samples)
+            else:
+                lmax = int(torch.diff(offsets).max().item())
+            need = L.synth_render_plan_workspace(ctypes_ref(args[0]), B, max(lmax, 1))
+            if workspace is None or workspace.numel() < need:
+                workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=params.device)
+            wsp, wsn = workspace.data_ptr(), workspace.numel()
+        st = L.synth_render_plan_ws(ctypes_ref(args[0]), *args[1:7], lmax, args[7], *plan, ordp,
+                                    wsp, wsn, _stream(params.device))
         _native.check("synth_render_plan_ws", st)
     else:
         st = L.synth_render_plan(ctypes_ref(args[0]), *args[1:], *plan, _stream(params.device))

@@ -71,7 +71,8 @@ def lib() -> ctypes.CDLL:
         L.synth_render_plan_ws.restype = ctypes.c_int
         L.synth_render_plan_ws.argtypes = (render_args[:7] + [ctypes.c_int64] + render_args[7:] +
                                            [ctypes.c_int] * 4 +
-                                           [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p])
+                                           [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                            ctypes.c_void_p])
         L.synth_mrstft_loss.restype = ctypes.c_int
         L.synth_mrstft_loss.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                         ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,

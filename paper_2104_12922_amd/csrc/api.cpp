@@ -210,8 +210,8 @@ int64_t chunks_of(int64_t n_samples, int q) {
 int render_plan_impl(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
                      uint64_t first_g, int64_t batch, const int64_t* offsets, int64_t n_samples,
                      int64_t max_samples, float* audio, int runs_per_segment,
-                     int slices_per_voice, int persistent, int grid_blocks, void* workspace,
-                     size_t workspace_bytes, void* stream) {
+                     int slices_per_voice, int persistent, int grid_blocks, const int32_t* order,
+                     void* workspace, size_t workspace_bytes, void* stream) {
   if (batch < 0) return SYNTH_EINVAL;
   RenderArgs a;
   bool clamp = false;
@@ -241,6 +241,8 @@ int render_plan_impl(const synth_config* cfg, const float* params, const uint64_
   a.n_uniform = offsets ? 0 : n_samples;
   a.batch = batch;
   a.slices = slices_per_voice;
+  a.order = order;
+  if (order && batch > 0x7FFFFFFF) return SYNTH_EINVAL;
   int grid = (int)items;
   if (persistent) {
     grid = grid_blocks > 0 ? grid_blocks : 256 * 12;
@@ -275,8 +277,8 @@ int synth_render_plan(const synth_config* cfg, const float* params, const uint64
                       float* audio, int runs_per_segment, int slices_per_voice, int persistent,
                       int grid_blocks, void* stream) {
   return render_plan_impl(cfg, params, voice_ids, first_g, batch, offsets, n_samples, 0, audio,
-                          runs_per_segment, slices_per_voice, persistent, grid_blocks, nullptr, 0,
-                          stream);
+                          runs_per_segment, slices_per_voice, persistent, grid_blocks, nullptr,
+                          nullptr, 0, stream);
 }
 
 size_t synth_render_plan_workspace(const synth_config* cfg, int64_t batch, int64_t max_samples) {
@@ -290,9 +292,10 @@ int synth_render_plan_ws(const synth_config* cfg, const float* params, const uin
                          uint64_t first_g, int64_t batch, const int64_t* offsets,
                          int64_t n_samples, int64_t max_samples, float* audio,
                          int runs_per_segment, int slices_per_voice, int persistent,
-                         int grid_blocks, void* workspace, size_t workspace_bytes, void* stream) {
+                         int grid_blocks, const int32_t* order, void* workspace,
+                         size_t workspace_bytes, void* stream) {
   return render_plan_impl(cfg, params, voice_ids, first_g, batch, offsets, n_samples, max_samples,
-                          audio, runs_per_segment, slices_per_voice, persistent, grid_blocks,
+                          audio, runs_per_segment, slices_per_voice, persistent, grid_blocks, order,
                           workspace, workspace_bytes, stream);
 }
 
@@ -344,7 +347,7 @@ int synth_render_ws(const synth_config* cfg, const float* params, const uint64_t
   int rps, slices;
   default_plan(cfg, batch, offsets, n_samples, true, &rps, &slices);
   return render_plan_impl(cfg, params, voice_ids, first_g, batch, offsets, n_samples, n_samples,
-                          audio, rps, slices, 0, 0, workspace, workspace_bytes, stream);
+                          audio, rps, slices, 0, 0, nullptr, workspace, workspace_bytes, stream);
 }
 
 size_t synth_render_backward_workspace(const synth_config* cfg, int64_t batch, int64_t n_samples) {

@@ -233,7 +233,11 @@ __global__ void __launch_bounds__(kWave) render_kernel(const RenderArgs a) {
   extern __shared__ __align__(16) float tile[];
   const int64_t nitems = a.batch * a.slices;
   for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x)
-    render_item<RPS, CLAMP>(a, item / a.slices, (int)(item % a.slices), sh, tile);
+  {
+    const int64_t k = item / a.slices;
+    const int64_t b = a.order ? (int64_t)a.order[k] : k;
+    if (b >= 0 && b < a.batch) render_item<RPS, CLAMP>(a, b, (int)(item % a.slices), sh, tile);
+  }
 }
 
 // Chunk-start carries for launches that split voices over workgroups: the

@@ -36,6 +36,7 @@ struct RenderArgs {
   int mix_mode;
   uint32_t nk0, nk1;         // noise key
   NebulaArgs neb;
+  const int32_t* order;      // null, or the voices in the order workgroups take them
   const double* carries;     // null, or [B][carry_stride][4] chunk-start carries
   int64_t carry_stride;      // chunks per voice in carries
 };

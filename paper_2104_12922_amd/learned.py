@@ -337,9 +337,15 @@ _TUNER = None
 
 def render_batch(seed, ids, nebula_table, lengths_s=(1, 2, 3, 4), tune: bool = True):
     """(u, packed audio, offsets) of voices ids drawn and rendered on the GPU
-    (with the launch plan the autotuner picked for this batch shape)."""
+    (with the launch plan the autotuner picked for this batch shape).  The
+    voices come back ordered longest first; u and the audio stay aligned."""
     global _TUNER
     from . import synth_render, synth_sample_params
+    # longest voices first: workgroups are dispatched in voice order, so the
+    # long voices start early and the short ones fill the tail of the launch
+    per = torch.tensor([int(round(x * 44100.0)) for x in lengths_s], dtype=torch.int64,
+                       device=ids.device)
+    ids = ids[torch.argsort(-per[ids % len(lengths_s)], stable=True)]
     offs = ragged_offsets(ids, lengths_s)
     u = synth_sample_params(seed, voice_ids=ids)
     if tune:

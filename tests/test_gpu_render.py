@@ -174,6 +174,13 @@ def test_ragged_slices_bit_identical(synth):
     # carries sized for 1 s: longer voices' later slices walk their chunks
     y = synth.synth_render_plan(u, tab, 4, 8, offsets=off, noise_seed=4, max_samples=44100)
     assert torch.equal(y, base)
+    # the order in which workgroups take the voices changes nothing
+    for perm in (np.argsort(-lengths, kind="stable"), np.random.default_rng(3).permutation(lengths.size)):
+        order = torch.from_numpy(perm.astype(np.int32)).cuda()
+        for sl, pers in ((1, False), (3, False), (2, True)):
+            y = synth.synth_render_plan(u, tab, 4, sl, pers, 3 if pers else 0, offsets=off,
+                                        noise_seed=4, order=order)
+            assert torch.equal(y, base), (sl, pers)
 
 
 def test_autotuner_picks_a_plan_and_renders_with_it(synth):
