@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 # from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB; the
 # factors make each counter read 1 GiB for a plain 1 GiB device copy).  Valid
 # only for the kernel sources with this digest; reported as null otherwise.
-RENDER_TRAFFIC = {"sources_sha256_16": "bf33673a02bf9ee7",
-                  "fetch_bytes": 8935347, "write_bytes": 6758020653, "valu_busy": 0.78}
+RENDER_TRAFFIC = {"sources_sha256_16": "ad1c82dc8b0a9774",
+                  "fetch_bytes": 10691610, "write_bytes": 6758832467, "valu_busy": 0.91}
 RENDER_SOURCES = ("render.hip", "voice_device.h", "philox.h")
 
 
@@ -374,7 +374,7 @@ def main():
     prof = render_traffic() if wl.batch == 16384 and plan in (None, (4, 1, 0, 0)) else None
     ms = dt / args.steps * 1e3
     value = total / (dt / args.steps)
-    alg_bytes = 4.0 * total + 4.0 * 78 * B + 8.0 * (B + 1)
+    alg_bytes = 4.0 * total + 4.0 * 78 * B + 8.0 * (B + 1) + 4.0 * B   # audio, params, offsets, order
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     out = {
         "metric": "rendered audio samples/sec", "value": value, "unit": "samples/s",
