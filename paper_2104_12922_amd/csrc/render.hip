@@ -157,6 +157,7 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
           t2 += s2; s2 *= R2; i2 *= R2;
         }
       }
+      t1 -= rint(t1);                            // exact; see sin_cycles_run
       float kf = (float)(m * h);
       float* trow = tile + lane * h;
       // Consume the LDS and cross-lane loads here, so that the loop below
@@ -164,7 +165,7 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
       asm volatile("" ::"v"(t1), "v"(i1), "v"(t2), "v"(i2), "v"(r1), "v"(r2));
       asm volatile("" ::"v"(A10), "v"(A1d), "v"(A20), "v"(A2d));
       for (int k = 0; k < h; ++k) {
-        const float x1 = sin_cycles(t1);
+        const float x1 = sin_cycles_run(t1);
         const float x2 = squaresaw(t2, K2, shape, sq_gain);
         const float A1 = fmaf(kf, A1d, A10);
         const float A2 = fmaf(kf, A2d, A20);

@@ -59,13 +59,15 @@ __device__ __forceinline__ double wave_excl_scan(double x, int lane) {
 // ---------------------------------------------------------------------------
 // float32 audio-rate helpers
 // ---------------------------------------------------------------------------
-// sin(2 pi th) for the sine VCO: th (cycles, float64) is reduced to the
-// nearest integer in float64, r = th - rint(th) in [-1/2, 1/2], and the
-// hardware sine (input in revolutions, absolute error ~1.3e-7 on [-1/2, 1/2])
-// is evaluated on float(r).
-__device__ __forceinline__ float sin_cycles(double th) {
-  const float r = (float)(th - rint(th));
-  return __builtin_amdgcn_sinf(r);
+// sin(2 pi th) for the sine VCO within one run of samples: the caller
+// reduces th to [-1/2, 1/2] in float64 at the run's start, so within a run
+// of at most 192 samples of at most 1/2 cycle each |th| < 97 and float(th)
+// is within 2^-18 cycles of it (sine error < 2.5e-5, typically far less: the
+// per-sample increment is f / sr); the hardware sine takes revolutions and
+// reduces its input itself (valid for |x| < 256).  The square-saw, whose
+// tanh edge amplifies phase error, keeps the exact half-cycle reduction.
+__device__ __forceinline__ float sin_cycles_run(double th) {
+  return __builtin_amdgcn_sinf((float)th);
 }
 
 // sin and cos of 2 pi th for the square-saw.  Its tanh edge multiplies the
