@@ -17,7 +17,8 @@ from . import _native
 NUM_PARAMS = _native.NUM_PARAMS
 
 __all__ = ["synth_sample_params", "synth_render", "synth_render_plan", "synth_is_test",
-           "synth_mrstft_loss", "synth_render_backward", "SynthRender", "MRSTFTLoss",
+           "synth_mrstft_loss", "synth_mrstft_target", "MrstftTarget",
+           "synth_render_backward", "SynthRender", "MRSTFTLoss",
            "NUM_PARAMS", "SynthError"]
 
 SynthError = _native.SynthError
@@ -176,10 +177,34 @@ def synth_mrstft_workspace(batch: int, n_samples: int, grad: bool = False) -> to
     return torch.empty(need, dtype=torch.uint8, device="cuda")
 
 
-def synth_mrstft_loss(x: torch.Tensor, target: torch.Tensor, grad: bool = False,
+class MrstftTarget:
+    """Log-magnitude spectra of a fixed [B, N] target, computed once by
+    synth_mrstft_target and reused by synth_mrstft_loss(x, <this>)."""
+
+    def __init__(self, target: torch.Tensor):
+        if target.dim() != 2:
+            raise ValueError("target must be [B, N]")
+        B, N = target.shape
+        self.shape = target.shape
+        self.device = target.device
+        nbytes = _native.lib().synth_mrstft_target_bytes(int(B), int(N))
+        self.tlog = torch.empty(max(nbytes, 8) // 4 + 1, dtype=torch.float32,
+                                device=target.device)
+        _native.check("synth_mrstft_target", _native.lib().synth_mrstft_target(
+            _dev_ptr(target, "target", torch.float32, B * N), B, N, self.tlog.data_ptr(),
+            self.tlog.numel() * 4, _stream(target.device)))
+
+
+def synth_mrstft_target(target: torch.Tensor) -> MrstftTarget:
+    return MrstftTarget(target)
+
+
+def synth_mrstft_loss(x: torch.Tensor, target, grad: bool = False,
                       workspace: torch.Tensor | None = None, out_grad: torch.Tensor | None = None):
     """Per-voice multi-resolution log-magnitude STFT L1 (float64 [B]) and, if
-    grad, d loss[b] / d x[b] (float32 [B, N]) - see synth.h."""
+    grad, d loss[b] / d x[b] (float32 [B, N]) - see synth.h.  target is a
+    [B, N] float32 tensor or an MrstftTarget of one (spectra computed once)."""
+    cached = isinstance(target, MrstftTarget)
     if x.shape != target.shape or x.dim() != 2:
         raise ValueError("x and target must both be [B, N]")
     B, N = x.shape
@@ -188,8 +213,12 @@ def synth_mrstft_loss(x: torch.Tensor, target: torch.Tensor, grad: bool = False,
     need = _native.lib().synth_mrstft_workspace(int(B), int(N), int(bool(grad)))
     if workspace is None or workspace.numel() * workspace.element_size() < need:
         workspace = torch.empty(max(need, 8), dtype=torch.uint8, device=x.device)
-    _native.check("synth_mrstft_loss", _native.lib().synth_mrstft_loss(
-        _dev_ptr(x, "x", torch.float32, B * N), _dev_ptr(target, "target", torch.float32, B * N),
+    if cached:
+        fn, tptr = "synth_mrstft_loss_cached", target.tlog.data_ptr()
+    else:
+        fn, tptr = "synth_mrstft_loss", _dev_ptr(target, "target", torch.float32, B * N)
+    _native.check(fn, getattr(_native.lib(), fn)(
+        _dev_ptr(x, "x", torch.float32, B * N), tptr,
         B, N, _dev_ptr(loss, "loss", torch.float64, B),
         _dev_ptr(g, "grad", torch.float32, B * N) if grad else None, workspace.data_ptr(),
         workspace.numel() * workspace.element_size(), _stream(x.device)))

@@ -51,6 +51,8 @@ struct MrArgs {
   double* partial;             // [batch][chunk_base[3]] loss partial sums
   float* grad;                 // output gradient (null: loss only)
   double* loss;
+  float* tlog;                 // target log2(|T| + eps) per frame and bin (MODE 1 writes, 2 reads)
+  int64_t tbase[3];            // float offset of each resolution's rows in tlog
 };
 
 // LDS of one resolution (Nc = n / 2 complex points per transform).
@@ -82,14 +84,19 @@ __device__ __forceinline__ void real_pair(const float2* buf, const float2* rs, i
   Xm = make_float2(D.x, -D.y);
 }
 
-// One bin's loss share (added to acc) and gradient spectrum value.
-__device__ __forceinline__ float2 bin_grad(float2 X, float2 T, double scale_d, float scale,
+// log2(|T| + eps) of a target bin (hardware sqrt and log2, about 1 ulp each).
+__device__ __forceinline__ float target_log(float2 T) {
+  const float at = __builtin_amdgcn_sqrtf(T.x * T.x + T.y * T.y);
+  return __builtin_amdgcn_logf(at + kEps);
+}
+
+// One bin's loss share (added to acc) and gradient spectrum value, from the
+// render bin X and the target's lt = target_log(T).
+__device__ __forceinline__ float2 bin_grad(float2 X, float lt, double scale_d, float scale,
                                            bool edge, bool want_grad, double& acc) {
   // hardware sqrt, log2 and reciprocal (about 1 ulp each)
   const float ax = __builtin_amdgcn_sqrtf(X.x * X.x + X.y * X.y);
-  const float at = __builtin_amdgcn_sqrtf(T.x * T.x + T.y * T.y);
-  const float d = 0.69314718055994531f *
-                  (__builtin_amdgcn_logf(ax + kEps) - __builtin_amdgcn_logf(at + kEps));
+  const float d = 0.69314718055994531f * (__builtin_amdgcn_logf(ax + kEps) - lt);
   acc += scale_d * (double)fabsf(d);
   float2 G = make_float2(0.f, 0.f);
   if (want_grad && ax > 0.0f && d != 0.0f) {
@@ -100,7 +107,10 @@ __device__ __forceinline__ float2 bin_grad(float2 X, float2 T, double scale_d, f
   return G;
 }
 
-template <int RES>
+// MODE 0: loss (and gradient) from render and target frames; MODE 1: only
+// the target's log magnitudes, written to a.tlog (no loss); MODE 2: loss
+// (and gradient) with the target's log magnitudes read from a.tlog.
+template <int RES, int MODE>
 __device__ __forceinline__ void mrstft_frames(const MrArgs& a, MrShared<256 << RES>& sh, int64_t b,
                                               int blk) {
   constexpr int r = RES;
@@ -114,7 +124,7 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, MrShared<256 << R
   const int lane = tid & 63, wv = tid >> 6;
   const int chunk = blk - a.chunk_base[r];
   const int F = a.F[r];
-  const bool want_grad = a.wgrad != nullptr;
+  const bool want_grad = MODE != 1 && a.wgrad != nullptr;
   // The scale is applied in float32 to the gradient and in float64 to the loss.
   const double scale_d = a.scale[r];
   const float scale = (float)scale_d;
@@ -146,8 +156,44 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, MrShared<256 << R
     if (live) {
       const float* fx = xs + (int64_t)f * hop;
       const float* ft = ts + (int64_t)f * hop;
-      // ---- render frame: X bins kept in registers ----
+      float* trow = a.tlog ? a.tlog + a.tbase[r] + ((int64_t)b * F + f) * (Nc + 1) : nullptr;
       float2 v[P];
+      // ---- target frame: log magnitudes of bins k, Nc - k, Nc / 2 ----
+      float Lk[QB + 1], Lm[QB + 1];
+      if constexpr (MODE == 2) {
+#pragma unroll
+        for (int q = 0; q <= QB; ++q) {
+          const int k = q < QB ? lane + 64 * q : Nc / 2;
+          Lk[q] = trow[k];
+          Lm[q] = trow[Nc - k];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          const int m = lane + 64 * q;
+          const float2 w2 = *reinterpret_cast<const float2*>(&sh.win[2 * m]);
+          v[q] = make_float2(w2.x * ft[2 * m], w2.y * ft[2 * m + 1]);
+        }
+        wfft::wave_fft<Nc, true>(v, buf, sh.pt, lane);
+#pragma unroll
+        for (int q = 0; q <= QB; ++q) {
+          float2 Tk, Tm;
+          real_pair<Nc>(buf, sh.rs, q < QB ? lane + 64 * q : Nc / 2, Tk, Tm);
+          Lk[q] = target_log(Tk);
+          Lm[q] = target_log(Tm);
+        }
+        if constexpr (MODE == 1) {
+#pragma unroll
+          for (int q = 0; q < QB; ++q) {
+            const int k = lane + 64 * q;
+            trow[k] = Lk[q];
+            trow[Nc - k] = Lm[q];
+          }
+          if (lane == 0) trow[Nc / 2] = Lk[QB];
+          continue;
+        }
+      }
+      // ---- render frame ----
 #pragma unroll
       for (int q = 0; q < P; ++q) {
         const int m = lane + 64 * q;
@@ -155,30 +201,19 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, MrShared<256 << R
         v[q] = make_float2(w2.x * fx[2 * m], w2.y * fx[2 * m + 1]);
       }
       wfft::wave_fft<Nc, true>(v, buf, sh.pt, lane);
-      float2 Xk[QB + 1], Xm[QB + 1];
-#pragma unroll
-      for (int q = 0; q <= QB; ++q) real_pair<Nc>(buf, sh.rs, q < QB ? lane + 64 * q : Nc / 2, Xk[q], Xm[q]);
-      // ---- target frame ----
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        const int m = lane + 64 * q;
-        const float2 w2 = *reinterpret_cast<const float2*>(&sh.win[2 * m]);
-        v[q] = make_float2(w2.x * ft[2 * m], w2.y * ft[2 * m + 1]);
-      }
-      wfft::wave_fft<Nc, true>(v, buf, sh.pt, lane);
       float2 Hk[QB + 1], Hm[QB + 1];
 #pragma unroll
       for (int q = 0; q <= QB; ++q) {
         const int k = q < QB ? lane + 64 * q : Nc / 2;
-        float2 Tk, Tm;
-        real_pair<Nc>(buf, sh.rs, k, Tk, Tm);
+        float2 Xk, Xm;
+        real_pair<Nc>(buf, sh.rs, k, Xk, Xm);
         if (q < QB) {
-          Hk[q] = bin_grad(Xk[q], Tk, scale_d, scale, k == 0, want_grad, acc);
-          Hm[q] = bin_grad(Xm[q], Tm, scale_d, scale, k == 0, want_grad, acc);   // bin Nc - k
+          Hk[q] = bin_grad(Xk, Lk[q], scale_d, scale, k == 0, want_grad, acc);
+          Hm[q] = bin_grad(Xm, Lm[q], scale_d, scale, k == 0, want_grad, acc);   // bin Nc - k
         } else {
           // bin Nc / 2, once per frame (lane 0)
           double a2 = 0.0;
-          Hk[q] = bin_grad(Xk[q], Tk, scale_d, scale, false, want_grad, a2);
+          Hk[q] = bin_grad(Xk, Lk[q], scale_d, scale, false, want_grad, a2);
           if (lane == 0) acc += a2;
           Hm[q] = make_float2(0.f, 0.f);
         }
@@ -254,6 +289,7 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, MrShared<256 << R
     for (int p = done + tid; p < kSegHops * hop; p += kMrThreads)
       seg[p] = p < done + 3 * hop ? sh.ola[p & (kOlaSlots - 1)] : 0.0f;
   }
+  if constexpr (MODE == 1) return;
   // fixed-order reduction of the per-lane loss shares
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o);
   if (lane == 0) sh.red[wv] = acc;
@@ -267,10 +303,10 @@ __device__ __forceinline__ void mrstft_frames(const MrArgs& a, MrShared<256 << R
 
 // One launch per resolution, so that each gets the LDS and registers of its
 // own transform size (and the occupancy they allow).
-template <int RES>
+template <int RES, int MODE>
 __global__ void __launch_bounds__(kMrThreads) mrstft_frames_kernel(const MrArgs a) {
   __shared__ MrShared<256 << RES> sh;
-  mrstft_frames<RES>(a, sh, blockIdx.y, a.chunk_base[RES] + (int)blockIdx.x);
+  mrstft_frames<RES, MODE>(a, sh, blockIdx.y, a.chunk_base[RES] + (int)blockIdx.x);
 }
 
 // Log-mel features by FFT, one workgroup of 4 wavefronts per voice: frames
@@ -535,9 +571,10 @@ __global__ void __launch_bounds__(256) mrstft_combine_kernel(const MrArgs a) {
   }
 }
 
-void plan(int64_t batch, int64_t n_samples, MrArgs& a, size_t& partial_bytes, size_t& wgrad_floats) {
+void plan(int64_t batch, int64_t n_samples, MrArgs& a, size_t& partial_bytes, size_t& wgrad_floats,
+          size_t* tlog_floats = nullptr) {
   int cb = 0;
-  int64_t wb = 0;
+  int64_t wb = 0, tb = 0;
   for (int r = 0; r < 3; ++r) {
     const int n = 512 << r;
     const int64_t F = n_samples < n ? 0 : (n_samples - n) / (n / 4) + 1;
@@ -546,8 +583,11 @@ void plan(int64_t batch, int64_t n_samples, MrArgs& a, size_t& partial_bytes, si
     cb += (int)((F + kFramesPerBlock - 1) / kFramesPerBlock);
     a.wbase[r] = wb;
     wb += batch * ((F + kFramesPerBlock - 1) / kFramesPerBlock) * kSegHops * (n / 4);
+    a.tbase[r] = tb;
+    tb += batch * F * (n / 2 + 1);
     a.scale[r] = F > 0 ? 1.0 / ((double)F * (double)(n / 2 + 1)) : 0.0;
   }
+  if (tlog_floats) *tlog_floats = (size_t)tb;
   a.chunk_base[3] = cb;
   partial_bytes = (size_t)batch * (size_t)(cb > 0 ? cb : 1) * sizeof(double);
   wgrad_floats = (size_t)wb;
@@ -573,15 +613,58 @@ size_t mrstft_workspace_bytes(int64_t batch, int64_t n_samples, bool with_grad) 
   return pb + (with_grad ? wf * sizeof(float) : 0);
 }
 
-hipError_t launch_mrstft(const float* x, const float* target, int64_t batch, int64_t n_samples,
-                         double* loss, float* grad, void* workspace, hipStream_t s) {
+namespace {
+template <int MODE>
+void launch_frames(const MrArgs& a, hipStream_t s) {
+  const int nch[3] = {a.chunk_base[1] - a.chunk_base[0], a.chunk_base[2] - a.chunk_base[1],
+                      a.chunk_base[3] - a.chunk_base[2]};
+  const unsigned B = (unsigned)a.batch;
+  if (nch[0] > 0)
+    hipLaunchKernelGGL((mrstft_frames_kernel<0, MODE>), dim3((unsigned)nch[0], B), dim3(kMrThreads),
+                       0, s, a);
+  if (nch[1] > 0)
+    hipLaunchKernelGGL((mrstft_frames_kernel<1, MODE>), dim3((unsigned)nch[1], B), dim3(kMrThreads),
+                       0, s, a);
+  if (nch[2] > 0)
+    hipLaunchKernelGGL((mrstft_frames_kernel<2, MODE>), dim3((unsigned)nch[2], B), dim3(kMrThreads),
+                       0, s, a);
+}
+}  // namespace
+
+size_t mrstft_target_bytes(int64_t batch, int64_t n_samples) {
+  MrArgs a = {};
+  size_t pb, wf, tf;
+  plan(batch, n_samples, a, pb, wf, &tf);
+  return tf * sizeof(float);
+}
+
+hipError_t launch_mrstft_target(const float* target, int64_t batch, int64_t n_samples, float* tlog,
+                                hipStream_t s) {
+  if (batch == 0) return hipSuccess;
+  if (batch > 65535) return hipErrorInvalidValue;
+  MrArgs a = {};
+  size_t pb, wf;
+  plan(batch, n_samples, a, pb, wf);
+  a.t = target;
+  a.x = target;
+  a.n = n_samples;
+  a.batch = batch;
+  a.tlog = tlog;
+  launch_frames<1>(a, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_mrstft(const float* x, const float* target, const float* tlog, int64_t batch,
+                         int64_t n_samples, double* loss, float* grad, void* workspace,
+                         hipStream_t s) {
   if (batch == 0) return hipSuccess;
   MrArgs a = {};
   size_t pb, wf;
   plan(batch, n_samples, a, pb, wf);
   pb = (pb + 255) & ~(size_t)255;
   a.x = x;
-  a.t = target;
+  a.t = target ? target : x;
+  a.tlog = const_cast<float*>(tlog);
   a.n = n_samples;
   a.batch = batch;
   a.partial = reinterpret_cast<double*>(workspace);
@@ -589,17 +672,10 @@ hipError_t launch_mrstft(const float* x, const float* target, int64_t batch, int
   a.grad = grad;
   a.loss = loss;
   if (batch > 65535) return hipErrorInvalidValue;
-  const int nch[3] = {a.chunk_base[1] - a.chunk_base[0], a.chunk_base[2] - a.chunk_base[1],
-                      a.chunk_base[3] - a.chunk_base[2]};
-  if (nch[0] > 0)
-    hipLaunchKernelGGL(mrstft_frames_kernel<0>, dim3((unsigned)nch[0], (unsigned)batch),
-                       dim3(kMrThreads), 0, s, a);
-  if (nch[1] > 0)
-    hipLaunchKernelGGL(mrstft_frames_kernel<1>, dim3((unsigned)nch[1], (unsigned)batch),
-                       dim3(kMrThreads), 0, s, a);
-  if (nch[2] > 0)
-    hipLaunchKernelGGL(mrstft_frames_kernel<2>, dim3((unsigned)nch[2], (unsigned)batch),
-                       dim3(kMrThreads), 0, s, a);
+  if (tlog)
+    launch_frames<2>(a, s);
+  else
+    launch_frames<0>(a, s);
   if (a.chunk_base[3] > 0) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

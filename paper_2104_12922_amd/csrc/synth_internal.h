@@ -136,7 +136,13 @@ hipError_t launch_logmel_fft(const float* audio, const int64_t* offsets, int64_t
                              int64_t batch, const void* mel_basis, int64_t ldm, float* features,
                              hipStream_t s);
 size_t mrstft_workspace_bytes(int64_t batch, int64_t n_samples, bool with_grad);
-hipError_t launch_mrstft(const float* x, const float* target, int64_t batch, int64_t n_samples,
-                         double* loss, float* grad, void* workspace, hipStream_t s);
+// tlog: NULL (target frames transformed every call) or the target's log
+// magnitudes from launch_mrstft_target (target then unused).
+hipError_t launch_mrstft(const float* x, const float* target, const float* tlog, int64_t batch,
+                         int64_t n_samples, double* loss, float* grad, void* workspace,
+                         hipStream_t s);
+size_t mrstft_target_bytes(int64_t batch, int64_t n_samples);
+hipError_t launch_mrstft_target(const float* target, int64_t batch, int64_t n_samples, float* tlog,
+                                hipStream_t s);
 
 }  // namespace synth

@@ -28,8 +28,9 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from . import (NUM_PARAMS, synth_mrstft_loss, synth_mrstft_workspace, synth_render,
-               synth_render_backward, synth_render_backward_workspace, synth_sample_params)
+from . import (NUM_PARAMS, synth_mrstft_loss, synth_mrstft_target, synth_mrstft_workspace,
+               synth_render, synth_render_backward, synth_render_backward_workspace,
+               synth_sample_params)
 from . import learned as Lr
 
 F32, F64 = torch.float32, torch.float64
@@ -64,15 +65,16 @@ def gradient_match(targets: torch.Tensor, voice_ids: torch.Tensor, nebula_table,
     gp = torch.empty(T, NUM_PARAMS, dtype=F32, device=dev)
     ws = None
     ws_loss = synth_mrstft_workspace(T, N, grad=steps > 0)
+    tc = synth_mrstft_target(targets)          # target spectra, once per match
     gx = torch.empty(T, N, dtype=F32, device=dev) if steps > 0 else None
     curve = []
     for s in range(steps + 1):
         synth_render(u, nebula_table, n_samples=N, voice_ids=voice_ids, noise_seed=noise_seed, out=x)
         last = s == steps
         if last:
-            loss = synth_mrstft_loss(x, targets, workspace=ws_loss)
+            loss = synth_mrstft_loss(x, tc, workspace=ws_loss)
         else:
-            loss, gx = synth_mrstft_loss(x, targets, grad=True, workspace=ws_loss, out_grad=gx)
+            loss, gx = synth_mrstft_loss(x, tc, grad=True, workspace=ws_loss, out_grad=gx)
         Lr.best_update(loss, T, 1, 1, 0, best, best_step, col_base=s, params=u, best_params=best_u)
         if record_curve:
             curve.append(best.mean())
@@ -99,12 +101,13 @@ def random_search(targets: torch.Tensor, voice_ids: torch.Tensor, nebula_table, 
     x = torch.empty(T, N, dtype=F32, device=dev)
     base = voice_ids.to(torch.int64) * budget
     ws_loss = synth_mrstft_workspace(T, N)
+    tc = synth_mrstft_target(targets)
     curve = {}
     for k in range(budget):
         cid = base + k
         u = synth_sample_params(seed, voice_ids=cid)
         synth_render(u, nebula_table, n_samples=N, voice_ids=voice_ids, noise_seed=noise_seed, out=x)
-        loss = synth_mrstft_loss(x, targets, workspace=ws_loss)
+        loss = synth_mrstft_loss(x, tc, workspace=ws_loss)
         Lr.best_update(loss, T, 1, 1, 0, best, best_k, col_base=k, params=u, best_params=best_u)
         if (k + 1) in record_at:
             curve[k + 1] = float(best.mean())

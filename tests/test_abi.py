@@ -129,6 +129,20 @@ def test_mrstft_argument_checks_before_launch():
     assert call(B=0) == 0
     assert call(nbytes=16) == -2                   # SYNTH_ENOMEM
 
+    def cached(B=2, n=4096, x=fake, t=fake, loss=fake, ws=fake, nbytes=1 << 40):
+        return L.synth_mrstft_loss_cached(x, t, B, n, loss, None, ws, nbytes, None)
+    assert cached(B=-1) == EINVAL
+    assert cached(t=None) == EINVAL
+    assert cached(ws=odd) == EINVAL
+    assert cached(B=65536) == EUNSUP
+    assert cached(nbytes=16) == -2
+    need = L.synth_mrstft_target_bytes(2, 4096)
+    assert need > 0 and L.synth_mrstft_target_bytes(2, 300) == 0   # no frame fits
+    assert L.synth_mrstft_target(fake, 2, 4096, fake, need - 1, None) == -2
+    assert L.synth_mrstft_target(None, 2, 4096, fake, need, None) == EINVAL
+    assert L.synth_mrstft_target(fake, 65536, 4096, fake, 1 << 40, None) == EUNSUP
+    assert L.synth_mrstft_target(fake, 2, 300, None, 0, None) == 0
+
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_native, "LIB_PATH", str(tmp_path / "missing.so"))

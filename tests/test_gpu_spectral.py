@@ -118,3 +118,22 @@ def test_mrstft_gradient_batch_b256_4s_sampled(synth):
     assert bool(torch.isfinite(loss).all()) and bool(torch.isfinite(g).all())
     pick = [0, 77, 128, 255]
     check(synth, x[pick].cpu(), t[pick].cpu())
+
+
+@pytest.mark.parametrize("B,N", [(3, 300), (3, 600), (5, 5000), (4, 44100), (256, 176400)])
+def test_mrstft_cached_target_is_bitwise_uncached(synth, B, N):
+    """Target spectra computed once (synth_mrstft_target) give bitwise the loss
+    and gradient of the uncached call, for two different renders against the
+    same cached target, with and without a gradient."""
+    x = renders(7, B, N).cuda() if B <= 8 else torch.randn(B, N).cuda() * 0.3
+    x2 = renders(8, B, N).cuda() if B <= 8 else torch.randn(B, N).cuda() * 0.3
+    t = renders(9, B, N).cuda() if B <= 8 else torch.randn(B, N).cuda() * 0.3
+    tc = synth.synth_mrstft_target(t)
+    for xi in (x, x2):
+        l0, g0 = synth.synth_mrstft_loss(xi, t, grad=True)
+        l1, g1 = synth.synth_mrstft_loss(xi, tc, grad=True)
+        l2 = synth.synth_mrstft_loss(xi, tc)
+        torch.cuda.synchronize()
+        assert torch.equal(l0, l1) and torch.equal(g0, g1) and torch.equal(l0, l2)
+    lt = synth.synth_mrstft_loss(t, tc)
+    assert float(lt.abs().max()) == 0.0
