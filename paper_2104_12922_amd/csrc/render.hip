@@ -123,7 +123,9 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
     if (c < c_lo) continue;                      // slice starts later: only carries needed
 
     const float a10 = (float)(L1 * y[1]), a1d = (float)(L1 * (yn[1] - y[1]) / qd);
-    const float a20 = (float)(L2 * y[3]), a2d = (float)(L2 * (yn[3] - y[3]) / qd);
+    // VCO 2's VCA ramp carries the square-saw gain (1 - shape / 2)
+    const float a20 = (float)(L2 * y[3]) * sq_gain;
+    const float a2d = (float)(L2 * (yn[3] - y[3]) / qd) * sq_gain;
     __syncthreads();                             // previous chunk's readers of namp are done
     if (lane < kSegsPerChunk)                    // noise VCA ramp, pre-scaled by the 2^-15 of the noise map
       sh.namp[lane] = make_float2((float)(L3 * y[4]) * (1.0f / 32768.0f),
@@ -166,7 +168,7 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
       asm volatile("" ::"v"(A10), "v"(A1d), "v"(A20), "v"(A2d));
       for (int k = 0; k < h; ++k) {
         const float x1 = sin_cycles_run(t1);
-        const float x2 = squaresaw(t2, K2, shape, sq_gain);
+        const float x2 = squaresaw_shape(t2, K2, shape);   // gain (1 - s/2) is in A2
         const float A1 = fmaf(kf, A1d, A10);
         const float A2 = fmaf(kf, A2d, A20);
         trow[k] = fmaf(A2, x2, A1 * x1);

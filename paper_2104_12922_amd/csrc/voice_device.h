@@ -19,9 +19,88 @@ constexpr double kLn2 = 0.693147180559945309417232121458;
 // ---------------------------------------------------------------------------
 // float64 control-rate helpers
 // ---------------------------------------------------------------------------
-// x^e for x in [0, 1] (0^e = 0, 1^e = 1 without evaluating exp2/log2).
+// 2^y in float64: y = n + f with n = rint(y), |f| <= 1/2, and
+// 2^f = exp(f ln 2) by its Taylor series to degree 13 (|f ln 2| < 0.35:
+// truncation below 2e-16 relative), scaled by 2^n.  y is clamped to
+// [-1100, 1023] (below -1075 the result is 0).
+__device__ __forceinline__ double exp2_f64(double y) {
+  y = fmin(fmax(y, -1100.0), 1023.0);
+  const double n = rint(y);
+  const double z = (y - n) * kLn2;            // y - n is exact
+  double p = 1.0 / 6227020800.0;              // 1/13!
+  p = fma(p, z, 1.0 / 479001600.0);
+  p = fma(p, z, 1.0 / 39916800.0);
+  p = fma(p, z, 1.0 / 3628800.0);
+  p = fma(p, z, 1.0 / 362880.0);
+  p = fma(p, z, 1.0 / 40320.0);
+  p = fma(p, z, 1.0 / 5040.0);
+  p = fma(p, z, 1.0 / 720.0);
+  p = fma(p, z, 1.0 / 120.0);
+  p = fma(p, z, 1.0 / 24.0);
+  p = fma(p, z, 1.0 / 6.0);
+  p = fma(p, z, 0.5);
+  p = fma(p, z, 1.0);
+  p = fma(p, z, 1.0);
+  return ldexp(p, (int)n);
+}
+
+// log2(x) for finite x > 0 in float64: x = m 2^e with m in [sqrt(1/2),
+// sqrt(2)), ln m = 2 atanh(t) with t = (m - 1) / (m + 1), |t| < 0.172, by the
+// odd series 2 (t + t^3/3 + ... + t^17/17) (truncation below 1e-15 relative).
+// 1 / (m + 1) is the hardware reciprocal refined by two Newton steps.
+__device__ __forceinline__ double log2_f64(double x) {
+  int e;
+  double m = frexp(x, &e);                    // m in [1/2, 1)
+  if (m < 0.70710678118654752) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double d = m + 1.0;
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  r = fma(fma(-d, r, 1.0), r, r);
+  const double t = (m - 1.0) * r;
+  const double t2 = t * t;
+  double p = 1.0 / 17.0;
+  p = fma(p, t2, 1.0 / 15.0);
+  p = fma(p, t2, 1.0 / 13.0);
+  p = fma(p, t2, 1.0 / 11.0);
+  p = fma(p, t2, 1.0 / 9.0);
+  p = fma(p, t2, 1.0 / 7.0);
+  p = fma(p, t2, 1.0 / 5.0);
+  p = fma(p, t2, 1.0 / 3.0);
+  p = fma(p, t2, 1.0);
+  return fma(2.0 * t * p, 1.0 / kLn2, (double)e);
+}
+
+// sin(2 pi p) in float64 for a phase p in cycles: r = p - rint(p) in
+// [-1/2, 1/2] (exact), folded to |r| <= 1/4 by sin(pi - a) = sin(a), then the
+// Taylor series of sin(2 pi r) to degree 23 (|2 pi r| <= pi/2: truncation
+// below 1e-20).
+__device__ __forceinline__ double sin_cycles_f64(double p) {
+  double r = p - rint(p);
+  if (r > 0.25) r = 0.5 - r;
+  if (r < -0.25) r = -0.5 - r;
+  const double a = r * kTwoPi, a2 = a * a;
+  double s = -1.0 / 25852016738884976640000.0;      // -1/23!
+  s = fma(s, a2, 1.0 / 51090942171709440000.0);     // 1/21!
+  s = fma(s, a2, -1.0 / 121645100408832000.0);
+  s = fma(s, a2, 1.0 / 355687428096000.0);
+  s = fma(s, a2, -1.0 / 1307674368000.0);
+  s = fma(s, a2, 1.0 / 6227020800.0);
+  s = fma(s, a2, -1.0 / 39916800.0);
+  s = fma(s, a2, 1.0 / 362880.0);
+  s = fma(s, a2, -1.0 / 5040.0);
+  s = fma(s, a2, 1.0 / 120.0);
+  s = fma(s, a2, -1.0 / 6.0);
+  s = fma(s, a2, 1.0);
+  return s * a;
+}
+
+// x^e for x in [0, 1] (0^e = 0, 1^e = 1 without evaluating exp2/log2); in
+// (0, 1) within about 1e-13 relative of the correctly rounded power.
 __device__ __forceinline__ double pow01(double x, double e) {
-  return x <= 0.0 ? 0.0 : (x >= 1.0 ? 1.0 : exp2(e * log2(x)));
+  return x <= 0.0 ? 0.0 : (x >= 1.0 ? 1.0 : exp2_f64(e * log2_f64(x)));
 }
 
 // clamp((j - start) / len, 0, 1); len == 0 is the step [j >= start].
@@ -92,16 +171,30 @@ __device__ __forceinline__ float tanh_from_log2(float z2) {
   return fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
 }
 
-// Square-saw: (1 - s/2) tanh(K sin 2 pi th) (1 + s cos 2 pi th); K2 = 2 log2(e) K.
-__device__ __forceinline__ float squaresaw(double th, float K2, float shape, float gain) {
+// Square-saw without its gain (1 - s/2), which the caller folds into the
+// VCA: tanh(K sin 2 pi th) (1 + s cos 2 pi th); K2 = 2 log2(e) K.
+__device__ __forceinline__ float squaresaw_shape(double th, float K2, float shape) {
   float s, c;
   sincos_cycles(th, s, c);
-  return gain * tanh_from_log2(K2 * s) * fmaf(shape, c, 1.0f);
+  return tanh_from_log2(K2 * s) * fmaf(shape, c, 1.0f);
 }
 
-// expm1(x) in float64: Taylor series for |x| <= 1/4 (terms to x^15, relative
-// truncation < 1e-19), the library routine otherwise.
+// expm1(x) in float64: Taylor series to x^8 for |x| <= 1/64 (relative
+// truncation < 1e-19; the usual case, a pitch glide of under a semitone per
+// control sample), to x^15 for |x| <= 1/4 (< 1e-19), the library routine
+// otherwise.
 __device__ __forceinline__ double expm1_f64(double x) {
+  if (fabs(x) <= 0.015625) {
+    double p = 1.0 / 40320.0;                // 1/8!
+    p = fma(p, x, 1.0 / 5040.0);
+    p = fma(p, x, 1.0 / 720.0);
+    p = fma(p, x, 1.0 / 120.0);
+    p = fma(p, x, 1.0 / 24.0);
+    p = fma(p, x, 1.0 / 6.0);
+    p = fma(p, x, 0.5);
+    p = fma(p, x, 1.0);
+    return p * x;
+  }
   if (fabs(x) > 0.25) return expm1(x);
   double p = 1.0 / 1307674368000.0;          // 1/15!
   p = fma(p, x, 1.0 / 87178291200.0);
@@ -249,7 +342,7 @@ __device__ inline void control_stage(const RenderArgs& a, VoiceShared& sh, doubl
       if (lane == 0) tl[i] = s62;
     }
     const double ph = th - floor(th);
-    const double num = v[pb + 3] * ((1.0 + sinpi(2.0 * ph)) / 2.0) +
+    const double num = v[pb + 3] * ((1.0 + sin_cycles_f64(ph)) / 2.0) +
                        v[pb + 4] * (1.0 - fabs(2.0 * ph - 1.0)) + v[pb + 5] * ph +
                        v[pb + 6] * (1.0 - ph) + v[pb + 7] * (ph < 0.5 ? 1.0 : 0.0);
     envs[(6 + i) * kWave + lane] = (num * dv[kLfoInvW + i]) * envs[(3 + 2 * i) * kWave + lane];
@@ -281,7 +374,7 @@ __device__ inline void control_stage(const RenderArgs& a, VoiceShared& sh, doubl
     const double base = midi + v[tb];
     const double m0 = base + v[tb + 1] * ya;
     const double m1 = base + v[tb + 1] * yb;
-    const double i0 = 440.0 * exp2((m0 - 69.0) / 12.0) / sr;
+    const double i0 = 440.0 * exp2_f64((m0 - 69.0) * (1.0 / 12.0)) / sr;
     const double Lr = (m1 - m0) * (kLn2 / (12.0 * qd));   // log of the per-sample ratio
     const double e1 = expm1_f64(Lr);
     const double eh = expm1_f64(Lr * hd);
