@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 # from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB; the
 # factors make each counter read 1 GiB for a plain 1 GiB device copy).  Valid
 # only for the kernel sources with this digest; reported as null otherwise.
-RENDER_TRAFFIC = {"sources_sha256_16": "9f74e8c86487dcd2",
-                  "fetch_bytes": 10695885, "write_bytes": 6758482202, "valu_busy": 0.93}
+RENDER_TRAFFIC = {"sources_sha256_16": "45cd108222b69c06",
+                  "fetch_bytes": 10745190, "write_bytes": 6759242650, "valu_busy": 0.89}
 RENDER_SOURCES = ("render.hip", "voice_device.h", "philox.h")
 
 
