@@ -160,9 +160,11 @@ int synth_render_plan_ws(const synth_config* cfg, const float* params, const uin
 
 /* Workspace (bytes of device memory) that synth_render_backward needs for a
  * batch of uniform-length voices: batch * (ceil(n_samples / q) * 21 +
- * chunks * 4) doubles (per-segment sums, then the chunk-start phase carries
- * of voices split over workgroups; chunks = ceil(ceil(n_samples / q) / 62)).
- * Returns 0 for an invalid cfg. */
+ * chunks * 88) doubles (per-segment sums; the chunk-start phase carries of
+ * voices split over workgroups; per-chunk totals of the chunk-parallel
+ * control-rate adjoint: 4 sums, 2 LFO phase adjoints, 78 parameter
+ * adjoints; chunks = ceil(ceil(n_samples / q) / 62)).  Returns 0 for an
+ * invalid cfg. */
 size_t synth_render_backward_workspace(const synth_config* cfg, int64_t batch, int64_t n_samples);
 
 /* Adjoint of synth_render (uniform lengths): grad_params[i][p] =
@@ -176,8 +178,9 @@ size_t synth_render_backward_workspace(const synth_config* cfg, int64_t batch, i
  *   workspace    dev buffer of >= synth_render_backward_workspace() bytes,
  *                caller-owned, contents clobbered.
  * Returns SYNTH_EUNSUPPORTED for mix_mode 1, for nebulas whose pitch can exceed
- * sample_rate / 2, and for voices longer than 512 * 62 control samples;
- * SYNTH_ENOMEM if workspace_bytes is too small. */
+ * sample_rate / 2, for voices longer than 512 * 62 control samples and for
+ * batch * chunks > 2^31 - 1; SYNTH_ENOMEM if workspace_bytes is too small.
+ * Bitwise deterministic. */
 int synth_render_backward(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
                           uint64_t first_g, int64_t batch, int64_t n_samples,
                           const float* grad_audio, float* grad_params, void* workspace,

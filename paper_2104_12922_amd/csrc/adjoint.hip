@@ -273,15 +273,10 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
   }
 }
 
-// d(human value) accumulators: one column per lane, summed in lane order at the end.
-struct AdjShared {
-  VoiceShared vs;
-  double gacc[kNumParams][kWave];
-  double lfo_carry[512][2];          // LFO phase (cycles) at each chunk's first owned point
-};
-
-__device__ __forceinline__ void gadd(AdjShared& S, int p, int lane, double x) {
-  S.gacc[p][lane] += x;
+// Adds x to lane's accumulator of parameter p (gradient pass only).
+template <bool G>
+__device__ __forceinline__ void gadd(double (*g)[kWave], int p, int lane, double x) {
+  if constexpr (G) g[p][lane] += x;
 }
 
 // Reverse exclusive scan over lanes: sum of x over lanes l' > l.
@@ -336,279 +331,375 @@ __device__ __forceinline__ bool ramp_live(double jd, double s, double L, double 
   return r >= 0.0 && r <= 1.0;
 }
 
-__global__ void __launch_bounds__(kWave) adjoint_control_kernel(const RenderArgs a,
-                                                                const double* __restrict__ red,
-                                                                float* __restrict__ grad_params) {
-  __shared__ AdjShared S;
-  const int lane = threadIdx.x;
-  const int64_t b = blockIdx.x;
-  const int q = a.q;
-  const int64_t N = a.n_uniform;
-  const int64_t J = (N + q - 1) / q;
-  const double* rv = red + b * J * kNumRed;
+// Control-rate adjoint of chunk c of a voice: control samples j = 62c ..
+// 62c + 61 on lanes 1..62 (lane l <-> j = 62c - 1 + l); lane 0 carries
+// segment 62c - 1, whose right-end adjoint lands on lane 1.  The chunk needs
+// from the others only Gend1/2 (the phase adjoints D of all later segments),
+// lc (both LFO phases at control sample 62c) and, for the parameter
+// adjoints, Lsuf (both LFOs' phase adjoints summed over all later control
+// samples).  dph_tot receives this chunk's LFO phase-adjoint sums; with GRADS
+// the chunk's parameter adjoints are added to gacc[p][lane].
+template <bool GRADS>
+__device__ __forceinline__ void control_chunk(const RenderArgs& a, const VoiceShared& vs,
+                                              double (*gacc)[kWave], const double* rv, int64_t c,
+                                              int64_t J, int lane, double Gend1, double Gend2,
+                                              const double* lc, const double* Lsuf,
+                                              double* dph_tot) {
+  const double* v = vs.v;
+  const double* dv = vs.d;
   const double rc = a.rc;
   const double kPitch = kLn2 / 12.0;
-
-  voice_setup(a, b, S.vs, lane);
-  const double* v = S.vs.v;
-  const double* dv = S.vs.d;
-  for (int p = 0; p < kNumParams; ++p) S.gacc[p][lane] = 0.0;
   const double note_off = v[1] * rc;
-  // chunk c owns control samples j = 62c .. 62c+61 on lanes 1..62 (lane l <->
-  // j = 62c - 1 + l); lane 0 carries segment 62c - 1, whose right-end
-  // adjoint lands on lane 1.
-  const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
   const bool owned_lane = lane >= 1 && lane <= kSegsPerChunk;
+  const int64_t j = c * kSegsPerChunk - 1 + lane;
+  const double jd = (double)j;
+  const bool inr = j >= 0 && j < J;
+  const bool own = owned_lane && inr;
+  double R[kNumRed];
+#pragma unroll
+  for (int r = 0; r < kNumRed; ++r) R[r] = inr ? rv[j * kNumRed + r] : 0.0;
+  // segment phase adjoints: later segments of this chunk + those of later chunks
+  const double D1 = own ? R[kRD1] : 0.0, D2 = own ? R[kRD2] : 0.0;
+  const double Ge1 = Gend1 + wave_rev_excl_scan(D1, lane);
+  const double Ge2 = Gend2 + wave_rev_excl_scan(D2, lane);
+  // lane 0 (segment 62c - 1) needs the sum over all of this chunk's segments.
+  // The shuffles run on every lane: a cross-lane read from a lane that is
+  // masked off by a branch returns no data.
+  const double ge1_1 = __shfl(Ge1, 1), d1_1 = __shfl(D1, 1);
+  const double ge2_1 = __shfl(Ge2, 1), d2_1 = __shfl(D2, 1);
+  const double G1 = lane == 0 ? ge1_1 + d1_1 : Ge1;
+  const double G2 = lane == 0 ? ge2_1 + d2_1 : Ge2;
+  const double B01 = (G1 + R[kRD1]) * R[kRC01] - R[kRE01];
+  const double B11 = (G1 + R[kRD1]) * R[kRC11] - R[kRE11];
+  const double B02 = (G2 + R[kRD2]) * R[kRC02] - R[kRE02];
+  const double B12 = (G2 + R[kRD2]) * R[kRC12] - R[kRE12];
+  // right-end contributions come from the previous segment (lane - 1)
+  const double pB11 = __shfl_up(B11, 1), pB12 = __shfl_up(B12, 1);
+  const double pA11 = __shfl_up(R[kRA11], 1), pA13 = __shfl_up(R[kRA13], 1);
+  const double pA14 = __shfl_up(R[kRA14], 1);
+  const bool lastj = (j == J - 1);
 
-  // ---- forward: LFO phase at every chunk's first owned control sample ----
-  double lc[2] = {S.vs.carry[0], S.vs.carry[1]};
-  for (int64_t c = 0; c < nchunks; ++c) {
-    const int64_t j = c * kSegsPerChunk - 1 + lane;
-    const double jd = (double)j;
-    if (lane == 0) {
-      S.lfo_carry[c][0] = lc[0];
-      S.lfo_carry[c][1] = lc[1];
-    }
+  // forward recompute at control sample j
+  EnvEval E[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) E[k] = env_eval(dv, k, jd, note_off);
+  double ph[2], shp[2][5], lfo[2], fpre[2];
+  {
+    // LFO phase: carry at the chunk's first owned sample + exclusive scan
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int pb = 32 + 8 * i;
-      const EnvEval Er = env_eval(dv, 2 + 2 * i, jd, note_off);
-      const double f = fmax(0.0, v[pb] + v[pb + 1] * Er.env);
-      const double inc = owned_lane && j < J ? f / rc : 0.0;
-      double s = inc;
+      fpre[i] = v[pb] + v[pb + 1] * E[2 + 2 * i].env;
+      const double inc = owned_lane ? fmax(0.0, fpre[i]) / rc : 0.0;
+      double incl = inc;
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) {
+        const double t = __shfl_up(incl, d);
+        if (lane >= d) incl += t;
+      }
+      const double th = lc[i] + (incl - inc);
+      const double p = th - floor(th);
+      ph[i] = p;
+      shp[i][0] = (1.0 + sinpi(2.0 * p)) / 2.0;
+      shp[i][1] = 1.0 - fabs(2.0 * p - 1.0);
+      shp[i][2] = p;
+      shp[i][3] = 1.0 - p;
+      shp[i][4] = p < 0.5 ? 1.0 : 0.0;
+      const double num = v[pb + 3] * shp[i][0] + v[pb + 4] * shp[i][1] + v[pb + 5] * shp[i][2] +
+                         v[pb + 6] * shp[i][3] + v[pb + 7] * shp[i][4];
+      lfo[i] = num * dv[kLfoInvW + i];
+    }
+  }
+  const double x[4] = {E[0].env, E[1].env, lfo[0] * E[3].env, lfo[1] * E[5].env};
+  double y[5];
+#pragma unroll
+  for (int o = 0; o < 5; ++o) {
+    const int pb = 48 + 4 * o;
+    y[o] = (v[pb] * x[0] + v[pb + 1] * x[1] + v[pb + 2] * x[2] + v[pb + 3] * x[3]) *
+           dv[kMixInvNorm + o];
+  }
+  double yn_p[2];
+  {
+    const double t0 = __shfl_down(y[0], 1), t2 = __shfl_down(y[2], 1);
+    yn_p[0] = lastj ? y[0] : t0;
+    yn_p[1] = lastj ? y[2] : t2;
+  }
+
+  // dy_o(j): transposed upsampling of the segment adjoints
+  double dy[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (own) {
+    const double b1 = B01 + (lane >= 1 ? pB11 : 0.0) + (lastj ? B11 : 0.0);
+    const double b2 = B02 + (lane >= 1 ? pB12 : 0.0) + (lastj ? B12 : 0.0);
+    dy[0] = v[69] * kPitch * b1;
+    dy[2] = v[72] * kPitch * b2;
+    dy[1] = R[kRA01] + pA11 + (lastj ? R[kRA11] : 0.0);
+    dy[3] = R[kRA03] + pA13 + (lastj ? R[kRA13] : 0.0);
+    dy[4] = R[kRA04] + pA14 + (lastj ? R[kRA14] : 0.0);
+    // pitch, phase, level, shape and K contributions of segment j
+    const double m1 = kPitch * (B01 + B11), m2 = kPitch * (B02 + B12);
+    gadd<GRADS>(gacc, 0, lane, m1 + m2);
+    gadd<GRADS>(gacc, 68, lane, m1);
+    gadd<GRADS>(gacc, 71, lane, m2);
+    gadd<GRADS>(gacc, 69, lane, kPitch * (y[0] * B01 + yn_p[0] * B11));
+    gadd<GRADS>(gacc, 72, lane, kPitch * (y[2] * B02 + yn_p[1] * B12));
+    gadd<GRADS>(gacc, 70, lane, R[kRD1] / kTwoPi);
+    gadd<GRADS>(gacc, 73, lane, R[kRD2] / kTwoPi);
+    gadd<GRADS>(gacc, 75, lane, R[kRL1]);
+    gadd<GRADS>(gacc, 76, lane, R[kRL2]);
+    gadd<GRADS>(gacc, 77, lane, R[kRL3]);
+    gadd<GRADS>(gacc, 74, lane, R[kRShape]);
+  }
+  // the square-saw gain K = 12000 / (f_hi log10 f_hi), f_hi from the highest pitch
+  const double dK = own ? R[kRK] : 0.0;
+  if (dK != 0.0) {
+    const double midi = v[0];
+    const double mh = midi + v[71] + fmax(0.0, v[72]);
+    const double m_hi = fmax(0.0, mh);
+    const double fh = 440.0 * exp2((m_hi - 69.0) / 12.0);
+    if (fh <= a.sr / 2.0) {
+      const double Kd = 12000.0 / (fh * log10(fh));
+      const double dKdf = -(Kd / fh) * (1.0 + 1.0 / log(fh));
+      const double dm = dK * dKdf * fh * kPitch;
+      if (mh >= 0.0) {
+        gadd<GRADS>(gacc, 0, lane, dm);
+        gadd<GRADS>(gacc, 71, lane, dm);
+        if (v[72] >= 0.0) gadd<GRADS>(gacc, 72, lane, dm);
+      }
+    }
+  }
+
+  // modulation mixer: y_o = sum_i G_oi x_i / n_o, n_o = max(1, sum_i G_oi)
+  double dx[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int o = 0; o < 5; ++o) {
+    const int pb = 48 + 4 * o;
+    const double inv = dv[kMixInvNorm + o];
+    const bool big = (v[pb] + v[pb + 1] + v[pb + 2] + v[pb + 3]) >= 1.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      dx[i] += v[pb + i] * dy[o] * inv;
+      if (own) gadd<GRADS>(gacc, pb + i, lane, dy[o] * (x[i] - (big ? y[o] : 0.0)) * inv);
+    }
+  }
+  double denv[6] = {dx[0], dx[1], 0.0, 0.0, 0.0, 0.0};
+  // LFOs
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int pb = 32 + 8 * i;
+    const double dl = dx[2 + i] * E[3 + 2 * i].env;
+    denv[3 + 2 * i] += dx[2 + i] * lfo[i];
+    const double invW = dv[kLfoInvW + i];
+    double dph = 0.0;
+    if (invW > 0.0) {
+      const double p = ph[i];
+      const double sd = (p * 2.0 - 1.0) > 0.0 ? 1.0 : ((p * 2.0 - 1.0) < 0.0 ? -1.0 : 0.0);
+      const double der = v[pb + 3] * (0.5 * kTwoPi * cospi(2.0 * p)) + v[pb + 4] * (-2.0 * sd) +
+                         v[pb + 5] - v[pb + 6];
+      dph = own ? dl * der * invW : 0.0;
+      if (own)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) gadd<GRADS>(gacc, pb + 3 + k, lane, dl * (shp[i][k] - lfo[i]) * invW);
+    }
+    // phase: d phi += dph / 2 pi; d inc(k) = sum_{j > k} dph(j)
+    if (own) gadd<GRADS>(gacc, pb + 2, lane, dph / kTwoPi);
+    const double later = Lsuf[i] + wave_rev_excl_scan(dph, lane);
+    {
+      double s = dph;
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-      lc[i] += s;
+      dph_tot[i] = s;
+    }
+    if (own && fpre[i] >= 0.0) {
+      const double df = later / rc;
+      gadd<GRADS>(gacc, pb, lane, df);
+      gadd<GRADS>(gacc, pb + 1, lane, df * E[2 + 2 * i].env);
+      denv[2 + 2 * i] += df * v[pb + 1];
+    }
+  }
+  // ADSRs
+  if (own) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int pb = 2 + 5 * k;
+      const EnvEval& e = E[k];
+      const double de = denv[k];
+      if (de == 0.0) continue;
+      const double A = dv[kEnvA + k], D = dv[kEnvD + k], Rr = dv[kEnvR + k];
+      const double Sus = dv[kEnvS + k], al = dv[kEnvAlpha + k];
+      const double dPa = de * e.M * e.Pr;
+      const double dM = de * e.Pa * e.Pr;
+      const double dPr = de * e.Pa * e.M;
+      gadd<GRADS>(gacc, pb + 2, lane, dM * (1.0 - e.Pd));
+      const double dPd = dM * (1.0 - Sus);
+      double gx, ga, dA = 0.0, dD = 0.0, dR = 0.0, dO = 0.0, dal = 0.0;
+      pow01_grad(e.att, al, e.Pa, gx, ga);
+      dal += dPa * ga;
+      if (ramp_live(jd, 0.0, A, dv[kEnvInvA + k])) dA += dPa * gx * (-jd * dv[kEnvInvA + k] * dv[kEnvInvA + k]);
+      pow01_grad(1.0 - e.dec, al, e.Pd, gx, ga);
+      dal += dPd * ga;
+      if (ramp_live(jd, A, D, dv[kEnvInvD + k])) {
+        const double dd = -dPd * gx;       // d/d dec
+        dA += dd * (-dv[kEnvInvD + k]);
+        dD += dd * (-(jd - A) * dv[kEnvInvD + k] * dv[kEnvInvD + k]);
+      }
+      pow01_grad(1.0 - e.rel, al, e.Pr, gx, ga);
+      dal += dPr * ga;
+      if (ramp_live(jd, note_off, Rr, dv[kEnvInvR + k])) {
+        const double dr = -dPr * gx;       // d/d rel
+        dO += dr * (-dv[kEnvInvR + k]);
+        dR += dr * (-(jd - note_off) * dv[kEnvInvR + k] * dv[kEnvInvR + k]);
+      }
+      gadd<GRADS>(gacc, pb + 0, lane, dA * rc);
+      gadd<GRADS>(gacc, pb + 1, lane, dD * rc);
+      gadd<GRADS>(gacc, pb + 3, lane, dR * rc);
+      gadd<GRADS>(gacc, pb + 4, lane, dal);
+      gadd<GRADS>(gacc, 1, lane, dO * rc);
+    }
+  }
+}
+
+// The control-rate adjoint runs chunk-parallel: one wavefront per (voice,
+// chunk).  The serial dependencies between chunks (LFO phases forward, the
+// phase-adjoint suffix sums backward) go through per-chunk totals stored by
+// earlier passes and combined in the order a single wavefront walking the
+// chunks would combine them, so every chunk sees the same inputs as in such
+// a walk.
+struct CtlArgs {
+  double* sums;      // [batch][chunks][4]: D1, D2 over owned segments; LFO 1, 2 increments
+  double* dph;       // [batch][chunks][2]: LFO 1, 2 phase-adjoint sums
+  double* gpart;     // [batch][chunks][78]: parameter adjoints per chunk (human values)
+  int64_t nchunks;
+};
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// LFO phases at chunk c's first owned control sample and the phase-adjoint
+// sums of all later chunks, from the pass-0 totals (serial order).
+__device__ __forceinline__ void chunk_inputs(const VoiceShared& vs, const double* sums, int64_t c,
+                                             int64_t nchunks, double* lc, double& Gend1,
+                                             double& Gend2) {
+  lc[0] = vs.carry[0];
+  lc[1] = vs.carry[1];
+  for (int64_t k = 0; k < c; ++k) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      lc[i] += sums[k * 4 + 2 + i];
       lc[i] -= floor(lc[i]);
     }
   }
-  __syncthreads();
-
-  // ---- backward over chunks ----
-  double Gend1 = 0.0, Gend2 = 0.0;     // sum of D over all later segments
-  double Lsuf[2] = {0.0, 0.0};         // sum of dtheta_lfo over all later control samples
-  for (int64_t c = nchunks - 1; c >= 0; --c) {
-    const int64_t j = c * kSegsPerChunk - 1 + lane;
-    const double jd = (double)j;
-    const bool inr = j >= 0 && j < J;
-    const bool own = owned_lane && inr;
-    double R[kNumRed];
-#pragma unroll
-    for (int r = 0; r < kNumRed; ++r) R[r] = inr ? rv[j * kNumRed + r] : 0.0;
-    // segment phase adjoints: Gend over later segments of this chunk + carry
-    const double D1 = own ? R[kRD1] : 0.0, D2 = own ? R[kRD2] : 0.0;
-    const double Ge1 = Gend1 + wave_rev_excl_scan(D1, lane);
-    const double Ge2 = Gend2 + wave_rev_excl_scan(D2, lane);
-    // lane 0 (segment 62c - 1) needs the sum over all of this chunk's segments.
-    // The shuffles run on every lane: a cross-lane read from a lane that is
-    // masked off by a branch returns no data.
-    const double ge1_1 = __shfl(Ge1, 1), d1_1 = __shfl(D1, 1);
-    const double ge2_1 = __shfl(Ge2, 1), d2_1 = __shfl(D2, 1);
-    const double G1 = lane == 0 ? ge1_1 + d1_1 : Ge1;
-    const double G2 = lane == 0 ? ge2_1 + d2_1 : Ge2;
-    const double B01 = (G1 + R[kRD1]) * R[kRC01] - R[kRE01];
-    const double B11 = (G1 + R[kRD1]) * R[kRC11] - R[kRE11];
-    const double B02 = (G2 + R[kRD2]) * R[kRC02] - R[kRE02];
-    const double B12 = (G2 + R[kRD2]) * R[kRC12] - R[kRE12];
-    {
-      double s1 = D1, s2 = D2;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        s1 += __shfl_xor(s1, o);
-        s2 += __shfl_xor(s2, o);
-      }
-      Gend1 += s1;
-      Gend2 += s2;
-    }
-    // right-end contributions come from the previous segment (lane - 1)
-    const double pB11 = __shfl_up(B11, 1), pB12 = __shfl_up(B12, 1);
-    const double pA11 = __shfl_up(R[kRA11], 1), pA13 = __shfl_up(R[kRA13], 1);
-    const double pA14 = __shfl_up(R[kRA14], 1);
-    const bool lastj = (j == J - 1);
-
-    // forward recompute at control sample j
-    EnvEval E[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) E[k] = env_eval(dv, k, jd, note_off);
-    double ph[2], shp[2][5], lfo[2], fpre[2];
-    {
-      // LFO phase: carry at the chunk's first owned sample + exclusive scan
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int pb = 32 + 8 * i;
-        fpre[i] = v[pb] + v[pb + 1] * E[2 + 2 * i].env;
-        const double inc = owned_lane ? fmax(0.0, fpre[i]) / rc : 0.0;
-        double incl = inc;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-          const double t = __shfl_up(incl, d);
-          if (lane >= d) incl += t;
-        }
-        const double th = S.lfo_carry[c][i] + (incl - inc);
-        const double p = th - floor(th);
-        ph[i] = p;
-        shp[i][0] = (1.0 + sinpi(2.0 * p)) / 2.0;
-        shp[i][1] = 1.0 - fabs(2.0 * p - 1.0);
-        shp[i][2] = p;
-        shp[i][3] = 1.0 - p;
-        shp[i][4] = p < 0.5 ? 1.0 : 0.0;
-        const double num = v[pb + 3] * shp[i][0] + v[pb + 4] * shp[i][1] + v[pb + 5] * shp[i][2] +
-                           v[pb + 6] * shp[i][3] + v[pb + 7] * shp[i][4];
-        lfo[i] = num * dv[kLfoInvW + i];
-      }
-    }
-    const double x[4] = {E[0].env, E[1].env, lfo[0] * E[3].env, lfo[1] * E[5].env};
-    double y[5];
-#pragma unroll
-    for (int o = 0; o < 5; ++o) {
-      const int pb = 48 + 4 * o;
-      y[o] = (v[pb] * x[0] + v[pb + 1] * x[1] + v[pb + 2] * x[2] + v[pb + 3] * x[3]) *
-             dv[kMixInvNorm + o];
-    }
-    double yn_p[2];
-    {
-      const double t0 = __shfl_down(y[0], 1), t2 = __shfl_down(y[2], 1);
-      yn_p[0] = lastj ? y[0] : t0;
-      yn_p[1] = lastj ? y[2] : t2;
-    }
-
-    // dy_o(j): transposed upsampling of the segment adjoints
-    double dy[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (own) {
-      const double b1 = B01 + (lane >= 1 ? pB11 : 0.0) + (lastj ? B11 : 0.0);
-      const double b2 = B02 + (lane >= 1 ? pB12 : 0.0) + (lastj ? B12 : 0.0);
-      dy[0] = v[69] * kPitch * b1;
-      dy[2] = v[72] * kPitch * b2;
-      dy[1] = R[kRA01] + pA11 + (lastj ? R[kRA11] : 0.0);
-      dy[3] = R[kRA03] + pA13 + (lastj ? R[kRA13] : 0.0);
-      dy[4] = R[kRA04] + pA14 + (lastj ? R[kRA14] : 0.0);
-      // pitch, phase, level, shape and K contributions of segment j
-      const double m1 = kPitch * (B01 + B11), m2 = kPitch * (B02 + B12);
-      gadd(S, 0, lane, m1 + m2);
-      gadd(S, 68, lane, m1);
-      gadd(S, 71, lane, m2);
-      gadd(S, 69, lane, kPitch * (y[0] * B01 + yn_p[0] * B11));
-      gadd(S, 72, lane, kPitch * (y[2] * B02 + yn_p[1] * B12));
-      gadd(S, 70, lane, R[kRD1] / kTwoPi);
-      gadd(S, 73, lane, R[kRD2] / kTwoPi);
-      gadd(S, 75, lane, R[kRL1]);
-      gadd(S, 76, lane, R[kRL2]);
-      gadd(S, 77, lane, R[kRL3]);
-      gadd(S, 74, lane, R[kRShape]);
-    }
-    // the square-saw gain K = 12000 / (f_hi log10 f_hi), f_hi from the highest pitch
-    const double dK = own ? R[kRK] : 0.0;
-    if (dK != 0.0) {
-      const double midi = v[0];
-      const double mh = midi + v[71] + fmax(0.0, v[72]);
-      const double m_hi = fmax(0.0, mh);
-      const double fh = 440.0 * exp2((m_hi - 69.0) / 12.0);
-      if (fh <= a.sr / 2.0) {
-        const double Kd = 12000.0 / (fh * log10(fh));
-        const double dKdf = -(Kd / fh) * (1.0 + 1.0 / log(fh));
-        const double dm = dK * dKdf * fh * kPitch;
-        if (mh >= 0.0) {
-          gadd(S, 0, lane, dm);
-          gadd(S, 71, lane, dm);
-          if (v[72] >= 0.0) gadd(S, 72, lane, dm);
-        }
-      }
-    }
-
-    // modulation mixer: y_o = sum_i G_oi x_i / n_o, n_o = max(1, sum_i G_oi)
-    double dx[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int o = 0; o < 5; ++o) {
-      const int pb = 48 + 4 * o;
-      const double inv = dv[kMixInvNorm + o];
-      const bool big = (v[pb] + v[pb + 1] + v[pb + 2] + v[pb + 3]) >= 1.0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        dx[i] += v[pb + i] * dy[o] * inv;
-        if (own) gadd(S, pb + i, lane, dy[o] * (x[i] - (big ? y[o] : 0.0)) * inv);
-      }
-    }
-    double denv[6] = {dx[0], dx[1], 0.0, 0.0, 0.0, 0.0};
-    // LFOs
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int pb = 32 + 8 * i;
-      const double dl = dx[2 + i] * E[3 + 2 * i].env;
-      denv[3 + 2 * i] += dx[2 + i] * lfo[i];
-      const double invW = dv[kLfoInvW + i];
-      double dph = 0.0;
-      if (invW > 0.0) {
-        const double p = ph[i];
-        const double sd = (p * 2.0 - 1.0) > 0.0 ? 1.0 : ((p * 2.0 - 1.0) < 0.0 ? -1.0 : 0.0);
-        const double der = v[pb + 3] * (0.5 * kTwoPi * cospi(2.0 * p)) + v[pb + 4] * (-2.0 * sd) +
-                           v[pb + 5] - v[pb + 6];
-        dph = own ? dl * der * invW : 0.0;
-        if (own)
-#pragma unroll
-          for (int k = 0; k < 5; ++k) gadd(S, pb + 3 + k, lane, dl * (shp[i][k] - lfo[i]) * invW);
-      }
-      // phase: d phi += dph / 2 pi; d inc(k) = sum_{j > k} dph(j)
-      if (own) gadd(S, pb + 2, lane, dph / kTwoPi);
-      const double later = Lsuf[i] + wave_rev_excl_scan(dph, lane);
-      {
-        double s = dph;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-        Lsuf[i] += s;
-      }
-      if (own && fpre[i] >= 0.0) {
-        const double df = later / rc;
-        gadd(S, pb, lane, df);
-        gadd(S, pb + 1, lane, df * E[2 + 2 * i].env);
-        denv[2 + 2 * i] += df * v[pb + 1];
-      }
-    }
-    // ADSRs
-    if (own) {
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const int pb = 2 + 5 * k;
-        const EnvEval& e = E[k];
-        const double de = denv[k];
-        if (de == 0.0) continue;
-        const double A = dv[kEnvA + k], D = dv[kEnvD + k], Rr = dv[kEnvR + k];
-        const double Sus = dv[kEnvS + k], al = dv[kEnvAlpha + k];
-        const double dPa = de * e.M * e.Pr;
-        const double dM = de * e.Pa * e.Pr;
-        const double dPr = de * e.Pa * e.M;
-        gadd(S, pb + 2, lane, dM * (1.0 - e.Pd));
-        const double dPd = dM * (1.0 - Sus);
-        double gx, ga, dA = 0.0, dD = 0.0, dR = 0.0, dO = 0.0, dal = 0.0;
-        pow01_grad(e.att, al, e.Pa, gx, ga);
-        dal += dPa * ga;
-        if (ramp_live(jd, 0.0, A, dv[kEnvInvA + k])) dA += dPa * gx * (-jd * dv[kEnvInvA + k] * dv[kEnvInvA + k]);
-        pow01_grad(1.0 - e.dec, al, e.Pd, gx, ga);
-        dal += dPd * ga;
-        if (ramp_live(jd, A, D, dv[kEnvInvD + k])) {
-          const double dd = -dPd * gx;       // d/d dec
-          dA += dd * (-dv[kEnvInvD + k]);
-          dD += dd * (-(jd - A) * dv[kEnvInvD + k] * dv[kEnvInvD + k]);
-        }
-        pow01_grad(1.0 - e.rel, al, e.Pr, gx, ga);
-        dal += dPr * ga;
-        if (ramp_live(jd, note_off, Rr, dv[kEnvInvR + k])) {
-          const double dr = -dPr * gx;       // d/d rel
-          dO += dr * (-dv[kEnvInvR + k]);
-          dR += dr * (-(jd - note_off) * dv[kEnvInvR + k] * dv[kEnvInvR + k]);
-        }
-        gadd(S, pb + 0, lane, dA * rc);
-        gadd(S, pb + 1, lane, dD * rc);
-        gadd(S, pb + 3, lane, dR * rc);
-        gadd(S, pb + 4, lane, dal);
-        gadd(S, 1, lane, dO * rc);
-      }
-    }
+  Gend1 = 0.0;
+  Gend2 = 0.0;
+  for (int64_t k = nchunks - 1; k > c; --k) {
+    Gend1 += sums[k * 4];
+    Gend2 += sums[k * 4 + 1];
   }
+}
+
+// Pass 0: per chunk, D1 and D2 summed over its owned segments and both LFO
+// phase increments summed over its owned control samples.
+__global__ void __launch_bounds__(kWave) adjoint_chunk_sums_kernel(const RenderArgs a,
+                                                                   const double* __restrict__ red,
+                                                                   CtlArgs t) {
+  __shared__ VoiceShared vs;
+  const int lane = threadIdx.x;
+  const int64_t b = blockIdx.x / t.nchunks, c = blockIdx.x % t.nchunks;
+  const int64_t J = (a.n_uniform + a.q - 1) / a.q;
+  const double* rv = red + b * J * kNumRed;
+  voice_setup(a, b, vs, lane);
+  const double* v = vs.v;
+  const double* dv = vs.d;
+  const double rc = a.rc;
+  const double note_off = v[1] * rc;
+  const int64_t j = c * kSegsPerChunk - 1 + lane;
+  const bool owned_lane = lane >= 1 && lane <= kSegsPerChunk;
+  const bool own = owned_lane && j < J;            // owned lanes have j >= 0
+  const double s1 = wave_sum(own ? rv[j * kNumRed + kRD1] : 0.0);
+  const double s2 = wave_sum(own ? rv[j * kNumRed + kRD2] : 0.0);
+  double li[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int pb = 32 + 8 * i;
+    const EnvEval Er = env_eval(dv, 2 + 2 * i, (double)j, note_off);
+    const double f = fmax(0.0, v[pb] + v[pb + 1] * Er.env);
+    li[i] = wave_sum(own ? f / rc : 0.0);
+  }
+  if (lane == 0) {
+    double* o = t.sums + (b * t.nchunks + c) * 4;
+    o[0] = s1;
+    o[1] = s2;
+    o[2] = li[0];
+    o[3] = li[1];
+  }
+}
+
+// Pass 1: per chunk, the LFO phase-adjoint sums (they need the chunk's whole
+// forward recompute and mixer adjoint, not its parameter adjoints).
+__global__ void __launch_bounds__(kWave) adjoint_chunk_lfo_kernel(const RenderArgs a,
+                                                                  const double* __restrict__ red,
+                                                                  CtlArgs t) {
+  __shared__ VoiceShared vs;
+  const int lane = threadIdx.x;
+  const int64_t b = blockIdx.x / t.nchunks, c = blockIdx.x % t.nchunks;
+  const int64_t J = (a.n_uniform + a.q - 1) / a.q;
+  voice_setup(a, b, vs, lane);
+  double lc[2], G1, G2;
+  chunk_inputs(vs, t.sums + b * t.nchunks * 4, c, t.nchunks, lc, G1, G2);
+  const double Lsuf[2] = {0.0, 0.0};
+  double tot[2];
+  control_chunk<false>(a, vs, nullptr, red + b * J * kNumRed, c, J, lane, G1, G2, lc, Lsuf, tot);
+  if (lane == 0) {
+    t.dph[(b * t.nchunks + c) * 2] = tot[0];
+    t.dph[(b * t.nchunks + c) * 2 + 1] = tot[1];
+  }
+}
+
+// Pass 2: per chunk, the parameter adjoints (human values), summed over the
+// lanes in lane order.
+struct GradShared {
+  VoiceShared vs;
+  double gacc[kNumParams][kWave];
+};
+
+__global__ void __launch_bounds__(kWave) adjoint_chunk_grad_kernel(const RenderArgs a,
+                                                                   const double* __restrict__ red,
+                                                                   CtlArgs t) {
+  __shared__ GradShared S;
+  const int lane = threadIdx.x;
+  const int64_t b = blockIdx.x / t.nchunks, c = blockIdx.x % t.nchunks;
+  const int64_t J = (a.n_uniform + a.q - 1) / a.q;
+  for (int p = 0; p < kNumParams; ++p) S.gacc[p][lane] = 0.0;
+  voice_setup(a, b, S.vs, lane);
+  double lc[2], G1, G2;
+  chunk_inputs(S.vs, t.sums + b * t.nchunks * 4, c, t.nchunks, lc, G1, G2);
+  double Lsuf[2] = {0.0, 0.0};
+  for (int64_t k = t.nchunks - 1; k > c; --k) {
+    Lsuf[0] += t.dph[(b * t.nchunks + k) * 2];
+    Lsuf[1] += t.dph[(b * t.nchunks + k) * 2 + 1];
+  }
+  double tot[2];
+  control_chunk<true>(a, S.vs, S.gacc, red + b * J * kNumRed, c, J, lane, G1, G2, lc, Lsuf, tot);
   __syncthreads();
-  // ---- lane-order reduction and the curve-mapping Jacobian ----
   for (int p = lane; p < kNumParams; p += kWave) {
     double s = 0.0;
     for (int l = 0; l < kWave; ++l) s += S.gacc[p][l];
+    t.gpart[(b * t.nchunks + c) * kNumParams + p] = s;
+  }
+}
+
+// Pass 3: per voice, the chunks' parameter adjoints summed (last chunk
+// first) and taken through the curve mapping's Jacobian to the normalised
+// parameters.
+__global__ void __launch_bounds__(kWave) adjoint_params_kernel(const RenderArgs a, CtlArgs t,
+                                                               float* __restrict__ grad_params) {
+  const int lane = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  for (int p = lane; p < kNumParams; p += kWave) {
+    double s = 0.0;
+    for (int64_t c = t.nchunks - 1; c >= 0; --c) s += t.gpart[(b * t.nchunks + c) * kNumParams + p];
     const double u = (double)a.params[b * kNumParams + p];
     const NebulaArgs& nb = a.neb;
     const double span = nb.hi[p] - nb.lo[p];
@@ -635,18 +726,30 @@ hipError_t launch_adjoint_rps(const RenderArgs& a, const float* g, double* red, 
                      shmem, s, a, g, red);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(adjoint_control_kernel, dim3((unsigned)a.batch), dim3(kWave), 0, s, a, red,
-                     gp);
+  // the control-rate passes' totals follow the segment sums and the carries
+  const int64_t J = (a.n_uniform + a.q - 1) / a.q;
+  CtlArgs t;
+  t.nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
+  t.sums = red + a.batch * (J * kNumRed + t.nchunks * 4);
+  t.dph = t.sums + a.batch * t.nchunks * 4;
+  t.gpart = t.dph + a.batch * t.nchunks * 2;
+  const dim3 chunks((unsigned)(a.batch * t.nchunks));
+  hipLaunchKernelGGL(adjoint_chunk_sums_kernel, chunks, dim3(kWave), 0, s, a, red, t);
+  hipLaunchKernelGGL(adjoint_chunk_lfo_kernel, chunks, dim3(kWave), 0, s, a, red, t);
+  hipLaunchKernelGGL(adjoint_chunk_grad_kernel, chunks, dim3(kWave), 0, s, a, red, t);
+  hipLaunchKernelGGL(adjoint_params_kernel, dim3((unsigned)a.batch), dim3(kWave), 0, s, a, t, gp);
   return hipGetLastError();
 }
 
 }  // namespace
 
 size_t adjoint_workspace_bytes(int64_t batch, int64_t n_samples, int q) {
-  // per-segment sums, then the chunk-start carries [batch][chunks][4]
+  // per-segment sums [batch][J][21], the chunk-start carries [batch][chunks][4],
+  // then the control-rate passes' per-chunk totals [batch][chunks][4 + 2 + 78]
   const int64_t J = (n_samples + q - 1) / q;
   const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
-  return (size_t)batch * ((size_t)J * kNumRed + (size_t)nchunks * 4) * sizeof(double);
+  return (size_t)batch * ((size_t)J * kNumRed + (size_t)nchunks * (4 + 4 + 2 + kNumParams)) *
+         sizeof(double);
 }
 
 double* adjoint_carries(double* ws, int64_t batch, int64_t n_samples, int q) {

@@ -372,6 +372,7 @@ int synth_render_backward(const synth_config* cfg, const float* params, const ui
   if (a.mix_mode != 0 || clamp) return SYNTH_EUNSUPPORTED;
   const int64_t J = (n_samples + a.q - 1) / a.q;
   if ((J + kSegsPerChunk - 1) / kSegsPerChunk > synth::adjoint_max_chunks()) return SYNTH_EUNSUPPORTED;
+  if (batch * ((J + kSegsPerChunk - 1) / kSegsPerChunk) > 0x7FFFFFFF) return SYNTH_EUNSUPPORTED;
   if (workspace_bytes < synth::adjoint_workspace_bytes(batch, n_samples, a.q)) return SYNTH_ENOMEM;
   const int rps = (a.q % 4 == 0 && a.q / 4 <= 192) ? 4 : 1;
   a.params = params;

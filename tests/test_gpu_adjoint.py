@@ -123,7 +123,7 @@ def test_adjoint_argument_errors(synth, nebula_table):
                                  gp.data_ptr(), ws.data_ptr(), 10, None)
     assert st == -2                                       # workspace too small
     need = L.synth_render_backward_workspace(ctypes.byref(cfg0), 2, 1000)
-    assert need == 2 * (10 * 21 + 1 * 4) * 8           # segment sums + one chunk's carries
+    assert need == 2 * (10 * 21 + 1 * 88) * 8          # segment sums + one chunk's carries and totals
 
 
 def test_adjoint_gradient_workload_b256_4s(synth):
