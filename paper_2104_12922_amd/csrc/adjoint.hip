@@ -273,9 +273,13 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
   }
 }
 
+// Per-lane parameter accumulators; rows padded by one double so that the
+// final per-parameter sums over lanes (lane p reads row p) hit distinct banks.
+constexpr int kAccRow = kWave + 1;
+
 // Adds x to lane's accumulator of parameter p (gradient pass only).
 template <bool G>
-__device__ __forceinline__ void gadd(double (*g)[kWave], int p, int lane, double x) {
+__device__ __forceinline__ void gadd(double (*g)[kAccRow], int p, int lane, double x) {
   if constexpr (G) g[p][lane] += x;
 }
 
@@ -341,7 +345,7 @@ __device__ __forceinline__ bool ramp_live(double jd, double s, double L, double 
 // the chunk's parameter adjoints are added to gacc[p][lane].
 template <bool GRADS>
 __device__ __forceinline__ void control_chunk(const RenderArgs& a, const VoiceShared& vs,
-                                              double (*gacc)[kWave], const double* rv, int64_t c,
+                                              double (*gacc)[kAccRow], const double* rv, int64_t c,
                                               int64_t J, int lane, double Gend1, double Gend2,
                                               const double* lc, const double* Lsuf,
                                               double* dph_tot) {
@@ -661,7 +665,7 @@ __global__ void __launch_bounds__(kWave) adjoint_chunk_lfo_kernel(const RenderAr
 // lanes in lane order.
 struct GradShared {
   VoiceShared vs;
-  double gacc[kNumParams][kWave];
+  double gacc[kNumParams][kAccRow];
 };
 
 __global__ void __launch_bounds__(kWave) adjoint_chunk_grad_kernel(const RenderArgs a,
