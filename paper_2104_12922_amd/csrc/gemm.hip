@@ -6,8 +6,9 @@
 //
 // Tiles of 128 x 128 x 32 per 256-thread workgroup (four wavefronts in 2 x 2,
 // each 64 x 64 as 2 x 2 MFMA 32 x 32 blocks).  Tiles are staged in LDS as
-// [row][k] with K contiguous (rows padded by 16 bytes), so every lane's
-// 8-element MFMA fragment is one 16-byte LDS read; the LDS tiles are double
+// [row][k] with K contiguous (rows padded by 16 bytes, 16-byte k-chunks
+// permuted per row, swz_k), so every lane's 8-element MFMA fragment is one
+// 16-byte LDS read; the LDS tiles are double
 // buffered and the next k-step is prefetched into registers.
 //
 // MFMA 32x32x16 lane layout (verified on gfx950): A fragment = row (lane % 32),
@@ -50,6 +51,14 @@ __device__ __forceinline__ bool aligned16(const void* p) {
   return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
 }
 
+// 16 elements as eight 4-byte loads (rows of an even leading dimension that
+// is not a multiple of 8, e.g. the MLP's 78-wide output rows)
+__device__ __forceinline__ void load16_by4(const uint16_t* p, uint4& r0, uint4& r1) {
+  const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+  r0 = make_uint4(q[0], q[1], q[2], q[3]);
+  r1 = make_uint4(q[4], q[5], q[6], q[7]);
+}
+
 // Staging of a 128 x 32 tile (rows row0.., k k0..) of an operand into
 // dst[row][k], in two phases so that the loads of the next k-step can be in
 // flight during the MFMAs: load() fills two 16-byte registers per thread,
@@ -57,8 +66,10 @@ __device__ __forceinline__ bool aligned16(const void* p) {
 //   K-major: thread t takes row t / 2, k (t & 1) * 16 .. +15 (32 bytes).
 //   row-major (X[k * ld + r]): thread t takes k t / 8, rows (t & 7) * 16 ..
 //   +15, written to LDS transposed (16 two-byte writes).
-// Tiles at the matrix edge or at the end K of the k-range (or unaligned
-// operands) are read element by element with bounds checks and zero fill.
+// Rows of an even leading dimension that is not a multiple of 8 are read as
+// 4-byte words.  Tiles at the matrix edge or at the end K of the k-range (or
+// unaligned operands) are read element by element with bounds checks and zero
+// fill.
 template <int OP>
 __device__ __forceinline__ void load_tile(uint4& r0, uint4& r1, int64_t K, const void* srcv,
                                           int64_t ld, int64_t row0, int64_t nrows, int64_t k0) {
@@ -74,6 +85,11 @@ __device__ __forceinline__ void load_tile(uint4& r0, uint4& r1, int64_t K, const
       r1 = p[1];
       return;
     }
+    if (gr < nrows && kb + 16 <= K && ((ld & 1) == 0) &&
+        (reinterpret_cast<uintptr_t>(src) & 3u) == 0) {
+      load16_by4(src + gr * ld + kb, r0, r1);
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < 16; ++e)
       v[e] = (gr < nrows && kb + e < K) ? src[gr * ld + kb + e] : (uint16_t)0;
@@ -86,6 +102,11 @@ __device__ __forceinline__ void load_tile(uint4& r0, uint4& r1, int64_t K, const
       r1 = p[1];
       return;
     }
+    if (gk < K && gr + 16 <= nrows && ((ld & 1) == 0) &&
+        (reinterpret_cast<uintptr_t>(src) & 3u) == 0) {
+      load16_by4(src + gk * ld + gr, r0, r1);
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < 16; ++e)
       v[e] = (gk < K && gr + e < nrows) ? src[gk * ld + gr + e] : (uint16_t)0;
@@ -96,21 +117,30 @@ __device__ __forceinline__ void load_tile(uint4& r0, uint4& r1, int64_t K, const
                   v[12] | ((uint32_t)v[13] << 16), v[14] | ((uint32_t)v[15] << 16));
 }
 
+// LDS column of element k of tile row `row`: the four 8-element (16-byte)
+// k-chunks of a row are permuted by (row / 16) mod 4.  The transposed stores
+// of row-major operands (the lanes of a wavefront at 8 k values, 16 rows
+// apart, rows 20 dwords apart) then spread over 16 banks instead of 4 (a
+// 2-way instead of an 8-way conflict), and an MFMA fragment (8 consecutive
+// k from a multiple of 8) is still one 16-byte read.
+__device__ __forceinline__ int swz_k(int row, int k) { return k ^ (((row >> 4) & 3) << 3); }
+
 template <int OP>
 __device__ __forceinline__ void store_tile(const uint4& r0, const uint4& r1,
                                            uint16_t (*dst)[PADK]) {
   const int t = threadIdx.x;
   if constexpr (OP == kOpKMajor) {
     const int r = t >> 1, kk = (t & 1) * 16;
-    *reinterpret_cast<uint4*>(&dst[r][kk]) = r0;
-    *reinterpret_cast<uint4*>(&dst[r][kk + 8]) = r1;
+    *reinterpret_cast<uint4*>(&dst[r][swz_k(r, kk)]) = r0;
+    *reinterpret_cast<uint4*>(&dst[r][swz_k(r, kk + 8)]) = r1;
   } else {
     const int kk = t >> 3, rr = (t & 7) * 16;
     const uint32_t w[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+    const int kc = swz_k(rr, kk);       // rows rr .. rr + 15 share the permutation
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      dst[rr + 2 * e][kk] = (uint16_t)(w[e] & 0xFFFFu);
-      dst[rr + 2 * e + 1][kk] = (uint16_t)(w[e] >> 16);
+      dst[rr + 2 * e][kc] = (uint16_t)(w[e] & 0xFFFFu);
+      dst[rr + 2 * e + 1][kc] = (uint16_t)(w[e] >> 16);
     }
   }
 }
@@ -180,11 +210,15 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
       const int kq = kk + 8 * (lane >> 5);
       bf16x8 af[2], bfr[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-        af[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 64 + i * 32 + (lane & 31)][kq]);
+      for (int i = 0; i < 2; ++i) {
+        const int r = wm * 64 + i * 32 + (lane & 31);
+        af[i] = *reinterpret_cast<const bf16x8*>(&As[buf][r][swz_k(r, kq)]);
+      }
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn * 64 + j * 32 + (lane & 31)][kq]);
+      for (int j = 0; j < 2; ++j) {
+        const int r = wn * 64 + j * 32 + (lane & 31);
+        bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][r][swz_k(r, kq)]);
+      }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
