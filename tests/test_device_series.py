@@ -1,0 +1,88 @@
+"""Accuracy of the float64 series the render's control stage evaluates on the
+GPU (exp2 by rint + Taylor, log2 by frexp + the atanh series, sin of a phase
+in cycles by quarter-cycle folding + Taylor, expm1 by Taylor for small
+arguments), re-evaluated here step by step in numpy float64 with the same
+reductions and the same numbers of terms, against numpy's library functions.
+The render's parity tests see these functions only through audio at 1e-4;
+this pins the ~1e-13 relative accuracy they are documented with."""
+import math
+
+import numpy as np
+
+LN2 = math.log(2.0)
+
+
+def horner(coefs, x):
+    p = np.full_like(x, coefs[0])
+    for c in coefs[1:]:
+        p = p * x + c
+    return p
+
+
+def exp2_series(y):
+    y = np.clip(y, -1100.0, 1023.0)
+    n = np.rint(y)
+    z = (y - n) * LN2
+    p = horner([1.0 / math.factorial(k) for k in range(13, -1, -1)], z)
+    return np.ldexp(p, n.astype(np.int64))
+
+
+def log2_series(x):
+    m, e = np.frexp(x)
+    low = m < 0.70710678118654752
+    m = np.where(low, 2.0 * m, m)
+    e = np.where(low, e - 1, e)
+    t = (m - 1.0) / (m + 1.0)
+    p = horner([1.0 / k for k in range(17, 0, -2)], t * t)
+    return e + 2.0 * t * p / LN2
+
+
+def sin_cycles_series(p):
+    r = p - np.rint(p)
+    r = np.where(r > 0.25, 0.5 - r, r)
+    r = np.where(r < -0.25, -0.5 - r, r)
+    a = 2.0 * math.pi * r
+    coefs = [(-1.0) ** (k // 2) / math.factorial(k) for k in range(23, 0, -2)]
+    return horner(coefs, a * a) * a
+
+
+def expm1_small(x):
+    return horner([1.0 / math.factorial(k) for k in range(8, 0, -1)], x) * x
+
+
+def rel(a, b):
+    return np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+
+
+def test_exp2_series():
+    y = np.random.default_rng(0).uniform(-1070.0, 30.0, 200000)
+    assert rel(exp2_series(y), np.exp2(y)).max() < 1e-15
+    assert exp2_series(np.array([-1200.0]))[0] == 0.0        # clamped, underflows to 0
+
+
+def test_log2_series():
+    rng = np.random.default_rng(1)
+    x = np.concatenate([rng.random(100000), 10.0 ** rng.uniform(-300, 0, 100000),
+                        1.0 - 10.0 ** rng.uniform(-15, -1, 50000)])
+    x = x[(x > 0) & (x < 1)]
+    ref = np.log2(x)
+    assert (np.abs(log2_series(x) - ref) / np.maximum(np.abs(ref), 1e-3)).max() < 1e-14
+
+
+def test_pow_from_series_matches_power():
+    rng = np.random.default_rng(2)
+    x = np.concatenate([rng.random(100000), 10.0 ** rng.uniform(-30, 0, 100000)])
+    x = x[(x > 0) & (x < 1)]
+    for alpha in (0.1, 0.5, 1.0, 2.0, 6.0):
+        p = exp2_series(alpha * log2_series(x))
+        assert rel(p, x ** alpha).max() < 1e-13
+
+
+def test_sin_cycles_series():
+    p = np.concatenate([np.random.default_rng(3).random(200000), [0.0, 0.25, 0.5, 0.75]])
+    assert np.abs(sin_cycles_series(p) - np.sin(2.0 * np.pi * p)).max() < 2e-15
+
+
+def test_expm1_small_branch():
+    x = np.random.default_rng(4).uniform(-1.0 / 64, 1.0 / 64, 200000)
+    assert rel(expm1_small(x), np.expm1(x)).max() < 1e-15
