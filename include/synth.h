@@ -212,18 +212,19 @@ int synth_mrstft_loss(const float* x, const float* target, int64_t batch, int64_
 /* The same loss against a fixed target whose spectra are computed once:
  * synth_mrstft_target writes, for every frame of every resolution, the
  * target's log2(|T_k| + 1e-5) for bins k <= n/2 (float32, exactly the values
- * synth_mrstft_loss computes inside) to tlog, dev, of >=
+ * synth_mrstft_loss computes inside) to tlog, dev, of tlog_bytes >=
  * synth_mrstft_target_bytes(batch, n_samples) bytes (about 24 bytes per
  * input sample; SYNTH_ENOMEM otherwise).  synth_mrstft_loss_cached then
  * transforms only the render's frames: loss and gradient are bitwise those of
- * synth_mrstft_loss with that target.  Same sizes, limits and workspace as
- * synth_mrstft_loss. */
+ * synth_mrstft_loss with that target.  tlog must come from
+ * synth_mrstft_target with the same batch and n_samples (a smaller tlog_bytes
+ * is SYNTH_ENOMEM).  Same sizes, limits and workspace as synth_mrstft_loss. */
 size_t synth_mrstft_target_bytes(int64_t batch, int64_t n_samples);
 int synth_mrstft_target(const float* target, int64_t batch, int64_t n_samples, float* tlog,
                         size_t tlog_bytes, void* stream);
-int synth_mrstft_loss_cached(const float* x, const float* tlog, int64_t batch, int64_t n_samples,
-                             double* loss, float* grad_x, void* workspace, size_t workspace_bytes,
-                             void* stream);
+int synth_mrstft_loss_cached(const float* x, const float* tlog, size_t tlog_bytes, int64_t batch,
+                             int64_t n_samples, double* loss, float* grad_x, void* workspace,
+                             size_t workspace_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Learned proposal: log-mel features and an MLP mapping them to parameters

@@ -214,11 +214,12 @@ def synth_mrstft_loss(x: torch.Tensor, target, grad: bool = False,
     if workspace is None or workspace.numel() * workspace.element_size() < need:
         workspace = torch.empty(max(need, 8), dtype=torch.uint8, device=x.device)
     if cached:
-        fn, tptr = "synth_mrstft_loss_cached", target.tlog.data_ptr()
+        fn = "synth_mrstft_loss_cached"
+        tptr = (target.tlog.data_ptr(), target.tlog.numel() * 4)
     else:
-        fn, tptr = "synth_mrstft_loss", _dev_ptr(target, "target", torch.float32, B * N)
+        fn, tptr = "synth_mrstft_loss", (_dev_ptr(target, "target", torch.float32, B * N),)
     _native.check(fn, getattr(_native.lib(), fn)(
-        _dev_ptr(x, "x", torch.float32, B * N), tptr,
+        _dev_ptr(x, "x", torch.float32, B * N), *tptr,
         B, N, _dev_ptr(loss, "loss", torch.float64, B),
         _dev_ptr(g, "grad", torch.float32, B * N) if grad else None, workspace.data_ptr(),
         workspace.numel() * workspace.element_size(), _stream(x.device)))

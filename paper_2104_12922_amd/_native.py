@@ -83,7 +83,10 @@ def lib() -> ctypes.CDLL:
         L.synth_mrstft_target.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                           ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.synth_mrstft_loss_cached.restype = ctypes.c_int
-        L.synth_mrstft_loss_cached.argtypes = L.synth_mrstft_loss.argtypes
+        L.synth_mrstft_loss_cached.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                               ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                               ctypes.c_void_p]
         L.synth_mrstft_workspace.restype = ctypes.c_size_t
         L.synth_mrstft_workspace.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
         L.synth_render_backward_workspace.restype = ctypes.c_size_t

@@ -442,13 +442,14 @@ int synth_mrstft_target(const float* target, int64_t batch, int64_t n_samples, f
   return to_status(synth::launch_mrstft_target(target, batch, n_samples, tlog, (hipStream_t)stream));
 }
 
-int synth_mrstft_loss_cached(const float* x, const float* tlog, int64_t batch, int64_t n_samples,
-                             double* loss, float* grad_x, void* workspace, size_t workspace_bytes,
-                             void* stream) {
+int synth_mrstft_loss_cached(const float* x, const float* tlog, size_t tlog_bytes, int64_t batch,
+                             int64_t n_samples, double* loss, float* grad_x, void* workspace,
+                             size_t workspace_bytes, void* stream) {
   if (batch < 0 || n_samples <= 0 || n_samples > ((int64_t)1 << 31)) return SYNTH_EINVAL;
   if (batch == 0) return SYNTH_OK;
   if (!x || !loss || !workspace) return SYNTH_EINVAL;
   if (!tlog && synth::mrstft_target_bytes(batch, n_samples) > 0) return SYNTH_EINVAL;
+  if (tlog_bytes < synth::mrstft_target_bytes(batch, n_samples)) return SYNTH_ENOMEM;
   if (reinterpret_cast<uintptr_t>(workspace) & 15) return SYNTH_EINVAL;
   if (batch > 65535) return SYNTH_EUNSUPPORTED;
   if (workspace_bytes < synth::mrstft_workspace_bytes(batch, n_samples, grad_x != nullptr))

@@ -129,14 +129,15 @@ def test_mrstft_argument_checks_before_launch():
     assert call(B=0) == 0
     assert call(nbytes=16) == -2                   # SYNTH_ENOMEM
 
-    def cached(B=2, n=4096, x=fake, t=fake, loss=fake, ws=fake, nbytes=1 << 40):
-        return L.synth_mrstft_loss_cached(x, t, B, n, loss, None, ws, nbytes, None)
+    def cached(B=2, n=4096, x=fake, t=fake, tbytes=1 << 40, loss=fake, ws=fake, nbytes=1 << 40):
+        return L.synth_mrstft_loss_cached(x, t, tbytes, B, n, loss, None, ws, nbytes, None)
     assert cached(B=-1) == EINVAL
     assert cached(t=None) == EINVAL
     assert cached(ws=odd) == EINVAL
     assert cached(B=65536) == EUNSUP
     assert cached(nbytes=16) == -2
     need = L.synth_mrstft_target_bytes(2, 4096)
+    assert cached(tbytes=need - 1) == -2                  # target spectra of another size
     assert need > 0 and L.synth_mrstft_target_bytes(2, 300) == 0   # no frame fits
     assert L.synth_mrstft_target(fake, 2, 4096, fake, need - 1, None) == -2
     assert L.synth_mrstft_target(None, 2, 4096, fake, need, None) == EINVAL
