@@ -25,6 +25,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per
+# second (a wave64 instruction occupies a SIMD for 4 cycles; transcendentals
+# issue at half rate and count as 2)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# minimum VALU lane-slots per output sample of the method as formulated: per
+# computed sample about 43 (two float64 phase and increment updates 4, the
+# sine's conversion and hardware sine 3, the square-saw's half-cycle reduction
+# 4, sign flips 4, sine and cosine 4, tanh 7, shape 2, two VCA ramps and the mix
+# 4, one eighth of a Philox-4x32-10 call 7.5 and the noise map and VCA 4),
+# times the about 88% of output samples that precede the silent tails
+RENDER_SLOTS_PER_SAMPLE = 38.0
 
 # HBM bytes moved by one render launch on the ragged 16384-voice workload,
 # from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB; the
@@ -377,6 +388,7 @@ def main():
     value = total / (dt / args.steps)
     alg_bytes = 4.0 * total + 4.0 * 78 * B + 8.0 * (B + 1) + 4.0 * B   # audio, params, offsets, order
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    alu_tops = RENDER_SLOTS_PER_SAMPLE * total / (kern_ms * 1e-3) / 1e12
     out = {
         "metric": "rendered audio samples/sec", "value": value, "unit": "samples/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -389,14 +401,18 @@ def main():
                    "launch_plan": list(plan) if plan is not None else "default",
                    "launch_order": "longest voices first"},
         "mhz": value / 1e6, "x_realtime": value / wl.sample_rate,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
+        # the render is bound by VALU issue: the roofline is the ALU one
+        # (algorithmic slots / kernel time), with the HBM figures beside it
+        "roofline": {"bound": "alu", "achieved": alu_tops, "peak": VALU_PEAK_TOPS,
+                     "unit": "T VALU lane-slots/s", "frac": alu_tops / VALU_PEAK_TOPS,
                      "traffic": (float(prof["fetch_bytes"] + prof["write_bytes"])
                                  if prof else None),
                      "traffic_unit": "B/launch",
+                     "slots_per_sample": RENDER_SLOTS_PER_SAMPLE,
                      "valu_busy_profiled": prof["valu_busy"] if prof else None,
-                     "kernel": "render_kernel", "kernel_ms": kern_ms,
-                     "alg_bytes_per_launch": alg_bytes},
+                     "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes},
+                     "kernel": "render_kernel", "kernel_ms": kern_ms},
         "context": {"paper_single_gpu_mhz": 714.0, "paper_gpu": "V100"},
     }
     if not args.no_cpu_baseline:
