@@ -372,13 +372,62 @@ def render_batch(seed, ids, nebula_table, lengths_s=(1, 2, 3, 4), tune: bool = T
     return u, audio, offs
 
 
+def train_pipelined(net: "MLP", lm: LogMel, nebula_table, mean, inv_std, steps: int,
+                    batch: int, seed: int, lengths_s=(1, 2, 3, 4), lr_at=None, first: int = 1,
+                    on_step=None):
+    """Training steps 0 .. steps - 1 on the voices of batches first, first + 1,
+    ...: the render, log-mel features and standardisation of step s + 1 run on
+    the caller's stream while the MLP takes step s on a second stream (two
+    feature buffers, events between the streams), so that the VALU-bound
+    render overlaps the matrix-core GEMMs.  Every step computes exactly what
+    it computes when the steps run one after another.  lr_at(s) gives the
+    learning rate of step s; on_step(s, losses) is called after step s is
+    enqueued.  Returns the per-step losses (0-d float64 tensors)."""
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    xb = [torch.empty(batch, MEL_FEATURES, dtype=BF16, device="cuda") for _ in range(2)]
+    ready = [torch.cuda.Event(), torch.cuda.Event()]
+    done = [torch.cuda.Event(), torch.cuda.Event()]
+    us = [None, None]
+    losses = []
+
+    def prepare(step, slot):
+        u, audio, offs = render_batch(seed, train_ids((first + step) * batch, batch),
+                                      nebula_table, lengths_s)
+        standardize(lm(audio, offsets=offs), mean, inv_std, out=xb[slot])
+        us[slot] = u
+        ready[slot].record(main)
+
+    if steps <= 0:
+        return losses
+    prepare(0, 0)
+    for s in range(steps):
+        c = s % 2
+        with torch.cuda.stream(side):
+            side.wait_event(ready[c])
+            if lr_at is not None:
+                net.lr = lr_at(s)
+            losses.append(net.train_step(xb[c], us[c]).clone())
+            done[c].record(side)
+        us[c].record_stream(side)        # drawn on the main stream, read on the side stream
+        if s + 1 < steps:
+            if s >= 1:
+                main.wait_event(done[1 - c])   # step s - 1 is done with its buffers
+            prepare(s + 1, 1 - c)
+        if on_step is not None:
+            on_step(s, losses)
+    main.wait_stream(side)
+    return losses
+
+
 def train_proposal(nebula_table, steps: int, batch: int = 4096, seed: int = 10,
                    lengths_s=(1, 2, 3, 4), lr: float = 3e-4, warmup: int = 500, init=None,
                    log_every: int = 0, log=print):
     """Train the proposal on freshly rendered training voices: each step draws
     `batch` new voices, renders them (ragged lengths), computes log-mel
     features and takes one Adam step on the MSE between the MLP's sigmoid
-    output and the drawn u.  Feature statistics come from the first batch.
+    output and the drawn u (render and MLP of consecutive steps overlapped,
+    train_pipelined).  Feature statistics come from the first batch.
     Returns (Proposal, history of (step, loss))."""
     from workloads import mlp_init
     lm = LogMel()
@@ -386,18 +435,17 @@ def train_proposal(nebula_table, steps: int, batch: int = 4096, seed: int = 10,
     _, audio, offs = render_batch(seed, train_ids(0, batch), nebula_table, lengths_s)
     mean, inv_std = feature_stats(lm(audio, offsets=offs))
     del audio
-    hist, pending = [], []
-    for s in range(steps):
-        u, audio, offs = render_batch(seed, train_ids((s + 1) * batch, batch), nebula_table,
-                                      lengths_s)
-        x = standardize(lm(audio, offsets=offs), mean, inv_std)
-        net.lr = lr * min(1.0, (s + 1) / max(1, warmup))
-        pending.append((s, net.train_step(x, u).clone()))
+    hist = []
+
+    def on_step(s, losses):
         if log_every and ((s + 1) % log_every == 0 or s + 1 == steps):
-            hist += [(i, float(l)) for i, l in pending]
-            pending = []
+            hist.extend((i, float(losses[i])) for i in range(len(hist), s + 1))
             log(f"train step {s + 1}/{steps} loss {hist[-1][1]:.5f}")
-    hist += [(i, float(l)) for i, l in pending]
+
+    losses = train_pipelined(net, lm, nebula_table, mean, inv_std, steps, batch, seed, lengths_s,
+                             lr_at=lambda s: lr * min(1.0, (s + 1) / max(1, warmup)),
+                             on_step=on_step)
+    hist.extend((i, float(losses[i])) for i in range(len(hist), len(losses)))
     return Proposal(net, lm, mean, inv_std), hist
 
 

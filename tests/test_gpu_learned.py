@@ -256,3 +256,31 @@ def test_best_update(L):
         assert float(bd[t]) == float(mn[t]) and int(idd[t]) == 100 + int(am[t])
         assert torch.equal(bpd[t].cpu(), params[int(am[t]), t])
     assert int(idd[4]) == 102
+
+
+def test_pipelined_training_is_bitwise_serial(L):
+    """The overlapped training loop (render of step s + 1 on one stream, MLP of
+    step s on another) computes bitwise what the steps compute one after
+    another: same per-step losses, same weights and Adam moments."""
+    tab = W.default_nebula().table()
+    B, steps, seed = 256, 4, W.SEED_TRAIN
+    lr_at = lambda s: 1e-3 * min(1.0, (s + 1) / 2)
+    lm = L.LogMel()
+    _, audio, offs = L.render_batch(seed, L.train_ids(0, B), tab)
+    mean, inv_std = L.feature_stats(lm(audio, offsets=offs))
+    serial = L.MLP(W.mlp_init(0))
+    l1 = []
+    for s in range(steps):
+        u, audio, offs = L.render_batch(seed, L.train_ids((s + 1) * B, B), tab)
+        x = L.standardize(lm(audio, offsets=offs), mean, inv_std)
+        serial.lr = lr_at(s)
+        l1.append(serial.train_step(x, u).clone())
+    piped = L.MLP(W.mlp_init(0))
+    l2 = L.train_pipelined(piped, lm, tab, mean, inv_std, steps, B, seed, lr_at=lr_at)
+    torch.cuda.synchronize()
+    assert len(l2) == steps
+    assert all(torch.equal(a, b) for a, b in zip(l1, l2)), ([float(a) for a in l1],
+                                                            [float(b) for b in l2])
+    for k in serial.names:
+        assert torch.equal(serial.w[k], piped.w[k]), k
+        assert torch.equal(serial.m[k], piped.m[k]) and torch.equal(serial.v[k], piped.v[k]), k
