@@ -382,7 +382,10 @@ def train_pipelined(net: "MLP", lm: LogMel, nebula_table, mean, inv_std, steps: 
     render overlaps the matrix-core GEMMs.  Every step computes exactly what
     it computes when the steps run one after another.  lr_at(s) gives the
     learning rate of step s; on_step(s, losses) is called after step s is
-    enqueued.  Returns the per-step losses (0-d float64 tensors)."""
+    enqueued; the losses are written on the second stream, so it must
+    synchronise the device before reading one (the caller's stream waits for
+    the second one when this returns).  Returns the per-step losses (0-d
+    float64 tensors)."""
     main = torch.cuda.current_stream()
     side = torch.cuda.Stream()
     xb = [torch.empty(batch, MEL_FEATURES, dtype=BF16, device="cuda") for _ in range(2)]
@@ -439,6 +442,7 @@ def train_proposal(nebula_table, steps: int, batch: int = 4096, seed: int = 10,
 
     def on_step(s, losses):
         if log_every and ((s + 1) % log_every == 0 or s + 1 == steps):
+            torch.cuda.synchronize()       # the losses are written on the MLP's stream
             hist.extend((i, float(losses[i])) for i in range(len(hist), s + 1))
             log(f"train step {s + 1}/{steps} loss {hist[-1][1]:.5f}")
 

@@ -141,23 +141,25 @@ class MatchService:
 
     def __init__(self, nebula_table, proposal: Lr.Proposal | None = None, steps: int = 50,
                  lr: float = 0.05, budget_bytes: int = 64 << 30, max_batch: int = 1024,
-                 init_seed: int = 21, noise_seed: int = 22):
+                 init_seed: int = 21, noise_seed: int = 22, concurrency: int = 4):
         self.table = nebula_table
         self.proposal = proposal
         self.steps, self.lr = steps, lr
         self.budget, self.max_batch = budget_bytes, max_batch
         self.init_seed, self.noise_seed = init_seed, noise_seed
+        self.concurrency = max(1, int(concurrency))
 
     @staticmethod
     def request_bytes(n_samples: int, q: int = 100) -> int:
         j = (n_samples + q - 1) // q
         return 12 * n_samples + 168 * j + 12 * 4 * NUM_PARAMS + 8192 * 6 + 64 * 1032 * 2
 
-    def admit(self, queue: list) -> list:
-        """Pop the next batch (same length, within budget) from queue."""
+    def admit(self, queue: list, budget: int | None = None) -> list:
+        """Pop the next batch (same length, within budget - by default the
+        whole budget) from queue."""
         n = queue[0].audio.numel()
         per = self.request_bytes(n)
-        cap = max(1, min(self.max_batch, self.budget // per))
+        cap = max(1, min(self.max_batch, (self.budget if budget is None else budget) // per))
         batch, rest = [], []
         for r in queue:
             if len(batch) < cap and r.audio.numel() == n:
@@ -174,24 +176,58 @@ class MatchService:
 
     def run(self, requests: list):
         """Serve every request; returns (results {rid: (best_u, loss)},
-        latencies {rid: seconds since the service started}, batches)."""
+        latencies {rid: seconds from the start until its batch finished on the
+        GPU}, batches).  Up to `concurrency` batches are in flight at once,
+        each on a stream of its own and together within the memory budget:
+        the host enqueues a batch's whole gradient descent without waiting, so
+        batches of different lengths share the GPU.  Initial estimates (the
+        proposal's buffers are shared) are computed on the caller's stream."""
         queue = list(requests)
         results, lat, batches = {}, {}, []
+        main = torch.cuda.current_stream()
+        streams = [torch.cuda.Stream() for _ in range(self.concurrency)]
+        free = list(range(self.concurrency))
+        inflight, done = [], []
+        used = 0
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        while queue:
-            batch = self.admit(queue)
-            targets = torch.stack([r.audio for r in batch]).contiguous()
-            ids = torch.tensor([r.voice_id for r in batch], dtype=torch.int64, device=targets.device)
-            u0 = self.initial_estimate(targets, ids)
-            res = gradient_match(targets, ids, self.table, u0, steps=self.steps, lr=self.lr,
-                                 noise_seed=self.noise_seed, record_curve=False)
-            torch.cuda.synchronize()
-            t = time.perf_counter() - t0
+        start = torch.cuda.Event(enable_timing=True)
+        start.record(main)
+        while queue or inflight:
+            per = self.request_bytes(queue[0].audio.numel()) if queue else 0
+            if queue and free and (self.budget - used >= per or not inflight):
+                batch = self.admit(queue, max(self.budget - used, per))
+                n = batch[0].audio.numel()
+                targets = torch.stack([r.audio for r in batch]).contiguous()
+                ids = torch.tensor([r.voice_id for r in batch], dtype=torch.int64,
+                                   device=targets.device)
+                u0 = self.initial_estimate(targets, ids).clone()
+                k = free.pop(0)
+                stream = streams[k]
+                stream.wait_stream(main)
+                with torch.cuda.stream(stream):
+                    res = gradient_match(targets, ids, self.table, u0, steps=self.steps,
+                                         lr=self.lr, noise_seed=self.noise_seed,
+                                         record_curve=False)
+                    end = torch.cuda.Event(enable_timing=True)
+                    end.record(stream)
+                for t in (targets, ids, u0):
+                    t.record_stream(stream)
+                nbytes = self.request_bytes(n) * len(batch)
+                used += nbytes
+                inflight.append((batch, n, nbytes, k, end, res))
+            else:
+                batch, n, nbytes, k, end, res = inflight.pop(0)   # the oldest batch
+                end.synchronize()
+                used -= nbytes
+                free.append(k)
+                done.append((batch, n, end, res))
+        torch.cuda.synchronize()
+        for batch, n, end, res in done:
+            t = start.elapsed_time(end) / 1e3
             for i, r in enumerate(batch):
                 results[r.rid] = (res.best_u[i], float(res.best_loss[i]))
                 lat[r.rid] = t
-            batches.append((len(batch), targets.shape[1], t))
+            batches.append((len(batch), n, t))
         return results, lat, batches
 
 
@@ -228,6 +264,8 @@ def main(argv=None):
     ap.add_argument("--rs-budget", type=int, default=1000)
     ap.add_argument("--rs-targets", type=int, default=0, help="targets given to random search (0 = all)")
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--concurrency", type=int, default=4,
+                    help="matching batches in flight at once (one stream each)")
     a = ap.parse_args(argv)
     tab = W.default_nebula().table()
     out = {"targets": a.targets, "steps": a.steps, "lr": a.lr}
@@ -291,13 +329,15 @@ def main(argv=None):
             reqs += [Request(i, i, x[j]) for j, i in enumerate(g)]
     pos = {int(r): k for k, r in enumerate(order)}
     reqs.sort(key=lambda r: pos[r.rid])
-    svc = MatchService(tab, prop, steps=a.steps, lr=a.lr, budget_bytes=int(a.budget_gb * 2**30))
+    svc = MatchService(tab, prop, steps=a.steps, lr=a.lr, budget_bytes=int(a.budget_gb * 2**30),
+                       concurrency=a.concurrency)
     t1 = time.perf_counter()
     _, lat, batches = svc.run(reqs)
     wall = time.perf_counter() - t1
     out["service"] = {"wall_s": wall, "requests_per_s": len(reqs) / wall,
                       "p50_s": percentile(lat.values(), 50), "p99_s": percentile(lat.values(), 99),
                       "batches": len(batches), "budget_gb": a.budget_gb,
+                      "concurrency": a.concurrency,
                       "renders_per_request": a.steps + 1}
     print(json.dumps(out), flush=True)
 

@@ -83,3 +83,24 @@ def test_service_admission_and_latency(S):
     assert sum(b[0] for b in batches) == 12
     assert all(np.isfinite(v[1]) for v in res.values())
     assert M.percentile(lat.values(), 50) <= M.percentile(lat.values(), 99)
+
+
+def test_service_concurrent_batches_match_one_at_a_time(S):
+    """Batches in flight together on separate streams give bitwise the results
+    of serving them one after another (same batches: the budget admits every
+    request of a length at once)."""
+    from paper_2104_12922_amd import matching as M
+    reqs = []
+    for rid in range(9):
+        secs = 0.25 * (1 + rid % 3)
+        tab, ids, _, x = targets(S, 1, secs, first=100 + rid)
+        reqs.append(M.Request(rid, 100 + rid, x[0].contiguous()))
+    out = []
+    for conc in (1, 3):
+        svc = M.MatchService(tab, proposal=None, steps=3, concurrency=conc)
+        res, lat, batches = svc.run(list(reqs))
+        assert sorted(b[0] for b in batches) == [3, 3, 3]
+        out.append(res)
+    for rid in range(9):
+        assert torch.equal(out[0][rid][0], out[1][rid][0]), rid
+        assert out[0][rid][1] == out[1][rid][1], rid
