@@ -374,51 +374,75 @@ def render_batch(seed, ids, nebula_table, lengths_s=(1, 2, 3, 4), tune: bool = T
 
 def train_pipelined(net: "MLP", lm: LogMel, nebula_table, mean, inv_std, steps: int,
                     batch: int, seed: int, lengths_s=(1, 2, 3, 4), lr_at=None, first: int = 1,
-                    on_step=None):
+                    on_step=None, group: int = 2, tune: bool = True):
     """Training steps 0 .. steps - 1 on the voices of batches first, first + 1,
-    ...: the render, log-mel features and standardisation of step s + 1 run on
-    the caller's stream while the MLP takes step s on a second stream (two
-    feature buffers, events between the streams), so that the VALU-bound
-    render overlaps the matrix-core GEMMs.  Every step computes exactly what
-    it computes when the steps run one after another.  lr_at(s) gives the
-    learning rate of step s; on_step(s, losses) is called after step s is
-    enqueued; the losses are written on the second stream, so it must
-    synchronise the device before reading one (the caller's stream waits for
-    the second one when this returns).  Returns the per-step losses (0-d
-    float64 tensors)."""
+    ...  The voices of `group` consecutive steps are drawn, rendered (one
+    launch: the short voices of one step fill the tail the long ones leave)
+    and featurised together, then split back into their steps in the order a
+    per-step render gives them; while the MLP takes the steps of one group on
+    a second stream, the next group is rendered on the caller's stream (two
+    feature buffers, events between the streams), so the VALU-bound render
+    overlaps the matrix-core GEMMs.  With one launch plan's runs per segment
+    (tune=False, or when the autotuner picks the same for both batch shapes)
+    every step computes bitwise what it computes when the steps run one after
+    another.  lr_at(s) gives the learning rate of step s; on_step(s, losses)
+    is called after step s is enqueued; the losses are written on the second
+    stream, so it must synchronise the device before reading one (the
+    caller's stream waits for the second one when this returns).  Returns the
+    per-step losses (0-d float64 tensors)."""
     main = torch.cuda.current_stream()
     side = torch.cuda.Stream()
-    xb = [torch.empty(batch, MEL_FEATURES, dtype=BF16, device="cuda") for _ in range(2)]
+    G = max(1, int(group))
+    per = torch.tensor([int(round(x * 44100.0)) for x in lengths_s], dtype=torch.int64,
+                       device="cuda")
+    xb = [torch.empty(G * batch, MEL_FEATURES, dtype=BF16, device="cuda") for _ in range(2)]
+    feat = [None]
     ready = [torch.cuda.Event(), torch.cuda.Event()]
     done = [torch.cuda.Event(), torch.cuda.Event()]
     us = [None, None]
     losses = []
+    ngroups = (steps + G - 1) // G
 
-    def prepare(step, slot):
-        u, audio, offs = render_batch(seed, train_ids((first + step) * batch, batch),
-                                      nebula_table, lengths_s)
-        standardize(lm(audio, offsets=offs), mean, inv_std, out=xb[slot])
-        us[slot] = u
+    def prepare(k, slot):
+        n = min(G, steps - k * G)
+        ids = torch.cat([train_ids((first + k * G + g) * batch, batch) for g in range(n)])
+        u, audio, offs = render_batch(seed, ids, nebula_table, lengths_s, tune=tune)
+        # render_batch orders the voices longest first (stable); the rows of
+        # step g, in that order, are where the sorted positions fall in
+        # [g batch, (g + 1) batch): gather them step by step
+        order = torch.argsort(-per[ids % len(lengths_s)], stable=True)
+        rows = torch.argsort(order // batch, stable=True)
+        f = lm(audio, offsets=offs, out=feat[0] if feat[0] is not None and
+               feat[0].shape[0] == n * batch else None)
+        feat[0] = f
+        x = standardize(f, mean, inv_std)
+        torch.index_select(x, 0, rows, out=xb[slot][:n * batch])
+        us[slot] = u.index_select(0, rows)
         ready[slot].record(main)
 
     if steps <= 0:
         return losses
     prepare(0, 0)
-    for s in range(steps):
-        c = s % 2
+    for k in range(ngroups):
+        c = k % 2
+        n = min(G, steps - k * G)
         with torch.cuda.stream(side):
             side.wait_event(ready[c])
-            if lr_at is not None:
-                net.lr = lr_at(s)
-            losses.append(net.train_step(xb[c], us[c]).clone())
+            for g in range(n):
+                s = k * G + g
+                if lr_at is not None:
+                    net.lr = lr_at(s)
+                rows = slice(g * batch, (g + 1) * batch)
+                losses.append(net.train_step(xb[c][rows], us[c][rows]).clone())
             done[c].record(side)
         us[c].record_stream(side)        # drawn on the main stream, read on the side stream
-        if s + 1 < steps:
-            if s >= 1:
-                main.wait_event(done[1 - c])   # step s - 1 is done with its buffers
-            prepare(s + 1, 1 - c)
+        if k + 1 < ngroups:
+            if k >= 1:
+                main.wait_event(done[1 - c])   # group k - 1 is done with its buffers
+            prepare(k + 1, 1 - c)
         if on_step is not None:
-            on_step(s, losses)
+            for g in range(n):
+                on_step(k * G + g, losses)
     main.wait_stream(side)
     return losses
 
