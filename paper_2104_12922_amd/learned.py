@@ -378,11 +378,12 @@ def train_pipelined(net: "MLP", lm: LogMel, nebula_table, mean, inv_std, steps: 
     """Training steps 0 .. steps - 1 on the voices of batches first, first + 1,
     ...  The voices of `group` consecutive steps are drawn, rendered (one
     launch: the short voices of one step fill the tail the long ones leave)
-    and featurised together, then split back into their steps in the order a
-    per-step render gives them; while the MLP takes the steps of one group on
-    a second stream, the next group is rendered on the caller's stream (two
-    feature buffers, events between the streams), so the VALU-bound render
-    overlaps the matrix-core GEMMs.  With one launch plan's runs per segment
+    and featurised together (a last, partial group too: its extra voices are
+    rendered and not trained on), then split back into their steps in the
+    order a per-step render gives them; while the MLP takes the steps of one
+    group on a second stream, the next group is rendered on the caller's
+    stream (two feature buffers, events between the streams), so the
+    VALU-bound render overlaps the matrix-core GEMMs.  With one launch plan's runs per segment
     (tune=False, or when the autotuner picks the same for both batch shapes)
     every step computes bitwise what it computes when the steps run one after
     another.  lr_at(s) gives the learning rate of step s; on_step(s, losses)
@@ -404,7 +405,9 @@ def train_pipelined(net: "MLP", lm: LogMel, nebula_table, mean, inv_std, steps: 
     ngroups = (steps + G - 1) // G
 
     def prepare(k, slot):
-        n = min(G, steps - k * G)
+        # always G steps' voices (a last, partial group renders voices it does
+        # not train on), so that every launch has the one tuned batch shape
+        n = G
         ids = torch.cat([train_ids((first + k * G + g) * batch, batch) for g in range(n)])
         u, audio, offs = render_batch(seed, ids, nebula_table, lengths_s, tune=tune)
         # render_batch orders the voices longest first (stable); the rows of

@@ -264,7 +264,7 @@ def test_pipelined_training_is_bitwise_serial(L):
     stream while the MLP takes the current pair on another) computes bitwise
     what the steps compute one after another, with one launch plan: same
     per-step losses, same weights and Adam moments (5 steps: a last pair of
-    one step)."""
+    which one step is trained)."""
     tab = W.default_nebula().table()
     B, steps, seed = 256, 5, W.SEED_TRAIN
     lr_at = lambda s: 1e-3 * min(1.0, (s + 1) / 2)
