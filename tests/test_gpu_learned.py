@@ -258,13 +258,14 @@ def test_best_update(L):
     assert int(idd[4]) == 102
 
 
-def test_pipelined_training_is_bitwise_serial(L):
+@pytest.mark.parametrize("group", [1, 2, 3])
+def test_pipelined_training_is_bitwise_serial(L, group):
     """The overlapped training loop (two steps' voices rendered in one launch
     and split back into their steps; the render of the next pair on one
     stream while the MLP takes the current pair on another) computes bitwise
     what the steps compute one after another, with one launch plan: same
-    per-step losses, same weights and Adam moments (5 steps: a last pair of
-    which one step is trained)."""
+    per-step losses, same weights and Adam moments (5 steps: with two or
+    three steps per render a last group of which only part is trained)."""
     tab = W.default_nebula().table()
     B, steps, seed = 256, 5, W.SEED_TRAIN
     lr_at = lambda s: 1e-3 * min(1.0, (s + 1) / 2)
@@ -280,7 +281,7 @@ def test_pipelined_training_is_bitwise_serial(L):
         l1.append(serial.train_step(x, u).clone())
     piped = L.MLP(W.mlp_init(0))
     l2 = L.train_pipelined(piped, lm, tab, mean, inv_std, steps, B, seed, lr_at=lr_at,
-                           tune=False)
+                           group=group, tune=False)
     torch.cuda.synchronize()
     assert len(l2) == steps
     assert all(torch.equal(a, b) for a, b in zip(l1, l2)), ([float(a) for a in l1],
