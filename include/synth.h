@@ -276,6 +276,17 @@ int synth_logmel_init(double sample_rate, void* dft_basis, void* mel_basis, void
 int synth_logmel(const float* audio, const int64_t* offsets, int64_t batch, int64_t n_samples,
                  const void* mel_basis, void* workspace, size_t workspace_bytes, float* features,
                  void* stream);
+/* synth_logmel's features standardised and rounded to bf16 in the same
+ * kernel: features_bf16[r][c] = bf16((x[c] - mean[c]) * inv_std[c]) (float32
+ * arithmetic, round to nearest even: bitwise what synth_standardize gives for
+ * synth_logmel's output) for the features x of voice b, written to row
+ * r = row_index[b] (row_index dev int64 [batch], or NULL for r = b; a row
+ * outside [0, batch) is not written).  mean, inv_std: dev float32 [8192];
+ * features_bf16: dev bf16 [batch][8192].  No workspace. */
+int synth_logmel_standardized(const float* audio, const int64_t* offsets, int64_t batch,
+                              int64_t n_samples, const void* mel_basis, const float* mean,
+                              const float* inv_std, const int64_t* row_index,
+                              void* features_bf16, void* stream);
 int synth_logmel_mfma(const float* audio, const int64_t* offsets, int64_t batch,
                       int64_t n_samples, const void* dft_basis, const void* mel_basis,
                       void* workspace, size_t workspace_bytes, float* features, void* stream);

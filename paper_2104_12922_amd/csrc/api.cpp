@@ -579,6 +579,19 @@ int synth_logmel(const float* audio, const int64_t* offsets, int64_t batch, int6
                        workspace_bytes, features, stream);
 }
 
+int synth_logmel_standardized(const float* audio, const int64_t* offsets, int64_t batch,
+                              int64_t n_samples, const void* mel_basis, const float* mean,
+                              const float* inv_std, const int64_t* row_index,
+                              void* features_bf16, void* stream) {
+  if (batch < 0) return SYNTH_EINVAL;
+  if (batch == 0) return SYNTH_OK;
+  if (!audio || !mel_basis || !mean || !inv_std || !features_bf16) return SYNTH_EINVAL;
+  if (!offsets && n_samples <= 0) return SYNTH_EINVAL;
+  return to_status(synth::launch_logmel_fft_std(audio, offsets, offsets ? 0 : n_samples, batch,
+                                                mel_basis, kMelLd, mean, inv_std, row_index,
+                                                features_bf16, (hipStream_t)stream));
+}
+
 int synth_logmel_mfma(const float* audio, const int64_t* offsets, int64_t batch,
                       int64_t n_samples, const void* dft_basis, const void* mel_basis,
                       void* workspace, size_t workspace_bytes, float* features, void* stream) {

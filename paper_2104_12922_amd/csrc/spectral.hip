@@ -349,10 +349,28 @@ struct MelShared {
   float2 pt[wfft::pt_size<1024>()];   // FFT pass twiddles
 };
 
+// float -> bf16, round to nearest even (NaN stays NaN)
+__device__ __forceinline__ uint16_t mel_f2bf(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Optional standardised output: bf16 (x - mean[c]) * inv_std[c] of feature c
+// of voice b to row row_map[b] (b without a map; rows outside [0, batch) are
+// not written) instead of the float32 features.
+struct MelStd {
+  const float* mean;
+  const float* inv_std;
+  const int64_t* row_map;
+  uint16_t* out;
+};
+
+template <bool STD>
 __global__ void __launch_bounds__(kMelThreads) __attribute__((amdgpu_waves_per_eu(2)))
 logmel_fft_kernel(const float* __restrict__ audio, const int64_t* __restrict__ offsets,
                   int64_t n_uniform, const uint16_t* __restrict__ mel, int64_t ldm,
-                  float* __restrict__ features) {
+                  float* __restrict__ features, MelStd sd) {
   constexpr int Nc = 1024, P = 16, hop = 2756, frames = 64;
   __shared__ float2 wbuf[kMelWaves][Nc];
   __shared__ MelShared ms;
@@ -368,7 +386,20 @@ logmel_fft_kernel(const float* __restrict__ audio, const int64_t* __restrict__ o
     len = n_uniform;
   }
   const float* x = audio + start;
-  float* feat = features + b * (int64_t)(kMelBands * frames);
+  float* feat = STD ? nullptr : features + b * (int64_t)(kMelBands * frames);
+  uint16_t* yrow = nullptr;
+  if constexpr (STD) {
+    const int64_t row = sd.row_map ? sd.row_map[b] : b;
+    if (row >= 0 && row < (int64_t)gridDim.x) yrow = sd.out + row * (int64_t)(kMelBands * frames);
+  }
+  // feature c of this voice takes value v
+  auto put = [&](int c, float v) {
+    if constexpr (STD) {
+      if (yrow) yrow[c] = mel_f2bf((v - sd.mean[c]) * sd.inv_std[c]);
+    } else {
+      feat[c] = v;
+    }
+  };
 
   // ---- set-up: band table (wavefront 0), twiddle table T[k] = exp(-2 pi i k / 2048) ----
   if (tid < 64) {
@@ -508,7 +539,7 @@ logmel_fft_kernel(const float* __restrict__ audio, const int64_t* __restrict__ o
     const int cnt = min(16, live - 16 * g);
     for (int e = tid; e < kMelBands * 16; e += kMelThreads) {
       const int bd = e >> 4, fr = e & 15;
-      if (fr < cnt) feat[bd * frames + 16 * g + fr] = ms.st[bd][fr];
+      if (fr < cnt) put(bd * frames + 16 * g + fr, ms.st[bd][fr]);
     }
     __syncthreads();
   }
@@ -520,7 +551,7 @@ logmel_fft_kernel(const float* __restrict__ audio, const int64_t* __restrict__ o
     const float floor_v = logf(zero + 1e-6f);
     for (int e = tid; e < kMelBands * nz; e += kMelThreads) {
       const int bd = e / nz;
-      feat[bd * frames + live + (e - bd * nz)] = floor_v;
+      put(bd * frames + live + (e - bd * nz), floor_v);
     }
   }
 }
@@ -600,8 +631,21 @@ hipError_t launch_logmel_fft(const float* audio, const int64_t* offsets, int64_t
                             hipStream_t s) {
   if (batch == 0) return hipSuccess;
   if (batch > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(logmel_fft_kernel, dim3((unsigned)batch), dim3(kMelThreads), 0, s, audio,
-                     offsets, n_uniform, (const uint16_t*)mel_basis, ldm, features);
+  hipLaunchKernelGGL(logmel_fft_kernel<false>, dim3((unsigned)batch), dim3(kMelThreads), 0, s,
+                     audio, offsets, n_uniform, (const uint16_t*)mel_basis, ldm, features,
+                     MelStd{});
+  return hipGetLastError();
+}
+
+hipError_t launch_logmel_fft_std(const float* audio, const int64_t* offsets, int64_t n_uniform,
+                                 int64_t batch, const void* mel_basis, int64_t ldm,
+                                 const float* mean, const float* inv_std, const int64_t* row_map,
+                                 void* out_bf16, hipStream_t s) {
+  if (batch == 0) return hipSuccess;
+  if (batch > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const MelStd sd{mean, inv_std, row_map, static_cast<uint16_t*>(out_bf16)};
+  hipLaunchKernelGGL(logmel_fft_kernel<true>, dim3((unsigned)batch), dim3(kMelThreads), 0, s,
+                     audio, offsets, n_uniform, (const uint16_t*)mel_basis, ldm, nullptr, sd);
   return hipGetLastError();
 }
 

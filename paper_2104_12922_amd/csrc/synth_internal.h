@@ -135,6 +135,11 @@ constexpr int kMelWeightsMax = 2304;   // nonzero mel weights over all bands
 hipError_t launch_logmel_fft(const float* audio, const int64_t* offsets, int64_t n_uniform,
                              int64_t batch, const void* mel_basis, int64_t ldm, float* features,
                              hipStream_t s);
+// The same features standardised and rounded to bf16 (see MelStd in spectral.hip).
+hipError_t launch_logmel_fft_std(const float* audio, const int64_t* offsets, int64_t n_uniform,
+                                 int64_t batch, const void* mel_basis, int64_t ldm,
+                                 const float* mean, const float* inv_std, const int64_t* row_map,
+                                 void* out_bf16, hipStream_t s);
 size_t mrstft_workspace_bytes(int64_t batch, int64_t n_samples, bool with_grad);
 // tlog: NULL (target frames transformed every call) or the target's log
 // magnitudes from launch_mrstft_target (target then unused).

@@ -30,6 +30,7 @@ def _sig(L):
     L.synth_logmel_init.argtypes = [ctypes.c_double, vp, vp, vp]
     L.synth_logmel.argtypes = [vp, vp, i64, i64, vp, vp, sz, vp, vp]
     L.synth_logmel_mfma.argtypes = [vp, vp, i64, i64, vp, vp, vp, sz, vp, vp]
+    L.synth_logmel_standardized.argtypes = [vp, vp, i64, i64, vp, vp, vp, vp, vp, vp]
     L.synth_colstats.argtypes = [vp, i32, i64, i64, i64, vp, vp, vp]
     L.synth_standardize.argtypes = [vp, vp, vp, i64, i64, vp, vp]
     L.synth_feature_stats.argtypes = [vp, i64, i64, f32, vp, vp, vp]
@@ -100,6 +101,20 @@ class LogMel:
             float(sample_rate), self.dft.data_ptr() if self.dft is not None else None,
             self.mel.data_ptr(), _stream(self.device)))
         self._ws = None
+
+    def standardized(self, audio: torch.Tensor, offsets: torch.Tensor, mean: torch.Tensor,
+                     inv_std: torch.Tensor, out: torch.Tensor, rows: torch.Tensor | None = None):
+        """bf16 standardised features of the ragged voices in one kernel
+        (FFT method): voice b's row goes to out[rows[b]] (out[b] without
+        rows); bitwise standardize(self(audio, offsets=offsets), ...)."""
+        B = offsets.numel() - 1
+        _native.check("synth_logmel_standardized", lib().synth_logmel_standardized(
+            _p(audio, "audio", F32, audio.numel()), _p(offsets, "offsets", torch.int64, B + 1),
+            B, 0, self.mel.data_ptr(), _p(mean, "mean", F32, MEL_FEATURES),
+            _p(inv_std, "inv_std", F32, MEL_FEATURES),
+            _p(rows, "rows", torch.int64, B) if rows is not None else None,
+            _p(out, "features", BF16, B * MEL_FEATURES), _stream(self.device)))
+        return out
 
     def __call__(self, audio: torch.Tensor, out: torch.Tensor | None = None,
                  offsets: torch.Tensor | None = None) -> torch.Tensor:
@@ -397,7 +412,6 @@ def train_pipelined(net: "MLP", lm: LogMel, nebula_table, mean, inv_std, steps: 
     per = torch.tensor([int(round(x * 44100.0)) for x in lengths_s], dtype=torch.int64,
                        device="cuda")
     xb = [torch.empty(G * batch, MEL_FEATURES, dtype=BF16, device="cuda") for _ in range(2)]
-    feat = [None]
     ready = [torch.cuda.Event(), torch.cuda.Event()]
     done = [torch.cuda.Event(), torch.cuda.Event()]
     us = [None, None]
@@ -415,11 +429,9 @@ def train_pipelined(net: "MLP", lm: LogMel, nebula_table, mean, inv_std, steps: 
         # [g batch, (g + 1) batch): gather them step by step
         order = torch.argsort(-per[ids % len(lengths_s)], stable=True)
         rows = torch.argsort(order // batch, stable=True)
-        f = lm(audio, offsets=offs, out=feat[0] if feat[0] is not None and
-               feat[0].shape[0] == n * batch else None)
-        feat[0] = f
-        x = standardize(f, mean, inv_std)
-        torch.index_select(x, 0, rows, out=xb[slot][:n * batch])
+        # features standardised in the log-mel kernel, each voice's row
+        # written straight to its place in the steps' order
+        lm.standardized(audio, offs, mean, inv_std, out=xb[slot], rows=torch.argsort(rows))
         us[slot] = u.index_select(0, rows)
         ready[slot].record(main)
 

@@ -289,3 +289,25 @@ def test_pipelined_training_is_bitwise_serial(L, group):
     for k in serial.names:
         assert torch.equal(serial.w[k], piped.w[k]), k
         assert torch.equal(serial.m[k], piped.m[k]) and torch.equal(serial.v[k], piped.v[k]), k
+
+
+def test_logmel_standardized_is_bitwise_two_kernels(L):
+    """synth_logmel_standardized (features standardised and rounded to bf16
+    inside the log-mel kernel, rows scattered by an index) is bitwise the
+    log-mel kernel followed by synth_standardize and the same row order."""
+    tab = W.default_nebula().table()
+    B = 96
+    lm = L.LogMel()
+    u, audio, offs = L.render_batch(W.SEED_TRAIN, L.train_ids(0, B), tab, tune=False)
+    f = lm(audio, offsets=offs)
+    mean, inv_std = L.feature_stats(f)
+    ref = L.standardize(f, mean, inv_std)
+    out = torch.empty_like(ref)
+    lm.standardized(audio, offs, mean, inv_std, out=out)
+    torch.cuda.synchronize()
+    assert torch.equal(out.view(torch.int16), ref.view(torch.int16))
+    perm = torch.randperm(B, generator=torch.Generator().manual_seed(0)).cuda()
+    out2 = torch.empty_like(ref)
+    lm.standardized(audio, offs, mean, inv_std, out=out2, rows=perm)
+    torch.cuda.synchronize()
+    assert torch.equal(out2[perm].view(torch.int16), ref.view(torch.int16))
