@@ -8,7 +8,12 @@ round_bf16=True the operands are rounded to bfloat16 at the points where the
 GPU path stores bf16 (input, weights, h1, h2, and the backward's dz3, dh2,
 dh1), so that both sides take the same quantisation decisions; accumulation
 is float64 here and float32 on the GPU.  With round_bf16=False the manual
-backward is the plain chain rule and is pinned against torch autograd.
+backward is the plain chain rule and is pinned against torch autograd; that
+plain form, given only bf16-rounded inputs and weights, is what the GPU path
+is held to (the rounding-point variant is a secondary diagnostic).
+
+adam_step is Adam (Kingma and Ba, ICLR 2015, Algorithm 1) with bias
+correction, written from that algorithm and pinned against torch.optim.Adam.
 """
 from __future__ import annotations
 
@@ -63,3 +68,16 @@ def backward(f, target, round_bf16=True):
     g["w1t"] = dh1.T @ f["x"]
     g["b1"] = dh1.sum(0)
     return loss, g
+
+
+def adam_step(w, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update at step t >= 1 (Kingma and Ba, Algorithm 1): the moment
+    estimates m, v are updated from the gradient g, bias-corrected by
+    1 - beta^t, and w moves by lr m_hat / (sqrt(v_hat) + eps).  Float64;
+    returns (w, m, v)."""
+    w, g, m, v = (torch.as_tensor(a).to(F64) for a in (w, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return w - lr * m_hat / (torch.sqrt(v_hat) + eps), m, v

@@ -78,3 +78,19 @@ def test_logmel_p16_within_bf16_rounding_of_float64():
     assert bool(loud.any())
     assert float((a - b).abs()[loud].max()) < 1e-2
     assert float((a - b).abs()[loud].median()) < 3e-3
+
+
+def test_adam_step_matches_torch_optim_adam():
+    """The oracle's Adam against the library routine (torch.optim.Adam, float64)
+    over five steps with changing gradients."""
+    g = torch.Generator().manual_seed(4)
+    w0 = torch.randn(50, generator=g, dtype=F64)
+    grads = [torch.randn(50, generator=g, dtype=F64) for _ in range(5)]
+    p = torch.nn.Parameter(w0.clone())
+    opt = torch.optim.Adam([p], lr=3e-3, betas=(0.9, 0.999), eps=1e-8)
+    w, m, v = w0.clone(), torch.zeros(50, dtype=F64), torch.zeros(50, dtype=F64)
+    for t, gk in enumerate(grads, start=1):
+        p.grad = gk.clone()
+        opt.step()
+        w, m, v = mlp.adam_step(w, gk, m, v, t, 3e-3)
+        assert torch.allclose(w, p.detach(), rtol=0, atol=1e-15), t
