@@ -84,24 +84,43 @@ __device__ __forceinline__ void real_pair(const float2* buf, const float2* rs, i
   Xm = make_float2(D.x, -D.y);
 }
 
-// log2(|T| + eps) of a target bin (hardware sqrt and log2, about 1 ulp each).
+// |X| of a bin without underflow (hardware sqrt, about 1 ulp).  Squaring the
+// components underflows for |X| below about 1e-19 (quiet release tails reach
+// that), which would drop the bin's magnitude to 0 and its gradient, whose
+// size 1 / (|X| + eps) is largest there, with it: a bin below 2^-50 is
+// scaled by 2^100 (exact) first.  Xs and as are the scaled bin and magnitude
+// (unscaled for the other bins); the result is |X|.
+__device__ __forceinline__ float bin_mag(float2 X, float2& Xs, float& as) {
+  const bool tiny = fmaxf(fabsf(X.x), fabsf(X.y)) < 0x1p-50f;
+  const float s = tiny ? 0x1p100f : 1.0f;
+  Xs = make_float2(X.x * s, X.y * s);
+  as = __builtin_amdgcn_sqrtf(Xs.x * Xs.x + Xs.y * Xs.y);
+  return tiny ? as * 0x1p-100f : as;
+}
+
+// log2(|T| + eps) of a target bin (hardware log2, about 1 ulp).
 __device__ __forceinline__ float target_log(float2 T) {
-  const float at = __builtin_amdgcn_sqrtf(T.x * T.x + T.y * T.y);
-  return __builtin_amdgcn_logf(at + kEps);
+  float2 Ts;
+  float as;
+  return __builtin_amdgcn_logf(bin_mag(T, Ts, as) + kEps);
 }
 
 // One bin's loss share (added to acc) and gradient spectrum value, from the
 // render bin X and the target's lt = target_log(T).
 __device__ __forceinline__ float2 bin_grad(float2 X, float lt, double scale_d, float scale,
                                            bool edge, bool want_grad, double& acc) {
-  // hardware sqrt, log2 and reciprocal (about 1 ulp each)
-  const float ax = __builtin_amdgcn_sqrtf(X.x * X.x + X.y * X.y);
+  // hardware log2 and reciprocal (about 1 ulp each); G = sign(d) scale
+  // X / (|X| (|X| + eps)) = sign(d) scale Xs / (as (|X| + eps)), whose
+  // denominator stays a normal float32 for every bin
+  float2 Xs;
+  float as;
+  const float ax = bin_mag(X, Xs, as);
   const float d = 0.69314718055994531f * (__builtin_amdgcn_logf(ax + kEps) - lt);
   acc += scale_d * (double)fabsf(d);
   float2 G = make_float2(0.f, 0.f);
-  if (want_grad && ax > 0.0f && d != 0.0f) {
-    const float gm = copysignf(scale, d) * __builtin_amdgcn_rcpf((ax + kEps) * ax);
-    G = make_float2(gm * X.x, gm * X.y);
+  if (want_grad && as > 0.0f && d != 0.0f) {
+    const float gm = copysignf(scale, d) * __builtin_amdgcn_rcpf((ax + kEps) * as);
+    G = make_float2(gm * Xs.x, gm * Xs.y);
   }
   if (edge) G = make_float2(2.0f * G.x, 0.0f);
   return G;
@@ -379,8 +398,7 @@ logmel_fft_kernel(const float* __restrict__ audio, const int64_t* __restrict__ o
   const int64_t b = blockIdx.x;
   int64_t start, len;
   if (offsets) {
-    start = offsets[b];
-    len = offsets[b + 1] - start;
+    packed_range(offsets, (int64_t)gridDim.x, b, start, len);
   } else {
     start = b * n_uniform;
     len = n_uniform;

@@ -1,12 +1,16 @@
 """GPU parity of the multi-resolution STFT loss and its gradient against the
 float64 oracle (autograd of the oracle loss), through the C ABI.
 
-Tolerances come from the arithmetic: evaluating the same definition with
-float32 FFTs on the CPU moves the per-voice loss by < 2e-7 relative and the
-gradient by up to ~2e-3 relative L2 (more for very quiet voices: bins near the
-float32 noise floor, where d log|X| / d|X| = 1 / (|X| + 1e-5) is large).  The
-GPU kernel is held to 1e-5 on the loss and, per voice, to max(1e-2, 10x the
-CPU float32 evaluation's error) on the gradient.
+Tolerances come from the arithmetic.  The loss is a mean of float32 log
+differences accumulated in float64: 1e-5 relative.  The gradient is compared
+element by element, per voice, relative to the voice's largest gradient
+magnitude: e = max_n |g(n) - g_ref(n)| / max_n |g_ref(n)|.  The float32
+floor of that measure is what the same definition evaluated with float32
+FFTs and float32 autograd on the CPU (``loss32``) reaches, e32; both
+evaluations round the frame, the transform, |X| and the log in float32, and
+the GPU's transform and hardware log2 / sqrt / reciprocal add a few ulp per
+step, so the GPU is held to e <= 16 e32 for every voice (no absolute floor).
+A voice with an exactly zero reference gradient must get exactly zero.
 """
 import sys
 
@@ -47,7 +51,10 @@ def loss32(x, t):
     return tot
 
 
-def check(synth, x32, t32, loss_rtol=1e-5, grad_rtol=1e-2):
+GRAD_FACTOR = 16.0
+
+
+def check(synth, x32, t32, loss_rtol=1e-5, factor=GRAD_FACTOR):
     x64, t64 = x32.double(), t32.double()
     xr = x64.clone().requires_grad_(True)
     ref = sp.mrstft_loss_per_voice(xr, t64)
@@ -61,13 +68,15 @@ def check(synth, x32, t32, loss_rtol=1e-5, grad_rtol=1e-2):
     assert torch.allclose(loss, ref.detach(), rtol=loss_rtol, atol=1e-9)
     for b in range(x32.shape[0]):
         gr = xr.grad[b]
-        if gr.norm() == 0:
-            assert g[b].abs().max() == 0
+        gmax = float(gr.abs().max())
+        if gmax == 0:
+            assert float(g[b].abs().max()) == 0.0
             continue
-        err = float((g[b] - gr).norm() / gr.norm())
-        err32 = float((xf.grad[b].double() - gr).norm() / gr.norm())
-        print("voice", b, "grad rel L2", err, "cpu float32", err32, file=sys.stderr, flush=True)
-        assert err <= max(grad_rtol, 10 * err32), (b, err, err32)
+        err = float((g[b] - gr).abs().max()) / gmax
+        err32 = float((xf.grad[b].double() - gr).abs().max()) / gmax
+        print("voice", b, "grad max-abs rel %.3e" % err, "cpu float32 %.3e" % err32,
+              "ratio %.2f" % (err / err32 if err32 > 0 else float("inf")), file=sys.stderr, flush=True)
+        assert err <= factor * err32, (b, err, err32)
 
 
 def test_mrstft_loss_and_grad_4s(synth):
@@ -116,8 +125,22 @@ def test_mrstft_gradient_batch_b256_4s_sampled(synth):
     loss, g = synth.synth_mrstft_loss(x, t, grad=True)
     torch.cuda.synchronize()
     assert bool(torch.isfinite(loss).all()) and bool(torch.isfinite(g).all())
-    pick = [0, 77, 128, 255]
+    pick = list(range(0, 256, 17)) + [255]
     check(synth, x[pick].cpu(), t[pick].cpu())
+
+
+def test_mrstft_gradient_of_tiny_bins(synth):
+    """Bins far below float32's squared range (|X| around 1e-22, as in quiet
+    release tails) keep their magnitude and their gradient, whose size
+    1 / (|X| + 1e-5) is the largest any bin has."""
+    g = torch.Generator().manual_seed(5)
+    x = torch.randn(3, 6000, generator=g) * 0.3
+    x[0] *= 1e-21                       # every bin tiny
+    x[1, 3000:] *= 1e-24                # a tiny second half
+    x[2, :2500] *= 1e-30                # tiny frames ahead of loud ones
+    t = torch.randn(3, 6000, generator=g) * 0.3
+    t[2] *= 1e-22                       # tiny target
+    check(synth, x, t)
 
 
 @pytest.mark.parametrize("B,N", [(3, 300), (3, 600), (5, 5000), (4, 44100), (256, 176400)])
