@@ -82,12 +82,13 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
   const double midi = v[0];
   const double m_hi = fmax(0.0, midi + v[71] + fmax(0.0, v[72]));
   const double f_hi = fmin(440.0 * exp2((m_hi - 69.0) / 12.0), sr / 2.0);
-  const float K = (float)(12000.0 / (f_hi * log10(f_hi)));
-  const float K2 = (float)(2.0 * 1.4426950408889634 * 12000.0 / (f_hi * log10(f_hi)));
+  const double Kd = 12000.0 / (f_hi * log10(f_hi));
   const float shape = (float)v[74];
   const float cg = (float)(1.0 - v[74] / 2.0);
+  const double shape_d = v[74], cg2pi_d = (1.0 - v[74] / 2.0) * kTwoPi, L2d = v[76];
+  const double L1d_2pi = v[75] * kTwoPi;
+  constexpr double kM2Log2e = -2.0 * 1.4426950408889634;   // exp(-2|z|) = 2^(kM2Log2e |z|)
   const float L1 = (float)v[75], L2 = (float)v[76], L3 = (float)v[77];
-  const float two_pi = 6.28318530717958647692f;
   const uint32_t glo = (uint32_t)g, ghi = (uint32_t)(g >> 32);
 
   int64_t c_start = 0;
@@ -110,8 +111,10 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
     control_stage<RPS, false>(a, sh, reinterpret_cast<double*>(tile), c, J, h, lane, y, yn);
     if (c < c_lo) continue;                      // slice starts later: only carries needed
     // unscaled VCA ramps of this lane's segment
-    const float a10 = (float)y[1], a1d = (float)((yn[1] - y[1]) / qd);
-    const float a30 = (float)y[3], a3d = (float)((yn[3] - y[3]) / qd);
+    const double a10_d = y[1], a1d_d = (yn[1] - y[1]) / qd;   // float64 ramp for the phase adjoint
+    const float a10 = (float)a10_d, a1d = (float)a1d_d;
+    const double a30_d = y[3], a3d_d = (yn[3] - y[3]) / qd;   // float64 ramp for the phase adjoint
+    const float a30 = (float)a30_d, a3d = (float)a3d_d;
     const float a40 = (float)y[4], a4d = (float)((yn[4] - y[4]) / qd);
     __syncthreads();
 
@@ -169,7 +172,9 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
         }
       }
       const float A10 = __shfl(a10, src), A1d = __shfl(a1d, src);
+      const double A10d = __shfl(a10_d, src), A1dd = __shfl(a1d_d, src);
       const float A30 = __shfl(a30, src), A3d = __shfl(a3d, src);
+      const double A30d = __shfl(a30_d, src), A3dd = __shfl(a3d_d, src);
       const float A40 = __shfl(a40, src), A4d = __shfl(a4d, src);
       double acc[kNumRed];
 #pragma unroll
@@ -195,26 +200,35 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
         const float gk = seg_valid ? tg[lane * h + k] : 0.0f;
         const float gnk = seg_valid ? tgn[lane * h + k] : 0.0f;
         const float a1 = fmaf(kf, A1d, A10), a3 = fmaf(kf, A3d, A30), a4 = fmaf(kf, A4d, A40);
-        // sine VCO
+        // sine VCO (its phase adjoint in float64 for the reason given below)
         const float r1f = (float)(t1 - rint(t1));
-        const float x1 = __builtin_amdgcn_sinf(r1f), c1 = __builtin_amdgcn_cosf(r1f);
-        const float dth1 = gk * L1 * a1 * two_pi * c1;
-        // square-saw VCO: T = tanh(K s), sech^2 = 4e/(1+e)^2 with e = exp(-2|K s|)
-        float s2f, c2f;
-        sincos_cycles(t2, s2f, c2f);
-        const float z2 = K2 * s2f;
-        const float e = __builtin_amdgcn_exp2f(-fabsf(z2));
-        const float ri = __builtin_amdgcn_rcpf(1.0f + e);
-        const float T = copysignf((1.0f - e) * ri, z2);
-        const float sech2 = 4.0f * e * ri * ri;
-        const float Q = fmaf(shape, c2f, 1.0f);
+        const float x1 = __builtin_amdgcn_sinf(r1f);
+        const double dth1 = (double)gk * L1d_2pi * fma((double)ks, A1dd, A10d) * cos_cycles_f64(t1);
+        // square-saw VCO: T = tanh(K s), sech^2 = 4e/(1+e)^2 with e = exp(-2|K s|).
+        // Its phase adjoint is a sum over the voice of terms of both signs that
+        // the tanh edge scales by up to 2 pi K; for pitch parameters the sum can
+        // be 1e6 times smaller than the sum of its magnitudes, so float32
+        // rounding of the terms (the hardware sine and exponential, the VCA
+        // ramp) would dominate it.  The term is evaluated in float64.
+        double s2, c2;
+        sincos_cycles_f64(t2, s2, c2);
+        const double zd = Kd * s2;
+        const double e = exp2_f64(kM2Log2e * fabs(zd));
+        const double de = 1.0 + e;
+        double ri = __builtin_amdgcn_rcp(de);
+        ri = fma(fma(-de, ri, 1.0), ri, ri);
+        ri = fma(fma(-de, ri, 1.0), ri, ri);
+        const double Td = copysign((1.0 - e) * ri, zd);
+        const double sech2 = 4.0 * e * ri * ri;
+        const double Qd = fma(shape_d, c2, 1.0);
+        const double gl2a3d = (double)gk * L2d * fma((double)ks, A3dd, A30d);
+        const double dth2 = gl2a3d * cg2pi_d * (sech2 * Kd * c2 * Qd - Td * shape_d * s2);
+        const float s2f = (float)s2, c2f = (float)c2, T = (float)Td, Q = (float)Qd;
         const float x2 = cg * T * Q;
-        const float dx2 = cg * two_pi * (sech2 * K * c2f * Q - T * shape * s2f);
         const float gl2a3 = gk * L2 * a3;
-        const float dth2 = gl2a3 * dx2;
         // phase-adjoint reductions (float64)
-        P1 += (double)dth1;
-        P2 += (double)dth2;
+        P1 += dth1;
+        P2 += dth2;
         const double l1 = live * i1, l2 = live * i2;
         acc[kRC01] += wt0 * l1;
         acc[kRC11] += wt1 * l1;
@@ -236,7 +250,7 @@ __global__ void __launch_bounds__(kWave) adjoint_audio_kernel(const RenderArgs a
         fa[kRL2 - kRA01] += gk * x2 * a3;
         fa[kRL3 - kRA01] += gnk * a4;
         fa[kRShape - kRA01] += gl2a3 * (cg * T * c2f - 0.5f * T * Q);
-        fa[kRK - kRA01] += gl2a3 * cg * sech2 * s2f * Q;
+        fa[kRK - kRA01] += gl2a3 * cg * (float)sech2 * s2f * Q;
         t1 += i1; i1 *= r1;
         t2 += i2; i2 *= r2;
       }

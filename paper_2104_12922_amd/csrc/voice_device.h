@@ -97,6 +97,62 @@ __device__ __forceinline__ double sin_cycles_f64(double p) {
   return s * a;
 }
 
+// sin(2 pi th) and cos(2 pi th) in float64: th is reduced to the nearest half
+// cycle, r = th - n/2 in [-1/4, 1/4] (exact), a = 2 pi r, and the Taylor
+// series of sin a to degree 23 and cos a to degree 22 (|a| <= pi/2:
+// truncation below 4e-18) give sin(2 pi th) = (-1)^n sin a, cos(2 pi th) =
+// (-1)^n cos a.
+__device__ __forceinline__ void sincos_cycles_f64(double th, double& s, double& c) {
+  const double n = rint(2.0 * th);
+  const double a = fma(-0.5, n, th) * kTwoPi, a2 = a * a;
+  double ps = -1.0 / 25852016738884976640000.0;      // -1/23!
+  ps = fma(ps, a2, 1.0 / 51090942171709440000.0);
+  ps = fma(ps, a2, -1.0 / 121645100408832000.0);
+  ps = fma(ps, a2, 1.0 / 355687428096000.0);
+  ps = fma(ps, a2, -1.0 / 1307674368000.0);
+  ps = fma(ps, a2, 1.0 / 6227020800.0);
+  ps = fma(ps, a2, -1.0 / 39916800.0);
+  ps = fma(ps, a2, 1.0 / 362880.0);
+  ps = fma(ps, a2, -1.0 / 5040.0);
+  ps = fma(ps, a2, 1.0 / 120.0);
+  ps = fma(ps, a2, -1.0 / 6.0);
+  ps = fma(ps, a2, 1.0);
+  double pc = 1.0 / 1124000727777607680000.0;       // 1/22!
+  pc = fma(pc, a2, -1.0 / 2432902008176640000.0);
+  pc = fma(pc, a2, 1.0 / 6402373705728000.0);
+  pc = fma(pc, a2, -1.0 / 20922789888000.0);
+  pc = fma(pc, a2, 1.0 / 87178291200.0);
+  pc = fma(pc, a2, -1.0 / 479001600.0);
+  pc = fma(pc, a2, 1.0 / 3628800.0);
+  pc = fma(pc, a2, -1.0 / 40320.0);
+  pc = fma(pc, a2, 1.0 / 720.0);
+  pc = fma(pc, a2, -1.0 / 24.0);
+  pc = fma(pc, a2, 0.5);
+  pc = fma(pc, -a2, 1.0);
+  const double sg = (((int)n) & 1) ? -1.0 : 1.0;
+  s = sg * (ps * a);
+  c = sg * pc;
+}
+
+// cos(2 pi th) in float64 by the reduction and series of sincos_cycles_f64.
+__device__ __forceinline__ double cos_cycles_f64(double th) {
+  const double n = rint(2.0 * th);
+  const double a = fma(-0.5, n, th) * kTwoPi, a2 = a * a;
+  double pc = 1.0 / 1124000727777607680000.0;       // 1/22!
+  pc = fma(pc, a2, -1.0 / 2432902008176640000.0);
+  pc = fma(pc, a2, 1.0 / 6402373705728000.0);
+  pc = fma(pc, a2, -1.0 / 20922789888000.0);
+  pc = fma(pc, a2, 1.0 / 87178291200.0);
+  pc = fma(pc, a2, -1.0 / 479001600.0);
+  pc = fma(pc, a2, 1.0 / 3628800.0);
+  pc = fma(pc, a2, -1.0 / 40320.0);
+  pc = fma(pc, a2, 1.0 / 720.0);
+  pc = fma(pc, a2, -1.0 / 24.0);
+  pc = fma(pc, a2, 0.5);
+  pc = fma(pc, -a2, 1.0);
+  return (((int)n) & 1) ? -pc : pc;
+}
+
 // x^e for x in [0, 1] (0^e = 0, 1^e = 1 without evaluating exp2/log2); in
 // (0, 1) within about 1e-13 relative of the correctly rounded power.
 __device__ __forceinline__ double pow01(double x, double e) {

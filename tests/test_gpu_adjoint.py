@@ -2,10 +2,12 @@
 against the float64 oracle's exact gradient (torch autograd), through the C ABI.
 
 Criterion per voice (R25 form): |g_gpu - g_ref| <= tol * max(|g_ref|,
-1e-3 * max|g_ref|) for every parameter.  The adjoint's forward recompute and
-derivative terms run in float32 per sample with float64 reductions; the
-parameter gradients are sums over ~1e4-1e5 samples whose float32 rounding
-errors average out, so tol = 5e-3.
+1e-3 * max|g_ref|) for every parameter, tol = 1e-3.  The adjoint's forward
+recompute follows the render's float64 phase recurrences; the square-saw's
+phase adjoint, a sum of large terms of both signs whose total can be 1e6
+times smaller than their magnitudes for pitch parameters, is evaluated in
+float64; the remaining float32 terms (sine VCO, amplitude-side sums) reach
+about 1e-4.
 """
 import sys
 
@@ -17,7 +19,7 @@ import workloads as W
 from oracle import philox, spectral as sp, voice
 
 pytestmark = pytest.mark.gpu
-TOL = 5e-3
+TOL = 1e-3
 
 
 @pytest.fixture(scope="module")
@@ -126,31 +128,25 @@ def test_adjoint_argument_errors(synth, nebula_table):
     assert need == 2 * (10 * 21 + 1 * 88) * 8          # segment sums + one chunk's carries and totals
 
 
-def test_adjoint_gradient_workload_b256_4s(synth):
-    """Gradient workload at full size: 256 voices x 4 s, loss against targets of
-    another seed; all gradients finite, two voices compared with the oracle."""
+def test_adjoint_gradient_workload_all_256_voices(synth):
+    """Gradient workload at full size: 256 voices x 4 s from seed 0, cotangent =
+    the GPU MR-STFT gradient against targets of seed 1; the batched GPU adjoint
+    against the oracle's autograd with the same cotangent, every voice."""
     wl = W.gradient_batch()
     tab = wl.nebula.table()
+    N = 176400
     u = synth.synth_sample_params(wl.seed, 0, wl.batch)
     ut = synth.synth_sample_params(W.SEED_TARGET, 0, wl.batch)
-    t = synth.synth_render(ut, tab, n_samples=176400, noise_seed=W.SEED_TARGET)
-    p = u.clone().requires_grad_(True)
-    y = synth.SynthRender.apply(p, tab, 176400, 0, wl.seed)
-    loss = synth.MRSTFTLoss.apply(y, t)
-    loss.sum().backward()
+    t = synth.synth_render(ut, tab, n_samples=N, noise_seed=W.SEED_TARGET)
+    y = synth.synth_render(u, tab, n_samples=N, noise_seed=wl.seed)
+    g_audio = synth.synth_mrstft_loss(y, t, grad=True)[1]
+    ga = synth.synth_render_backward(u, g_audio, tab, noise_seed=wl.seed)
     torch.cuda.synchronize()
-    assert bool(torch.isfinite(p.grad).all())
-    g_audio = synth.synth_mrstft_loss(y.detach(), t, grad=True)[1]
-    pick = [0, 255]
-    uu = u[pick].cpu().numpy().astype(np.float64)
-    ref = oracle_grad(uu, g_audio[pick].cpu().numpy().astype(np.float64), 176400, tab,
-                      noise_seed=wl.seed)
-    # same cotangent through the GPU adjoint directly (ids 0 and 255)
-    ga = np.stack([synth.synth_render_backward(u[i:i + 1].contiguous(), g_audio[i:i + 1].contiguous(),
-                                               tab, first_g=i, noise_seed=wl.seed)[0].cpu().numpy()
-                   for i in pick]).astype(np.float64)
-    ref0 = oracle_grad(uu[:1], g_audio[:1].cpu().numpy().astype(np.float64), 176400, tab,
-                       noise_seed=wl.seed, first_g=0)
-    ref1 = oracle_grad(uu[1:], g_audio[255:256].cpu().numpy().astype(np.float64), 176400, tab,
-                       noise_seed=wl.seed, first_g=255)
-    check(ga, np.concatenate([ref0, ref1]))
+    ga = ga.cpu().numpy().astype(np.float64)
+    uu = u.cpu().numpy().astype(np.float64)
+    gc = g_audio.cpu().numpy().astype(np.float64)
+    ref = np.concatenate([oracle_grad(uu[i:i + 32], gc[i:i + 32], N, tab, noise_seed=wl.seed,
+                                      first_g=i) for i in range(0, wl.batch, 32)])
+    check(ga, ref)
+
+
