@@ -1,13 +1,31 @@
 """GPU parity of the learned proposal's kernels (bf16 MFMA GEMM with fused
-epilogues, log-mel features, MLP forward/backward, Adam) against float64
-references that take the same bf16 quantisation decisions.
+epilogues, log-mel features, MLP forward/backward, Adam) against the plain
+float64 definitions in the oracle, element by element.
 
-Tolerances: the GPU accumulates in float32 (relative ~1e-6 for K <= 8192);
-bf16 stores of intermediates can round a value one bf16 ulp (2^-8) the other
-way when the float32 and float64 accumulations straddle a rounding tie, which
-moves downstream results by O(1e-5) relative.  GEMM/MLP results are held to
-2e-3 relative L2; log-mel to 5e-3 absolute (one bf16 ulp of a band's dominant
-power term) with a median below 1e-4.
+Tolerances come from bf16's unit roundoff u = 2^-8 (8 significant bits):
+
+* log-mel (each of the 128 x 64 features of a voice, against
+  ``oracle.spectral.logmel``): the power spectrum and the mel basis are
+  rounded to bf16 (relative error <= u each, so <= 2u + u^2 on a band's sum
+  of nonnegative terms), and the transform adds an absolute error delta per
+  bin: float32 FFT (FFT path) delta = 16 * 2^-24 sqrt(log2 2048) ||y||_2, or
+  frames and DFT basis rounded to bf16 (matrix-core path) delta = 4 u ||y||_2
+  (4 standard deviations of a sum of independently rounded terms), with y the
+  windowed frame.  |X|^2 then moves by <= 2 |X| delta + delta^2, and a
+  feature log(m + 1e-6) by <= log1p((2.01 u m + sum_k M_bk (2 |X_k| delta +
+  delta^2)) / (m + 1e-6)), plus 4 float32 ulp of the feature for the log and
+  the float32 result.
+* MLP (against ``oracle.mlp.forward`` / ``backward`` in float64 given only the
+  bf16-rounded inputs and weights the GPU reads): the GPU also stores the
+  activations h1, h2 and the backward's dz3, dh2, dh1 in bf16 (one rounding
+  <= u each on the way to every result; float32 accumulation adds ~1e-6), so
+  each output row is held to 2.5 u ~ 1e-2 of its largest magnitude and each
+  gradient row (one hidden or output unit's weights; a bias vector is one row)
+  to 5 u ~ 2e-2.  Measured on the CPU with the same rounding points at batch
+  4096: 0.8 u and 1.5 u.
+
+The references that round at the kernels' own points (``logmel_p16``,
+``logmel_bf16``, ``round_bf16=True``) remain as secondary, tighter checks.
 """
 import sys
 
@@ -28,6 +46,49 @@ def L():
         pytest.skip("needs a GPU")
     from paper_2104_12922_amd import learned
     return learned
+
+
+U_BF16 = 2.0 ** -8
+
+
+def rowmax_rel(a, b):
+    """max over rows of max |a - b| / max |b| (a vector is one row)."""
+    a = torch.as_tensor(a, dtype=torch.float64)
+    b = torch.as_tensor(b, dtype=torch.float64)
+    if b.dim() == 1:
+        a, b = a[None], b[None]
+    a, b = a.reshape(b.shape[0], -1), b.reshape(b.shape[0], -1)
+    return float(((a - b).abs().amax(-1) / b.abs().amax(-1).clamp(min=1e-300)).max())
+
+
+def logmel_tolerance(x, method, sr=44100.0):
+    """Per-feature error bound [B, 128, 64] of the GPU log-mel against the
+    float64 definition (module docstring)."""
+    y = sp.frames(x.double(), sp.MEL_NFFT, sp.MEL_HOP, count=sp.MEL_FRAMES) * sp.hann(sp.MEL_NFFT)
+    l2 = y.pow(2).sum(-1).sqrt()[:, None, :]                               # [B, 1, 64]
+    X = torch.fft.rfft(y, dim=-1).abs()                                    # [B, 64, 1025]
+    M = torch.from_numpy(sp.mel_filterbank(sr))
+    m = torch.einsum("bk,ntk->nbt", M, X * X)
+    MX = torch.einsum("bk,ntk->nbt", M, X)
+    W1 = M.sum(-1)[None, :, None]
+    if method == "fft":
+        delta = 16.0 * 2.0 ** -24 * np.sqrt(np.log2(sp.MEL_NFFT)) * l2
+    else:
+        delta = 4.0 * U_BF16 * l2
+    # the float32 log (a few ulp) and the float32 feature itself
+    out32 = 4.0 * 2.0 ** -24 * torch.log(m + sp.MEL_EPS).abs()
+    return torch.log1p((2.01 * U_BF16 * m + 2.0 * MX * delta + W1 * delta * delta) / (m + sp.MEL_EPS)) + out32
+
+
+def check_logmel_plain(feat, x, method, sr=44100.0):
+    B = x.shape[0]
+    ref = sp.logmel(x.double(), sr=sr)
+    tol = logmel_tolerance(x, method, sr)
+    d = (feat.cpu().double().reshape(B, 128, 64) - ref).abs()
+    r = d / tol
+    print(method, sr, "vs float64 logmel: max abs %.3e, max err/bound %.3f" % (float(d.max()), float(r.max())),
+          file=sys.stderr, flush=True)
+    assert bool((d <= tol).all()), (float(r.max()), int(r.argmax()))
 
 
 def rel(a, b):
@@ -69,13 +130,16 @@ def test_gemm_epilogues(L, epi):
 
 
 @pytest.mark.parametrize("method", ["fft", "mfma"])
-def test_logmel_matches_bf16_reference(L, method):
-    """FFT path against the reference rounding P and the mel basis to bf16;
-    MFMA path against the reference rounding frames, basis, P and mel to bf16."""
+def test_logmel_matches_definition(L, method):
+    """Every feature of 6 rendered 4 s voices against the float64 definition,
+    within the bf16 bound; secondary: the FFT path against the reference
+    rounding P and the mel basis to bf16, the MFMA path against the reference
+    rounding frames, basis, P and mel to bf16."""
     u = philox.sample_params(0, np.arange(6))
     x = voice.render_uniform(torch.tensor(u), np.arange(6), 176400, W.default_nebula().table()).float()
     feat = L.LogMel(method=method)(x.cuda())
     torch.cuda.synchronize()
+    check_logmel_plain(feat, x, method)
     ref = (sp.logmel_p16 if method == "fft" else sp.logmel_bf16)(x.double()).reshape(6, -1)
     d = (feat.cpu().double() - ref).abs()
     print(method, "logmel max abs", float(d.max()), "median", float(d.median()), file=sys.stderr)
@@ -95,6 +159,7 @@ def test_logmel_fft_other_sample_rates(L, sr):
     x[:, :n4] = torch.randn(3, n4, generator=g) * 0.3
     feat = L.LogMel(sample_rate=sr)(x.cuda())
     torch.cuda.synchronize()
+    check_logmel_plain(feat, x, "fft", sr)
     ref = sp.logmel_p16(x.double(), sr=sr).reshape(3, -1)
     d = (feat.cpu().double() - ref).abs()
     print(sr, "logmel max abs", float(d.max()), "median", float(d.median()), file=sys.stderr)
@@ -102,15 +167,17 @@ def test_logmel_fft_other_sample_rates(L, sr):
     assert float(d.max()) < 5e-3
 
 
-@pytest.mark.parametrize("split_k", [True, False])
-def test_mlp_forward_backward_full_size(L, split_k):
-    """8192 -> 1024 -> 1024 -> 78 at batch 512 against the float64 reference;
-    with split_k every GEMM but dh2 and dW1 splits its reduction."""
+@pytest.mark.parametrize("B,split_k", [(4096, True), (512, True), (512, False)])
+def test_mlp_forward_backward_full_size(L, B, split_k):
+    """8192 -> 1024 -> 1024 -> 78 at the training batch (4096, with the split-K
+    plan the training loop uses) and at 512, against the plain float64
+    forward and chain rule on the bf16-rounded inputs and weights, element by
+    element per row (module docstring); secondary: the reference that rounds
+    h1, h2, dz3, dh2 and dh1 where the GPU stores bf16, by relative L2."""
     w = W.mlp_init(0)
     rng = np.random.default_rng(1)
     for k, n in (("b1", 1024), ("b2", 1024), ("b3", 78)):
         w[k] = (rng.standard_normal(n) * 0.05).astype(np.float32)
-    B = 512
     x = torch.tensor(rng.standard_normal((B, 8192)), dtype=torch.float32)
     t = torch.tensor(rng.random((B, 78)), dtype=torch.float32)
     net = L.MLP(w, split_k=split_k)
@@ -125,14 +192,24 @@ def test_mlp_forward_backward_full_size(L, split_k):
         net.backward(xb, t.cuda())
         assert torch.equal(out2, out)
         assert all(torch.equal(first[k], net.g[k]) for k in first)
-    f = omlp.forward(x.double(), w, round_bf16=True)
-    ref_loss, g = omlp.backward(f, t.double(), round_bf16=True)
-    assert rel(out.cpu(), f["out"]) < 2e-3
-    assert abs(float(loss) - float(ref_loss)) < 1e-6 * max(1.0, float(ref_loss)) + 1e-7
+    wq = dict(w)
+    for k in ("w1t", "w2t", "w3t"):
+        wq[k] = net.wb[k].cpu().double()             # the bf16 weights the GEMMs read
+    f = omlp.forward(xb.cpu().double(), wq, round_bf16=False)
+    ref_loss, g = omlp.backward(f, t.double(), round_bf16=False)
+    e = rowmax_rel(out.cpu(), f["out"])
+    print("B", B, "out row-max rel %.3e (bound %.3e)" % (e, 2.5 * U_BF16), file=sys.stderr)
+    assert e <= 2.5 * U_BF16
+    assert abs(float(loss) - float(ref_loss)) <= 2.5 * U_BF16 * float(ref_loss)
     for k in ("w1t", "b1", "w2t", "b2", "w3t", "b3"):
-        e = rel(net.g[k].cpu(), g[k])
-        print(k, "rel L2", e, file=sys.stderr)
-        assert e < 2e-3, (k, e)
+        e = rowmax_rel(net.g[k].cpu(), g[k])
+        print(k, "row-max rel %.3e (bound %.3e)" % (e, 5 * U_BF16), file=sys.stderr)
+        assert e <= 5 * U_BF16, (k, e)
+    fr = omlp.forward(x.double(), w, round_bf16=True)
+    _, gr = omlp.backward(fr, t.double(), round_bf16=True)
+    assert rel(out.cpu(), fr["out"]) < 2e-3
+    for k in ("w1t", "b1", "w2t", "b2", "w3t", "b3"):
+        assert rel(net.g[k].cpu(), gr[k]) < 2e-3, k
 
 
 def test_adam_step(L):
@@ -147,11 +224,12 @@ def test_adam_step(L):
     for k in grads:
         gk = grads[k].cpu().double()
         w, m, v = before[k].double(), torch.zeros_like(gk), torch.zeros_like(gk)
-        for t in (1, 2):     # bias-corrected Adam, written out in float64
-            m = 0.9 * m + 0.1 * gk
-            v = 0.999 * v + 0.001 * gk * gk
-            w = w - 1e-2 * (m / (1 - 0.9 ** t)) / (torch.sqrt(v / (1 - 0.999 ** t)) + 1e-8)
-        assert torch.allclose(net.w[k].cpu().double(), w, atol=1e-6), k
+        for t in (1, 2):
+            w, m, v = omlp.adam_step(w, gk, m, v, t, 1e-2)
+        assert torch.allclose(net.w[k].cpu().double(), w, rtol=0, atol=1e-6), k
+        assert torch.allclose(net.m[k].cpu().double(), m, rtol=1e-6, atol=1e-12), k
+        # beta2 is a float32 on the GPU: 1 - 0.999f differs from 0.001 by 1.3e-5 relative
+        assert torch.allclose(net.v[k].cpu().double(), v, rtol=3e-5, atol=1e-12), k
     assert torch.equal(net.wb["w1t"].cpu(), net.w["w1t"].cpu().to(BF))
 
 
@@ -174,7 +252,8 @@ def test_short_training_reduces_loss(L):
     predicting 0.5 (1/12); most of the 78 parameters are barely observable in
     a log-mel spectrogram, so the mean over all of them moves little."""
     tab = W.default_nebula().table()
-    prop, hist = L.train_proposal(tab, steps=300, batch=256, seed=W.SEED_TRAIN, warmup=50)
+    prop, hist = L.train_proposal(tab, steps=300, init=W.mlp_init(0), batch=256, seed=W.SEED_TRAIN,
+                                  warmup=50)
     per = L.heldout_mse(prop, tab, seed=W.SEED_HELDOUT, count=512, batch=256, per_param=True)
     print("train loss first/last", hist[0][1], hist[-1][1], "held-out MSE", float(per.mean()),
           "midi", float(per[0]), "duration", float(per[1]), file=sys.stderr)
@@ -202,6 +281,7 @@ def test_logmel_ragged_and_short_voices_read_as_zero_padded(L, method):
     fs = lm(full[:, :50000].contiguous().cuda())          # uniform but shorter than the frames span
     torch.cuda.synchronize()
     assert torch.equal(fr.cpu(), fp.cpu())
+    check_logmel_plain(fr, padded, method)
     ref = (sp.logmel_p16 if method == "fft" else sp.logmel_bf16)(padded.double()).reshape(4, -1)
     d = (fr.cpu().double() - ref).abs()
     assert float(d.median()) < 1e-4 and float(d.max()) < 5e-3
