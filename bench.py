@@ -8,8 +8,9 @@ one pass of the hot path over the batch: the parameter draw (Philox) and the
 fused render, with every input resident in HBM before the timed region.
 
 Prints one JSON line: rendered samples/s (and MHz, x real time), the render
-kernel's HBM roofline fraction measured with HIP events on its stream, and the
-float64 CPU oracle timed on a bounded sample of the same workload.
+kernel's HBM roofline fraction (algorithmic bytes over its average launch time,
+measured with HIP events on its stream; its VALU issue rate beside it), and
+the float64 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -70,11 +71,17 @@ def parse():
     ap.add_argument("--autotune", type=int, default=1,
                     help="time the candidate launch plans on this batch first (untimed) and "
                          "render with the fastest")
-    ap.add_argument("--workload", default="render", choices=("render", "plain", "learned", "grad"),
+    ap.add_argument("--no-match", action="store_true",
+                    help="leave the sound-matching experiment out of the headline line")
+    ap.add_argument("--match-targets", type=int, default=4096)
+    ap.add_argument("--match-train-steps", type=int, default=12208)
+    ap.add_argument("--workload", default="render",
+                    choices=("render", "plain", "learned", "grad", "match"),
                     help="render: the headline ragged render; plain: 128 voices x 4 s "
                          "(200 renders per timed step, in a HIP graph); learned: one proposal "
                          "training step (render + log-mel + MLP); grad: render, MR-STFT "
-                         "loss and gradient, render adjoint")
+                         "loss and gradient, render adjoint; match: the sound-matching "
+                         "experiment alone")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (the "
                          "reference point that scales HBM byte counters) and exit")
@@ -314,6 +321,180 @@ def bench_grad(args):
     print(json.dumps(out), flush=True)
 
 
+def sound_match(targets=4096, train_steps=12208, train_batch=4096, steps=50, lr=0.05,
+                rs_budget=1000, budget_gb=64.0, concurrency=4, log=None):
+    """Sound matching (the second half of the headline metric): train the
+    learned proposal on 12208 x 4096 = 5e7 voices rendered on the fly (seed
+    10), report its held-out parameter MSE and re-rendered log-mel L1 (seed
+    11), then match targets of 1-4 s (length 1 + g mod 4 s, seed 20) three
+    ways - proposal + 50 Adam steps through the adjoint, random start + 50
+    steps (the no-MLP ablation), random search with 1000 draws (seed 21) -
+    and report the mean MR-STFT L1 and log-mel L1 of the best render after
+    1, 10, 51, 100 and 1000 renders per target; then serve the targets as
+    queued requests (memory-budget admission) for p50/p99 latency."""
+    import torch
+    import workloads as W
+    import paper_2104_12922_amd as S
+    from paper_2104_12922_amd import learned as Lr, matching as M
+    say = log or (lambda *a: None)
+    tab = W.default_nebula().table()
+    out = {"targets": targets, "adam_steps": steps, "lr": lr}
+    t0 = time.perf_counter()
+    prop, hist = Lr.train_proposal(tab, train_steps, init=W.mlp_init(0), batch=train_batch,
+                                   seed=W.SEED_TRAIN)
+    torch.cuda.synchronize()
+    out["train"] = {"steps": train_steps, "batch": train_batch, "voices": train_steps * train_batch,
+                    "seconds": time.perf_counter() - t0, "first_loss": hist[0][1],
+                    "last_loss": hist[-1][1],
+                    "heldout_param_mse": Lr.heldout_mse(prop, tab, seed=W.SEED_HELDOUT),
+                    "heldout_param_mse_predicting_half": 1.0 / 12.0,
+                    "heldout_logmel_l1": Lr.heldout_logmel_l1(prop, tab, seed=W.SEED_HELDOUT)}
+    say("sound_match train", out["train"])
+    lm = Lr.LogMel()
+    budgets = tuple(sorted({1, 10, steps + 1, 100, rs_budget}))
+    acc = {}
+
+    def add(method, b, mr, l1, n):
+        a = acc.setdefault(method, {}).setdefault(b, [0.0, 0.0, 0])
+        a[0] += mr * n
+        a[1] += l1 * n
+        a[2] += n
+
+    for secs in (1, 2, 3, 4):
+        g = [i for i in range(targets) if 1 + i % 4 == secs]
+        if not g:
+            continue
+        ids = torch.tensor(g, dtype=torch.int64, device="cuda")
+        n = secs * 44100
+        x = S.synth_render(S.synth_sample_params(W.SEED_MATCH, voice_ids=ids), tab, n_samples=n,
+                           voice_ids=ids, noise_seed=W.SEED_MATCH)
+
+        def l1_of(u):
+            y = S.synth_render(u, tab, n_samples=n, voice_ids=ids, noise_seed=W.SEED_CAND_NOISE)
+            return float(Lr.sum_f64(M.logmel_l1(y, x, lm), 1.0 / len(g)))
+
+        r_p = M.gradient_match(x, ids, tab, prop(x), steps=steps, lr=lr, snapshot_at=budgets)
+        r_r = M.gradient_match(x, ids, tab, S.synth_sample_params(W.SEED_RS, voice_ids=ids),
+                               steps=steps, lr=lr, snapshot_at=budgets)
+        _, _, rs_curve, rs_snaps = M.random_search(x, ids, tab, budget=rs_budget, seed=W.SEED_RS,
+                                                   record_at=budgets, snapshot_at=budgets)
+        for name, r in (("proposal+gd", r_p), ("random_init+gd", r_r)):
+            for b, u in r.snapshots.items():
+                add(name, b, r.curve[b - 1], l1_of(u), len(g))
+        for b, u in rs_snaps.items():
+            add("random_search", b, rs_curve[b], l1_of(u), len(g))
+        say("sound_match", secs, "s: proposal+gd", r_p.curve[-1], "random_init+gd", r_r.curve[-1],
+            "random_search", rs_curve)
+    out["mrstft_l1"] = {m: {str(b): v[0] / v[2] for b, v in sorted(d.items())} for m, d in acc.items()}
+    out["logmel_l1"] = {m: {str(b): v[1] / v[2] for b, v in sorted(d.items())} for m, d in acc.items()}
+    rs_best = out["mrstft_l1"]["random_search"][str(rs_budget)]
+    reach = [int(b) for b, v in out["mrstft_l1"]["proposal+gd"].items() if v <= rs_best]
+    out["renders_to_random_search_best"] = {
+        "proposal+gd": min(reach) if reach else None, "random_search": rs_budget}
+
+    # service: requests in a fixed shuffled order, admission by device-memory budget
+    order = np.random.default_rng(W.SEED_MATCH).permutation(targets)
+    reqs = []
+    for secs in (1, 2, 3, 4):
+        g = [i for i in range(targets) if 1 + i % 4 == secs]
+        if g:
+            ids = torch.tensor(g, dtype=torch.int64, device="cuda")
+            x = S.synth_render(S.synth_sample_params(W.SEED_MATCH, voice_ids=ids), tab,
+                               n_samples=secs * 44100, voice_ids=ids, noise_seed=W.SEED_MATCH)
+            reqs += [M.Request(i, i, x[j]) for j, i in enumerate(g)]
+    pos = {int(r): k for k, r in enumerate(order)}
+    reqs.sort(key=lambda r: pos[r.rid])
+    svc = M.MatchService(tab, prop, steps=steps, lr=lr, budget_bytes=int(budget_gb * 2**30),
+                         concurrency=concurrency)
+    t1 = time.perf_counter()
+    _, lat, batches = svc.run(reqs)
+    wall = time.perf_counter() - t1
+    out["service"] = {"wall_s": wall, "requests_per_s": len(reqs) / wall,
+                      "p50_s": M.percentile(lat.values(), 50), "p99_s": M.percentile(lat.values(), 99),
+                      "batches": len(batches), "budget_gb": budget_gb, "concurrency": concurrency,
+                      "renders_per_request": steps + 1}
+    out["seconds"] = time.perf_counter() - t0
+    return out
+
+
+class RenderStep:
+    """The timed step of the headline workload: the parameter draw and the
+    ragged render of the whole batch, inputs resident in HBM, voices launched
+    longest first, the launch plan autotuned on this batch (untimed).  The
+    draw and the render are captured in two HIP graphs replayed back to back,
+    so that HIP events between the two replays time the render kernel inside
+    the timed steps.  ``run()`` performs one step; ``params`` and ``audio``
+    hold its results."""
+
+    def __init__(self, wl, rps=0, autotune=True, graph=True):
+        import torch
+        import paper_2104_12922_amd as S
+        self.S, self.wl = S, wl
+        self.table = wl.nebula.table()
+        dev = torch.device("cuda:0")
+        torch.cuda.set_device(dev)
+        B = wl.batch
+        self.offsets = torch.from_numpy(wl.offsets).to(dev)
+        self.params = torch.empty(B, 78, dtype=torch.float32, device=dev)
+        self.audio = torch.empty(wl.total_samples, dtype=torch.float32, device=dev)
+        self.stream = torch.cuda.Stream(device=dev)
+        # launch order: longest voices first (the lengths are known with the
+        # offsets), so that short voices fill the end of the launch
+        self.order = torch.from_numpy(np.argsort(-wl.lengths, kind="stable").astype(np.int32)).to(dev)
+        self.lmax = int(wl.lengths.max())
+        self.plan = (4, 1, 0, 0)                       # the library's default plan
+        if rps:
+            self.plan = (rps, 1, 0, 0)
+        elif autotune:
+            from paper_2104_12922_amd.autotune import RenderTuner
+            with torch.cuda.stream(self.stream):
+                self.draw()
+                self.plan, _ = RenderTuner().tune(self.params, self.table, offsets=self.offsets,
+                                                  order=self.order, max_samples=self.lmax,
+                                                  noise_seed=wl.key_noise(), out=self.audio)
+            torch.cuda.synchronize()
+        self.graphs = None
+        with torch.cuda.stream(self.stream):
+            self.draw()
+            self.render()
+            torch.cuda.synchronize()
+            if graph:
+                self.graphs = (torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph())
+                with torch.cuda.graph(self.graphs[0], stream=self.stream):
+                    self.draw()
+                with torch.cuda.graph(self.graphs[1], stream=self.stream):
+                    self.render()
+                torch.cuda.synchronize()
+
+    def draw(self):
+        wl = self.wl
+        self.S.synth_sample_params(wl.seed, wl.first_g, wl.batch, out=self.params)
+
+    def render(self):
+        p, wl = self.plan, self.wl
+        self.S.synth_render_plan(self.params, self.table, p[0], p[1], persistent=bool(p[2]),
+                                 grid_blocks=p[3], offsets=self.offsets,
+                                 carries=len(p) > 4 and bool(p[4]), max_samples=self.lmax,
+                                 order=self.order, noise_seed=wl.key_noise(), out=self.audio)
+
+    def run(self, events=None):
+        """One step; `events` (a pair of torch.cuda.Event) bracket the render."""
+        import torch
+        with torch.cuda.stream(self.stream):
+            if self.graphs is not None:
+                self.graphs[0].replay()
+            else:
+                self.draw()
+            if events is not None:
+                events[0].record(self.stream)
+            if self.graphs is not None:
+                self.graphs[1].replay()
+            else:
+                self.render()
+            if events is not None:
+                events[1].record(self.stream)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -328,75 +509,31 @@ def main():
         return bench_grad(args)
     if args.workload == "plain":
         return bench_plain(args)
+    if args.workload == "match":
+        res = sound_match(targets=args.match_targets, train_steps=args.match_train_steps,
+                          log=lambda *a: print(*a, file=sys.stderr, flush=True))
+        print(json.dumps({"metric": "sound-match MR-STFT and log-mel L1 per render budget",
+                          "sound_match": res}), flush=True)
+        return
     import torch
     import workloads as W
-    import paper_2104_12922_amd as S
 
     wl = W.ragged_batch(args.batch)
-    table = wl.nebula.table()
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    B = wl.batch
-    total = wl.total_samples
-    offsets = torch.from_numpy(wl.offsets).to(dev)
-    params = torch.empty(B, 78, dtype=torch.float32, device=dev)
-    audio = torch.empty(total, dtype=torch.float32, device=dev)
-    stream = torch.cuda.Stream(device=dev)
-
-    # launch order: longest voices first (the lengths are known with the
-    # offsets), so that short voices fill the end of the launch
-    order = torch.from_numpy(np.argsort(-wl.lengths, kind="stable").astype(np.int32)).to(dev)
-    lmax = int(wl.lengths.max())
-    plan = (4, 1, 0, 0)                       # the library's default plan
-    if args.rps:
-        plan = (args.rps, 1, 0, 0)
-    elif args.autotune:
-        from paper_2104_12922_amd.autotune import RenderTuner
-        with torch.cuda.stream(stream):
-            S.synth_sample_params(wl.seed, wl.first_g, B, out=params)
-            plan, _ = RenderTuner().tune(params, table, offsets=offsets, order=order,
-                                         max_samples=lmax, noise_seed=wl.key_noise(), out=audio)
-        torch.cuda.synchronize()
-
-    def render():
-        S.synth_render_plan(params, table, plan[0], plan[1], persistent=bool(plan[2]),
-                            grid_blocks=plan[3], offsets=offsets,
-                            carries=len(plan) > 4 and bool(plan[4]), max_samples=lmax,
-                            order=order, noise_seed=wl.key_noise(), out=audio)
-
-    def step():
-        S.synth_sample_params(wl.seed, wl.first_g, B, out=params)
-        render()
-
-    with torch.cuda.stream(stream):
-        step()
-        torch.cuda.synchronize()
-        # render-kernel time with HIP events on the stream the kernel runs on
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(max(3, min(args.steps, 10)))]
-        for a, b in ev:
-            a.record(stream)
-            render()
-            b.record(stream)
-        torch.cuda.synchronize()
-        kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-
-        graph = None
-        if args.graph:
-            graph = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(graph, stream=stream):
-                step()
-            torch.cuda.synchronize()
-        run = graph.replay if graph is not None else step
-
-        for _ in range(args.warmup):
-            run()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            run()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+    st = RenderStep(wl, rps=args.rps, autotune=bool(args.autotune), graph=bool(args.graph))
+    # the render kernel's duration in every timed step: HIP events on its
+    # stream, recorded between the draw and render graph replays
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    for _ in range(args.warmup):
+        st.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        st.run(ev[k])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    plan, B, total = st.plan, wl.batch, wl.total_samples
 
     prof = render_traffic() if wl.batch == 16384 and plan in (None, (4, 1, 0, 0)) else None
     ms = dt / args.steps * 1e3
@@ -405,7 +542,10 @@ def main():
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     alu_tops = RENDER_SLOTS_PER_SAMPLE * total / (kern_ms * 1e-3) / 1e12
     out = {
-        "metric": "rendered audio samples/sec", "value": value, "unit": "samples/s",
+        # the headline metric: value is the render throughput; the sound-match
+        # L1 per render budget is the "sound_match" object
+        "metric": "rendered audio samples/sec (MHz, x real-time) & sound-match log-mel L1 per render budget",
+        "value": value, "unit": "samples/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (Philox-drawn parameters, rendered on the fly)",
@@ -416,22 +556,35 @@ def main():
                    "launch_plan": list(plan) if plan is not None else "default",
                    "launch_order": "longest voices first"},
         "mhz": value / 1e6, "x_realtime": value / wl.sample_rate,
-        # the render is bound by VALU issue: the roofline is the ALU one
-        # (algorithmic slots / kernel time), with the HBM figures beside it
-        "roofline": {"bound": "alu", "achieved": alu_tops, "peak": VALU_PEAK_TOPS,
-                     "unit": "T VALU lane-slots/s", "frac": alu_tops / VALU_PEAK_TOPS,
+        # the HBM roofline of the render kernel: algorithmic bytes per launch
+        # (4 B per output sample + 312 B of parameters, 8 B of offsets and 4 B
+        # of launch order per voice) / its average launch time.  The kernel is
+        # limited by VALU issue below that roofline; "alu" gives the issue rate
+        # against a per-sample floor of this formulation's own count (a lower
+        # bound counted for this design, not a hardware constant).
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (float(prof["fetch_bytes"] + prof["write_bytes"])
                                  if prof else None),
-                     "traffic_unit": "B/launch",
-                     "slots_per_sample": RENDER_SLOTS_PER_SAMPLE,
-                     "valu_busy_profiled": prof["valu_busy"] if prof else None,
-                     "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes},
-                     "kernel": "render_kernel", "kernel_ms": kern_ms},
+                     "alg_bytes_per_launch": alg_bytes,
+                     "kernel": "render_kernel", "kernel_ms": kern_ms,
+                     "alu": {"achieved": alu_tops, "peak": VALU_PEAK_TOPS,
+                             "unit": "T VALU lane-slots/s", "frac": alu_tops / VALU_PEAK_TOPS,
+                             "slots_per_sample_floor": RENDER_SLOTS_PER_SAMPLE,
+                             "floor_basis": "this design's own count of issue slots per sample",
+                             "valu_busy_profiled": prof["valu_busy"] if prof else None}},
         "context": {"paper_single_gpu_mhz": 714.0, "paper_gpu": "V100"},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    if not args.no_match:
+        # the metric's second half, on the same GPU after the timed region
+        try:
+            out["sound_match"] = sound_match(targets=args.match_targets,
+                                             train_steps=args.match_train_steps,
+                                             log=lambda *a: print(*a, file=sys.stderr, flush=True))
+        except Exception as e:                      # the render line is still reported
+            out["sound_match"] = {"error": f"{type(e).__name__}: {e}"}
     print(json.dumps(out), flush=True)
 
 

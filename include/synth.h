@@ -95,8 +95,12 @@ int synth_sample_params(uint64_t seed, uint64_t first_g, int64_t batch,
  *              noise oscillator's counter.
  *   offsets    dev int64 [batch + 1] or NULL.  If given, voice i is written to
  *              audio[offsets[i] .. offsets[i+1]) (ragged lengths, packed); the
- *              offsets must be non-decreasing.  If NULL every voice has
- *              n_samples samples and voice i starts at audio[i * n_samples].
+ *              offsets must be non-decreasing from offsets[0] = 0.  They are
+ *              read on the device (not checked on the host); every kernel cuts
+ *              a voice's range to [0, offsets[batch]), so malformed offsets
+ *              give undefined audio but no access outside audio[0 ..
+ *              offsets[batch]).  If NULL every voice has n_samples samples
+ *              and voice i starts at audio[i * n_samples].
  *   n_samples  uniform length when offsets == NULL (> 0); ignored otherwise.
  *   audio      dev float32, written: batch * n_samples floats, or offsets[batch].
  *   Output: y(n) = L1 * sine(n) * a1(n) + L2 * squaresaw(n) * a2(n)
@@ -366,6 +370,32 @@ int synth_logit_adam(int64_t n, float* z, float* u, const float* grad_u, float* 
 int synth_best_update(const double* loss, int64_t rows, int64_t cols, int64_t row_stride,
                       int64_t col_stride, int64_t col_base, const float* params, int64_t param_dim,
                       double* best, int64_t* best_idx, float* best_params, void* stream);
+
+/* -------------------------------------------------------------------------
+ * Fixed-order float64 reductions closing the learned and matching paths on
+ * the device (the proposal's mean squared error, the spectral loss's chain
+ * rule, and the distances the paper scores sounds with: L1 between log-mel
+ * spectrograms, Section 4, and the squared error of estimated parameters).
+ * Bitwise reproducible: every sum runs in a fixed order.
+ * ------------------------------------------------------------------------- */
+
+/* Sums of f(a - b) with f = |.| (kind 0) or (.)^2 (kind 1), a and b float32
+ * rows x cols matrices (row strides lda, ldb >= cols; b NULL reads as 0).
+ * axis 1: out[r] = scale * sum_c f(a[r][c] - b[r][c]) for r < rows (rows
+ * < 2^31); axis 0: out[c] = scale * sum_r f(...) for c < cols.  With
+ * accumulate != 0 the result is added to out's previous value.  out: dev
+ * float64.  SYNTH_EINVAL on a bad kind, axis, size, stride or NULL pointer. */
+int synth_diff_reduce(int kind, int axis, const float* a, const float* b, int64_t rows,
+                      int64_t cols, int64_t lda, int64_t ldb, double scale, int accumulate,
+                      double* out, void* stream);
+
+/* out[0] = scale * sum_i x[i] (x dev float64 [n], out dev float64 [1]). */
+int synth_sum_f64(const double* x, int64_t n, double scale, double* out, void* stream);
+
+/* out[r][c] = g[r][c] * float(s[r]) (g, out dev float32 rows x cols, may
+ * alias; s dev float64 [rows]): a per-row chain-rule factor. */
+int synth_scale_rows(const float* g, const double* s, int64_t rows, int64_t cols, float* out,
+                     void* stream);
 
 #ifdef __cplusplus
 }

@@ -301,7 +301,8 @@ class MRSTFTLoss(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gl):
         (g,) = ctx.saved_tensors
-        return g * gl.to(g.dtype)[:, None], None
+        from .learned import scale_rows
+        return scale_rows(g, gl.detach().to(torch.float64).contiguous()), None
 
 
 def ctypes_ref(cfg):

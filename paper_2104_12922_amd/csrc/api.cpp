@@ -599,6 +599,30 @@ int synth_logmel_mfma(const float* audio, const int64_t* offsets, int64_t batch,
                        workspace_bytes, features, stream);
 }
 
+int synth_diff_reduce(int kind, int axis, const float* a, const float* b, int64_t rows,
+                      int64_t cols, int64_t lda, int64_t ldb, double scale, int accumulate,
+                      double* out, void* stream) {
+  if ((kind != 0 && kind != 1) || (axis != 0 && axis != 1) || rows < 0 || cols < 0) return SYNTH_EINVAL;
+  if (lda < cols || (b && ldb < cols)) return SYNTH_EINVAL;
+  if ((axis == 1 ? rows : cols) > 0 && !out) return SYNTH_EINVAL;
+  if (rows > 0 && cols > 0 && !a) return SYNTH_EINVAL;
+  if (axis == 1 && rows > 0x7FFFFFFF) return SYNTH_EINVAL;
+  return to_status(synth::launch_diff_reduce(kind, axis, a, b, rows, cols, lda, ldb, scale,
+                                             accumulate, out, (hipStream_t)stream));
+}
+
+int synth_sum_f64(const double* x, int64_t n, double scale, double* out, void* stream) {
+  if (n < 0 || !out || (n > 0 && !x)) return SYNTH_EINVAL;
+  return to_status(synth::launch_sum_f64(x, n, scale, out, (hipStream_t)stream));
+}
+
+int synth_scale_rows(const float* g, const double* s, int64_t rows, int64_t cols, float* out,
+                     void* stream) {
+  if (rows < 0 || cols < 0) return SYNTH_EINVAL;
+  if (rows * cols > 0 && (!g || !s || !out)) return SYNTH_EINVAL;
+  return to_status(synth::launch_scale_rows(g, s, rows, cols, out, (hipStream_t)stream));
+}
+
 int synth_colstats(const void* x, int x_bf16, int64_t rows, int64_t cols, int64_t ld, float* sum,
                    float* sumsq, void* stream) {
   if (rows < 0 || cols < 0 || ld < cols || (cols > 0 && (!x || !sum))) return SYNTH_EINVAL;

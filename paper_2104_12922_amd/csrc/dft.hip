@@ -223,8 +223,7 @@ __global__ void __launch_bounds__(kThreads) dft_power_kernel(const float* __rest
     int64_t start = 0, len = 0;
     if (v < batch) {
       if (offsets) {
-        start = offsets[v];
-        len = offsets[v + 1] - start;
+        packed_range(offsets, batch, v, start, len);
       } else {
         start = v * n_uniform;
         len = n_uniform;

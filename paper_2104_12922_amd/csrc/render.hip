@@ -59,8 +59,7 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
 
   int64_t off0, N;
   if (a.offsets) {
-    off0 = a.offsets[b];
-    N = a.offsets[b + 1] - off0;
+    packed_range(a.offsets, a.batch, b, off0, N);
   } else {
     off0 = b * a.n_uniform;
     N = a.n_uniform;
@@ -260,7 +259,8 @@ __global__ void __launch_bounds__(kWave) carry_sums_kernel(const RenderArgs a, d
   __shared__ double envs[8 * kWave];
   const int lane = threadIdx.x;
   const int64_t c = blockIdx.x, b = blockIdx.y;
-  const int64_t N = a.offsets ? a.offsets[b + 1] - a.offsets[b] : a.n_uniform;
+  int64_t off0 = 0, N = a.n_uniform;
+  if (a.offsets) packed_range(a.offsets, a.batch, b, off0, N);
   const int64_t J = (N + a.q - 1) / a.q;
   const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
   if (N <= 0 || c >= nchunks) return;
@@ -285,7 +285,8 @@ __global__ void __launch_bounds__(kWave) carry_scan_kernel(const RenderArgs a, d
   __shared__ VoiceShared sh;
   const int lane = threadIdx.x;
   const int64_t b = blockIdx.x;
-  const int64_t N = a.offsets ? a.offsets[b + 1] - a.offsets[b] : a.n_uniform;
+  int64_t off0 = 0, N = a.n_uniform;
+  if (a.offsets) packed_range(a.offsets, a.batch, b, off0, N);
   const int64_t J = (N + a.q - 1) / a.q;
   const int64_t nchunks = (J + kSegsPerChunk - 1) / kSegsPerChunk;
   if (N <= 0) return;
@@ -310,8 +311,7 @@ __global__ void __launch_bounds__(256) peak_normalise_kernel(const RenderArgs a)
   const int64_t b = blockIdx.x;
   int64_t off0, N;
   if (a.offsets) {
-    off0 = a.offsets[b];
-    N = a.offsets[b + 1] - off0;
+    packed_range(a.offsets, a.batch, b, off0, N);
   } else {
     off0 = b * a.n_uniform;
     N = a.n_uniform;

@@ -18,6 +18,22 @@ struct NebulaArgs {
   uint32_t linear[3];             // bit p: curve == 1 (no warp)
 };
 
+// Voice b's sample range [start, start + len) in a packed batch with
+// offsets[0 .. batch] (int64, required non-decreasing with offsets[0] = 0, so
+// that the buffer holds offsets[batch] samples).  The range is cut to
+// [0, offsets[batch]) (empty if nothing is left), so a malformed offsets
+// array cannot make a kernel read or write outside the caller's buffer; for
+// valid offsets it is offsets[b] .. offsets[b + 1].
+__device__ __forceinline__ void packed_range(const int64_t* offsets, int64_t batch, int64_t b,
+                                             int64_t& start, int64_t& len) {
+  const int64_t total = offsets[batch];
+  int64_t s = offsets[b], e = offsets[b + 1];
+  if (s < 0) s = 0;
+  if (e > total) e = total;
+  start = s;
+  len = e > s ? e - s : 0;
+}
+
 struct RenderArgs {
   const float* params;       // [B][78]
   const uint64_t* voice_ids; // [B] or null
@@ -80,6 +96,12 @@ size_t gemm_split_bytes(int64_t M, int64_t N, int split);
 
 // elementwise / reduction helpers of the learned proposal (mlp.hip)
 hipError_t launch_f32_to_bf16(const float* x, void* y, int64_t n, hipStream_t s);
+hipError_t launch_diff_reduce(int kind, int axis, const float* a, const float* b, int64_t rows,
+                              int64_t cols, int64_t lda, int64_t ldb, double scale, int accumulate,
+                              double* out, hipStream_t s);
+hipError_t launch_sum_f64(const double* x, int64_t n, double scale, double* out, hipStream_t s);
+hipError_t launch_scale_rows(const float* g, const double* sc, int64_t rows, int64_t cols,
+                             float* out, hipStream_t s);
 hipError_t launch_colsum(const void* x, int x_bf16, int64_t rows, int64_t cols, int64_t ld,
                          float* sum, float* sumsq, hipStream_t s);
 hipError_t launch_feature_stats(const float* x, int64_t rows, int64_t cols, float min_var,

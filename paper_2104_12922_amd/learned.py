@@ -43,6 +43,12 @@ def _sig(L):
     L.synth_logit_init.argtypes = [vp, vp, vp, i64, f32, vp]
     L.synth_logit_adam.argtypes = [i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]
     L.synth_best_update.argtypes = [vp, i64, i64, i64, i64, i64, vp, i64, vp, vp, vp, vp]
+    f64 = ctypes.c_double
+    L.synth_diff_reduce.argtypes = [i32, i32, vp, vp, i64, i64, i64, i64, f64, i32, vp, vp]
+    L.synth_sum_f64.argtypes = [vp, i64, f64, vp, vp]
+    L.synth_scale_rows.argtypes = [vp, vp, i64, i64, vp, vp]
+    for n in ("synth_diff_reduce", "synth_sum_f64", "synth_scale_rows"):
+        getattr(L, n).restype = ctypes.c_int
     for n in ("synth_gemm_bf16", "synth_logmel_init", "synth_logmel", "synth_logmel_mfma",
               "synth_colstats",
               "synth_standardize", "synth_to_bf16", "synth_mlp_forward", "synth_mlp_backward",
@@ -63,6 +69,42 @@ def lib():
 
 def _p(t, name, dtype, numel=None):
     return _dev_ptr(t, name, dtype, numel)
+
+
+def diff_reduce(a, b=None, kind=0, axis=1, scale=1.0, out=None, accumulate=False):
+    """Fixed-order float64 sums of |a - b| (kind 0) or (a - b)^2 (kind 1) over
+    the columns of each row (axis 1, out [rows]) or the rows of each column
+    (axis 0, out [cols]), times scale (synth_diff_reduce)."""
+    rows, cols = a.shape
+    n_out = rows if axis == 1 else cols
+    if out is None:
+        out = torch.zeros(n_out, dtype=torch.float64, device=a.device)
+    _native.check("synth_diff_reduce", lib().synth_diff_reduce(
+        int(kind), int(axis), _p(a, "a", F32), _p(b, "b", F32, a.numel()) if b is not None else None,
+        rows, cols, a.stride(0), b.stride(0) if b is not None else cols, float(scale),
+        int(bool(accumulate)), _p(out, "out", torch.float64, n_out), _stream(a.device)))
+    return out
+
+
+def sum_f64(x, scale=1.0, out=None):
+    """scale * sum(x) of a float64 device vector, in a fixed order (0-d float64)."""
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=x.device)
+    _native.check("synth_sum_f64", lib().synth_sum_f64(
+        _p(x, "x", torch.float64), x.numel(), float(scale), _p(out, "out", torch.float64, 1),
+        _stream(x.device)))
+    return out
+
+
+def scale_rows(g, s, out=None):
+    """out[r, c] = g[r, c] * float(s[r]) (synth_scale_rows)."""
+    rows, cols = g.shape
+    if out is None:
+        out = torch.empty_like(g)
+    _native.check("synth_scale_rows", lib().synth_scale_rows(
+        _p(g, "g", F32, rows * cols), _p(s, "s", torch.float64, rows),
+        rows, cols, _p(out, "out", F32, rows * cols), _stream(g.device)))
+    return out
 
 
 def gemm_bf16(A, B, M, N, K, a_layout=0, b_layout=0, lda=None, ldb=None, out=None, out_bf16=False,
@@ -245,7 +287,7 @@ class MLP:
             g["w1t"].data_ptr(), g["b1"].data_ptr(), g["w2t"].data_ptr(), g["b2"].data_ptr(),
             g["w3t"].data_ptr(), g["b3"].data_ptr(), a["dz3"].data_ptr(), a["dh2"].data_ptr(),
             a["dh1"].data_ptr(), a["loss_rows"].data_ptr(), *self._ws_args(), _stream(self.device)))
-        return a["loss_rows"].sum() / (B * self.d_out)
+        return sum_f64(a["loss_rows"][:B], 1.0 / (B * self.d_out))
 
     def adam_step(self):
         self.step_count += 1
@@ -350,10 +392,12 @@ class Proposal:
 _TUNER = None
 
 
-def render_batch(seed, ids, nebula_table, lengths_s=(1, 2, 3, 4), tune: bool = True):
+def render_batch(seed, ids, nebula_table, lengths_s=(1, 2, 3, 4), tune: bool = True,
+                 return_ids: bool = False):
     """(u, packed audio, offsets) of voices ids drawn and rendered on the GPU
     (with the launch plan the autotuner picked for this batch shape).  The
-    voices come back ordered longest first; u and the audio stay aligned."""
+    voices come back ordered longest first; u and the audio stay aligned
+    (return_ids=True appends the voice ids in that order)."""
     global _TUNER
     from . import synth_render, synth_sample_params
     # longest voices first: workgroups are dispatched in voice order, so the
@@ -384,6 +428,8 @@ def render_batch(seed, ids, nebula_table, lengths_s=(1, 2, 3, 4), tune: bool = T
                               key=key, out=out, max_samples=lmax)
     else:
         audio = synth_render(u, nebula_table, offsets=offs, voice_ids=ids, noise_seed=seed)
+    if return_ids:
+        return u, audio, offs, ids
     return u, audio, offs
 
 
@@ -462,18 +508,18 @@ def train_pipelined(net: "MLP", lm: LogMel, nebula_table, mean, inv_std, steps: 
     return losses
 
 
-def train_proposal(nebula_table, steps: int, batch: int = 4096, seed: int = 10,
-                   lengths_s=(1, 2, 3, 4), lr: float = 3e-4, warmup: int = 500, init=None,
+def train_proposal(nebula_table, steps: int, init, batch: int = 4096, seed: int = 10,
+                   lengths_s=(1, 2, 3, 4), lr: float = 3e-4, warmup: int = 500,
                    log_every: int = 0, log=print):
     """Train the proposal on freshly rendered training voices: each step draws
     `batch` new voices, renders them (ragged lengths), computes log-mel
     features and takes one Adam step on the MSE between the MLP's sigmoid
     output and the drawn u (render and MLP of consecutive steps overlapped,
-    train_pipelined).  Feature statistics come from the first batch.
+    train_pipelined).  `init`: the initial weights (dict of float32 arrays,
+    as MLP takes them).  Feature statistics come from the first batch.
     Returns (Proposal, history of (step, loss))."""
-    from workloads import mlp_init
     lm = LogMel()
-    net = MLP(init if init is not None else mlp_init(0), lr=lr)
+    net = MLP(init, lr=lr)
     _, audio, offs = render_batch(seed, train_ids(0, batch), nebula_table, lengths_s)
     mean, inv_std = feature_stats(lm(audio, offsets=offs))
     del audio
@@ -496,13 +542,33 @@ def heldout_mse(proposal: Proposal, nebula_table, seed: int = 11, count: int = 4
                 lengths_s=(1, 2, 3, 4), batch: int = 1024, per_param: bool = False):
     """Mean squared error of the proposal's u on held-out voices (another
     seed); per_param=True returns the float64 [78] per-parameter errors."""
-    tot = torch.zeros(78, dtype=torch.float64, device="cuda")
-    n = 0
+    per = torch.zeros(78, dtype=torch.float64, device="cuda")
     for first in range(0, count, batch):
         ids = torch.arange(first, min(first + batch, count), device="cuda", dtype=torch.int64)
         u, audio, offs = render_batch(seed, ids, nebula_table, lengths_s)
         est = proposal(audio, offs)
-        tot += ((est - u).double() ** 2).sum(0)
-        n += u.shape[0]
-    per = (tot / n).cpu()
-    return per if per_param else float(per.mean())
+        diff_reduce(est, u, kind=1, axis=0, scale=1.0 / count, out=per, accumulate=True)
+    if per_param:
+        return per.cpu()
+    return float(sum_f64(per, 1.0 / 78))
+
+
+def heldout_logmel_l1(proposal: Proposal, nebula_table, seed: int = 11, count: int = 4096,
+                      lengths_s=(1, 2, 3, 4), batch: int = 1024) -> float:
+    """Re-rendered log-mel L1 of the proposal on held-out voices: each voice
+    (another seed, lengths 1-4 s) is re-rendered from the proposal's u with
+    its own voice id and noise key, and the mean |log-mel difference| over
+    the 128 x 64 features is averaged over the voices."""
+    tot = torch.zeros((), dtype=torch.float64, device="cuda")
+    lm = proposal.logmel
+    for first in range(0, count, batch):
+        ids = torch.arange(first, min(first + batch, count), device="cuda", dtype=torch.int64)
+        u, audio, offs, ids = render_batch(seed, ids, nebula_table, lengths_s, return_ids=True)
+        est = proposal(audio, offs)
+        from . import synth_render
+        again = synth_render(est.contiguous(), nebula_table, offsets=offs, voice_ids=ids,
+                             noise_seed=seed)
+        fa, fb = lm(again, offsets=offs), lm(audio, offsets=offs)
+        d = diff_reduce(fa, fb, kind=0, axis=1, scale=1.0 / (fa.shape[1] * count))
+        tot += sum_f64(d)
+    return float(tot)

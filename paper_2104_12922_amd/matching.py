@@ -43,16 +43,20 @@ class MatchResult:
     best_step: torch.Tensor       # int64 [T]: render index (0 = the starting estimate)
     curve: list = field(default_factory=list)   # best-so-far mean loss after each render
     renders: int = 0
+    snapshots: dict = field(default_factory=dict)   # render count -> best parameters then
 
 
 def gradient_match(targets: torch.Tensor, voice_ids: torch.Tensor, nebula_table, u0: torch.Tensor,
                    steps: int = 50, lr: float = 0.05, noise_seed: int = 22,
-                   init_eps: float = 1e-4, record_curve: bool = True) -> MatchResult:
+                   init_eps: float = 1e-4, record_curve: bool = True,
+                   snapshot_at=()) -> MatchResult:
     """Adam on logits from u0 for `steps` steps against targets [T, N].
 
     Candidate renders use voice_ids for the noise counter and `noise_seed` as
     the noise key (a key different from the targets': their noise is not
-    recoverable).  Returns the best render over the trajectory."""
+    recoverable).  Returns the best render over the trajectory; `snapshot_at`
+    (render counts) keeps a copy of the best parameters after that many
+    renders in result.snapshots."""
     T, N = targets.shape
     dev = targets.device
     z, u = Lr.logit_init(u0.contiguous(), init_eps)
@@ -68,6 +72,7 @@ def gradient_match(targets: torch.Tensor, voice_ids: torch.Tensor, nebula_table,
     tc = synth_mrstft_target(targets)          # target spectra, once per match
     gx = torch.empty(T, N, dtype=F32, device=dev) if steps > 0 else None
     curve = []
+    snaps = {}
     for s in range(steps + 1):
         synth_render(u, nebula_table, n_samples=N, voice_ids=voice_ids, noise_seed=noise_seed, out=x)
         last = s == steps
@@ -77,7 +82,9 @@ def gradient_match(targets: torch.Tensor, voice_ids: torch.Tensor, nebula_table,
             loss, gx = synth_mrstft_loss(x, tc, grad=True, workspace=ws_loss, out_grad=gx)
         Lr.best_update(loss, T, 1, 1, 0, best, best_step, col_base=s, params=u, best_params=best_u)
         if record_curve:
-            curve.append(best.mean())
+            curve.append(Lr.sum_f64(best, 1.0 / T))
+        if s + 1 in snapshot_at:
+            snaps[s + 1] = best_u.clone()
         if last:
             break
         if ws is None:
@@ -85,14 +92,16 @@ def gradient_match(targets: torch.Tensor, voice_ids: torch.Tensor, nebula_table,
         synth_render_backward(u, gx, nebula_table, voice_ids=voice_ids, noise_seed=noise_seed,
                               out=gp, workspace=ws)
         Lr.logit_adam(z, u, gp, m, v, s + 1, lr=lr)
-    return MatchResult(best_u, best, best_step, [float(c) for c in curve], steps + 1)
+    return MatchResult(best_u, best, best_step, [float(c) for c in curve], steps + 1, snaps)
 
 
 def random_search(targets: torch.Tensor, voice_ids: torch.Tensor, nebula_table, budget: int = 1000,
-                  seed: int = 21, noise_seed: int = 22, record_at=(1, 10, 51, 100, 1000)):
+                  seed: int = 21, noise_seed: int = 22, record_at=(1, 10, 51, 100, 1000),
+                  snapshot_at=()):
     """`budget` random draws per target; candidate k of target t is voice
     t_id * budget + k of the generator keyed by `seed`.  Returns
-    (best_u, best_loss, {budget: mean best loss})."""
+    (best_u, best_loss, {budget: mean best loss}) and, with `snapshot_at`,
+    a fourth item {budget: copy of the best parameters after that many}."""
     T, N = targets.shape
     dev = targets.device
     best = torch.full((T,), math.inf, dtype=F64, device=dev)
@@ -103,6 +112,7 @@ def random_search(targets: torch.Tensor, voice_ids: torch.Tensor, nebula_table, 
     ws_loss = synth_mrstft_workspace(T, N)
     tc = synth_mrstft_target(targets)
     curve = {}
+    snaps = {}
     for k in range(budget):
         cid = base + k
         u = synth_sample_params(seed, voice_ids=cid)
@@ -110,13 +120,19 @@ def random_search(targets: torch.Tensor, voice_ids: torch.Tensor, nebula_table, 
         loss = synth_mrstft_loss(x, tc, workspace=ws_loss)
         Lr.best_update(loss, T, 1, 1, 0, best, best_k, col_base=k, params=u, best_params=best_u)
         if (k + 1) in record_at:
-            curve[k + 1] = float(best.mean())
+            curve[k + 1] = float(Lr.sum_f64(best, 1.0 / T))
+        if (k + 1) in snapshot_at:
+            snaps[k + 1] = best_u.clone()
+    if snapshot_at:
+        return best_u, best, curve, snaps
     return best_u, best, curve
 
 
 def logmel_l1(a: torch.Tensor, b: torch.Tensor, logmel: Lr.LogMel) -> torch.Tensor:
-    """Per-voice mean |log-mel(a) - log-mel(b)| (evaluation metric)."""
-    return (logmel(a) - logmel(b)).abs().mean(dim=1)
+    """Per-voice mean |log-mel(a) - log-mel(b)| over the 128 x 64 features
+    (float64 [B]; evaluation metric)."""
+    fa, fb = logmel(a), logmel(b)
+    return Lr.diff_reduce(fa, fb, kind=0, axis=1, scale=1.0 / fa.shape[1])
 
 
 # ---------------------------------------------------------------------------
@@ -233,114 +249,3 @@ class MatchService:
 
 def percentile(values, p):
     return float(np.percentile(np.asarray(list(values), dtype=np.float64), p))
-
-
-# ---------------------------------------------------------------------------
-# Experiment: proposal + gradient matching vs random search
-# ---------------------------------------------------------------------------
-def _targets(table, first, count, seconds, seed):
-    from . import synth_render, synth_sample_params
-    ids = torch.arange(first, first + count, dtype=torch.int64, device="cuda")
-    u = synth_sample_params(seed, voice_ids=ids)
-    x = synth_render(u, table, n_samples=int(round(seconds * 44100)), voice_ids=ids, noise_seed=seed)
-    return ids, x
-
-
-def main(argv=None):
-    """Train the proposal, then match targets of 1-4 s (length 1 + g mod 4 s)
-    with the proposal + gradient steps, with random init + gradient steps, and
-    by random search; print one JSON line of errors per render budget,
-    throughput and service latency."""
-    import argparse
-    import json
-
-    import workloads as W
-    ap = argparse.ArgumentParser(description=main.__doc__)
-    ap.add_argument("--targets", type=int, default=4096)
-    ap.add_argument("--train-steps", type=int, default=2000)
-    ap.add_argument("--train-batch", type=int, default=4096)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--lr", type=float, default=0.05)
-    ap.add_argument("--rs-budget", type=int, default=1000)
-    ap.add_argument("--rs-targets", type=int, default=0, help="targets given to random search (0 = all)")
-    ap.add_argument("--budget-gb", type=float, default=64.0)
-    ap.add_argument("--concurrency", type=int, default=4,
-                    help="matching batches in flight at once (one stream each)")
-    a = ap.parse_args(argv)
-    tab = W.default_nebula().table()
-    out = {"targets": a.targets, "steps": a.steps, "lr": a.lr}
-
-    t0 = time.perf_counter()
-    prop, hist = Lr.train_proposal(tab, a.train_steps, batch=a.train_batch, seed=W.SEED_TRAIN,
-                                   log_every=max(1, a.train_steps // 20),
-                                   log=lambda s: print(s, flush=True))
-    torch.cuda.synchronize()
-    out["train"] = {"steps": a.train_steps, "batch": a.train_batch,
-                    "seconds": time.perf_counter() - t0, "first_loss": hist[0][1],
-                    "last_loss": hist[-1][1],
-                    "heldout_mse": Lr.heldout_mse(prop, tab, seed=W.SEED_HELDOUT)}
-    print(json.dumps({"train": out["train"]}), flush=True)
-
-    lm = Lr.LogMel()
-    budgets = sorted({1, 10, a.steps + 1, 100, a.rs_budget} & set(range(1, a.rs_budget + 1)))
-    agg = {"proposal+gd": {}, "random+gd": {}, "random_search": {}, "logmel_l1": {}}
-    counts = {}
-    for secs in (1, 2, 3, 4):
-        g = [i for i in range(a.targets) if 1 + i % 4 == secs]
-        if not g:
-            continue
-        # targets of this length are the voices g = secs - 1, secs + 3, ... rendered at seed 20
-        ids = torch.tensor(g, dtype=torch.int64, device="cuda")
-        u = synth_sample_params(W.SEED_MATCH, voice_ids=ids)
-        x = synth_render(u, tab, n_samples=secs * 44100, voice_ids=ids, noise_seed=W.SEED_MATCH)
-        counts[secs] = len(g)
-        r_p = gradient_match(x, ids, tab, prop(x), steps=a.steps, lr=a.lr)
-        r_r = gradient_match(x, ids, tab, synth_sample_params(W.SEED_RS, voice_ids=ids),
-                             steps=a.steps, lr=a.lr)
-        nrs = len(g) if a.rs_targets == 0 else max(1, (a.rs_targets * len(g)) // a.targets)
-        _, _, rs_curve = random_search(x[:nrs].contiguous(), ids[:nrs], tab, budget=a.rs_budget,
-                                       record_at=tuple(budgets))
-        for name, r in (("proposal+gd", r_p), ("random+gd", r_r)):
-            for b in budgets:
-                if b <= len(r.curve):
-                    agg[name].setdefault(b, []).append((r.curve[b - 1], len(g)))
-        for b, v in rs_curve.items():
-            agg["random_search"].setdefault(b, []).append((v, nrs))
-        y = synth_render(r_p.best_u, tab, n_samples=secs * 44100, voice_ids=ids, noise_seed=22)
-        agg["logmel_l1"].setdefault("proposal+gd", []).append((float(logmel_l1(y, x, lm).mean()), len(g)))
-        print(json.dumps({"seconds": secs, "n": len(g), "proposal+gd": r_p.curve[-1],
-                          "random+gd": r_r.curve[-1], "random_search": rs_curve}), flush=True)
-
-    def wmean(v):
-        return sum(a * n for a, n in v) / sum(n for _, n in v)
-    out["mrstft_l1_by_renders"] = {k: {str(b): wmean(v) for b, v in d.items()}
-                                   for k, d in agg.items() if k != "logmel_l1"}
-    out["logmel_l1"] = {k: wmean(v) for k, v in agg["logmel_l1"].items()}
-
-    # service: requests in a fixed shuffled order, admission by memory budget
-    order = np.random.default_rng(W.SEED_MATCH).permutation(a.targets)
-    reqs = []
-    for secs in (1, 2, 3, 4):
-        g = [i for i in range(a.targets) if 1 + i % 4 == secs]
-        if g:
-            ids = torch.tensor(g, dtype=torch.int64, device="cuda")
-            u = synth_sample_params(W.SEED_MATCH, voice_ids=ids)
-            x = synth_render(u, tab, n_samples=secs * 44100, voice_ids=ids, noise_seed=W.SEED_MATCH)
-            reqs += [Request(i, i, x[j]) for j, i in enumerate(g)]
-    pos = {int(r): k for k, r in enumerate(order)}
-    reqs.sort(key=lambda r: pos[r.rid])
-    svc = MatchService(tab, prop, steps=a.steps, lr=a.lr, budget_bytes=int(a.budget_gb * 2**30),
-                       concurrency=a.concurrency)
-    t1 = time.perf_counter()
-    _, lat, batches = svc.run(reqs)
-    wall = time.perf_counter() - t1
-    out["service"] = {"wall_s": wall, "requests_per_s": len(reqs) / wall,
-                      "p50_s": percentile(lat.values(), 50), "p99_s": percentile(lat.values(), 99),
-                      "batches": len(batches), "budget_gb": a.budget_gb,
-                      "concurrency": a.concurrency,
-                      "renders_per_request": a.steps + 1}
-    print(json.dumps(out), flush=True)
-
-
-if __name__ == "__main__":
-    main()

@@ -235,3 +235,53 @@ def test_ragged_batch_b16384_sampled_against_oracle(synth):
     offs = wl.offsets
     got = np.concatenate([y[offs[i]:offs[i + 1]].cpu().numpy() for i in pick]).astype(np.float64)
     assert np.abs(got - ref).max() <= TOL
+
+
+def test_timed_bench_step_matches_oracle(synth):
+    """The exact step the throughput benchmark times (bench.RenderStep: the
+    parameter draw and the ragged 16384-voice render with the autotuned launch
+    plan and the longest-first voice order, captured in HIP graphs), after
+    three graph replays: the parameters of every voice bit-exact, 256 sampled
+    voices (a third of each length, 1, 2 and 4 s) against the oracle."""
+    import bench
+    wl = W.ragged_batch()
+    st = bench.RenderStep(wl)
+    say("bench step plan", st.plan)
+    for _ in range(3):
+        st.run()
+    torch.cuda.synchronize()
+    assert st.graphs is not None
+    u = st.params.cpu().numpy().astype(np.float64)
+    assert np.array_equal(u, philox.sample_params(wl.seed, np.arange(wl.batch, dtype=np.uint64)))
+    rng = np.random.default_rng(7)
+    pick = np.sort(np.concatenate([rng.choice(np.nonzero(wl.lengths == n)[0], 86 if k < 2 else 84,
+                                              replace=False)
+                                   for k, n in enumerate(np.unique(wl.lengths))]))
+    assert len(pick) == 256
+    y = st.audio
+    assert bool(torch.isfinite(y).all())
+    ref = oracle_render(u[pick], pick, wl.lengths[pick], st.table, noise_seed=wl.key_noise())
+    offs = wl.offsets
+    got = np.concatenate([y[offs[i]:offs[i + 1]].cpu().numpy() for i in pick]).astype(np.float64)
+    err = np.abs(got - ref).max()
+    say("bench step: 256 sampled voices, max |gpu - oracle| = %.3e" % err)
+    assert err <= TOL
+
+
+def test_malformed_offsets_stay_inside_the_buffer(synth, nebula_table):
+    """Offsets that decrease ([0, 100, 50, 60]) are a caller error; the
+    kernels cut every voice's range to [0, offsets[batch]), so nothing is
+    written outside the 60-sample buffer (a guard region after it stays
+    untouched) and the voices that fit are rendered as for valid offsets."""
+    u = synth.synth_sample_params(3, 0, 3)
+    buf = torch.full((60 + 4096,), 7.0, device="cuda")
+    offs = torch.tensor([0, 100, 50, 60], dtype=torch.int64, device="cuda")
+    synth.synth_render(u, nebula_table, offsets=offs, out=buf[:60])
+    torch.cuda.synchronize()
+    assert bool((buf[60:] == 7.0).all())
+    ok = synth.synth_render(u, nebula_table, n_samples=60)
+    torch.cuda.synchronize()
+    assert torch.equal(buf[:50], ok[0, :50])            # voice 0, cut to the buffer
+    # [50, 60) is written by voice 0 (cut) and voice 2: either value
+    tail = buf[50:60]
+    assert bool(((tail == ok[0, 50:60]) | (tail == ok[2, :10])).all())
