@@ -121,6 +121,23 @@ int synth_render_ws(const synth_config* cfg, const float* params, const uint64_t
                     uint64_t first_g, int64_t batch, const int64_t* offsets, int64_t n_samples,
                     float* audio, void* workspace, size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * synth_render_ws with its workspace taken from a buffer the library holds,
+ * a static device array of SYNTH_NOALLOC_SCRATCH_BYTES (16 MiB) on each device
+ * it runs on, kept until the process ends.  Same arguments and bit-identical
+ * audio as synth_render_ws / synth_render; allocates nothing.  Returns
+ * SYNTH_ENOMEM when the batch needs more workspace than the array holds
+ * (synth_render_workspace(cfg, batch, n_samples) > SYNTH_NOALLOC_SCRATCH_BYTES:
+ * batch * ceil(ceil(n_samples / q) / 62) * 32 bytes for a split batch), and
+ * SYNTH_EDEVICE if the array's device address cannot be obtained.  Every call
+ * on one device shares that device's array: calls that overlap on a device
+ * (concurrent streams or threads) race and must be serialised by the caller. */
+#define SYNTH_NOALLOC_SCRATCH_BYTES (16 << 20)
+int synth_render_noalloc(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
+                         uint64_t first_g, int64_t batch, const int64_t* offsets, int64_t n_samples,
+                         float* audio, void* stream);
+
 /* Same as synth_render with an explicit launch plan (used by the autotuner and
  * by tests): runs_per_segment in {1, 2, 4} splits each control period into
  * that many per-lane runs; slices_per_voice >= 1 splits each voice over that

@@ -3,6 +3,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
+#include <mutex>
+
 #include <hip/hip_runtime.h>
 
 #include "synth.h"
@@ -348,6 +351,52 @@ int synth_render_ws(const synth_config* cfg, const float* params, const uint64_t
   default_plan(cfg, batch, offsets, n_samples, true, &rps, &slices);
   return render_plan_impl(cfg, params, voice_ids, first_g, batch, offsets, n_samples, n_samples,
                           audio, rps, slices, 0, 0, nullptr, workspace, workspace_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free render.  The chunk-carry workspace of synth_render_ws comes
+// from a static device array, `scratch`: each device the library runs on holds
+// its own copy until the process ends.  In host code `scratch` names a
+// host-side stand-in, not device memory, so its device address is looked up
+// once per device (hipGetSymbolAddress, with that device current) and only
+// that address is passed to kernels.  Every call on a device shares its array:
+// calls that overlap on one device (concurrent streams or threads) race.  The
+// carry kernels write every entry the render reads in the same call, so
+// nothing needs clearing between calls.
+// ---------------------------------------------------------------------------
+namespace {
+static __device__ __align__(256) unsigned char scratch[SYNTH_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+std::atomic<void*> g_scratch_ptr[kMaxDevices];
+
+// This device's address of `scratch`, or nullptr if it cannot be looked up.
+void* device_scratch() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  void* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+  if (p) return p;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+  if (!p) {
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev].store(p, std::memory_order_release);
+  }
+  return p;
+}
+}  // namespace
+
+int synth_render_noalloc(const synth_config* cfg, const float* params, const uint64_t* voice_ids,
+                         uint64_t first_g, int64_t batch, const int64_t* offsets, int64_t n_samples,
+                         float* audio, void* stream) {
+  const size_t need = offsets ? 0 : synth_render_workspace(cfg, batch, n_samples);
+  if (need == 0)      // the default plan needs no workspace: this is synth_render
+    return synth_render(cfg, params, voice_ids, first_g, batch, offsets, n_samples, audio, stream);
+  if (need > (size_t)SYNTH_NOALLOC_SCRATCH_BYTES) return SYNTH_ENOMEM;
+  void* ws = device_scratch();
+  if (!ws) return SYNTH_EDEVICE;
+  return synth_render_ws(cfg, params, voice_ids, first_g, batch, offsets, n_samples, audio, ws,
+                         (size_t)SYNTH_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 size_t synth_render_backward_workspace(const synth_config* cfg, int64_t batch, int64_t n_samples) {
