@@ -48,6 +48,53 @@ __device__ void zero_fill(float* out, int64_t z0, int64_t z1, int lane, bool ali
   }
 }
 
+// Four consecutive samples li .. li + 3 of a pass (one segment): tile value
+// plus noise through the noise VCA.  wa, wb: the Philox words of the samples
+// (16-bit halves, low half first); x = (h + 0.5) / 32768 - 1 with the 2^-15
+// folded into the ramp namp (per segment of the pass: value at the segment's
+// first sample and slope).  The segment index li / q is formed in float32:
+// (li + 1/2) / q lies at least 1/(2q) from an integer and li < 64 q, so the
+// truncation is exact.
+__device__ __forceinline__ void noise_vca4(float* o, uint32_t wa, uint32_t wb, float4 t, int li,
+                                           int q, float inv_qf, const float2* namp) {
+  const int lsg = (int)fmaf((float)li, inv_qf, 0.5f * inv_qf);
+  const float2 na = namp[lsg];
+  const float a0 = fmaf((float)(li - __mul24(lsg, q)), na.y, na.x);
+  o[0] = fmaf((float)(wa & 0xFFFFu) - 32767.5f, a0, t.x);
+  o[1] = fmaf((float)(wa >> 16) - 32767.5f, fmaf(1.0f, na.y, a0), t.y);
+  o[2] = fmaf((float)(wb & 0xFFFFu) - 32767.5f, fmaf(2.0f, na.y, a0), t.z);
+  o[3] = fmaf((float)(wb >> 16) - 32767.5f, fmaf(3.0f, na.y, a0), t.w);
+}
+
+// Noise group gi of a pass: samples 8 gi .. 8 gi + 7 (pass-local; the pass
+// starts at a multiple of 8 samples), one Philox call whose four words hold
+// their 16-bit noise in sample order, added through the noise VCA to the tile
+// values and written to out[8 gi ..] (VEC: two 16-byte stores, the group
+// whole and out 16-byte aligned; else element by element below cnt).  The
+// tile holds a multiple of 8 floats >= cnt, so its reads stay inside it.
+template <bool VEC>
+__device__ __forceinline__ void noise_group(float* out, const float* tile, int gi, int cnt,
+                                            uint32_t glo, uint32_t ghi, uint32_t grp0, uint32_t k0,
+                                            uint32_t k1, int q, float inv_qf, const float2* namp) {
+  const int li = 8 * gi;
+  uint32_t w[4] = {glo, ghi, grp0 + (uint32_t)gi, 1u};
+  philox4x32_10(w, k0, k1);
+  const float4 ta = *reinterpret_cast<const float4*>(tile + li);
+  const float4 tb = *reinterpret_cast<const float4*>(tile + li + 4);
+  float o[8];
+  noise_vca4(o, w[0], w[1], ta, li, q, inv_qf, namp);
+  noise_vca4(o + 4, w[2], w[3], tb, li + 4, q, inv_qf, namp);
+  float* dst = out + li;
+  if constexpr (VEC) {
+    *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
+    *reinterpret_cast<float4*>(dst + 4) = make_float4(o[4], o[5], o[6], o[7]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if (li + e < cnt) dst[e] = o[e];
+  }
+}
+
 template <int RPS, bool CLAMP>
 __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShared& sh,
                             float* tile) {
@@ -99,6 +146,7 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
   const double L1 = v[75], L2 = v[76], L3 = v[77];
 
   const uint32_t glo = (uint32_t)g, ghi = (uint32_t)(g >> 32);
+  const float inv_qf = 1.0f / (float)q;
 
   int64_t c_start = 0;
   if (a.carries && c_lo > 0 && c_lo < a.carry_stride) {
@@ -159,17 +207,19 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
         }
       }
       t1 -= rint(t1);                            // exact; see sin_cycles_run
-      float kf = (float)(m * h);
+      // VCA ramps at the run's first sample, then advanced by their slopes
+      // (float32; 25 additions move them by about 1e-6 relative)
+      const float kf0 = (float)(m * h);
+      float A1 = fmaf(kf0, A1d, A10);
+      float A2 = fmaf(kf0, A2d, A20);
       float* trow = tile + lane * h;
       // Consume the LDS and cross-lane loads here, so that the loop below
       // carries no wait on them (its own LDS stores are never waited for).
       asm volatile("" ::"v"(t1), "v"(i1), "v"(t2), "v"(i2), "v"(r1), "v"(r2));
-      asm volatile("" ::"v"(A10), "v"(A1d), "v"(A20), "v"(A2d));
+      asm volatile("" ::"v"(A1), "v"(A1d), "v"(A2), "v"(A2d));
       for (int k = 0; k < h; ++k) {
         const float x1 = sin_cycles_run(t1);
-        const float x2 = squaresaw_shape(t2, K2, shape);   // gain (1 - s/2) is in A2
-        const float A1 = fmaf(kf, A1d, A10);
-        const float A2 = fmaf(kf, A2d, A20);
+        const float x2 = squaresaw_unit(t2, K2, shape);   // gain (1 - s/2) is in A2
         trow[k] = fmaf(A2, x2, A1 * x1);
         if constexpr (CLAMP) {
           t1 += fmin(i1, 0.5); t2 += fmin(i2, 0.5);
@@ -178,52 +228,33 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
         }
         i1 *= r1;
         i2 *= r2;
-        kf += 1.0f;
+        A1 += A1d;
+        A2 += A2d;
       }
       __syncthreads();
-      // Store pass: noise + VCA, 4 consecutive samples per lane per 16-byte store.
-      // Every lane computes one Philox call (8 noise samples) per 512 samples;
-      // lane l's 4 samples of each 256-sample half take two of its group's
-      // words from the lane that drew them.  4 samples never straddle a
-      // segment because q is a multiple of 4.
+      // Store pass: noise + VCA.  Lane l takes noise groups gi = l, l + 64, ...
+      // of the pass: one Philox call gives the 16-bit noise of samples 8 gi ..
+      // 8 gi + 7 in its four words, in sample order, so no lane needs another's
+      // words; the lane adds them through the noise VCA to its 8 tile samples
+      // and writes them with two 16-byte stores.  The pass starts at a sample
+      // that is a multiple of 8 (16, 32 or 64 segments of q = 4k samples), and
+      // 4 samples never straddle a segment because q is a multiple of 4.
       const int64_t pbase = (c * kSegsPerChunk + (int64_t)p * segs_pp) * q;
       int64_t cnt64 = (int64_t)((nseg - p * segs_pp) < segs_pp ? (nseg - p * segs_pp) : segs_pp) * q;
       if (cnt64 > N - pbase) cnt64 = N - pbase;
       const int cnt = (int)cnt64;
       const uint32_t grp0 = (uint32_t)(pbase >> 3);
       const int seg0 = p * segs_pp;
-      for (int base = 0; base < cnt; base += 512) {
-        uint32_t w[4] = {glo, ghi, grp0 + (uint32_t)(base >> 3) + (uint32_t)lane, 1u};
-        philox4x32_10(w, a.nk0, a.nk1);
-#pragma unroll
-        for (int sub = 0; sub < 2; ++sub) {
-          const int src_l = sub * 32 + (lane >> 1);
-          const uint32_t w0 = __shfl(w[0], src_l), w1 = __shfl(w[1], src_l);
-          const uint32_t w2 = __shfl(w[2], src_l), w3 = __shfl(w[3], src_l);
-          const uint32_t wa = (lane & 1) ? w2 : w0;
-          const uint32_t wb = (lane & 1) ? w3 : w1;
-          const int li = base + sub * 256 + 4 * lane;   // pass-local sample
-          if (li < cnt) {
-            const int lsg = (int)__umulhi((uint32_t)li, a.q_magic);   // li / q
-            const float2 na = sh.namp[seg0 + lsg];
-            const float a0 = fmaf((float)(li - lsg * q), na.y, na.x);   // noise VCA at li
-            const float4 t4 = *reinterpret_cast<const float4*>(tile + li);
-            float o[4];
-            o[0] = fmaf((float)(wa & 0xFFFFu) - 32767.5f, a0, t4.x);
-            o[1] = fmaf((float)(wa >> 16) - 32767.5f, fmaf(1.0f, na.y, a0), t4.y);
-            o[2] = fmaf((float)(wb & 0xFFFFu) - 32767.5f, fmaf(2.0f, na.y, a0), t4.z);
-            o[3] = fmaf((float)(wb >> 16) - 32767.5f, fmaf(3.0f, na.y, a0), t4.w);
-            float* dst = out + pbase + li;
-            if (aligned && li + 4 <= cnt) {
-              *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
-            } else {
-#pragma unroll
-              for (int e = 0; e < 4; ++e)
-                if (li + e < cnt) dst[e] = o[e];
-            }
-          }
-        }
-      }
+      // whole groups with vector stores (no branch in the loop body), then
+      // the last partial group, or every group of an unaligned voice, element
+      // by element
+      const int full = aligned ? (cnt & ~7) : 0;
+      for (int gi = lane; 8 * gi < full; gi += kWave)
+        noise_group<true>(out + pbase, tile, gi, cnt, glo, ghi, grp0, a.nk0, a.nk1, q, inv_qf,
+                          sh.namp + seg0);
+      for (int gi = (full >> 3) + lane; 8 * gi < cnt; gi += kWave)
+        noise_group<false>(out + pbase, tile, gi, cnt, glo, ghi, grp0, a.nk0, a.nk1, q, inv_qf,
+                           sh.namp + seg0);
       __syncthreads();
     }
   }

@@ -205,34 +205,25 @@ __device__ __forceinline__ float sin_cycles_run(double th) {
   return __builtin_amdgcn_sinf((float)th);
 }
 
-// sin and cos of 2 pi th for the square-saw.  Its tanh edge multiplies the
-// sine by K (up to ~1600) at every zero crossing, so the sine must be
-// relatively accurate there, at th = 0 and th = 1/2 alike: th is reduced to
-// the nearest half cycle in float64, r = th - n/2 in [-1/4, 1/4] (exact),
-// sin(2 pi th) = (-1)^n sin(2 pi r), cos(2 pi th) = (-1)^n cos(2 pi r).  The
-// hardware sine has ~9e-7 relative error near 0, which moves tanh(K sin) by
-// at most ~4e-7.
-__device__ __forceinline__ void sincos_cycles(double th, float& s, float& c) {
+// Square-saw without its gain (1 - s/2), which the caller folds into the VCA:
+// tanh(K sin 2 pi th) (1 + shape cos 2 pi th), K2 = 2 log2(e) K.  Its tanh
+// edge multiplies the sine by K (up to ~1600) at every zero crossing, so the
+// sine must be relatively accurate there, at th = 0 and th = 1/2 alike: th is
+// reduced to the nearest half cycle in float64, r = th - n/2 in [-1/4, 1/4]
+// (exact), and with s = sin 2 pi r, c = cos 2 pi r (hardware, ~9e-7 relative
+// near 0, moving tanh(K s) by at most ~4e-7) and sigma = (-1)^n,
+// sin 2 pi th = sigma s and cos 2 pi th = sigma c; tanh is odd, so the value
+// is tanh(K s) (sigma + shape c).  tanh(z) = 1 - 2 / (exp(2z) + 1) from
+// z2 = 2 log2(e) z saturates to +-1 through exp2 overflow or underflow
+// (absolute error ~1e-7).
+__device__ __forceinline__ float squaresaw_unit(double th, float K2, float shape) {
   const double n = rint(2.0 * th);
   const float r = (float)fma(-0.5, n, th);
-  const uint32_t flip = ((uint32_t)(int)n) << 31;     // sign bit of (-1)^n
-  s = __uint_as_float(__float_as_uint(__builtin_amdgcn_sinf(r)) ^ flip);
-  c = __uint_as_float(__float_as_uint(__builtin_amdgcn_cosf(r)) ^ flip);
-}
-
-// tanh(z) = 1 - 2 / (exp(2z) + 1) from z2 = 2 log2(e) z; saturates to +-1
-// through exp2 overflow or underflow, absolute error ~1e-7.
-__device__ __forceinline__ float tanh_from_log2(float z2) {
-  const float e = __builtin_amdgcn_exp2f(z2);
-  return fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
-}
-
-// Square-saw without its gain (1 - s/2), which the caller folds into the
-// VCA: tanh(K sin 2 pi th) (1 + s cos 2 pi th); K2 = 2 log2(e) K.
-__device__ __forceinline__ float squaresaw_shape(double th, float K2, float shape) {
-  float s, c;
-  sincos_cycles(th, s, c);
-  return tanh_from_log2(K2 * s) * fmaf(shape, c, 1.0f);
+  const float s = __builtin_amdgcn_sinf(r), c = __builtin_amdgcn_cosf(r);
+  const float sigma = __uint_as_float((((uint32_t)(int)n) << 31) | 0x3F800000u);   // (-1)^n
+  const float e = __builtin_amdgcn_exp2f(K2 * s);
+  const float t = fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
+  return t * fmaf(shape, c, sigma);
 }
 
 // expm1(x) in float64: Taylor series to x^8 for |x| <= 1/64 (relative
