@@ -217,6 +217,7 @@ __device__ void render_item(const RenderArgs& a, int64_t b, int slice, VoiceShar
       // carries no wait on them (its own LDS stores are never waited for).
       asm volatile("" ::"v"(t1), "v"(i1), "v"(t2), "v"(i2), "v"(r1), "v"(r2));
       asm volatile("" ::"v"(A1), "v"(A1d), "v"(A2), "v"(A2d));
+#pragma unroll 5
       for (int k = 0; k < h; ++k) {
         const float x1 = sin_cycles_run(t1);
         const float x2 = squaresaw_unit(t2, K2, shape);   // gain (1 - s/2) is in A2

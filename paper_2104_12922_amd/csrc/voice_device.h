@@ -5,6 +5,7 @@
 
 #include <math.h>
 
+#include "series_tables.h"
 #include "synth_internal.h"
 
 namespace synth {
@@ -16,38 +17,63 @@ constexpr int kPointsPerChunk = kSegsPerChunk + 1;
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kLn2 = 0.693147180559945309417232121458;
 
+// Series coefficients in device memory.  Machine LICM is off (see build.py),
+// so a float64 constant used in a loop is rematerialised with two VALU moves
+// at every use; read from memory the compiler cannot fold, uniform addresses
+// become scalar loads into SGPRs, which the float64 FMAs take as operands.
+enum {
+  kExpC3 = 0, kExpC4, kExpC5,                              // 1/3!, 1/4!, 1/5!
+  kLogC3, kLogC4, kLogC5, kLogC6, kLogC7,                  // 1/3, -1/4, 1/5, -1/6, 1/7
+  kSin3, kSin5, kSin7, kSin9, kSin11, kSin13, kSin15, kSin17, kSin19, kSin21, kSin23,
+  kCos2, kCos4, kCos6, kCos8, kCos10, kCos12, kCos14, kCos16, kCos18, kCos20, kCos22,
+  kEm3, kEm4, kEm5, kEm6, kEm7, kEm8, kEm9, kEm10, kEm11, kEm12, kEm13, kEm14, kEm15,
+  kNumSeriesC
+};
+static __device__ double kSeriesC[kNumSeriesC] = {
+    1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0,
+    1.0 / 3.0, -0.25, 1.0 / 5.0, -1.0 / 6.0, 1.0 / 7.0,
+    // (-1)^k / (2k + 1)!, k = 1 .. 11
+    -1.0 / 6.0, 1.0 / 120.0, -1.0 / 5040.0, 1.0 / 362880.0, -1.0 / 39916800.0,
+    1.0 / 6227020800.0, -1.0 / 1307674368000.0, 1.0 / 355687428096000.0,
+    -1.0 / 121645100408832000.0, 1.0 / 51090942171709440000.0, -1.0 / 25852016738884976640000.0,
+    // (-1)^k / (2k)!, k = 1 .. 11
+    -0.5, 1.0 / 24.0, -1.0 / 720.0, 1.0 / 40320.0, -1.0 / 3628800.0, 1.0 / 479001600.0,
+    -1.0 / 87178291200.0, 1.0 / 20922789888000.0, -1.0 / 6402373705728000.0,
+    1.0 / 2432902008176640000.0, -1.0 / 1124000727777607680000.0,
+    // 1 / k!, k = 3 .. 15
+    1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0, 1.0 / 5040.0, 1.0 / 40320.0,
+    1.0 / 362880.0, 1.0 / 3628800.0, 1.0 / 39916800.0, 1.0 / 479001600.0,
+    1.0 / 6227020800.0, 1.0 / 87178291200.0, 1.0 / 1307674368000.0};
+
 // ---------------------------------------------------------------------------
 // float64 control-rate helpers
 // ---------------------------------------------------------------------------
-// 2^y in float64: y = n + f with n = rint(y), |f| <= 1/2, and
-// 2^f = exp(f ln 2) by its Taylor series to degree 13 (|f ln 2| < 0.35:
-// truncation below 2e-16 relative), scaled by 2^n.  y is clamped to
+// 2^y in float64 by Tang's table-driven method (ACM TOMS 15(2), 1989): with
+// n = rint(256 y), y = e + j/256 + r, j = n mod 256, e = floor(n / 256) and
+// r = y - n/256 exact (|r| <= 1/512), 2^y = 2^e 2^(j/256) exp(r ln 2); the
+// table entry is correctly rounded and exp(z), |z| <= 0.0014, its Taylor
+// series to degree 5 (truncation below 1e-20 relative).  y is clamped to
 // [-1100, 1023] (below -1075 the result is 0).
 __device__ __forceinline__ double exp2_f64(double y) {
   y = fmin(fmax(y, -1100.0), 1023.0);
-  const double n = rint(y);
-  const double z = (y - n) * kLn2;            // y - n is exact
-  double p = 1.0 / 6227020800.0;              // 1/13!
-  p = fma(p, z, 1.0 / 479001600.0);
-  p = fma(p, z, 1.0 / 39916800.0);
-  p = fma(p, z, 1.0 / 3628800.0);
-  p = fma(p, z, 1.0 / 362880.0);
-  p = fma(p, z, 1.0 / 40320.0);
-  p = fma(p, z, 1.0 / 5040.0);
-  p = fma(p, z, 1.0 / 720.0);
-  p = fma(p, z, 1.0 / 120.0);
-  p = fma(p, z, 1.0 / 24.0);
-  p = fma(p, z, 1.0 / 6.0);
+  const double nd = rint(y * 256.0);
+  const int n = (int)nd;
+  const double z = fma(nd, -1.0 / 256.0, y) * kLn2;
+  double p = fma(z, kSeriesC[kExpC5], kSeriesC[kExpC4]);
+  p = fma(p, z, kSeriesC[kExpC3]);
   p = fma(p, z, 0.5);
   p = fma(p, z, 1.0);
   p = fma(p, z, 1.0);
-  return ldexp(p, (int)n);
+  return ldexp(kExp2T[n & 255] * p, n >> 8);
 }
 
-// log2(x) for finite x > 0 in float64: x = m 2^e with m in [sqrt(1/2),
-// sqrt(2)), ln m = 2 atanh(t) with t = (m - 1) / (m + 1), |t| < 0.172, by the
-// odd series 2 (t + t^3/3 + ... + t^17/17) (truncation below 1e-15 relative).
-// 1 / (m + 1) is the hardware reciprocal refined by two Newton steps.
+// log2(x) for finite x > 0 in float64 by the table-driven method (Tang, ACM
+// TOMS 16(4), 1990): x = m 2^e with m in [1/sqrt 2, sqrt 2), c = 1 + j/256 the
+// table point nearest m (j = rint(256 (m - 1)) in -75 .. 106), u = m/c - 1
+// formed as m (1/c) - 1 with the correctly rounded 1/c (|u| <= 0.0028,
+// absolute error ~1e-16), log2 x = (e + log2 c) + log1p(u) / ln 2 with log1p
+// by its series to degree 7 (truncation below 1e-21); near x = 1 both c = 1
+// and log2 c = 0, so the result stays relatively accurate there.
 __device__ __forceinline__ double log2_f64(double x) {
   int e;
   double m = frexp(x, &e);                    // m in [1/2, 1)
@@ -55,22 +81,15 @@ __device__ __forceinline__ double log2_f64(double x) {
     m *= 2.0;
     e -= 1;
   }
-  const double d = m + 1.0;
-  double r = __builtin_amdgcn_rcp(d);
-  r = fma(fma(-d, r, 1.0), r, r);
-  r = fma(fma(-d, r, 1.0), r, r);
-  const double t = (m - 1.0) * r;
-  const double t2 = t * t;
-  double p = 1.0 / 17.0;
-  p = fma(p, t2, 1.0 / 15.0);
-  p = fma(p, t2, 1.0 / 13.0);
-  p = fma(p, t2, 1.0 / 11.0);
-  p = fma(p, t2, 1.0 / 9.0);
-  p = fma(p, t2, 1.0 / 7.0);
-  p = fma(p, t2, 1.0 / 5.0);
-  p = fma(p, t2, 1.0 / 3.0);
-  p = fma(p, t2, 1.0);
-  return fma(2.0 * t * p, 1.0 / kLn2, (double)e);
+  const int j = (int)rint((m - 1.0) * 256.0) + kLogJ0;
+  const double u = fma(m, kInvC[j], -1.0);
+  double p = fma(u, kSeriesC[kLogC7], kSeriesC[kLogC6]);
+  p = fma(p, u, kSeriesC[kLogC5]);
+  p = fma(p, u, kSeriesC[kLogC4]);
+  p = fma(p, u, kSeriesC[kLogC3]);
+  p = fma(p, u, -0.5);
+  p = fma(p, u, 1.0);
+  return fma(p * u, 1.0 / kLn2, kLog2T[j] + (double)e);
 }
 
 // sin(2 pi p) in float64 for a phase p in cycles: r = p - rint(p) in
@@ -82,17 +101,9 @@ __device__ __forceinline__ double sin_cycles_f64(double p) {
   if (r > 0.25) r = 0.5 - r;
   if (r < -0.25) r = -0.5 - r;
   const double a = r * kTwoPi, a2 = a * a;
-  double s = -1.0 / 25852016738884976640000.0;      // -1/23!
-  s = fma(s, a2, 1.0 / 51090942171709440000.0);     // 1/21!
-  s = fma(s, a2, -1.0 / 121645100408832000.0);
-  s = fma(s, a2, 1.0 / 355687428096000.0);
-  s = fma(s, a2, -1.0 / 1307674368000.0);
-  s = fma(s, a2, 1.0 / 6227020800.0);
-  s = fma(s, a2, -1.0 / 39916800.0);
-  s = fma(s, a2, 1.0 / 362880.0);
-  s = fma(s, a2, -1.0 / 5040.0);
-  s = fma(s, a2, 1.0 / 120.0);
-  s = fma(s, a2, -1.0 / 6.0);
+  double s = kSeriesC[kSin23];
+#pragma unroll
+  for (int k = kSin21; k >= kSin3; --k) s = fma(s, a2, kSeriesC[k]);
   s = fma(s, a2, 1.0);
   return s * a;
 }
@@ -105,30 +116,14 @@ __device__ __forceinline__ double sin_cycles_f64(double p) {
 __device__ __forceinline__ void sincos_cycles_f64(double th, double& s, double& c) {
   const double n = rint(2.0 * th);
   const double a = fma(-0.5, n, th) * kTwoPi, a2 = a * a;
-  double ps = -1.0 / 25852016738884976640000.0;      // -1/23!
-  ps = fma(ps, a2, 1.0 / 51090942171709440000.0);
-  ps = fma(ps, a2, -1.0 / 121645100408832000.0);
-  ps = fma(ps, a2, 1.0 / 355687428096000.0);
-  ps = fma(ps, a2, -1.0 / 1307674368000.0);
-  ps = fma(ps, a2, 1.0 / 6227020800.0);
-  ps = fma(ps, a2, -1.0 / 39916800.0);
-  ps = fma(ps, a2, 1.0 / 362880.0);
-  ps = fma(ps, a2, -1.0 / 5040.0);
-  ps = fma(ps, a2, 1.0 / 120.0);
-  ps = fma(ps, a2, -1.0 / 6.0);
+  double ps = kSeriesC[kSin23];
+#pragma unroll
+  for (int k = kSin21; k >= kSin3; --k) ps = fma(ps, a2, kSeriesC[k]);
   ps = fma(ps, a2, 1.0);
-  double pc = 1.0 / 1124000727777607680000.0;       // 1/22!
-  pc = fma(pc, a2, -1.0 / 2432902008176640000.0);
-  pc = fma(pc, a2, 1.0 / 6402373705728000.0);
-  pc = fma(pc, a2, -1.0 / 20922789888000.0);
-  pc = fma(pc, a2, 1.0 / 87178291200.0);
-  pc = fma(pc, a2, -1.0 / 479001600.0);
-  pc = fma(pc, a2, 1.0 / 3628800.0);
-  pc = fma(pc, a2, -1.0 / 40320.0);
-  pc = fma(pc, a2, 1.0 / 720.0);
-  pc = fma(pc, a2, -1.0 / 24.0);
-  pc = fma(pc, a2, 0.5);
-  pc = fma(pc, -a2, 1.0);
+  double pc = kSeriesC[kCos22];
+#pragma unroll
+  for (int k = kCos20; k >= kCos2; --k) pc = fma(pc, a2, kSeriesC[k]);
+  pc = fma(pc, a2, 1.0);
   const double sg = (((int)n) & 1) ? -1.0 : 1.0;
   s = sg * (ps * a);
   c = sg * pc;
@@ -138,18 +133,10 @@ __device__ __forceinline__ void sincos_cycles_f64(double th, double& s, double& 
 __device__ __forceinline__ double cos_cycles_f64(double th) {
   const double n = rint(2.0 * th);
   const double a = fma(-0.5, n, th) * kTwoPi, a2 = a * a;
-  double pc = 1.0 / 1124000727777607680000.0;       // 1/22!
-  pc = fma(pc, a2, -1.0 / 2432902008176640000.0);
-  pc = fma(pc, a2, 1.0 / 6402373705728000.0);
-  pc = fma(pc, a2, -1.0 / 20922789888000.0);
-  pc = fma(pc, a2, 1.0 / 87178291200.0);
-  pc = fma(pc, a2, -1.0 / 479001600.0);
-  pc = fma(pc, a2, 1.0 / 3628800.0);
-  pc = fma(pc, a2, -1.0 / 40320.0);
-  pc = fma(pc, a2, 1.0 / 720.0);
-  pc = fma(pc, a2, -1.0 / 24.0);
-  pc = fma(pc, a2, 0.5);
-  pc = fma(pc, -a2, 1.0);
+  double pc = kSeriesC[kCos22];
+#pragma unroll
+  for (int k = kCos20; k >= kCos2; --k) pc = fma(pc, a2, kSeriesC[k]);
+  pc = fma(pc, a2, 1.0);
   return (((int)n) & 1) ? -pc : pc;
 }
 
@@ -232,30 +219,17 @@ __device__ __forceinline__ float squaresaw_unit(double th, float K2, float shape
 // otherwise.
 __device__ __forceinline__ double expm1_f64(double x) {
   if (fabs(x) <= 0.015625) {
-    double p = 1.0 / 40320.0;                // 1/8!
-    p = fma(p, x, 1.0 / 5040.0);
-    p = fma(p, x, 1.0 / 720.0);
-    p = fma(p, x, 1.0 / 120.0);
-    p = fma(p, x, 1.0 / 24.0);
-    p = fma(p, x, 1.0 / 6.0);
+    double p = kSeriesC[kEm8];
+#pragma unroll
+    for (int k = kEm7; k >= kEm3; --k) p = fma(p, x, kSeriesC[k]);
     p = fma(p, x, 0.5);
     p = fma(p, x, 1.0);
     return p * x;
   }
   if (fabs(x) > 0.25) return expm1(x);
-  double p = 1.0 / 1307674368000.0;          // 1/15!
-  p = fma(p, x, 1.0 / 87178291200.0);
-  p = fma(p, x, 1.0 / 6227020800.0);
-  p = fma(p, x, 1.0 / 479001600.0);
-  p = fma(p, x, 1.0 / 39916800.0);
-  p = fma(p, x, 1.0 / 3628800.0);
-  p = fma(p, x, 1.0 / 362880.0);
-  p = fma(p, x, 1.0 / 40320.0);
-  p = fma(p, x, 1.0 / 5040.0);
-  p = fma(p, x, 1.0 / 720.0);
-  p = fma(p, x, 1.0 / 120.0);
-  p = fma(p, x, 1.0 / 24.0);
-  p = fma(p, x, 1.0 / 6.0);
+  double p = kSeriesC[kEm15];
+#pragma unroll
+  for (int k = kEm14; k >= kEm3; --k) p = fma(p, x, kSeriesC[k]);
   p = fma(p, x, 0.5);
   p = fma(p, x, 1.0);
   return p * x;

@@ -1,10 +1,11 @@
-"""Accuracy of the float64 series the render's control stage evaluates on the
-GPU (exp2 by rint + Taylor, log2 by frexp + the atanh series, sin of a phase
-in cycles by quarter-cycle folding + Taylor, expm1 by Taylor for small
-arguments), re-evaluated here step by step in numpy float64 with the same
-reductions and the same numbers of terms, against numpy's library functions.
-The render's parity tests see these functions only through audio at 1e-4;
-this pins the ~1e-13 relative accuracy they are documented with."""
+"""Accuracy of the float64 series the render's control stage and the adjoint
+evaluate on the GPU (exp2 and log2 by Tang's table-driven method, sin of a
+phase in cycles by quarter-cycle folding + Taylor, expm1 by Taylor for small
+arguments, sine and cosine by half-cycle reduction + Taylor), re-evaluated
+here step by step in numpy float64 with the same reductions, tables and
+numbers of terms, against numpy's library functions.  The render's parity
+tests see these functions only through audio at 1e-4; this pins the ~1e-13
+relative accuracy they are documented with (about 1e-16 per function)."""
 import math
 
 import numpy as np
@@ -19,12 +20,29 @@ def horner(coefs, x):
     return p
 
 
+def _tables():
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2104_12922_amd", "csrc", "gen_series_tables.py")
+    spec = importlib.util.spec_from_file_location("gen_series_tables", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    e, l, c = mod.tables()
+    return (np.array([float(v) for v in e]), np.array([float(v) for v in l]),
+            np.array([float(v) for v in c]))
+
+
+EXP2_T, LOG2_T, INV_C = _tables()
+
+
 def exp2_series(y):
     y = np.clip(y, -1100.0, 1023.0)
-    n = np.rint(y)
-    z = (y - n) * LN2
-    p = horner([1.0 / math.factorial(k) for k in range(13, -1, -1)], z)
-    return np.ldexp(p, n.astype(np.int64))
+    nd = np.rint(y * 256.0)
+    n = nd.astype(np.int64)
+    z = (y - nd / 256.0) * LN2                       # exact difference
+    p = horner([1.0 / math.factorial(k) for k in range(5, -1, -1)], z)
+    return np.ldexp(EXP2_T[n & 255] * p, n >> 8)
 
 
 def log2_series(x):
@@ -32,9 +50,11 @@ def log2_series(x):
     low = m < 0.70710678118654752
     m = np.where(low, 2.0 * m, m)
     e = np.where(low, e - 1, e)
-    t = (m - 1.0) / (m + 1.0)
-    p = horner([1.0 / k for k in range(17, 0, -2)], t * t)
-    return e + 2.0 * t * p / LN2
+    j = np.rint((m - 1.0) * 256.0).astype(np.int64) + 76
+    # u = fma(m, 1/c, -1): the product in extended precision, one rounding
+    u = (m.astype(np.longdouble) * INV_C[j].astype(np.longdouble) - 1).astype(np.float64)
+    p = horner([(-1.0) ** (k + 1) / k for k in range(7, 0, -1)], u)
+    return (LOG2_T[j] + e.astype(np.float64)) + p * u / LN2
 
 
 def sin_cycles_series(p):
