@@ -18,6 +18,9 @@ philox   Philox4x32-10 counter-based generator (Salmon et al., SC 2011), used
 voice    vectorised float64 Voice render (Sections 3.1-3.3).
 brute    scalar pure-Python Voice render for tiny inputs (pins ``voice``).
 spectral STFT, multi-resolution log-magnitude STFT L1 and log-mel features.
+mlp      the learned proposal's MLP forward/backward and Adam.
+mmd      maximum mean discrepancy between sets of sounds (Section 5) with the
+         L1 distance between log-mel embeddings.
 
 Parity status
 -------------
