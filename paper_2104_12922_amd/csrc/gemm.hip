@@ -64,15 +64,17 @@ __device__ __forceinline__ void load16_by4(const uint16_t* p, uint4& r0, uint4& 
 // flight during the MFMAs: load() fills two 16-byte registers per thread,
 // store() writes them to LDS.
 //   K-major: thread t takes row t / 2, k (t & 1) * 16 .. +15 (32 bytes).
-//   row-major (X[k * ld + r]): thread t takes k t / 8, rows (t & 7) * 16 ..
-//   +15, written to LDS transposed (16 two-byte writes).
+//   row-major (X[k * ld + r]): with G = NT / 32 groups of 16 rows, thread t
+//   takes k t / G, rows (t % G) * 16 .. +15, written to LDS transposed (16
+//   two-byte writes).  NT threads cover NT / 2 rows (a 128- or 256-row tile).
 // Rows of an even leading dimension that is not a multiple of 8 are read as
 // 4-byte words.  Tiles at the matrix edge or at the end K of the k-range (or
 // unaligned operands) are read element by element with bounds checks and zero
 // fill.
-template <int OP>
+template <int OP, int NT = 256>
 __device__ __forceinline__ void load_tile(uint4& r0, uint4& r1, int64_t K, const void* srcv,
                                           int64_t ld, int64_t row0, int64_t nrows, int64_t k0) {
+  constexpr int G = NT / 32;          // row-major: groups of 16 rows per k
   const int t = threadIdx.x;
   const uint16_t* src = reinterpret_cast<const uint16_t*>(srcv);
   uint16_t v[16];
@@ -94,8 +96,8 @@ __device__ __forceinline__ void load_tile(uint4& r0, uint4& r1, int64_t K, const
     for (int e = 0; e < 16; ++e)
       v[e] = (gr < nrows && kb + e < K) ? src[gr * ld + kb + e] : (uint16_t)0;
   } else {
-    const int64_t gk = k0 + (t >> 3);
-    const int64_t gr = row0 + (t & 7) * 16;
+    const int64_t gk = k0 + t / G;
+    const int64_t gr = row0 + (t % G) * 16;
     if (gk < K && gr + 16 <= nrows && ((ld & 7) == 0) && aligned16(src)) {
       const uint4* p = reinterpret_cast<const uint4*>(src + gk * ld + gr);
       r0 = p[0];
@@ -125,16 +127,17 @@ __device__ __forceinline__ void load_tile(uint4& r0, uint4& r1, int64_t K, const
 // k from a multiple of 8) is still one 16-byte read.
 __device__ __forceinline__ int swz_k(int row, int k) { return k ^ (((row >> 4) & 3) << 3); }
 
-template <int OP>
+template <int OP, int NT = 256>
 __device__ __forceinline__ void store_tile(const uint4& r0, const uint4& r1,
                                            uint16_t (*dst)[PADK]) {
+  constexpr int G = NT / 32;
   const int t = threadIdx.x;
   if constexpr (OP == kOpKMajor) {
     const int r = t >> 1, kk = (t & 1) * 16;
     *reinterpret_cast<uint4*>(&dst[r][swz_k(r, kk)]) = r0;
     *reinterpret_cast<uint4*>(&dst[r][swz_k(r, kk + 8)]) = r1;
   } else {
-    const int kk = t >> 3, rr = (t & 7) * 16;
+    const int kk = t / G, rr = (t % G) * 16;
     const uint32_t w[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
     const int kc = swz_k(rr, kk);       // rows rr .. rr + 15 share the permutation
 #pragma unroll
@@ -283,6 +286,112 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
     }
 }
 
+// Large tiles for the MLP's big products (output dims multiples of 256):
+// 256 x 256 x 32 per 512-thread workgroup, eight wavefronts in 2 x 4, each
+// 128 x 64 as 4 x 2 MFMA 32 x 32 blocks.  Per k-step a workgroup moves 32 KB
+// of operands for 4.2 MFLOP, half the bytes per flop of the 128 x 128 tile,
+// so the operand traffic from L2 and the last-level cache stays below what
+// the matrix cores consume.  Same staging, LDS layout, double buffering, split
+// K and epilogues (the standard ones; split K writes partials).
+constexpr int BM2 = 256, BN2 = 256;
+
+template <int AOP, int BOP>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
+    gemm_bf16_big_kernel(GemmArgs g) {
+  __shared__ __align__(16) uint16_t As[2][BM2][PADK];
+  __shared__ __align__(16) uint16_t Bs[2][BN2][PADK];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wave = t >> 6;
+  const int wm = wave >> 2, wn = wave & 3;
+  const int64_t tiles_n = g.N / BN2;
+  const int64_t tiles = (g.M / BM2) * tiles_n;
+  const int64_t tile = blockIdx.x % tiles;
+  const int64_t tm = tile / tiles_n, tn = tile % tiles_n;
+  const int64_t m0 = tm * BM2, n0 = tn * BN2;
+  const int split = g.split > 1 ? g.split : 1;
+  const int64_t part = blockIdx.x / tiles;
+  const int64_t kper = ((g.K + split - 1) / split + BK - 1) / BK * BK;
+  const int64_t kbeg = part * kper;
+  const int64_t kend = kbeg + kper < g.K ? kbeg + kper : g.K;
+
+  // eight named accumulators (an array of them is not kept in registers)
+  f32x16 c00 = {}, c01 = {}, c10 = {}, c11 = {}, c20 = {}, c21 = {}, c30 = {}, c31 = {};
+#define SYNTH_ACC(i, j) ((i) == 0 ? ((j) == 0 ? c00 : c01) : (i) == 1 ? ((j) == 0 ? c10 : c11) \
+                         : (i) == 2 ? ((j) == 0 ? c20 : c21) : ((j) == 0 ? c30 : c31))
+
+  uint4 a0, a1, b0, b1;
+  load_tile<AOP, 512>(a0, a1, kend, g.A, g.lda, m0, g.M, kbeg);
+  load_tile<BOP, 512>(b0, b1, kend, g.B, g.ldb, n0, g.N, kbeg);
+  store_tile<AOP, 512>(a0, a1, As[0]);
+  store_tile<BOP, 512>(b0, b1, Bs[0]);
+  __syncthreads();
+  const int64_t nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  for (int64_t ks = 0; ks < nk; ++ks) {
+    const int buf = (int)(ks & 1);
+    const bool more = ks + 1 < nk;
+    if (more) {
+      load_tile<AOP, 512>(a0, a1, kend, g.A, g.lda, m0, g.M, kbeg + (ks + 1) * BK);
+      load_tile<BOP, 512>(b0, b1, kend, g.B, g.ldb, n0, g.N, kbeg + (ks + 1) * BK);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      const int kq = kk + 8 * (lane >> 5);
+      bf16x8 af[4], bfr[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wm * 128 + i * 32 + (lane & 31);
+        af[i] = *reinterpret_cast<const bf16x8*>(&As[buf][r][swz_k(r, kq)]);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int r = wn * 64 + j * 32 + (lane & 31);
+        bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][r][swz_k(r, kq)]);
+      }
+      c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0], bfr[0], c00, 0, 0, 0);
+      c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0], bfr[1], c01, 0, 0, 0);
+      c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[1], bfr[0], c10, 0, 0, 0);
+      c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[1], bfr[1], c11, 0, 0, 0);
+      c20 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[2], bfr[0], c20, 0, 0, 0);
+      c21 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[2], bfr[1], c21, 0, 0, 0);
+      c30 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[3], bfr[0], c30, 0, 0, 0);
+      c31 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[3], bfr[1], c31, 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (more) {
+      store_tile<AOP, 512>(a0, a1, As[buf ^ 1]);
+      store_tile<BOP, 512>(b0, b1, Bs[buf ^ 1]);
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t col = n0 + wn * 64 + j * 32 + (lane & 31);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = m0 + wm * 128 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const float x = SYNTH_ACC(i, j)[v];
+        if (split > 1) g.partial[(part * g.M + row) * g.N + col] = x;
+        else epi_store(g, row, col, x * g.alpha);
+      }
+    }
+#undef SYNTH_ACC
+}
+
+// The large-tile kernel applies when both output dims are multiples of 256
+// (no edge tiles), K is a multiple of 32, the epilogue is a standard one, and
+// the operands take the 16-byte load path (leading dims multiples of 8,
+// 16-byte aligned pointers).
+bool big_tiles(const GemmArgs& g) {
+  return g.M % BM2 == 0 && g.N % BN2 == 0 && g.K % BK == 0 && g.K > 0 &&
+         g.epilogue <= kEpiGeluGrad && g.lda % 8 == 0 && g.ldb % 8 == 0 &&
+         (reinterpret_cast<uintptr_t>(g.A) & 15u) == 0 && (reinterpret_cast<uintptr_t>(g.B) & 15u) == 0;
+}
+
 // Sum of the split-K partials in part order, then the epilogue.
 __global__ void __launch_bounds__(256) gemm_split_reduce_kernel(GemmArgs g) {
   const int64_t n = g.M * g.N;
@@ -306,6 +415,13 @@ hipError_t launch_b(const GemmArgs& g, int b_op, dim3 grid, hipStream_t s) {
 }  // namespace
 
 int gemm_split_for(int64_t M, int64_t N, int64_t K) {
+  if (M % BM2 == 0 && N % BN2 == 0 && K % BK == 0 && K > 0) {
+    // large tiles: one 512-thread workgroup per CU, each part >= 8 k-steps
+    const int64_t tiles2 = (M / BM2) * (N / BN2);
+    int64_t split = 1;
+    while (tiles2 * split < 256 && K >= split * 2 * 8 * BK) split *= 2;
+    return (int)split;
+  }
   const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   int64_t split = 1;
   // double the split while the grid is under two workgroups per CU (one
@@ -322,16 +438,34 @@ size_t gemm_split_bytes(int64_t M, int64_t N, int split) {
 
 hipError_t launch_gemm_bf16(const GemmArgs& g, int a_op, int b_op, hipStream_t s) {
   if (g.M == 0 || g.N == 0) return hipSuccess;
-  const int64_t tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   const int split = g.split > 1 ? g.split : 1;
   if (split > 1 && (!g.partial || g.epilogue > kEpiGeluGrad)) return hipErrorInvalidValue;
-  if (tiles * split > 0x7FFFFFFF) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)(tiles * split));
+  if ((a_op != kOpKMajor && a_op != kOpRowMajorMN) || (b_op != kOpKMajor && b_op != kOpRowMajorMN))
+    return hipErrorInvalidValue;
   hipError_t e;
-  switch (a_op) {
-    case kOpKMajor: e = launch_b<kOpKMajor>(g, b_op, grid, s); break;
-    case kOpRowMajorMN: e = launch_b<kOpRowMajorMN>(g, b_op, grid, s); break;
-    default: return hipErrorInvalidValue;
+  if (big_tiles(g)) {
+    const int64_t tiles2 = (g.M / BM2) * (g.N / BN2);
+    if (tiles2 * split > 0x7FFFFFFF) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(tiles2 * split));
+    if (a_op == kOpKMajor) {
+      if (b_op == kOpKMajor)
+        hipLaunchKernelGGL((gemm_bf16_big_kernel<kOpKMajor, kOpKMajor>), grid, dim3(512), 0, s, g);
+      else
+        hipLaunchKernelGGL((gemm_bf16_big_kernel<kOpKMajor, kOpRowMajorMN>), grid, dim3(512), 0, s, g);
+    } else {
+      if (b_op == kOpKMajor)
+        hipLaunchKernelGGL((gemm_bf16_big_kernel<kOpRowMajorMN, kOpKMajor>), grid, dim3(512), 0, s, g);
+      else
+        hipLaunchKernelGGL((gemm_bf16_big_kernel<kOpRowMajorMN, kOpRowMajorMN>), grid, dim3(512), 0,
+                           s, g);
+    }
+    e = hipGetLastError();
+  } else {
+    const int64_t tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+    if (tiles * split > 0x7FFFFFFF) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(tiles * split));
+    e = a_op == kOpKMajor ? launch_b<kOpKMajor>(g, b_op, grid, s)
+                          : launch_b<kOpRowMajorMN>(g, b_op, grid, s);
   }
   if (e != hipSuccess || split == 1) return e;
   int64_t blocks = (g.M * g.N + 255) / 256;

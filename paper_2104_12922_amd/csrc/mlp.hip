@@ -107,20 +107,26 @@ __global__ void standardize_kernel(const float* __restrict__ x, const float* __r
 }
 
 // MSE on sigmoid outputs: loss_rows[r] = sum_c (o - u)^2; dz = 2 (o - u) o (1 - o) / (rows cols)
-__global__ void mse_sigmoid_grad_kernel(const float* __restrict__ out, const float* __restrict__ target,
-                                        int64_t rows, int64_t cols, uint16_t* __restrict__ dz,
-                                        double* __restrict__ loss_rows) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// One wavefront per row: lane c takes columns c, c + 64, ...; the row's
+// squared error is summed over lanes in a fixed tree (deterministic).
+__global__ void __launch_bounds__(256) mse_sigmoid_grad_kernel(const float* __restrict__ out,
+                                                               const float* __restrict__ target,
+                                                               int64_t rows, int64_t cols,
+                                                               uint16_t* __restrict__ dz,
+                                                               double* __restrict__ loss_rows) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= rows) return;
   const float scale = 2.0f / ((float)rows * (float)cols);
   double l = 0.0;
-  for (int64_t c = 0; c < cols; ++c) {
+  for (int64_t c = lane; c < cols; c += 64) {
     const float o = out[r * cols + c];
     const float d = o - target[r * cols + c];
     l += (double)d * d;
     dz[r * cols + c] = f2bf(scale * d * o * (1.0f - o));
   }
-  loss_rows[r] = l;
+  for (int off = 32; off > 0; off >>= 1) l += __shfl_down(l, off);
+  if (lane == 0) loss_rows[r] = l;
 }
 
 // Adam (bias-corrected) on float32 master weights, refreshing the bf16 copy.
@@ -240,7 +246,7 @@ hipError_t launch_mse_sigmoid_grad(const float* out, const float* target, int64_
                                    int64_t cols, void* dz_bf16, double* loss_rows,
                                    hipStream_t s) {
   if (rows == 0) return hipSuccess;
-  hipLaunchKernelGGL(mse_sigmoid_grad_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0,
+  hipLaunchKernelGGL(mse_sigmoid_grad_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0,
                      s, out, target, rows, cols, (uint16_t*)dz_bf16, loss_rows);
   return hipGetLastError();
 }

@@ -237,12 +237,28 @@ class MLP:
         self.device = torch.device(device)
         self.d_in, self.d_h, self.d_out = init["w1t"].shape[1], init["w1t"].shape[0], init["w3t"].shape[0]
         self.names = ("w1t", "b1", "w2t", "b2", "w3t", "b3")
-        self.w = {k: torch.as_tensor(np.asarray(init[k], np.float32)).to(self.device).contiguous()
-                  for k in self.names}
-        self.wb = {k: to_bf16(self.w[k]) for k in ("w1t", "w2t", "w3t")}
-        self.m = {k: torch.zeros_like(v) for k, v in self.w.items()}
-        self.v = {k: torch.zeros_like(v) for k, v in self.w.items()}
-        self.g = {k: torch.zeros_like(v) for k, v in self.w.items()}
+        # One flat buffer per state (weights, gradients, moments): the weight
+        # matrices first (their bf16 copies are one flat buffer too), then the
+        # biases, so that Adam is two launches; every view starts 16-byte
+        # aligned for the GEMMs' vector loads.
+        mats, vecs = ("w1t", "w2t", "w3t"), ("b1", "b2", "b3")
+        shapes = {k: tuple(np.asarray(init[k]).shape) for k in self.names}
+        sizes = {k: int(np.prod(shapes[k])) for k in self.names}
+        self._n_mat = sum(sizes[k] for k in mats)
+        n_all = self._n_mat + sum(sizes[k] for k in vecs)
+        flat = {s: torch.zeros(n_all, dtype=F32, device=self.device) for s in ("w", "m", "v", "g")}
+        self._flat = flat
+        self._wb_flat = torch.empty(self._n_mat, dtype=BF16, device=self.device)
+        off, views = 0, {}
+        for k in mats + vecs:
+            views[k] = (off, off + sizes[k])
+            off += sizes[k]
+        self.w, self.m, self.v, self.g = ({k: flat[s][a:b].view(shapes[k]) for k, (a, b) in views.items()}
+                                          for s in ("w", "m", "v", "g"))
+        for k in self.names:
+            self.w[k].copy_(torch.as_tensor(np.asarray(init[k], np.float32)))
+        self.wb = {k: self._wb_flat[views[k][0]:views[k][1]].view(shapes[k]) for k in mats}
+        to_bf16(flat["w"][:self._n_mat], out=self._wb_flat)
         self.lr, self.betas, self.eps = lr, betas, eps
         self.step_count = 0
         self._act_batch = 0
@@ -290,14 +306,17 @@ class MLP:
         return sum_f64(a["loss_rows"][:B], 1.0 / (B * self.d_out))
 
     def adam_step(self):
+        """One Adam step on every parameter: the weight matrices (refreshing
+        their bf16 copies) and the biases, two launches over the flat buffers."""
         self.step_count += 1
         b1, b2 = self.betas
-        for k in self.names:
+        f, n = self._flat, self._n_mat
+        for a, b, wb in ((0, n, self._wb_flat), (n, f["w"].numel(), None)):
             _native.check("synth_adam", lib().synth_adam(
-                self.w[k].numel(), self.w[k].data_ptr(),
-                self.wb[k].data_ptr() if k in self.wb else None, self.g[k].data_ptr(),
-                self.m[k].data_ptr(), self.v[k].data_ptr(), float(self.lr), float(b1), float(b2),
-                float(self.eps), self.step_count, _stream(self.device)))
+                b - a, f["w"][a:].data_ptr(), wb.data_ptr() if wb is not None else None,
+                f["g"][a:].data_ptr(), f["m"][a:].data_ptr(), f["v"][a:].data_ptr(),
+                float(self.lr), float(b1), float(b2), float(self.eps), self.step_count,
+                _stream(self.device)))
 
     def train_step(self, x_bf16, target):
         self.forward(x_bf16)

@@ -96,7 +96,8 @@ def rel(a, b):
     return float((a - b).norm() / max(b.norm(), 1e-300))
 
 
-@pytest.mark.parametrize("M,N,K", [(256, 256, 128), (200, 78, 100), (130, 300, 1000), (64, 1030, 2048)])
+@pytest.mark.parametrize("M,N,K", [(256, 256, 128), (512, 768, 1056), (200, 78, 100), (130, 300, 1000),
+                                   (64, 1030, 2048)])
 @pytest.mark.parametrize("a_layout,b_layout", [(0, 0), (0, 1), (1, 0), (1, 1)])
 def test_gemm_layouts(L, M, N, K, a_layout, b_layout):
     g = torch.Generator().manual_seed(M * 7 + N + K)
@@ -109,9 +110,9 @@ def test_gemm_layouts(L, M, N, K, a_layout, b_layout):
     assert rel(C.cpu(), ref) < 1e-5
 
 
+@pytest.mark.parametrize("M,N,K", [(300, 200, 256), (512, 256, 352)])   # edge tiles; 256-tiles
 @pytest.mark.parametrize("epi", [1, 2, 3])
-def test_gemm_epilogues(L, epi):
-    M, N, K = 300, 200, 256
+def test_gemm_epilogues(L, epi, M, N, K):
     g = torch.Generator().manual_seed(epi)
     A = torch.randn(M, K, generator=g).to(BF)
     Bt = (torch.randn(N, K, generator=g) / 16).to(BF)
