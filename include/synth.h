@@ -138,6 +138,23 @@ int synth_render_noalloc(const synth_config* cfg, const float* params, const uin
                          uint64_t first_g, int64_t batch, const int64_t* offsets, int64_t n_samples,
                          float* audio, void* stream);
 
+/* Corpus generator (Section 2.1: every sound of the corpus is addressed by
+ * its index and reproduced from the seed alone, parameters and noise alike;
+ * Section 2.2: a 9:1 train/test split in blocks of 1024).  For voices
+ * g = voice_ids[i] (dev uint64 [batch]) or first_g + i (voice_ids NULL):
+ *   params   dev float32 [batch][78]: synth_sample_params(seed, g)
+ *   audio    dev float32 [batch][n_samples]: synth_render of those
+ *            parameters with the noise keyed by seed (cfg->noise_seed is
+ *            not used; the rest of cfg as for synth_render)
+ *   is_test  dev uint8 [batch]: synth_is_test(g)
+ * workspace as synth_render_ws (synth_render_workspace(cfg, batch,
+ * n_samples) bytes, or NULL).  A voice's outputs depend only on (seed, g),
+ * so the corpus shards over devices and processes by ranges of g with no
+ * communication.  Errors as synth_sample_params and synth_render_ws. */
+int synth_generate(const synth_config* cfg, uint64_t seed, const uint64_t* voice_ids,
+                   uint64_t first_g, int64_t batch, int64_t n_samples, float* params, float* audio,
+                   uint8_t* is_test, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Same as synth_render with an explicit launch plan (used by the autotuner and
  * by tests): runs_per_segment in {1, 2, 4} splits each control period into
  * that many per-lane runs; slices_per_voice >= 1 splits each voice over that

@@ -59,6 +59,11 @@ def lib() -> ctypes.CDLL:
         L.synth_render.argtypes = render_args + [ctypes.c_void_p]
         L.synth_render_noalloc.restype = ctypes.c_int
         L.synth_render_noalloc.argtypes = render_args + [ctypes.c_void_p]
+        L.synth_generate.restype = ctypes.c_int
+        L.synth_generate.argtypes = [ctypes.POINTER(SynthConfig), ctypes.c_uint64, ctypes.c_void_p,
+                                     ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.synth_render_workspace.restype = ctypes.c_size_t
         L.synth_render_workspace.argtypes = [ctypes.POINTER(SynthConfig), ctypes.c_int64,
                                              ctypes.c_int64]

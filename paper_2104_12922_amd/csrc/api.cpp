@@ -399,6 +399,22 @@ int synth_render_noalloc(const synth_config* cfg, const float* params, const uin
                          (size_t)SYNTH_NOALLOC_SCRATCH_BYTES, stream);
 }
 
+int synth_generate(const synth_config* cfg, uint64_t seed, const uint64_t* voice_ids,
+                   uint64_t first_g, int64_t batch, int64_t n_samples, float* params, float* audio,
+                   uint8_t* is_test, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!cfg || batch < 0 || n_samples <= 0) return SYNTH_EINVAL;
+  if (batch == 0) return SYNTH_OK;
+  if (!params || !audio || !is_test) return SYNTH_EINVAL;
+  synth_config c = *cfg;
+  c.noise_seed = seed;               // the corpus's noise is keyed by its seed
+  int st = synth_sample_params(seed, first_g, batch, voice_ids, params, stream);
+  if (st != SYNTH_OK) return st;
+  st = synth_render_ws(&c, params, voice_ids, first_g, batch, nullptr, n_samples, audio, workspace,
+                       workspace_bytes, stream);
+  if (st != SYNTH_OK) return st;
+  return to_status(synth::launch_is_test(first_g, batch, voice_ids, is_test, (hipStream_t)stream));
+}
+
 size_t synth_render_backward_workspace(const synth_config* cfg, int64_t batch, int64_t n_samples) {
   RenderArgs a;
   bool clamp = false;

@@ -28,7 +28,25 @@ __global__ void __launch_bounds__(256) sample_params_kernel(uint64_t seed, uint6
   }
 }
 
+// is_test[i] = 1 if voice g = ids[i] (or first_g + i) lies in a test block:
+// (g div 1024) mod 10 == 9 (the corpus's 9:1 split in blocks of 1024).
+__global__ void __launch_bounds__(256) is_test_kernel(uint64_t first_g, int64_t batch,
+                                                      const uint64_t* ids, uint8_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  const uint64_t g = ids ? ids[i] : first_g + (uint64_t)i;
+  out[i] = (uint8_t)(((g >> 10) % 10u) == 9u);
+}
+
 }  // namespace
+
+hipError_t launch_is_test(uint64_t first_g, int64_t batch, const uint64_t* voice_ids,
+                          uint8_t* is_test, hipStream_t s) {
+  if (batch == 0) return hipSuccess;
+  hipLaunchKernelGGL(is_test_kernel, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s,
+                     first_g, batch, voice_ids, is_test);
+  return hipGetLastError();
+}
 
 hipError_t launch_sample_params(uint64_t seed, uint64_t first_g, int64_t batch,
                                 const uint64_t* voice_ids, float* params, hipStream_t s) {

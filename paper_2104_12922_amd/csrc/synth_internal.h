@@ -128,6 +128,8 @@ hipError_t launch_best_update(const double* loss, int64_t rows, int64_t cols, in
                               int64_t param_dim, double* best, int64_t* best_idx,
                               float* best_params, hipStream_t s);
 
+hipError_t launch_is_test(uint64_t first_g, int64_t batch, const uint64_t* voice_ids,
+                          uint8_t* is_test, hipStream_t s);
 hipError_t launch_sample_params(uint64_t seed, uint64_t first_g, int64_t batch,
                                 const uint64_t* voice_ids, float* params, hipStream_t s);
 
