@@ -42,9 +42,9 @@ RENDER_SLOTS_PER_SAMPLE = 38.0
 # from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB; the
 # factors make each counter read 1 GiB for a plain 1 GiB device copy).  Valid
 # only for the kernel sources with this digest; reported as null otherwise.
-RENDER_TRAFFIC = {"sources_sha256_16": "45cd108222b69c06",
-                  "fetch_bytes": 10745190, "write_bytes": 6759242650, "valu_busy": 0.89}
-RENDER_SOURCES = ("render.hip", "voice_device.h", "philox.h")
+RENDER_TRAFFIC = {"sources_sha256_16": "50789e57c17d3a78",
+                  "fetch_bytes": 10880320, "write_bytes": 6758691344, "valu_busy": 0.91}
+RENDER_SOURCES = ("render.hip", "voice_device.h", "philox.h", "series_tables.h")
 
 
 def render_traffic():
@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graph", type=int, default=1, help="capture the step in a HIP graph")
     ap.add_argument("--rps", type=int, default=0, help="runs per segment (0 = library default)")
+    ap.add_argument("--slices", type=int, default=0,
+                    help="plain workload: slices per voice with chunk carries (0 = library default)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="time the candidate launch plans on this batch first (untimed) and "
                          "render with the fastest")
@@ -76,12 +78,13 @@ def parse():
     ap.add_argument("--match-targets", type=int, default=4096)
     ap.add_argument("--match-train-steps", type=int, default=12208)
     ap.add_argument("--workload", default="render",
-                    choices=("render", "plain", "learned", "grad", "match"),
+                    choices=("render", "plain", "learned", "grad", "match", "nebula"),
                     help="render: the headline ragged render; plain: 128 voices x 4 s "
                          "(200 renders per timed step, in a HIP graph); learned: one proposal "
                          "training step (render + log-mel + MLP); grad: render, MR-STFT "
                          "loss and gradient, render adjoint; match: the sound-matching "
-                         "experiment alone")
+                         "experiment alone; nebula: MMD of 1000 x 1000 log-mel sets and "
+                         "nebula-search trials (256 sounds x 4 s each)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (the "
                          "reference point that scales HBM byte counters) and exit")
@@ -235,12 +238,27 @@ def bench_plain(args):
     with torch.cuda.stream(stream):
         u = S.synth_sample_params(wl.seed, 0, B)
         out = torch.empty(B, N, device="cuda")
-        S.synth_render(u, tab, n_samples=N, noise_seed=wl.key_noise(), out=out)
+        if args.slices:                 # an explicit plan: slices per voice, chunk carries first
+            rps = args.rps or 4
+            import ctypes
+            from paper_2104_12922_amd import _native
+            cfg, keep = _native.make_config(tab)
+            need = _native.lib().synth_render_plan_workspace(ctypes.byref(cfg), B, N)
+            ws = torch.empty(max(1, need), dtype=torch.uint8, device="cuda")
+
+            def render():
+                S.synth_render_plan(u, tab, rps, args.slices, n_samples=N,
+                                    noise_seed=wl.key_noise(), out=out, carries=True, workspace=ws)
+        else:                           # the library's default plan
+
+            def render():
+                S.synth_render(u, tab, n_samples=N, noise_seed=wl.key_noise(), out=out)
+        render()
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=stream):
             for _ in range(reps):
-                S.synth_render(u, tab, n_samples=N, noise_seed=wl.key_noise(), out=out)
+                render()
         torch.cuda.synchronize()
         for _ in range(args.warmup):
             g.replay()
@@ -261,7 +279,9 @@ def bench_plain(args):
            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": wl.name, "voices": B, "samples": B * N,
-                      "renders_per_step": reps},
+                      "renders_per_step": reps,
+                      "plan": {"rps": args.rps or 4, "slices": args.slices} if args.slices
+                      else "library default"},
            "roofline": {"bound": "hbm", "achieved": alg / (per * 1e-3) / 1e9,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": alg / (per * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
@@ -319,6 +339,61 @@ def bench_grad(args):
            "data": "synthetic", "config": {"workload": wl.name, "voices": B, "samples": B * N},
            "phase_ms": {"render": ms[0], "mrstft_loss_grad": ms[1], "render_adjoint": ms[2]}}
     print(json.dumps(out), flush=True)
+
+
+def bench_nebula(args):
+    """MMD between two sets of 1000 sounds' log-mel embeddings (8192 floats;
+    the paper's trial size) with its VALU roofline, and the rate of nebula
+    search trials (draw, render, embed 256 sounds of 4 s, MMD against 256
+    target sounds)."""
+    import torch
+    import workloads as W
+    from paper_2104_12922_amd import nebula as NB
+    n, dim = 1000, 8192
+    g = torch.Generator().manual_seed(0)
+    X = (torch.randn(n, dim, generator=g) - 4.0).cuda()
+    Y = (torch.randn(n, dim, generator=g) * 1.1 - 4.0).cuda()
+    out = torch.empty(4, dtype=torch.float64, device="cuda")
+    ws = NB._Workspace()
+    for _ in range(max(1, args.warmup)):
+        NB.mmd_l1(X, Y, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    ev = _events(args.steps)
+    for a, b in ev:
+        a.record()
+        NB.mmd_l1(X, Y, out=out, workspace=ws)
+        b.record()
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    pair_dims = 3.0 * n * n * dim            # S(X, Y), S(X, X), S(Y, Y)
+    tops = 2.0 * pair_dims / (ms * 1e-3) / 1e12
+    # search trials: 256 sounds x 4 s from the default nebula with random curves
+    base = W.default_nebula().table()
+    sets = NB.SoundSets(n_sounds=256, n_samples=176400, seed=30)
+    target = sets.embed(base, 10 ** 6).clone()
+    search = NB.NebulaSearch(base, target, sets=sets, target_per_trial=256, seed=1)
+    rng = np.random.default_rng(0)
+    trials = max(4, args.steps)
+    for k in range(2):
+        search.score(rng.uniform(-1, 1, 78), k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(trials):
+        search.score(rng.uniform(-1, 1, 78), 2 + k)
+    torch.cuda.synchronize()
+    trial_s = (time.perf_counter() - t0) / trials
+    res = {"metric": "MMD pair sums and nebula-search trials", "value": 1.0 / trial_s,
+           "unit": "trials/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": trial_s * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "mmd_1000x1000_logmel8192 + search trial 256 x 4 s",
+                      "mmd_sets": [n, n], "dim": dim, "trial_sounds": 256, "trial_target": 256},
+           "mmd_ms": ms, "mmd": float(out[0]),
+           "roofline": {"bound": "alu", "achieved": tops, "peak": VALU_PEAK_TOPS,
+                        "unit": "T VALU lane-slots/s", "frac": tops / VALU_PEAK_TOPS,
+                        "traffic": None, "kernel": "l1_pair_sum_kernel",
+                        "alg_slots_per_launch_set": 2.0 * pair_dims}}
+    print(json.dumps(res), flush=True)
 
 
 def sound_match(targets=4096, train_steps=12208, train_batch=4096, steps=50, lr=0.05,
@@ -509,6 +584,8 @@ def main():
         return bench_grad(args)
     if args.workload == "plain":
         return bench_plain(args)
+    if args.workload == "nebula":
+        return bench_nebula(args)
     if args.workload == "match":
         res = sound_match(targets=args.match_targets, train_steps=args.match_train_steps,
                           log=lambda *a: print(*a, file=sys.stderr, flush=True))

@@ -431,6 +431,43 @@ int synth_sum_f64(const double* x, int64_t n, double scale, double* out, void* s
 int synth_scale_rows(const float* g, const double* s, int64_t rows, int64_t cols, float* out,
                      void* stream);
 
+/* -------------------------------------------------------------------------
+ * Maximum mean discrepancy between two sets of sounds (Section 5, equation
+ * "mmd"), with the L1 distance between embeddings (float32 log-mel
+ * spectrograms, flattened) as the auditory distance d: the biased
+ * (V-statistic) estimate over all pairs, self-pairs included,
+ *   MMD(X, Y) = 2 S(X, Y) / (n m) - S(X, X) / n^2 - S(Y, Y) / m^2,
+ *   S(A, B)   = sum_{i, j} sum_k |A[i][k] - B[j][k]|.
+ * Each sum accumulates a pair's distance in float32 over runs of 256
+ * dimensions and everything else in float64, in a fixed order, so results
+ * are bitwise reproducible.
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of device workspace synth_l1_pair_sum needs for sets of n and m
+ * embeddings of dim floats (0 for an empty set or n, m above 2^17). */
+size_t synth_l1_pair_sum_workspace(int64_t n, int64_t m, int64_t dim);
+
+/* Bytes of device workspace synth_mmd_l1 needs: the largest of the three
+ * pair sums' (n, m), (n, n), (m, m). */
+size_t synth_mmd_l1_workspace(int64_t n, int64_t m, int64_t dim);
+
+/* out[0] = S(A, B) (dev float64) for A dev float32 [n][dim] (row stride lda
+ * >= dim), B dev float32 [m][dim] (ldb >= dim); 0 <= n, m <= 2^17, dim >= 0
+ * (an empty set or dim 0 gives 0).  workspace: dev, 8-byte aligned, at least
+ * synth_l1_pair_sum_workspace(n, m, dim) bytes, overwritten.  SYNTH_EINVAL
+ * on a bad size, stride or NULL pointer, SYNTH_ENOMEM on a short workspace. */
+int synth_l1_pair_sum(const float* A, int64_t lda, int64_t n, const float* B, int64_t ldb,
+                      int64_t m, int64_t dim, void* workspace, size_t workspace_bytes,
+                      double* out, void* stream);
+
+/* out[0..3] = {MMD(X, Y), S(X, Y), S(X, X), S(Y, Y)} (dev float64 [4]) for X
+ * dev float32 [n][dim], Y dev float32 [m][dim] (dense rows), 1 <= n, m <=
+ * 2^17.  MMD(X, X) is exactly 0: S(X, X) is computed as S(X, Y) would be for
+ * Y = X.  workspace >= synth_mmd_l1_workspace(n, m, dim) bytes.  Errors as
+ * synth_l1_pair_sum. */
+int synth_mmd_l1(const float* X, int64_t n, const float* Y, int64_t m, int64_t dim,
+                 void* workspace, size_t workspace_bytes, double* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -73,6 +73,8 @@ int prepare(const synth_config* cfg, RenderArgs* a, bool* clamp) {
 
 }  // namespace
 
+constexpr int64_t kMaxSet = (int64_t)1 << 17;   // sounds per set for the MMD sums
+
 extern "C" {
 
 int synth_num_params(void) { return SYNTH_NUM_PARAMS; }
@@ -686,6 +688,48 @@ int synth_scale_rows(const float* g, const double* s, int64_t rows, int64_t cols
   if (rows < 0 || cols < 0) return SYNTH_EINVAL;
   if (rows * cols > 0 && (!g || !s || !out)) return SYNTH_EINVAL;
   return to_status(synth::launch_scale_rows(g, s, rows, cols, out, (hipStream_t)stream));
+}
+
+size_t synth_l1_pair_sum_workspace(int64_t n, int64_t m, int64_t dim) {
+  if (n <= 0 || m <= 0 || dim < 0 || n > kMaxSet || m > kMaxSet) return 0;
+  return synth::l1_pair_sum_workspace(n, m, dim);
+}
+
+size_t synth_mmd_l1_workspace(int64_t n, int64_t m, int64_t dim) {
+  size_t need = synth_l1_pair_sum_workspace(n, m, dim);
+  const size_t xx = synth_l1_pair_sum_workspace(n, n, dim);
+  const size_t yy = synth_l1_pair_sum_workspace(m, m, dim);
+  need = xx > need ? xx : need;
+  return yy > need ? yy : need;
+}
+
+int synth_l1_pair_sum(const float* A, int64_t lda, int64_t n, const float* B, int64_t ldb,
+                      int64_t m, int64_t dim, void* workspace, size_t workspace_bytes,
+                      double* out, void* stream) {
+  if (n < 0 || m < 0 || dim < 0 || n > kMaxSet || m > kMaxSet || !out) return SYNTH_EINVAL;
+  if (lda < dim || ldb < dim) return SYNTH_EINVAL;
+  if (n > 0 && m > 0 && dim > 0 && (!A || !B)) return SYNTH_EINVAL;
+  const size_t need = synth_l1_pair_sum_workspace(n, m, dim);
+  if (need > 0 && (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 7))) return SYNTH_EINVAL;
+  if (workspace_bytes < need) return SYNTH_ENOMEM;
+  return to_status(synth::launch_l1_pair_sum(A, lda, n, B, ldb, m, dim, (double*)workspace, out,
+                                             (hipStream_t)stream));
+}
+
+int synth_mmd_l1(const float* X, int64_t n, const float* Y, int64_t m, int64_t dim,
+                 void* workspace, size_t workspace_bytes, double* out, void* stream) {
+  if (n < 1 || m < 1 || dim < 0 || n > kMaxSet || m > kMaxSet || !out) return SYNTH_EINVAL;
+  if (dim > 0 && (!X || !Y)) return SYNTH_EINVAL;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 7)) return SYNTH_EINVAL;
+  if (workspace_bytes < synth_mmd_l1_workspace(n, m, dim)) return SYNTH_ENOMEM;
+  const hipStream_t s = (hipStream_t)stream;
+  double* ws = (double*)workspace;
+  // the three sums reuse the workspace in stream order
+  hipError_t e = synth::launch_l1_pair_sum(X, dim, n, Y, dim, m, dim, ws, out + 1, s);
+  if (e == hipSuccess) e = synth::launch_l1_pair_sum(X, dim, n, X, dim, n, dim, ws, out + 2, s);
+  if (e == hipSuccess) e = synth::launch_l1_pair_sum(Y, dim, m, Y, dim, m, dim, ws, out + 3, s);
+  if (e == hipSuccess) e = synth::launch_mmd_combine(out, n, m, s);
+  return to_status(e);
 }
 
 int synth_colstats(const void* x, int x_bf16, int64_t rows, int64_t cols, int64_t ld, float* sum,

@@ -102,6 +102,10 @@ hipError_t launch_diff_reduce(int kind, int axis, const float* a, const float* b
 hipError_t launch_sum_f64(const double* x, int64_t n, double scale, double* out, hipStream_t s);
 hipError_t launch_scale_rows(const float* g, const double* sc, int64_t rows, int64_t cols,
                              float* out, hipStream_t s);
+size_t l1_pair_sum_workspace(int64_t n, int64_t m, int64_t dim);
+hipError_t launch_l1_pair_sum(const float* A, int64_t lda, int64_t n, const float* B, int64_t ldb,
+                              int64_t m, int64_t dim, double* partial, double* out, hipStream_t s);
+hipError_t launch_mmd_combine(double* out, int64_t n, int64_t m, hipStream_t s);
 hipError_t launch_colsum(const void* x, int x_bf16, int64_t rows, int64_t cols, int64_t ld,
                          float* sum, float* sumsq, hipStream_t s);
 hipError_t launch_feature_stats(const float* x, int64_t rows, int64_t cols, float min_var,
