@@ -78,13 +78,14 @@ def parse():
     ap.add_argument("--match-targets", type=int, default=4096)
     ap.add_argument("--match-train-steps", type=int, default=12208)
     ap.add_argument("--workload", default="render",
-                    choices=("render", "plain", "learned", "grad", "match", "nebula"),
+                    choices=("render", "plain", "learned", "grad", "match", "nebula", "vcf"),
                     help="render: the headline ragged render; plain: 128 voices x 4 s "
                          "(200 renders per timed step, in a HIP graph); learned: one proposal "
                          "training step (render + log-mel + MLP); grad: render, MR-STFT "
                          "loss and gradient, render adjoint; match: the sound-matching "
                          "experiment alone; nebula: MMD of 1000 x 1000 log-mel sets and "
-                         "nebula-search trials (256 sounds x 4 s each)")
+                         "nebula-search trials (256 sounds x 4 s each); vcf: the resonant "
+                         "low-pass filter and its adjoint on the ragged 16384-voice renders")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (the "
                          "reference point that scales HBM byte counters) and exit")
@@ -396,6 +397,60 @@ def bench_nebula(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_vcf(args):
+    """Resonant low-pass filter (forward and adjoint) on the rendered ragged
+    16384-voice batch (1, 2 and 4 s voices), cutoff driven by a control-rate
+    envelope per voice."""
+    import torch
+    import workloads as W
+    import paper_2104_12922_amd as S
+    from paper_2104_12922_amd import vcf as V
+    wl = W.ragged_batch(args.batch)
+    B = wl.batch
+    offs = torch.from_numpy(wl.offsets).cuda()
+    lmax = int(wl.lengths.max())
+    u = S.synth_sample_params(wl.seed, 0, B)
+    x = S.synth_render(u, wl.nebula.table(), offsets=offs, noise_seed=wl.key_noise())
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    J = (lmax + 99) // 100
+    env = torch.rand(B, J, device="cuda", generator=gen)
+    params = torch.stack([torch.rand(B, device="cuda", generator=gen) * 70 + 30,
+                          torch.rand(B, device="cuda", generator=gen) * 72 - 24,
+                          torch.rand(B, device="cuda", generator=gen) * 14.5 + 0.5], 1).contiguous()
+    g = torch.randn(x.numel(), device="cuda", generator=gen)
+    y = torch.empty_like(x)
+    for _ in range(max(1, args.warmup)):
+        _, st = V.lowpass(x, env, params, 100, offsets=offs, max_samples=lmax, keep_states=True, out=y)
+        V.lowpass_backward(x, g, env, params, st, 100, offsets=offs, max_samples=lmax)
+    torch.cuda.synchronize()
+    ef, eb = _events(args.steps), _events(args.steps)
+    for i in range(args.steps):
+        ef[i][0].record()
+        _, st = V.lowpass(x, env, params, 100, offsets=offs, max_samples=lmax, keep_states=True, out=y)
+        ef[i][1].record()
+        eb[i][0].record()
+        V.lowpass_backward(x, g, env, params, st, 100, offsets=offs, max_samples=lmax)
+        eb[i][1].record()
+    torch.cuda.synchronize()
+    fms = float(np.mean([a.elapsed_time(b) for a, b in ef]))
+    bms = float(np.mean([a.elapsed_time(b) for a, b in eb]))
+    n = x.numel()
+    fgbs, bgbs = 8.0 * n / (fms * 1e-3) / 1e9, 12.0 * n / (bms * 1e-3) / 1e9
+    res = {"metric": "filtered audio samples/sec (forward + adjoint)", "value": n / ((fms + bms) * 1e-3),
+           "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": fms + bms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": wl.name, "voices": B, "samples": n, "period": 100},
+           "forward_ms": fms, "adjoint_ms": bms,
+           "roofline": {"bound": "hbm", "achieved": fgbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": fgbs / HBM_PEAK_GBS, "traffic": None, "kernel": "vcf_forward_kernel",
+                        "alg_bytes_per_launch": 8.0 * n},
+           "adjoint_roofline": {"bound": "hbm", "achieved": bgbs, "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": bgbs / HBM_PEAK_GBS,
+                                "kernel": "vcf_backward_kernel", "alg_bytes_per_launch": 12.0 * n}}
+    print(json.dumps(res), flush=True)
+
+
 def sound_match(targets=4096, train_steps=12208, train_batch=4096, steps=50, lr=0.05,
                 rs_budget=1000, budget_gb=64.0, concurrency=4, log=None):
     """Sound matching (the second half of the headline metric): train the
@@ -586,6 +641,8 @@ def main():
         return bench_plain(args)
     if args.workload == "nebula":
         return bench_nebula(args)
+    if args.workload == "vcf":
+        return bench_vcf(args)
     if args.workload == "match":
         res = sound_match(targets=args.match_targets, train_steps=args.match_train_steps,
                           log=lambda *a: print(*a, file=sys.stderr, flush=True))

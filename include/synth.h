@@ -468,6 +468,55 @@ int synth_l1_pair_sum(const float* A, int64_t lda, int64_t n, const float* B, in
 int synth_mmd_l1(const float* X, int64_t n, const float* Y, int64_t m, int64_t dim,
                  void* workspace, size_t workspace_bytes, double* out, void* stream);
 
+/* -------------------------------------------------------------------------
+ * Resonant low-pass filter module (a subtractive filter, one of the modules
+ * Section 7 lists to add) and its adjoint.  Per voice b, control period j
+ * (samples [j period, (j + 1) period)) has the cutoff
+ *   f = clamp(440 * 2^((cutoff + depth * env[b][j] - 69) / 12), 10 Hz, 0.45 sample_rate)
+ * and R. Bristow-Johnson's cookbook second-order low-pass at f and Q
+ * (w = 2 pi f / sample_rate, alpha = sin w / (2 Q), b0 = b2 = (1 - cos w) /
+ * 2 / (1 + alpha), b1 = (1 - cos w) / (1 + alpha), a1 = -2 cos w / (1 +
+ * alpha), a2 = (1 - alpha) / (1 + alpha)), run as the direct-form-I
+ * recurrence y[n] = b0 x[n] + b1 x[n-1] + b2 x[n-2] - a1 y[n-1] - a2 y[n-2]
+ * from a zero state with the coefficients switched at period boundaries
+ * (float64 state and coefficients, float32 samples).  Unit gain at DC, gain Q
+ * at the cutoff.
+ *   x, y        dev float32, [batch][n_samples] (offsets NULL) or packed with
+ *               offsets (dev int64 [batch + 1], as synth_render); y may be x.
+ *   max_samples with offsets: the longest voice (sizes env and states);
+ *               ignored without.
+ *   env         dev float32 [batch][env_ld], env_ld >= ceil(longest / period):
+ *               the control signal (for instance an ADSR) per period.
+ *   params      dev float32 [batch][3]: cutoff (MIDI note number), depth
+ *               (semitones per unit of env), Q (> 0).
+ *   period      4 .. 256 samples (SYNTH_EUNSUPPORTED otherwise).
+ *   states      dev float64 [batch][state_ld][2] or NULL: the recurrence
+ *               state at every 64-period chunk start, which the backward
+ *               pass needs; state_ld >= synth_vcf_state_chunks(longest, period).
+ * SYNTH_EINVAL on a bad size, stride or NULL pointer.
+ * ------------------------------------------------------------------------- */
+
+/* Number of 64-period chunks of a voice of max_samples samples (0 for
+ * out-of-range arguments). */
+int64_t synth_vcf_state_chunks(int64_t max_samples, int period);
+
+int synth_vcf_lowpass(const float* x, const int64_t* offsets, int64_t batch, int64_t n_samples,
+                      int64_t max_samples, const float* env, int64_t env_ld, const float* params,
+                      int period, double sample_rate, float* y, double* states, int64_t state_ld,
+                      void* stream);
+
+/* Adjoint of synth_vcf_lowpass for the same inputs, given grad_y = dL/dy and
+ * the states its forward call wrote: grad_x = dL/dx (dev float32, layout of
+ * x; may be grad_y), grad_params = dL/d(cutoff, depth, Q) (dev float32
+ * [batch][3]), grad_env = dL/denv (dev float32 [batch][env_ld], rows written
+ * for the voice's periods; may be NULL).  The clamp passes the gradient
+ * where 10 Hz <= f <= 0.45 sample_rate and blocks it outside. */
+int synth_vcf_lowpass_backward(const float* x, const float* grad_y, const int64_t* offsets,
+                               int64_t batch, int64_t n_samples, int64_t max_samples,
+                               const float* env, int64_t env_ld, const float* params, int period,
+                               double sample_rate, const double* states, int64_t state_ld,
+                               float* grad_x, float* grad_params, float* grad_env, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

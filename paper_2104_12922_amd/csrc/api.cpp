@@ -732,6 +732,58 @@ int synth_mmd_l1(const float* X, int64_t n, const float* Y, int64_t m, int64_t d
   return to_status(e);
 }
 
+int64_t synth_vcf_state_chunks(int64_t max_samples, int period) {
+  if (max_samples <= 0 || period < 4 || period > 256) return 0;
+  return synth::vcf_chunks(max_samples, period);
+}
+
+namespace {
+int vcf_check(const float* x, const int64_t* offsets, int64_t batch, int64_t n_samples,
+              const float* env, int64_t env_ld, const float* params, int period,
+              double sample_rate, const float* out, const double* states, int64_t state_ld,
+              int64_t max_samples) {
+  if (batch < 0 || batch > 0x7FFFFFFF) return SYNTH_EINVAL;
+  if (period < 4 || period > 256) return SYNTH_EUNSUPPORTED;
+  if (!(sample_rate > 0.0) || !isfinite(sample_rate)) return SYNTH_EINVAL;
+  if (batch == 0) return SYNTH_OK;
+  if (!x || !env || !params || !out) return SYNTH_EINVAL;
+  if (!offsets && n_samples <= 0) return SYNTH_EINVAL;
+  if (max_samples <= 0 || max_samples > ((int64_t)1 << 40)) return SYNTH_EINVAL;
+  if (env_ld < (max_samples + period - 1) / period) return SYNTH_EINVAL;
+  if (states && state_ld < synth::vcf_chunks(max_samples, period)) return SYNTH_EINVAL;
+  return SYNTH_OK;
+}
+}  // namespace
+
+int synth_vcf_lowpass(const float* x, const int64_t* offsets, int64_t batch, int64_t n_samples,
+                      int64_t max_samples, const float* env, int64_t env_ld, const float* params,
+                      int period, double sample_rate, float* y, double* states, int64_t state_ld,
+                      void* stream) {
+  const int64_t lmax = offsets ? max_samples : n_samples;
+  const int st = vcf_check(x, offsets, batch, n_samples, env, env_ld, params, period, sample_rate,
+                           y, states, state_ld, batch > 0 ? lmax : 1);
+  if (st != SYNTH_OK || batch == 0) return st;
+  return to_status(synth::launch_vcf_forward(x, offsets, batch, offsets ? 0 : n_samples, env,
+                                             env_ld, params, period, sample_rate, y, states,
+                                             state_ld, (hipStream_t)stream));
+}
+
+int synth_vcf_lowpass_backward(const float* x, const float* grad_y, const int64_t* offsets,
+                               int64_t batch, int64_t n_samples, int64_t max_samples,
+                               const float* env, int64_t env_ld, const float* params, int period,
+                               double sample_rate, const double* states, int64_t state_ld,
+                               float* grad_x, float* grad_params, float* grad_env, void* stream) {
+  const int64_t lmax = offsets ? max_samples : n_samples;
+  const int st = vcf_check(x, offsets, batch, n_samples, env, env_ld, params, period, sample_rate,
+                           grad_x, states, state_ld, batch > 0 ? lmax : 1);
+  if (st != SYNTH_OK || batch == 0) return st;
+  if (!grad_y || !states || !grad_params) return SYNTH_EINVAL;
+  return to_status(synth::launch_vcf_backward(x, grad_y, offsets, batch, offsets ? 0 : n_samples,
+                                              env, env_ld, params, period, sample_rate, states,
+                                              state_ld, grad_x, grad_params, grad_env,
+                                              (hipStream_t)stream));
+}
+
 int synth_colstats(const void* x, int x_bf16, int64_t rows, int64_t cols, int64_t ld, float* sum,
                    float* sumsq, void* stream) {
   if (rows < 0 || cols < 0 || ld < cols || (cols > 0 && (!x || !sum))) return SYNTH_EINVAL;

@@ -1,0 +1,525 @@
+// Resonant low-pass filter module and its adjoint: the subtractive filter
+// Section 7 lists as a module to add.  Per voice, control period j (samples
+// [j q, (j + 1) q)) has the cutoff
+//   f_j = clamp(440 * 2^((cutoff + depth * env[j] - 69) / 12), 10 Hz, 0.45 sr)
+// and the second-order low-pass section of R. Bristow-Johnson's "Audio EQ
+// Cookbook" at f_j and the voice's Q (c = cos w, s = sin w, w = 2 pi f / sr,
+// alpha = s / (2 Q)):
+//   b0 = b2 = (1 - c) / 2 / (1 + alpha), b1 = (1 - c) / (1 + alpha),
+//   a1 = -2 c / (1 + alpha), a2 = (1 - alpha) / (1 + alpha),
+// run as the direct-form-I recurrence
+//   y[n] = b0 x[n] + b1 x[n-1] + b2 x[n-2] - a1 y[n-1] - a2 y[n-2]
+// from a zero state, coefficients switched at period boundaries.
+//
+// The recurrence is linear in the state v[n] = (y[n-1], y[n-2]): a period of
+// length L maps v to A^L v + z, A = [[-a1, -a2], [1, 0]], z its zero-state
+// response.  One wavefront takes one voice, 64 periods (a chunk) at a time:
+// the chunk's samples are staged in LDS (period p at p (q + 1), padded so
+// that the 64 lanes' reads hit distinct banks), lane p runs period p from a
+// zero state (z) and raises A to the period's length by squaring, an
+// inclusive scan of the affine maps (M, z) over the lanes gives every
+// period's entry state from the chunk's, and each lane runs its period
+// again from that state, writing y over x in LDS; the chunk is then stored
+// with coalesced writes.  State and coefficients are float64; samples are
+// float32 in HBM, read and written once each (8 bytes per sample: the
+// kernel is bound by HBM).
+//
+// The adjoint: with lambda[n] = dL/dy[n] (through all later samples),
+//   lambda[n] = g[n] - a1(n+1) lambda[n+1] - a2(n+2) lambda[n+2],
+//   dL/dx[m]  = b0(m) lambda[m] + b1(m+1) lambda[m+1] + b2(m+2) lambda[m+2],
+//   dL/db_k(j) = sum_{n in j} lambda[n] x[n-k], dL/da_k(j) = -sum_{n in j} lambda[n] y[n-k],
+// (coef(m): the coefficient of the period holding sample m), then through
+// the cookbook formulas to w and Q, and through f to the cutoff, the depth
+// and env[j].  It walks the chunks last to first; per chunk it recomputes
+// the forward entry states from the chunk-start state the forward pass saved
+// (same scan as the forward), runs the lambda recurrence backward per lane
+// from a zero state, scans the lanes' affine maps in reverse, runs lambda
+// again from the true entry states (lambda over g in LDS), then a forward
+// sweep per period rebuilds y, sums the coefficient gradients and forms
+// dL/dx over x in LDS.
+#include "voice_device.h"
+
+namespace synth {
+namespace {
+
+using voice::exp2_f64;
+using voice::kLn2;
+using voice::kTwoPi;
+using voice::sincos_cycles_f64;
+
+constexpr double kVcfFMin = 10.0;
+constexpr double kVcfFMaxFrac = 0.45;
+
+struct VcfArgs {
+  const float* x;
+  const float* g;            // backward: dL/dy
+  const int64_t* offsets;    // [B + 1] or null
+  int64_t n_uniform;
+  int64_t batch;
+  const float* env;          // [B][env_ld]
+  int64_t env_ld;
+  const float* params;       // [B][3]: cutoff (MIDI note), depth (semitones), Q
+  int q;                     // samples per control period
+  uint32_t q_magic;          // x / q == umulhi(x, q_magic) for x < 2^16
+  double sr;
+  float* y;                  // forward output / backward dL/dx
+  double* states;            // [B][state_ld][2]: (y[c0 - 1], y[c0 - 2]) at chunk starts
+  int64_t state_ld;
+  float* g_params;           // backward: [B][3]
+  float* g_env;              // backward: [B][env_ld] or null
+};
+
+struct Coef {
+  double b0, b1, a1, a2;     // b2 = b0
+};
+
+struct CoefGrad {
+  Coef k;
+  double dw[4];              // d(b0, b1, a1, a2) / dw
+  double dq[4];              // d(b0, b1, a1, a2) / dQ
+  double dmdw;               // dw / dm (m: cutoff + depth env), 0 when clamped
+};
+
+__device__ __forceinline__ double vcf_cutoff(double m, double sr, bool& live) {
+  const double f = 440.0 * exp2_f64((m - 69.0) / 12.0);
+  live = f >= kVcfFMin && f <= kVcfFMaxFrac * sr;
+  return fmin(fmax(f, kVcfFMin), kVcfFMaxFrac * sr);
+}
+
+__device__ __forceinline__ Coef vcf_coef(const VcfArgs& a, double cutoff, double depth, double Q,
+                                         double env) {
+  bool live;
+  const double f = vcf_cutoff(fma(depth, env, cutoff), a.sr, live);
+  double s, c;
+  sincos_cycles_f64(f / a.sr, s, c);
+  const double alpha = s / (2.0 * Q);
+  const double ia0 = 1.0 / (1.0 + alpha);
+  Coef k;
+  k.b0 = (1.0 - c) * 0.5 * ia0;
+  k.b1 = (1.0 - c) * ia0;
+  k.a1 = -2.0 * c * ia0;
+  k.a2 = (1.0 - alpha) * ia0;
+  return k;
+}
+
+__device__ __forceinline__ CoefGrad vcf_coef_grad(const VcfArgs& a, double cutoff, double depth,
+                                                  double Q, double env) {
+  bool live;
+  const double f = vcf_cutoff(fma(depth, env, cutoff), a.sr, live);
+  double s, c;
+  sincos_cycles_f64(f / a.sr, s, c);
+  const double alpha = s / (2.0 * Q);
+  const double ia0 = 1.0 / (1.0 + alpha);
+  CoefGrad r;
+  r.k.b0 = (1.0 - c) * 0.5 * ia0;
+  r.k.b1 = (1.0 - c) * ia0;
+  r.k.a1 = -2.0 * c * ia0;
+  r.k.a2 = (1.0 - alpha) * ia0;
+  const double dal_w = c / (2.0 * Q), dal_q = -alpha / Q;
+  // coefficient = N / (1 + alpha): d = (dN - coefficient * dalpha) / (1 + alpha)
+  r.dw[0] = (0.5 * s - r.k.b0 * dal_w) * ia0;
+  r.dw[1] = (s - r.k.b1 * dal_w) * ia0;
+  r.dw[2] = (2.0 * s - r.k.a1 * dal_w) * ia0;
+  r.dw[3] = -(1.0 + r.k.a2) * dal_w * ia0;
+  r.dq[0] = -r.k.b0 * dal_q * ia0;
+  r.dq[1] = -r.k.b1 * dal_q * ia0;
+  r.dq[2] = -r.k.a1 * dal_q * ia0;
+  r.dq[3] = -(1.0 + r.k.a2) * dal_q * ia0;
+  // w = 2 pi f / sr, f = 440 2^((m - 69) / 12): dw/dm = w ln 2 / 12
+  r.dmdw = live ? kTwoPi * f / a.sr * (kLn2 / 12.0) : 0.0;
+  return r;
+}
+
+struct Mat2 {
+  double m00, m01, m10, m11;
+};
+
+__device__ __forceinline__ Mat2 mat_mul(const Mat2& p, const Mat2& r) {   // p r
+  Mat2 o;
+  o.m00 = fma(p.m00, r.m00, p.m01 * r.m10);
+  o.m01 = fma(p.m00, r.m01, p.m01 * r.m11);
+  o.m10 = fma(p.m10, r.m00, p.m11 * r.m10);
+  o.m11 = fma(p.m10, r.m01, p.m11 * r.m11);
+  return o;
+}
+
+__device__ __forceinline__ Mat2 mat_pow(Mat2 p, int e) {
+  Mat2 r = {1.0, 0.0, 0.0, 1.0};
+  while (e > 0) {
+    if (e & 1) r = mat_mul(r, p);
+    e >>= 1;
+    if (e) p = mat_mul(p, p);
+  }
+  return r;
+}
+
+__device__ __forceinline__ void voice_range(const VcfArgs& a, int64_t b, int64_t& start,
+                                            int64_t& len) {
+  if (a.offsets) {
+    packed_range(a.offsets, a.batch, b, start, len);
+  } else {
+    start = b * a.n_uniform;
+    len = a.n_uniform;
+  }
+}
+
+__device__ __forceinline__ int lds_pos(int p, const VcfArgs& a) {   // p < 64 q
+  const int seg = (int)__umulhi((uint32_t)p, a.q_magic);
+  return seg * (a.q + 1) + (p - seg * a.q);
+}
+
+// Stage samples [c0, c0 + cnt) of src (voice base pointer) into the padded
+// LDS layout; positions past cnt read as 0.
+__device__ __forceinline__ void stage_in(float* lds, const float* __restrict__ src, int64_t c0,
+                                         int cnt, const VcfArgs& a) {
+  const int lane = threadIdx.x, n = 64 * a.q;
+  for (int p = lane; p < n; p += 64) lds[lds_pos(p, a)] = p < cnt ? src[c0 + p] : 0.0f;
+}
+
+__device__ __forceinline__ void stage_out(const float* lds, float* __restrict__ dst, int64_t c0,
+                                          int cnt, const VcfArgs& a) {
+  const int lane = threadIdx.x;
+  for (int p = lane; p < cnt; p += 64) dst[c0 + p] = lds[lds_pos(p, a)];
+}
+
+// Inclusive scan over lanes of the affine maps v -> M v + z, earlier lanes
+// applied first (dir = +1: lane - d is earlier; dir = -1: lane + d is).
+template <int DIR>
+__device__ __forceinline__ void scan_affine(Mat2& M, double& z0, double& z1) {
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    Mat2 P;
+    double p0, p1;
+    if (DIR > 0) {
+      P.m00 = __shfl_up(M.m00, d); P.m01 = __shfl_up(M.m01, d);
+      P.m10 = __shfl_up(M.m10, d); P.m11 = __shfl_up(M.m11, d);
+      p0 = __shfl_up(z0, d); p1 = __shfl_up(z1, d);
+    } else {
+      P.m00 = __shfl_down(M.m00, d); P.m01 = __shfl_down(M.m01, d);
+      P.m10 = __shfl_down(M.m10, d); P.m11 = __shfl_down(M.m11, d);
+      p0 = __shfl_down(z0, d); p1 = __shfl_down(z1, d);
+    }
+    const bool has = DIR > 0 ? lane >= d : lane + d < 64;
+    if (has) {
+      const double n0 = fma(M.m00, p0, fma(M.m01, p1, z0));
+      const double n1 = fma(M.m10, p0, fma(M.m11, p1, z1));
+      M = mat_mul(M, P);
+      z0 = n0;
+      z1 = n1;
+    }
+  }
+}
+
+// Forward recompute of one chunk: each active lane's entry state (y[s-1],
+// y[s-2]) from the chunk-start state (v0, v1); returns the chunk's exit
+// state via (e0, e1) (uniform).  xa: staged x; xh1, xh2: x[c0-1], x[c0-2].
+__device__ __forceinline__ void forward_entry_states(const float* xa, const VcfArgs& a,
+                                                     const Coef& k, int len, double xh1, double xh2,
+                                                     double v0, double v1, double& in0,
+                                                     double& in1, double& e0, double& e1) {
+  const int lane = threadIdx.x;
+  const float* xs = xa + lane * (a.q + 1);
+  double x1 = lane ? (double)xa[(lane - 1) * (a.q + 1) + a.q - 1] : xh1;
+  double x2 = lane ? (double)xa[(lane - 1) * (a.q + 1) + a.q - 2] : xh2;
+  double y1 = 0.0, y2 = 0.0;
+  for (int i = 0; i < len; ++i) {
+    const double x0 = (double)xs[i];
+    const double ff = fma(k.b0, x0 + x2, k.b1 * x1);
+    const double y0 = fma(-k.a1, y1, fma(-k.a2, y2, ff));
+    x2 = x1; x1 = x0; y2 = y1; y1 = y0;
+  }
+  Mat2 M = {1.0, 0.0, 0.0, 1.0};
+  double z0 = 0.0, z1 = 0.0;
+  if (len > 0) {
+    const Mat2 A = {-k.a1, -k.a2, 1.0, 0.0};
+    M = mat_pow(A, len);
+    z0 = y1;
+    z1 = y2;
+  }
+  scan_affine<1>(M, z0, z1);
+  const double o0 = fma(M.m00, v0, fma(M.m01, v1, z0));
+  const double o1 = fma(M.m10, v0, fma(M.m11, v1, z1));
+  in0 = __shfl_up(o0, 1);
+  in1 = __shfl_up(o1, 1);
+  if (lane == 0) {
+    in0 = v0;
+    in1 = v1;
+  }
+  e0 = __shfl(o0, 63);
+  e1 = __shfl(o1, 63);
+}
+
+__global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
+  extern __shared__ float lds[];              // 64 (q + 1)
+  const int64_t b = blockIdx.x;
+  const int lane = threadIdx.x;
+  int64_t start, L;
+  voice_range(a, b, start, L);
+  if (L <= 0) return;
+  const float* xv = a.x + start;
+  float* yv = a.y + start;
+  const double cutoff = a.params[b * 3], depth = a.params[b * 3 + 1], Q = a.params[b * 3 + 2];
+  const int64_t J = (L + a.q - 1) / a.q;
+  const int64_t chunks = (J + 63) / 64;
+  double v0 = 0.0, v1 = 0.0, xh1 = 0.0, xh2 = 0.0;
+  for (int64_t c = 0; c < chunks; ++c) {
+    const int64_t c0 = c * 64 * a.q;
+    const int cnt = (int)min((int64_t)64 * a.q, L - c0);
+    if (a.states && lane == 0) {
+      a.states[(b * a.state_ld + c) * 2] = v0;
+      a.states[(b * a.state_ld + c) * 2 + 1] = v1;
+    }
+    stage_in(lds, xv, c0, cnt, a);
+    __syncthreads();
+    const int64_t j = c * 64 + lane;
+    const int len = j < J ? (int)min((int64_t)a.q, L - j * a.q) : 0;
+    Coef k = {0.0, 0.0, 0.0, 0.0};
+    if (len > 0) k = vcf_coef(a, cutoff, depth, Q, (double)a.env[b * a.env_ld + j]);
+    double in0, in1, e0, e1;
+    forward_entry_states(lds, a, k, len, xh1, xh2, v0, v1, in0, in1, e0, e1);
+    // x history for this lane's period and for the next chunk, read before
+    // any lane overwrites its period with y
+    float* xs = lds + lane * (a.q + 1);
+    double x1 = lane ? (double)lds[(lane - 1) * (a.q + 1) + a.q - 1] : xh1;
+    double x2 = lane ? (double)lds[(lane - 1) * (a.q + 1) + a.q - 2] : xh2;
+    const double nxh1 = (double)lds[63 * (a.q + 1) + a.q - 1];
+    const double nxh2 = (double)lds[63 * (a.q + 1) + a.q - 2];
+    __syncthreads();
+    double y1 = in0, y2 = in1;
+    for (int i = 0; i < len; ++i) {
+      const double x0 = (double)xs[i];
+      const double ff = fma(k.b0, x0 + x2, k.b1 * x1);
+      const double y0 = fma(-k.a1, y1, fma(-k.a2, y2, ff));
+      xs[i] = (float)y0;
+      x2 = x1; x1 = x0; y2 = y1; y1 = y0;
+    }
+    __syncthreads();
+    stage_out(lds, yv, c0, cnt, a);
+    __syncthreads();
+    v0 = e0;
+    v1 = e1;
+    xh1 = nxh1;
+    xh2 = nxh2;
+  }
+}
+
+__global__ void __launch_bounds__(64) vcf_backward_kernel(VcfArgs a) {
+  extern __shared__ float lds[];              // x, then dL/dx: 64 (q + 1); g, then lambda
+  float* xa = lds;
+  float* ga = lds + 64 * (a.q + 1);
+  const int64_t b = blockIdx.x;
+  const int lane = threadIdx.x;
+  int64_t start, L;
+  voice_range(a, b, start, L);
+  if (L <= 0) {
+    if (lane < 3) a.g_params[b * 3 + lane] = 0.0f;
+    return;
+  }
+  const float* xv = a.x + start;
+  const float* gv = a.g + start;
+  float* dxv = a.y + start;
+  const double cutoff = a.params[b * 3], depth = a.params[b * 3 + 1], Q = a.params[b * 3 + 2];
+  const int64_t J = (L + a.q - 1) / a.q;
+  const int64_t chunks = (J + 63) / 64;
+  double u0 = 0.0, u1 = 0.0;                  // (lambda[c_end], lambda[c_end + 1])
+  double gc = 0.0, gd = 0.0, gq = 0.0;        // this lane's share of dL/d(cutoff, depth, Q)
+  for (int64_t c = chunks - 1; c >= 0; --c) {
+    const int64_t c0 = c * 64 * a.q;
+    const int cnt = (int)min((int64_t)64 * a.q, L - c0);
+    stage_in(xa, xv, c0, cnt, a);
+    stage_in(ga, gv, c0, cnt, a);
+    const double v0 = a.states[(b * a.state_ld + c) * 2];
+    const double v1 = a.states[(b * a.state_ld + c) * 2 + 1];
+    const double xh1 = c0 >= 1 ? (double)xv[c0 - 1] : 0.0;
+    const double xh2 = c0 >= 2 ? (double)xv[c0 - 2] : 0.0;
+    __syncthreads();
+    const int64_t j = c * 64 + lane;
+    const int len = j < J ? (int)min((int64_t)a.q, L - j * a.q) : 0;
+    const double envj = len > 0 ? (double)a.env[b * a.env_ld + j] : 0.0;
+    CoefGrad kg = {};
+    if (len > 0) kg = vcf_coef_grad(a, cutoff, depth, Q, envj);
+    const Coef k = kg.k;
+    // the next period's coefficients (lane 63: the first period of the next
+    // chunk; zero past the voice, where lambda is 0)
+    Coef kn;
+    kn.b0 = __shfl_down(k.b0, 1);
+    kn.b1 = __shfl_down(k.b1, 1);
+    kn.a1 = __shfl_down(k.a1, 1);
+    kn.a2 = __shfl_down(k.a2, 1);
+    if (lane == 63) {
+      kn = {0.0, 0.0, 0.0, 0.0};
+      if (j + 1 < J) kn = vcf_coef(a, cutoff, depth, Q, (double)a.env[b * a.env_ld + j + 1]);
+    }
+    // forward entry states (y[s-1], y[s-2]) of every period
+    double fin0, fin1, fe0, fe1;
+    forward_entry_states(xa, a, k, len, xh1, xh2, v0, v1, fin0, fin1, fe0, fe1);
+    // lambda over the period from a zero state (samples last to first; the
+    // last two use the next period's a1 / a2), and the period's affine map
+    // (lambda[e], lambda[e+1]) -> (lambda[s], lambda[s+1])
+    float* gs = ga + lane * (a.q + 1);
+    double l1 = 0.0, l2 = 0.0;
+    for (int i = len - 1; i >= 0; --i) {
+      const double a1 = i == len - 1 ? kn.a1 : k.a1;
+      const double a2 = i >= len - 2 ? kn.a2 : k.a2;
+      const double l0 = fma(-a1, l1, fma(-a2, l2, (double)gs[i]));
+      l2 = l1;
+      l1 = l0;
+    }
+    Mat2 M = {1.0, 0.0, 0.0, 1.0};
+    double z0 = 0.0, z1 = 0.0;
+    if (len > 0) {
+      M = {-kn.a1, -kn.a2, 1.0, 0.0};
+      if (len >= 2) {
+        const Mat2 C2 = {-k.a1, -kn.a2, 1.0, 0.0};
+        M = mat_mul(C2, M);
+        if (len >= 3) {
+          const Mat2 Bm = {-k.a1, -k.a2, 1.0, 0.0};
+          M = mat_mul(mat_pow(Bm, len - 2), M);
+        }
+      }
+      z0 = l1;
+      z1 = l2;
+    }
+    scan_affine<-1>(M, z0, z1);
+    const double o0 = fma(M.m00, u0, fma(M.m01, u1, z0));
+    const double o1 = fma(M.m10, u0, fma(M.m11, u1, z1));
+    double in0 = __shfl_down(o0, 1), in1 = __shfl_down(o1, 1);   // (lambda[e], lambda[e+1])
+    if (lane == 63) {
+      in0 = u0;
+      in1 = u1;
+    }
+    const double nu0 = __shfl(o0, 0), nu1 = __shfl(o1, 0);
+    // lambda from the true entry state, written over g
+    l1 = in0;
+    l2 = in1;
+    for (int i = len - 1; i >= 0; --i) {
+      const double a1 = i == len - 1 ? kn.a1 : k.a1;
+      const double a2 = i >= len - 2 ? kn.a2 : k.a2;
+      const double l0 = fma(-a1, l1, fma(-a2, l2, (double)gs[i]));
+      gs[i] = (float)l0;
+      l2 = l1;
+      l1 = l0;
+    }
+    // x history of this period, read before any lane writes dL/dx over x
+    double x1 = lane ? (double)xa[(lane - 1) * (a.q + 1) + a.q - 1] : xh1;
+    double x2 = lane ? (double)xa[(lane - 1) * (a.q + 1) + a.q - 2] : xh2;
+    __syncthreads();
+    // forward sweep: y rebuilt from the entry state, the coefficient
+    // gradients, and dL/dx[n - 2] once lambda[n] is known
+    float* xs = xa + lane * (a.q + 1);
+    double y1 = fin0, y2 = fin1;
+    double lm1 = 0.0, lm2 = 0.0;               // lambda[n-1], lambda[n-2]
+    double Gb0 = 0.0, Gb1 = 0.0, Gb2 = 0.0, Ga1 = 0.0, Ga2 = 0.0;
+    for (int i = 0; i < len; ++i) {
+      const double x0 = (double)xs[i];
+      const double l0 = (double)gs[i];
+      Gb0 = fma(l0, x0, Gb0);
+      Gb1 = fma(l0, x1, Gb1);
+      Gb2 = fma(l0, x2, Gb2);
+      Ga1 = fma(-l0, y1, Ga1);
+      Ga2 = fma(-l0, y2, Ga2);
+      const double ff = fma(k.b0, x0 + x2, k.b1 * x1);
+      const double y0 = fma(-k.a1, y1, fma(-k.a2, y2, ff));
+      if (i >= 2) xs[i - 2] = (float)fma(k.b0, lm2 + l0, k.b1 * lm1);
+      x2 = x1; x1 = x0; y2 = y1; y1 = y0;
+      lm2 = lm1; lm1 = l0;
+    }
+    if (len >= 2) xs[len - 2] = (float)fma(k.b0, lm2, fma(k.b1, lm1, kn.b0 * in0));
+    if (len >= 1) xs[len - 1] = (float)fma(k.b0, lm1, fma(kn.b1, in0, kn.b0 * in1));
+    if (len > 0) {
+      const double Gw = Gb0 * kg.dw[0] + Gb1 * kg.dw[1] + Gb2 * kg.dw[0] + Ga1 * kg.dw[2] +
+                        Ga2 * kg.dw[3];
+      const double Gq = Gb0 * kg.dq[0] + Gb1 * kg.dq[1] + Gb2 * kg.dq[0] + Ga1 * kg.dq[2] +
+                        Ga2 * kg.dq[3];
+      const double gm = Gw * kg.dmdw;
+      gc += gm;
+      gd = fma(gm, envj, gd);
+      gq += Gq;
+      if (a.g_env) a.g_env[b * a.env_ld + j] = (float)(gm * depth);
+    }
+    __syncthreads();
+    stage_out(xa, dxv, c0, cnt, a);
+    __syncthreads();
+    u0 = nu0;
+    u1 = nu1;
+  }
+  // per-voice sums over lanes in a fixed order
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    gc += __shfl_down(gc, off);
+    gd += __shfl_down(gd, off);
+    gq += __shfl_down(gq, off);
+  }
+  if (lane == 0) {
+    a.g_params[b * 3] = (float)gc;
+    a.g_params[b * 3 + 1] = (float)gd;
+    a.g_params[b * 3 + 2] = (float)gq;
+  }
+}
+
+VcfArgs make_args(const float* x, const float* g, const int64_t* offsets, int64_t batch,
+                  int64_t n_samples, const float* env, int64_t env_ld, const float* params,
+                  int q, double sr, float* y, double* states, int64_t state_ld, float* g_params,
+                  float* g_env) {
+  VcfArgs a;
+  a.x = x;
+  a.g = g;
+  a.offsets = offsets;
+  a.n_uniform = offsets ? 0 : n_samples;
+  a.batch = batch;
+  a.env = env;
+  a.env_ld = env_ld;
+  a.params = params;
+  a.q = q;
+  a.q_magic = (uint32_t)((0x100000000ULL + (uint64_t)q - 1) / (uint64_t)q);
+  a.sr = sr;
+  a.y = y;
+  a.states = states;
+  a.state_ld = state_ld;
+  a.g_params = g_params;
+  a.g_env = g_env;
+  return a;
+}
+
+}  // namespace
+
+int64_t vcf_chunks(int64_t max_samples, int q) {
+  const int64_t J = (max_samples + q - 1) / q;
+  return (J + 63) / 64;
+}
+
+hipError_t launch_vcf_forward(const float* x, const int64_t* offsets, int64_t batch,
+                              int64_t n_samples, const float* env, int64_t env_ld,
+                              const float* params, int q, double sr, float* y, double* states,
+                              int64_t state_ld, hipStream_t s) {
+  const VcfArgs a = make_args(x, nullptr, offsets, batch, n_samples, env, env_ld, params, q, sr, y,
+                              states, state_ld, nullptr, nullptr);
+  const size_t lds = (size_t)64 * (q + 1) * sizeof(float);
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute((const void*)vcf_forward_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(vcf_forward_kernel, dim3((unsigned)batch), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_vcf_backward(const float* x, const float* g, const int64_t* offsets,
+                               int64_t batch, int64_t n_samples, const float* env, int64_t env_ld,
+                               const float* params, int q, double sr, const double* states,
+                               int64_t state_ld, float* g_x, float* g_params, float* g_env,
+                               hipStream_t s) {
+  const VcfArgs a = make_args(x, g, offsets, batch, n_samples, env, env_ld, params, q, sr, g_x,
+                              const_cast<double*>(states), state_ld, g_params, g_env);
+  const size_t lds = (size_t)2 * 64 * (q + 1) * sizeof(float);
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute((const void*)vcf_backward_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(vcf_backward_kernel, dim3((unsigned)batch), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace synth
