@@ -59,10 +59,13 @@ def u24(word) -> np.ndarray:
     return (np.asarray(word, dtype=np.uint64) >> np.uint64(8)).astype(np.float64) * 2.0 ** -24
 
 
-def sample_params(seed: int, voice_ids, num_params: int = 78) -> np.ndarray:
+def sample_params(seed: int, voice_ids, num_params: int = 78, tag: int = 0) -> np.ndarray:
     """Normalised parameters u[g, p] in [0, 1) for the given global voice ids.
 
     Section 3.3: parameters are drawn uniformly in the normalised range.
+    Counter (g mod 2^32, g div 2^32, p div 4, tag): tag names the synth
+    architecture (0: the default Voice), so that architectures draw
+    independent streams for the same seed and index.
     Returns float64 [B, num_params] whose values are exactly representable in float32.
     """
     g = np.asarray(voice_ids, dtype=np.uint64).reshape(-1)
@@ -71,7 +74,7 @@ def sample_params(seed: int, voice_ids, num_params: int = 78) -> np.ndarray:
     nblk = (num_params + 3) // 4
     blk = np.arange(nblk, dtype=np.uint64)
     ctr = np.stack(np.broadcast_arrays(glo[:, None], ghi[:, None], blk[None, :],
-                                       np.zeros((1, 1), np.uint64)), axis=-1)
+                                       np.full((1, 1), tag, np.uint64)), axis=-1)
     key = np.stack([klo, khi]).astype(np.uint64)
     words = philox4x32(ctr, key)  # [B, nblk, 4]
     return u24(words.reshape(len(g), nblk * 4)[:, :num_params])

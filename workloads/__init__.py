@@ -111,6 +111,32 @@ def curved_test_nebula() -> Nebula:
     return n
 
 
+FM_NUM_PARAMS = 44
+
+
+def fm_default_nebula(duration_min: float = 0.0) -> Nebula:
+    """Default nebula of the 4-operator FM voice (parameter order in
+    oracle/fm.py): midi_f0 24..84, note duration 0..4 s, operator ratio
+    0.5..8 (curve 2: low ratios favoured), detune +-50 cents (symmetric),
+    level 0..1, ADSR ranges as the Voice's, modulation index 0..2 cycles
+    (curve 2), mix weights 0..1."""
+    lo = np.zeros(FM_NUM_PARAMS)
+    hi = np.ones(FM_NUM_PARAMS)
+    curve = np.ones(FM_NUM_PARAMS)
+    sym = np.zeros(FM_NUM_PARAMS, dtype=bool)
+    lo[0], hi[0] = 24.0, 84.0
+    lo[1], hi[1] = duration_min, 4.0
+    for i in range(4):
+        b = 2 + 8 * i
+        lo[b:b + 8] = (0.5, -50.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.1)
+        hi[b:b + 8] = (8.0, 50.0, 1.0, 2.0, 2.0, 1.0, 2.0, 6.0)
+        curve[b] = 2.0
+        sym[b + 1] = True
+    hi[34:40] = 2.0
+    curve[34:40] = 2.0
+    return Nebula(lo, hi, curve, sym, name="fm_default" if duration_min == 0 else "fm_default_ragged")
+
+
 # ----------------------------------------------------------------------------
 # Workload shapes
 # ----------------------------------------------------------------------------
