@@ -169,17 +169,70 @@ __device__ __forceinline__ int lds_pos(int p, const VcfArgs& a) {   // p < 64 q
 }
 
 // Stage samples [c0, c0 + cnt) of src (voice base pointer) into the padded
-// LDS layout; positions past cnt read as 0.
+// LDS layout; positions past cnt read as 0.  Lane l takes 16-byte groups l,
+// l + 64, ... (coalesced), eight groups' loads in flight before their LDS
+// writes; vec: the voice's samples start 16-byte aligned (else 4-byte loads).
+constexpr int kStageBatch = 8;
+
+template <bool V4>
+__device__ __forceinline__ void stage_in_t(float* lds, const float* __restrict__ base, int cnt,
+                                           const VcfArgs& a) {
+  const int lane = threadIdx.x, groups = 16 * a.q;          // 64 q samples / 4
+  for (int g0 = 0; g0 < groups; g0 += 64 * kStageBatch) {
+    float4 v[kStageBatch];
+#pragma unroll
+    for (int k = 0; k < kStageBatch; ++k) {
+      const int p = 4 * (g0 + lane + 64 * k);
+      if (V4) {
+        v[k] = *reinterpret_cast<const float4*>(base + min(p, cnt - 4));
+      } else {
+        v[k].x = base[min(p, cnt - 1)];
+        v[k].y = base[min(p + 1, cnt - 1)];
+        v[k].z = base[min(p + 2, cnt - 1)];
+        v[k].w = base[min(p + 3, cnt - 1)];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kStageBatch; ++k) {
+      const int g = g0 + lane + 64 * k;
+      if (g < groups) {
+        const int p = 4 * g;
+        lds[lds_pos(p, a)] = p < cnt ? v[k].x : 0.0f;
+        lds[lds_pos(p + 1, a)] = p + 1 < cnt ? v[k].y : 0.0f;
+        lds[lds_pos(p + 2, a)] = p + 2 < cnt ? v[k].z : 0.0f;
+        lds[lds_pos(p + 3, a)] = p + 3 < cnt ? v[k].w : 0.0f;
+      }
+    }
+  }
+}
+
+// Loads are unconditional (addresses clamped into [0, cnt)) so that a batch
+// is in flight at once; values past cnt are replaced by 0.  16-byte loads
+// when the voice's samples start 16-byte aligned and cnt is a multiple of 4.
 __device__ __forceinline__ void stage_in(float* lds, const float* __restrict__ src, int64_t c0,
-                                         int cnt, const VcfArgs& a) {
-  const int lane = threadIdx.x, n = 64 * a.q;
-  for (int p = lane; p < n; p += 64) lds[lds_pos(p, a)] = p < cnt ? src[c0 + p] : 0.0f;
+                                         int cnt, const VcfArgs& a, bool vec) {
+  if (vec && (cnt & 3) == 0)
+    stage_in_t<true>(lds, src + c0, cnt, a);
+  else
+    stage_in_t<false>(lds, src + c0, cnt, a);
 }
 
 __device__ __forceinline__ void stage_out(const float* lds, float* __restrict__ dst, int64_t c0,
-                                          int cnt, const VcfArgs& a) {
+                                          int cnt, const VcfArgs& a, bool vec) {
   const int lane = threadIdx.x;
-  for (int p = lane; p < cnt; p += 64) dst[c0 + p] = lds[lds_pos(p, a)];
+  float* base = dst + c0;
+  for (int p = 4 * lane; p < cnt; p += 256) {
+    const float4 v = make_float4(lds[lds_pos(p, a)], lds[lds_pos(p + 1, a)],
+                                 lds[lds_pos(p + 2, a)], lds[lds_pos(p + 3, a)]);
+    if (vec && p + 4 <= cnt) {
+      *reinterpret_cast<float4*>(base + p) = v;
+    } else {
+      base[p] = v.x;
+      if (p + 1 < cnt) base[p + 1] = v.y;
+      if (p + 2 < cnt) base[p + 2] = v.z;
+      if (p + 3 < cnt) base[p + 3] = v.w;
+    }
+  }
 }
 
 // Inclusive scan over lanes of the affine maps v -> M v + z, earlier lanes
@@ -211,6 +264,74 @@ __device__ __forceinline__ void scan_affine(Mat2& M, double& z0, double& z1) {
   }
 }
 
+// Walks a lane's period in LDS: f(i, x[i]) for i = 0 .. len - 1 in order
+// (sweep) or len - 1 .. 0 (sweep_rev), the next block of eight LDS reads in
+// flight while the current block runs.  f may write x[i] (in place).
+constexpr int kSweep = 8;
+
+template <class F>
+__device__ __forceinline__ void sweep(const float* xs, int len, F&& f) {
+  const int full = len & ~(kSweep - 1);
+  float cur[kSweep], nxt[kSweep];
+#pragma unroll
+  for (int e = 0; e < kSweep; ++e) cur[e] = full > 0 ? xs[e] : 0.0f;
+  for (int i = 0; i < full; i += kSweep) {
+    const bool more = i + kSweep < full;
+#pragma unroll
+    for (int e = 0; e < kSweep; ++e) nxt[e] = more ? xs[i + kSweep + e] : 0.0f;
+#pragma unroll
+    for (int e = 0; e < kSweep; ++e) f(i + e, cur[e]);
+#pragma unroll
+    for (int e = 0; e < kSweep; ++e) cur[e] = nxt[e];
+  }
+  for (int i = full; i < len; ++i) f(i, xs[i]);
+}
+
+template <class F>
+__device__ __forceinline__ void sweep_rev(const float* xs, int len, F&& f) {
+  const int full = len & ~(kSweep - 1);
+  for (int i = len - 1; i >= full; --i) f(i, xs[i]);
+  float cur[kSweep], nxt[kSweep];
+#pragma unroll
+  for (int e = 0; e < kSweep; ++e) cur[e] = full > 0 ? xs[full - kSweep + e] : 0.0f;
+  for (int i = full - kSweep; i >= 0; i -= kSweep) {
+    const bool more = i > 0;
+#pragma unroll
+    for (int e = 0; e < kSweep; ++e) nxt[e] = more ? xs[i - kSweep + e] : 0.0f;
+#pragma unroll
+    for (int e = kSweep - 1; e >= 0; --e) f(i + e, cur[e]);
+#pragma unroll
+    for (int e = 0; e < kSweep; ++e) cur[e] = nxt[e];
+  }
+}
+
+template <class F>
+__device__ __forceinline__ void sweep2(const float* xs, const float* gs, int len, F&& f) {
+  const int full = len & ~(kSweep - 1);
+  float cx[kSweep], cg[kSweep], nx[kSweep], ng[kSweep];
+#pragma unroll
+  for (int e = 0; e < kSweep; ++e) {
+    cx[e] = full > 0 ? xs[e] : 0.0f;
+    cg[e] = full > 0 ? gs[e] : 0.0f;
+  }
+  for (int i = 0; i < full; i += kSweep) {
+    const bool more = i + kSweep < full;
+#pragma unroll
+    for (int e = 0; e < kSweep; ++e) {
+      nx[e] = more ? xs[i + kSweep + e] : 0.0f;
+      ng[e] = more ? gs[i + kSweep + e] : 0.0f;
+    }
+#pragma unroll
+    for (int e = 0; e < kSweep; ++e) f(i + e, cx[e], cg[e]);
+#pragma unroll
+    for (int e = 0; e < kSweep; ++e) {
+      cx[e] = nx[e];
+      cg[e] = ng[e];
+    }
+  }
+  for (int i = full; i < len; ++i) f(i, xs[i], gs[i]);
+}
+
 // Forward recompute of one chunk: each active lane's entry state (y[s-1],
 // y[s-2]) from the chunk-start state (v0, v1); returns the chunk's exit
 // state via (e0, e1) (uniform).  xa: staged x; xh1, xh2: x[c0-1], x[c0-2].
@@ -223,12 +344,12 @@ __device__ __forceinline__ void forward_entry_states(const float* xa, const VcfA
   double x1 = lane ? (double)xa[(lane - 1) * (a.q + 1) + a.q - 1] : xh1;
   double x2 = lane ? (double)xa[(lane - 1) * (a.q + 1) + a.q - 2] : xh2;
   double y1 = 0.0, y2 = 0.0;
-  for (int i = 0; i < len; ++i) {
-    const double x0 = (double)xs[i];
+  sweep(xs, len, [&](int, float xf) {
+    const double x0 = (double)xf;
     const double ff = fma(k.b0, x0 + x2, k.b1 * x1);
     const double y0 = fma(-k.a1, y1, fma(-k.a2, y2, ff));
     x2 = x1; x1 = x0; y2 = y1; y1 = y0;
-  }
+  });
   Mat2 M = {1.0, 0.0, 0.0, 1.0};
   double z0 = 0.0, z1 = 0.0;
   if (len > 0) {
@@ -259,6 +380,7 @@ __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
   if (L <= 0) return;
   const float* xv = a.x + start;
   float* yv = a.y + start;
+  const bool vec = ((reinterpret_cast<uintptr_t>(xv) | reinterpret_cast<uintptr_t>(yv)) & 15) == 0;
   const double cutoff = a.params[b * 3], depth = a.params[b * 3 + 1], Q = a.params[b * 3 + 2];
   const int64_t J = (L + a.q - 1) / a.q;
   const int64_t chunks = (J + 63) / 64;
@@ -270,7 +392,7 @@ __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
       a.states[(b * a.state_ld + c) * 2] = v0;
       a.states[(b * a.state_ld + c) * 2 + 1] = v1;
     }
-    stage_in(lds, xv, c0, cnt, a);
+    stage_in(lds, xv, c0, cnt, a, vec);
     __syncthreads();
     const int64_t j = c * 64 + lane;
     const int len = j < J ? (int)min((int64_t)a.q, L - j * a.q) : 0;
@@ -287,15 +409,15 @@ __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
     const double nxh2 = (double)lds[63 * (a.q + 1) + a.q - 2];
     __syncthreads();
     double y1 = in0, y2 = in1;
-    for (int i = 0; i < len; ++i) {
-      const double x0 = (double)xs[i];
+    sweep(xs, len, [&](int i, float xf) {
+      const double x0 = (double)xf;
       const double ff = fma(k.b0, x0 + x2, k.b1 * x1);
       const double y0 = fma(-k.a1, y1, fma(-k.a2, y2, ff));
       xs[i] = (float)y0;
       x2 = x1; x1 = x0; y2 = y1; y1 = y0;
-    }
+    });
     __syncthreads();
-    stage_out(lds, yv, c0, cnt, a);
+    stage_out(lds, yv, c0, cnt, a, vec);
     __syncthreads();
     v0 = e0;
     v1 = e1;
@@ -319,6 +441,8 @@ __global__ void __launch_bounds__(64) vcf_backward_kernel(VcfArgs a) {
   const float* xv = a.x + start;
   const float* gv = a.g + start;
   float* dxv = a.y + start;
+  const bool vec = ((reinterpret_cast<uintptr_t>(xv) | reinterpret_cast<uintptr_t>(gv) |
+                     reinterpret_cast<uintptr_t>(dxv)) & 15) == 0;
   const double cutoff = a.params[b * 3], depth = a.params[b * 3 + 1], Q = a.params[b * 3 + 2];
   const int64_t J = (L + a.q - 1) / a.q;
   const int64_t chunks = (J + 63) / 64;
@@ -327,8 +451,8 @@ __global__ void __launch_bounds__(64) vcf_backward_kernel(VcfArgs a) {
   for (int64_t c = chunks - 1; c >= 0; --c) {
     const int64_t c0 = c * 64 * a.q;
     const int cnt = (int)min((int64_t)64 * a.q, L - c0);
-    stage_in(xa, xv, c0, cnt, a);
-    stage_in(ga, gv, c0, cnt, a);
+    stage_in(xa, xv, c0, cnt, a, vec);
+    stage_in(ga, gv, c0, cnt, a, vec);
     const double v0 = a.states[(b * a.state_ld + c) * 2];
     const double v1 = a.states[(b * a.state_ld + c) * 2 + 1];
     const double xh1 = c0 >= 1 ? (double)xv[c0 - 1] : 0.0;
@@ -359,13 +483,13 @@ __global__ void __launch_bounds__(64) vcf_backward_kernel(VcfArgs a) {
     // (lambda[e], lambda[e+1]) -> (lambda[s], lambda[s+1])
     float* gs = ga + lane * (a.q + 1);
     double l1 = 0.0, l2 = 0.0;
-    for (int i = len - 1; i >= 0; --i) {
+    sweep_rev(gs, len, [&](int i, float gf) {
       const double a1 = i == len - 1 ? kn.a1 : k.a1;
       const double a2 = i >= len - 2 ? kn.a2 : k.a2;
-      const double l0 = fma(-a1, l1, fma(-a2, l2, (double)gs[i]));
+      const double l0 = fma(-a1, l1, fma(-a2, l2, (double)gf));
       l2 = l1;
       l1 = l0;
-    }
+    });
     Mat2 M = {1.0, 0.0, 0.0, 1.0};
     double z0 = 0.0, z1 = 0.0;
     if (len > 0) {
@@ -393,14 +517,14 @@ __global__ void __launch_bounds__(64) vcf_backward_kernel(VcfArgs a) {
     // lambda from the true entry state, written over g
     l1 = in0;
     l2 = in1;
-    for (int i = len - 1; i >= 0; --i) {
+    sweep_rev(gs, len, [&](int i, float gf) {
       const double a1 = i == len - 1 ? kn.a1 : k.a1;
       const double a2 = i >= len - 2 ? kn.a2 : k.a2;
-      const double l0 = fma(-a1, l1, fma(-a2, l2, (double)gs[i]));
+      const double l0 = fma(-a1, l1, fma(-a2, l2, (double)gf));
       gs[i] = (float)l0;
       l2 = l1;
       l1 = l0;
-    }
+    });
     // x history of this period, read before any lane writes dL/dx over x
     double x1 = lane ? (double)xa[(lane - 1) * (a.q + 1) + a.q - 1] : xh1;
     double x2 = lane ? (double)xa[(lane - 1) * (a.q + 1) + a.q - 2] : xh2;
@@ -411,9 +535,9 @@ __global__ void __launch_bounds__(64) vcf_backward_kernel(VcfArgs a) {
     double y1 = fin0, y2 = fin1;
     double lm1 = 0.0, lm2 = 0.0;               // lambda[n-1], lambda[n-2]
     double Gb0 = 0.0, Gb1 = 0.0, Gb2 = 0.0, Ga1 = 0.0, Ga2 = 0.0;
-    for (int i = 0; i < len; ++i) {
-      const double x0 = (double)xs[i];
-      const double l0 = (double)gs[i];
+    sweep2(xs, gs, len, [&](int i, float xf, float lf) {
+      const double x0 = (double)xf;
+      const double l0 = (double)lf;
       Gb0 = fma(l0, x0, Gb0);
       Gb1 = fma(l0, x1, Gb1);
       Gb2 = fma(l0, x2, Gb2);
@@ -424,7 +548,7 @@ __global__ void __launch_bounds__(64) vcf_backward_kernel(VcfArgs a) {
       if (i >= 2) xs[i - 2] = (float)fma(k.b0, lm2 + l0, k.b1 * lm1);
       x2 = x1; x1 = x0; y2 = y1; y1 = y0;
       lm2 = lm1; lm1 = l0;
-    }
+    });
     if (len >= 2) xs[len - 2] = (float)fma(k.b0, lm2, fma(k.b1, lm1, kn.b0 * in0));
     if (len >= 1) xs[len - 1] = (float)fma(k.b0, lm1, fma(kn.b1, in0, kn.b0 * in1));
     if (len > 0) {
@@ -439,7 +563,7 @@ __global__ void __launch_bounds__(64) vcf_backward_kernel(VcfArgs a) {
       if (a.g_env) a.g_env[b * a.env_ld + j] = (float)(gm * depth);
     }
     __syncthreads();
-    stage_out(xa, dxv, c0, cnt, a);
+    stage_out(xa, dxv, c0, cnt, a, vec);
     __syncthreads();
     u0 = nu0;
     u1 = nu1;
