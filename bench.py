@@ -78,14 +78,15 @@ def parse():
     ap.add_argument("--match-targets", type=int, default=4096)
     ap.add_argument("--match-train-steps", type=int, default=12208)
     ap.add_argument("--workload", default="render",
-                    choices=("render", "plain", "learned", "grad", "match", "nebula", "vcf"),
+                    choices=("render", "plain", "learned", "grad", "match", "nebula", "vcf", "fm"),
                     help="render: the headline ragged render; plain: 128 voices x 4 s "
                          "(200 renders per timed step, in a HIP graph); learned: one proposal "
                          "training step (render + log-mel + MLP); grad: render, MR-STFT "
                          "loss and gradient, render adjoint; match: the sound-matching "
                          "experiment alone; nebula: MMD of 1000 x 1000 log-mel sets and "
                          "nebula-search trials (256 sounds x 4 s each); vcf: the resonant "
-                         "low-pass filter and its adjoint on the ragged 16384-voice renders")
+                         "low-pass filter and its adjoint on the ragged 16384-voice renders; "
+                         "fm: the 4-operator FM voice on the ragged 16384-voice batch")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (the "
                          "reference point that scales HBM byte counters) and exit")
@@ -451,6 +452,44 @@ def bench_vcf(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_fm(args):
+    """The 4-operator FM voice: parameter draw and render of the ragged
+    16384-voice batch (1, 2 and 4 s voices, note durations 0.1-4 s)."""
+    import torch
+    import workloads as W
+    from paper_2104_12922_amd import fm as FMV
+    wl = W.ragged_batch(args.batch)
+    B = wl.batch
+    offs = torch.from_numpy(wl.offsets).cuda()
+    tab = W.fm_default_nebula(duration_min=0.1).table()
+    out = torch.empty(wl.total_samples, dtype=torch.float32, device="cuda")
+    for _ in range(max(1, args.warmup)):
+        u = FMV.fm_sample_params(wl.seed, batch=B)
+        FMV.fm_render(u, tab, offsets=offs, out=out)
+    torch.cuda.synchronize()
+    ev = _events(args.steps)
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        u = FMV.fm_sample_params(wl.seed, batch=B)
+        FMV.fm_render(u, tab, offsets=offs, out=out)
+        b.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    n = wl.total_samples
+    gbs = 4.0 * n / (ms * 1e-3) / 1e9
+    res = {"metric": "rendered FM audio samples/sec", "value": n / (ms * 1e-3), "unit": "samples/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "wall_ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": wl.name + "_fm4", "voices": B, "samples": n},
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "fm_render_kernel",
+                        "alg_bytes_per_launch": 4.0 * n}}
+    print(json.dumps(res), flush=True)
+
+
 def sound_match(targets=4096, train_steps=12208, train_batch=4096, steps=50, lr=0.05,
                 rs_budget=1000, budget_gb=64.0, concurrency=4, log=None):
     """Sound matching (the second half of the headline metric): train the
@@ -643,6 +682,8 @@ def main():
         return bench_nebula(args)
     if args.workload == "vcf":
         return bench_vcf(args)
+    if args.workload == "fm":
+        return bench_fm(args)
     if args.workload == "match":
         res = sound_match(targets=args.match_targets, train_steps=args.match_train_steps,
                           log=lambda *a: print(*a, file=sys.stderr, flush=True))

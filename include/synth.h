@@ -517,6 +517,41 @@ int synth_vcf_lowpass_backward(const float* x, const float* grad_y, const int64_
                                double sample_rate, const double* states, int64_t state_ld,
                                float* grad_x, float* grad_params, float* grad_env, void* stream);
 
+/* -------------------------------------------------------------------------
+ * Four-operator FM voice (the FM architecture Sections 3.2 and 7 announce).
+ * 44 normalised parameters per voice: 0 midi_f0, 1 note duration (s);
+ * 2 + 8i for operator i = 0..3: ratio, detune (cents), level, attack (s),
+ * decay (s), sustain, release (s), envelope curve exponent; 34..39 the
+ * modulation indices M[0][1], M[0][2], M[0][3], M[1][2], M[1][3], M[2][3]
+ * (cycles; operator j modulates the phase of operator i < j); 40..43 the
+ * mix weights.  Operator i: f_i = 440 2^((midi_f0 - 69) / 12) ratio_i
+ * 2^(detune_i / 1200) (at most sr / 2), o_i(n) = level_i env_i(n)
+ * sin(2 pi (n f_i / sr + sum_{j > i} M[i][j] o_j(n))), env_i the Voice's
+ * ADSR at the control rate upsampled linearly; y = sum_i w_i o_i /
+ * max(1, sum_i w_i).  No operator feedback.  Indices above about 64 cycles
+ * lose the hardware sine's accuracy.
+ * ------------------------------------------------------------------------- */
+typedef struct synth_fm_config {
+    double sample_rate;      /* as synth_config: an integer multiple q of */
+    double control_rate;     /* control_rate, 4 <= q <= 1024 */
+    const double* nebula;    /* host [44][4] doubles: (min, max, curve, symmetric) */
+} synth_fm_config;
+
+/* Normalised FM parameters [batch][44] float32 (dev): the draw of
+ * synth_sample_params with counter word 3 = 1 (the FM voice's stream), so
+ * the FM and default voices of one (seed, g) are independent. */
+int synth_fm_sample_params(uint64_t seed, uint64_t first_g, int64_t batch,
+                           const uint64_t* voice_ids, float* params, void* stream);
+
+/* Render batch FM voices from params (dev float32 [batch][44]) into audio
+ * (dev float32): uniform [batch][n_samples] when offsets is NULL, else
+ * packed with offsets (dev int64 [batch + 1], as synth_render).  SYNTH_EINVAL
+ * for a bad nebula (min > max, curve <= 0, symmetric not 0/1, envelope
+ * curve minimum <= 0), size or pointer; SYNTH_EUNSUPPORTED for rates whose
+ * ratio is not an integer in 4 .. 1024. */
+int synth_fm_render(const synth_fm_config* cfg, const float* params, int64_t batch,
+                    const int64_t* offsets, int64_t n_samples, float* audio, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

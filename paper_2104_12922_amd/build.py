@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsynth.so")
 
 SOURCES = ["api.cpp", "params.hip", "render.hip", "spectral.hip", "adjoint.hip", "gemm.hip",
-           "mlp.hip", "dft.hip", "reduce.hip", "mmd.hip", "vcf.hip"]
+           "mlp.hip", "dft.hip", "reduce.hip", "mmd.hip", "vcf.hip", "fm.hip"]
 
 # Packed-FP32 instructions are disabled for all device code (plain float code
 # is scheduled onto the non-packed VALU).  Machine LICM is disabled: it hoists

@@ -74,6 +74,8 @@ int prepare(const synth_config* cfg, RenderArgs* a, bool* clamp) {
 }  // namespace
 
 constexpr int64_t kMaxSet = (int64_t)1 << 17;   // sounds per set for the MMD sums
+constexpr int kFmNumParams = 44;
+constexpr uint32_t kFmArchTag = 1;             // the FM voice's parameter-draw stream
 
 extern "C" {
 
@@ -204,6 +206,46 @@ int synth_sample_params(uint64_t seed, uint64_t first_g, int64_t batch, const ui
   if (batch > ((int64_t)1 << 31) * 256 / 20) return SYNTH_EINVAL;
   return to_status(synth::launch_sample_params(seed, first_g, batch, voice_ids, params,
                                                (hipStream_t)stream));
+}
+
+int synth_fm_sample_params(uint64_t seed, uint64_t first_g, int64_t batch,
+                           const uint64_t* voice_ids, float* params, void* stream) {
+  if (batch < 0) return SYNTH_EINVAL;
+  if (batch == 0) return SYNTH_OK;
+  if (!params) return SYNTH_EINVAL;
+  if (batch > ((int64_t)1 << 31) * 256 / 11) return SYNTH_EINVAL;
+  return to_status(synth::launch_sample_params(seed, first_g, batch, voice_ids, params,
+                                               (hipStream_t)stream, kFmNumParams, kFmArchTag));
+}
+
+int synth_fm_render(const synth_fm_config* cfg, const float* params, int64_t batch,
+                    const int64_t* offsets, int64_t n_samples, float* audio, void* stream) {
+  if (!cfg || !cfg->nebula || batch < 0) return SYNTH_EINVAL;
+  const double sr = cfg->sample_rate, rc = cfg->control_rate;
+  if (!(sr > 0.0) || !(rc > 0.0) || !isfinite(sr) || !isfinite(rc)) return SYNTH_EINVAL;
+  const double qf = sr / rc, qr = nearbyint(qf);
+  if (fabs(qr - qf) > 1e-9 * qf || qr < 4.0 || qr > 1024.0) return SYNTH_EUNSUPPORTED;
+  NebulaArgs nb;
+  memset(&nb, 0, sizeof(nb));
+  const double* t = cfg->nebula;
+  for (int p = 0; p < kFmNumParams; ++p) {
+    const double lo = t[4 * p + 0], hi = t[4 * p + 1], c = t[4 * p + 2], sy = t[4 * p + 3];
+    if (!isfinite(lo) || !isfinite(hi) || !(lo <= hi) || !(c > 0.0) || !isfinite(c))
+      return SYNTH_EINVAL;
+    if (sy != 0.0 && sy != 1.0) return SYNTH_EINVAL;
+    nb.lo[p] = lo;
+    nb.hi[p] = hi;
+    nb.inv_curve[p] = 1.0 / c;
+    if (sy == 1.0) nb.sym[p >> 5] |= 1u << (p & 31);
+    if (c == 1.0) nb.linear[p >> 5] |= 1u << (p & 31);
+  }
+  for (int k = 0; k < 4; ++k)              // envelope curve exponents must be positive
+    if (!(nb.lo[2 + 8 * k + 7] > 0.0)) return SYNTH_EINVAL;
+  if (batch == 0) return SYNTH_OK;
+  if (!params || !audio || batch > 0x7FFFFFFF) return SYNTH_EINVAL;
+  if (!offsets && (n_samples <= 0 || n_samples > ((int64_t)1 << 40))) return SYNTH_EINVAL;
+  return to_status(synth::launch_fm_render(params, offsets, batch, offsets ? 0 : n_samples, audio,
+                                           sr, rc, (int)qr, nb, nullptr, (hipStream_t)stream));
 }
 
 namespace {

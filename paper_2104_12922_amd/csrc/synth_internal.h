@@ -106,6 +106,9 @@ size_t l1_pair_sum_workspace(int64_t n, int64_t m, int64_t dim);
 hipError_t launch_l1_pair_sum(const float* A, int64_t lda, int64_t n, const float* B, int64_t ldb,
                               int64_t m, int64_t dim, double* partial, double* out, hipStream_t s);
 hipError_t launch_mmd_combine(double* out, int64_t n, int64_t m, hipStream_t s);
+hipError_t launch_fm_render(const float* params, const int64_t* offsets, int64_t batch,
+                            int64_t n_samples, float* audio, double sr, double rc, int q,
+                            const NebulaArgs& neb, const int32_t* order, hipStream_t s);
 int64_t vcf_chunks(int64_t max_samples, int q);
 hipError_t launch_vcf_forward(const float* x, const int64_t* offsets, int64_t batch,
                               int64_t n_samples, const float* env, int64_t env_ld,
@@ -145,7 +148,8 @@ hipError_t launch_best_update(const double* loss, int64_t rows, int64_t cols, in
 hipError_t launch_is_test(uint64_t first_g, int64_t batch, const uint64_t* voice_ids,
                           uint8_t* is_test, hipStream_t s);
 hipError_t launch_sample_params(uint64_t seed, uint64_t first_g, int64_t batch,
-                                const uint64_t* voice_ids, float* params, hipStream_t s);
+                                const uint64_t* voice_ids, float* params, hipStream_t s,
+                                int n_params = kNumParams, uint32_t tag = 0);
 
 // runs_per_segment in {1, 2, 4}; clamp: some pitch can exceed sr / 2.
 hipError_t launch_render(const RenderArgs& a, int runs_per_segment, bool clamp, int grid,

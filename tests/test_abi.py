@@ -170,8 +170,10 @@ def header_arities():
 def test_ctypes_signatures_match_header_arity():
     """Every binding declares exactly the header's parameters: an argument past
     the declared list would be passed as a C int (a truncated stream pointer)."""
-    from paper_2104_12922_amd import learned
+    from paper_2104_12922_amd import fm, learned, nebula, vcf
     L = learned.lib()
+    for m in (fm, nebula, vcf):           # each module declares its entry points on first use
+        assert m.lib() is L
     ar = header_arities()
     assert len(ar) == len(header_functions())
     for name, n in ar.items():
