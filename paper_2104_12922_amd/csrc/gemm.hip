@@ -163,8 +163,45 @@ __device__ __forceinline__ void epi_store(const GemmArgs& g, int64_t row, int64_
   else reinterpret_cast<float*>(g.C)[o] = x;
 }
 
+// The standard epilogue for the 16 accumulators of one lane (column col,
+// rows row0 + 8 (v / 4) + (v % 4)): the GELU' pre-activations it reads are
+// loaded for all 16 first, so the loads are in flight together instead of
+// one round trip per element.
+__device__ __forceinline__ void epi_store16(const GemmArgs& g, int64_t row0, int64_t col,
+                                            f32x16 acc) {
+  if (col >= g.N) return;
+  float aux[16];
+  if (g.epilogue == kEpiGeluGrad) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = row0 + 8 * (v >> 2) + (v & 3);
+      aux[v] = row < g.M ? g.aux[row * g.ldc + col] : 0.0f;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int64_t row = row0 + 8 * (v >> 2) + (v & 3);
+    if (row >= g.M) continue;
+    float x = acc[v] * g.alpha;
+    if (g.epilogue == kEpiGeluGrad) {
+      const int64_t o = row * g.ldc + col;
+      if (g.bias) x += g.bias[col];
+      if (g.pre) g.pre[o] = x;
+      x *= gelu_erf_grad(aux[v]);
+      if (g.beta != 0.0f)
+        x += g.beta * (g.c_bf16 ? bf2f(reinterpret_cast<const uint16_t*>(g.C)[o])
+                                : reinterpret_cast<const float*>(g.C)[o]);
+      if (g.c_bf16) reinterpret_cast<uint16_t*>(g.C)[o] = f2bf(x);
+      else reinterpret_cast<float*>(g.C)[o] = x;
+    } else {
+      epi_store(g, row, col, x);
+    }
+  }
+}
+
 template <int AOP, int BOP>
-__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+    gemm_bf16_kernel(GemmArgs g) {
   __shared__ __align__(16) uint16_t As[2][BM][PADK];
   __shared__ __align__(16) uint16_t Bs[2][BN][PADK];
   const int t = threadIdx.x;
@@ -183,13 +220,9 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
   const int64_t kbeg = part * kper;
   const int64_t kend = kbeg + kper < g.K ? kbeg + kper : g.K;
 
-  f32x16 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+  // four named accumulators (an array of them is not kept in registers)
+  f32x16 s00 = {}, s01 = {}, s10 = {}, s11 = {};
+#define SYNTH_SACC(i, j) ((i) == 0 ? ((j) == 0 ? s00 : s01) : ((j) == 0 ? s10 : s11))
 
   // LDS double buffer; the next k-step's tiles are loaded into registers
   // before this step's MFMAs and written to the other buffer after them.
@@ -226,7 +259,7 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+          SYNTH_SACC(i, j) = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], SYNTH_SACC(i, j), 0, 0, 0);
     }
     __builtin_amdgcn_sched_barrier(0);
     if (more) {
@@ -247,7 +280,7 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int64_t row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-          if (col < g.N && row < g.M) g.partial[(part * g.M + row) * g.N + col] = acc[i][j][v];
+          if (col < g.N && row < g.M) g.partial[(part * g.M + row) * g.N + col] = SYNTH_SACC(i, j)[v];
         }
       }
     return;
@@ -258,10 +291,14 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
     for (int j = 0; j < 2; ++j) {
       const int64_t col = n0 + wn * 64 + j * 32 + (lane & 31);
       const bool col_ok = col < g.N;
+      if (g.epilogue <= kEpiGeluGrad) {
+        epi_store16(g, m0 + wm * 64 + i * 32 + 4 * (lane >> 5), col, SYNTH_SACC(i, j));
+        continue;
+      }
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int64_t row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        float x = acc[i][j][v] * g.alpha;
+        float x = SYNTH_SACC(i, j)[v] * g.alpha;
         if (g.epilogue == kEpiPowerPairs) {
           x += (g.bias && col_ok) ? g.bias[col] : 0.0f;
           // (Re, Im) sit in adjacent columns = adjacent lanes; every lane shuffles
@@ -272,19 +309,16 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
             if (g.c_bf16) reinterpret_cast<uint16_t*>(g.C)[o] = f2bf(p);
             else reinterpret_cast<float*>(g.C)[o] = p;
           }
-          continue;
-        }
-        if (!col_ok || row >= g.M) continue;
-        if (g.epilogue == kEpiLogMelT) {
+        } else if (col_ok && row < g.M) {    // kEpiLogMelT
           if (g.bias) x += g.bias[col];
           const int64_t o = (row / 64) * 8192 + col * 64 + (row % 64);
           reinterpret_cast<float*>(g.C)[o] = logf(x + 1e-6f);
-          continue;
         }
-        epi_store(g, row, col, x);
       }
     }
 }
+
+#undef SYNTH_SACC
 
 // Large tiles for the MLP's big products (output dims multiples of 256):
 // 256 x 256 x 32 per 512-thread workgroup, eight wavefronts in 2 x 4, each
@@ -306,11 +340,18 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))
   const int wm = wave >> 2, wn = wave & 3;
   const int64_t tiles_n = g.N / BN2;
   const int64_t tiles = (g.M / BM2) * tiles_n;
-  const int64_t tile = blockIdx.x % tiles;
+  // Workgroups are dispatched to the 8 XCDs round-robin by index; renumber
+  // them so that each XCD takes a contiguous run of (part, tile) with the
+  // tiles row-major: the workgroups sharing an L2 then share A's rows and
+  // the same B, instead of every XCD streaming all of both.
+  const int64_t nblk = gridDim.x;
+  const int64_t vid = (nblk % 8 == 0) ? (int64_t)(blockIdx.x % 8) * (nblk / 8) + blockIdx.x / 8
+                                      : (int64_t)blockIdx.x;
+  const int64_t tile = vid % tiles;
   const int64_t tm = tile / tiles_n, tn = tile % tiles_n;
   const int64_t m0 = tm * BM2, n0 = tn * BN2;
   const int split = g.split > 1 ? g.split : 1;
-  const int64_t part = blockIdx.x / tiles;
+  const int64_t part = vid / tiles;
   const int64_t kper = ((g.K + split - 1) / split + BK - 1) / BK * BK;
   const int64_t kbeg = part * kper;
   const int64_t kend = kbeg + kper < g.K ? kbeg + kper : g.K;
@@ -371,12 +412,13 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int64_t col = n0 + wn * 64 + j * 32 + (lane & 31);
+      const int64_t row0 = m0 + wm * 128 + i * 32 + 4 * (lane >> 5);
+      if (split > 1) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t row = m0 + wm * 128 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const float x = SYNTH_ACC(i, j)[v];
-        if (split > 1) g.partial[(part * g.M + row) * g.N + col] = x;
-        else epi_store(g, row, col, x * g.alpha);
+        for (int v = 0; v < 16; ++v)
+          g.partial[(part * g.M + row0 + 8 * (v >> 2) + (v & 3)) * g.N + col] = SYNTH_ACC(i, j)[v];
+      } else {
+        epi_store16(g, row0, col, SYNTH_ACC(i, j));
       }
     }
 #undef SYNTH_ACC
