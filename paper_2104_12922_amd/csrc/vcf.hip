@@ -11,16 +11,19 @@
 //   y[n] = b0 x[n] + b1 x[n-1] + b2 x[n-2] - a1 y[n-1] - a2 y[n-2]
 // from a zero state, coefficients switched at period boundaries.
 //
-// The recurrence is linear in the state v[n] = (y[n-1], y[n-2]): a period of
-// length L maps v to A^L v + z, A = [[-a1, -a2], [1, 0]], z its zero-state
-// response.  One wavefront takes one voice, 64 periods (a chunk) at a time:
-// the chunk's samples are staged in LDS (period p at p (q + 1), padded so
-// that the 64 lanes' reads hit distinct banks), lane p runs period p from a
-// zero state (z) and raises A to the period's length by squaring, an
-// inclusive scan of the affine maps (M, z) over the lanes gives every
-// period's entry state from the chunk's, and each lane runs its period
-// again from that state, writing y over x in LDS; the chunk is then stored
-// with coalesced writes.  State and coefficients are float64; samples are
+// The recurrence is linear in the state v[n] = (y[n-1], y[n-2]): a run of L
+// samples with constant coefficients maps v to A^L v + z, A = [[-a1, -a2],
+// [1, 0]], z its zero-state response.  Each period is cut into S lane
+// segments of h = q / S samples (S = 4 when that leaves h >= 2), and one
+// wavefront takes one voice, 64 segments (a chunk) at a time: the chunk's
+// samples are staged in LDS (segment s at s (h + 1), padded so that the 64
+// lanes' reads hit distinct banks), lane s runs segment s from a zero state
+// (z) and raises A to its length by squaring, an inclusive scan of the
+// affine maps (M, z) over the lanes gives every segment's entry state from
+// the chunk's, and each lane runs its segment again from that state,
+// writing y over x in LDS; the chunk is then stored with coalesced writes.
+// Small chunks keep the LDS per workgroup small, so that several wavefronts
+// share a SIMD and hide the sequential sweeps' latency.  State and coefficients are float64; samples are
 // float32 in HBM, read and written once each (8 bytes per sample: the
 // kernel is bound by HBM).
 //
@@ -50,6 +53,15 @@ using voice::sincos_cycles_f64;
 constexpr double kVcfFMin = 10.0;
 constexpr double kVcfFMaxFrac = 0.45;
 
+// Lane segments per control period: each lane takes a quarter (or half)
+// period when that leaves at least two samples, so a chunk of 64 segments is
+// small in LDS and more wavefronts share a CU.
+int vcf_segments(int q) {
+  if (q % 4 == 0 && q / 4 >= 2) return 4;
+  if (q % 2 == 0 && q / 2 >= 2) return 2;
+  return 1;
+}
+
 struct VcfArgs {
   const float* x;
   const float* g;            // backward: dL/dy
@@ -60,7 +72,9 @@ struct VcfArgs {
   int64_t env_ld;
   const float* params;       // [B][3]: cutoff (MIDI note), depth (semitones), Q
   int q;                     // samples per control period
-  uint32_t q_magic;          // x / q == umulhi(x, q_magic) for x < 2^16
+  int S;                     // lane segments per period (1, 2 or 4)
+  int h;                     // samples per lane segment, q / S (>= 2)
+  uint32_t h_magic;          // x / h == umulhi(x, h_magic) for x < 2^16
   double sr;
   float* y;                  // forward output / backward dL/dx
   double* states;            // [B][state_ld][2]: (y[c0 - 1], y[c0 - 2]) at chunk starts
@@ -163,21 +177,21 @@ __device__ __forceinline__ void voice_range(const VcfArgs& a, int64_t b, int64_t
   }
 }
 
-__device__ __forceinline__ int lds_pos(int p, const VcfArgs& a) {   // p < 64 q
-  const int seg = (int)__umulhi((uint32_t)p, a.q_magic);
-  return seg * (a.q + 1) + (p - seg * a.q);
+__device__ __forceinline__ int lds_pos(int p, const VcfArgs& a) {   // p < 64 h
+  const int seg = (int)__umulhi((uint32_t)p, a.h_magic);
+  return seg * (a.h + 1) + (p - seg * a.h);
 }
 
 // Stage samples [c0, c0 + cnt) of src (voice base pointer) into the padded
 // LDS layout; positions past cnt read as 0.  Lane l takes 16-byte groups l,
 // l + 64, ... (coalesced), eight groups' loads in flight before their LDS
 // writes; vec: the voice's samples start 16-byte aligned (else 4-byte loads).
-constexpr int kStageBatch = 8;
+constexpr int kStageBatch = 4;
 
 template <bool V4>
 __device__ __forceinline__ void stage_in_t(float* lds, const float* __restrict__ base, int cnt,
                                            const VcfArgs& a) {
-  const int lane = threadIdx.x, groups = 16 * a.q;          // 64 q samples / 4
+  const int lane = threadIdx.x, groups = 16 * a.h;          // 64 h samples / 4
   for (int g0 = 0; g0 < groups; g0 += 64 * kStageBatch) {
     float4 v[kStageBatch];
 #pragma unroll
@@ -340,9 +354,9 @@ __device__ __forceinline__ void forward_entry_states(const float* xa, const VcfA
                                                      double v0, double v1, double& in0,
                                                      double& in1, double& e0, double& e1) {
   const int lane = threadIdx.x;
-  const float* xs = xa + lane * (a.q + 1);
-  double x1 = lane ? (double)xa[(lane - 1) * (a.q + 1) + a.q - 1] : xh1;
-  double x2 = lane ? (double)xa[(lane - 1) * (a.q + 1) + a.q - 2] : xh2;
+  const float* xs = xa + lane * (a.h + 1);
+  double x1 = lane ? (double)xa[(lane - 1) * (a.h + 1) + a.h - 1] : xh1;
+  double x2 = lane ? (double)xa[(lane - 1) * (a.h + 1) + a.h - 2] : xh2;
   double y1 = 0.0, y2 = 0.0;
   sweep(xs, len, [&](int, float xf) {
     const double x0 = (double)xf;
@@ -382,12 +396,12 @@ __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
   float* yv = a.y + start;
   const bool vec = ((reinterpret_cast<uintptr_t>(xv) | reinterpret_cast<uintptr_t>(yv)) & 15) == 0;
   const double cutoff = a.params[b * 3], depth = a.params[b * 3 + 1], Q = a.params[b * 3 + 2];
-  const int64_t J = (L + a.q - 1) / a.q;
+  const int64_t J = (L + a.h - 1) / a.h;          // lane segments of the voice
   const int64_t chunks = (J + 63) / 64;
   double v0 = 0.0, v1 = 0.0, xh1 = 0.0, xh2 = 0.0;
   for (int64_t c = 0; c < chunks; ++c) {
-    const int64_t c0 = c * 64 * a.q;
-    const int cnt = (int)min((int64_t)64 * a.q, L - c0);
+    const int64_t c0 = c * 64 * a.h;
+    const int cnt = (int)min((int64_t)64 * a.h, L - c0);
     if (a.states && lane == 0) {
       a.states[(b * a.state_ld + c) * 2] = v0;
       a.states[(b * a.state_ld + c) * 2 + 1] = v1;
@@ -395,18 +409,18 @@ __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
     stage_in(lds, xv, c0, cnt, a, vec);
     __syncthreads();
     const int64_t j = c * 64 + lane;
-    const int len = j < J ? (int)min((int64_t)a.q, L - j * a.q) : 0;
+    const int len = j < J ? (int)min((int64_t)a.h, L - j * a.h) : 0;
     Coef k = {0.0, 0.0, 0.0, 0.0};
-    if (len > 0) k = vcf_coef(a, cutoff, depth, Q, (double)a.env[b * a.env_ld + j]);
+    if (len > 0) k = vcf_coef(a, cutoff, depth, Q, (double)a.env[b * a.env_ld + j / a.S]);
     double in0, in1, e0, e1;
     forward_entry_states(lds, a, k, len, xh1, xh2, v0, v1, in0, in1, e0, e1);
     // x history for this lane's period and for the next chunk, read before
     // any lane overwrites its period with y
-    float* xs = lds + lane * (a.q + 1);
-    double x1 = lane ? (double)lds[(lane - 1) * (a.q + 1) + a.q - 1] : xh1;
-    double x2 = lane ? (double)lds[(lane - 1) * (a.q + 1) + a.q - 2] : xh2;
-    const double nxh1 = (double)lds[63 * (a.q + 1) + a.q - 1];
-    const double nxh2 = (double)lds[63 * (a.q + 1) + a.q - 2];
+    float* xs = lds + lane * (a.h + 1);
+    double x1 = lane ? (double)lds[(lane - 1) * (a.h + 1) + a.h - 1] : xh1;
+    double x2 = lane ? (double)lds[(lane - 1) * (a.h + 1) + a.h - 2] : xh2;
+    const double nxh1 = (double)lds[63 * (a.h + 1) + a.h - 1];
+    const double nxh2 = (double)lds[63 * (a.h + 1) + a.h - 2];
     __syncthreads();
     double y1 = in0, y2 = in1;
     sweep(xs, len, [&](int i, float xf) {
@@ -426,10 +440,10 @@ __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
   }
 }
 
-__global__ void __launch_bounds__(64) vcf_backward_kernel(VcfArgs a) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) vcf_backward_kernel(VcfArgs a) {
   extern __shared__ float lds[];              // x, then dL/dx: 64 (q + 1); g, then lambda
   float* xa = lds;
-  float* ga = lds + 64 * (a.q + 1);
+  float* ga = lds + 64 * (a.h + 1);
   const int64_t b = blockIdx.x;
   const int lane = threadIdx.x;
   int64_t start, L;
@@ -444,13 +458,13 @@ __global__ void __launch_bounds__(64) vcf_backward_kernel(VcfArgs a) {
   const bool vec = ((reinterpret_cast<uintptr_t>(xv) | reinterpret_cast<uintptr_t>(gv) |
                      reinterpret_cast<uintptr_t>(dxv)) & 15) == 0;
   const double cutoff = a.params[b * 3], depth = a.params[b * 3 + 1], Q = a.params[b * 3 + 2];
-  const int64_t J = (L + a.q - 1) / a.q;
+  const int64_t J = (L + a.h - 1) / a.h;      // lane segments of the voice
   const int64_t chunks = (J + 63) / 64;
   double u0 = 0.0, u1 = 0.0;                  // (lambda[c_end], lambda[c_end + 1])
   double gc = 0.0, gd = 0.0, gq = 0.0;        // this lane's share of dL/d(cutoff, depth, Q)
   for (int64_t c = chunks - 1; c >= 0; --c) {
-    const int64_t c0 = c * 64 * a.q;
-    const int cnt = (int)min((int64_t)64 * a.q, L - c0);
+    const int64_t c0 = c * 64 * a.h;
+    const int cnt = (int)min((int64_t)64 * a.h, L - c0);
     stage_in(xa, xv, c0, cnt, a, vec);
     stage_in(ga, gv, c0, cnt, a, vec);
     const double v0 = a.states[(b * a.state_ld + c) * 2];
@@ -459,8 +473,8 @@ __global__ void __launch_bounds__(64) vcf_backward_kernel(VcfArgs a) {
     const double xh2 = c0 >= 2 ? (double)xv[c0 - 2] : 0.0;
     __syncthreads();
     const int64_t j = c * 64 + lane;
-    const int len = j < J ? (int)min((int64_t)a.q, L - j * a.q) : 0;
-    const double envj = len > 0 ? (double)a.env[b * a.env_ld + j] : 0.0;
+    const int len = j < J ? (int)min((int64_t)a.h, L - j * a.h) : 0;
+    const double envj = len > 0 ? (double)a.env[b * a.env_ld + j / a.S] : 0.0;
     CoefGrad kg = {};
     if (len > 0) kg = vcf_coef_grad(a, cutoff, depth, Q, envj);
     const Coef k = kg.k;
@@ -473,7 +487,7 @@ __global__ void __launch_bounds__(64) vcf_backward_kernel(VcfArgs a) {
     kn.a2 = __shfl_down(k.a2, 1);
     if (lane == 63) {
       kn = {0.0, 0.0, 0.0, 0.0};
-      if (j + 1 < J) kn = vcf_coef(a, cutoff, depth, Q, (double)a.env[b * a.env_ld + j + 1]);
+      if (j + 1 < J) kn = vcf_coef(a, cutoff, depth, Q, (double)a.env[b * a.env_ld + (j + 1) / a.S]);
     }
     // forward entry states (y[s-1], y[s-2]) of every period
     double fin0, fin1, fe0, fe1;
@@ -481,7 +495,7 @@ __global__ void __launch_bounds__(64) vcf_backward_kernel(VcfArgs a) {
     // lambda over the period from a zero state (samples last to first; the
     // last two use the next period's a1 / a2), and the period's affine map
     // (lambda[e], lambda[e+1]) -> (lambda[s], lambda[s+1])
-    float* gs = ga + lane * (a.q + 1);
+    float* gs = ga + lane * (a.h + 1);
     double l1 = 0.0, l2 = 0.0;
     sweep_rev(gs, len, [&](int i, float gf) {
       const double a1 = i == len - 1 ? kn.a1 : k.a1;
@@ -526,12 +540,12 @@ __global__ void __launch_bounds__(64) vcf_backward_kernel(VcfArgs a) {
       l1 = l0;
     });
     // x history of this period, read before any lane writes dL/dx over x
-    double x1 = lane ? (double)xa[(lane - 1) * (a.q + 1) + a.q - 1] : xh1;
-    double x2 = lane ? (double)xa[(lane - 1) * (a.q + 1) + a.q - 2] : xh2;
+    double x1 = lane ? (double)xa[(lane - 1) * (a.h + 1) + a.h - 1] : xh1;
+    double x2 = lane ? (double)xa[(lane - 1) * (a.h + 1) + a.h - 2] : xh2;
     __syncthreads();
     // forward sweep: y rebuilt from the entry state, the coefficient
     // gradients, and dL/dx[n - 2] once lambda[n] is known
-    float* xs = xa + lane * (a.q + 1);
+    float* xs = xa + lane * (a.h + 1);
     double y1 = fin0, y2 = fin1;
     double lm1 = 0.0, lm2 = 0.0;               // lambda[n-1], lambda[n-2]
     double Gb0 = 0.0, Gb1 = 0.0, Gb2 = 0.0, Ga1 = 0.0, Ga2 = 0.0;
@@ -551,17 +565,21 @@ __global__ void __launch_bounds__(64) vcf_backward_kernel(VcfArgs a) {
     });
     if (len >= 2) xs[len - 2] = (float)fma(k.b0, lm2, fma(k.b1, lm1, kn.b0 * in0));
     if (len >= 1) xs[len - 1] = (float)fma(k.b0, lm1, fma(kn.b1, in0, kn.b0 * in1));
+    double gm = 0.0;
     if (len > 0) {
       const double Gw = Gb0 * kg.dw[0] + Gb1 * kg.dw[1] + Gb2 * kg.dw[0] + Ga1 * kg.dw[2] +
                         Ga2 * kg.dw[3];
       const double Gq = Gb0 * kg.dq[0] + Gb1 * kg.dq[1] + Gb2 * kg.dq[0] + Ga1 * kg.dq[2] +
                         Ga2 * kg.dq[3];
-      const double gm = Gw * kg.dmdw;
+      gm = Gw * kg.dmdw;
       gc += gm;
       gd = fma(gm, envj, gd);
       gq += Gq;
-      if (a.g_env) a.g_env[b * a.env_ld + j] = (float)(gm * depth);
     }
+    // dL/denv[period]: the S lane segments of a period are adjacent lanes
+    for (int off = 1; off < a.S; off <<= 1) gm += __shfl_xor(gm, off);
+    if (a.g_env && len > 0 && (lane & (a.S - 1)) == 0)
+      a.g_env[b * a.env_ld + j / a.S] = (float)(gm * depth);
     __syncthreads();
     stage_out(xa, dxv, c0, cnt, a, vec);
     __syncthreads();
@@ -596,7 +614,9 @@ VcfArgs make_args(const float* x, const float* g, const int64_t* offsets, int64_
   a.env_ld = env_ld;
   a.params = params;
   a.q = q;
-  a.q_magic = (uint32_t)((0x100000000ULL + (uint64_t)q - 1) / (uint64_t)q);
+  a.S = vcf_segments(q);
+  a.h = q / a.S;
+  a.h_magic = (uint32_t)((0x100000000ULL + (uint64_t)a.h - 1) / (uint64_t)a.h);
   a.sr = sr;
   a.y = y;
   a.states = states;
@@ -609,7 +629,8 @@ VcfArgs make_args(const float* x, const float* g, const int64_t* offsets, int64_
 }  // namespace
 
 int64_t vcf_chunks(int64_t max_samples, int q) {
-  const int64_t J = (max_samples + q - 1) / q;
+  const int h = q / vcf_segments(q);
+  const int64_t J = (max_samples + h - 1) / h;
   return (J + 63) / 64;
 }
 
@@ -619,7 +640,7 @@ hipError_t launch_vcf_forward(const float* x, const int64_t* offsets, int64_t ba
                               int64_t state_ld, hipStream_t s) {
   const VcfArgs a = make_args(x, nullptr, offsets, batch, n_samples, env, env_ld, params, q, sr, y,
                               states, state_ld, nullptr, nullptr);
-  const size_t lds = (size_t)64 * (q + 1) * sizeof(float);
+  const size_t lds = (size_t)64 * (a.h + 1) * sizeof(float);
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)vcf_forward_kernel,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -636,7 +657,7 @@ hipError_t launch_vcf_backward(const float* x, const float* g, const int64_t* of
                                hipStream_t s) {
   const VcfArgs a = make_args(x, g, offsets, batch, n_samples, env, env_ld, params, q, sr, g_x,
                               const_cast<double*>(states), state_ld, g_params, g_env);
-  const size_t lds = (size_t)2 * 64 * (q + 1) * sizeof(float);
+  const size_t lds = (size_t)2 * 64 * (a.h + 1) * sizeof(float);
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)vcf_backward_kernel,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
