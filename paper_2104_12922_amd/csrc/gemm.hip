@@ -119,6 +119,24 @@ __device__ __forceinline__ void load_tile(uint4& r0, uint4& r1, int64_t K, const
                   v[12] | ((uint32_t)v[13] << 16), v[14] | ((uint32_t)v[15] << 16));
 }
 
+// load_tile for tiles known to lie inside the operand with 16-byte aligned
+// rows (the large-tile kernel's shapes): two unconditional 16-byte loads, so
+// that the loads of two k-steps can be in flight with exact wait counts.
+template <int OP, int NT>
+__device__ __forceinline__ void load_tile_full(uint4& r0, uint4& r1, const void* srcv, int64_t ld,
+                                               int64_t row0, int64_t k0) {
+  constexpr int G = NT / 32;
+  const int t = threadIdx.x;
+  const uint16_t* src = reinterpret_cast<const uint16_t*>(srcv);
+  const uint4* p;
+  if constexpr (OP == kOpKMajor)
+    p = reinterpret_cast<const uint4*>(src + (row0 + (t >> 1)) * ld + k0 + (t & 1) * 16);
+  else
+    p = reinterpret_cast<const uint4*>(src + (k0 + t / G) * ld + row0 + (t % G) * 16);
+  r0 = p[0];
+  r1 = p[1];
+}
+
 // LDS column of element k of tile row `row`: the four 8-element (16-byte)
 // k-chunks of a row are permuted by (row / 16) mod 4.  The transposed stores
 // of row-major operands (the lanes of a wavefront at 8 k values, 16 rows
@@ -361,21 +379,23 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))
 #define SYNTH_ACC(i, j) ((i) == 0 ? ((j) == 0 ? c00 : c01) : (i) == 1 ? ((j) == 0 ? c10 : c11) \
                          : (i) == 2 ? ((j) == 0 ? c20 : c21) : ((j) == 0 ? c30 : c31))
 
-  uint4 a0, a1, b0, b1;
-  load_tile<AOP, 512>(a0, a1, kend, g.A, g.lda, m0, g.M, kbeg);
-  load_tile<BOP, 512>(b0, b1, kend, g.B, g.ldb, n0, g.N, kbeg);
+  // Two k-steps of loads in flight: while the MFMAs run on the LDS tile of
+  // step ks, the registers hold step ks + 1 (stored to the other LDS buffer
+  // after the MFMAs) and the loads of step ks + 2 are issued, so each global
+  // load has two steps of matrix work to arrive.  The loop is unrolled by two
+  // so that the register sets alternate without copies.
+  uint4 a0, a1, b0, b1, p0, p1, q0, q1;
+  load_tile_full<AOP, 512>(a0, a1, g.A, g.lda, m0, kbeg);
+  load_tile_full<BOP, 512>(b0, b1, g.B, g.ldb, n0, kbeg);
   store_tile<AOP, 512>(a0, a1, As[0]);
   store_tile<BOP, 512>(b0, b1, Bs[0]);
-  __syncthreads();
   const int64_t nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
-  for (int64_t ks = 0; ks < nk; ++ks) {
-    const int buf = (int)(ks & 1);
-    const bool more = ks + 1 < nk;
-    if (more) {
-      load_tile<AOP, 512>(a0, a1, kend, g.A, g.lda, m0, g.M, kbeg + (ks + 1) * BK);
-      load_tile<BOP, 512>(b0, b1, kend, g.B, g.ldb, n0, g.N, kbeg + (ks + 1) * BK);
-    }
-    __builtin_amdgcn_sched_barrier(0);
+  if (nk > 1) {
+    load_tile_full<AOP, 512>(a0, a1, g.A, g.lda, m0, kbeg + BK);
+    load_tile_full<BOP, 512>(b0, b1, g.B, g.ldb, n0, kbeg + BK);
+  }
+  __syncthreads();
+  auto mfma_step = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
       const int kq = kk + 8 * (lane >> 5);
@@ -399,10 +419,33 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))
       c30 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[3], bfr[0], c30, 0, 0, 0);
       c31 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[3], bfr[1], c31, 0, 0, 0);
     }
+  };
+  for (int64_t ks = 0; ks < nk; ks += 2) {
+    // step ks (LDS buffer 0); registers a/b hold step ks + 1
+    if (ks + 2 < nk) {
+      load_tile_full<AOP, 512>(p0, p1, g.A, g.lda, m0, kbeg + (ks + 2) * BK);
+      load_tile_full<BOP, 512>(q0, q1, g.B, g.ldb, n0, kbeg + (ks + 2) * BK);
+    }
     __builtin_amdgcn_sched_barrier(0);
-    if (more) {
-      store_tile<AOP, 512>(a0, a1, As[buf ^ 1]);
-      store_tile<BOP, 512>(b0, b1, Bs[buf ^ 1]);
+    mfma_step(0);
+    __builtin_amdgcn_sched_barrier(0);
+    if (ks + 1 < nk) {
+      store_tile<AOP, 512>(a0, a1, As[1]);
+      store_tile<BOP, 512>(b0, b1, Bs[1]);
+    }
+    __syncthreads();
+    if (ks + 1 >= nk) break;
+    // step ks + 1 (LDS buffer 1); registers p/q hold step ks + 2
+    if (ks + 3 < nk) {
+      load_tile_full<AOP, 512>(a0, a1, g.A, g.lda, m0, kbeg + (ks + 3) * BK);
+      load_tile_full<BOP, 512>(b0, b1, g.B, g.ldb, n0, kbeg + (ks + 3) * BK);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_step(1);
+    __builtin_amdgcn_sched_barrier(0);
+    if (ks + 2 < nk) {
+      store_tile<AOP, 512>(p0, p1, As[0]);
+      store_tile<BOP, 512>(q0, q1, Bs[0]);
     }
     __syncthreads();
   }

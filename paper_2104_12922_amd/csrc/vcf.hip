@@ -54,11 +54,13 @@ constexpr double kVcfFMin = 10.0;
 constexpr double kVcfFMaxFrac = 0.45;
 
 // Lane segments per control period: each lane takes a quarter (or half)
-// period when that leaves at least two samples, so a chunk of 64 segments is
-// small in LDS and more wavefronts share a CU.
+// period when that leaves at least 32 samples, so a chunk of 64 segments is
+// small in LDS and more wavefronts share a CU, while the per-segment work
+// (coefficients, the matrix power, the lane scan) stays small per sample.
+// Segments hold at least 4 samples (the period is at least 4).
 int vcf_segments(int q) {
-  if (q % 4 == 0 && q / 4 >= 2) return 4;
-  if (q % 2 == 0 && q / 2 >= 2) return 2;
+  if (q % 4 == 0 && q / 4 >= 32) return 4;
+  if (q % 2 == 0 && q / 2 >= 32) return 2;
   return 1;
 }
 
@@ -73,7 +75,7 @@ struct VcfArgs {
   const float* params;       // [B][3]: cutoff (MIDI note), depth (semitones), Q
   int q;                     // samples per control period
   int S;                     // lane segments per period (1, 2 or 4)
-  int h;                     // samples per lane segment, q / S (>= 2)
+  int h;                     // samples per lane segment, q / S (>= 4)
   uint32_t h_magic;          // x / h == umulhi(x, h_magic) for x < 2^16
   double sr;
   float* y;                  // forward output / backward dL/dx
@@ -177,9 +179,14 @@ __device__ __forceinline__ void voice_range(const VcfArgs& a, int64_t b, int64_t
   }
 }
 
-__device__ __forceinline__ int lds_pos(int p, const VcfArgs& a) {   // p < 64 h
+// LDS positions of samples p .. p + 3 of a chunk (p < 64 h; segment s at
+// s (h + 1), so sample p sits at p + p / h).  Segments hold at least 4
+// samples, so the four cross at most one boundary: one division for four.
+__device__ __forceinline__ void lds_pos4(int p, const VcfArgs& a, int* i) {
   const int seg = (int)__umulhi((uint32_t)p, a.h_magic);
-  return seg * (a.h + 1) + (p - seg * a.h);
+  const int off = p - seg * a.h, base = p + seg;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) i[e] = base + e + (off + e >= a.h ? 1 : 0);
 }
 
 // Stage samples [c0, c0 + cnt) of src (voice base pointer) into the padded
@@ -211,10 +218,12 @@ __device__ __forceinline__ void stage_in_t(float* lds, const float* __restrict__
       const int g = g0 + lane + 64 * k;
       if (g < groups) {
         const int p = 4 * g;
-        lds[lds_pos(p, a)] = p < cnt ? v[k].x : 0.0f;
-        lds[lds_pos(p + 1, a)] = p + 1 < cnt ? v[k].y : 0.0f;
-        lds[lds_pos(p + 2, a)] = p + 2 < cnt ? v[k].z : 0.0f;
-        lds[lds_pos(p + 3, a)] = p + 3 < cnt ? v[k].w : 0.0f;
+        int i[4];
+        lds_pos4(p, a, i);
+        lds[i[0]] = p < cnt ? v[k].x : 0.0f;
+        lds[i[1]] = p + 1 < cnt ? v[k].y : 0.0f;
+        lds[i[2]] = p + 2 < cnt ? v[k].z : 0.0f;
+        lds[i[3]] = p + 3 < cnt ? v[k].w : 0.0f;
       }
     }
   }
@@ -236,8 +245,9 @@ __device__ __forceinline__ void stage_out(const float* lds, float* __restrict__ 
   const int lane = threadIdx.x;
   float* base = dst + c0;
   for (int p = 4 * lane; p < cnt; p += 256) {
-    const float4 v = make_float4(lds[lds_pos(p, a)], lds[lds_pos(p + 1, a)],
-                                 lds[lds_pos(p + 2, a)], lds[lds_pos(p + 3, a)]);
+    int i[4];
+    lds_pos4(p, a, i);
+    const float4 v = make_float4(lds[i[0]], lds[i[1]], lds[i[2]], lds[i[3]]);
     if (vec && p + 4 <= cnt) {
       *reinterpret_cast<float4*>(base + p) = v;
     } else {
@@ -278,21 +288,25 @@ __device__ __forceinline__ void scan_affine(Mat2& M, double& z0, double& z1) {
   }
 }
 
-// Walks a lane's period in LDS: f(i, x[i]) for i = 0 .. len - 1 in order
+// Walks a lane's segment in LDS: f(i, x[i]) for i = 0 .. len - 1 in order
 // (sweep) or len - 1 .. 0 (sweep_rev), the next block of eight LDS reads in
-// flight while the current block runs.  f may write x[i] (in place).
+// flight while the current block runs.  The block reads are unconditional:
+// they may run up to eight floats past either end of the segment, which the
+// LDS pads (kLdsPad floats before and after the staged samples) keep inside
+// the allocation; values read past the segment are never used.  f may write
+// x[i] (in place).
 constexpr int kSweep = 8;
+constexpr int kLdsPad = 8;
 
 template <class F>
 __device__ __forceinline__ void sweep(const float* xs, int len, F&& f) {
   const int full = len & ~(kSweep - 1);
   float cur[kSweep], nxt[kSweep];
 #pragma unroll
-  for (int e = 0; e < kSweep; ++e) cur[e] = full > 0 ? xs[e] : 0.0f;
+  for (int e = 0; e < kSweep; ++e) cur[e] = xs[e];
   for (int i = 0; i < full; i += kSweep) {
-    const bool more = i + kSweep < full;
 #pragma unroll
-    for (int e = 0; e < kSweep; ++e) nxt[e] = more ? xs[i + kSweep + e] : 0.0f;
+    for (int e = 0; e < kSweep; ++e) nxt[e] = xs[i + kSweep + e];
 #pragma unroll
     for (int e = 0; e < kSweep; ++e) f(i + e, cur[e]);
 #pragma unroll
@@ -307,11 +321,10 @@ __device__ __forceinline__ void sweep_rev(const float* xs, int len, F&& f) {
   for (int i = len - 1; i >= full; --i) f(i, xs[i]);
   float cur[kSweep], nxt[kSweep];
 #pragma unroll
-  for (int e = 0; e < kSweep; ++e) cur[e] = full > 0 ? xs[full - kSweep + e] : 0.0f;
+  for (int e = 0; e < kSweep; ++e) cur[e] = xs[full - kSweep + e];
   for (int i = full - kSweep; i >= 0; i -= kSweep) {
-    const bool more = i > 0;
 #pragma unroll
-    for (int e = 0; e < kSweep; ++e) nxt[e] = more ? xs[i - kSweep + e] : 0.0f;
+    for (int e = 0; e < kSweep; ++e) nxt[e] = xs[i - kSweep + e];
 #pragma unroll
     for (int e = kSweep - 1; e >= 0; --e) f(i + e, cur[e]);
 #pragma unroll
@@ -325,15 +338,14 @@ __device__ __forceinline__ void sweep2(const float* xs, const float* gs, int len
   float cx[kSweep], cg[kSweep], nx[kSweep], ng[kSweep];
 #pragma unroll
   for (int e = 0; e < kSweep; ++e) {
-    cx[e] = full > 0 ? xs[e] : 0.0f;
-    cg[e] = full > 0 ? gs[e] : 0.0f;
+    cx[e] = xs[e];
+    cg[e] = gs[e];
   }
   for (int i = 0; i < full; i += kSweep) {
-    const bool more = i + kSweep < full;
 #pragma unroll
     for (int e = 0; e < kSweep; ++e) {
-      nx[e] = more ? xs[i + kSweep + e] : 0.0f;
-      ng[e] = more ? gs[i + kSweep + e] : 0.0f;
+      nx[e] = xs[i + kSweep + e];
+      ng[e] = gs[i + kSweep + e];
     }
 #pragma unroll
     for (int e = 0; e < kSweep; ++e) f(i + e, cx[e], cg[e]);
@@ -386,7 +398,8 @@ __device__ __forceinline__ void forward_entry_states(const float* xa, const VcfA
 }
 
 __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
-  extern __shared__ float lds[];              // 64 (q + 1)
+  extern __shared__ float lds_raw[];          // pad, 64 (h + 1), pad
+  float* lds = lds_raw + kLdsPad;
   const int64_t b = blockIdx.x;
   const int lane = threadIdx.x;
   int64_t start, L;
@@ -441,9 +454,9 @@ __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
 }
 
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) vcf_backward_kernel(VcfArgs a) {
-  extern __shared__ float lds[];              // x, then dL/dx: 64 (q + 1); g, then lambda
-  float* xa = lds;
-  float* ga = lds + 64 * (a.h + 1);
+  extern __shared__ float lds_raw[];          // pad, x then dL/dx, pad, pad, g then lambda, pad
+  float* xa = lds_raw + kLdsPad;
+  float* ga = xa + 64 * (a.h + 1) + 2 * kLdsPad;
   const int64_t b = blockIdx.x;
   const int lane = threadIdx.x;
   int64_t start, L;
@@ -640,7 +653,7 @@ hipError_t launch_vcf_forward(const float* x, const int64_t* offsets, int64_t ba
                               int64_t state_ld, hipStream_t s) {
   const VcfArgs a = make_args(x, nullptr, offsets, batch, n_samples, env, env_ld, params, q, sr, y,
                               states, state_ld, nullptr, nullptr);
-  const size_t lds = (size_t)64 * (a.h + 1) * sizeof(float);
+  const size_t lds = (size_t)(64 * (a.h + 1) + 2 * kLdsPad) * sizeof(float);
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)vcf_forward_kernel,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -657,7 +670,7 @@ hipError_t launch_vcf_backward(const float* x, const float* g, const int64_t* of
                                hipStream_t s) {
   const VcfArgs a = make_args(x, g, offsets, batch, n_samples, env, env_ld, params, q, sr, g_x,
                               const_cast<double*>(states), state_ld, g_params, g_env);
-  const size_t lds = (size_t)2 * 64 * (a.h + 1) * sizeof(float);
+  const size_t lds = (size_t)2 * (64 * (a.h + 1) + 2 * kLdsPad) * sizeof(float);
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)vcf_backward_kernel,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
