@@ -533,7 +533,7 @@ int synth_vcf_lowpass_backward(const float* x, const float* grad_y, const int64_
  * ------------------------------------------------------------------------- */
 typedef struct synth_fm_config {
     double sample_rate;      /* as synth_config: an integer multiple q of */
-    double control_rate;     /* control_rate, 4 <= q <= 1024 */
+    double control_rate;     /* control_rate, q % 4 == 0, 4 <= q <= 1024 */
     const double* nebula;    /* host [44][4] doubles: (min, max, curve, symmetric) */
 } synth_fm_config;
 
@@ -548,7 +548,7 @@ int synth_fm_sample_params(uint64_t seed, uint64_t first_g, int64_t batch,
  * packed with offsets (dev int64 [batch + 1], as synth_render).  SYNTH_EINVAL
  * for a bad nebula (min > max, curve <= 0, symmetric not 0/1, envelope
  * curve minimum <= 0), size or pointer; SYNTH_EUNSUPPORTED for rates whose
- * ratio is not an integer in 4 .. 1024. */
+ * ratio is not a multiple of 4 in 4 .. 1024. */
 int synth_fm_render(const synth_fm_config* cfg, const float* params, int64_t batch,
                     const int64_t* offsets, int64_t n_samples, float* audio, void* stream);
 

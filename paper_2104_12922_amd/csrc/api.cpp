@@ -225,6 +225,7 @@ int synth_fm_render(const synth_fm_config* cfg, const float* params, int64_t bat
   if (!(sr > 0.0) || !(rc > 0.0) || !isfinite(sr) || !isfinite(rc)) return SYNTH_EINVAL;
   const double qf = sr / rc, qr = nearbyint(qf);
   if (fabs(qr - qf) > 1e-9 * qf || qr < 4.0 || qr > 1024.0) return SYNTH_EUNSUPPORTED;
+  if ((int)qr % 4 != 0) return SYNTH_EUNSUPPORTED;
   NebulaArgs nb;
   memset(&nb, 0, sizeof(nb));
   const double* t = cfg->nebula;

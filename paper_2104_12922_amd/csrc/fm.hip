@@ -12,11 +12,12 @@
 // at a time; lane l evaluates the four envelopes at control sample 64c + l
 // (float64, the Voice's ADSR code) into LDS, then every lane renders four
 // consecutive samples per step (lanes on consecutive 16-byte groups, so each
-// store instruction writes 1 KB of contiguous audio).  Phases n f_i / sr are
-// formed in float64 and reduced to [0, 1) before the float32 hardware sine
-// (which takes revolutions).  Periods after every envelope has reached 0
-// are zero-filled without computation.  Bound by VALU issue: four sines,
-// four float64 phases and the envelope interpolation per sample.
+// store instruction writes 1 KB of contiguous audio).  The four samples share
+// a control period; the phase n f_i / sr of the first is formed in float64
+// and reduced to [0, 1), the next three add f_i / sr in float32 (within
+// 2e-7 cycles), and the float32 hardware sine takes revolutions.  Periods
+// after every envelope has reached 0 are zero-filled without computation.
+// Bound by VALU issue: four sines and four modulated phases per sample.
 #include "voice_device.h"
 
 namespace synth {
@@ -85,13 +86,14 @@ __global__ void __launch_bounds__(64) fm_render_kernel(FmArgs a) {
   const double note_off = v[1] * rc;
   // operator constants (uniform)
   double inc[4];
-  float lvl[4];
+  float lvl[4], incf[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int pb = kOpBase[i];
     const double f = 440.0 * voice::exp2_f64((v[0] - 69.0) / 12.0) * v[pb] *
                      voice::exp2_f64(v[pb + 1] / 1200.0);
     inc[i] = fmin(f, a.sr / 2.0) / a.sr;
+    incf[i] = (float)inc[i];
     lvl[i] = (float)v[pb + 2];
   }
   const float m01 = (float)v[kModBase], m02 = (float)v[kModBase + 1], m03 = (float)v[kModBase + 2];
@@ -131,19 +133,29 @@ __global__ void __launch_bounds__(64) fm_render_kernel(FmArgs a) {
     }
     __syncthreads();
     for (int p = 4 * lane; p < cnt; p += 256) {
+      // samples p .. p + 3 lie in one control period (q and p are multiples
+      // of 4): one period index, one float64 phase per operator, the other
+      // three phases and envelope values by float32 steps from it
+      const int seg = (int)__umulhi((uint32_t)p, a.q_magic);
+      const float t0 = (float)(p - seg * a.q) * inv_q;
+      const double n0d = (double)(c0 + p);
+      float ph0[4], e0[4], de[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double th = n0d * inc[i];
+        ph0[i] = (float)(th - floor(th));
+        e0[i] = envs[i][seg];
+        de[i] = envs[i][seg + 1] - e0[i];
+      }
       float y[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int pe = p + e;
-        const int seg = (int)__umulhi((uint32_t)pe, a.q_magic);
-        const float t = (float)(pe - seg * a.q) * inv_q;
-        const double n = (double)(c0 + pe);
+        const float t = fmaf((float)e, inv_q, t0);
         float ph[4], en[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const double th = n * inc[i];
-          ph[i] = (float)(th - floor(th));
-          en[i] = fmaf(t, envs[i][seg + 1] - envs[i][seg], envs[i][seg]);
+          ph[i] = fmaf((float)e, incf[i], ph0[i]);
+          en[i] = fmaf(t, de[i], e0[i]);
         }
         const float o3 = en[3] * __builtin_amdgcn_sinf(ph[3]);
         const float o2 = en[2] * __builtin_amdgcn_sinf(fmaf(m23, o3, ph[2]));
