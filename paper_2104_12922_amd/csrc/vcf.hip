@@ -14,18 +14,19 @@
 // The recurrence is linear in the state v[n] = (y[n-1], y[n-2]): a run of L
 // samples with constant coefficients maps v to A^L v + z, A = [[-a1, -a2],
 // [1, 0]], z its zero-state response.  Each period is cut into S lane
-// segments of h = q / S samples (S = 4 when that leaves h >= 2), and one
-// wavefront takes one voice, 64 segments (a chunk) at a time: the chunk's
-// samples are staged in LDS (segment s at s (h + 1), padded so that the 64
-// lanes' reads hit distinct banks), lane s runs segment s from a zero state
-// (z) and raises A to its length by squaring, an inclusive scan of the
-// affine maps (M, z) over the lanes gives every segment's entry state from
-// the chunk's, and each lane runs its segment again from that state,
-// writing y over x in LDS; the chunk is then stored with coalesced writes.
-// Small chunks keep the LDS per workgroup small, so that several wavefronts
-// share a SIMD and hide the sequential sweeps' latency.  State and coefficients are float64; samples are
-// float32 in HBM, read and written once each (8 bytes per sample: the
-// kernel is bound by HBM).
+// segments of h = q / S samples (S = 4 or 2 when that leaves h >= 32), and
+// one wavefront takes one voice, 64 segments (a chunk) at a time: the
+// chunk's samples are staged in LDS as they lie in HBM (16-byte writes;
+// segment s at s h: an even h gives the lanes' sweep reads bank conflicts,
+// 2-way for h = 50, cheaper than a padded layout's index arithmetic), lane s
+// runs segment s from a zero state (z) and raises A to its length by
+// squaring, an inclusive scan of the affine maps (M, z) over the lanes gives
+// every segment's entry state from the chunk's, and each lane runs its
+// segment again from that state, writing y over x in LDS; the chunk is then
+// stored with coalesced writes.  Small chunks keep the LDS per workgroup
+// small, so that several wavefronts share a SIMD and hide the sequential
+// sweeps' latency.  State and coefficients are float64; samples are float32
+// in HBM, read and written once each (8 bytes per sample).
 //
 // The adjoint: with lambda[n] = dL/dy[n] (through all later samples),
 //   lambda[n] = g[n] - a1(n+1) lambda[n+1] - a2(n+2) lambda[n+2],
@@ -76,7 +77,6 @@ struct VcfArgs {
   int q;                     // samples per control period
   int S;                     // lane segments per period (1, 2 or 4)
   int h;                     // samples per lane segment, q / S (>= 4)
-  uint32_t h_magic;          // x / h == umulhi(x, h_magic) for x < 2^16
   double sr;
   float* y;                  // forward output / backward dL/dx
   double* states;            // [B][state_ld][2]: (y[c0 - 1], y[c0 - 2]) at chunk starts
@@ -179,75 +179,47 @@ __device__ __forceinline__ void voice_range(const VcfArgs& a, int64_t b, int64_t
   }
 }
 
-// LDS positions of samples p .. p + 3 of a chunk (p < 64 h; segment s at
-// s (h + 1), so sample p sits at p + p / h).  Segments hold at least 4
-// samples, so the four cross at most one boundary: one division for four.
-__device__ __forceinline__ void lds_pos4(int p, const VcfArgs& a, int* i) {
-  const int seg = (int)__umulhi((uint32_t)p, a.h_magic);
-  const int off = p - seg * a.h, base = p + seg;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) i[e] = base + e + (off + e >= a.h ? 1 : 0);
+// Stage samples [c0, c0 + cnt) of src (voice base pointer) into LDS
+// (chunk-relative sample p at lds[p]) with direct global-to-LDS loads: each
+// wave instruction moves 64 consecutive 16-byte groups (1 KB; 4-byte words
+// when the voice's samples are not 16-byte aligned or cnt is not a multiple
+// of 4) into LDS without passing through registers, so the whole chunk is in
+// flight at once.  Addresses are clamped into [0, cnt): positions past cnt
+// hold copies of earlier samples, which no sweep uses.  The loads complete
+// asynchronously: stage_wait() must run before the LDS is read.
+__device__ __forceinline__ void lds_dma(const float* src, float* dst, int bytes) {
+  auto* d = (__attribute__((address_space(3))) void*)dst;
+  if (bytes == 16)
+    __builtin_amdgcn_global_load_lds(src, d, 16, 0, 0);
+  else
+    __builtin_amdgcn_global_load_lds(src, d, 4, 0, 0);
 }
 
-// Stage samples [c0, c0 + cnt) of src (voice base pointer) into the padded
-// LDS layout; positions past cnt read as 0.  Lane l takes 16-byte groups l,
-// l + 64, ... (coalesced), eight groups' loads in flight before their LDS
-// writes; vec: the voice's samples start 16-byte aligned (else 4-byte loads).
-constexpr int kStageBatch = 4;
-
-template <bool V4>
-__device__ __forceinline__ void stage_in_t(float* lds, const float* __restrict__ base, int cnt,
-                                           const VcfArgs& a) {
-  const int lane = threadIdx.x, groups = 16 * a.h;          // 64 h samples / 4
-  for (int g0 = 0; g0 < groups; g0 += 64 * kStageBatch) {
-    float4 v[kStageBatch];
-#pragma unroll
-    for (int k = 0; k < kStageBatch; ++k) {
-      const int p = 4 * (g0 + lane + 64 * k);
-      if (V4) {
-        v[k] = *reinterpret_cast<const float4*>(base + min(p, cnt - 4));
-      } else {
-        v[k].x = base[min(p, cnt - 1)];
-        v[k].y = base[min(p + 1, cnt - 1)];
-        v[k].z = base[min(p + 2, cnt - 1)];
-        v[k].w = base[min(p + 3, cnt - 1)];
-      }
+__device__ __forceinline__ void stage_in(float* lds, const float* __restrict__ src, int64_t c0,
+                                         int cnt, const VcfArgs& a, bool vec) {
+  const int lane = threadIdx.x, span = 64 * a.h;            // LDS floats of a chunk
+  const float* base = src + c0;
+  if (vec && (cnt & 3) == 0) {
+    for (int k = 0; 256 * k < span; ++k) {
+      const int p = 256 * k + 4 * lane;
+      if (p < span) lds_dma(base + min(p, cnt - 4), lds + 256 * k, 16);
     }
-#pragma unroll
-    for (int k = 0; k < kStageBatch; ++k) {
-      const int g = g0 + lane + 64 * k;
-      if (g < groups) {
-        const int p = 4 * g;
-        int i[4];
-        lds_pos4(p, a, i);
-        lds[i[0]] = p < cnt ? v[k].x : 0.0f;
-        lds[i[1]] = p + 1 < cnt ? v[k].y : 0.0f;
-        lds[i[2]] = p + 2 < cnt ? v[k].z : 0.0f;
-        lds[i[3]] = p + 3 < cnt ? v[k].w : 0.0f;
-      }
-    }
+  } else {
+    for (int k = 0; 64 * k < span; ++k)
+      lds_dma(base + min(64 * k + lane, cnt - 1), lds + 64 * k, 4);
   }
 }
 
-// Loads are unconditional (addresses clamped into [0, cnt)) so that a batch
-// is in flight at once; values past cnt are replaced by 0.  16-byte loads
-// when the voice's samples start 16-byte aligned and cnt is a multiple of 4.
-__device__ __forceinline__ void stage_in(float* lds, const float* __restrict__ src, int64_t c0,
-                                         int cnt, const VcfArgs& a, bool vec) {
-  if (vec && (cnt & 3) == 0)
-    stage_in_t<true>(lds, src + c0, cnt, a);
-  else
-    stage_in_t<false>(lds, src + c0, cnt, a);
-}
+// Waits for this wave's outstanding global loads, the staging ones included
+// (s_waitcnt vmcnt(0); the other counters left free).
+__device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 __device__ __forceinline__ void stage_out(const float* lds, float* __restrict__ dst, int64_t c0,
-                                          int cnt, const VcfArgs& a, bool vec) {
+                                          int cnt, bool vec) {
   const int lane = threadIdx.x;
   float* base = dst + c0;
   for (int p = 4 * lane; p < cnt; p += 256) {
-    int i[4];
-    lds_pos4(p, a, i);
-    const float4 v = make_float4(lds[i[0]], lds[i[1]], lds[i[2]], lds[i[3]]);
+    const float4 v = *reinterpret_cast<const float4*>(lds + p);
     if (vec && p + 4 <= cnt) {
       *reinterpret_cast<float4*>(base + p) = v;
     } else {
@@ -366,9 +338,9 @@ __device__ __forceinline__ void forward_entry_states(const float* xa, const VcfA
                                                      double v0, double v1, double& in0,
                                                      double& in1, double& e0, double& e1) {
   const int lane = threadIdx.x;
-  const float* xs = xa + lane * (a.h + 1);
-  double x1 = lane ? (double)xa[(lane - 1) * (a.h + 1) + a.h - 1] : xh1;
-  double x2 = lane ? (double)xa[(lane - 1) * (a.h + 1) + a.h - 2] : xh2;
+  const float* xs = xa + lane * a.h;
+  double x1 = lane ? (double)xa[lane * a.h - 1] : xh1;
+  double x2 = lane ? (double)xa[lane * a.h - 2] : xh2;
   double y1 = 0.0, y2 = 0.0;
   sweep(xs, len, [&](int, float xf) {
     const double x0 = (double)xf;
@@ -398,7 +370,7 @@ __device__ __forceinline__ void forward_entry_states(const float* xa, const VcfA
 }
 
 __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
-  extern __shared__ float lds_raw[];          // pad, 64 (h + 1), pad
+  extern __shared__ float lds_raw[];          // pad, 64 h, pad
   float* lds = lds_raw + kLdsPad;
   const int64_t b = blockIdx.x;
   const int lane = threadIdx.x;
@@ -411,7 +383,19 @@ __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
   const double cutoff = a.params[b * 3], depth = a.params[b * 3 + 1], Q = a.params[b * 3 + 2];
   const int64_t J = (L + a.h - 1) / a.h;          // lane segments of the voice
   const int64_t chunks = (J + 63) / 64;
+  // coefficients of lane segment 64 c + lane (zero past the voice)
+  auto seg_coef = [&](int64_t c) {
+    const int64_t j = c * 64 + lane;
+    Coef k = {0.0, 0.0, 0.0, 0.0};
+    if (j < J) k = vcf_coef(a, cutoff, depth, Q, (double)a.env[b * a.env_ld + j / a.S]);
+    return k;
+  };
+  // Per chunk: wait for its samples, run it, compute the next chunk's
+  // coefficients (their loads then wait for no store), store it, and start
+  // the next chunk's loads.
   double v0 = 0.0, v1 = 0.0, xh1 = 0.0, xh2 = 0.0;
+  Coef k = seg_coef(0);
+  stage_in(lds, xv, 0, (int)min((int64_t)64 * a.h, L), a, vec);
   for (int64_t c = 0; c < chunks; ++c) {
     const int64_t c0 = c * 64 * a.h;
     const int cnt = (int)min((int64_t)64 * a.h, L - c0);
@@ -419,21 +403,19 @@ __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
       a.states[(b * a.state_ld + c) * 2] = v0;
       a.states[(b * a.state_ld + c) * 2 + 1] = v1;
     }
-    stage_in(lds, xv, c0, cnt, a, vec);
-    __syncthreads();
     const int64_t j = c * 64 + lane;
     const int len = j < J ? (int)min((int64_t)a.h, L - j * a.h) : 0;
-    Coef k = {0.0, 0.0, 0.0, 0.0};
-    if (len > 0) k = vcf_coef(a, cutoff, depth, Q, (double)a.env[b * a.env_ld + j / a.S]);
+    stage_wait();
+    __syncthreads();
     double in0, in1, e0, e1;
     forward_entry_states(lds, a, k, len, xh1, xh2, v0, v1, in0, in1, e0, e1);
-    // x history for this lane's period and for the next chunk, read before
-    // any lane overwrites its period with y
-    float* xs = lds + lane * (a.h + 1);
-    double x1 = lane ? (double)lds[(lane - 1) * (a.h + 1) + a.h - 1] : xh1;
-    double x2 = lane ? (double)lds[(lane - 1) * (a.h + 1) + a.h - 2] : xh2;
-    const double nxh1 = (double)lds[63 * (a.h + 1) + a.h - 1];
-    const double nxh2 = (double)lds[63 * (a.h + 1) + a.h - 2];
+    // x history for this lane's segment and for the next chunk, read before
+    // any lane overwrites its segment with y
+    float* xs = lds + lane * a.h;
+    double x1 = lane ? (double)lds[lane * a.h - 1] : xh1;
+    double x2 = lane ? (double)lds[lane * a.h - 2] : xh2;
+    const double nxh1 = (double)lds[64 * a.h - 1];
+    const double nxh2 = (double)lds[64 * a.h - 2];
     __syncthreads();
     double y1 = in0, y2 = in1;
     sweep(xs, len, [&](int i, float xf) {
@@ -443,9 +425,13 @@ __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
       xs[i] = (float)y0;
       x2 = x1; x1 = x0; y2 = y1; y1 = y0;
     });
+    const bool more = c + 1 < chunks;
+    const Coef kn = more ? seg_coef(c + 1) : k;
     __syncthreads();
-    stage_out(lds, yv, c0, cnt, a, vec);
+    stage_out(lds, yv, c0, cnt, vec);
     __syncthreads();
+    if (more) stage_in(lds, xv, c0 + 64 * a.h, (int)min((int64_t)64 * a.h, L - c0 - 64 * a.h), a, vec);
+    k = kn;
     v0 = e0;
     v1 = e1;
     xh1 = nxh1;
@@ -456,7 +442,7 @@ __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) vcf_backward_kernel(VcfArgs a) {
   extern __shared__ float lds_raw[];          // pad, x then dL/dx, pad, pad, g then lambda, pad
   float* xa = lds_raw + kLdsPad;
-  float* ga = xa + 64 * (a.h + 1) + 2 * kLdsPad;
+  float* ga = xa + 64 * a.h + 2 * kLdsPad;
   const int64_t b = blockIdx.x;
   const int lane = threadIdx.x;
   int64_t start, L;
@@ -473,42 +459,67 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) vc
   const double cutoff = a.params[b * 3], depth = a.params[b * 3 + 1], Q = a.params[b * 3 + 2];
   const int64_t J = (L + a.h - 1) / a.h;      // lane segments of the voice
   const int64_t chunks = (J + 63) / 64;
-  double u0 = 0.0, u1 = 0.0;                  // (lambda[c_end], lambda[c_end + 1])
-  double gc = 0.0, gd = 0.0, gq = 0.0;        // this lane's share of dL/d(cutoff, depth, Q)
-  for (int64_t c = chunks - 1; c >= 0; --c) {
+  // What a chunk needs from HBM besides its samples: the forward state at
+  // its start, x[c0 - 1], x[c0 - 2], and the coefficients (with their
+  // derivatives) of lane segment 64 c + lane and of the segment after it
+  // (lane 63: the first of the next chunk; zero past the voice, where lambda
+  // is 0).
+  struct ChunkIn {
+    double v0, v1, xh1, xh2, envj;
+    CoefGrad kg;
+    Coef kn;
+  };
+  auto chunk_in = [&](int64_t c) {
+    ChunkIn r;
+    const int64_t c0 = c * 64 * a.h;
+    r.v0 = a.states[(b * a.state_ld + c) * 2];
+    r.v1 = a.states[(b * a.state_ld + c) * 2 + 1];
+    r.xh1 = c0 >= 1 ? (double)xv[c0 - 1] : 0.0;
+    r.xh2 = c0 >= 2 ? (double)xv[c0 - 2] : 0.0;
+    const int64_t j = c * 64 + lane;
+    r.envj = j < J ? (double)a.env[b * a.env_ld + j / a.S] : 0.0;
+    r.kg = {};
+    if (j < J) r.kg = vcf_coef_grad(a, cutoff, depth, Q, r.envj);
+    r.kn.b0 = __shfl_down(r.kg.k.b0, 1);
+    r.kn.b1 = __shfl_down(r.kg.k.b1, 1);
+    r.kn.a1 = __shfl_down(r.kg.k.a1, 1);
+    r.kn.a2 = __shfl_down(r.kg.k.a2, 1);
+    if (lane == 63) {
+      r.kn = {0.0, 0.0, 0.0, 0.0};
+      if (j + 1 < J) r.kn = vcf_coef(a, cutoff, depth, Q, (double)a.env[b * a.env_ld + (j + 1) / a.S]);
+    }
+    return r;
+  };
+  auto stage_chunk = [&](int64_t c) {
     const int64_t c0 = c * 64 * a.h;
     const int cnt = (int)min((int64_t)64 * a.h, L - c0);
     stage_in(xa, xv, c0, cnt, a, vec);
     stage_in(ga, gv, c0, cnt, a, vec);
-    const double v0 = a.states[(b * a.state_ld + c) * 2];
-    const double v1 = a.states[(b * a.state_ld + c) * 2 + 1];
-    const double xh1 = c0 >= 1 ? (double)xv[c0 - 1] : 0.0;
-    const double xh2 = c0 >= 2 ? (double)xv[c0 - 2] : 0.0;
-    __syncthreads();
+  };
+  // Per chunk (last to first): wait for its samples, run it, gather the
+  // previous chunk's inputs (their loads then wait for no store), store
+  // dL/dx, and start the previous chunk's sample loads.
+  double u0 = 0.0, u1 = 0.0;                  // (lambda[c_end], lambda[c_end + 1])
+  double gc = 0.0, gd = 0.0, gq = 0.0;        // this lane's share of dL/d(cutoff, depth, Q)
+  ChunkIn in = chunk_in(chunks - 1);
+  stage_chunk(chunks - 1);
+  for (int64_t c = chunks - 1; c >= 0; --c) {
+    const int64_t c0 = c * 64 * a.h;
+    const int cnt = (int)min((int64_t)64 * a.h, L - c0);
+    const double v0 = in.v0, v1 = in.v1, xh1 = in.xh1, xh2 = in.xh2, envj = in.envj;
+    const CoefGrad kg = in.kg;
+    const Coef k = kg.k, kn = in.kn;
     const int64_t j = c * 64 + lane;
     const int len = j < J ? (int)min((int64_t)a.h, L - j * a.h) : 0;
-    const double envj = len > 0 ? (double)a.env[b * a.env_ld + j / a.S] : 0.0;
-    CoefGrad kg = {};
-    if (len > 0) kg = vcf_coef_grad(a, cutoff, depth, Q, envj);
-    const Coef k = kg.k;
-    // the next period's coefficients (lane 63: the first period of the next
-    // chunk; zero past the voice, where lambda is 0)
-    Coef kn;
-    kn.b0 = __shfl_down(k.b0, 1);
-    kn.b1 = __shfl_down(k.b1, 1);
-    kn.a1 = __shfl_down(k.a1, 1);
-    kn.a2 = __shfl_down(k.a2, 1);
-    if (lane == 63) {
-      kn = {0.0, 0.0, 0.0, 0.0};
-      if (j + 1 < J) kn = vcf_coef(a, cutoff, depth, Q, (double)a.env[b * a.env_ld + (j + 1) / a.S]);
-    }
+    stage_wait();
+    __syncthreads();
     // forward entry states (y[s-1], y[s-2]) of every period
     double fin0, fin1, fe0, fe1;
     forward_entry_states(xa, a, k, len, xh1, xh2, v0, v1, fin0, fin1, fe0, fe1);
     // lambda over the period from a zero state (samples last to first; the
     // last two use the next period's a1 / a2), and the period's affine map
     // (lambda[e], lambda[e+1]) -> (lambda[s], lambda[s+1])
-    float* gs = ga + lane * (a.h + 1);
+    float* gs = ga + lane * a.h;
     double l1 = 0.0, l2 = 0.0;
     sweep_rev(gs, len, [&](int i, float gf) {
       const double a1 = i == len - 1 ? kn.a1 : k.a1;
@@ -553,12 +564,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) vc
       l1 = l0;
     });
     // x history of this period, read before any lane writes dL/dx over x
-    double x1 = lane ? (double)xa[(lane - 1) * (a.h + 1) + a.h - 1] : xh1;
-    double x2 = lane ? (double)xa[(lane - 1) * (a.h + 1) + a.h - 2] : xh2;
+    double x1 = lane ? (double)xa[lane * a.h - 1] : xh1;
+    double x2 = lane ? (double)xa[lane * a.h - 2] : xh2;
     __syncthreads();
     // forward sweep: y rebuilt from the entry state, the coefficient
     // gradients, and dL/dx[n - 2] once lambda[n] is known
-    float* xs = xa + lane * (a.h + 1);
+    float* xs = xa + lane * a.h;
     double y1 = fin0, y2 = fin1;
     double lm1 = 0.0, lm2 = 0.0;               // lambda[n-1], lambda[n-2]
     double Gb0 = 0.0, Gb1 = 0.0, Gb2 = 0.0, Ga1 = 0.0, Ga2 = 0.0;
@@ -591,11 +602,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) vc
     }
     // dL/denv[period]: the S lane segments of a period are adjacent lanes
     for (int off = 1; off < a.S; off <<= 1) gm += __shfl_xor(gm, off);
+    if (c > 0) in = chunk_in(c - 1);
     if (a.g_env && len > 0 && (lane & (a.S - 1)) == 0)
       a.g_env[b * a.env_ld + j / a.S] = (float)(gm * depth);
     __syncthreads();
-    stage_out(xa, dxv, c0, cnt, a, vec);
+    stage_out(xa, dxv, c0, cnt, vec);
     __syncthreads();
+    if (c > 0) stage_chunk(c - 1);
     u0 = nu0;
     u1 = nu1;
   }
@@ -629,7 +642,6 @@ VcfArgs make_args(const float* x, const float* g, const int64_t* offsets, int64_
   a.q = q;
   a.S = vcf_segments(q);
   a.h = q / a.S;
-  a.h_magic = (uint32_t)((0x100000000ULL + (uint64_t)a.h - 1) / (uint64_t)a.h);
   a.sr = sr;
   a.y = y;
   a.states = states;
@@ -653,7 +665,7 @@ hipError_t launch_vcf_forward(const float* x, const int64_t* offsets, int64_t ba
                               int64_t state_ld, hipStream_t s) {
   const VcfArgs a = make_args(x, nullptr, offsets, batch, n_samples, env, env_ld, params, q, sr, y,
                               states, state_ld, nullptr, nullptr);
-  const size_t lds = (size_t)(64 * (a.h + 1) + 2 * kLdsPad) * sizeof(float);
+  const size_t lds = (size_t)(64 * a.h + 2 * kLdsPad) * sizeof(float);
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)vcf_forward_kernel,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -670,7 +682,7 @@ hipError_t launch_vcf_backward(const float* x, const float* g, const int64_t* of
                                hipStream_t s) {
   const VcfArgs a = make_args(x, g, offsets, batch, n_samples, env, env_ld, params, q, sr, g_x,
                               const_cast<double*>(states), state_ld, g_params, g_env);
-  const size_t lds = (size_t)2 * (64 * (a.h + 1) + 2 * kLdsPad) * sizeof(float);
+  const size_t lds = (size_t)2 * (64 * a.h + 2 * kLdsPad) * sizeof(float);
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)vcf_backward_kernel,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
