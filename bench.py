@@ -420,17 +420,21 @@ def bench_vcf(args):
                           torch.rand(B, device="cuda", generator=gen) * 14.5 + 0.5], 1).contiguous()
     g = torch.randn(x.numel(), device="cuda", generator=gen)
     y = torch.empty_like(x)
+    # launch order: longest voices first (lengths known with the batch)
+    order = torch.from_numpy(np.argsort(-wl.lengths, kind="stable").astype(np.int32)).cuda()
     for _ in range(max(1, args.warmup)):
-        _, st = V.lowpass(x, env, params, 100, offsets=offs, max_samples=lmax, keep_states=True, out=y)
-        V.lowpass_backward(x, g, env, params, st, 100, offsets=offs, max_samples=lmax)
+        _, st = V.lowpass(x, env, params, 100, offsets=offs, max_samples=lmax, keep_states=True,
+                          out=y, order=order)
+        V.lowpass_backward(x, g, env, params, st, 100, offsets=offs, max_samples=lmax, order=order)
     torch.cuda.synchronize()
     ef, eb = _events(args.steps), _events(args.steps)
     for i in range(args.steps):
         ef[i][0].record()
-        _, st = V.lowpass(x, env, params, 100, offsets=offs, max_samples=lmax, keep_states=True, out=y)
+        _, st = V.lowpass(x, env, params, 100, offsets=offs, max_samples=lmax, keep_states=True,
+                          out=y, order=order)
         ef[i][1].record()
         eb[i][0].record()
-        V.lowpass_backward(x, g, env, params, st, 100, offsets=offs, max_samples=lmax)
+        V.lowpass_backward(x, g, env, params, st, 100, offsets=offs, max_samples=lmax, order=order)
         eb[i][1].record()
     torch.cuda.synchronize()
     fms = float(np.mean([a.elapsed_time(b) for a, b in ef]))
@@ -441,7 +445,8 @@ def bench_vcf(args):
            "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": fms + bms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64", "data": "synthetic",
-           "config": {"workload": wl.name, "voices": B, "samples": n, "period": 100},
+           "config": {"workload": wl.name, "voices": B, "samples": n, "period": 100,
+                      "launch_order": "longest voices first"},
            "forward_ms": fms, "adjoint_ms": bms,
            "roofline": {"bound": "hbm", "achieved": fgbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": fgbs / HBM_PEAK_GBS, "traffic": None, "kernel": "vcf_forward_kernel",
@@ -463,16 +468,17 @@ def bench_fm(args):
     offs = torch.from_numpy(wl.offsets).cuda()
     tab = W.fm_default_nebula(duration_min=0.1).table()
     out = torch.empty(wl.total_samples, dtype=torch.float32, device="cuda")
+    order = torch.from_numpy(np.argsort(-wl.lengths, kind="stable").astype(np.int32)).cuda()
     for _ in range(max(1, args.warmup)):
         u = FMV.fm_sample_params(wl.seed, batch=B)
-        FMV.fm_render(u, tab, offsets=offs, out=out)
+        FMV.fm_render(u, tab, offsets=offs, out=out, order=order)
     torch.cuda.synchronize()
     ev = _events(args.steps)
     t0 = time.perf_counter()
     for a, b in ev:
         a.record()
         u = FMV.fm_sample_params(wl.seed, batch=B)
-        FMV.fm_render(u, tab, offsets=offs, out=out)
+        FMV.fm_render(u, tab, offsets=offs, out=out, order=order)
         b.record()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / args.steps
@@ -483,7 +489,8 @@ def bench_fm(args):
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
            "wall_ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": wl.name + "_fm4", "voices": B, "samples": n},
+           "config": {"workload": wl.name + "_fm4", "voices": B, "samples": n,
+                      "launch_order": "longest voices first"},
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "fm_render_kernel",
                         "alg_bytes_per_launch": 4.0 * n}}

@@ -493,6 +493,10 @@ int synth_mmd_l1(const float* X, int64_t n, const float* Y, int64_t m, int64_t d
  *   states      dev float64 [batch][state_ld][2] or NULL: the recurrence
  *               state at every 64-period chunk start, which the backward
  *               pass needs; state_ld >= synth_vcf_state_chunks(longest, period).
+ *   order       NULL, or dev int32 [batch], a permutation of 0 .. batch - 1:
+ *               the order in which workgroups take the voices (for ragged
+ *               batches, longest first shortens the tail); results do not
+ *               depend on it.  batch <= 2^31 - 1 with an order.
  * SYNTH_EINVAL on a bad size, stride or NULL pointer.
  * ------------------------------------------------------------------------- */
 
@@ -503,19 +507,21 @@ int64_t synth_vcf_state_chunks(int64_t max_samples, int period);
 int synth_vcf_lowpass(const float* x, const int64_t* offsets, int64_t batch, int64_t n_samples,
                       int64_t max_samples, const float* env, int64_t env_ld, const float* params,
                       int period, double sample_rate, float* y, double* states, int64_t state_ld,
-                      void* stream);
+                      const int32_t* order, void* stream);
 
 /* Adjoint of synth_vcf_lowpass for the same inputs, given grad_y = dL/dy and
  * the states its forward call wrote: grad_x = dL/dx (dev float32, layout of
  * x; may be grad_y), grad_params = dL/d(cutoff, depth, Q) (dev float32
  * [batch][3]), grad_env = dL/denv (dev float32 [batch][env_ld], rows written
  * for the voice's periods; may be NULL).  The clamp passes the gradient
- * where 10 Hz <= f <= 0.45 sample_rate and blocks it outside. */
+ * where 10 Hz <= f <= 0.45 sample_rate and blocks it outside.  order as
+ * synth_vcf_lowpass. */
 int synth_vcf_lowpass_backward(const float* x, const float* grad_y, const int64_t* offsets,
                                int64_t batch, int64_t n_samples, int64_t max_samples,
                                const float* env, int64_t env_ld, const float* params, int period,
                                double sample_rate, const double* states, int64_t state_ld,
-                               float* grad_x, float* grad_params, float* grad_env, void* stream);
+                               float* grad_x, float* grad_params, float* grad_env,
+                               const int32_t* order, void* stream);
 
 /* -------------------------------------------------------------------------
  * Four-operator FM voice (the FM architecture Sections 3.2 and 7 announce).
@@ -548,9 +554,12 @@ int synth_fm_sample_params(uint64_t seed, uint64_t first_g, int64_t batch,
  * packed with offsets (dev int64 [batch + 1], as synth_render).  SYNTH_EINVAL
  * for a bad nebula (min > max, curve <= 0, symmetric not 0/1, envelope
  * curve minimum <= 0), size or pointer; SYNTH_EUNSUPPORTED for rates whose
- * ratio is not a multiple of 4 in 4 .. 1024. */
+ * ratio is not a multiple of 4 in 4 .. 1024.  order: NULL, or dev int32
+ * [batch], a permutation of 0 .. batch - 1, the order in which workgroups
+ * take the voices (results do not depend on it). */
 int synth_fm_render(const synth_fm_config* cfg, const float* params, int64_t batch,
-                    const int64_t* offsets, int64_t n_samples, float* audio, void* stream);
+                    const int64_t* offsets, int64_t n_samples, float* audio,
+                    const int32_t* order, void* stream);
 
 #ifdef __cplusplus
 }

@@ -219,7 +219,8 @@ int synth_fm_sample_params(uint64_t seed, uint64_t first_g, int64_t batch,
 }
 
 int synth_fm_render(const synth_fm_config* cfg, const float* params, int64_t batch,
-                    const int64_t* offsets, int64_t n_samples, float* audio, void* stream) {
+                    const int64_t* offsets, int64_t n_samples, float* audio,
+                    const int32_t* order, void* stream) {
   if (!cfg || !cfg->nebula || batch < 0) return SYNTH_EINVAL;
   const double sr = cfg->sample_rate, rc = cfg->control_rate;
   if (!(sr > 0.0) || !(rc > 0.0) || !isfinite(sr) || !isfinite(rc)) return SYNTH_EINVAL;
@@ -246,7 +247,7 @@ int synth_fm_render(const synth_fm_config* cfg, const float* params, int64_t bat
   if (!params || !audio || batch > 0x7FFFFFFF) return SYNTH_EINVAL;
   if (!offsets && (n_samples <= 0 || n_samples > ((int64_t)1 << 40))) return SYNTH_EINVAL;
   return to_status(synth::launch_fm_render(params, offsets, batch, offsets ? 0 : n_samples, audio,
-                                           sr, rc, (int)qr, nb, nullptr, (hipStream_t)stream));
+                                           sr, rc, (int)qr, nb, order, (hipStream_t)stream));
 }
 
 namespace {
@@ -801,29 +802,32 @@ int vcf_check(const float* x, const int64_t* offsets, int64_t batch, int64_t n_s
 int synth_vcf_lowpass(const float* x, const int64_t* offsets, int64_t batch, int64_t n_samples,
                       int64_t max_samples, const float* env, int64_t env_ld, const float* params,
                       int period, double sample_rate, float* y, double* states, int64_t state_ld,
-                      void* stream) {
+                      const int32_t* order, void* stream) {
   const int64_t lmax = offsets ? max_samples : n_samples;
   const int st = vcf_check(x, offsets, batch, n_samples, env, env_ld, params, period, sample_rate,
                            y, states, state_ld, batch > 0 ? lmax : 1);
   if (st != SYNTH_OK || batch == 0) return st;
+  if (order && batch > 0x7FFFFFFF) return SYNTH_EINVAL;
   return to_status(synth::launch_vcf_forward(x, offsets, batch, offsets ? 0 : n_samples, env,
                                              env_ld, params, period, sample_rate, y, states,
-                                             state_ld, (hipStream_t)stream));
+                                             state_ld, order, (hipStream_t)stream));
 }
 
 int synth_vcf_lowpass_backward(const float* x, const float* grad_y, const int64_t* offsets,
                                int64_t batch, int64_t n_samples, int64_t max_samples,
                                const float* env, int64_t env_ld, const float* params, int period,
                                double sample_rate, const double* states, int64_t state_ld,
-                               float* grad_x, float* grad_params, float* grad_env, void* stream) {
+                               float* grad_x, float* grad_params, float* grad_env,
+                               const int32_t* order, void* stream) {
   const int64_t lmax = offsets ? max_samples : n_samples;
   const int st = vcf_check(x, offsets, batch, n_samples, env, env_ld, params, period, sample_rate,
                            grad_x, states, state_ld, batch > 0 ? lmax : 1);
   if (st != SYNTH_OK || batch == 0) return st;
   if (!grad_y || !states || !grad_params) return SYNTH_EINVAL;
+  if (order && batch > 0x7FFFFFFF) return SYNTH_EINVAL;
   return to_status(synth::launch_vcf_backward(x, grad_y, offsets, batch, offsets ? 0 : n_samples,
                                               env, env_ld, params, period, sample_rate, states,
-                                              state_ld, grad_x, grad_params, grad_env,
+                                              state_ld, grad_x, grad_params, grad_env, order,
                                               (hipStream_t)stream));
 }
 

@@ -113,12 +113,12 @@ int64_t vcf_chunks(int64_t max_samples, int q);
 hipError_t launch_vcf_forward(const float* x, const int64_t* offsets, int64_t batch,
                               int64_t n_samples, const float* env, int64_t env_ld,
                               const float* params, int q, double sr, float* y, double* states,
-                              int64_t state_ld, hipStream_t s);
+                              int64_t state_ld, const int32_t* order, hipStream_t s);
 hipError_t launch_vcf_backward(const float* x, const float* g, const int64_t* offsets,
                                int64_t batch, int64_t n_samples, const float* env, int64_t env_ld,
                                const float* params, int q, double sr, const double* states,
                                int64_t state_ld, float* g_x, float* g_params, float* g_env,
-                               hipStream_t s);
+                               const int32_t* order, hipStream_t s);
 hipError_t launch_colsum(const void* x, int x_bf16, int64_t rows, int64_t cols, int64_t ld,
                          float* sum, float* sumsq, hipStream_t s);
 hipError_t launch_feature_stats(const float* x, int64_t rows, int64_t cols, float min_var,

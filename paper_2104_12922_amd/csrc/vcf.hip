@@ -83,6 +83,7 @@ struct VcfArgs {
   int64_t state_ld;
   float* g_params;           // backward: [B][3]
   float* g_env;              // backward: [B][env_ld] or null
+  const int32_t* order;      // null, or the voices in the order workgroups take them
 };
 
 struct Coef {
@@ -372,7 +373,7 @@ __device__ __forceinline__ void forward_entry_states(const float* xa, const VcfA
 __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
   extern __shared__ float lds_raw[];          // pad, 64 h, pad
   float* lds = lds_raw + kLdsPad;
-  const int64_t b = blockIdx.x;
+  const int64_t b = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
   const int lane = threadIdx.x;
   int64_t start, L;
   voice_range(a, b, start, L);
@@ -443,7 +444,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) vc
   extern __shared__ float lds_raw[];          // pad, x then dL/dx, pad, pad, g then lambda, pad
   float* xa = lds_raw + kLdsPad;
   float* ga = xa + 64 * a.h + 2 * kLdsPad;
-  const int64_t b = blockIdx.x;
+  const int64_t b = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
   const int lane = threadIdx.x;
   int64_t start, L;
   voice_range(a, b, start, L);
@@ -629,7 +630,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) vc
 VcfArgs make_args(const float* x, const float* g, const int64_t* offsets, int64_t batch,
                   int64_t n_samples, const float* env, int64_t env_ld, const float* params,
                   int q, double sr, float* y, double* states, int64_t state_ld, float* g_params,
-                  float* g_env) {
+                  float* g_env, const int32_t* order) {
   VcfArgs a;
   a.x = x;
   a.g = g;
@@ -648,6 +649,7 @@ VcfArgs make_args(const float* x, const float* g, const int64_t* offsets, int64_
   a.state_ld = state_ld;
   a.g_params = g_params;
   a.g_env = g_env;
+  a.order = order;
   return a;
 }
 
@@ -662,9 +664,9 @@ int64_t vcf_chunks(int64_t max_samples, int q) {
 hipError_t launch_vcf_forward(const float* x, const int64_t* offsets, int64_t batch,
                               int64_t n_samples, const float* env, int64_t env_ld,
                               const float* params, int q, double sr, float* y, double* states,
-                              int64_t state_ld, hipStream_t s) {
+                              int64_t state_ld, const int32_t* order, hipStream_t s) {
   const VcfArgs a = make_args(x, nullptr, offsets, batch, n_samples, env, env_ld, params, q, sr, y,
-                              states, state_ld, nullptr, nullptr);
+                              states, state_ld, nullptr, nullptr, order);
   const size_t lds = (size_t)(64 * a.h + 2 * kLdsPad) * sizeof(float);
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)vcf_forward_kernel,
@@ -679,9 +681,9 @@ hipError_t launch_vcf_backward(const float* x, const float* g, const int64_t* of
                                int64_t batch, int64_t n_samples, const float* env, int64_t env_ld,
                                const float* params, int q, double sr, const double* states,
                                int64_t state_ld, float* g_x, float* g_params, float* g_env,
-                               hipStream_t s) {
+                               const int32_t* order, hipStream_t s) {
   const VcfArgs a = make_args(x, g, offsets, batch, n_samples, env, env_ld, params, q, sr, g_x,
-                              const_cast<double*>(states), state_ld, g_params, g_env);
+                              const_cast<double*>(states), state_ld, g_params, g_env, order);
   const size_t lds = (size_t)2 * (64 * a.h + 2 * kLdsPad) * sizeof(float);
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)vcf_backward_kernel,

@@ -24,7 +24,7 @@ def _sig(L):
     L.synth_fm_sample_params.restype = ctypes.c_int
     L.synth_fm_sample_params.argtypes = [u64, u64, i64, vp, vp, vp]
     L.synth_fm_render.restype = ctypes.c_int
-    L.synth_fm_render.argtypes = [ctypes.POINTER(FmConfig), vp, i64, vp, i64, vp, vp]
+    L.synth_fm_render.argtypes = [ctypes.POINTER(FmConfig), vp, i64, vp, i64, vp, vp, vp]
     return L
 
 
@@ -55,8 +55,11 @@ def fm_sample_params(seed: int, first_g: int = 0, batch: int | None = None,
 
 def fm_render(params: torch.Tensor, nebula, n_samples: int | None = None,
               offsets: torch.Tensor | None = None, sample_rate: float = 44100.0,
-              control_rate: float = 441.0, out: torch.Tensor | None = None) -> torch.Tensor:
-    """Render B FM voices: [B, n_samples], or the packed buffer with offsets."""
+              control_rate: float = 441.0, out: torch.Tensor | None = None,
+              order: torch.Tensor | None = None) -> torch.Tensor:
+    """Render B FM voices: [B, n_samples], or the packed buffer with offsets.
+    `order` (int32 [B], a permutation) is the order in which workgroups take
+    the voices; results do not depend on it."""
     B = params.shape[0]
     tab = np.ascontiguousarray(np.asarray(nebula, dtype=np.float64).reshape(NUM_PARAMS, 4))
     cfg = FmConfig(float(sample_rate), float(control_rate),
@@ -69,6 +72,7 @@ def fm_render(params: torch.Tensor, nebula, n_samples: int | None = None,
         ctypes.byref(cfg), _dev_ptr(params, "params", torch.float32, B * NUM_PARAMS), B,
         _dev_ptr(offsets, "offsets", torch.int64, B + 1) if offsets is not None else None,
         int(n_samples) if offsets is None else 0, _dev_ptr(out, "audio", torch.float32, total),
+        _dev_ptr(order, "order", torch.int32, B) if order is not None else None,
         _stream(params.device)))
     del tab
     if offsets is None:

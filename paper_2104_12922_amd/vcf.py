@@ -26,10 +26,11 @@ def _sig(L):
     L.synth_vcf_state_chunks.restype = i64
     L.synth_vcf_state_chunks.argtypes = [i64, i32]
     L.synth_vcf_lowpass.restype = ctypes.c_int
-    L.synth_vcf_lowpass.argtypes = [vp, vp, i64, i64, i64, vp, i64, vp, i32, f64, vp, vp, i64, vp]
+    L.synth_vcf_lowpass.argtypes = [vp, vp, i64, i64, i64, vp, i64, vp, i32, f64, vp, vp, i64, vp,
+                                    vp]
     L.synth_vcf_lowpass_backward.restype = ctypes.c_int
     L.synth_vcf_lowpass_backward.argtypes = [vp, vp, vp, i64, i64, i64, vp, i64, vp, i32, f64, vp,
-                                             i64, vp, vp, vp, vp]
+                                             i64, vp, vp, vp, vp, vp]
     return L
 
 
@@ -60,10 +61,13 @@ def state_chunks(max_samples: int, period: int = 100) -> int:
 
 def lowpass(x: torch.Tensor, env: torch.Tensor, params: torch.Tensor, period: int = 100,
             sample_rate: float = 44100.0, offsets: torch.Tensor | None = None,
-            max_samples: int | None = None, keep_states: bool = False, out=None):
+            max_samples: int | None = None, keep_states: bool = False, out=None,
+            order: torch.Tensor | None = None):
     """Filter voices: x [B, N] (or packed with offsets), env [B, >= ceil(len /
     period)] float32, params [B, 3] float32 (cutoff, depth, Q).  Returns y
-    (and the chunk states the backward pass needs, with keep_states)."""
+    (and the chunk states the backward pass needs, with keep_states).
+    `order` (int32 [B], a permutation) is the order in which workgroups take
+    the voices; results do not depend on it."""
     B, N, lmax = _shape(x, offsets, max_samples)
     if out is None:
         out = torch.empty_like(x)
@@ -76,15 +80,16 @@ def lowpass(x: torch.Tensor, env: torch.Tensor, params: torch.Tensor, period: in
             _dev_ptr(x, "x", F32), _dev_ptr(offsets, "offsets", torch.int64, B + 1) if offsets is not None else None,
             B, N, lmax, _dev_ptr(env, "env", F32), env.stride(0), _dev_ptr(params, "params", F32, 3 * B),
             int(period), float(sample_rate), _dev_ptr(out, "y", F32),
-            states.data_ptr() if states is not None else None, sld, _stream(x.device)))
+            states.data_ptr() if states is not None else None, sld,
+            _dev_ptr(order, "order", torch.int32, B) if order is not None else None, _stream(x.device)))
     return (out, states) if keep_states else out
 
 
 def lowpass_backward(x, grad_y, env, params, states, period: int = 100,
                      sample_rate: float = 44100.0, offsets=None, max_samples=None,
-                     grad_env: bool = True):
+                     grad_env: bool = True, order: torch.Tensor | None = None):
     """(dL/dx, dL/dparams [B, 3], dL/denv or None) for the forward call that
-    wrote `states` on the same inputs."""
+    wrote `states` on the same inputs; `order` as for lowpass."""
     B, N, lmax = _shape(x, offsets, max_samples)
     gx = torch.empty_like(x)
     gp = torch.empty(B, 3, dtype=F32, device=x.device)
@@ -96,7 +101,8 @@ def lowpass_backward(x, grad_y, env, params, states, period: int = 100,
             B, N, lmax, _dev_ptr(env, "env", F32), env.stride(0), _dev_ptr(params, "params", F32, 3 * B),
             int(period), float(sample_rate), _dev_ptr(states, "states", F64), states.shape[1],
             _dev_ptr(gx, "grad_x", F32), _dev_ptr(gp, "grad_params", F32),
-            _dev_ptr(ge, "grad_env", F32) if ge is not None else None, _stream(x.device)))
+            _dev_ptr(ge, "grad_env", F32) if ge is not None else None,
+            _dev_ptr(order, "order", torch.int32, B) if order is not None else None, _stream(x.device)))
     return gx, gp, ge
 
 

@@ -93,6 +93,9 @@ def test_full_size_sampled(F):
     u = F.fm_sample_params(0, batch=B)
     y = F.fm_render(u, tab, offsets=offs)
     assert torch.isfinite(y).all() and float(y.abs().max()) <= 1.0 + 1e-6
+    # the launch order (longest voices first, as timed) changes no sample
+    order = torch.from_numpy(np.argsort(-lens, kind="stable").astype(np.int32)).cuda()
+    assert torch.equal(F.fm_render(u, tab, offsets=offs, order=order), y)
     uu = u.cpu().numpy().astype(np.float64)
     for b in (0, 1, 2, 12345):
         s, e = int(offs[b]), int(offs[b + 1])

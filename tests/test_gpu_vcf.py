@@ -131,6 +131,14 @@ def test_adjoint_identity_at_full_size(V):
     rhs = float(torch.dot(g.double(), hx.double()))
     assert abs(lhs - rhs) <= 1e-5 * (float(gx.double().abs().dot(dx.double().abs())) + 1.0)
     assert torch.isfinite(gp).all() and torch.isfinite(ge).all()
+    # the launch order (longest voices first, as timed) changes no result
+    order = torch.from_numpy(np.argsort(-lens, kind="stable").astype(np.int32)).cuda()
+    hx2, st2 = V.lowpass(dx, env, params, 100, SR, offsets=offs, max_samples=176400,
+                         keep_states=True, order=order)
+    gx2, gp2, ge2 = V.lowpass_backward(dx, g, env, params, st2, 100, SR, offsets=offs,
+                                       max_samples=176400, order=order)
+    assert torch.equal(hx2, hx)           # (rows of st past a voice's chunks are unwritten)
+    assert torch.equal(gx2, gx) and torch.equal(gp2, gp) and torch.equal(ge2, ge)
     # sampled voices of each length against the oracle (forward)
     for b in (0, 1, 2):
         s, e = int(offs[b]), int(offs[b + 1])
@@ -153,10 +161,10 @@ def test_autograd_function_and_errors(V):
     y = torch.empty_like(X)
     s = torch.cuda.current_stream().cuda_stream
     args = lambda period, env_ld: (X.data_ptr(), None, 2, 1000, 1000, E.data_ptr(), env_ld,
-                                   P.data_ptr(), period, SR, y.data_ptr(), None, 0, s)
+                                   P.data_ptr(), period, SR, y.data_ptr(), None, 0, None, s)
     assert L.synth_vcf_lowpass(*args(3, E.shape[1])) == -4          # period 3: unsupported
     assert L.synth_vcf_lowpass(*args(100, 9)) == -1                 # env rows too short
     assert L.synth_vcf_lowpass(*args(100, E.shape[1])) == 0
     assert L.synth_vcf_lowpass_backward(X.data_ptr(), y.data_ptr(), None, 2, 1000, 1000,
                                         E.data_ptr(), E.shape[1], P.data_ptr(), 100, SR, None, 0,
-                                        y.data_ptr(), P.data_ptr(), None, s) == -1   # no states
+                                        y.data_ptr(), P.data_ptr(), None, None, s) == -1   # no states
