@@ -46,7 +46,6 @@
 namespace synth {
 namespace {
 
-using voice::exp2_f64;
 using voice::kLn2;
 using voice::kTwoPi;
 using voice::sincos_cycles_f64;
@@ -97,8 +96,34 @@ struct CoefGrad {
   double dmdw;               // dw / dm (m: cutoff + depth env), 0 when clamped
 };
 
+// 2^y in float64 without a table lookup (the filter's cutoff is formed once
+// per lane segment, after a load of its control value; a second, dependent
+// load would double the latency): y = n + r with n = rint(y), |r| <= 1/2, and
+// 2^r = exp(z), z = r ln 2, |z| <= 0.347, by its Taylor series to degree 13
+// (truncation below 5e-18 relative).  y is clamped to [-1100, 1023].
+__device__ __forceinline__ double exp2_series_f64(double y) {
+  y = fmin(fmax(y, -1100.0), 1023.0);
+  const double n = rint(y);
+  const double z = (y - n) * kLn2;
+  double p = 1.0 / 6227020800.0;                   // 1 / 13!
+  p = fma(p, z, 1.0 / 479001600.0);
+  p = fma(p, z, 1.0 / 39916800.0);
+  p = fma(p, z, 1.0 / 3628800.0);
+  p = fma(p, z, 1.0 / 362880.0);
+  p = fma(p, z, 1.0 / 40320.0);
+  p = fma(p, z, 1.0 / 5040.0);
+  p = fma(p, z, 1.0 / 720.0);
+  p = fma(p, z, 1.0 / 120.0);
+  p = fma(p, z, 1.0 / 24.0);
+  p = fma(p, z, 1.0 / 6.0);
+  p = fma(p, z, 0.5);
+  p = fma(p, z, 1.0);
+  p = fma(p, z, 1.0);
+  return ldexp(p, (int)n);
+}
+
 __device__ __forceinline__ double vcf_cutoff(double m, double sr, bool& live) {
-  const double f = 440.0 * exp2_f64((m - 69.0) / 12.0);
+  const double f = 440.0 * exp2_series_f64((m - 69.0) / 12.0);
   live = f >= kVcfFMin && f <= kVcfFMaxFrac * sr;
   return fmin(fmax(f, kVcfFMin), kVcfFMaxFrac * sr);
 }
@@ -201,10 +226,11 @@ __device__ __forceinline__ void stage_in(float* lds, const float* __restrict__ s
   const int lane = threadIdx.x, span = 64 * a.h;            // LDS floats of a chunk
   const float* base = src + c0;
   if (vec && (cnt & 3) == 0) {
-    for (int k = 0; 256 * k < span; ++k) {
-      const int p = 256 * k + 4 * lane;
-      if (p < span) lds_dma(base + min(p, cnt - 4), lds + 256 * k, 16);
-    }
+    const int full = span / 256;                              // groups of 64 x 16 bytes
+#pragma unroll 4
+    for (int k = 0; k < full; ++k) lds_dma(base + min(256 * k + 4 * lane, cnt - 4), lds + 256 * k, 16);
+    const int p = 256 * full + 4 * lane;
+    if (p < span) lds_dma(base + min(p, cnt - 4), lds + 256 * full, 16);
   } else {
     for (int k = 0; 64 * k < span; ++k)
       lds_dma(base + min(64 * k + lane, cnt - 1), lds + 64 * k, 4);
@@ -215,20 +241,37 @@ __device__ __forceinline__ void stage_in(float* lds, const float* __restrict__ s
 // (s_waitcnt vmcnt(0); the other counters left free).
 __device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// Store samples [c0, c0 + cnt) of the chunk in LDS to dst (voice base
+// pointer): lane l takes 16-byte groups l, l + 64, ...; with 16-byte aligned
+// samples and cnt a multiple of 4, batches of four groups' LDS reads are
+// issued before their stores, else 4-byte stores.
+constexpr int kOutBatch = 4;
+
 __device__ __forceinline__ void stage_out(const float* lds, float* __restrict__ dst, int64_t c0,
                                           int cnt, bool vec) {
   const int lane = threadIdx.x;
   float* base = dst + c0;
+  if (vec && (cnt & 3) == 0) {
+    int p0 = 0;
+    for (; p0 + 256 * kOutBatch <= cnt; p0 += 256 * kOutBatch) {
+      float4 v[kOutBatch];
+#pragma unroll
+      for (int k = 0; k < kOutBatch; ++k)
+        v[k] = *reinterpret_cast<const float4*>(lds + p0 + 256 * k + 4 * lane);
+#pragma unroll
+      for (int k = 0; k < kOutBatch; ++k)
+        *reinterpret_cast<float4*>(base + p0 + 256 * k + 4 * lane) = v[k];
+    }
+    for (int p = p0 + 4 * lane; p < cnt; p += 256)
+      *reinterpret_cast<float4*>(base + p) = *reinterpret_cast<const float4*>(lds + p);
+    return;
+  }
   for (int p = 4 * lane; p < cnt; p += 256) {
     const float4 v = *reinterpret_cast<const float4*>(lds + p);
-    if (vec && p + 4 <= cnt) {
-      *reinterpret_cast<float4*>(base + p) = v;
-    } else {
-      base[p] = v.x;
-      if (p + 1 < cnt) base[p + 1] = v.y;
-      if (p + 2 < cnt) base[p + 2] = v.z;
-      if (p + 3 < cnt) base[p + 3] = v.w;
-    }
+    base[p] = v.x;
+    if (p + 1 < cnt) base[p + 1] = v.y;
+    if (p + 2 < cnt) base[p + 2] = v.z;
+    if (p + 3 < cnt) base[p + 3] = v.w;
   }
 }
 
@@ -371,7 +414,7 @@ __device__ __forceinline__ void forward_entry_states(const float* xa, const VcfA
 }
 
 __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
-  extern __shared__ float lds_raw[];          // pad, 64 h, pad
+  extern __shared__ float lds_raw[];          // pad, 64 h, pad, 64 control values
   float* lds = lds_raw + kLdsPad;
   const int64_t b = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
   const int lane = threadIdx.x;
@@ -384,18 +427,17 @@ __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
   const double cutoff = a.params[b * 3], depth = a.params[b * 3 + 1], Q = a.params[b * 3 + 2];
   const int64_t J = (L + a.h - 1) / a.h;          // lane segments of the voice
   const int64_t chunks = (J + 63) / 64;
-  // coefficients of lane segment 64 c + lane (zero past the voice)
-  auto seg_coef = [&](int64_t c) {
-    const int64_t j = c * 64 + lane;
-    Coef k = {0.0, 0.0, 0.0, 0.0};
-    if (j < J) k = vcf_coef(a, cutoff, depth, Q, (double)a.env[b * a.env_ld + j / a.S]);
-    return k;
+  // control values of chunk c's lane segments into lds_env[lane] (loaded
+  // with the chunk's samples, so the coefficients wait for no other load)
+  float* lds_env = lds + 64 * a.h + kLdsPad;
+  auto stage_env = [&](int64_t c) {
+    const int64_t j = min(c * 64 + lane, J - 1);
+    lds_dma(a.env + b * a.env_ld + j / a.S, lds_env, 4);
   };
-  // Per chunk: wait for its samples, run it, compute the next chunk's
-  // coefficients (their loads then wait for no store), store it, and start
-  // the next chunk's loads.
+  // Per chunk: wait for its samples and control values, form the
+  // coefficients, run the chunk, store it, and start the next chunk's loads.
   double v0 = 0.0, v1 = 0.0, xh1 = 0.0, xh2 = 0.0;
-  Coef k = seg_coef(0);
+  stage_env(0);
   stage_in(lds, xv, 0, (int)min((int64_t)64 * a.h, L), a, vec);
   for (int64_t c = 0; c < chunks; ++c) {
     const int64_t c0 = c * 64 * a.h;
@@ -408,6 +450,8 @@ __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
     const int len = j < J ? (int)min((int64_t)a.h, L - j * a.h) : 0;
     stage_wait();
     __syncthreads();
+    Coef k = {0.0, 0.0, 0.0, 0.0};
+    if (len > 0) k = vcf_coef(a, cutoff, depth, Q, (double)lds_env[lane]);
     double in0, in1, e0, e1;
     forward_entry_states(lds, a, k, len, xh1, xh2, v0, v1, in0, in1, e0, e1);
     // x history for this lane's segment and for the next chunk, read before
@@ -426,13 +470,13 @@ __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
       xs[i] = (float)y0;
       x2 = x1; x1 = x0; y2 = y1; y1 = y0;
     });
-    const bool more = c + 1 < chunks;
-    const Coef kn = more ? seg_coef(c + 1) : k;
     __syncthreads();
     stage_out(lds, yv, c0, cnt, vec);
     __syncthreads();
-    if (more) stage_in(lds, xv, c0 + 64 * a.h, (int)min((int64_t)64 * a.h, L - c0 - 64 * a.h), a, vec);
-    k = kn;
+    if (c + 1 < chunks) {
+      stage_env(c + 1);
+      stage_in(lds, xv, c0 + 64 * a.h, (int)min((int64_t)64 * a.h, L - c0 - 64 * a.h), a, vec);
+    }
     v0 = e0;
     v1 = e1;
     xh1 = nxh1;
@@ -667,7 +711,7 @@ hipError_t launch_vcf_forward(const float* x, const int64_t* offsets, int64_t ba
                               int64_t state_ld, const int32_t* order, hipStream_t s) {
   const VcfArgs a = make_args(x, nullptr, offsets, batch, n_samples, env, env_ld, params, q, sr, y,
                               states, state_ld, nullptr, nullptr, order);
-  const size_t lds = (size_t)(64 * a.h + 2 * kLdsPad) * sizeof(float);
+  const size_t lds = (size_t)(64 * a.h + 2 * kLdsPad + 64) * sizeof(float);
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)vcf_forward_kernel,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
