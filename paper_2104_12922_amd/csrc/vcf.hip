@@ -41,6 +41,8 @@
 // again from the true entry states (lambda over g in LDS), then a forward
 // sweep per period rebuilds y, sums the coefficient gradients and forms
 // dL/dx over x in LDS.
+#include <type_traits>
+
 #include "voice_device.h"
 
 namespace synth {
@@ -561,18 +563,38 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) vc
     // forward entry states (y[s-1], y[s-2]) of every period
     double fin0, fin1, fe0, fe1;
     forward_entry_states(xa, a, k, len, xh1, xh2, v0, v1, fin0, fin1, fe0, fe1);
-    // lambda over the period from a zero state (samples last to first; the
-    // last two use the next period's a1 / a2), and the period's affine map
-    // (lambda[e], lambda[e+1]) -> (lambda[s], lambda[s+1])
+    // lambda over the segment, samples last to first, from the state (l1,
+    // l2) = (lambda[e], lambda[e+1]) after it: the last sample takes the
+    // next segment's a1 and a2, the one before it the next segment's a2, the
+    // rest this segment's; with `store`, lambda is written over g.
     float* gs = ga + lane * a.h;
+    auto lambda_run = [&](double& l1, double& l2, auto store) {
+      int n = len;
+      if (n >= 1) {
+        const double l0 = fma(-kn.a1, l1, fma(-kn.a2, l2, (double)gs[n - 1]));
+        if (store) gs[n - 1] = (float)l0;
+        l2 = l1;
+        l1 = l0;
+        --n;
+      }
+      if (n >= 1) {
+        const double l0 = fma(-k.a1, l1, fma(-kn.a2, l2, (double)gs[n - 1]));
+        if (store) gs[n - 1] = (float)l0;
+        l2 = l1;
+        l1 = l0;
+        --n;
+      }
+      sweep_rev(gs, n, [&](int i, float gf) {
+        const double l0 = fma(-k.a1, l1, fma(-k.a2, l2, (double)gf));
+        if (store) gs[i] = (float)l0;
+        l2 = l1;
+        l1 = l0;
+      });
+    };
+    // from a zero state: the segment's affine map (lambda[e], lambda[e+1])
+    // -> (lambda[s], lambda[s+1])
     double l1 = 0.0, l2 = 0.0;
-    sweep_rev(gs, len, [&](int i, float gf) {
-      const double a1 = i == len - 1 ? kn.a1 : k.a1;
-      const double a2 = i >= len - 2 ? kn.a2 : k.a2;
-      const double l0 = fma(-a1, l1, fma(-a2, l2, (double)gf));
-      l2 = l1;
-      l1 = l0;
-    });
+    lambda_run(l1, l2, std::false_type{});
     Mat2 M = {1.0, 0.0, 0.0, 1.0};
     double z0 = 0.0, z1 = 0.0;
     if (len > 0) {
@@ -600,14 +622,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) vc
     // lambda from the true entry state, written over g
     l1 = in0;
     l2 = in1;
-    sweep_rev(gs, len, [&](int i, float gf) {
-      const double a1 = i == len - 1 ? kn.a1 : k.a1;
-      const double a2 = i >= len - 2 ? kn.a2 : k.a2;
-      const double l0 = fma(-a1, l1, fma(-a2, l2, (double)gf));
-      gs[i] = (float)l0;
-      l2 = l1;
-      l1 = l0;
-    });
+    lambda_run(l1, l2, std::true_type{});
     // x history of this period, read before any lane writes dL/dx over x
     double x1 = lane ? (double)xa[lane * a.h - 1] : xh1;
     double x2 = lane ? (double)xa[lane * a.h - 2] : xh2;
@@ -617,29 +632,35 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) vc
     float* xs = xa + lane * a.h;
     double y1 = fin0, y2 = fin1;
     double lm1 = 0.0, lm2 = 0.0;               // lambda[n-1], lambda[n-2]
-    double Gb0 = 0.0, Gb1 = 0.0, Gb2 = 0.0, Ga1 = 0.0, Ga2 = 0.0;
-    sweep2(xs, gs, len, [&](int i, float xf, float lf) {
+    // sums of lambda[n] (x[n] + x[n-2]) (b0 = b2), lambda[n] x[n-1],
+    // lambda[n] y[n-1], lambda[n] y[n-2]
+    double Gb02 = 0.0, Gb1 = 0.0, Ga1 = 0.0, Ga2 = 0.0;
+    auto fwd_step = [&](int i, float xf, float lf, auto write) {
       const double x0 = (double)xf;
       const double l0 = (double)lf;
-      Gb0 = fma(l0, x0, Gb0);
+      const double x02 = x0 + x2;
+      Gb02 = fma(l0, x02, Gb02);
       Gb1 = fma(l0, x1, Gb1);
-      Gb2 = fma(l0, x2, Gb2);
-      Ga1 = fma(-l0, y1, Ga1);
-      Ga2 = fma(-l0, y2, Ga2);
-      const double ff = fma(k.b0, x0 + x2, k.b1 * x1);
-      const double y0 = fma(-k.a1, y1, fma(-k.a2, y2, ff));
-      if (i >= 2) xs[i - 2] = (float)fma(k.b0, lm2 + l0, k.b1 * lm1);
+      Ga1 = fma(l0, y1, Ga1);
+      Ga2 = fma(l0, y2, Ga2);
+      const double y0 = fma(-k.a1, y1, fma(-k.a2, y2, fma(k.b0, x02, k.b1 * x1)));
+      if (write) xs[i - 2] = (float)fma(k.b0, lm2 + l0, k.b1 * lm1);
       x2 = x1; x1 = x0; y2 = y1; y1 = y0;
       lm2 = lm1; lm1 = l0;
-    });
+    };
+    // the first two samples complete no dL/dx of this segment
+    if (len >= 1) fwd_step(0, xs[0], gs[0], std::false_type{});
+    if (len >= 2) fwd_step(1, xs[1], gs[1], std::false_type{});
+    if (len > 2)
+      sweep2(xs + 2, gs + 2, len - 2, [&](int i, float xf, float lf) {
+        fwd_step(i + 2, xf, lf, std::true_type{});
+      });
     if (len >= 2) xs[len - 2] = (float)fma(k.b0, lm2, fma(k.b1, lm1, kn.b0 * in0));
     if (len >= 1) xs[len - 1] = (float)fma(k.b0, lm1, fma(kn.b1, in0, kn.b0 * in1));
     double gm = 0.0;
     if (len > 0) {
-      const double Gw = Gb0 * kg.dw[0] + Gb1 * kg.dw[1] + Gb2 * kg.dw[0] + Ga1 * kg.dw[2] +
-                        Ga2 * kg.dw[3];
-      const double Gq = Gb0 * kg.dq[0] + Gb1 * kg.dq[1] + Gb2 * kg.dq[0] + Ga1 * kg.dq[2] +
-                        Ga2 * kg.dq[3];
+      const double Gw = Gb02 * kg.dw[0] + Gb1 * kg.dw[1] - Ga1 * kg.dw[2] - Ga2 * kg.dw[3];
+      const double Gq = Gb02 * kg.dq[0] + Gb1 * kg.dq[1] - Ga1 * kg.dq[2] - Ga2 * kg.dq[3];
       gm = Gw * kg.dmdw;
       gc += gm;
       gd = fma(gm, envj, gd);
