@@ -99,10 +99,15 @@ def copy_only(nbytes):
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
-    for _ in range(3):
+    ev = _events(3)
+    for a, b in ev:
+        a.record()
         dst.copy_(src)
+        b.record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev[1:]]))
+    print(json.dumps({"copy_bytes": nbytes, "launches": 3, "ms_per_copy": ms,
+                      "read_plus_write_GBps": 2.0 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def cpu_baseline(wl, min_seconds):
