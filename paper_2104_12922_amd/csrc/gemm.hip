@@ -479,12 +479,37 @@ bool big_tiles(const GemmArgs& g) {
 
 // Sum of the split-K partials in part order, then the epilogue.
 __global__ void __launch_bounds__(256) gemm_split_reduce_kernel(GemmArgs g) {
+  // One workgroup per output row (rows strided over the grid): the row's
+  // columns are read from each part as 16-byte vectors when N is a multiple
+  // of 4 and the workspace 16-byte aligned, else one by one; no index
+  // division.
   const int64_t n = g.M * g.N;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    float x = 0.0f;
-    for (int p = 0; p < g.split; ++p) x += g.partial[p * n + i];
-    epi_store(g, i / g.N, i % g.N, x * g.alpha);
+  const int t = threadIdx.x;
+  const bool vec = (g.N & 3) == 0 && (reinterpret_cast<uintptr_t>(g.partial) & 15u) == 0;
+  for (int64_t row = blockIdx.x; row < g.M; row += gridDim.x) {
+    const float* src = g.partial + row * g.N;
+    if (vec) {
+      for (int64_t c4 = t; 4 * c4 < g.N; c4 += 256) {
+        float4 x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int p = 0; p < g.split; ++p) {
+          const float4 v = *reinterpret_cast<const float4*>(src + p * n + 4 * c4);
+          x.x += v.x;
+          x.y += v.y;
+          x.z += v.z;
+          x.w += v.w;
+        }
+        epi_store(g, row, 4 * c4, x.x * g.alpha);
+        epi_store(g, row, 4 * c4 + 1, x.y * g.alpha);
+        epi_store(g, row, 4 * c4 + 2, x.z * g.alpha);
+        epi_store(g, row, 4 * c4 + 3, x.w * g.alpha);
+      }
+    } else {
+      for (int64_t col = t; col < g.N; col += 256) {
+        float x = 0.0f;
+        for (int p = 0; p < g.split; ++p) x += src[p * n + col];
+        epi_store(g, row, col, x * g.alpha);
+      }
+    }
   }
 }
 
@@ -553,8 +578,7 @@ hipError_t launch_gemm_bf16(const GemmArgs& g, int a_op, int b_op, hipStream_t s
                           : launch_b<kOpRowMajorMN>(g, b_op, grid, s);
   }
   if (e != hipSuccess || split == 1) return e;
-  int64_t blocks = (g.M * g.N + 255) / 256;
-  if (blocks > 65535 * 4) blocks = 65535 * 4;
+  const int64_t blocks = g.M < 65535 ? g.M : 65535;
   hipLaunchKernelGGL(gemm_split_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g);
   return hipGetLastError();
 }
