@@ -386,10 +386,26 @@ def train_ids(first: int, count: int, device="cuda") -> torch.Tensor:
     return (i // TRAIN_BLOCK) * (TRAIN_BLOCK + TEST_BLOCK) + i % TRAIN_BLOCK
 
 
+_LENGTHS = {}
+
+
+def _lengths_tensor(lengths_s, sample_rate, device) -> torch.Tensor:
+    """Voice lengths in samples (int64, on `device`), made once per (lengths,
+    rate, device): building a device tensor from a host list is a blocking
+    copy from pageable memory, which waits for the work queued on every
+    stream and so would stall a loop that overlaps streams."""
+    key = (tuple(float(x) for x in lengths_s), float(sample_rate), str(device))
+    t = _LENGTHS.get(key)
+    if t is None:
+        t = torch.tensor([int(round(x * sample_rate)) for x in lengths_s], dtype=torch.int64,
+                         device=device)
+        _LENGTHS[key] = t
+    return t
+
+
 def ragged_offsets(ids: torch.Tensor, lengths_s=(1, 2, 3, 4), sample_rate=44100.0) -> torch.Tensor:
     """offsets [B + 1] of voices rendered lengths_s[g mod len] seconds long."""
-    per = torch.tensor([int(round(x * sample_rate)) for x in lengths_s], dtype=torch.int64,
-                       device=ids.device)
+    per = _lengths_tensor(lengths_s, sample_rate, ids.device)
     n = per[ids % len(lengths_s)]
     return torch.cat([torch.zeros(1, dtype=torch.int64, device=ids.device), torch.cumsum(n, 0)])
 
@@ -421,8 +437,7 @@ def render_batch(seed, ids, nebula_table, lengths_s=(1, 2, 3, 4), tune: bool = T
     from . import synth_render, synth_sample_params
     # longest voices first: workgroups are dispatched in voice order, so the
     # long voices start early and the short ones fill the tail of the launch
-    per = torch.tensor([int(round(x * 44100.0)) for x in lengths_s], dtype=torch.int64,
-                       device=ids.device)
+    per = _lengths_tensor(lengths_s, 44100.0, ids.device)
     ids = ids[torch.argsort(-per[ids % len(lengths_s)], stable=True)]
     offs = ragged_offsets(ids, lengths_s)
     u = synth_sample_params(seed, voice_ids=ids)
@@ -474,8 +489,7 @@ def train_pipelined(net: "MLP", lm: LogMel, nebula_table, mean, inv_std, steps: 
     main = torch.cuda.current_stream()
     side = torch.cuda.Stream()
     G = max(1, int(group))
-    per = torch.tensor([int(round(x * 44100.0)) for x in lengths_s], dtype=torch.int64,
-                       device="cuda")
+    per = _lengths_tensor(lengths_s, 44100.0, torch.device("cuda"))
     xb = [torch.empty(G * batch, MEL_FEATURES, dtype=BF16, device="cuda") for _ in range(2)]
     ready = [torch.cuda.Event(), torch.cuda.Event()]
     done = [torch.cuda.Event(), torch.cuda.Event()]

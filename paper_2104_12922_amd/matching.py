@@ -214,8 +214,10 @@ class MatchService:
                 batch = self.admit(queue, max(self.budget - used, per))
                 n = batch[0].audio.numel()
                 targets = torch.stack([r.audio for r in batch]).contiguous()
-                ids = torch.tensor([r.voice_id for r in batch], dtype=torch.int64,
-                                   device=targets.device)
+                # pinned host memory and an asynchronous copy: a copy from
+                # pageable memory would wait for the batches in flight
+                ids = torch.tensor([r.voice_id for r in batch], dtype=torch.int64).pin_memory()
+                ids = ids.to(targets.device, non_blocking=True)
                 u0 = self.initial_estimate(targets, ids).clone()
                 k = free.pop(0)
                 stream = streams[k]
