@@ -110,6 +110,33 @@ def test_backward_matches_oracle(V, B, N, period):
     assert np.all(np.abs(ge[:, :J] - re[:, :J]) <= 1e-5 * np.abs(re[:, :J]) + 1e-7 * es)
 
 
+def test_backward_ragged_short_segment_tails(V):
+    """Ragged voices whose last lane segment (50 samples at period 100) holds
+    1, 2 or 3 samples, or a few whole segments: the adjoint's peeled first
+    and last samples of a segment, against the oracle voice by voice."""
+    lens = [1, 2, 3, 51, 52, 53, 101, 150, 3201, 3202, 6403]
+    B, N = len(lens), max(lens)
+    x, env, params = _inputs(B, N, 17)
+    w = np.random.default_rng(18).standard_normal((B, N)).astype(np.float32)
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    xp = torch.from_numpy(np.concatenate([x[b, :l] for b, l in enumerate(lens)])).cuda()
+    wp = torch.from_numpy(np.concatenate([w[b, :l] for b, l in enumerate(lens)])).cuda()
+    E, P = torch.from_numpy(env).cuda(), torch.from_numpy(params).cuda()
+    O = torch.from_numpy(offs).cuda()
+    _, st = V.lowpass(xp, E, P, 100, SR, offsets=O, max_samples=N, keep_states=True)
+    gx, gp, ge = V.lowpass_backward(xp, wp, E, P, st, 100, SR, offsets=O, max_samples=N)
+    gx, gp, ge = gx.cpu().numpy(), gp.cpu().numpy(), ge.cpu().numpy()
+    for b, l in enumerate(lens):
+        rx, rp, re = _oracle_grads(x[b:b + 1, :l], env[b:b + 1], params[b:b + 1], w[b:b + 1, :l])
+        got = gx[offs[b]:offs[b + 1]]
+        scale = np.max(np.abs(rx))
+        assert np.all(np.abs(got - rx[0]) <= 4 * U * np.abs(rx[0]) + 1e-6 * scale), (b, l)
+        assert np.all(np.abs(gp[b] - rp[0]) <= 1e-5 * np.abs(rp[0]) + 1e-7 * np.max(np.abs(rp))), (b, l)
+        J = (l + 99) // 100
+        es = np.max(np.abs(re[0, :J]))
+        assert np.all(np.abs(ge[b, :J] - re[0, :J]) <= 1e-5 * np.abs(re[0, :J]) + 1e-7 * es), (b, l)
+
+
 def test_adjoint_identity_at_full_size(V):
     """<dL/dx, dx> = <g, H dx> for the linear map H = lowpass(., env, params)
     on the ragged 16384-voice batch (1, 2, 4 s)."""
