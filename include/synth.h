@@ -344,10 +344,12 @@ int synth_standardize(const float* x, const float* mean, const float* inv_std, i
 /* y (bf16) = round-to-nearest-even(x), n elements. */
 int synth_to_bf16(const float* x, void* y, int64_t n, void* stream);
 
-/* Bytes of the optional MLP workspace (0 when no GEMM of this shape splits
- * its reduction).  With it, a GEMM whose output has too few 128 x 128 tiles to
- * fill the chip splits K over several workgroups, writes float32 partial sums
- * there and adds them in a fixed order, so results stay deterministic. */
+/* Bytes of the optional MLP workspace (0 for invalid sizes).  With it, a
+ * GEMM whose output has too few tiles to fill the chip splits K over
+ * several workgroups, writes float32 partial sums there and adds them in a
+ * fixed order, and the backward's bias gradients are summed over row
+ * slices there (float64) and then over the slices in order: results stay
+ * deterministic.  Without it (NULL) the same sums run unsplit. */
 size_t synth_mlp_workspace(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out);
 
 /* MLP forward, d_in -> d_h -> d_h -> d_out: h1 = gelu(x W1 + b1),

@@ -882,7 +882,8 @@ size_t synth_mlp_workspace(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_o
   if (batch <= 0 || d_in <= 0 || d_h <= 0 || d_out <= 0) return 0;
   int64_t sh[8][3];
   mlp_shapes(batch, d_in, d_h, d_out, sh);
-  size_t b = 0;
+  // the bias gradients' column sums use it too (between the GEMMs)
+  size_t b = synth::colsum_ws_bytes(batch, d_h > d_out ? d_h : d_out);
   for (auto& m : sh) {
     const size_t x = synth::gemm_split_bytes(m[0], m[1], synth::gemm_split_for(m[0], m[1], m[2]));
     b = x > b ? x : b;
@@ -939,7 +940,7 @@ int synth_mlp_backward(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out, 
   g.M = d_out; g.N = d_h; g.K = batch; g.A = dz3; g.lda = d_out; g.B = h2; g.ldb = d_h;
   g.C = gw3t; g.ldc = d_h; g.c_bf16 = 0;
   if ((e = gemm_maybe_split(g, kOpRowMajorMN, kOpRowMajorMN, workspace, s)) != hipSuccess) return SYNTH_EDEVICE;
-  if ((e = synth::launch_colsum(dz3, 1, batch, d_out, d_out, gb3, nullptr, s)) != hipSuccess) return SYNTH_EDEVICE;
+  if ((e = synth::launch_colsum_bf16_ws(dz3, batch, d_out, d_out, gb3, workspace, workspace_bytes, s)) != hipSuccess) return SYNTH_EDEVICE;
   // dh2 = (dz3 W3^T^T) * gelu'(h2pre): A = dz3 [batch][d_out], B[k][n] = W3^T[k][n]
   g = {}; g.alpha = 1.0f;
   g.M = batch; g.N = d_h; g.K = d_out; g.A = dz3; g.lda = d_out; g.B = w3t; g.ldb = d_h;
@@ -950,7 +951,7 @@ int synth_mlp_backward(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out, 
   g.M = d_h; g.N = d_h; g.K = batch; g.A = dh2; g.lda = d_h; g.B = h1; g.ldb = d_h;
   g.C = gw2t; g.ldc = d_h;
   if ((e = gemm_maybe_split(g, kOpRowMajorMN, kOpRowMajorMN, workspace, s)) != hipSuccess) return SYNTH_EDEVICE;
-  if ((e = synth::launch_colsum(dh2, 1, batch, d_h, d_h, gb2, nullptr, s)) != hipSuccess) return SYNTH_EDEVICE;
+  if ((e = synth::launch_colsum_bf16_ws(dh2, batch, d_h, d_h, gb2, workspace, workspace_bytes, s)) != hipSuccess) return SYNTH_EDEVICE;
   // dh1 = (dh2 W2^T^T) * gelu'(h1pre)
   g = {}; g.alpha = 1.0f;
   g.M = batch; g.N = d_h; g.K = d_h; g.A = dh2; g.lda = d_h; g.B = w2t; g.ldb = d_h;
@@ -961,7 +962,7 @@ int synth_mlp_backward(int64_t batch, int64_t d_in, int64_t d_h, int64_t d_out, 
   g.M = d_h; g.N = d_in; g.K = batch; g.A = dh1; g.lda = d_h; g.B = x; g.ldb = d_in;
   g.C = gw1t; g.ldc = d_in;
   if ((e = gemm_maybe_split(g, kOpRowMajorMN, kOpRowMajorMN, workspace, s)) != hipSuccess) return SYNTH_EDEVICE;
-  return to_status(synth::launch_colsum(dh1, 1, batch, d_h, d_h, gb1, nullptr, s));
+  return to_status(synth::launch_colsum_bf16_ws(dh1, batch, d_h, d_h, gb1, workspace, workspace_bytes, s));
 }
 
 int synth_logit_init(const float* u, float* z, float* u_out, int64_t n, float eps, void* stream) {

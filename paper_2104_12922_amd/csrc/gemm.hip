@@ -491,7 +491,20 @@ __global__ void __launch_bounds__(256) gemm_split_reduce_kernel(GemmArgs g) {
     if (vec) {
       for (int64_t c4 = t; 4 * c4 < g.N; c4 += 256) {
         float4 x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        for (int p = 0; p < g.split; ++p) {
+        int p = 0;
+        for (; p + 4 <= g.split; p += 4) {     // four parts' loads in flight, added in order
+          float4 v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const float4*>(src + (p + u) * n + 4 * c4);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            x.x += v[u].x;
+            x.y += v[u].y;
+            x.z += v[u].z;
+            x.w += v[u].w;
+          }
+        }
+        for (; p < g.split; ++p) {
           const float4 v = *reinterpret_cast<const float4*>(src + p * n + 4 * c4);
           x.x += v.x;
           x.y += v.y;
@@ -506,7 +519,15 @@ __global__ void __launch_bounds__(256) gemm_split_reduce_kernel(GemmArgs g) {
     } else {
       for (int64_t col = t; col < g.N; col += 256) {
         float x = 0.0f;
-        for (int p = 0; p < g.split; ++p) x += src[p * n + col];
+        int p = 0;
+        for (; p + 4 <= g.split; p += 4) {
+          float v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[u] = src[(p + u) * n + col];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) x += v[u];
+        }
+        for (; p < g.split; ++p) x += src[p * n + col];
         epi_store(g, row, col, x * g.alpha);
       }
     }

@@ -66,6 +66,76 @@ __global__ void __launch_bounds__(1024) colsum_kernel(const void* __restrict__ x
   }
 }
 
+// Column sums of a bf16 matrix in two passes, for the bias gradients:
+// workgroup (column tile t, row slice r) of 4 wavefronts sums rows
+// [r R0, (r + 1) R0) of 128 columns (each lane two adjacent columns, read as
+// one 4-byte word, so a wavefront reads 256 contiguous bytes of a row;
+// wavefront w takes rows w, w + 4, ... of the slice), adds the four
+// wavefronts' sums in a fixed order and writes ws[r][col] (float64); the
+// second pass adds the slices in order.  Deterministic.
+constexpr int kColTile = 128, kColWaves = 4;
+
+__global__ void __launch_bounds__(64 * kColWaves) colsum_part_kernel(const uint16_t* __restrict__ x,
+                                                                     int64_t rows, int64_t cols,
+                                                                     int64_t ld, int64_t r0n,
+                                                                     double* __restrict__ ws) {
+  __shared__ double red[kColWaves][kColTile];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t c0 = blockIdx.x * (int64_t)kColTile + 2 * lane;
+  const int64_t rb = blockIdx.y * r0n, re = min(rows, rb + r0n);
+  double s0 = 0.0, s1 = 0.0;
+  if (c0 + 1 < cols) {
+    // eight rows' loads in flight before their adds (in row order)
+    int64_t r = rb + w;
+    for (; r + 7 * kColWaves < re; r += 8 * kColWaves) {
+      uint32_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const uint32_t*>(x + (r + u * kColWaves) * ld + c0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        s0 += (double)bf2f((uint16_t)(v[u] & 0xFFFFu));
+        s1 += (double)bf2f((uint16_t)(v[u] >> 16));
+      }
+    }
+    for (; r < re; r += kColWaves) {
+      const uint32_t v = *reinterpret_cast<const uint32_t*>(x + r * ld + c0);
+      s0 += (double)bf2f((uint16_t)(v & 0xFFFFu));
+      s1 += (double)bf2f((uint16_t)(v >> 16));
+    }
+  } else if (c0 < cols) {
+    for (int64_t r = rb + w; r < re; r += kColWaves) s0 += (double)bf2f(x[r * ld + c0]);
+  }
+  red[w][2 * lane] = s0;
+  red[w][2 * lane + 1] = s1;
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int cc = 2 * lane + e;
+      const double t = ((red[0][cc] + red[1][cc]) + red[2][cc]) + red[3][cc];
+      if (c0 + e < cols) ws[blockIdx.y * cols + c0 + e] = t;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) colsum_final_kernel(const double* __restrict__ ws,
+                                                           int64_t slices, int64_t cols,
+                                                           float* __restrict__ sum) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double s = 0.0;
+  int64_t r = 0;
+  for (; r + 8 <= slices; r += 8) {      // eight slices' loads in flight, added in order
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = ws[(r + u) * cols + c];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; r < slices; ++r) s += ws[r * cols + c];
+  sum[c] = (float)s;
+}
+
 // Per-column mean and 1 / sqrt(max(var, min_var)) (population variance), two
 // float64 passes over the rows.
 __global__ void __launch_bounds__(1024) feature_stats_kernel(const float* __restrict__ x,
@@ -223,6 +293,31 @@ hipError_t launch_colsum(const void* x, int x_bf16, int64_t rows, int64_t cols, 
   if (cols == 0) return hipSuccess;
   hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((cols + kRedCols - 1) / kRedCols)), dim3(1024),
                      0, s, x, x_bf16, rows, cols, ld, sum, sumsq);
+  return hipGetLastError();
+}
+
+size_t colsum_ws_bytes(int64_t rows, int64_t cols) {
+  const int64_t slices = rows < 32 ? rows : 32;
+  return (size_t)(slices > 0 ? slices : 1) * (size_t)cols * sizeof(double);
+}
+
+hipError_t launch_colsum_bf16_ws(const void* x, int64_t rows, int64_t cols, int64_t ld, float* sum,
+                                 void* ws, size_t ws_bytes, hipStream_t s) {
+  if (cols == 0) return hipSuccess;
+  // two-byte elements read in pairs: rows must start 4-byte aligned
+  const bool pairs = (ld % 2 == 0) && (reinterpret_cast<uintptr_t>(x) & 3u) == 0;
+  if (!ws || ws_bytes < colsum_ws_bytes(rows, cols) || rows < 1 || !pairs ||
+      (reinterpret_cast<uintptr_t>(ws) & 7u) != 0)
+    return launch_colsum(x, 1, rows, cols, ld, sum, nullptr, s);
+  const int64_t slices = rows < 32 ? rows : 32;
+  const int64_t r0n = (rows + slices - 1) / slices;
+  const dim3 grid((unsigned)((cols + kColTile - 1) / kColTile), (unsigned)slices);
+  hipLaunchKernelGGL(colsum_part_kernel, grid, dim3(64 * kColWaves), 0, s,
+                     static_cast<const uint16_t*>(x), rows, cols, ld, r0n, static_cast<double*>(ws));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const double*>(ws), slices, cols, sum);
   return hipGetLastError();
 }
 

@@ -121,6 +121,12 @@ hipError_t launch_vcf_backward(const float* x, const float* g, const int64_t* of
                                const int32_t* order, hipStream_t s);
 hipError_t launch_colsum(const void* x, int x_bf16, int64_t rows, int64_t cols, int64_t ld,
                          float* sum, float* sumsq, hipStream_t s);
+// Column sums of a bf16 matrix (bias gradients) in two deterministic passes
+// through a float64 workspace of colsum_ws_bytes(rows, cols) bytes (falls
+// back to launch_colsum when the workspace is missing or too small).
+size_t colsum_ws_bytes(int64_t rows, int64_t cols);
+hipError_t launch_colsum_bf16_ws(const void* x, int64_t rows, int64_t cols, int64_t ld, float* sum,
+                                 void* ws, size_t ws_bytes, hipStream_t s);
 hipError_t launch_feature_stats(const float* x, int64_t rows, int64_t cols, float min_var,
                                 float* mean, float* inv_std, hipStream_t s);
 hipError_t launch_standardize(const float* x, const float* mean, const float* inv_std,
