@@ -16,9 +16,10 @@
 // [1, 0]], z its zero-state response.  Each period is cut into S lane
 // segments of h = q / S samples (S = 4 or 2 when that leaves h >= 32), and
 // one wavefront takes one voice, 64 segments (a chunk) at a time: the
-// chunk's samples are staged in LDS as they lie in HBM (16-byte writes;
-// segment s at s h: an even h gives the lanes' sweep reads bank conflicts,
-// 2-way for h = 50, cheaper than a padded layout's index arithmetic), lane s
+// chunk's samples are staged in LDS as they lie in HBM by direct
+// global-to-LDS loads (segment s at s h: an even h gives the lanes' sweep
+// reads bank conflicts, 2-way for h = 50, cheaper than a padded layout's
+// index arithmetic), lane s
 // runs segment s from a zero state (z) and raises A to its length by
 // squaring, an inclusive scan of the affine maps (M, z) over the lanes gives
 // every segment's entry state from the chunk's, and each lane runs its
