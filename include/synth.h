@@ -498,7 +498,9 @@ int synth_mmd_l1(const float* X, int64_t n, const float* Y, int64_t m, int64_t d
  *   order       NULL, or dev int32 [batch], a permutation of 0 .. batch - 1:
  *               the order in which workgroups take the voices (for ragged
  *               batches, longest first shortens the tail); results do not
- *               depend on it.  batch <= 2^31 - 1 with an order.
+ *               depend on it.  batch <= 2^31 - 1 with an order; an entry
+ *               outside 0 .. batch - 1 is skipped (that workgroup does
+ *               nothing).
  * SYNTH_EINVAL on a bad size, stride or NULL pointer.
  * ------------------------------------------------------------------------- */
 
@@ -558,7 +560,8 @@ int synth_fm_sample_params(uint64_t seed, uint64_t first_g, int64_t batch,
  * curve minimum <= 0), size or pointer; SYNTH_EUNSUPPORTED for rates whose
  * ratio is not a multiple of 4 in 4 .. 1024.  order: NULL, or dev int32
  * [batch], a permutation of 0 .. batch - 1, the order in which workgroups
- * take the voices (results do not depend on it). */
+ * take the voices (results do not depend on it; an entry outside
+ * 0 .. batch - 1 is skipped). */
 int synth_fm_render(const synth_fm_config* cfg, const float* params, int64_t batch,
                     const int64_t* offsets, int64_t n_samples, float* audio,
                     const int32_t* order, void* stream);

@@ -58,6 +58,7 @@ __global__ void __launch_bounds__(64) fm_render_kernel(FmArgs a) {
   __shared__ float envs[4][65];
   const int lane = threadIdx.x;
   const int64_t b = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
+  if (b < 0 || b >= a.batch) return;         // an order entry out of range renders nothing
   int64_t start, L;
   if (a.offsets) {
     packed_range(a.offsets, a.batch, b, start, L);

@@ -420,6 +420,7 @@ __global__ void __launch_bounds__(64) vcf_forward_kernel(VcfArgs a) {
   extern __shared__ float lds_raw[];          // pad, 64 h, pad, 64 control values
   float* lds = lds_raw + kLdsPad;
   const int64_t b = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
+  if (b < 0 || b >= a.batch) return;         // an order entry out of range renders nothing
   const int lane = threadIdx.x;
   int64_t start, L;
   voice_range(a, b, start, L);
@@ -492,6 +493,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) vc
   float* xa = lds_raw + kLdsPad;
   float* ga = xa + 64 * a.h + 2 * kLdsPad;
   const int64_t b = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
+  if (b < 0 || b >= a.batch) return;         // an order entry out of range renders nothing
   const int lane = threadIdx.x;
   int64_t start, L;
   voice_range(a, b, start, L);
