@@ -116,3 +116,11 @@ def test_errors(F):
         F.fm_render(u, bad, n_samples=100)
     with pytest.raises(Exception):
         F.fm_render(u, tab, n_samples=100, sample_rate=44100.0, control_rate=440.0)
+    with pytest.raises(Exception):                     # period 98: not a multiple of 4
+        F.fm_render(u, tab, n_samples=100, sample_rate=44100.0, control_rate=450.0)
+    # other periods that are multiples of 4 (here 64 and 1024) render
+    for sr, rc in ((44800.0, 700.0), (65536.0, 64.0)):
+        y = F.fm_render(u, tab, n_samples=3000, sample_rate=sr, control_rate=rc).cpu().numpy()
+        uu = u.cpu().numpy().astype(np.float64)
+        ref = OFM.render_uniform(torch.tensor(uu), 3000, tab, sr=sr, rc=rc).numpy()
+        assert np.all(np.abs(y - ref).max(1) <= _bound(uu, tab)), (sr, rc)

@@ -92,7 +92,8 @@ def _oracle_grads(x, env, params, w, period=100):
     return xt.grad.numpy(), pt.grad.numpy(), et.grad.numpy()
 
 
-@pytest.mark.parametrize("B,N,period", [(3, 2530, 100), (2, 6500, 100), (2, 400, 4)])
+@pytest.mark.parametrize("B,N,period", [(3, 2530, 100), (2, 6500, 100), (2, 400, 4), (2, 4161, 64),
+                                        (2, 2600, 256), (2, 1500, 36)])
 def test_backward_matches_oracle(V, B, N, period):
     x, env, params = _inputs(B, N, 100 + N, period)
     w = np.random.default_rng(N).standard_normal((B, N)).astype(np.float32)
