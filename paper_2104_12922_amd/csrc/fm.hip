@@ -9,8 +9,9 @@
 //
 // No operator feeds back on itself, so every sample is a closed-form
 // function of n: one wavefront per voice takes 64 control periods (a chunk)
-// at a time; lane l evaluates the four envelopes at control sample 64c + l
-// (float64, the Voice's ADSR code) into LDS, then every lane renders four
+// at a time; lane l evaluates the four envelopes at control sample
+// 64c + l + 1 (float64, the Voice's ADSR code; 64c is the previous chunk's
+// last) into LDS, then every lane renders four
 // consecutive samples per step (lanes on consecutive 16-byte groups, so each
 // store instruction writes 1 KB of contiguous audio).  The four samples share
 // a control period; the phase n f_i / sr of the first is formed in float64
@@ -126,11 +127,24 @@ __global__ void __launch_bounds__(64) fm_render_kernel(FmArgs a) {
       }
       break;
     }
-    // control values at j0 + 0 .. 64 (the last period holds its value)
-    for (int k = lane; k <= 64; k += 64) {
-      const double jd = (double)min(j0 + k, J - 1);
+    // control values at j0 + 0 .. 64 (the last period holds its value): lane
+    // l evaluates j0 + l + 1; the value at j0 is the previous chunk's last
+    // one (the same control sample), so every lane works on each evaluation
+    {
+      float carry[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) envs[i][k] = lvl[i] * (float)adsr_value(dv, i, jd, note_off);
+      for (int i = 0; i < 4; ++i) carry[i] = envs[i][64];
+      if (j0 == 0 && lane == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) carry[i] = lvl[i] * (float)adsr_value(dv, i, 0.0, note_off);
+      }
+      const double jd = (double)min(j0 + lane + 1, J - 1);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float e = lvl[i] * (float)adsr_value(dv, i, jd, note_off);
+        if (lane == 0) envs[i][0] = carry[i];
+        envs[i][lane + 1] = e;
+      }
     }
     __syncthreads();
     for (int p = 4 * lane; p < cnt; p += 256) {
