@@ -524,11 +524,18 @@ def sound_match(targets=4096, train_steps=12208, train_batch=4096, steps=50, lr=
     prop, hist = Lr.train_proposal(tab, train_steps, init=W.mlp_init(0), batch=train_batch,
                                    seed=W.SEED_TRAIN)
     torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    per = Lr.heldout_mse(prop, tab, seed=W.SEED_HELDOUT, per_param=True)
     out["train"] = {"steps": train_steps, "batch": train_batch, "voices": train_steps * train_batch,
-                    "seconds": time.perf_counter() - t0, "first_loss": hist[0][1],
+                    "seconds": train_s, "first_loss": hist[0][1],
                     "last_loss": hist[-1][1],
-                    "heldout_param_mse": Lr.heldout_mse(prop, tab, seed=W.SEED_HELDOUT),
+                    "heldout_param_mse": float(per.mean()),
                     "heldout_param_mse_predicting_half": 1.0 / 12.0,
+                    # the two parameters a log-mel spectrogram determines best
+                    "heldout_param_mse_pitch": float(per[0]),
+                    "heldout_param_mse_duration": float(per[1]),
+                    # parameters whose error is below half that of predicting 0.5
+                    "params_below_half_of_predicting_half": int((per < 0.5 / 12.0).sum()),
                     "heldout_logmel_l1": Lr.heldout_logmel_l1(prop, tab, seed=W.SEED_HELDOUT)}
     say("sound_match train", out["train"])
     lm = Lr.LogMel()
